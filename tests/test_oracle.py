@@ -1,0 +1,549 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+generator outputs, hand-worked examples (tests/golden), library routines that
+a special case reduces to (stable sort, bincount, brute force, sorting for
+D = 1), invariants of the definitions, and statistical statements of the
+paper's analysis (Lemma 3.1/3.2).  The suite is sized to run in seconds.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests import treecheck
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    out = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                out.append(line)
+    return out
+
+
+def _pts(text):
+    cols = [list(map(int, p.split(","))) for p in text.split()]
+    return np.ascontiguousarray(np.array(cols, dtype=np.int64).T)
+
+
+# ---------------------------------------------------------------- sampling key
+def test_splitmix64_reference_outputs(orc):
+    for line in _golden("splitmix64.txt"):
+        vals = [int(v, 0) for v in line.split()]
+        state, expect = vals[0], vals[1:]
+        for e in expect:
+            state = (state + 0x9E3779B97F4A7C15) & (2 ** 64 - 1)
+            assert orc.mix64(state) == e
+
+
+def test_sample_key_depends_on_seed_depth_and_id(orc):
+    k = orc.sample_key(42, 0, 7)
+    assert k != orc.sample_key(43, 0, 7)
+    assert k != orc.sample_key(42, 1, 7)
+    assert k != orc.sample_key(42, 0, 8)
+    # the key is mix(mix(id ^ seed) + (h+1)*golden), a composition of bijections
+    assert k == orc.mix64((orc.mix64(7 ^ 42) + 0x9E3779B97F4A7C15) & (2 ** 64 - 1))
+
+
+# -------------------------------------------------------------------- sampling
+def test_sample_is_bottom_s_by_key(orc):
+    rng = np.random.default_rng(0)
+    ids = rng.choice(10 ** 12, size=5000, replace=False).astype(np.int64)
+    s = 300
+    got = orc.sample(99, 3, ids, s)
+    keys = np.array([orc.sample_key(99, 3, int(i)) for i in ids], dtype=np.uint64)
+    ref = np.lexsort((ids, keys))[:s]          # library sort by (key, id)
+    assert np.array_equal(np.sort(got), np.sort(ref))
+
+
+def test_sample_independent_of_order(orc):
+    ids = np.arange(20000, dtype=np.int64)
+    perm = np.random.default_rng(1).permutation(ids.shape[0])
+    a = ids[orc.sample(5, 2, ids, 2048)]
+    b = ids[perm][orc.sample(5, 2, ids[perm], 2048)]
+    assert np.array_equal(np.sort(a), np.sort(b))
+
+
+@pytest.mark.parametrize("h", [0, 1, 6, 12])
+def test_sample_is_uniform(orc, h):
+    # chi-square over 16 equal position bins: a uniform sample without
+    # replacement puts s/16 in each (hypergeometric, slightly below binomial sd)
+    n, s, bins = 65536, 2048, 16
+    ids = np.arange(n, dtype=np.int64)
+    pos = orc.sample(42, h, ids, s)
+    counts = np.bincount(pos * bins // n, minlength=bins)
+    exp = s / bins
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    assert chi2 < 45.0, chi2          # 15 dof: P(chi2 > 45) ~ 1e-4
+
+
+def test_sample_salted_by_depth(orc):
+    ids = np.arange(65536, dtype=np.int64)
+    a = set(orc.sample(42, 0, ids, 2048).tolist())
+    b = set(orc.sample(42, 1, ids, 2048).tolist())
+    # independent 2048-of-65536 samples overlap in about 64 points
+    assert len(a & b) < 140
+
+
+# ------------------------------------------------------------------ split rule
+def test_split_rule_worked_examples(orc):
+    for line in _golden("split_rule.txt"):
+        name, pts, expect = [f.strip() for f in line.split("|")]
+        P = _pts(pts)
+        got = orc.split_rule(P)
+        if expect == "none":
+            assert got is None, name
+            continue
+        d, x, nleft = map(int, expect.split())
+        assert got == (d, x), name
+        assert int((P[d] < x).sum()) == nleft, name
+
+
+def test_split_rule_properties(orc):
+    rng = np.random.default_rng(3)
+    for trial in range(300):
+        D = int(rng.integers(1, 5))
+        m = int(rng.integers(2, 60))
+        span = int(rng.choice([3, 50, 10 ** 6]))
+        P = rng.integers(0, span, size=(D, m)).astype(np.int64)
+        got = orc.split_rule(P)
+        widths = P.max(axis=1) - P.min(axis=1)
+        if widths.max() == 0:
+            assert got is None
+            continue
+        d, x = got
+        assert widths[d] == widths.max() and np.all(widths[:d] < widths[d])
+        left = P[d] < x
+        assert 0 < left.sum() < m
+        v = np.sort(P[d])
+        if v[m // 2] != v[0]:
+            assert x == v[m // 2]
+        else:
+            assert x == v[v > v[0]].min()
+        if np.unique(P[d]).shape[0] == m:
+            assert left.sum() == m // 2
+
+
+# ------------------------------------------------------------ skeleton + sieve
+def _golden_map(name):
+    return {k.strip(): v.strip() for k, v in (l.split("|") for l in _golden(name))}
+
+
+def test_skeleton_and_sieve_worked_example(orc):
+    g = _golden_map("skeleton_sieve.txt")
+    lam = int(g["lambda"])
+    dim, x, ext = orc.skeleton(_pts(g["samples"]), lam)
+    assert dim.tolist() == list(map(int, g["sk_dim"].split()))
+    assert x[1:].tolist() == list(map(int, g["sk_x"].split()))[1:]
+    assert ext.tolist() == list(map(int, g["sk_ext"].split()))
+    P = _pts(g["points"])
+    labels, order = orc.sieve(P, lam, (dim, x, ext))
+    assert labels.tolist() == list(map(int, g["labels"].split()))
+    assert order.tolist() == list(map(int, g["order"].split()))
+    # the chunked formulation (counts A, column-major exclusive prefix B,
+    # distribution P'[B[i][j]++] = p) gives the same order as the oracle
+    l = int(g["chunk"])
+    nb = 1 << lam
+    A = np.array(list(map(int, g["A"].split()))).reshape(-1, nb)
+    B = np.array(list(map(int, g["B"].split()))).reshape(-1, nb)
+    n = labels.shape[0]
+    chunks = np.arange(n) // l
+    assert np.array_equal(A, np.stack([np.bincount(labels[chunks == c], minlength=nb)
+                                        for c in range(A.shape[0])]))
+    assert np.array_equal(B.T.ravel(), np.concatenate([[0], np.cumsum(A.T.ravel())[:-1]]))
+    Bw = B.copy()
+    dest = np.empty(n, dtype=np.int64)
+    for i in range(n):
+        dest[Bw[chunks[i], labels[i]]] = i
+        Bw[chunks[i], labels[i]] += 1
+    assert dest.tolist() == order.tolist()
+    assert B[0].tolist() == list(map(int, g["starts"].split()))
+
+
+def _check_skeleton_recursion(orc, S, lam, sk):
+    """Each interior heap node's splitter is the split rule of the sample
+    subset that reaches it; zero-width subsets are external."""
+    dim, x, ext = sk
+    D, s = S.shape
+    node = np.ones(s, dtype=np.int64)
+    for level in range(lam):
+        for v in range(1 << level, 2 << level):
+            sub = S[:, node == v]
+            if sub.shape[1] == 0:
+                continue
+            rule = orc.split_rule(sub)
+            if rule is None:
+                assert ext[v] == 1
+            else:
+                assert ext[v] == 0 and (dim[v], x[v]) == rule
+        live = ext[node] == 0
+        go = np.zeros(s, dtype=np.int64)
+        go[live] = (S[dim[node[live]], np.nonzero(live)[0]] >= x[node[live]]).astype(np.int64)
+        node = np.where(live, 2 * node + go, node)
+    return node
+
+
+def test_skeleton_recursion_and_sieve_is_stable_counting_sort(orc):
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        D = int(rng.integers(1, 4))
+        lam = int(rng.integers(1, 7))
+        span = int(rng.choice([4, 1000, 10 ** 9]))
+        S = rng.integers(0, span, size=(D, int(rng.integers(1, 400)))).astype(np.int64)
+        sk = orc.skeleton(S, lam)
+        _check_skeleton_recursion(orc, S, lam, sk)
+        P = rng.integers(0, span, size=(D, 3000)).astype(np.int64)
+        labels, order = orc.sieve(P, lam, sk)
+        assert np.array_equal(order, np.argsort(labels, kind="stable"))
+        # each point lies inside the cell of its bucket: check every ancestor
+        dim, x, ext = sk
+        for i in range(0, 3000, 7):
+            v = 1
+            while not ext[v]:
+                v = 2 * v + int(P[dim[v], i] >= x[v])
+            lvl = int(np.log2(v))
+            assert labels[i] == (v << (lam - lvl)) - (1 << lam)
+        # every sample point's bucket is non-empty, so no skeleton child is empty
+        sl, _ = orc.sieve(S, lam, sk)
+        for v in range(1, 2 << lam):
+            if ext[v] and (v == 1 or not ext[v // 2]):
+                lvl = int(np.log2(v))
+                assert np.any(sl == (v << (lam - lvl)) - (1 << lam))
+
+
+# ------------------------------------------------------------------ whole tree
+def _build(orc, coords, ids, **kw):
+    p = orc.Params(coords.shape[0], **kw)
+    return orc.Tree(p, coords, ids), p
+
+
+@pytest.mark.parametrize("D,n", [(1, 5000), (2, 30000), (3, 100000), (5, 20000)])
+def test_tree_invariants_uniform(orc, D, n):
+    c, i = synth.uniform_points(n, D, seed=11 + D)
+    T, p = _build(orc, c, i)
+    rows, ids, coords = T.export()
+    treecheck.check_tree(rows, ids, coords, p.phi, c, i)
+
+
+def test_tree_invariants_small_params(orc):
+    c, i = synth.uniform_points(20000, 2, seed=4)
+    T, p = _build(orc, c, i, lam=3, phi=4, sigma=4)
+    rows, ids, coords = T.export()
+    treecheck.check_tree(rows, ids, coords, p.phi, c, i)
+
+
+def test_one_dimension_is_sorting(orc):
+    # Section 3.2: in one dimension a kd-tree build sorts the points.
+    c, i = synth.uniform_points(50000, 1, seed=8, hi=1000)   # many duplicates
+    T, p = _build(orc, c, i)
+    rows, ids, coords = T.export()
+    leaves = rows[:, 0] == 1
+    sizes = rows[leaves, 3]
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    mn = np.minimum.reduceat(coords[0], starts)
+    mx = np.maximum.reduceat(coords[0], starts)
+    assert np.all(mx[:-1] <= mn[1:])
+    assert np.array_equal(np.sort(coords[0]), np.sort(c[0]))
+
+
+def test_tree_independent_of_input_order(orc):
+    c, i = synth.uniform_points(60000, 3, seed=21)
+    perm = np.random.default_rng(2).permutation(i.shape[0])
+    A, _ = _build(orc, c, i)
+    B, _ = _build(orc, np.ascontiguousarray(c[:, perm]), i[perm])
+    for a, b in zip(A.export(), B.export()):
+        assert np.array_equal(a, b)
+
+
+def test_plain_splits_are_exact_medians(orc):
+    c, i = synth.uniform_points(30000, 3, seed=22)   # distinct values w.h.p.
+    T, p = _build(orc, c, i)
+    rows, ids, coords = T.export()
+    depth, plain = T.depths()
+    info = treecheck.parse(rows)
+    start, lc = info[0], info[2]
+    checked = 0
+    for v in np.nonzero(plain == 1)[0]:
+        d, x, m = rows[v, 1], rows[v, 2], rows[v, 3]
+        seg = coords[d, start[v]:start[v] + m]
+        if np.unique(seg).shape[0] == m:
+            assert rows[lc[v], 3] == m // 2
+            checked += 1
+    assert checked > 100
+
+
+def test_root_skeleton_matches_sample_of_the_whole_set(orc):
+    c, i = synth.uniform_points(50000, 2, seed=23)
+    T, p = _build(orc, c, i)
+    rows, _, _ = T.export()
+    dim, x, ext = orc.root_skeleton(p, c, i)
+    # walk the exported tree's top levels in heap order
+    info = treecheck.parse(rows)
+    lc, rc = info[2], info[3]
+    heap = {1: 0}
+    for v in range(1, 1 << p.lam):
+        if v not in heap or ext[v]:
+            continue
+        t = heap[v]
+        assert rows[t, 0] == 0 and (rows[t, 1], rows[t, 2]) == (dim[v], x[v])
+        heap[2 * v], heap[2 * v + 1] = lc[t], rc[t]
+
+
+def test_root_balance_statistics(orc):
+    # the root splitter is the median of s = 2048 samples, so the left share is
+    # 1/2 with standard deviation about 1/(2 sqrt(s)) = 0.011 (order statistics;
+    # Lemma 3.1 bounds the same quantity)
+    fr = []
+    for seed in range(30):
+        c, i = synth.uniform_points(20000, 2, seed=100 + seed)
+        T, p = _build(orc, c, i, seed=seed)
+        rows, _, _ = T.export()
+        fr.append(rows[1, 3] / rows[0, 3])
+    fr = np.array(fr)
+    sd = 0.5 / np.sqrt(2048) * np.sqrt(1 - 2048 / 20000)   # finite-population factor
+    assert abs(fr.mean() - 0.5) < 4 * sd / np.sqrt(len(fr))
+    assert 0.6 * sd < fr.std(ddof=1) < 1.5 * sd
+
+
+def test_height_bound(orc):
+    # Lemma 3.2: height log n + O(1); uniform data stays within a few levels of
+    # the perfectly balanced log2(n / phi)
+    c, i = synth.uniform_points(200000, 3, seed=24)
+    T, p = _build(orc, c, i)
+    assert T.height() <= int(np.ceil(np.log2(200000 / 32))) + 4
+
+
+def test_duplicates_heavy_leaves(orc):
+    c, i = synth.duplicate_heavy_points(40000, 2, seed=25, n_distinct=50)
+    T, p = _build(orc, c, i)
+    rows, ids, coords = T.export()
+    treecheck.check_tree(rows, ids, coords, p.phi, c, i)
+    leaves = rows[:, 0] == 1
+    assert rows[leaves, 3].max() > p.phi        # heavy leaves exist
+    assert leaves.sum() <= 2 * 50
+
+
+def test_degenerate_sample_exact_split(orc):
+    # All points on one location except a few that the root sample misses: the
+    # sample of 2048 is entirely identical while the set is not, which forces
+    # the exact-split fallback at the root.
+    n = 200000
+    i = np.arange(n, dtype=np.int64)
+    c = np.full((2, n), 500, dtype=np.int64)
+    p = orc.Params(2)
+    samp = orc.sample(p.seed, 0, i, 2048)
+    others = np.setdiff1d(np.arange(0, n, 997), samp)[:40]
+    c[:, others] = synth.uniform_points(40, 2, seed=26)[0]
+    T = orc.Tree(p, c, i)
+    rows, ids, coords = T.export()
+    treecheck.check_tree(rows, ids, coords, p.phi, c, i)
+    depth, plain = T.depths()
+    assert plain[0] == 1
+    d, x = orc.split_rule(c)
+    assert (rows[0, 1], rows[0, 2]) == (d, x)
+    assert rows[:, 3][rows[:, 0] == 1].max() > 190000      # one heavy leaf
+
+
+def test_all_identical_and_tiny(orc):
+    c = np.full((3, 5000), 77, dtype=np.int64)
+    i = np.arange(5000, dtype=np.int64)
+    T, p = _build(orc, c, i)
+    rows, ids, coords = T.export()
+    assert rows.shape[0] == 1 and rows[0, 0] == 1 and rows[0, 3] == 5000
+    for n in (0, 1, 31, 32, 33):
+        c, i = synth.uniform_points(n, 2, seed=n)
+        T, p = _build(orc, c, i)
+        rows, ids, coords = T.export()
+        assert rows[0, 3] == n
+        if n <= 32:
+            assert rows.shape[0] == 1
+        else:
+            treecheck.check_tree(rows, ids, coords, p.phi, c, i)
+
+
+# ---------------------------------------------------------------------- queries
+def _brute_knn_numpy(c, i, q, k):
+    out_i = np.full((q.shape[1], k), -1, dtype=np.int64)
+    out_d = np.full((q.shape[1], k), -1, dtype=np.int64)
+    for j in range(q.shape[1]):
+        d2 = ((c - q[:, j:j + 1]) ** 2).sum(axis=0)
+        o = np.lexsort((i, d2))[:k]
+        out_i[j, :o.shape[0]] = i[o]
+        out_d[j, :o.shape[0]] = d2[o]
+    return out_i, out_d
+
+
+@pytest.mark.parametrize("D,n,k,span", [(2, 20000, 10, 10 ** 9), (3, 20000, 1, 10 ** 9),
+                                        (3, 5000, 100, 10 ** 9), (2, 5000, 7, 20), (1, 3000, 5, 100),
+                                        (4, 3000, 10, 10 ** 6)])
+def test_knn_matches_definition(orc, D, n, k, span):
+    c, i = synth.uniform_points(n, D, seed=30 + D, hi=span)
+    q = synth.uniform_queries(200, D, seed=31, hi=span)
+    T, _ = _build(orc, c, i)
+    got = T.knn(q, k)
+    bi, bd = orc.brute_knn(c, i, q, k)
+    assert np.array_equal(got[0], bi) and np.array_equal(got[1], bd)
+    ni, nd = _brute_knn_numpy(c, i, q[:, :50], k)
+    assert np.array_equal(bi[:50], ni) and np.array_equal(bd[:50], nd)
+
+
+def test_knn_k_larger_than_n_and_empty(orc):
+    c, i = synth.uniform_points(20, 2, seed=40)
+    q = synth.uniform_queries(5, 2, seed=41)
+    T, _ = _build(orc, c, i)
+    ids, d2 = T.knn(q, 30)
+    assert np.all(ids[:, 20:] == -1) and np.all(d2[:, 20:] == -1)
+    assert np.all(np.sort(ids[:, :20], axis=1) == np.sort(i))
+    E, _ = _build(orc, np.zeros((2, 0), dtype=np.int64), np.zeros(0, dtype=np.int64))
+    ids, d2 = E.knn(q, 3)
+    assert np.all(ids == -1) and np.all(d2 == -1)
+
+
+def test_knn_brute_force_matches_scipy(orc):
+    scipy_spatial = pytest.importorskip("scipy.spatial")
+    c, i = synth.uniform_points(5000, 3, seed=42, hi=1 << 20)   # exact in float64
+    q = synth.uniform_queries(100, 3, seed=43, hi=1 << 20)
+    bi, bd = orc.brute_knn(c, i, q, 8)
+    dist, idx = scipy_spatial.cKDTree(c.T.astype(np.float64)).query(q.T.astype(np.float64), k=8)
+    assert np.array_equal(bd, np.rint(dist ** 2).astype(np.int64))
+
+
+@pytest.mark.parametrize("D,span", [(2, 10 ** 9), (3, 10 ** 9), (2, 50)])
+def test_range_count_matches_definition(orc, D, span):
+    c, i = synth.uniform_points(30000, D, seed=50 + D, hi=span)
+    lo, hi = synth.log_uniform_boxes(300, D, seed=51, side_lo=1, side_hi=span, hi=span)
+    T, _ = _build(orc, c, i)
+    got = T.range_count(lo, hi)
+    ref = orc.brute_range_count(c, lo, hi)
+    assert np.array_equal(got, ref)
+    np_ref = np.array([np.all((c >= lo[:, j:j + 1]) & (c <= hi[:, j:j + 1]), axis=0).sum()
+                       for j in range(lo.shape[1])])
+    assert np.array_equal(ref, np_ref)
+    # empty boxes (lo > hi) count nothing; the whole domain counts everything
+    lo2 = lo.copy()
+    lo2[0] = hi[0] + 1
+    assert np.all(T.range_count(lo2, hi) == 0)
+    full_lo = np.zeros((D, 1), dtype=np.int64)
+    full_hi = np.full((D, 1), (1 << 30) - 1, dtype=np.int64)
+    assert T.range_count(full_lo, full_hi)[0] == 30000
+
+
+# ---------------------------------------------------------------------- updates
+def test_balance_predicate_worked_cases(orc):
+    for line in _golden("balance.txt"):
+        l, n, b = map(int, line.split())
+        assert orc.balanced(l, n) == bool(b), (l, n)
+
+
+def _check_after_updates(orc, T, p, cur_c, cur_i, q, boxes):
+    rows, ids, coords = T.export()
+    treecheck.check_tree(rows, ids, coords, p.phi, cur_c, cur_i)
+    k = 10
+    got = T.knn(q, k)
+    ref = orc.brute_knn(cur_c, cur_i, q, k)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    assert np.array_equal(T.range_count(*boxes), orc.brute_range_count(cur_c, *boxes))
+
+
+def test_insert_delete_sequence_matches_definition(orc):
+    D = 3
+    c, i, state = synth.clustered_points(40000, D, seed=60, n_clusters=40)
+    T, p = _build(orc, c, i)
+    q = synth.uniform_queries(100, D, seed=61)
+    boxes = synth.log_uniform_boxes(100, D, seed=62)
+    cur_c, cur_i = c, i
+    next_id = 40000
+    for step in range(4):
+        nc, ni, state = synth.clustered_points(4000, D, seed=63 + step, continue_from=state, id_base=next_id)
+        next_id += 4000
+        T.insert(nc, ni)
+        cur_c = np.concatenate([cur_c, nc], axis=1)
+        cur_i = np.concatenate([cur_i, ni])
+        _check_after_updates(orc, T, p, cur_c, cur_i, q, boxes)
+        pick = synth.sample_existing(cur_i, 3000, seed=70 + step)
+        removed = T.delete(cur_c[:, pick], cur_i[pick])
+        assert removed == 3000
+        keep = np.ones(cur_i.shape[0], dtype=bool)
+        keep[pick] = False
+        cur_c, cur_i = np.ascontiguousarray(cur_c[:, keep]), cur_i[keep]
+        _check_after_updates(orc, T, p, cur_c, cur_i, q, boxes)
+
+
+def test_insert_into_empty_equals_build(orc):
+    c, i = synth.uniform_points(10000, 2, seed=80)
+    E, p = _build(orc, np.zeros((2, 0), dtype=np.int64), np.zeros(0, dtype=np.int64))
+    E.insert(c, i)
+    B, _ = _build(orc, c, i)
+    for a, b in zip(E.export(), B.export()):
+        assert np.array_equal(a, b)
+
+
+def test_root_rebuild_exactly_at_the_balance_bound(orc):
+    # Insert points that all fall left of the root splitter.  The root stays
+    # (weight-balanced) while |lc| / |T| <= 0.8 and is rebuilt one point later;
+    # a rebuild of the root is a fresh Build of all points at depth 0.
+    c, i = synth.uniform_points(3000, 2, seed=81)
+    T, p = _build(orc, c, i)
+    rows, _, _ = T.export()
+    d, x, n = rows[0, 1], rows[0, 2], rows[0, 3]
+    l = rows[1, 3]
+    k = 4 * n - 5 * l                 # (l + k) / (n + k) == 0.8 exactly
+    assert k > 0
+    rng = np.random.default_rng(82)
+    newc = rng.integers(0, 10 ** 9, size=(2, k + 1)).astype(np.int64)
+    newc[d] = rng.integers(0, x, size=k + 1)
+    newi = np.arange(10 ** 6, 10 ** 6 + k + 1, dtype=np.int64)
+    T.insert(newc[:, :k], newi[:k])
+    rows2, _, _ = T.export()
+    assert (rows2[0, 1], rows2[0, 2], rows2[0, 3]) == (d, x, n + k)
+    T.insert(newc[:, k:], newi[k:])
+    allc = np.concatenate([c, newc], axis=1)
+    alli = np.concatenate([i, newi])
+    F, _ = _build(orc, allc, alli)
+    for a, b in zip(T.export(), F.export()):
+        assert np.array_equal(a, b)
+
+
+def test_delete_absent_and_mismatched_is_noop(orc):
+    c, i = synth.uniform_points(5000, 2, seed=83)
+    T, p = _build(orc, c, i)
+    before = T.export()
+    absent_c, absent_i = synth.uniform_points(100, 2, seed=84, id_base=10 ** 7)
+    assert T.delete(absent_c, absent_i) == 0
+    wrong = c[:, :100].copy()
+    wrong[0] += 1                     # right ids, wrong coordinates
+    assert T.delete(wrong, i[:100]) == 0
+    for a, b in zip(before, T.export()):
+        assert np.array_equal(a, b)
+    # a repeated entry deletes once
+    assert T.delete(np.concatenate([c[:, :5], c[:, :5]], axis=1), np.concatenate([i[:5], i[:5]])) == 5
+
+
+def test_delete_everything_and_reinsert(orc):
+    c, i = synth.uniform_points(4000, 3, seed=85)
+    T, p = _build(orc, c, i)
+    assert T.delete(c, i) == 4000
+    rows, ids, coords = T.export()
+    assert rows.shape[0] == 1 and rows[0, 3] == 0
+    T.insert(c, i)
+    B, _ = _build(orc, c, i)
+    for a, b in zip(T.export(), B.export()):
+        assert np.array_equal(a, b)
+
+
+def test_delete_then_insert_restores_query_answers(orc):
+    c, i = synth.uniform_points(20000, 2, seed=86)
+    T, p = _build(orc, c, i)
+    q = synth.uniform_queries(100, 2, seed=87)
+    ref = T.knn(q, 10)
+    extra_c, extra_i = synth.uniform_points(5000, 2, seed=88, id_base=10 ** 6)
+    T.insert(extra_c, extra_i)
+    assert T.delete(extra_c, extra_i) == 5000
+    got = T.knn(q, 10)
+    assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1])
