@@ -1,0 +1,161 @@
+/*
+ * pkd.h -- C interface of the MI355X (gfx950) Pkd-tree library (libpkd.so).
+ *
+ * The library builds and maintains a kd-tree over int64 points with the
+ * sampling-based multi-level sieve of "Parallel kd-tree with Batch Updates"
+ * (Men, Shen, Gu, Sun, SIGMOD 2025):
+ *   Build        -- Algorithm 1, Section 3.1
+ *   BatchInsert  -- Algorithm 2, Section 4.1
+ *   BatchDelete  -- Section 4.2
+ *   k-NN, range count -- Section 2 (definitions), Section 5 (traversals)
+ * Every step runs in HIP kernels on the GPU; this header holds only plain C
+ * types.
+ *
+ * Conventions for every call
+ *   - Return value: PKD_OK (0) or a negative PKD_ERR_* code; pkd_strerror()
+ *     names it.  No C++ exception crosses this interface.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is ordered on that stream.  Calls that must report data-dependent
+ *     errors (range checks) or that size their own work from device results
+ *     synchronize the stream before returning; results are then ready.
+ *   - Point sets are structure-of-arrays: `coords` is int64 [dim][n] (row d
+ *     holds coordinate d of all points, contiguous), `ids` is int64 [n].  All
+ *     point, query and output pointers given to a call are DEVICE pointers
+ *     owned by the caller; the library only reads inputs and only writes
+ *     outputs during the call's stream work.
+ *   - Coordinates (points, queries, box corners) must lie in [0, 2^30); this
+ *     keeps squared distances exact in int64 for dim <= 7.  Violations return
+ *     PKD_ERR_RANGE and leave any tree unchanged.
+ *   - Ids are caller-chosen int64 values and must be unique within a tree
+ *     (precondition; not checked).
+ *   - A tree owns its device storage (allocated with stream-ordered
+ *     hipMallocAsync).  A tree must not be used by two calls concurrently.
+ *   - On any error a mutating call leaves the tree as it was.
+ */
+#ifndef PKD_H
+#define PKD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PKD_OK 0
+#define PKD_ERR_INVALID_ARG (-1)   /* null pointer, negative count, bad parameter */
+#define PKD_ERR_RANGE (-2)         /* a coordinate outside [0, 2^30) */
+#define PKD_ERR_UNSUPPORTED (-3)   /* dim outside 1..7, sample size > 4096, n >= 2^31 */
+#define PKD_ERR_OOM (-4)           /* device allocation failed */
+#define PKD_ERR_HIP (-5)           /* a HIP runtime call failed */
+#define PKD_ERR_CAPACITY (-6)      /* a query needs a deeper traversal stack than built in */
+#define PKD_ERR_INTERNAL (-7)      /* an internal consistency check failed */
+
+typedef struct pkd_tree pkd_tree;   /* opaque; device-resident */
+
+/* Parameters that change the tree (Section 5 gives the defaults). */
+typedef struct {
+  int32_t dim;        /* D, 1..7 */
+  int32_t lambda;     /* skeleton levels per sieve round (lambda), 1..8; default 6 */
+  int32_t leaf_size;  /* leaf wrap phi: a leaf holds at most phi points unless all
+                         its points are identical (heavy leaf); default 32 */
+  int32_t oversample; /* sigma; the sample size is s = 2^lambda * sigma <= 4096;
+                         default 32 (s = 2048) */
+  int32_t alpha_num;  /* balance parameter alpha = alpha_num / alpha_den with */
+  int32_t alpha_den;  /* 0 <= 2*alpha_num < alpha_den; default 3/10 */
+  uint64_t seed;      /* seed of the sampling hash; default 42 */
+} pkd_params;
+
+/* Parameters that never change any result (work decomposition only). */
+typedef struct {
+  int32_t tile_points;  /* points per sieve tile: 1024, 2048 or 4096; default 2048 */
+  int32_t reserved[7];
+} pkd_tuning;
+
+/* Fill defaults for dimension `dim`. */
+void pkd_default_params(pkd_params* p, int32_t dim);
+void pkd_default_tuning(pkd_tuning* t);
+
+/*
+ * Build (Algorithm 1, Section 3.1).  Builds a tree over the n points
+ * (coords: device int64 [dim][n], ids: device int64 [n]); n may be 0.
+ * tuning may be NULL (defaults).  On success *out receives a new tree, which
+ * the caller releases with pkd_free.  The inputs are not modified and are no
+ * longer referenced after the call returns.  Synchronizes `stream`.
+ */
+int pkd_build(const pkd_params* params, const pkd_tuning* tuning, void* stream,
+              const int64_t* coords, const int64_t* ids, int64_t n, pkd_tree** out);
+
+/*
+ * BatchInsert (Algorithm 2, Section 4.1).  Inserts m points (device
+ * coords [dim][m], ids [m]; ids not yet in the tree).  A node whose two
+ * subtrees stay alpha-weight-balanced after the insertion is kept; the topmost
+ * node that would become unbalanced is rebuilt from its points and the batch
+ * points below it; a leaf that receives points becomes Build(leaf + points).
+ * Synchronizes `stream`.
+ */
+int pkd_batch_insert(pkd_tree* tree, void* stream, const int64_t* coords,
+                     const int64_t* ids, int64_t m);
+
+/*
+ * BatchDelete (Section 4.2).  Removes, for every batch entry (device
+ * coords [dim][m], ids [m]), the stored point with the same id and the same
+ * coordinates; entries that match no stored point are ignored, a repeated
+ * entry removes once.  Subtrees that become alpha-unbalanced are rebuilt
+ * (topmost first) from their remaining points.  *n_deleted (host pointer, may
+ * be NULL) receives the number of points removed.  Synchronizes `stream`.
+ */
+int pkd_batch_delete(pkd_tree* tree, void* stream, const int64_t* coords,
+                     const int64_t* ids, int64_t m, int64_t* n_deleted);
+
+/*
+ * k-NN (Section 2; depth-first search of Section 5).  For each of the nq
+ * queries (device int64 [dim][nq]) writes the min(k, n) stored points with the
+ * smallest (squared distance, id) pairs, ascending, into out_ids / out_d2
+ * (device int64 [nq][k], row-major); unused slots get -1.  Squared distances
+ * are exact int64.  1 <= k <= 128.  Synchronizes `stream`.
+ */
+int pkd_knn(const pkd_tree* tree, void* stream, const int64_t* queries, int64_t nq,
+            int32_t k, int64_t* out_ids, int64_t* out_d2);
+
+/*
+ * Range count (Section 2; traversal with subtree sizes, Section 5).  For each
+ * closed box [lo, hi] (device int64 [dim][nb] each) writes the number of stored
+ * points p with lo_d <= p_d <= hi_d in every dimension into out (device int64
+ * [nb]); a box with lo_d > hi_d in some dimension counts 0.
+ * Synchronizes `stream`.
+ */
+int pkd_range_count(const pkd_tree* tree, void* stream, const int64_t* lo,
+                    const int64_t* hi, int64_t nb, int64_t* out);
+
+/* Number of points (host out). */
+int pkd_size(const pkd_tree* tree, int64_t* n);
+
+/* Sizes needed by pkd_export: number of nodes and of points (host outs). */
+int pkd_export_sizes(const pkd_tree* tree, int64_t* num_nodes, int64_t* n);
+
+/*
+ * Canonical host copy of the tree (a test aid).  HOST buffers:
+ *   rows        int64 [num_nodes][4]: pre-order (kind, dim, x, size); kind 0 =
+ *               interior node with splitter (dim, x), 1 = leaf (dim -1, x 0)
+ *   leaf_ids    int64 [n]: ids of the leaf points, leaves in pre-order, ids
+ *               ascending inside each leaf
+ *   leaf_coords int64 [dim][n]: their coordinates
+ * Any of the three pointers may be NULL.  depths (int32 [num_nodes], may be
+ * NULL) receives each node's depth.
+ */
+int pkd_export(const pkd_tree* tree, int64_t* rows, int64_t* leaf_ids,
+               int64_t* leaf_coords, int32_t* depths);
+
+/* Height of the tree (edges on the longest root-leaf path). */
+int pkd_height(const pkd_tree* tree, int32_t* height);
+
+/* Release a tree (NULL is ignored). */
+void pkd_free(pkd_tree* tree);
+
+const char* pkd_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PKD_H */

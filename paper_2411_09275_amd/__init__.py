@@ -1,0 +1,203 @@
+"""Python binding of libpkd, the MI355X Pkd-tree library.
+
+Argument marshalling only: every step of build, update and query runs in the
+HIP kernels of ``libpkd.so``; PyTorch supplies device memory and the stream.
+The library must be built (``python -m paper_2411_09275_amd.build`` or
+``__graft_entry__.build()``); importing this module on a machine without it
+raises immediately rather than falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpkd.so")
+
+PKD_OK = 0
+ERRORS = {
+    -1: "PKD_ERR_INVALID_ARG", -2: "PKD_ERR_RANGE", -3: "PKD_ERR_UNSUPPORTED", -4: "PKD_ERR_OOM",
+    -5: "PKD_ERR_HIP", -6: "PKD_ERR_CAPACITY", -7: "PKD_ERR_INTERNAL",
+}
+
+# Every symbol the C header declares (checked by the ABI test).
+EXPORTS = ["pkd_default_params", "pkd_default_tuning", "pkd_build", "pkd_batch_insert", "pkd_batch_delete",
+           "pkd_knn", "pkd_range_count", "pkd_size", "pkd_export_sizes", "pkd_export", "pkd_height",
+           "pkd_free", "pkd_strerror"]
+
+
+class PkdError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, ERRORS.get(code, "unknown"), code))
+
+
+class _Params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("lambda_", C.c_int32), ("leaf_size", C.c_int32), ("oversample", C.c_int32),
+                ("alpha_num", C.c_int32), ("alpha_den", C.c_int32), ("seed", C.c_uint64)]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("tile_points", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpkd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpkd.so is not built (%s); run paper_2411_09275_amd/build.py" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.pkd_default_params.argtypes = [C.POINTER(_Params), i32]
+        L.pkd_default_tuning.argtypes = [C.POINTER(_Tuning)]
+        L.pkd_build.argtypes = [C.POINTER(_Params), C.POINTER(_Tuning), vp, vp, vp, i64, C.POINTER(vp)]
+        L.pkd_batch_insert.argtypes = [vp, vp, vp, vp, i64]
+        L.pkd_batch_delete.argtypes = [vp, vp, vp, vp, i64, C.POINTER(i64)]
+        L.pkd_knn.argtypes = [vp, vp, vp, i64, i32, vp, vp]
+        L.pkd_range_count.argtypes = [vp, vp, vp, vp, i64, vp]
+        L.pkd_size.argtypes = [vp, C.POINTER(i64)]
+        L.pkd_height.argtypes = [vp, C.POINTER(i32)]
+        L.pkd_export_sizes.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+        L.pkd_export.argtypes = [vp, vp, vp, vp, vp]
+        L.pkd_free.argtypes = [vp]
+        L.pkd_free.restype = None
+        L.pkd_strerror.argtypes = [C.c_int]
+        L.pkd_strerror.restype = C.c_char_p
+        for f in ("pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
+                  "pkd_height", "pkd_export_sizes", "pkd_export"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != PKD_OK:
+        raise PkdError(rc, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, shape=None):
+    """A contiguous int64 CUDA tensor (the caller's buffer when it already is one)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.from_numpy(np.ascontiguousarray(t, dtype=np.int64))
+    t = t.to(device="cuda", dtype=torch.int64).contiguous()
+    if shape is not None:
+        assert tuple(t.shape) == tuple(shape), (tuple(t.shape), shape)
+    return t
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr() if t.numel() > 0 else 0)
+
+
+class Params:
+    """Result-affecting parameters; defaults follow Section 5 of the paper
+    (lambda=6, phi=32, sigma=32, alpha=0.3)."""
+
+    def __init__(self, dim, lam=6, phi=32, sigma=32, alpha=(3, 10), seed=42):
+        self.dim, self.lam, self.phi, self.sigma = int(dim), int(lam), int(phi), int(sigma)
+        self.alpha = (int(alpha[0]), int(alpha[1]))
+        self.seed = int(seed)
+
+    def _c(self):
+        p = _Params()
+        p.dim, p.lambda_, p.leaf_size, p.oversample = self.dim, self.lam, self.phi, self.sigma
+        p.alpha_num, p.alpha_den = self.alpha
+        p.seed = self.seed & (2 ** 64 - 1)
+        return p
+
+
+class Tree:
+    """A device-resident Pkd-tree (``pkd_tree*``)."""
+
+    def __init__(self, params: Params, coords, ids, tile: int = 2048, stream=None):
+        self.p = params
+        c = _dev(coords)
+        i = _dev(ids)
+        n = i.shape[0]
+        assert tuple(c.shape) == (params.dim, n)
+        t = _Tuning()
+        lib().pkd_default_tuning(C.byref(t))
+        t.tile_points = tile
+        h = C.c_void_p()
+        _check(lib().pkd_build(C.byref(params._c()), C.byref(t), _stream(stream), _ptr(c), _ptr(i), n, C.byref(h)),
+               "pkd_build")
+        self.h = h
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().pkd_free(self.h)
+        self.h = None
+
+    def size(self) -> int:
+        n = C.c_int64()
+        _check(lib().pkd_size(self.h, C.byref(n)), "pkd_size")
+        return n.value
+
+    def height(self) -> int:
+        h = C.c_int32()
+        _check(lib().pkd_height(self.h, C.byref(h)), "pkd_height")
+        return h.value
+
+    def knn(self, queries, k: int, stream=None):
+        """(ids, d2) as int64 CUDA tensors [nq, k]."""
+        torch = _torch()
+        q = _dev(queries)
+        nq = q.shape[1] if q.dim() == 2 else 0
+        oi = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+        od = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+        _check(lib().pkd_knn(self.h, _stream(stream), _ptr(q), nq, k, _ptr(oi), _ptr(od)), "pkd_knn")
+        return oi, od
+
+    def range_count(self, lo, hi, stream=None):
+        torch = _torch()
+        lo, hi = _dev(lo), _dev(hi)
+        nb = lo.shape[1]
+        out = torch.empty(nb, dtype=torch.int64, device="cuda")
+        _check(lib().pkd_range_count(self.h, _stream(stream), _ptr(lo), _ptr(hi), nb, _ptr(out)), "pkd_range_count")
+        return out
+
+    def insert(self, coords, ids, stream=None):
+        c, i = _dev(coords), _dev(ids)
+        _check(lib().pkd_batch_insert(self.h, _stream(stream), _ptr(c), _ptr(i), i.shape[0]), "pkd_batch_insert")
+
+    def delete(self, coords, ids, stream=None) -> int:
+        c, i = _dev(coords), _dev(ids)
+        n = C.c_int64()
+        _check(lib().pkd_batch_delete(self.h, _stream(stream), _ptr(c), _ptr(i), i.shape[0], C.byref(n)),
+               "pkd_batch_delete")
+        return n.value
+
+    def export(self):
+        """Canonical pre-order form: rows [N,4] (kind, dim, x, size), leaf ids
+        (ascending inside each leaf) and their coordinates [D, n]; numpy."""
+        N, n = C.c_int64(), C.c_int64()
+        _check(lib().pkd_export_sizes(self.h, C.byref(N), C.byref(n)), "pkd_export_sizes")
+        rows = np.empty((N.value, 4), dtype=np.int64)
+        ids = np.empty(n.value, dtype=np.int64)
+        coords = np.empty((self.p.dim, n.value), dtype=np.int64)
+        depths = np.empty(N.value, dtype=np.int32)
+        _check(lib().pkd_export(self.h, rows.ctypes.data_as(C.c_void_p), ids.ctypes.data_as(C.c_void_p),
+                                coords.ctypes.data_as(C.c_void_p), depths.ctypes.data_as(C.c_void_p)), "pkd_export")
+        self.last_depths = depths
+        return rows, ids, coords

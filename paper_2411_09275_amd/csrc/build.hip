@@ -1,0 +1,1636 @@
+// Build of a Pkd-tree on the GPU: Algorithm 1 of the paper (Section 3.1),
+// re-planned for gfx950.
+//
+// One sieve round processes every live subproblem of a recursion level at once
+// (segmented launches), so the GPU sees one large grid per step:
+//   candidates  -- hash-key prefilter of each subproblem's ids (sampling)
+//   select      -- bottom-s sample by (key, id) with an LDS radix select, then
+//                  the lambda-level skeleton on the sample (LDS presorted build)
+//   count       -- per tile: walk the skeleton, 2^lambda-bin LDS histogram
+//   scan        -- exclusive prefix sum of the tile x bucket counts in
+//                  column-major order, segmented by subproblem
+//   scatter     -- stable, LDS-staged, coalesced distribution of coordinates
+//                  and ids into the twin buffer (buffers swap every round
+//                  instead of copying back, Section 5)
+//   emit        -- skeleton nodes become tree nodes; buckets become the next
+//                  round's subproblems (>= s points) or finisher tasks
+// Subproblems below s = 2^lambda*sigma points are finished by the plain
+// construction in LDS, one workgroup per subproblem.
+#include <algorithm>
+#include <cstring>
+
+#include "pkd_internal.h"
+
+namespace pkd {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kChunkTiles = 64;      // tiles per scan chunk
+
+struct Bufs {
+  int64_t* c[3];   // coordinates: c[b][d*cap[b] + i]
+  int64_t* id[3];  // ids: id[b][i]
+  int64_t cap[3];
+};
+
+__device__ inline uint32_t lane_id() { return threadIdx.x & 63; }
+
+template <int D>
+__device__ inline int64_t pick(const int64_t (&c)[D], int d) {
+  int64_t v = c[0];
+#pragma unroll
+  for (int e = 1; e < D; ++e) v = (d == e) ? c[e] : v;
+  return v;
+}
+
+// Bucket label of a point: lambda steps down the heap-ordered skeleton.  Nodes
+// that are external above level lambda carry the all-left splitter, so every
+// walk takes exactly lambda steps and ends at the leftmost depth-lambda
+// position below its external node.
+template <int D>
+__device__ inline int route(const int64_t (&c)[D], const int64_t* sx, const uint8_t* sdim, int lambda) {
+  int v = 1;
+  for (int l = 0; l < lambda; ++l) v = 2 * v + (pick<D>(c, sdim[v]) >= sx[v] ? 1 : 0);
+  return v - (1 << lambda);
+}
+
+__device__ inline int find_owner(const int64_t* off, int n, int64_t t) {
+  // largest s with off[s] <= t
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Candidate threshold exponent: keys below 2^(64-t) are candidates, so that a
+// subproblem of m points keeps about m/2^t in [1.25 s, 2.5 s) of them.
+__host__ __device__ inline int cand_shift(int64_t m, int s) {
+  int t = 0;
+  while (4 * m >= 5 * static_cast<int64_t>(s) * (int64_t{2} << t) && t < 62) ++t;
+  return t;
+}
+
+// ---------------------------------------------------------------- classify
+__global__ void k_classify(const Task* front, int n_front, int s, Task* sieve, int* n_sieve, Task* fin,
+                           int* n_fin) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_front) return;
+  Task t = front[i];
+  if (t.m >= s) sieve[atomicAdd(n_sieve, 1)] = t;
+  else fin[atomicAdd(n_fin, 1)] = t;
+}
+
+// ------------------------------------------------------------ tile layout
+// Single workgroup: exclusive prefix sums of tiles and chunks per subproblem.
+__global__ void k_tile_scan(const Task* sp, int ns, int tile, int64_t* tile_off, int64_t* chunk_off,
+                            int8_t* shift, int s, int small_max, const int8_t* shift_override) {
+  __shared__ int64_t part_t[1024], part_c[1024];
+  int tid = threadIdx.x, nt = blockDim.x;
+  int per = (ns + nt - 1) / nt;
+  int b = tid * per, e = min(ns, b + per);
+  int64_t st = 0, sc = 0;
+  for (int i = b; i < e; ++i) {
+    int64_t tiles = (sp[i].m + tile - 1) / tile;
+    st += tiles;
+    sc += (tiles + kChunkTiles - 1) / kChunkTiles;
+  }
+  part_t[tid] = st;
+  part_c[tid] = sc;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t a = 0, c = 0;
+    for (int i = 0; i < nt; ++i) {
+      int64_t x = part_t[i], y = part_c[i];
+      part_t[i] = a;
+      part_c[i] = c;
+      a += x;
+      c += y;
+    }
+    tile_off[ns] = a;
+    chunk_off[ns] = c;
+  }
+  __syncthreads();
+  st = part_t[tid];
+  sc = part_c[tid];
+  for (int i = b; i < e; ++i) {
+    tile_off[i] = st;
+    chunk_off[i] = sc;
+    int64_t tiles = (sp[i].m + tile - 1) / tile;
+    st += tiles;
+    sc += (tiles + kChunkTiles - 1) / kChunkTiles;
+    int sh = sp[i].m <= small_max ? 0 : cand_shift(sp[i].m, s);
+    if (shift_override && shift_override[i] >= 0) sh = shift_override[i];
+    shift[i] = static_cast<int8_t>(sh);
+  }
+}
+
+// ------------------------------------------------------------- candidates
+// For subproblems larger than small_max: every point whose sampling key falls
+// below the subproblem's threshold is appended (key, position) to that
+// subproblem's candidate list.  Appends are wave-aggregated.
+__global__ void k_candidates(const Task* sp, int ns, const int64_t* tile_off, int tile, Bufs bufs, int src,
+                             uint64_t seed, const int8_t* shift, int small_max, uint64_t* cand_key,
+                             uint32_t* cand_pos, uint32_t* cand_cnt, int cap) {
+  __shared__ int sig_sh;
+  int64_t t = blockIdx.x;
+  if (threadIdx.x == 0) sig_sh = find_owner(tile_off, ns, t);
+  __syncthreads();
+  int sig = sig_sh;
+  Task q = sp[sig];
+  if (q.m <= small_max) return;
+  int sh = shift[sig];
+  uint64_t thr = sh == 0 ? ~0ULL : (~0ULL >> sh);   // key <= thr  <=>  key < 2^(64-sh)
+  int64_t lo = (t - tile_off[sig]) * tile;
+  int64_t hi = min<int64_t>(lo + tile, q.m);
+  const int64_t* ids = bufs.id[src] + q.start;
+  uint64_t* kout = cand_key + static_cast<int64_t>(sig) * cap;
+  uint32_t* pout = cand_pos + static_cast<int64_t>(sig) * cap;
+  for (int64_t base = lo; base < hi; base += kBlock) {
+    int64_t i = base + threadIdx.x;
+    uint64_t key = 0;
+    bool take = false;
+    if (i < hi) {
+      key = sample_key(seed, q.depth, ids[i]);
+      take = key <= thr;
+    }
+    unsigned long long mask = __ballot(take);
+    if (mask == 0) continue;
+    int leader = __ffsll(static_cast<long long>(mask)) - 1;
+    uint32_t wbase = 0;
+    if (lane_id() == static_cast<uint32_t>(leader)) wbase = atomicAdd(cand_cnt + sig, static_cast<uint32_t>(__popcll(mask)));
+    wbase = __shfl(wbase, leader);
+    if (take) {
+      uint32_t k = wbase + static_cast<uint32_t>(__popcll(mask & ((1ULL << lane_id()) - 1)));
+      if (k < static_cast<uint32_t>(cap)) {
+        kout[k] = key;
+        pout[k] = static_cast<uint32_t>(i);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------- LDS presorted kd build
+// Shared pieces of the skeleton kernel and the finisher kernel.  Points are
+// held in LDS as 30-bit coordinates; O[d] lists the points sorted by
+// coordinate d (ties by index).  A node owns the same position range [a, a+L)
+// in every O[d], so its widest dimension and its upper median are read
+// directly, and a split is a stable partition of each O[d] by the side flag.
+
+// Bitonic sort of n2 (power of two) 64-bit keys, ascending.
+__device__ void lds_bitonic(uint64_t* key, int n2) {
+  for (int k = 2; k <= n2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < (n2 >> 1); i += blockDim.x) {
+        int lo = 2 * i - (i & (j - 1));
+        int hi = lo + j;
+        bool up = (lo & k) == 0;
+        uint64_t a = key[lo], b = key[hi];
+        if ((a > b) == up) {
+          key[lo] = b;
+          key[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Sort each dimension: O[d][p] = index of the p-th smallest (coordinate, index).
+template <int D>
+__device__ void lds_presort(const uint32_t* C, uint16_t* O, uint64_t* key, int m, int P) {
+  int n2 = 1;
+  while (n2 < m) n2 <<= 1;
+  for (int d = 0; d < D; ++d) {
+    for (int i = threadIdx.x; i < n2; i += blockDim.x)
+      key[i] = i < m ? (static_cast<uint64_t>(C[d * P + i]) << 16) | static_cast<uint64_t>(i) : ~0ULL;
+    __syncthreads();
+    lds_bitonic(key, n2);
+    for (int i = threadIdx.x; i < m; i += blockDim.x) O[d * P + i] = static_cast<uint16_t>(key[i] & 0xFFFF);
+    __syncthreads();
+  }
+}
+
+// Split rule of a node that owns positions [a, a+L) (L >= 1): widest
+// dimension (max - min, lowest index on ties), upper median v[floor(L/2)],
+// moved to the next larger distinct value if it equals the minimum.
+// Returns false when the node has zero width in every dimension.
+template <int D>
+__device__ bool lds_split_rule(const uint32_t* C, const uint16_t* O, int P, int a, int L, int* od, uint32_t* ox,
+                               int* onl) {
+  int best = -1;
+  uint32_t bw = 0;
+  for (int d = 0; d < D; ++d) {
+    uint32_t lo = C[d * P + O[d * P + a]];
+    uint32_t hi = C[d * P + O[d * P + a + L - 1]];
+    if (hi - lo > bw) {   // strict: the lowest index wins ties
+      bw = hi - lo;
+      best = d;
+    }
+  }
+  if (best < 0) return false;
+  const uint32_t* Cd = C + best * P;
+  const uint16_t* Od = O + best * P;
+  uint32_t mn = Cd[Od[a]];
+  uint32_t x = Cd[Od[a + L / 2]];
+  if (x == mn) {
+    // first position with value > mn
+    int lo = a, hi = a + L - 1;   // Cd[Od[hi]] > mn since the width is positive
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (Cd[Od[mid]] > mn) hi = mid; else lo = mid + 1;
+    }
+    x = Cd[Od[lo]];
+  }
+  // number of values < x
+  int lo = a, hi = a + L;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (Cd[Od[mid]] < x) lo = mid + 1; else hi = mid;
+  }
+  *od = best;
+  *ox = x;
+  *onl = lo - a;
+  return true;
+}
+
+// Block-wide exclusive scan of small non-negative counts in position order:
+// F[p] = sum of v[q] for q < p, for p in [0, n].  One value per position.
+__device__ void lds_exscan_u8(const uint8_t* v, uint16_t* F, int n, uint32_t* part) {
+  int nt = blockDim.x, tid = threadIdx.x;
+  int per = (n + nt - 1) / nt;
+  int b = tid * per, e = min(n, b + per);
+  uint32_t s = 0;
+  for (int p = b; p < e; ++p) s += v[p];
+  part[tid] = s;
+  __syncthreads();
+  if (tid < 64) {
+    // one wave scans the block partials
+    uint32_t acc = 0;
+    for (int base = 0; base < nt; base += 64) {
+      uint32_t x = (base + tid < nt) ? part[base + tid] : 0;
+      uint32_t incl = x;
+      for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o);
+        if (tid >= o) incl += y;
+      }
+      if (base + tid < nt) part[base + tid] = acc + incl - x;
+      acc += __shfl(incl, 63);
+    }
+  }
+  __syncthreads();
+  s = part[tid];
+  for (int p = b; p < e; ++p) {
+    F[p] = static_cast<uint16_t>(s);
+    s += v[p];
+  }
+  if (e == n && b < e) F[n] = static_cast<uint16_t>(s);
+  if (n == 0 && tid == 0) F[0] = 0;
+  __syncthreads();
+}
+
+// Stable partition of every O[d] inside the nodes that split at this step.
+// seg_of_pt[e] is the node (segment slot) of point e or kNone; for split
+// segments segA/segNL give the start and the left count; flag[e] = 1 sends e
+// left.  Points of non-splitting segments keep their positions.
+constexpr uint16_t kNone = 0xFFFF;
+
+template <int D>
+__device__ void lds_partition(uint16_t* O, uint16_t* Otmp, int P, int m, const uint16_t* seg_of_pt,
+                              const uint8_t* splits, const uint16_t* segA, const uint16_t* segNL,
+                              const uint8_t* flag, uint8_t* fpos, uint16_t* F, uint32_t* part) {
+  for (int d = 0; d < D; ++d) {
+    uint16_t* Od = O + d * P;
+    for (int p = threadIdx.x; p < m; p += blockDim.x) {
+      uint16_t e = Od[p];
+      uint16_t k = seg_of_pt[e];
+      fpos[p] = (k != kNone && splits[k]) ? flag[e] : 0;
+    }
+    __syncthreads();
+    lds_exscan_u8(fpos, F, m, part);
+    for (int p = threadIdx.x; p < m; p += blockDim.x) {
+      uint16_t e = Od[p];
+      uint16_t k = seg_of_pt[e];
+      int np = p;
+      if (k != kNone && splits[k]) {
+        int a = segA[k];
+        int lrank = F[p] - F[a];
+        np = flag[e] ? a + lrank : a + segNL[k] + (p - a - lrank);
+      }
+      Otmp[np] = e;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < m; p += blockDim.x) Od[p] = Otmp[p];
+    __syncthreads();
+  }
+}
+
+// LDS layouts (byte offsets), computed identically on host and device.  The
+// 8-byte arrays come first so every array is naturally aligned.
+__host__ __device__ inline int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+__host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t{7}; }
+
+struct SkelLayout {
+  size_t key, C, O, Otmp, node_of, F, flag, fpos, end;
+  __host__ __device__ SkelLayout(int D, int P) {
+    size_t o = 0;
+    key = o;      o += sizeof(uint64_t) * next_pow2(P);
+    C = o;        o += sizeof(uint32_t) * D * P;
+    O = o;        o += sizeof(uint16_t) * D * P;
+    Otmp = o;     o += sizeof(uint16_t) * P;
+    node_of = o;  o += sizeof(uint16_t) * P;
+    F = o;        o += sizeof(uint16_t) * (P + 8);
+    flag = o;     o += P;
+    fpos = o;     o += P;
+    end = align8(o);
+  }
+};
+
+struct FinLayout {
+  size_t IDS, key, C, O, Otmp, seg, F, flag, fpos, lA0, lA1, lL0, lL1, lN0, lN1, sxs, snl, srank, sdm, ssplit, end;
+  int MS;   // segments per level: splitting segments hold > phi points each
+  __host__ __device__ FinLayout(int D, int P, int phi) {
+    MS = min(P, 2 * P / (phi + 1) + 2);
+    size_t o = 0;
+    IDS = o;    o += sizeof(int64_t) * P;
+    key = o;    o += sizeof(uint64_t) * P;
+    lN0 = o;    o += sizeof(int32_t) * MS;
+    lN1 = o;    o += sizeof(int32_t) * MS;
+    sxs = o;    o += sizeof(uint32_t) * MS;
+    C = o;      o += sizeof(uint32_t) * D * P;
+    O = o;      o += sizeof(uint16_t) * D * P;
+    Otmp = o;   o += sizeof(uint16_t) * P;
+    seg = o;    o += sizeof(uint16_t) * P;
+    F = o;      o += sizeof(uint16_t) * (P + 8);
+    lA0 = o;    o += sizeof(uint16_t) * MS;
+    lA1 = o;    o += sizeof(uint16_t) * MS;
+    lL0 = o;    o += sizeof(uint16_t) * MS;
+    lL1 = o;    o += sizeof(uint16_t) * MS;
+    snl = o;    o += sizeof(uint16_t) * MS;
+    srank = o;  o += sizeof(uint16_t) * MS;
+    flag = o;   o += P;
+    fpos = o;   o += P;
+    sdm = o;    o += MS;
+    ssplit = o; o += MS;
+    end = align8(o);
+  }
+};
+
+// ------------------------------------------------- select sample + skeleton
+// One workgroup per sieve subproblem.  Phase 1 finds the s smallest (key, id)
+// among the candidates (radix select over the 64-bit keys, ties by id);
+// phase 2 gathers their coordinates and builds the lambda-level skeleton.
+struct SelectOut {
+  int64_t* rx;        // [ns][2^lambda] splitters in routing form
+  uint8_t* rdim;      // [ns][2^lambda]
+  int8_t* ext;        // [ns][2^(lambda+1)] external flags (reachable nodes only)
+  int* root_ext_list; // subproblems whose skeleton root is external
+  int* n_root_ext;
+  int8_t* shift_fix;  // retry: corrected threshold exponent per subproblem (-1 = ok)
+  int* flags;
+};
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_select_skeleton(const Task* sp, int ns, Bufs bufs, int src,
+                                                            uint64_t seed, int s, int lambda,
+                                                            const int8_t* shift, int small_max,
+                                                            const uint64_t* cand_key, const uint32_t* cand_pos,
+                                                            const uint32_t* cand_cnt, int cap, SelectOut out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int sig = blockIdx.x;
+  const Task q = sp[sig];
+  const int tid = threadIdx.x;
+  const int64_t* ids = bufs.id[src] + q.start;
+  const int64_t* X = bufs.c[src];
+  const int64_t xcap = bufs.cap[src];
+  const int P = s;   // padded stride of the per-dimension arrays
+
+  __shared__ uint32_t hist[256];
+  __shared__ int sh_c, sh_done, sh_pass, sh_need, sh_cnt, sh_bad;
+  __shared__ uint64_t sh_prefix, sh_T;
+  __shared__ int sh_tie_n;
+  __shared__ uint32_t tie_pos[256];
+  __shared__ int64_t tie_id[256];
+
+  // ---- phase 1: candidate keys into LDS
+  uint64_t* K = reinterpret_cast<uint64_t*>(smem);
+  uint32_t* Pos = reinterpret_cast<uint32_t*>(smem + sizeof(uint64_t) * cap);
+  if (tid == 0) {
+    int c;
+    if (q.m <= small_max) {
+      c = q.m;
+    } else {
+      c = static_cast<int>(cand_cnt[sig]);
+    }
+    sh_c = c;
+    sh_bad = 0;
+    if (q.m > small_max && (c > cap || c < s)) {
+      // retry with a threshold that keeps more (underflow) or fewer (overflow)
+      int sh0 = shift[sig];
+      out.shift_fix[sig] = static_cast<int8_t>(c > cap ? sh0 + 1 : max(0, sh0 - 1));
+      atomicOr(out.flags, c > cap ? kErrCandOverflow : kErrCandUnderflow);
+      sh_bad = 1;
+    }
+  }
+  __syncthreads();
+  if (sh_bad) return;
+  const int c = sh_c;
+  if (q.m <= small_max) {
+    for (int i = tid; i < c; i += kBlock) {
+      K[i] = sample_key(seed, q.depth, ids[i]);
+      Pos[i] = static_cast<uint32_t>(i);
+    }
+  } else {
+    const uint64_t* kin = cand_key + static_cast<int64_t>(sig) * cap;
+    const uint32_t* pin = cand_pos + static_cast<int64_t>(sig) * cap;
+    for (int i = tid; i < c; i += kBlock) {
+      K[i] = kin[i];
+      Pos[i] = pin[i];
+    }
+  }
+  if (tid == 0) {
+    sh_done = 0;
+    sh_pass = 0;
+    sh_need = s;
+    sh_prefix = 0;
+    sh_cnt = 0;
+    sh_tie_n = 0;
+  }
+  __syncthreads();
+  // radix select over the 8 bytes of the key, most significant first
+  for (int pass = 0; pass < 8; ++pass) {
+    for (int i = tid; i < 256; i += kBlock) hist[i] = 0;
+    __syncthreads();
+    const int shv = 56 - 8 * pass;
+    const uint64_t prefix = sh_prefix;
+    for (int i = tid; i < c; i += kBlock) {
+      uint64_t k = K[i];
+      bool match = pass == 0 || (k >> (64 - 8 * pass)) == prefix;
+      if (match) atomicAdd(&hist[(k >> shv) & 255], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int need = sh_need;
+      uint32_t cum = 0;
+      int b = 0;
+      for (; b < 255; ++b) {
+        if (cum + hist[b] >= static_cast<uint32_t>(need)) break;
+        cum += hist[b];
+      }
+      if (cum + hist[b] == static_cast<uint32_t>(need)) {
+        sh_done = 1;
+        sh_pass = pass;
+        sh_T = (prefix << 8) | static_cast<uint64_t>(b);
+      } else {
+        sh_need = need - static_cast<int>(cum);
+        sh_prefix = (prefix << 8) | static_cast<uint64_t>(b);
+      }
+    }
+    __syncthreads();
+    if (sh_done) break;
+  }
+  uint16_t* samp = reinterpret_cast<uint16_t*>(smem + (sizeof(uint64_t) + sizeof(uint32_t)) * cap);
+  if (sh_done) {
+    const int bits = 8 * (sh_pass + 1);
+    const uint64_t T = sh_T;
+    for (int i = tid; i < c; i += kBlock) {
+      if ((K[i] >> (64 - bits)) <= T) {
+        int k = atomicAdd(&sh_cnt, 1);
+        if (k < s) samp[k] = static_cast<uint16_t>(i);
+      }
+    }
+  } else {
+    // All 64 key bits fixed: sh_prefix is the s-th smallest key K*; take the
+    // keys below it and the sh_need smallest ids among those equal to it.
+    const uint64_t Ks = sh_prefix;
+    for (int i = tid; i < c; i += kBlock) {
+      if (K[i] < Ks) {
+        int k = atomicAdd(&sh_cnt, 1);
+        if (k < s) samp[k] = static_cast<uint16_t>(i);
+      } else if (K[i] == Ks) {
+        int k = atomicAdd(&sh_tie_n, 1);
+        if (k < 256) {
+          tie_pos[k] = static_cast<uint32_t>(i);
+          tie_id[k] = ids[Pos[i]];
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int nt = min(sh_tie_n, 256);
+      if (sh_tie_n > 256) atomicOr(out.flags, kErrInternal);
+      for (int r = 0; r < sh_need; ++r) {
+        int best = -1;
+        for (int j = 0; j < nt; ++j)
+          if (tie_pos[j] != 0xFFFFFFFFu && (best < 0 || tie_id[j] < tie_id[best])) best = j;
+        if (best < 0) break;
+        int k = sh_cnt++;
+        if (k < s) samp[k] = static_cast<uint16_t>(tie_pos[best]);
+        tie_pos[best] = 0xFFFFFFFFu;
+      }
+    }
+  }
+  __syncthreads();
+  if (sh_cnt != s) {
+    if (tid == 0) atomicOr(out.flags, kErrInternal);
+    return;
+  }
+  // translate candidate slots into positions inside the subproblem
+  uint32_t* sampPos = reinterpret_cast<uint32_t*>(smem + (sizeof(uint64_t) + sizeof(uint32_t)) * cap +
+                                                  sizeof(uint16_t) * s);
+  for (int i = tid; i < s; i += kBlock) sampPos[i] = Pos[samp[i]];
+  __syncthreads();
+  // keep sampPos; the rest of LDS is reused below.  Layout of phase 2:
+  uint32_t sp_copy_reg[kMaxSample / kBlock];
+#pragma unroll
+  for (int k = 0; k < kMaxSample / kBlock; ++k) {
+    const int i = tid + k * kBlock;
+    sp_copy_reg[k] = i < s ? sampPos[i] : 0;
+  }
+  __syncthreads();
+
+  // ---- phase 2: skeleton on the sample
+  SkelLayout lay(D, P);
+  uint64_t* key = reinterpret_cast<uint64_t*>(smem + lay.key);
+  uint32_t* C = reinterpret_cast<uint32_t*>(smem + lay.C);
+  uint16_t* O = reinterpret_cast<uint16_t*>(smem + lay.O);
+  uint16_t* Otmp = reinterpret_cast<uint16_t*>(smem + lay.Otmp);
+  uint16_t* node_of = reinterpret_cast<uint16_t*>(smem + lay.node_of);
+  uint16_t* F = reinterpret_cast<uint16_t*>(smem + lay.F);
+  uint8_t* flag = smem + lay.flag;
+  uint8_t* fpos = smem + lay.fpos;
+  __shared__ uint32_t part[kBlock];
+  __shared__ uint16_t segA[2 << kMaxLambda], segL[2 << kMaxLambda], segNL[2 << kMaxLambda];
+  __shared__ uint8_t live[2 << kMaxLambda], splits[2 << kMaxLambda], sdim[1 << kMaxLambda];
+  __shared__ uint32_t sx[1 << kMaxLambda];
+
+#pragma unroll
+  for (int k = 0; k < kMaxSample / kBlock; ++k) {
+    const int i = tid + k * kBlock;
+    if (i < s) {
+      const int64_t pos = q.start + static_cast<int64_t>(sp_copy_reg[k]);
+      for (int d = 0; d < D; ++d) C[d * P + i] = static_cast<uint32_t>(X[d * xcap + pos]);
+      node_of[i] = 1;
+    }
+  }
+  const int nheap = 2 << lambda;
+  for (int v = tid; v < nheap; v += kBlock) {
+    live[v] = 0;
+    splits[v] = 0;
+  }
+  __syncthreads();
+  lds_presort<D>(C, O, key, s, P);
+  if (tid == 0) {
+    live[1] = 1;
+    segA[1] = 0;
+    segL[1] = static_cast<uint16_t>(s);
+  }
+  __syncthreads();
+  for (int level = 0; level < lambda; ++level) {
+    const int v0 = 1 << level, v1 = 2 << level;
+    for (int v = v0 + tid; v < v1; v += kBlock) {
+      splits[v] = 0;
+      if (!live[v]) continue;
+      int d, nl;
+      uint32_t x;
+      if (lds_split_rule<D>(C, O, P, segA[v], segL[v], &d, &x, &nl) && nl > 0 && nl < segL[v]) {
+        splits[v] = 1;
+        sdim[v] = static_cast<uint8_t>(d);
+        sx[v] = x;
+        segNL[v] = static_cast<uint16_t>(nl);
+        live[2 * v] = live[2 * v + 1] = 1;
+        segA[2 * v] = segA[v];
+        segL[2 * v] = static_cast<uint16_t>(nl);
+        segA[2 * v + 1] = static_cast<uint16_t>(segA[v] + nl);
+        segL[2 * v + 1] = static_cast<uint16_t>(segL[v] - nl);
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < s; e += kBlock) {
+      int v = node_of[e];
+      flag[e] = splits[v] ? (C[sdim[v] * P + e] < sx[v] ? 1 : 0) : 0;
+    }
+    __syncthreads();
+    lds_partition<D>(O, Otmp, P, s, node_of, splits, segA, segNL, flag, fpos, F, part);
+    for (int e = tid; e < s; e += kBlock) {
+      int v = node_of[e];
+      if (splits[v]) node_of[e] = static_cast<uint16_t>(2 * v + (flag[e] ? 0 : 1));
+    }
+    __syncthreads();
+  }
+  // routing form: interior nodes keep (dim, x); everything else sends left
+  const int NB = 1 << lambda;
+  int64_t* rx = out.rx + static_cast<int64_t>(sig) * NB;
+  uint8_t* rd = out.rdim + static_cast<int64_t>(sig) * NB;
+  int8_t* ex = out.ext + static_cast<int64_t>(sig) * nheap;
+  for (int v = tid; v < nheap; v += kBlock) {
+    bool interior = v < NB && live[v] && splits[v];
+    if (v < NB) {
+      rx[v] = interior ? static_cast<int64_t>(sx[v]) : kAllLeft;
+      rd[v] = interior ? sdim[v] : 0;
+    }
+    ex[v] = (live[v] && !interior) ? 1 : 0;
+  }
+  if (tid == 0 && !splits[1]) {
+    int k = atomicAdd(out.n_root_ext, 1);
+    out.root_ext_list[k] = sig;
+  }
+}
+
+// ------------------------------------------------------------------ count
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_count(const Task* sp, int ns, const int64_t* tile_off, int tile,
+                                                  Bufs bufs, int src, const int64_t* rx, const uint8_t* rdim,
+                                                  const int8_t* mode, int lambda, uint32_t* A, int check,
+                                                  int* flags) {
+  __shared__ int64_t sx[1 << kMaxLambda];
+  __shared__ uint8_t sd[1 << kMaxLambda];
+  __shared__ uint32_t hist[1 << kMaxLambda];
+  __shared__ int sig_sh;
+  const int NB = 1 << lambda;
+  const int64_t t = blockIdx.x;
+  if (threadIdx.x == 0) sig_sh = find_owner(tile_off, ns, t);
+  for (int j = threadIdx.x; j < NB; j += kBlock) hist[j] = 0;
+  __syncthreads();
+  const int sig = sig_sh;
+  const Task q = sp[sig];
+  if (mode[sig] == 1) {   // heavy leaf: nothing moves
+    for (int j = threadIdx.x; j < NB; j += kBlock) A[t * NB + j] = 0;
+    return;
+  }
+  for (int j = threadIdx.x; j < NB; j += kBlock) {
+    sx[j] = rx[static_cast<int64_t>(sig) * NB + j];
+    sd[j] = rdim[static_cast<int64_t>(sig) * NB + j];
+  }
+  __syncthreads();
+  const int64_t lo = q.start + (t - tile_off[sig]) * tile;
+  const int64_t hi = min<int64_t>(lo + tile, static_cast<int64_t>(q.start) + q.m);
+  const int64_t* X = bufs.c[src];
+  const int64_t cap = bufs.cap[src];
+  bool bad = false;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+    int64_t c[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      c[d] = X[d * cap + i];
+      bad |= static_cast<uint64_t>(c[d]) >= static_cast<uint64_t>(kCoordLimit);
+    }
+    atomicAdd(&hist[route<D>(c, sx, sd, lambda)], 1u);
+  }
+  if (check && bad) atomicOr(flags, kErrRange);
+  __syncthreads();
+  for (int j = threadIdx.x; j < NB; j += kBlock) A[t * NB + j] = hist[j];
+}
+
+// ------------------------------------------------------------------- scan
+// Column sums of each chunk of kChunkTiles tiles.
+__global__ void k_chunk_sum(const int64_t* chunk_off, const int64_t* tile_off, int ns, int lambda,
+                            const uint32_t* A, uint32_t* S) {
+  __shared__ int sig_sh;
+  __shared__ uint32_t part[kBlock];
+  const int NB = 1 << lambda;
+  const int64_t c = blockIdx.x;
+  if (threadIdx.x == 0) sig_sh = find_owner(chunk_off, ns, c);
+  __syncthreads();
+  const int sig = sig_sh;
+  const int64_t t0 = tile_off[sig] + (c - chunk_off[sig]) * kChunkTiles;
+  const int64_t t1 = min<int64_t>(t0 + kChunkTiles, tile_off[sig + 1]);
+  const int j = threadIdx.x % NB, lane = threadIdx.x / NB, lanes = kBlock / NB;
+  uint32_t acc = 0;
+  for (int64_t t = t0 + lane; t < t1; t += lanes) acc += A[t * NB + j];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < NB) {
+    uint32_t s = 0;
+    for (int l = 0; l < lanes; ++l) s += part[l * NB + threadIdx.x];
+    S[c * NB + threadIdx.x] = s;
+  }
+}
+
+// Per subproblem: exclusive prefix of the chunk sums over chunks (per bucket),
+// bucket sizes and bucket starts (prefix over buckets, offset by the start).
+__global__ void k_sp_scan(const Task* sp, const int64_t* chunk_off, int lambda, uint32_t* S, int32_t* bsize,
+                          int32_t* bstart) {
+  __shared__ uint32_t part[kBlock];
+  __shared__ uint32_t tot[1 << kMaxLambda];
+  const int NB = 1 << lambda;
+  const int sig = blockIdx.x;
+  const int64_t c0 = chunk_off[sig], c1 = chunk_off[sig + 1];
+  const int j = threadIdx.x % NB, lane = threadIdx.x / NB, lanes = kBlock / NB;
+  const int64_t nc = c1 - c0;
+  const int64_t per = (nc + lanes - 1) / lanes;
+  const int64_t b = c0 + lane * per, e = min(c1, b + per);
+  uint32_t acc = 0;
+  for (int64_t c = b; c < e; ++c) acc += S[c * NB + j];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < NB) {
+    uint32_t run = 0;
+    for (int l = 0; l < lanes; ++l) {
+      uint32_t x = part[l * NB + threadIdx.x];
+      part[l * NB + threadIdx.x] = run;
+      run += x;
+    }
+    tot[threadIdx.x] = run;
+  }
+  __syncthreads();
+  uint32_t run = part[threadIdx.x];
+  for (int64_t c = b; c < e; ++c) {
+    uint32_t x = S[c * NB + j];
+    S[c * NB + j] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0) {
+    int32_t at = sp[sig].start;
+    for (int k = 0; k < NB; ++k) {
+      bsize[static_cast<int64_t>(sig) * NB + k] = static_cast<int32_t>(tot[k]);
+      bstart[static_cast<int64_t>(sig) * NB + k] = at;
+      at += static_cast<int32_t>(tot[k]);
+    }
+  }
+}
+
+// B[t][j] = bucket start + prefix over earlier chunks + prefix over earlier
+// tiles of the chunk: the write cursor of tile t for bucket j.
+__global__ void k_apply(const int64_t* chunk_off, const int64_t* tile_off, int ns, int lambda, const uint32_t* A,
+                        const uint32_t* S, const int32_t* bstart, int32_t* B) {
+  __shared__ int sig_sh;
+  const int NB = 1 << lambda;
+  const int64_t c = blockIdx.x;
+  if (threadIdx.x == 0) sig_sh = find_owner(chunk_off, ns, c);
+  __syncthreads();
+  const int sig = sig_sh;
+  const int64_t t0 = tile_off[sig] + (c - chunk_off[sig]) * kChunkTiles;
+  const int64_t t1 = min<int64_t>(t0 + kChunkTiles, tile_off[sig + 1]);
+  for (int j = threadIdx.x; j < NB; j += kBlock) {
+    int32_t run = bstart[static_cast<int64_t>(sig) * NB + j] + static_cast<int32_t>(S[c * NB + j]);
+    for (int64_t t = t0; t < t1; ++t) {
+      B[t * NB + j] = run;
+      run += static_cast<int32_t>(A[t * NB + j]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- scatter
+// Stable distribution of one tile.  Each wave ranks its 64 consecutive points
+// among equal labels with ballots; chunk counts are scanned in LDS; every
+// array (D coordinates, then ids) is staged in LDS in bucket order and written
+// out as contiguous runs.
+template <int D, int PPT>
+__global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, const int64_t* tile_off, Bufs bufs,
+                                                    int src, int dst, const int64_t* rx, const uint8_t* rdim,
+                                                    const int8_t* mode, int lambda, const int32_t* B) {
+  constexpr int T = kBlock * PPT;
+  constexpr int NCH = T / 64;
+  __shared__ int64_t sx[1 << kMaxLambda];
+  __shared__ uint8_t sd[1 << kMaxLambda];
+  __shared__ int32_t cur[1 << kMaxLambda];
+  __shared__ uint16_t cnt[NCH][1 << kMaxLambda];
+  __shared__ uint16_t ls[(1 << kMaxLambda) + 1];
+  __shared__ int64_t stage[T];
+  __shared__ uint8_t slab[T];
+  __shared__ int sig_sh;
+  const int NB = 1 << lambda;
+  const int64_t t = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (tid == 0) sig_sh = find_owner(tile_off, ns, t);
+  for (int i = tid; i < NCH * (1 << kMaxLambda); i += kBlock) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+  const int sig = sig_sh;
+  if (mode[sig] == 1) return;
+  const Task q = sp[sig];
+  for (int j = tid; j < NB; j += kBlock) {
+    sx[j] = rx[static_cast<int64_t>(sig) * NB + j];
+    sd[j] = rdim[static_cast<int64_t>(sig) * NB + j];
+    cur[j] = B[t * NB + j];
+  }
+  __syncthreads();
+  const int64_t lo = q.start + (t - tile_off[sig]) * T;
+  const int len = static_cast<int>(min<int64_t>(T, static_cast<int64_t>(q.start) + q.m - lo));
+  const int64_t* X = bufs.c[src];
+  const int64_t cap = bufs.cap[src];
+  const uint32_t lane = lane_id();
+  const int wave = tid >> 6;
+  const unsigned long long lt = (1ULL << lane) - 1;
+  int64_t val[PPT][D];
+  int lab[PPT];
+  int rank[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int li = k * kBlock + tid;
+    const bool ok = li < len;
+    int label = 0;
+    if (ok) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) val[k][d] = X[d * cap + lo + li];
+      label = route<D>(val[k], sx, sd, lambda);
+    }
+    unsigned long long peers = __ballot(ok);
+    for (int b = 0; b < lambda; ++b) {
+      unsigned long long m = __ballot((label >> b) & 1);
+      peers &= ((label >> b) & 1) ? m : ~m;
+    }
+    lab[k] = label;
+    rank[k] = __popcll(peers & lt);
+    const int ch = k * (kBlock / 64) + wave;
+    if (ok && (peers & lt) == 0) cnt[ch][label] = static_cast<uint16_t>(__popcll(peers));
+  }
+  __syncthreads();
+  for (int j = tid; j < NB; j += kBlock) {
+    uint16_t run = 0;
+    for (int ch = 0; ch < NCH; ++ch) {
+      uint16_t x = cnt[ch][j];
+      cnt[ch][j] = run;
+      run += x;
+    }
+    ls[j] = run;   // total of bucket j in this tile, scanned below
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint16_t run = 0;
+    for (int j = 0; j < NB; ++j) {
+      uint16_t x = ls[j];
+      ls[j] = run;
+      run += x;
+    }
+    ls[NB] = run;
+  }
+  __syncthreads();
+  int lpos[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int li = k * kBlock + tid;
+    const int ch = k * (kBlock / 64) + wave;
+    lpos[k] = -1;
+    if (li < len) {
+      lpos[k] = ls[lab[k]] + cnt[ch][lab[k]] + rank[k];
+      slab[lpos[k]] = static_cast<uint8_t>(lab[k]);
+    }
+  }
+  __syncthreads();
+  int64_t* Y = bufs.c[dst];
+  const int64_t ycap = bufs.cap[dst];
+  const int64_t* Iin = bufs.id[src];
+  int64_t* Iout = bufs.id[dst];
+  for (int a = 0; a <= D; ++a) {
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      if (lpos[k] >= 0) {
+        int64_t v;
+        if (a < D) {
+          v = val[k][0];
+#pragma unroll
+          for (int d = 1; d < D; ++d) v = (a == d) ? val[k][d] : v;
+        } else {
+          v = Iin[lo + k * kBlock + tid];
+        }
+        stage[lpos[k]] = v;
+      }
+    }
+    __syncthreads();
+    int64_t* out = a < D ? Y + a * ycap : Iout;
+    for (int p = tid; p < len; p += kBlock) {
+      const int j = slab[p];
+      out[cur[j] + (p - ls[j])] = stage[p];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------- emit
+// Skeleton nodes of each subproblem become tree nodes; its buckets become
+// tasks of the next round.  One workgroup of 64 threads per subproblem.
+__global__ void k_emit(const Task* sp, int ns, int lambda, const int64_t* rx, const uint8_t* rdim, const int8_t* ext,
+                       const int8_t* mode, const int32_t* bsize, const int32_t* bstart, int dst, Node* nodes,
+                       int* node_count, Task* front, int* n_front, Task* fin, int* n_fin, int* flags) {
+  const int NB = 1 << lambda;
+  const int nheap = 2 << lambda;
+  __shared__ int32_t size[2 << kMaxLambda], off[2 << kMaxLambda], idx[2 << kMaxLambda];
+  __shared__ uint8_t reach[2 << kMaxLambda];
+  const int sig = blockIdx.x;
+  const Task q = sp[sig];
+  if (mode[sig] == 1) {
+    // identical points: one heavy leaf, data stays where it is
+    if (threadIdx.x == 0) {
+      Task h = q;
+      h.mode = 1;
+      fin[atomicAdd(n_fin, 1)] = h;
+    }
+    return;
+  }
+  const int8_t* ex = ext + static_cast<int64_t>(sig) * nheap;
+  for (int j = threadIdx.x; j < NB; j += blockDim.x) {
+    size[NB + j] = bsize[static_cast<int64_t>(sig) * NB + j];
+    off[NB + j] = bstart[static_cast<int64_t>(sig) * NB + j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = NB - 1; v >= 1; --v) {
+      size[v] = size[2 * v] + size[2 * v + 1];
+      off[v] = off[2 * v];
+    }
+    reach[1] = 1;
+    int cnt = 0;
+    for (int v = 2; v < nheap; ++v) {
+      reach[v] = reach[v >> 1] && !ex[v >> 1];
+      if (reach[v]) ++cnt;
+    }
+    int base = atomicAdd(node_count, cnt);
+    idx[1] = q.slot;
+    int r = 0;
+    for (int v = 2; v < nheap; ++v)
+      if (reach[v]) idx[v] = base + r++;
+    const int64_t* sxv = rx + static_cast<int64_t>(sig) * NB;
+    const uint8_t* sdv = rdim + static_cast<int64_t>(sig) * NB;
+    for (int v = 1; v < nheap; ++v) {
+      if (!reach[v]) continue;
+      int level = 31 - __clz(v);
+      if (!ex[v]) {
+        Node nd;
+        nd.x = sxv[v];
+        nd.size = size[v];
+        nd.off = off[v];
+        nd.left = idx[2 * v];
+        nd.right = idx[2 * v + 1];
+        nd.dim = sdv[v];
+        nd.depth = static_cast<int16_t>(q.depth + level);
+        nd.pad = 0;
+        nodes[idx[v]] = nd;
+      } else {
+        if (size[v] <= 0) atomicOr(flags, kErrInternal);
+        Task c;
+        c.start = off[v];
+        c.m = size[v];
+        c.slot = idx[v];
+        c.depth = static_cast<int16_t>(q.depth + level);
+        c.buf = static_cast<int8_t>(dst);
+        c.mode = 0;
+        front[atomicAdd(n_front, 1)] = c;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- finisher
+// Plain construction of a subproblem of m < s points (Section 3: median split
+// on the widest dimension, one level at a time) in LDS, one workgroup per
+// subproblem; P >= m is the padded size of the launch's class.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_finish(const Task* tasks, const int* list, int P, Bufs bufs, int final_buf,
+                                                   int phi, Node* nodes, int* node_count, int64_t node_cap,
+                                                   int* height, int* flags) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Task q = tasks[list[blockIdx.x]];
+  const int m = q.m;
+  const int tid = threadIdx.x;
+  const FinLayout lay(D, P, phi);
+  int64_t* IDS = reinterpret_cast<int64_t*>(smem + lay.IDS);
+  uint64_t* key = reinterpret_cast<uint64_t*>(smem + lay.key);
+  uint32_t* C = reinterpret_cast<uint32_t*>(smem + lay.C);
+  uint16_t* O = reinterpret_cast<uint16_t*>(smem + lay.O);
+  uint16_t* Otmp = reinterpret_cast<uint16_t*>(smem + lay.Otmp);
+  uint16_t* seg = reinterpret_cast<uint16_t*>(smem + lay.seg);
+  uint16_t* F = reinterpret_cast<uint16_t*>(smem + lay.F);
+  uint8_t* flag = smem + lay.flag;
+  uint8_t* fpos = smem + lay.fpos;
+  uint16_t* lA[2] = {reinterpret_cast<uint16_t*>(smem + lay.lA0), reinterpret_cast<uint16_t*>(smem + lay.lA1)};
+  uint16_t* lL[2] = {reinterpret_cast<uint16_t*>(smem + lay.lL0), reinterpret_cast<uint16_t*>(smem + lay.lL1)};
+  int32_t* lN[2] = {reinterpret_cast<int32_t*>(smem + lay.lN0), reinterpret_cast<int32_t*>(smem + lay.lN1)};
+  uint32_t* sxs = reinterpret_cast<uint32_t*>(smem + lay.sxs);
+  uint16_t* snl = reinterpret_cast<uint16_t*>(smem + lay.snl);
+  uint16_t* srank = reinterpret_cast<uint16_t*>(smem + lay.srank);
+  uint8_t* sdm = smem + lay.sdm;
+  uint8_t* ssplit = smem + lay.ssplit;
+  __shared__ uint32_t part[kBlock];
+  __shared__ int sh_nlist, sh_nsplit, sh_base, sh_over, sh_maxdepth;
+
+  const int src = q.buf;
+  const int64_t* X = bufs.c[src];
+  const int64_t xcap = bufs.cap[src];
+  bool bad = false;
+  for (int i = tid; i < m; i += kBlock) {
+    for (int d = 0; d < D; ++d) {
+      int64_t v = X[d * xcap + q.start + i];
+      bad |= static_cast<uint64_t>(v) >= static_cast<uint64_t>(kCoordLimit);
+      C[d * P + i] = static_cast<uint32_t>(v);
+    }
+    IDS[i] = bufs.id[src][q.start + i];
+    seg[i] = 0;
+  }
+  if (bad) atomicOr(flags, kErrRange);
+  if (tid == 0) {
+    sh_nlist = 1;
+    sh_over = 0;
+    sh_maxdepth = 0;
+    lA[0][0] = 0;
+    lL[0][0] = static_cast<uint16_t>(m);
+    lN[0][0] = q.slot;
+  }
+  __syncthreads();
+  if (m > phi) lds_presort<D>(C, O, key, m, P);
+  else
+    for (int i = tid; i < m; i += kBlock) O[i] = static_cast<uint16_t>(i);
+  __syncthreads();
+  int cur = 0;
+  int depth = q.depth;
+  while (true) {
+    const int nl = sh_nlist;
+    if (nl == 0) break;
+    // decide every segment of this level
+    for (int k = tid; k < nl; k += kBlock) {
+      const int a = lA[cur][k], L = lL[cur][k];
+      int d = 0, nleft = 0;
+      uint32_t x = 0;
+      bool split = L > phi && lds_split_rule<D>(C, O, P, a, L, &d, &x, &nleft);
+      if (split && (nleft <= 0 || nleft >= L)) {
+        atomicOr(flags, kErrInternal);
+        split = false;
+      }
+      ssplit[k] = split ? 1 : 0;
+      if (split) {
+        sdm[k] = static_cast<uint8_t>(d);
+        sxs[k] = x;
+        snl[k] = static_cast<uint16_t>(nleft);
+      } else {
+        // leaf (at most phi points, or a heavy leaf of identical points)
+        Node nd;
+        nd.x = 0;
+        nd.size = L;
+        nd.off = q.start + a;
+        nd.left = -1;
+        nd.right = -1;
+        nd.dim = -1;
+        nd.depth = static_cast<int16_t>(depth);
+        nd.pad = 0;
+        const int32_t at = lN[cur][k];
+        if (at < node_cap) nodes[at] = nd;
+        atomicMax(&sh_maxdepth, depth);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int r = 0;
+      for (int k = 0; k < nl; ++k) {
+        srank[k] = static_cast<uint16_t>(r);
+        r += ssplit[k];
+      }
+      sh_nsplit = r;
+      int b = r > 0 ? atomicAdd(node_count, 2 * r) : 0;
+      if (static_cast<int64_t>(b) + 2 * r > node_cap) sh_over = 1;
+      sh_base = b;
+    }
+    __syncthreads();
+    const int nsplit = sh_nsplit;
+    const int nbase = sh_base;
+    const bool over = sh_over != 0;
+    const int nxt = cur ^ 1;
+    for (int k = tid; k < nl; k += kBlock) {
+      if (!ssplit[k]) continue;
+      const int a = lA[cur][k], L = lL[cur][k], r = srank[k];
+      const int cl = nbase + 2 * r, cr = cl + 1;
+      if (!over && lN[cur][k] < node_cap) {
+        Node nd;
+        nd.x = sxs[k];
+        nd.size = L;
+        nd.off = q.start + a;
+        nd.left = cl;
+        nd.right = cr;
+        nd.dim = sdm[k];
+        nd.depth = static_cast<int16_t>(depth);
+        nd.pad = 0;
+        nodes[lN[cur][k]] = nd;
+      }
+      lA[nxt][2 * r] = static_cast<uint16_t>(a);
+      lL[nxt][2 * r] = snl[k];
+      lN[nxt][2 * r] = cl;
+      lA[nxt][2 * r + 1] = static_cast<uint16_t>(a + snl[k]);
+      lL[nxt][2 * r + 1] = static_cast<uint16_t>(L - snl[k]);
+      lN[nxt][2 * r + 1] = cr;
+    }
+    if (nsplit == 0) break;
+    // side flags of the points of splitting segments
+    for (int e = tid; e < m; e += kBlock) {
+      const int k = seg[e];
+      flag[e] = (k != kNone && ssplit[k]) ? (C[sdm[k] * P + e] < sxs[k] ? 1 : 0) : 0;
+    }
+    __syncthreads();
+    lds_partition<D>(O, Otmp, P, m, seg, ssplit, lA[cur], snl, flag, fpos, F, part);
+    for (int e = tid; e < m; e += kBlock) {
+      const int k = seg[e];
+      if (k == kNone) continue;
+      seg[e] = ssplit[k] ? static_cast<uint16_t>(2 * srank[k] + (flag[e] ? 0 : 1)) : kNone;
+    }
+    if (tid == 0) sh_nlist = 2 * nsplit;
+    __syncthreads();
+    cur = nxt;
+    ++depth;
+  }
+  __syncthreads();
+  if (sh_over) {
+    if (tid == 0) atomicOr(flags, kErrNodeOverflow);
+    return;
+  }
+  if (tid == 0) atomicMax(height, sh_maxdepth);
+  int64_t* Y = bufs.c[final_buf];
+  const int64_t ycap = bufs.cap[final_buf];
+  for (int p = tid; p < m; p += kBlock) {
+    const int e = O[p];
+    for (int d = 0; d < D; ++d) Y[d * ycap + q.start + p] = static_cast<int64_t>(C[d * P + e]);
+    bufs.id[final_buf][q.start + p] = IDS[e];
+  }
+}
+
+// Heavy leaf of identical points found by the sieve (m may exceed any LDS
+// size): copy the points into the tree array and write one leaf.
+__global__ void k_finish_heavy(const Task* tasks, const int* list, int D, Bufs bufs, int final_buf, Node* nodes,
+                               int* height) {
+  const Task q = tasks[list[blockIdx.x]];
+  const int src = q.buf;
+  if (src != final_buf) {
+    for (int64_t i = threadIdx.x; i < q.m; i += blockDim.x) {
+      for (int d = 0; d < D; ++d)
+        bufs.c[final_buf][d * bufs.cap[final_buf] + q.start + i] = bufs.c[src][d * bufs.cap[src] + q.start + i];
+      bufs.id[final_buf][q.start + i] = bufs.id[src][q.start + i];
+    }
+  }
+  if (threadIdx.x == 0) {
+    Node nd;
+    nd.x = 0;
+    nd.size = q.m;
+    nd.off = q.start;
+    nd.left = -1;
+    nd.right = -1;
+    nd.dim = -1;
+    nd.depth = q.depth;
+    nd.pad = 0;
+    nodes[q.slot] = nd;
+    atomicMax(height, static_cast<int>(q.depth));
+  }
+}
+
+// Sort finisher tasks into classes by padded size (64, 128, ..., 4096) and
+// heavy leaves (class 7).
+__global__ void k_bin_finish(const Task* fin, int n_fin, int* lists, int stride, int* counts) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_fin) return;
+  const Task t = fin[i];
+  int cls = 7;
+  if (t.mode == 0) {
+    cls = 0;
+    while ((64 << cls) < t.m) ++cls;
+  }
+  lists[cls * stride + atomicAdd(counts + cls, 1)] = i;
+}
+
+// ------------------------------------------- exact split of a large subproblem
+// Used when a subproblem's sample is entirely identical: per-dimension min and
+// max, then an exact radix selection of the upper median.
+template <int D>
+__global__ void k_minmax(const int64_t* X, int64_t cap, int64_t start, int64_t m, unsigned long long* mn,
+                         unsigned long long* mx) {
+  unsigned long long lo[D], hi[D];
+  for (int d = 0; d < D; ++d) {
+    lo[d] = ~0ULL;
+    hi[d] = 0;
+  }
+  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    for (int d = 0; d < D; ++d) {
+      unsigned long long v = static_cast<unsigned long long>(X[d * cap + start + i]);
+      lo[d] = v < lo[d] ? v : lo[d];
+      hi[d] = v > hi[d] ? v : hi[d];
+    }
+  }
+  for (int d = 0; d < D; ++d) {
+    atomicMin(mn + d, lo[d]);
+    atomicMax(mx + d, hi[d]);
+  }
+}
+
+__global__ void k_digit_hist(const int64_t* Xd, int64_t start, int64_t m, int pshift, uint64_t prefix,
+                             int dshift, int dmask, unsigned int* hist) {
+  __shared__ unsigned int h[256];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    uint64_t v = static_cast<uint64_t>(Xd[start + i]);
+    if (pshift >= 64 || (v >> pshift) == prefix) atomicAdd(&h[(v >> dshift) & dmask], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += blockDim.x)
+    if (h[i]) atomicAdd(hist + i, h[i]);
+}
+
+__global__ void k_min_above(const int64_t* Xd, int64_t start, int64_t m, uint64_t v0, unsigned long long* out) {
+  unsigned long long best = ~0ULL;
+  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    unsigned long long v = static_cast<unsigned long long>(Xd[start + i]);
+    if (v > v0 && v < best) best = v;
+  }
+  atomicMin(out, best);
+}
+
+// ------------------------------------------------------------ host helpers
+template <class K>
+int allow_lds(K kernel, size_t bytes) {
+  PKD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(bytes)));
+  return PKD_OK;
+}
+
+template <class T>
+int grow(hipStream_t st, T** p, size_t* cap_elems, size_t need, bool keep) {
+  if (need <= *cap_elems && *p) return PKD_OK;
+  size_t n = std::max<size_t>(need + need / 4, 256);
+  void* q = nullptr;
+  PKD_TRY(dev_alloc(&q, n * sizeof(T), st));
+  if (*p && keep) PKD_HIP(hipMemcpyAsync(q, *p, *cap_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
+  if (*p) dev_free(*p, st);
+  *p = static_cast<T*>(q);
+  *cap_elems = n;
+  return PKD_OK;
+}
+
+template <class T>
+struct DArr {
+  T* p = nullptr;
+  size_t cap = 0;
+  hipStream_t st = nullptr;
+  int need(size_t n, bool keep = false) { return grow(st, &p, &cap, n, keep); }
+  ~DArr() {
+    if (p) dev_free(p, st);
+  }
+};
+
+int kernel_status(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_status(e, what);
+  return PKD_OK;
+}
+
+template <int D>
+size_t select_lds_bytes(int s, int cap) {
+  size_t ph1 = (sizeof(uint64_t) + sizeof(uint32_t)) * cap + sizeof(uint16_t) * s + sizeof(uint32_t) * s + 64;
+  return std::max(ph1, SkelLayout(D, s).end);
+}
+
+template <int D>
+size_t finish_lds_bytes(int P, int phi) {
+  return FinLayout(D, P, phi).end;
+}
+
+// Exact split of subproblem q whose sample was entirely identical (host-driven,
+// rare).  Returns mode 1 (heavy: all points identical) or 2 (skeleton set to a
+// single exact split at the root).
+template <int D>
+int exact_split(hipStream_t st, const Task& q, const int64_t* X, int64_t cap, int lambda, int64_t* rx,
+                uint8_t* rdim, int8_t* ext, int8_t* mode_dev, int sig, unsigned long long* scratch) {
+  const int NB = 1 << lambda;
+  unsigned long long h_init[2 * kMaxDim];
+  for (int d = 0; d < D; ++d) {
+    h_init[d] = ~0ULL;
+    h_init[D + d] = 0;
+  }
+  PKD_HIP(hipMemcpyAsync(scratch, h_init, sizeof(unsigned long long) * 2 * D, hipMemcpyHostToDevice, st));
+  int grid = static_cast<int>(std::min<int64_t>(1024, (q.m + 255) / 256));
+  hipLaunchKernelGGL(k_minmax<D>, dim3(grid), dim3(256), 0, st, X, cap, int64_t{q.start}, int64_t{q.m}, scratch,
+                     scratch + D);
+  PKD_TRY(kernel_status("k_minmax"));
+  unsigned long long mm[2 * kMaxDim];
+  PKD_HIP(hipMemcpyAsync(mm, scratch, sizeof(unsigned long long) * 2 * D, hipMemcpyDeviceToHost, st));
+  PKD_HIP(hipStreamSynchronize(st));
+  int best = -1;
+  unsigned long long bw = 0;
+  for (int d = 0; d < D; ++d) {
+    unsigned long long w = mm[D + d] - mm[d];
+    if (w > bw) {
+      bw = w;
+      best = d;
+    }
+  }
+  int8_t mode = 1;
+  if (best >= 0) {
+    // upper median: the value of rank floor(m/2) (0-based) on dimension best
+    const int64_t* Xd = X + best * cap;
+    int64_t r = q.m / 2;
+    uint64_t prefix = 0;
+    const int shifts[4] = {22, 14, 6, 0};
+    const int bits[4] = {8, 8, 8, 6};
+    unsigned int* hist = reinterpret_cast<unsigned int*>(scratch + 2 * kMaxDim);
+    for (int pass = 0; pass < 4; ++pass) {
+      PKD_HIP(hipMemsetAsync(hist, 0, 256 * sizeof(unsigned int), st));
+      int pshift = pass == 0 ? 64 : shifts[pass] + bits[pass];
+      hipLaunchKernelGGL(k_digit_hist, dim3(grid), dim3(256), 0, st, Xd, int64_t{q.start}, int64_t{q.m}, pshift,
+                         prefix, shifts[pass], (1 << bits[pass]) - 1, hist);
+      PKD_TRY(kernel_status("k_digit_hist"));
+      unsigned int h[256];
+      PKD_HIP(hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipStreamSynchronize(st));
+      int b = 0;
+      for (; b < (1 << bits[pass]); ++b) {
+        if (r < static_cast<int64_t>(h[b])) break;
+        r -= h[b];
+      }
+      prefix = (prefix << bits[pass]) | static_cast<uint64_t>(b);
+    }
+    uint64_t x = prefix;
+    if (x == mm[best]) {
+      unsigned long long init = ~0ULL;
+      PKD_HIP(hipMemcpyAsync(scratch, &init, sizeof(init), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_min_above, dim3(grid), dim3(256), 0, st, Xd, int64_t{q.start}, int64_t{q.m},
+                         static_cast<uint64_t>(mm[best]), scratch);
+      PKD_TRY(kernel_status("k_min_above"));
+      PKD_HIP(hipMemcpyAsync(&x, scratch, sizeof(x), hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipStreamSynchronize(st));
+    }
+    std::vector<int64_t> hx(NB, kAllLeft);
+    std::vector<uint8_t> hd(NB, 0);
+    std::vector<int8_t> he(2 * NB, 0);
+    hx[1] = static_cast<int64_t>(x);
+    hd[1] = static_cast<uint8_t>(best);
+    he[2] = he[3] = 1;
+    PKD_HIP(hipMemcpyAsync(rx + static_cast<int64_t>(sig) * NB, hx.data(), sizeof(int64_t) * NB,
+                           hipMemcpyHostToDevice, st));
+    PKD_HIP(hipMemcpyAsync(rdim + static_cast<int64_t>(sig) * NB, hd.data(), NB, hipMemcpyHostToDevice, st));
+    PKD_HIP(hipMemcpyAsync(ext + static_cast<int64_t>(sig) * 2 * NB, he.data(), 2 * NB, hipMemcpyHostToDevice, st));
+    mode = 2;
+    PKD_HIP(hipMemcpyAsync(mode_dev + sig, &mode, 1, hipMemcpyHostToDevice, st));
+    PKD_HIP(hipStreamSynchronize(st));
+    return PKD_OK;
+  }
+  PKD_HIP(hipMemcpyAsync(mode_dev + sig, &mode, 1, hipMemcpyHostToDevice, st));
+  PKD_HIP(hipStreamSynchronize(st));
+  return PKD_OK;
+}
+
+template <int D>
+int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, const int64_t* in_c,
+                  const int64_t* in_id, int64_t in_cap) {
+  const Params& P = T->prm;
+  const int NB = 1 << P.lambda;
+  const int nheap = 2 << P.lambda;
+  const int s = P.s;
+  const int tile = P.tile;
+  const int cap = 3 * s;            // candidate capacity per subproblem
+  const int small_max = 3 * s;      // subproblems up to this size sample from all points
+  const int F = T->cur;             // final buffer
+  Bufs bufs;
+  for (int b = 0; b < 2; ++b) {
+    bufs.c[b] = T->buf[b];
+    bufs.id[b] = T->buf[b] ? T->buf[b] + static_cast<int64_t>(D) * T->cap : nullptr;
+    bufs.cap[b] = T->cap;
+  }
+  bufs.c[2] = const_cast<int64_t*>(in_c);
+  bufs.id[2] = const_cast<int64_t*>(in_id);
+  bufs.cap[2] = in_cap;
+
+  DArr<Task> front, next, sieve, fin;
+  DArr<int64_t> tile_off, chunk_off, rx;
+  DArr<uint32_t> A, S, cand_cnt, cand_pos;
+  DArr<uint64_t> cand_key;
+  DArr<int32_t> B, bsize, bstart;
+  DArr<uint8_t> rdim;
+  DArr<int8_t> ext, mode, shift, shift_fix;
+  DArr<int> ctr, lists, rootext;
+  DArr<unsigned long long> scratch;
+  for (auto* a : {&tile_off, &chunk_off, &rx}) a->st = st;
+  front.st = next.st = sieve.st = fin.st = st;
+  A.st = S.st = cand_cnt.st = cand_pos.st = cand_key.st = B.st = bsize.st = bstart.st = st;
+  rdim.st = ext.st = mode.st = shift.st = shift_fix.st = ctr.st = lists.st = rootext.st = scratch.st = st;
+
+  // counters: 0 n_sieve, 1 n_fin, 2 n_next, 3 node_count, 4 flags, 5 n_root_ext, 6 height, 7 spare
+  PKD_TRY(ctr.need(16));
+  PKD_TRY(scratch.need(2 * kMaxDim + 128));
+  int hc[16] = {0};
+  hc[3] = T->node_count;
+  hc[6] = T->height;
+  PKD_HIP(hipMemcpyAsync(ctr.p, hc, sizeof(hc), hipMemcpyHostToDevice, st));
+  int* d_nsieve = ctr.p + 0;
+  int* d_nfin = ctr.p + 1;
+  int* d_nnext = ctr.p + 2;
+  int* d_nodes = ctr.p + 3;
+  int* d_flags = ctr.p + 4;
+  int* d_nrootext = ctr.p + 5;
+  int* d_height = ctr.p + 6;
+
+  int n_front = static_cast<int>(roots.size());
+  PKD_TRY(front.need(n_front));
+  PKD_HIP(hipMemcpyAsync(front.p, roots.data(), sizeof(Task) * n_front, hipMemcpyHostToDevice, st));
+  int src = roots.empty() ? 2 : roots[0].buf;
+  int dst = 1 - F;
+  int n_fin = 0;
+  int node_count = T->node_count;
+  bool first = true;
+
+  int rounds = 0;
+  while (n_front > 0) {
+    if (++rounds > 200) return PKD_ERR_INTERNAL;   // every round shrinks every subproblem
+    PKD_TRY(fin.need(static_cast<size_t>(n_fin) + n_front + 1, true));
+    PKD_TRY(sieve.need(n_front));
+    PKD_HIP(hipMemsetAsync(d_nsieve, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_classify, dim3((n_front + 255) / 256), dim3(256), 0, st, front.p, n_front, s, sieve.p,
+                       d_nsieve, fin.p, d_nfin);
+    PKD_TRY(kernel_status("k_classify"));
+    PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+    PKD_HIP(hipStreamSynchronize(st));
+    if (hc[4] & kErrRange) return PKD_ERR_RANGE;
+    if (hc[4] & kErrInternal) return PKD_ERR_INTERNAL;
+    const int ns = hc[0];
+    n_fin = hc[1];
+    node_count = hc[3];
+    T->node_count = node_count;   // nodes that a growth of the node array must keep
+    if (ns == 0) break;
+
+    // tile layout and candidate thresholds
+    PKD_TRY(tile_off.need(ns + 1));
+    PKD_TRY(chunk_off.need(ns + 1));
+    PKD_TRY(shift.need(ns));
+    PKD_TRY(shift_fix.need(ns));
+    PKD_TRY(mode.need(ns));
+    PKD_HIP(hipMemsetAsync(shift_fix.p, 0xFF, ns, st));
+    PKD_HIP(hipMemsetAsync(mode.p, 0, ns, st));
+    const int8_t* override_p = nullptr;
+    int64_t ntiles = 0, nchunks = 0;
+    PKD_TRY(rx.need(static_cast<size_t>(ns) * NB));
+    PKD_TRY(rdim.need(static_cast<size_t>(ns) * NB));
+    PKD_TRY(ext.need(static_cast<size_t>(ns) * nheap));
+    PKD_TRY(rootext.need(ns));
+    PKD_TRY(cand_cnt.need(ns));
+    for (int attempt = 0;; ++attempt) {
+      hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, sieve.p, ns, tile, tile_off.p, chunk_off.p,
+                         shift.p, s, small_max, override_p);
+      PKD_TRY(kernel_status("k_tile_scan"));
+      int64_t tot[2];
+      PKD_HIP(hipMemcpyAsync(&tot[0], tile_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipMemcpyAsync(&tot[1], chunk_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipStreamSynchronize(st));
+      ntiles = tot[0];
+      nchunks = tot[1];
+      PKD_TRY(cand_key.need(static_cast<size_t>(ns) * cap));
+      PKD_TRY(cand_pos.need(static_cast<size_t>(ns) * cap));
+      PKD_HIP(hipMemsetAsync(cand_cnt.p, 0, sizeof(uint32_t) * ns, st));
+      hipLaunchKernelGGL(k_candidates, dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
+                         tile_off.p, tile, bufs, src, P.seed, shift.p, small_max, cand_key.p, cand_pos.p,
+                         cand_cnt.p, cap);
+      PKD_TRY(kernel_status("k_candidates"));
+      SelectOut so{rx.p, rdim.p, ext.p, rootext.p, d_nrootext, shift_fix.p, d_flags};
+      PKD_HIP(hipMemsetAsync(d_nrootext, 0, sizeof(int), st));
+      size_t lds = select_lds_bytes<D>(s, cap);
+      PKD_TRY(allow_lds(k_select_skeleton<D>, lds));
+      hipLaunchKernelGGL(k_select_skeleton<D>, dim3(ns), dim3(kBlock), lds, st, sieve.p, ns, bufs, src, P.seed, s,
+                         P.lambda, shift.p, small_max, cand_key.p, cand_pos.p, cand_cnt.p, cap, so);
+      PKD_TRY(kernel_status("k_select_skeleton"));
+      PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipStreamSynchronize(st));
+      if (hc[4] & kErrInternal) return PKD_ERR_INTERNAL;
+      if (!(hc[4] & (kErrCandOverflow | kErrCandUnderflow))) break;
+      if (attempt > 8) return PKD_ERR_INTERNAL;
+      int clear = hc[4] & ~(kErrCandOverflow | kErrCandUnderflow);
+      PKD_HIP(hipMemcpyAsync(d_flags, &clear, sizeof(int), hipMemcpyHostToDevice, st));
+      override_p = shift_fix.p;
+    }
+    // exact splits where a sample was entirely identical (rare)
+    const int n_root_ext = hc[5];
+    if (n_root_ext > 0) {
+      std::vector<int> ids(n_root_ext);
+      std::vector<Task> tq(ns);
+      PKD_HIP(hipMemcpyAsync(ids.data(), rootext.p, sizeof(int) * n_root_ext, hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipMemcpyAsync(tq.data(), sieve.p, sizeof(Task) * ns, hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipStreamSynchronize(st));
+      for (int sig : ids)
+        PKD_TRY(exact_split<D>(st, tq[sig], bufs.c[src], bufs.cap[src], P.lambda, rx.p, rdim.p, ext.p, mode.p, sig,
+                               scratch.p));
+    }
+    // sieve: count, column-major scan, stable scatter
+    PKD_TRY(A.need(static_cast<size_t>(ntiles) * NB));
+    PKD_TRY(B.need(static_cast<size_t>(ntiles) * NB));
+    PKD_TRY(S.need(static_cast<size_t>(nchunks) * NB));
+    PKD_TRY(bsize.need(static_cast<size_t>(ns) * NB));
+    PKD_TRY(bstart.need(static_cast<size_t>(ns) * NB));
+    hipLaunchKernelGGL(k_count<D>, dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
+                       tile_off.p, tile, bufs, src, rx.p, rdim.p, mode.p, P.lambda, A.p, first && src == 2 ? 1 : 0,
+                       d_flags);
+    PKD_TRY(kernel_status("k_count"));
+    hipLaunchKernelGGL(k_chunk_sum, dim3(static_cast<unsigned>(nchunks)), dim3(kBlock), 0, st, chunk_off.p,
+                       tile_off.p, ns, P.lambda, A.p, S.p);
+    PKD_TRY(kernel_status("k_chunk_sum"));
+    hipLaunchKernelGGL(k_sp_scan, dim3(ns), dim3(kBlock), 0, st, sieve.p, chunk_off.p, P.lambda, S.p, bsize.p,
+                       bstart.p);
+    PKD_TRY(kernel_status("k_sp_scan"));
+    hipLaunchKernelGGL(k_apply, dim3(static_cast<unsigned>(nchunks)), dim3(kBlock), 0, st, chunk_off.p, tile_off.p,
+                       ns, P.lambda, A.p, S.p, bstart.p, B.p);
+    PKD_TRY(kernel_status("k_apply"));
+    if (tile == 2048)
+      hipLaunchKernelGGL((k_scatter<D, 8>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
+                         tile_off.p, bufs, src, dst, rx.p, rdim.p, mode.p, P.lambda, B.p);
+    else if (tile == 1024)
+      hipLaunchKernelGGL((k_scatter<D, 4>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
+                         tile_off.p, bufs, src, dst, rx.p, rdim.p, mode.p, P.lambda, B.p);
+    else
+      hipLaunchKernelGGL((k_scatter<D, 16>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
+                         tile_off.p, bufs, src, dst, rx.p, rdim.p, mode.p, P.lambda, B.p);
+    PKD_TRY(kernel_status("k_scatter"));
+    // nodes and next round's tasks
+    PKD_TRY(ensure_nodes(T, st, static_cast<int64_t>(node_count) + static_cast<int64_t>(ns) * nheap));
+    PKD_TRY(next.need(static_cast<size_t>(ns) * NB));
+    PKD_TRY(fin.need(static_cast<size_t>(n_fin) + ns + 1, true));
+    PKD_HIP(hipMemsetAsync(d_nnext, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_emit, dim3(ns), dim3(64), 0, st, sieve.p, ns, P.lambda, rx.p, rdim.p, ext.p, mode.p,
+                       bsize.p, bstart.p, dst, T->nodes, d_nodes, next.p, d_nnext, fin.p, d_nfin, d_flags);
+    PKD_TRY(kernel_status("k_emit"));
+    PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+    PKD_HIP(hipStreamSynchronize(st));
+    if (hc[4] & kErrRange) return PKD_ERR_RANGE;
+    if (hc[4] & kErrInternal) return PKD_ERR_INTERNAL;
+    n_front = hc[2];
+    n_fin = hc[1];
+    node_count = hc[3];
+    T->node_count = node_count;
+    std::swap(front.p, next.p);
+    std::swap(front.cap, next.cap);
+    src = dst;
+    dst = (dst == F) ? 1 - F : F;
+    first = false;
+  }
+
+  // finisher over every small subproblem, by size class
+  if (n_fin > 0) {
+    PKD_TRY(lists.need(static_cast<size_t>(8) * n_fin + 8));
+    int* d_counts = ctr.p + 8;
+    PKD_HIP(hipMemsetAsync(d_counts, 0, sizeof(int) * 8, st));
+    hipLaunchKernelGGL(k_bin_finish, dim3((n_fin + 255) / 256), dim3(256), 0, st, fin.p, n_fin, lists.p, n_fin,
+                       d_counts);
+    PKD_TRY(kernel_status("k_bin_finish"));
+    int counts[8];
+    PKD_HIP(hipMemcpyAsync(counts, d_counts, sizeof(counts), hipMemcpyDeviceToHost, st));
+    PKD_HIP(hipStreamSynchronize(st));
+    // node estimate: at most 2m-1 nodes per task; start from a data-typical
+    // bound and retry with the exact count if the estimate was short
+    std::vector<Task> none;
+    int64_t fin_pts_bound = 0;
+    {
+      std::vector<Task> hf(n_fin);
+      PKD_HIP(hipMemcpyAsync(hf.data(), fin.p, sizeof(Task) * n_fin, hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipStreamSynchronize(st));
+      for (const Task& t : hf) fin_pts_bound += t.mode == 1 ? 1 : (4 * static_cast<int64_t>(t.m)) / std::max(1, P.phi) + 3;
+    }
+    const int base_nodes = node_count;
+    T->node_count = base_nodes;   // the finisher's nodes are rewritten on a retry
+    int64_t want = base_nodes + fin_pts_bound;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      PKD_TRY(ensure_nodes(T, st, want));
+      int zero_flags = 0;
+      PKD_HIP(hipMemcpyAsync(d_nodes, &base_nodes, sizeof(int), hipMemcpyHostToDevice, st));
+      PKD_HIP(hipMemcpyAsync(d_flags, &zero_flags, sizeof(int), hipMemcpyHostToDevice, st));
+      for (int cls = 0; cls < 7; ++cls) {
+        if (counts[cls] == 0) continue;
+        const int Pc = 64 << cls;
+        size_t lds = finish_lds_bytes<D>(Pc, P.phi);
+        PKD_TRY(allow_lds(k_finish<D>, lds));
+        hipLaunchKernelGGL(k_finish<D>, dim3(counts[cls]), dim3(kBlock), lds, st, fin.p, lists.p + cls * n_fin, Pc,
+                           bufs, F, P.phi, T->nodes, d_nodes, T->node_cap, d_height, d_flags);
+        PKD_TRY(kernel_status("k_finish"));
+      }
+      if (counts[7] > 0) {
+        hipLaunchKernelGGL(k_finish_heavy, dim3(counts[7]), dim3(256), 0, st, fin.p, lists.p + 7 * n_fin, D, bufs, F,
+                           T->nodes, d_height);
+        PKD_TRY(kernel_status("k_finish_heavy"));
+      }
+      PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipStreamSynchronize(st));
+      if (hc[4] & kErrRange) return PKD_ERR_RANGE;
+      if (hc[4] & kErrInternal) return PKD_ERR_INTERNAL;
+      node_count = hc[3];
+      if (!(hc[4] & kErrNodeOverflow)) break;
+      if (attempt == 2) return PKD_ERR_INTERNAL;
+      want = node_count;   // the counter kept counting: the exact need
+    }
+  }
+  T->node_count = node_count;
+  T->height = hc[6];
+  return PKD_OK;
+}
+
+}  // namespace
+
+int build_tasks(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, const int64_t* in_c,
+                const int64_t* in_id, int64_t input_cap) {
+  const int D = T->prm.D;
+  switch (D) {
+    case 1: return build_tasks_d<1>(T, st, roots, in_c, in_id, input_cap);
+    case 2: return build_tasks_d<2>(T, st, roots, in_c, in_id, input_cap);
+    case 3: return build_tasks_d<3>(T, st, roots, in_c, in_id, input_cap);
+    case 4: return build_tasks_d<4>(T, st, roots, in_c, in_id, input_cap);
+    case 5: return build_tasks_d<5>(T, st, roots, in_c, in_id, input_cap);
+    case 6: return build_tasks_d<6>(T, st, roots, in_c, in_id, input_cap);
+    case 7: return build_tasks_d<7>(T, st, roots, in_c, in_id, input_cap);
+    default: return PKD_ERR_UNSUPPORTED;
+  }
+}
+
+}  // namespace pkd

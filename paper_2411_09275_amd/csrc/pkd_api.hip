@@ -1,0 +1,382 @@
+// C interface of libpkd: argument checks, tree storage, query launches and the
+// canonical export.  See include/pkd.h for the contract of every call.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "pkd_internal.h"
+
+namespace pkd {
+
+int run_knn(const pkd_tree* T, hipStream_t st, const int64_t* q, int64_t nq, int k, int64_t* oi, int64_t* od,
+            int* flags);
+int run_range(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, int64_t nb, int64_t* out,
+              int* flags);
+int run_insert(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m);
+int run_delete(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m, int64_t* removed);
+
+int hip_status(hipError_t e, const char* what) {
+  if (std::getenv("PKD_VERBOSE")) std::fprintf(stderr, "libpkd: %s failed: %s\n", what, hipGetErrorString(e));
+  (void)hipGetLastError();
+  return e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation ? PKD_ERR_OOM : PKD_ERR_HIP;
+}
+
+namespace {
+int g_pool_mode = -1;   // 1: stream-ordered pool allocations, 0: plain hipMalloc
+
+void init_pool() {
+  if (g_pool_mode >= 0) return;
+  int dev = 0, ok = 0;
+  g_pool_mode = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  if (hipDeviceGetAttribute(&ok, hipDeviceAttributeMemoryPoolsSupported, dev) != hipSuccess || !ok) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
+  // keep freed blocks in the pool: repeated builds reuse them without remapping
+  uint64_t keep = UINT64_MAX;
+  (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  g_pool_mode = 1;
+}
+}  // namespace
+
+int dev_alloc(void** p, size_t bytes, hipStream_t s) {
+  init_pool();
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = g_pool_mode == 1 ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_status(e, "device allocation");
+  }
+  return PKD_OK;
+}
+
+void dev_free(void* p, hipStream_t s) {
+  if (!p) return;
+  if (g_pool_mode == 1) (void)hipFreeAsync(p, s);
+  else (void)hipFree(p);
+}
+
+int ensure_nodes(pkd_tree* T, hipStream_t st, int64_t need) {
+  if (need <= T->node_cap) return PKD_OK;
+  if (need >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
+  int64_t cap = std::max<int64_t>(need + need / 4, 1024);
+  cap = std::min<int64_t>(cap, INT32_MAX - 1);
+  void* q = nullptr;
+  PKD_TRY(dev_alloc(&q, sizeof(Node) * cap, st));
+  if (T->nodes && T->node_count > 0)
+    PKD_HIP(hipMemcpyAsync(q, T->nodes, sizeof(Node) * T->node_count, hipMemcpyDeviceToDevice, st));
+  dev_free(T->nodes, st);
+  T->nodes = static_cast<Node*>(q);
+  T->node_cap = cap;
+  return PKD_OK;
+}
+
+int check_params(const pkd_params* p, const pkd_tuning* t, Params* out) {
+  if (!p) return PKD_ERR_INVALID_ARG;
+  if (p->dim < 1 || p->dim > kMaxDim) return PKD_ERR_UNSUPPORTED;
+  if (p->lambda < 1 || p->lambda > kMaxLambda || p->leaf_size < 1 || p->oversample < 1) return PKD_ERR_INVALID_ARG;
+  if (p->alpha_den <= 0 || p->alpha_num < 0 || 2 * static_cast<int64_t>(p->alpha_num) >= p->alpha_den)
+    return PKD_ERR_INVALID_ARG;
+  int64_t s = static_cast<int64_t>(p->oversample) << p->lambda;
+  if (s > kMaxSample) return PKD_ERR_UNSUPPORTED;
+  int tile = t ? t->tile_points : 2048;
+  if (tile != 1024 && tile != 2048 && tile != 4096) return PKD_ERR_INVALID_ARG;
+  out->D = p->dim;
+  out->lambda = p->lambda;
+  out->phi = p->leaf_size;
+  out->sigma = p->oversample;
+  out->s = static_cast<int>(s);
+  out->alpha_num = p->alpha_num;
+  out->alpha_den = p->alpha_den;
+  out->seed = p->seed;
+  out->tile = tile;
+  return PKD_OK;
+}
+
+// Allocate both point buffers of the tree with capacity `cap`.
+int alloc_points(pkd_tree* T, hipStream_t st, int64_t cap) {
+  cap = std::max<int64_t>(cap, 1);
+  const size_t bytes = sizeof(int64_t) * static_cast<size_t>(T->prm.D + 1) * static_cast<size_t>(cap);
+  void* a = nullptr;
+  void* b = nullptr;
+  PKD_TRY(dev_alloc(&a, bytes, st));
+  int rc = dev_alloc(&b, bytes, st);
+  if (rc != PKD_OK) {
+    dev_free(a, st);
+    return rc;
+  }
+  T->buf[0] = static_cast<int64_t*>(a);
+  T->buf[1] = static_cast<int64_t*>(b);
+  T->cap = cap;
+  T->cur = 0;
+  return PKD_OK;
+}
+
+void release(pkd_tree* T, hipStream_t st) {
+  if (!T) return;
+  dev_free(T->buf[0], st);
+  dev_free(T->buf[1], st);
+  dev_free(T->nodes, st);
+  T->buf[0] = T->buf[1] = nullptr;
+  T->nodes = nullptr;
+}
+
+int write_empty_root(pkd_tree* T, hipStream_t st) {
+  Node nd;
+  std::memset(&nd, 0, sizeof(nd));
+  nd.left = nd.right = -1;
+  nd.dim = -1;
+  PKD_HIP(hipMemcpyAsync(T->nodes, &nd, sizeof(nd), hipMemcpyHostToDevice, st));
+  PKD_HIP(hipStreamSynchronize(st));
+  T->node_count = 1;
+  T->height = 0;
+  return PKD_OK;
+}
+
+int flags_alloc(int** f, hipStream_t st) {
+  PKD_TRY(dev_alloc(reinterpret_cast<void**>(f), sizeof(int) * 4, st));
+  PKD_HIP(hipMemsetAsync(*f, 0, sizeof(int) * 4, st));
+  return PKD_OK;
+}
+
+int flags_check(int* f, hipStream_t st) {
+  int h = 0;
+  PKD_HIP(hipMemcpyAsync(&h, f, sizeof(int), hipMemcpyDeviceToHost, st));
+  PKD_HIP(hipStreamSynchronize(st));
+  dev_free(f, st);
+  if (h & kErrRange) return PKD_ERR_RANGE;
+  if (h & kErrStack) return PKD_ERR_CAPACITY;
+  if (h) return PKD_ERR_INTERNAL;
+  return PKD_OK;
+}
+
+}  // namespace pkd
+
+using namespace pkd;
+
+extern "C" {
+
+void pkd_default_params(pkd_params* p, int32_t dim) {
+  if (!p) return;
+  p->dim = dim;
+  p->lambda = 6;
+  p->leaf_size = 32;
+  p->oversample = 32;
+  p->alpha_num = 3;
+  p->alpha_den = 10;
+  p->seed = 42;
+}
+
+void pkd_default_tuning(pkd_tuning* t) {
+  if (!t) return;
+  std::memset(t, 0, sizeof(*t));
+  t->tile_points = 2048;
+}
+
+int pkd_build(const pkd_params* params, const pkd_tuning* tuning, void* stream, const int64_t* coords,
+              const int64_t* ids, int64_t n, pkd_tree** out) {
+  if (!out) return PKD_ERR_INVALID_ARG;
+  *out = nullptr;
+  Params prm;
+  PKD_TRY(check_params(params, tuning, &prm));
+  if (n < 0 || (n > 0 && (!coords || !ids))) return PKD_ERR_INVALID_ARG;
+  if (n >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  pkd_tree* T = new pkd_tree;
+  T->prm = prm;
+  int rc = alloc_points(T, st, n);
+  if (rc == PKD_OK) rc = ensure_nodes(T, st, std::max<int64_t>(1024, n / 8));
+  if (rc == PKD_OK) {
+    if (n == 0) {
+      rc = write_empty_root(T, st);
+    } else {
+      T->node_count = 1;
+      T->height = 0;
+      Task root;
+      root.start = 0;
+      root.m = static_cast<int32_t>(n);
+      root.slot = 0;
+      root.depth = 0;
+      root.buf = 2;
+      root.mode = 0;
+      rc = build_tasks(T, st, std::vector<Task>{root}, coords, ids, n);
+    }
+  }
+  if (rc != PKD_OK) {
+    release(T, st);
+    (void)hipStreamSynchronize(st);
+    delete T;
+    return rc;
+  }
+  T->n = n;
+  *out = T;
+  return PKD_OK;
+}
+
+int pkd_knn(const pkd_tree* tree, void* stream, const int64_t* queries, int64_t nq, int32_t k, int64_t* out_ids,
+            int64_t* out_d2) {
+  if (!tree || nq < 0 || k < 1 || k > 128) return PKD_ERR_INVALID_ARG;
+  if (nq == 0) return PKD_OK;
+  if (!queries || !out_ids || !out_d2) return PKD_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int* f = nullptr;
+  PKD_TRY(flags_alloc(&f, st));
+  int rc = run_knn(tree, st, queries, nq, k, out_ids, out_d2, f);
+  int rc2 = flags_check(f, st);
+  return rc != PKD_OK ? rc : rc2;
+}
+
+int pkd_range_count(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi, int64_t nb,
+                    int64_t* out) {
+  if (!tree || nb < 0) return PKD_ERR_INVALID_ARG;
+  if (nb == 0) return PKD_OK;
+  if (!lo || !hi || !out) return PKD_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int* f = nullptr;
+  PKD_TRY(flags_alloc(&f, st));
+  int rc = run_range(tree, st, lo, hi, nb, out, f);
+  int rc2 = flags_check(f, st);
+  return rc != PKD_OK ? rc : rc2;
+}
+
+int pkd_batch_insert(pkd_tree* tree, void* stream, const int64_t* coords, const int64_t* ids, int64_t m) {
+  if (!tree || m < 0) return PKD_ERR_INVALID_ARG;
+  if (m == 0) return PKD_OK;
+  if (!coords || !ids) return PKD_ERR_INVALID_ARG;
+  if (tree->n + m >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
+  return run_insert(tree, static_cast<hipStream_t>(stream), coords, ids, m);
+}
+
+int pkd_batch_delete(pkd_tree* tree, void* stream, const int64_t* coords, const int64_t* ids, int64_t m,
+                     int64_t* n_deleted) {
+  if (n_deleted) *n_deleted = 0;
+  if (!tree || m < 0) return PKD_ERR_INVALID_ARG;
+  if (m == 0) return PKD_OK;
+  if (!coords || !ids) return PKD_ERR_INVALID_ARG;
+  int64_t removed = 0;
+  int rc = run_delete(tree, static_cast<hipStream_t>(stream), coords, ids, m, &removed);
+  if (rc == PKD_OK && n_deleted) *n_deleted = removed;
+  return rc;
+}
+
+int pkd_size(const pkd_tree* tree, int64_t* n) {
+  if (!tree || !n) return PKD_ERR_INVALID_ARG;
+  *n = tree->n;
+  return PKD_OK;
+}
+
+int pkd_height(const pkd_tree* tree, int32_t* h) {
+  if (!tree || !h) return PKD_ERR_INVALID_ARG;
+  *h = tree->height;
+  return PKD_OK;
+}
+
+namespace {
+int copy_host(const pkd_tree* T, std::vector<Node>& nodes, std::vector<int64_t>& pts) {
+  nodes.resize(T->node_count);
+  const int D = T->prm.D;
+  pts.resize(static_cast<size_t>(D + 1) * T->n);
+  PKD_HIP(hipDeviceSynchronize());
+  PKD_HIP(hipMemcpy(nodes.data(), T->nodes, sizeof(Node) * T->node_count, hipMemcpyDeviceToHost));
+  for (int d = 0; d <= D; ++d)
+    if (T->n > 0)
+      PKD_HIP(hipMemcpy(pts.data() + static_cast<size_t>(d) * T->n, T->buf[T->cur] + static_cast<int64_t>(d) * T->cap,
+                        sizeof(int64_t) * T->n, hipMemcpyDeviceToHost));
+  return PKD_OK;
+}
+
+// Pre-order walk from the root; returns the node count or -1 when the stored
+// links do not form a tree over [0, n).
+int64_t walk(const pkd_tree* T, const std::vector<Node>& nodes, std::vector<int32_t>* order) {
+  std::vector<int32_t> stack{0};
+  int64_t count = 0;
+  while (!stack.empty()) {
+    int32_t t = stack.back();
+    stack.pop_back();
+    if (t < 0 || t >= static_cast<int32_t>(nodes.size()) || count > static_cast<int64_t>(nodes.size())) return -1;
+    ++count;
+    if (order) order->push_back(t);
+    if (nodes[t].left >= 0) {
+      stack.push_back(nodes[t].right);
+      stack.push_back(nodes[t].left);
+    }
+  }
+  (void)T;
+  return count;
+}
+}  // namespace
+
+int pkd_export_sizes(const pkd_tree* tree, int64_t* num_nodes, int64_t* n) {
+  if (!tree || !num_nodes || !n) return PKD_ERR_INVALID_ARG;
+  std::vector<Node> nodes(tree->node_count);
+  PKD_HIP(hipDeviceSynchronize());
+  PKD_HIP(hipMemcpy(nodes.data(), tree->nodes, sizeof(Node) * tree->node_count, hipMemcpyDeviceToHost));
+  int64_t c = walk(tree, nodes, nullptr);
+  if (c < 0) return PKD_ERR_INTERNAL;
+  *num_nodes = c;
+  *n = tree->n;
+  return PKD_OK;
+}
+
+int pkd_export(const pkd_tree* tree, int64_t* rows, int64_t* leaf_ids, int64_t* leaf_coords, int32_t* depths) {
+  if (!tree) return PKD_ERR_INVALID_ARG;
+  std::vector<Node> nodes;
+  std::vector<int64_t> pts;
+  PKD_TRY(copy_host(tree, nodes, pts));
+  std::vector<int32_t> order;
+  if (walk(tree, nodes, &order) < 0) return PKD_ERR_INTERNAL;
+  const int D = tree->prm.D;
+  const int64_t n = tree->n;
+  int64_t at = 0;
+  std::vector<int64_t> idx;
+  for (size_t r = 0; r < order.size(); ++r) {
+    const Node& nd = nodes[order[r]];
+    const bool leaf = nd.left < 0;
+    if (rows) {
+      rows[4 * r + 0] = leaf ? 1 : 0;
+      rows[4 * r + 1] = leaf ? -1 : nd.dim;
+      rows[4 * r + 2] = leaf ? 0 : nd.x;
+      rows[4 * r + 3] = nd.size;
+    }
+    if (depths) depths[r] = nd.depth;
+    if (!leaf) continue;
+    if (nd.off < 0 || static_cast<int64_t>(nd.off) + nd.size > n || at + nd.size > n) return PKD_ERR_INTERNAL;
+    idx.resize(nd.size);
+    for (int32_t i = 0; i < nd.size; ++i) idx[i] = nd.off + i;
+    const int64_t* id = pts.data() + static_cast<size_t>(D) * n;
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return id[a] < id[b]; });
+    for (int32_t i = 0; i < nd.size; ++i) {
+      if (leaf_ids) leaf_ids[at + i] = id[idx[i]];
+      if (leaf_coords)
+        for (int d = 0; d < D; ++d) leaf_coords[static_cast<int64_t>(d) * n + at + i] = pts[static_cast<size_t>(d) * n + idx[i]];
+    }
+    at += nd.size;
+  }
+  return at == n ? PKD_OK : PKD_ERR_INTERNAL;
+}
+
+void pkd_free(pkd_tree* tree) {
+  if (!tree) return;
+  (void)hipDeviceSynchronize();
+  release(tree, nullptr);
+  (void)hipDeviceSynchronize();
+  delete tree;
+}
+
+const char* pkd_strerror(int code) {
+  switch (code) {
+    case PKD_OK: return "ok";
+    case PKD_ERR_INVALID_ARG: return "invalid argument";
+    case PKD_ERR_RANGE: return "coordinate outside [0, 2^30)";
+    case PKD_ERR_UNSUPPORTED: return "unsupported size or dimension";
+    case PKD_ERR_OOM: return "device out of memory";
+    case PKD_ERR_HIP: return "HIP runtime error";
+    case PKD_ERR_CAPACITY: return "traversal stack capacity exceeded";
+    case PKD_ERR_INTERNAL: return "internal consistency check failed";
+  }
+  return "unknown error";
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal declarations shared by the HIP sources of libpkd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/pkd.h"
+
+namespace pkd {
+
+constexpr int kMaxDim = 7;
+constexpr int kMaxLambda = 8;
+constexpr int kMaxSample = 4096;                 // s = 2^lambda * sigma
+constexpr int64_t kCoordLimit = int64_t{1} << 30;
+constexpr int64_t kCoordMax = kCoordLimit - 1;
+constexpr int64_t kAllLeft = INT64_MAX;          // splitter that sends every point left
+constexpr int kMaxStack = 160;                   // traversal stack of the query kernels
+
+// Tree node, 32 bytes.  Subtrees are contiguous slices [off, off+size) of the
+// tree's point array (points are kept in in-order leaf order).
+struct Node {
+  int64_t x;       // interior: splitter coordinate (dim, x); left iff p[dim] < x
+  int32_t size;    // number of points in the subtree
+  int32_t off;     // first point of the subtree in the point array
+  int32_t left;    // interior: left child; leaf: -1
+  int32_t right;   // interior: right child; leaf: -1
+  int16_t dim;     // interior: 0..D-1; leaf: -1
+  int16_t depth;   // depth of the node in the whole tree (sampling salt)
+  int32_t pad;
+};
+static_assert(sizeof(Node) == 32, "node layout");
+
+// A subproblem of the build: the points [start, start+m) of some buffer,
+// whose subtree root is to be written into node `slot` at tree depth `depth`.
+struct Task {
+  int32_t start;
+  int32_t m;
+  int32_t slot;
+  int16_t depth;
+  int8_t buf;      // 0: tree array A, 1: twin array B, 2: caller input
+  int8_t mode;     // finisher: 0 plain build, 1 heavy leaf (identical points)
+};
+static_assert(sizeof(Task) == 16, "task layout");
+
+// SplitMix64 finaliser (Steele, Lea & Flood 2014; variant-13 constants of the
+// reference splitmix64.c) and the sampling key derived from it.
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t sample_key(uint64_t seed, int32_t depth, int64_t id) {
+  return mix64(mix64(static_cast<uint64_t>(id) ^ seed) + static_cast<uint64_t>(depth + 1) * 0x9E3779B97F4A7C15ULL);
+}
+
+struct Params {
+  int D, lambda, phi, sigma, s;
+  int64_t alpha_num, alpha_den;
+  uint64_t seed;
+  int tile;
+};
+
+// Device-side error flags (bitmask in one int).
+enum : int {
+  kErrRange = 1,
+  kErrCandOverflow = 2,
+  kErrCandUnderflow = 4,
+  kErrNodeOverflow = 8,
+  kErrStack = 16,
+  kErrInternal = 32,
+};
+
+}  // namespace pkd
+
+struct pkd_tree {
+  pkd::Params prm;
+  int64_t n = 0;          // points stored
+  int64_t cap = 0;        // capacity of each point buffer
+  int64_t* buf[2] = {nullptr, nullptr};  // buf[cur] holds the tree's points; the other is the twin
+  int cur = 0;
+  pkd::Node* nodes = nullptr;
+  int64_t node_cap = 0;
+  int32_t node_count = 0; // nodes allocated (node 0 is the root)
+  int32_t height = 0;      // longest root-leaf path (edges)
+};
+
+// ---- host helpers shared by the sources (defined in pkd_api.hip) -----------
+namespace pkd {
+int hip_status(hipError_t e, const char* what);
+#define PKD_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return ::pkd::hip_status(e_, #call); \
+  } while (0)
+#define PKD_TRY(call)            \
+  do {                           \
+    int rc_ = (call);            \
+    if (rc_ != PKD_OK) return rc_; \
+  } while (0)
+
+int dev_alloc(void** p, size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// Build the subtrees of the given root tasks into `tree` (whose point buffers
+// and node array are set up by the caller).  Points of the tasks live in the
+// buffer named by Task::buf; results go to tree->buf[tree->cur].
+int build_tasks(pkd_tree* tree, hipStream_t st, const std::vector<Task>& roots,
+                const int64_t* in_coords, const int64_t* in_ids, int64_t input_cap);
+int ensure_nodes(pkd_tree* tree, hipStream_t st, int64_t need);
+}  // namespace pkd

@@ -1,0 +1,187 @@
+"""GPU parity: the HIP build equals the oracle's tree node for node (splitters,
+sizes, leaf membership as sorted id sets, coordinates), and queries equal the
+plain definitions (brute force) and the oracle.  All through the C-ABI."""
+import numpy as np
+import pytest
+
+import synth
+from tests import treecheck
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_09275_amd as pk
+    pk.lib()
+    return pk
+
+
+def _params(orc, pk, D, **kw):
+    return orc.Params(D, **kw), pk.Params(D, **kw)
+
+
+def _same_tree(gt, ot, label=""):
+    g = gt.export()
+    o = ot.export()
+    assert g[0].shape == o[0].shape, (label, g[0].shape, o[0].shape)
+    rows_eq = np.all(g[0] == o[0], axis=1)
+    if not rows_eq.all():
+        bad = np.nonzero(~rows_eq)[0][:5]
+        raise AssertionError("%s: node rows differ at %s: gpu %s oracle %s" % (label, bad, g[0][bad], o[0][bad]))
+    assert np.array_equal(g[1], o[1]), label
+    assert np.array_equal(g[2], o[2]), label
+    return g
+
+
+def _build_both(orc, pk, c, i, tile=2048, **kw):
+    D = c.shape[0]
+    op, gp = _params(orc, pk, D, **kw)
+    ot = orc.Tree(op, c, i)
+    gt = pk.Tree(gp, c, i, tile=tile)
+    return gt, ot, op
+
+
+CASES = [
+    ("2d-uniform-100k", lambda: synth.uniform_points(100000, 2, seed=1), {}),
+    ("3d-uniform-300k", lambda: synth.uniform_points(300000, 3, seed=2), {}),
+    ("1d-dups", lambda: synth.uniform_points(50000, 1, seed=3, hi=5000), {}),
+    ("5d-uniform", lambda: synth.uniform_points(60000, 5, seed=4), {}),
+    ("7d-uniform", lambda: synth.uniform_points(30000, 7, seed=5), {}),
+    ("3d-clustered", lambda: synth.clustered_points(200000, 3, seed=6, n_clusters=50)[:2], {}),
+    ("2d-small-params", lambda: synth.uniform_points(40000, 2, seed=7), dict(lam=3, phi=4, sigma=4)),
+    ("3d-lambda8", lambda: synth.uniform_points(200000, 3, seed=8), dict(lam=8, sigma=8)),
+    ("2d-dup-heavy", lambda: synth.duplicate_heavy_points(60000, 2, seed=9, n_distinct=40), {}),
+    ("2d-lambda1", lambda: synth.uniform_points(30000, 2, seed=10), dict(lam=1, sigma=64)),
+]
+
+
+@pytest.mark.parametrize("name,gen,kw", CASES, ids=[c[0] for c in CASES])
+def test_build_matches_oracle(orc, pk, name, gen, kw):
+    print("case", name, flush=True)
+    c, i = gen()
+    gt, ot, op = _build_both(orc, pk, c, i, **kw)
+    rows, ids, coords = _same_tree(gt, ot, name)
+    treecheck.check_tree(rows, ids, coords, op.phi, c, i)
+    assert gt.size() == i.shape[0]
+    assert gt.height() == ot.height()
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 31, 32, 33, 100, 2047, 2048, 2049, 6144, 6145, 13000])
+def test_build_boundary_sizes(orc, pk, n):
+    c, i = synth.uniform_points(n, 3, seed=100 + n)
+    gt, ot, op = _build_both(orc, pk, c, i)
+    _same_tree(gt, ot, "n=%d" % n)
+
+
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+def test_tile_size_does_not_change_the_tree(orc, pk, tile):
+    c, i = synth.uniform_points(400000, 2, seed=11)
+    gt, ot, op = _build_both(orc, pk, c, i, tile=tile)
+    _same_tree(gt, ot, "tile=%d" % tile)
+
+
+def test_input_order_does_not_change_the_tree(orc, pk):
+    c, i = synth.uniform_points(150000, 3, seed=12)
+    perm = np.random.default_rng(0).permutation(i.shape[0])
+    a = pk.Tree(pk.Params(3), c, i).export()
+    b = pk.Tree(pk.Params(3), np.ascontiguousarray(c[:, perm]), i[perm]).export()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_identical_points_and_degenerate_sample(orc, pk):
+    c = np.full((2, 9000), 1234, dtype=np.int64)
+    i = np.arange(9000, dtype=np.int64)
+    gt, ot, op = _build_both(orc, pk, c, i)
+    _same_tree(gt, ot, "identical")
+    # all points on one location except a few the root sample misses: the
+    # sample is entirely identical while the set is not (exact split path)
+    n = 200000
+    i = np.arange(n, dtype=np.int64)
+    c = np.full((2, n), 500, dtype=np.int64)
+    samp = orc.sample(42, 0, i, 2048)
+    others = np.setdiff1d(np.arange(0, n, 997), samp)[:40]
+    c[:, others] = synth.uniform_points(40, 2, seed=26)[0]
+    gt, ot, op = _build_both(orc, pk, c, i)
+    _same_tree(gt, ot, "degenerate-sample")
+
+
+def test_repeat_build_is_deterministic(pk):
+    c, i = synth.uniform_points(500000, 3, seed=13)
+    a = pk.Tree(pk.Params(3), c, i).export()
+    for _ in range(2):
+        b = pk.Tree(pk.Params(3), c, i).export()
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_out_of_range_coordinates_rejected(pk):
+    c, i = synth.uniform_points(10000, 2, seed=14)
+    for bad in (-1, 1 << 30):
+        cc = c.copy()
+        cc[1, 777] = bad
+        with pytest.raises(pk.PkdError) as e:
+            pk.Tree(pk.Params(2), cc, i)
+        assert e.value.code == -2
+    small = c[:, :100].copy()
+    small[0, 5] = -3
+    with pytest.raises(pk.PkdError):
+        pk.Tree(pk.Params(2), small, i[:100])
+
+
+# --------------------------------------------------------------------- queries
+@pytest.mark.parametrize("D,n,k,hi", [(2, 100000, 10, 10 ** 9), (3, 200000, 1, 10 ** 9), (3, 100000, 16, 10 ** 9),
+                                      (2, 50000, 7, 300), (1, 20000, 5, 1000), (5, 40000, 10, 10 ** 6),
+                                      (3, 30000, 100, 10 ** 9), (2, 20, 10, 10 ** 9), (3, 50000, 33, 10 ** 9)])
+def test_knn_matches_definition(orc, pk, D, n, k, hi):
+    c, i = synth.uniform_points(n, D, seed=20 + D, hi=hi)
+    q = synth.uniform_queries(500, D, seed=21, hi=hi)
+    t = pk.Tree(pk.Params(D), c, i)
+    gi, gd = t.knn(q, k)
+    bi, bd = orc.brute_knn(c, i, q, k)
+    assert np.array_equal(gd.cpu().numpy(), bd)
+    assert np.array_equal(gi.cpu().numpy(), bi)
+
+
+def test_knn_empty_tree_and_duplicates(orc, pk):
+    q = synth.uniform_queries(50, 2, seed=22)
+    t = pk.Tree(pk.Params(2), np.zeros((2, 0), dtype=np.int64), np.zeros(0, dtype=np.int64))
+    gi, gd = t.knn(q, 5)
+    assert (gi.cpu().numpy() == -1).all() and (gd.cpu().numpy() == -1).all()
+    c, i = synth.duplicate_heavy_points(30000, 2, seed=23, n_distinct=30)
+    t = pk.Tree(pk.Params(2), c, i)
+    gi, gd = t.knn(q, 10)
+    bi, bd = orc.brute_knn(c, i, q, 10)
+    assert np.array_equal(gi.cpu().numpy(), bi) and np.array_equal(gd.cpu().numpy(), bd)
+
+
+@pytest.mark.parametrize("D,hi,dups", [(2, 10 ** 9, 0), (3, 10 ** 9, 0), (2, 60, 0), (2, 10 ** 9, 25)])
+def test_range_count_matches_definition(orc, pk, D, hi, dups):
+    if dups:
+        c, i = synth.duplicate_heavy_points(60000, D, seed=30, n_distinct=dups)
+    else:
+        c, i = synth.uniform_points(100000, D, seed=30 + D, hi=hi)
+    lo, up = synth.log_uniform_boxes(1000, D, seed=31, side_lo=1, side_hi=hi, hi=hi)
+    t = pk.Tree(pk.Params(D), c, i)
+    got = t.range_count(lo, up).cpu().numpy()
+    assert np.array_equal(got, orc.brute_range_count(c, lo, up))
+    lo2 = lo.copy()
+    lo2[0] = up[0] + 1
+    assert (t.range_count(lo2, up).cpu().numpy() == 0).all()
+
+
+def test_queries_reject_out_of_range(pk):
+    c, i = synth.uniform_points(1000, 2, seed=32)
+    t = pk.Tree(pk.Params(2), c, i)
+    q = synth.uniform_queries(10, 2, seed=33)
+    q[0, 3] = 1 << 30
+    with pytest.raises(pk.PkdError):
+        t.knn(q, 3)
+    lo, hi = synth.log_uniform_boxes(10, 2, seed=34)
+    lo[1, 2] = -5
+    with pytest.raises(pk.PkdError):
+        t.range_count(lo, hi)
