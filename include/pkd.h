@@ -149,6 +149,19 @@ int pkd_export(const pkd_tree* tree, int64_t* rows, int64_t* leaf_ids,
 /* Height of the tree (edges on the longest root-leaf path). */
 int pkd_height(const pkd_tree* tree, int32_t* height);
 
+/*
+ * Kernel timing (diagnostics).  pkd_profile_enable(1) clears and starts
+ * per-kernel accounting: every launch of the kernels below is bracketed by HIP
+ * events on the stream it runs on; pkd_profile_get(kernel, ...) returns the
+ * number of launches, their summed duration in milliseconds and the summed
+ * algorithmic bytes (what the method must move: for the sieve count pass 8*D
+ * bytes per point, for the scatter pass 2*(8*D+8) bytes per point).
+ * kernel: 0 sieve count, 1 sieve scatter, 2 sample select + skeleton,
+ * 3 finisher, 4 k-NN, 5 range count.  Host outs; any may be NULL.
+ */
+int pkd_profile_enable(int32_t on);
+int pkd_profile_get(int32_t kernel, int64_t* launches, double* total_ms, double* alg_bytes);
+
 /* Release a tree (NULL is ignored). */
 void pkd_free(pkd_tree* tree);
 

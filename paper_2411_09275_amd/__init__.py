@@ -25,7 +25,7 @@ ERRORS = {
 # Every symbol the C header declares (checked by the ABI test).
 EXPORTS = ["pkd_default_params", "pkd_default_tuning", "pkd_build", "pkd_batch_insert", "pkd_batch_delete",
            "pkd_knn", "pkd_range_count", "pkd_size", "pkd_export_sizes", "pkd_export", "pkd_height",
-           "pkd_free", "pkd_strerror"]
+           "pkd_free", "pkd_strerror", "pkd_profile_enable", "pkd_profile_get"]
 
 
 class PkdError(RuntimeError):
@@ -67,9 +67,11 @@ def lib():
         L.pkd_export.argtypes = [vp, vp, vp, vp, vp]
         L.pkd_free.argtypes = [vp]
         L.pkd_free.restype = None
+        L.pkd_profile_enable.argtypes = [i32]
+        L.pkd_profile_get.argtypes = [i32, C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.pkd_strerror.argtypes = [C.c_int]
         L.pkd_strerror.restype = C.c_char_p
-        for f in ("pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
+        for f in ("pkd_profile_enable", "pkd_profile_get", "pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
                   "pkd_height", "pkd_export_sizes", "pkd_export"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -105,6 +107,22 @@ def _dev(t, shape=None):
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr() if t.numel() > 0 else 0)
+
+
+PROFILE_KERNELS = {"sieve_count": 0, "sieve_scatter": 1, "select_skeleton": 2, "finisher": 3, "knn": 4,
+                   "range_count": 5}
+
+
+def profile_enable(on: bool = True):
+    """Clear and (re)start per-kernel timing with HIP events on the launch stream."""
+    _check(lib().pkd_profile_enable(1 if on else 0), "pkd_profile_enable")
+
+
+def profile_get(name: str):
+    """(launches, total milliseconds, algorithmic bytes) of one profiled kernel."""
+    n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+    _check(lib().pkd_profile_get(PROFILE_KERNELS[name], C.byref(n), C.byref(ms), C.byref(b)), "pkd_profile_get")
+    return n.value, ms.value, b.value
 
 
 class Params:

@@ -86,8 +86,11 @@ __global__ void k_classify(const Task* front, int n_front, int s, Task* sieve, i
 // ------------------------------------------------------------ tile layout
 // Single workgroup: exclusive prefix sums of tiles and chunks per subproblem.
 __global__ void k_tile_scan(const Task* sp, int ns, int tile, int64_t* tile_off, int64_t* chunk_off,
-                            int8_t* shift, int s, int small_max, const int8_t* shift_override) {
+                            int8_t* shift, int s, int small_max, const int8_t* shift_override, int64_t* total_pts) {
   __shared__ int64_t part_t[1024], part_c[1024];
+  __shared__ unsigned long long pts;
+  if (threadIdx.x == 0) pts = 0;
+  __syncthreads();
   int tid = threadIdx.x, nt = blockDim.x;
   int per = (ns + nt - 1) / nt;
   int b = tid * per, e = min(ns, b + per);
@@ -99,8 +102,14 @@ __global__ void k_tile_scan(const Task* sp, int ns, int tile, int64_t* tile_off,
   }
   part_t[tid] = st;
   part_c[tid] = sc;
+  {
+    unsigned long long mine = 0;
+    for (int i = b; i < e; ++i) mine += static_cast<unsigned long long>(sp[i].m);
+    atomicAdd(&pts, mine);
+  }
   __syncthreads();
   if (tid == 0) {
+    *total_pts = static_cast<int64_t>(pts);
     int64_t a = 0, c = 0;
     for (int i = 0; i < nt; ++i) {
       int64_t x = part_t[i], y = part_c[i];
@@ -1455,7 +1464,7 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
     PKD_HIP(hipMemsetAsync(shift_fix.p, 0xFF, ns, st));
     PKD_HIP(hipMemsetAsync(mode.p, 0, ns, st));
     const int8_t* override_p = nullptr;
-    int64_t ntiles = 0, nchunks = 0;
+    int64_t ntiles = 0, nchunks = 0, round_pts = 0;
     PKD_TRY(rx.need(static_cast<size_t>(ns) * NB));
     PKD_TRY(rdim.need(static_cast<size_t>(ns) * NB));
     PKD_TRY(ext.need(static_cast<size_t>(ns) * nheap));
@@ -1463,14 +1472,16 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
     PKD_TRY(cand_cnt.need(ns));
     for (int attempt = 0;; ++attempt) {
       hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, sieve.p, ns, tile, tile_off.p, chunk_off.p,
-                         shift.p, s, small_max, override_p);
+                         shift.p, s, small_max, override_p, reinterpret_cast<int64_t*>(scratch.p + 2 * kMaxDim + 64));
       PKD_TRY(kernel_status("k_tile_scan"));
-      int64_t tot[2];
+      int64_t tot[3];
       PKD_HIP(hipMemcpyAsync(&tot[0], tile_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st));
       PKD_HIP(hipMemcpyAsync(&tot[1], chunk_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipMemcpyAsync(&tot[2], scratch.p + 2 * kMaxDim + 64, sizeof(int64_t), hipMemcpyDeviceToHost, st));
       PKD_HIP(hipStreamSynchronize(st));
       ntiles = tot[0];
       nchunks = tot[1];
+      round_pts = tot[2];
       PKD_TRY(cand_key.need(static_cast<size_t>(ns) * cap));
       PKD_TRY(cand_pos.need(static_cast<size_t>(ns) * cap));
       PKD_HIP(hipMemsetAsync(cand_cnt.p, 0, sizeof(uint32_t) * ns, st));
@@ -1482,8 +1493,10 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
       PKD_HIP(hipMemsetAsync(d_nrootext, 0, sizeof(int), st));
       size_t lds = select_lds_bytes<D>(s, cap);
       PKD_TRY(allow_lds(k_select_skeleton<D>, lds));
+      Prof::begin(kProfSelect, st);
       hipLaunchKernelGGL(k_select_skeleton<D>, dim3(ns), dim3(kBlock), lds, st, sieve.p, ns, bufs, src, P.seed, s,
                          P.lambda, shift.p, small_max, cand_key.p, cand_pos.p, cand_cnt.p, cap, so);
+      Prof::end(kProfSelect, st, 0.0);
       PKD_TRY(kernel_status("k_select_skeleton"));
       PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
       PKD_HIP(hipStreamSynchronize(st));
@@ -1512,9 +1525,11 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
     PKD_TRY(S.need(static_cast<size_t>(nchunks) * NB));
     PKD_TRY(bsize.need(static_cast<size_t>(ns) * NB));
     PKD_TRY(bstart.need(static_cast<size_t>(ns) * NB));
+    Prof::begin(kProfCount, st);
     hipLaunchKernelGGL(k_count<D>, dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
                        tile_off.p, tile, bufs, src, rx.p, rdim.p, mode.p, P.lambda, A.p, first && src == 2 ? 1 : 0,
                        d_flags);
+    Prof::end(kProfCount, st, 8.0 * D * static_cast<double>(round_pts));
     PKD_TRY(kernel_status("k_count"));
     hipLaunchKernelGGL(k_chunk_sum, dim3(static_cast<unsigned>(nchunks)), dim3(kBlock), 0, st, chunk_off.p,
                        tile_off.p, ns, P.lambda, A.p, S.p);
@@ -1525,6 +1540,7 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
     hipLaunchKernelGGL(k_apply, dim3(static_cast<unsigned>(nchunks)), dim3(kBlock), 0, st, chunk_off.p, tile_off.p,
                        ns, P.lambda, A.p, S.p, bstart.p, B.p);
     PKD_TRY(kernel_status("k_apply"));
+    Prof::begin(kProfScatter, st);
     if (tile == 2048)
       hipLaunchKernelGGL((k_scatter<D, 8>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
                          tile_off.p, bufs, src, dst, rx.p, rdim.p, mode.p, P.lambda, B.p);
@@ -1534,6 +1550,7 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
     else
       hipLaunchKernelGGL((k_scatter<D, 16>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
                          tile_off.p, bufs, src, dst, rx.p, rdim.p, mode.p, P.lambda, B.p);
+    Prof::end(kProfScatter, st, 2.0 * (8.0 * D + 8.0) * static_cast<double>(round_pts));
     PKD_TRY(kernel_status("k_scatter"));
     // nodes and next round's tasks
     PKD_TRY(ensure_nodes(T, st, static_cast<int64_t>(node_count) + static_cast<int64_t>(ns) * nheap));
@@ -1592,8 +1609,10 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
         const int Pc = 64 << cls;
         size_t lds = finish_lds_bytes<D>(Pc, P.phi);
         PKD_TRY(allow_lds(k_finish<D>, lds));
+        Prof::begin(kProfFinish, st);
         hipLaunchKernelGGL(k_finish<D>, dim3(counts[cls]), dim3(kBlock), lds, st, fin.p, lists.p + cls * n_fin, Pc,
                            bufs, F, P.phi, T->nodes, d_nodes, T->node_cap, d_height, d_flags);
+        Prof::end(kProfFinish, st, 0.0);
         PKD_TRY(kernel_status("k_finish"));
       }
       if (counts[7] > 0) {

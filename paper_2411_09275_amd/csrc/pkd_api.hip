@@ -58,6 +58,63 @@ void dev_free(void* p, hipStream_t s) {
   else (void)hipFree(p);
 }
 
+// ---- kernel timing -------------------------------------------------------
+namespace {
+struct ProfState {
+  bool on = false;
+  int64_t launches[kProfN] = {0};
+  double ms[kProfN] = {0};
+  double bytes[kProfN] = {0};
+  struct Pending {
+    int kernel;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> spare;
+  hipEvent_t open_ev[kProfN] = {nullptr};
+  hipEvent_t get() {
+    if (!spare.empty()) {
+      hipEvent_t e = spare.back();
+      spare.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+ProfState g_prof;
+}  // namespace
+
+bool Prof::on() { return g_prof.on; }
+void Prof::begin(int kernel, hipStream_t st) {
+  if (!g_prof.on) return;
+  hipEvent_t e = g_prof.get();
+  (void)hipEventRecord(e, st);
+  g_prof.open_ev[kernel] = e;
+}
+void Prof::end(int kernel, hipStream_t st, double alg_bytes) {
+  if (!g_prof.on || !g_prof.open_ev[kernel]) return;
+  hipEvent_t e = g_prof.get();
+  (void)hipEventRecord(e, st);
+  g_prof.pending.push_back({kernel, g_prof.open_ev[kernel], e, alg_bytes});
+  g_prof.open_ev[kernel] = nullptr;
+}
+void Prof::flush() {
+  for (auto& p : g_prof.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      g_prof.launches[p.kernel] += 1;
+      g_prof.ms[p.kernel] += ms;
+      g_prof.bytes[p.kernel] += p.bytes;
+    }
+    g_prof.spare.push_back(p.a);
+    g_prof.spare.push_back(p.b);
+  }
+  g_prof.pending.clear();
+}
+
 int ensure_nodes(pkd_tree* T, hipStream_t st, int64_t need) {
   if (need <= T->node_cap) return PKD_OK;
   if (need >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
@@ -223,7 +280,9 @@ int pkd_knn(const pkd_tree* tree, void* stream, const int64_t* queries, int64_t 
   hipStream_t st = static_cast<hipStream_t>(stream);
   int* f = nullptr;
   PKD_TRY(flags_alloc(&f, st));
+  Prof::begin(kProfKnn, st);
   int rc = run_knn(tree, st, queries, nq, k, out_ids, out_d2, f);
+  Prof::end(kProfKnn, st, 0.0);
   int rc2 = flags_check(f, st);
   return rc != PKD_OK ? rc : rc2;
 }
@@ -236,7 +295,9 @@ int pkd_range_count(const pkd_tree* tree, void* stream, const int64_t* lo, const
   hipStream_t st = static_cast<hipStream_t>(stream);
   int* f = nullptr;
   PKD_TRY(flags_alloc(&f, st));
+  Prof::begin(kProfRange, st);
   int rc = run_range(tree, st, lo, hi, nb, out, f);
+  Prof::end(kProfRange, st, 0.0);
   int rc2 = flags_check(f, st);
   return rc != PKD_OK ? rc : rc2;
 }
@@ -355,6 +416,26 @@ int pkd_export(const pkd_tree* tree, int64_t* rows, int64_t* leaf_ids, int64_t* 
     at += nd.size;
   }
   return at == n ? PKD_OK : PKD_ERR_INTERNAL;
+}
+
+int pkd_profile_enable(int32_t on) {
+  Prof::flush();
+  g_prof.on = on != 0;
+  for (int k = 0; k < kProfN; ++k) {
+    g_prof.launches[k] = 0;
+    g_prof.ms[k] = 0;
+    g_prof.bytes[k] = 0;
+  }
+  return PKD_OK;
+}
+
+int pkd_profile_get(int32_t kernel, int64_t* launches, double* total_ms, double* alg_bytes) {
+  if (kernel < 0 || kernel >= kProfN) return PKD_ERR_INVALID_ARG;
+  Prof::flush();
+  if (launches) *launches = g_prof.launches[kernel];
+  if (total_ms) *total_ms = g_prof.ms[kernel];
+  if (alg_bytes) *alg_bytes = g_prof.bytes[kernel];
+  return PKD_OK;
 }
 
 void pkd_free(pkd_tree* tree) {

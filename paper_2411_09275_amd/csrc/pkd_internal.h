@@ -110,4 +110,14 @@ void dev_free(void* p, hipStream_t s);
 int build_tasks(pkd_tree* tree, hipStream_t st, const std::vector<Task>& roots,
                 const int64_t* in_coords, const int64_t* in_ids, int64_t input_cap);
 int ensure_nodes(pkd_tree* tree, hipStream_t st, int64_t need);
+
+// Per-kernel timing (pkd_profile_*): Prof::begin/end bracket one launch with
+// events on its stream; the elapsed time is collected at the next flush.
+enum ProfKernel { kProfCount = 0, kProfScatter, kProfSelect, kProfFinish, kProfKnn, kProfRange, kProfN };
+struct Prof {
+  static bool on();
+  static void begin(int kernel, hipStream_t st);
+  static void end(int kernel, hipStream_t st, double alg_bytes);
+  static void flush();   // after the stream has been synchronized
+};
 }  // namespace pkd
