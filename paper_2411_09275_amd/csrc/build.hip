@@ -28,13 +28,19 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kChunkTiles = 64;      // tiles per scan chunk
 
-struct Bufs {
-  int64_t* c[3];   // coordinates: c[b][d*cap[b] + i]
-  int64_t* id[3];  // ids: id[b][i]
-  int64_t cap[3];
-};
-
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63; }
+
+// Wave-aggregated append: every lane with `take` gets a distinct slot of
+// *counter; one atomic per wave.
+__device__ inline int wave_append(bool take, int* counter) {
+  const unsigned long long mask = __ballot(take);
+  if (mask == 0) return -1;
+  const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+  int base = 0;
+  if (lane_id() == static_cast<uint32_t>(leader)) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader);
+  return take ? base + static_cast<int>(__popcll(mask & ((1ULL << lane_id()) - 1))) : -1;
+}
 
 template <int D>
 __device__ inline int64_t pick(const int64_t (&c)[D], int d) {
@@ -76,11 +82,14 @@ __host__ __device__ inline int cand_shift(int64_t m, int s) {
 // ---------------------------------------------------------------- classify
 __global__ void k_classify(const Task* front, int n_front, int s, Task* sieve, int* n_sieve, Task* fin,
                            int* n_fin) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_front) return;
-  Task t = front[i];
-  if (t.m >= s) sieve[atomicAdd(n_sieve, 1)] = t;
-  else fin[atomicAdd(n_fin, 1)] = t;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = i < n_front;
+  Task t{};
+  if (ok) t = front[i];
+  const int a = wave_append(ok && t.m >= s, n_sieve);
+  const int b = wave_append(ok && t.m < s, n_fin);
+  if (a >= 0) sieve[a] = t;
+  if (b >= 0) fin[b] = t;
 }
 
 // ------------------------------------------------------------ tile layout
@@ -914,19 +923,25 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
 
 // ------------------------------------------------------------------- emit
 // Skeleton nodes of each subproblem become tree nodes; its buckets become
-// tasks of the next round.  One workgroup of 64 threads per subproblem.
-__global__ void k_emit(const Task* sp, int ns, int lambda, const int64_t* rx, const uint8_t* rdim, const int8_t* ext,
-                       const int8_t* mode, const int32_t* bsize, const int32_t* bstart, int dst, Node* nodes,
-                       int* node_count, Task* front, int* n_front, Task* fin, int* n_fin, int* flags) {
+// tasks of the next round.  One workgroup of 64 threads per subproblem; the
+// heap is processed level by level.
+__global__ void __launch_bounds__(64) k_emit(const Task* sp, int ns, int lambda, const int64_t* rx,
+                                             const uint8_t* rdim, const int8_t* ext, const int8_t* mode,
+                                             const int32_t* bsize, const int32_t* bstart, int dst, Node* nodes,
+                                             int* node_count, Task* front, int* n_front, Task* fin, int* n_fin,
+                                             int* flags) {
   const int NB = 1 << lambda;
   const int nheap = 2 << lambda;
   __shared__ int32_t size[2 << kMaxLambda], off[2 << kMaxLambda], idx[2 << kMaxLambda];
-  __shared__ uint8_t reach[2 << kMaxLambda];
+  __shared__ uint8_t reach[2 << kMaxLambda], exs[2 << kMaxLambda];
+  __shared__ int32_t part[64];
+  __shared__ int sh_base;
   const int sig = blockIdx.x;
+  const int tid = threadIdx.x;
   const Task q = sp[sig];
   if (mode[sig] == 1) {
     // identical points: one heavy leaf, data stays where it is
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       Task h = q;
       h.mode = 1;
       fin[atomicAdd(n_fin, 1)] = h;
@@ -934,54 +949,74 @@ __global__ void k_emit(const Task* sp, int ns, int lambda, const int64_t* rx, co
     return;
   }
   const int8_t* ex = ext + static_cast<int64_t>(sig) * nheap;
-  for (int j = threadIdx.x; j < NB; j += blockDim.x) {
+  for (int v = tid; v < nheap; v += 64) exs[v] = ex[v];
+  for (int j = tid; j < NB; j += 64) {
     size[NB + j] = bsize[static_cast<int64_t>(sig) * NB + j];
     off[NB + j] = bstart[static_cast<int64_t>(sig) * NB + j];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int v = NB - 1; v >= 1; --v) {
+  for (int l = lambda - 1; l >= 0; --l) {
+    for (int v = (1 << l) + tid; v < (2 << l); v += 64) {
       size[v] = size[2 * v] + size[2 * v + 1];
       off[v] = off[2 * v];
     }
-    reach[1] = 1;
-    int cnt = 0;
-    for (int v = 2; v < nheap; ++v) {
-      reach[v] = reach[v >> 1] && !ex[v >> 1];
-      if (reach[v]) ++cnt;
+    __syncthreads();
+  }
+  if (tid == 0) reach[1] = 1;
+  __syncthreads();
+  for (int l = 1; l <= lambda; ++l) {
+    for (int v = (1 << l) + tid; v < (2 << l); v += 64) reach[v] = reach[v >> 1] && !exs[v >> 1];
+    __syncthreads();
+  }
+  // rank the reachable heap nodes other than the root in heap order
+  const int per = (nheap + 63) / 64;
+  const int b = tid * per, e = min(nheap, b + per);
+  int cnt = 0;
+  for (int v = max(b, 2); v < e; ++v) cnt += reach[v];
+  int incl = cnt;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o);
+    if (tid >= o) incl += y;
+  }
+  if (tid == 63) sh_base = atomicAdd(node_count, incl);
+  __syncthreads();
+  int r = sh_base + incl - cnt;
+  for (int v = max(b, 2); v < e; ++v)
+    if (reach[v]) idx[v] = r++;
+  if (tid == 0) idx[1] = q.slot;
+  __syncthreads();
+  const int64_t* sxv = rx + static_cast<int64_t>(sig) * NB;
+  const uint8_t* sdv = rdim + static_cast<int64_t>(sig) * NB;
+  for (int base = 0; base < nheap; base += 64) {
+    const int v = base + tid;
+    const bool live = v >= 1 && v < nheap && reach[v];
+    const bool interior = live && !exs[v];
+    const bool external = live && exs[v];
+    if (interior) {
+      const int level = 31 - __clz(v);
+      Node nd;
+      nd.x = sxv[v];
+      nd.size = size[v];
+      nd.off = off[v];
+      nd.left = idx[2 * v];
+      nd.right = idx[2 * v + 1];
+      nd.dim = sdv[v];
+      nd.depth = static_cast<int16_t>(q.depth + level);
+      nd.pad = 0;
+      nodes[idx[v]] = nd;
     }
-    int base = atomicAdd(node_count, cnt);
-    idx[1] = q.slot;
-    int r = 0;
-    for (int v = 2; v < nheap; ++v)
-      if (reach[v]) idx[v] = base + r++;
-    const int64_t* sxv = rx + static_cast<int64_t>(sig) * NB;
-    const uint8_t* sdv = rdim + static_cast<int64_t>(sig) * NB;
-    for (int v = 1; v < nheap; ++v) {
-      if (!reach[v]) continue;
-      int level = 31 - __clz(v);
-      if (!ex[v]) {
-        Node nd;
-        nd.x = sxv[v];
-        nd.size = size[v];
-        nd.off = off[v];
-        nd.left = idx[2 * v];
-        nd.right = idx[2 * v + 1];
-        nd.dim = sdv[v];
-        nd.depth = static_cast<int16_t>(q.depth + level);
-        nd.pad = 0;
-        nodes[idx[v]] = nd;
-      } else {
-        if (size[v] <= 0) atomicOr(flags, kErrInternal);
-        Task c;
-        c.start = off[v];
-        c.m = size[v];
-        c.slot = idx[v];
-        c.depth = static_cast<int16_t>(q.depth + level);
-        c.buf = static_cast<int8_t>(dst);
-        c.mode = 0;
-        front[atomicAdd(n_front, 1)] = c;
-      }
+    const int at = wave_append(external, n_front);
+    if (external) {
+      const int level = 31 - __clz(v);
+      if (size[v] <= 0) atomicOr(flags, kErrInternal);
+      Task c;
+      c.start = off[v];
+      c.m = size[v];
+      c.slot = idx[v];
+      c.depth = static_cast<int16_t>(q.depth + level);
+      c.buf = static_cast<int8_t>(dst);
+      c.mode = 0;
+      front[at] = c;
     }
   }
 }
@@ -1186,15 +1221,21 @@ __global__ void k_finish_heavy(const Task* tasks, const int* list, int D, Bufs b
 // Sort finisher tasks into classes by padded size (64, 128, ..., 4096) and
 // heavy leaves (class 7).
 __global__ void k_bin_finish(const Task* fin, int n_fin, int* lists, int stride, int* counts) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_fin) return;
-  const Task t = fin[i];
-  int cls = 7;
-  if (t.mode == 0) {
-    cls = 0;
-    while ((64 << cls) < t.m) ++cls;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = i < n_fin;
+  int cls = -1;
+  if (ok) {
+    const Task t = fin[i];
+    cls = 7;
+    if (t.mode == 0) {
+      cls = 0;
+      while ((64 << cls) < t.m) ++cls;
+    }
   }
-  lists[cls * stride + atomicAdd(counts + cls, 1)] = i;
+  for (int c = 0; c < 8; ++c) {
+    const int at = wave_append(cls == c, counts + c);
+    if (at >= 0) lists[c * stride + at] = i;
+  }
 }
 
 // ------------------------------------------- exact split of a large subproblem
@@ -1249,36 +1290,6 @@ template <class K>
 int allow_lds(K kernel, size_t bytes) {
   PKD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                               static_cast<int>(bytes)));
-  return PKD_OK;
-}
-
-template <class T>
-int grow(hipStream_t st, T** p, size_t* cap_elems, size_t need, bool keep) {
-  if (need <= *cap_elems && *p) return PKD_OK;
-  size_t n = std::max<size_t>(need + need / 4, 256);
-  void* q = nullptr;
-  PKD_TRY(dev_alloc(&q, n * sizeof(T), st));
-  if (*p && keep) PKD_HIP(hipMemcpyAsync(q, *p, *cap_elems * sizeof(T), hipMemcpyDeviceToDevice, st));
-  if (*p) dev_free(*p, st);
-  *p = static_cast<T*>(q);
-  *cap_elems = n;
-  return PKD_OK;
-}
-
-template <class T>
-struct DArr {
-  T* p = nullptr;
-  size_t cap = 0;
-  hipStream_t st = nullptr;
-  int need(size_t n, bool keep = false) { return grow(st, &p, &cap, n, keep); }
-  ~DArr() {
-    if (p) dev_free(p, st);
-  }
-};
-
-int kernel_status(const char* what) {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_status(e, what);
   return PKD_OK;
 }
 
@@ -1398,19 +1409,15 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
   bufs.id[2] = const_cast<int64_t*>(in_id);
   bufs.cap[2] = in_cap;
 
-  DArr<Task> front, next, sieve, fin;
-  DArr<int64_t> tile_off, chunk_off, rx;
-  DArr<uint32_t> A, S, cand_cnt, cand_pos;
-  DArr<uint64_t> cand_key;
-  DArr<int32_t> B, bsize, bstart;
-  DArr<uint8_t> rdim;
-  DArr<int8_t> ext, mode, shift, shift_fix;
-  DArr<int> ctr, lists, rootext;
-  DArr<unsigned long long> scratch;
-  for (auto* a : {&tile_off, &chunk_off, &rx}) a->st = st;
-  front.st = next.st = sieve.st = fin.st = st;
-  A.st = S.st = cand_cnt.st = cand_pos.st = cand_key.st = B.st = bsize.st = bstart.st = st;
-  rdim.st = ext.st = mode.st = shift.st = shift_fix.st = ctr.st = lists.st = rootext.st = scratch.st = st;
+  DArr<Task> front(st), next(st), sieve(st), fin(st);
+  DArr<int64_t> rx(st);
+  DArr<uint32_t> cand_cnt(st), cand_pos(st);
+  DArr<uint64_t> cand_key(st);
+  DArr<uint8_t> rdim(st);
+  DArr<int8_t> ext(st), mode(st), shift_fix(st);
+  DArr<int> ctr(st), lists(st), rootext(st);
+  DArr<unsigned long long> scratch(st);
+  SieveWork W(st);
 
   // counters: 0 n_sieve, 1 n_fin, 2 n_next, 3 node_count, 4 flags, 5 n_root_ext, 6 height, 7 spare
   PKD_TRY(ctr.need(16));
@@ -1456,9 +1463,6 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
     if (ns == 0) break;
 
     // tile layout and candidate thresholds
-    PKD_TRY(tile_off.need(ns + 1));
-    PKD_TRY(chunk_off.need(ns + 1));
-    PKD_TRY(shift.need(ns));
     PKD_TRY(shift_fix.need(ns));
     PKD_TRY(mode.need(ns));
     PKD_HIP(hipMemsetAsync(shift_fix.p, 0xFF, ns, st));
@@ -1471,22 +1475,12 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
     PKD_TRY(rootext.need(ns));
     PKD_TRY(cand_cnt.need(ns));
     for (int attempt = 0;; ++attempt) {
-      hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, sieve.p, ns, tile, tile_off.p, chunk_off.p,
-                         shift.p, s, small_max, override_p, reinterpret_cast<int64_t*>(scratch.p + 2 * kMaxDim + 64));
-      PKD_TRY(kernel_status("k_tile_scan"));
-      int64_t tot[3];
-      PKD_HIP(hipMemcpyAsync(&tot[0], tile_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-      PKD_HIP(hipMemcpyAsync(&tot[1], chunk_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-      PKD_HIP(hipMemcpyAsync(&tot[2], scratch.p + 2 * kMaxDim + 64, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-      PKD_HIP(hipStreamSynchronize(st));
-      ntiles = tot[0];
-      nchunks = tot[1];
-      round_pts = tot[2];
+      PKD_TRY(sieve_layout(st, sieve.p, ns, tile, W, s, small_max, override_p, &ntiles, &nchunks, &round_pts));
       PKD_TRY(cand_key.need(static_cast<size_t>(ns) * cap));
       PKD_TRY(cand_pos.need(static_cast<size_t>(ns) * cap));
       PKD_HIP(hipMemsetAsync(cand_cnt.p, 0, sizeof(uint32_t) * ns, st));
       hipLaunchKernelGGL(k_candidates, dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
-                         tile_off.p, tile, bufs, src, P.seed, shift.p, small_max, cand_key.p, cand_pos.p,
+                         W.tile_off.p, tile, bufs, src, P.seed, W.shift.p, small_max, cand_key.p, cand_pos.p,
                          cand_cnt.p, cap);
       PKD_TRY(kernel_status("k_candidates"));
       SelectOut so{rx.p, rdim.p, ext.p, rootext.p, d_nrootext, shift_fix.p, d_flags};
@@ -1495,7 +1489,7 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
       PKD_TRY(allow_lds(k_select_skeleton<D>, lds));
       Prof::begin(kProfSelect, st);
       hipLaunchKernelGGL(k_select_skeleton<D>, dim3(ns), dim3(kBlock), lds, st, sieve.p, ns, bufs, src, P.seed, s,
-                         P.lambda, shift.p, small_max, cand_key.p, cand_pos.p, cand_cnt.p, cap, so);
+                         P.lambda, W.shift.p, small_max, cand_key.p, cand_pos.p, cand_cnt.p, cap, so);
       Prof::end(kProfSelect, st, 0.0);
       PKD_TRY(kernel_status("k_select_skeleton"));
       PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
@@ -1520,45 +1514,15 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
                                scratch.p));
     }
     // sieve: count, column-major scan, stable scatter
-    PKD_TRY(A.need(static_cast<size_t>(ntiles) * NB));
-    PKD_TRY(B.need(static_cast<size_t>(ntiles) * NB));
-    PKD_TRY(S.need(static_cast<size_t>(nchunks) * NB));
-    PKD_TRY(bsize.need(static_cast<size_t>(ns) * NB));
-    PKD_TRY(bstart.need(static_cast<size_t>(ns) * NB));
-    Prof::begin(kProfCount, st);
-    hipLaunchKernelGGL(k_count<D>, dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
-                       tile_off.p, tile, bufs, src, rx.p, rdim.p, mode.p, P.lambda, A.p, first && src == 2 ? 1 : 0,
-                       d_flags);
-    Prof::end(kProfCount, st, 8.0 * D * static_cast<double>(round_pts));
-    PKD_TRY(kernel_status("k_count"));
-    hipLaunchKernelGGL(k_chunk_sum, dim3(static_cast<unsigned>(nchunks)), dim3(kBlock), 0, st, chunk_off.p,
-                       tile_off.p, ns, P.lambda, A.p, S.p);
-    PKD_TRY(kernel_status("k_chunk_sum"));
-    hipLaunchKernelGGL(k_sp_scan, dim3(ns), dim3(kBlock), 0, st, sieve.p, chunk_off.p, P.lambda, S.p, bsize.p,
-                       bstart.p);
-    PKD_TRY(kernel_status("k_sp_scan"));
-    hipLaunchKernelGGL(k_apply, dim3(static_cast<unsigned>(nchunks)), dim3(kBlock), 0, st, chunk_off.p, tile_off.p,
-                       ns, P.lambda, A.p, S.p, bstart.p, B.p);
-    PKD_TRY(kernel_status("k_apply"));
-    Prof::begin(kProfScatter, st);
-    if (tile == 2048)
-      hipLaunchKernelGGL((k_scatter<D, 8>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
-                         tile_off.p, bufs, src, dst, rx.p, rdim.p, mode.p, P.lambda, B.p);
-    else if (tile == 1024)
-      hipLaunchKernelGGL((k_scatter<D, 4>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
-                         tile_off.p, bufs, src, dst, rx.p, rdim.p, mode.p, P.lambda, B.p);
-    else
-      hipLaunchKernelGGL((k_scatter<D, 16>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
-                         tile_off.p, bufs, src, dst, rx.p, rdim.p, mode.p, P.lambda, B.p);
-    Prof::end(kProfScatter, st, 2.0 * (8.0 * D + 8.0) * static_cast<double>(round_pts));
-    PKD_TRY(kernel_status("k_scatter"));
+    PKD_TRY(sieve_pass(st, D, P.lambda, tile, sieve.p, ns, bufs, src, dst, rx.p, rdim.p, mode.p, W, ntiles, nchunks,
+                       round_pts, first && src == 2 ? 1 : 0, d_flags));
     // nodes and next round's tasks
     PKD_TRY(ensure_nodes(T, st, static_cast<int64_t>(node_count) + static_cast<int64_t>(ns) * nheap));
     PKD_TRY(next.need(static_cast<size_t>(ns) * NB));
     PKD_TRY(fin.need(static_cast<size_t>(n_fin) + ns + 1, true));
     PKD_HIP(hipMemsetAsync(d_nnext, 0, sizeof(int), st));
     hipLaunchKernelGGL(k_emit, dim3(ns), dim3(64), 0, st, sieve.p, ns, P.lambda, rx.p, rdim.p, ext.p, mode.p,
-                       bsize.p, bstart.p, dst, T->nodes, d_nodes, next.p, d_nnext, fin.p, d_nfin, d_flags);
+                       W.bsize.p, W.bstart.p, dst, T->nodes, d_nodes, next.p, d_nnext, fin.p, d_nfin, d_flags);
     PKD_TRY(kernel_status("k_emit"));
     PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
     PKD_HIP(hipStreamSynchronize(st));
@@ -1635,7 +1599,84 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
   return PKD_OK;
 }
 
+template <int D>
+int sieve_pass_d(hipStream_t st, int lambda, int tile, const Task* tasks, int ns, const Bufs& bufs, int src, int dst,
+                 const int64_t* rx, const uint8_t* rdim, const int8_t* mode, SieveWork& W, int64_t ntiles,
+                 int64_t nchunks, int64_t pts, int check, int* d_flags) {
+  const int NB = 1 << lambda;
+  PKD_TRY(W.A.need(static_cast<size_t>(ntiles) * NB));
+  PKD_TRY(W.B.need(static_cast<size_t>(ntiles) * NB));
+  PKD_TRY(W.S.need(static_cast<size_t>(nchunks) * NB));
+  PKD_TRY(W.bsize.need(static_cast<size_t>(ns) * NB));
+  PKD_TRY(W.bstart.need(static_cast<size_t>(ns) * NB));
+  Prof::begin(kProfCount, st);
+  hipLaunchKernelGGL(k_count<D>, dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, tasks, ns, W.tile_off.p,
+                     tile, bufs, src, rx, rdim, mode, lambda, W.A.p, check, d_flags);
+  Prof::end(kProfCount, st, 8.0 * D * static_cast<double>(pts));
+  PKD_TRY(kernel_status("k_count"));
+  hipLaunchKernelGGL(k_chunk_sum, dim3(static_cast<unsigned>(nchunks)), dim3(kBlock), 0, st, W.chunk_off.p,
+                     W.tile_off.p, ns, lambda, W.A.p, W.S.p);
+  PKD_TRY(kernel_status("k_chunk_sum"));
+  hipLaunchKernelGGL(k_sp_scan, dim3(ns), dim3(kBlock), 0, st, tasks, W.chunk_off.p, lambda, W.S.p, W.bsize.p,
+                     W.bstart.p);
+  PKD_TRY(kernel_status("k_sp_scan"));
+  hipLaunchKernelGGL(k_apply, dim3(static_cast<unsigned>(nchunks)), dim3(kBlock), 0, st, W.chunk_off.p, W.tile_off.p,
+                     ns, lambda, W.A.p, W.S.p, W.bstart.p, W.B.p);
+  PKD_TRY(kernel_status("k_apply"));
+  Prof::begin(kProfScatter, st);
+  if (tile == 2048)
+    hipLaunchKernelGGL((k_scatter<D, 8>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, tasks, ns,
+                       W.tile_off.p, bufs, src, dst, rx, rdim, mode, lambda, W.B.p);
+  else if (tile == 1024)
+    hipLaunchKernelGGL((k_scatter<D, 4>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, tasks, ns,
+                       W.tile_off.p, bufs, src, dst, rx, rdim, mode, lambda, W.B.p);
+  else
+    hipLaunchKernelGGL((k_scatter<D, 16>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, tasks, ns,
+                       W.tile_off.p, bufs, src, dst, rx, rdim, mode, lambda, W.B.p);
+  Prof::end(kProfScatter, st, 2.0 * (8.0 * D + 8.0) * static_cast<double>(pts));
+  PKD_TRY(kernel_status("k_scatter"));
+  return PKD_OK;
+}
+
 }  // namespace
+
+int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,
+                 const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts) {
+  PKD_TRY(W.tile_off.need(ns + 1));
+  PKD_TRY(W.chunk_off.need(ns + 1));
+  PKD_TRY(W.shift.need(ns));
+  PKD_TRY(W.tot.need(4));
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, tasks, ns, tile, W.tile_off.p, W.chunk_off.p, W.shift.p,
+                     s, small_max, shift_override, W.tot.p + 2);
+  PKD_TRY(kernel_status("k_tile_scan"));
+  PKD_HIP(hipMemcpyAsync(W.tot.p, W.tile_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+  PKD_HIP(hipMemcpyAsync(W.tot.p + 1, W.chunk_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+  int64_t tot[3];
+  PKD_HIP(hipMemcpyAsync(tot, W.tot.p, sizeof(tot), hipMemcpyDeviceToHost, st));
+  PKD_HIP(hipStreamSynchronize(st));
+  *ntiles = tot[0];
+  *nchunks = tot[1];
+  *pts = tot[2];
+  return PKD_OK;
+}
+
+int sieve_pass(hipStream_t st, int D, int lambda, int tile, const Task* tasks, int ns, const Bufs& bufs, int src,
+               int dst, const int64_t* rx, const uint8_t* rdim, const int8_t* mode, SieveWork& W, int64_t ntiles,
+               int64_t nchunks, int64_t pts, int check, int* d_flags) {
+  switch (D) {
+#define PKD_SIEVE_CASE(DD) \
+  case DD: return sieve_pass_d<DD>(st, lambda, tile, tasks, ns, bufs, src, dst, rx, rdim, mode, W, ntiles, nchunks, pts, check, d_flags);
+    PKD_SIEVE_CASE(1)
+    PKD_SIEVE_CASE(2)
+    PKD_SIEVE_CASE(3)
+    PKD_SIEVE_CASE(4)
+    PKD_SIEVE_CASE(5)
+    PKD_SIEVE_CASE(6)
+    PKD_SIEVE_CASE(7)
+#undef PKD_SIEVE_CASE
+  }
+  return PKD_ERR_UNSUPPORTED;
+}
 
 int build_tasks(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, const int64_t* in_c,
                 const int64_t* in_id, int64_t input_cap) {

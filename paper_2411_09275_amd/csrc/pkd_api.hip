@@ -316,6 +316,7 @@ int pkd_batch_delete(pkd_tree* tree, void* stream, const int64_t* coords, const 
   if (!tree || m < 0) return PKD_ERR_INVALID_ARG;
   if (m == 0) return PKD_OK;
   if (!coords || !ids) return PKD_ERR_INVALID_ARG;
+  if (m >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
   int64_t removed = 0;
   int rc = run_delete(tree, static_cast<hipStream_t>(stream), coords, ids, m, &removed);
   if (rc == PKD_OK && n_deleted) *n_deleted = removed;

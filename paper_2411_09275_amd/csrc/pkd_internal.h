@@ -56,6 +56,15 @@ __host__ __device__ inline uint64_t sample_key(uint64_t seed, int32_t depth, int
   return mix64(mix64(static_cast<uint64_t>(id) ^ seed) + static_cast<uint64_t>(depth + 1) * 0x9E3779B97F4A7C15ULL);
 }
 
+// The point buffers a kernel may read or write: 0 and 1 are the tree's two
+// arrays (coordinate d of point i at c[b][d*cap[b] + i], id at id[b][i]),
+// 2 is a caller-owned input.
+struct Bufs {
+  int64_t* c[3];
+  int64_t* id[3];
+  int64_t cap[3];
+};
+
 struct Params {
   int D, lambda, phi, sigma, s;
   int64_t alpha_num, alpha_den;
@@ -103,6 +112,60 @@ int hip_status(hipError_t e, const char* what);
 
 int dev_alloc(void** p, size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
+
+inline int kernel_status(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_status(e, what);
+  return PKD_OK;
+}
+
+// Grow-only device array (stream-ordered); need(n, keep) reallocates when
+// more than the current capacity is needed, copying the old contents if keep.
+template <class T>
+struct DArr {
+  T* p = nullptr;
+  size_t cap = 0;
+  hipStream_t st = nullptr;
+  explicit DArr(hipStream_t s = nullptr) : st(s) {}
+  DArr(const DArr&) = delete;
+  DArr& operator=(const DArr&) = delete;
+  int need(size_t n, bool keep = false) {
+    if (n <= cap && p) return PKD_OK;
+    size_t c = n + n / 4 > 256 ? n + n / 4 : 256;
+    void* q = nullptr;
+    PKD_TRY(dev_alloc(&q, c * sizeof(T), st));
+    if (p && keep) PKD_HIP(hipMemcpyAsync(q, p, cap * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (p) dev_free(p, st);
+    p = static_cast<T*>(q);
+    cap = c;
+    return PKD_OK;
+  }
+  ~DArr() {
+    if (p) dev_free(p, st);
+  }
+};
+
+// Scratch of one segmented sieve pass: tile and chunk layout, tile x bucket
+// counts (A), write cursors (B), chunk sums (S), bucket sizes and starts.
+struct SieveWork {
+  DArr<int64_t> tile_off, chunk_off, tot;
+  DArr<int8_t> shift;
+  DArr<uint32_t> A, S;
+  DArr<int32_t> B, bsize, bstart;
+  explicit SieveWork(hipStream_t s)
+      : tile_off(s), chunk_off(s), tot(s), shift(s), A(s), S(s), B(s), bsize(s), bstart(s) {}
+};
+
+// Tile layout of `ns` tasks (device array): tiles of `tile` points, scan
+// chunks; returns the numbers of tiles and chunks and the points covered.
+int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,
+                 const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts);
+// Count, column-major scan and stable scatter of the tasks' points from
+// buffer src to dst through per-task routing skeletons rx/rdim ([ns][2^lambda]).
+// Bucket sizes and starts land in W.bsize / W.bstart ([ns][2^lambda]).
+int sieve_pass(hipStream_t st, int D, int lambda, int tile, const Task* tasks, int ns, const Bufs& bufs, int src,
+               int dst, const int64_t* rx, const uint8_t* rdim, const int8_t* mode, SieveWork& W, int64_t ntiles,
+               int64_t nchunks, int64_t pts, int check, int* d_flags);
 
 // Build the subtrees of the given root tasks into `tree` (whose point buffers
 // and node array are set up by the caller).  Points of the tasks live in the

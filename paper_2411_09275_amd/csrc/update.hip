@@ -1,9 +1,752 @@
-// Batch updates (placeholder until the update path lands).
+// Batch updates on the GPU: BatchInsert (Algorithm 2, Section 4.1) and
+// BatchDelete (Section 4.2).
+//
+//   route     the batch is sieved through skeletons fetched from the tree (the
+//             top lambda levels below each routing node), one sieve round per
+//             lambda levels, with the build's count/scan/scatter kernels, until
+//             every batch point sits in the slice of the leaf it belongs to;
+//             the batch ends up in the tree's in-order.
+//   match     (delete) each entry claims the stored point of its leaf with the
+//             same id and coordinates; absent entries drop out.
+//   decide    the rounds are replayed top-down with exact counts (inserted
+//             points, or points actually removed): a touched node that stays
+//             alpha-balanced keeps its splitter and takes its new size; the
+//             topmost one that does not becomes a rebuild region and nothing
+//             below it is visited; an inserted-into leaf is rebuilt.
+//   relayout  the tree keeps its points packed in in-order: one prefix sum of
+//             the size changes gives every surviving point and node its new
+//             offset; old points, batch points and survivors move in one pass.
+//   rebuild   all regions are rebuilt by one segmented Build (Algorithm 1),
+//             each at the depth of the node it replaces.
+#include <algorithm>
+#include <cstring>
+
 #include "pkd_internal.h"
 
 namespace pkd {
-int run_insert(pkd_tree*, hipStream_t, const int64_t*, const int64_t*, int64_t) { return PKD_ERR_UNSUPPORTED; }
-int run_delete(pkd_tree*, hipStream_t, const int64_t*, const int64_t*, int64_t, int64_t*) {
+
+namespace {
+
+constexpr int kUBlock = 256;
+
+struct Res {      // a routed slice of the batch that ends at a leaf
+  int32_t node, start, count, buf;
+};
+
+struct Region {   // a node to rebuild (old range [a, b), batch slice [s, e))
+  int32_t node, depth, a, b, s, e, new_start, new_size;
+};
+
+template <int D>
+__global__ void k_validate(const int64_t* coords, int64_t m, int* flags) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < m;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    for (int d = 0; d < D; ++d) bad |= static_cast<uint64_t>(coords[d * m + i]) >= static_cast<uint64_t>(kCoordLimit);
+  if (bad) atomicOr(flags, kErrRange);
+}
+
+// Skeleton of the top lambda levels below each routing node, in heap order:
+// hn[v] is the tree node at heap position v (-1 below a leaf); interior
+// positions above level lambda route by their splitter, the rest send left.
+__global__ void __launch_bounds__(64) k_fetch_skeleton(const Task* tasks, const Node* nodes, int lambda, int64_t* rx,
+                                                       uint8_t* rdim, int32_t* hn_out) {
+  const int NB = 1 << lambda, nheap = 2 << lambda;
+  __shared__ int32_t hn[2 << kMaxLambda];
+  const int sig = blockIdx.x;
+  for (int v = threadIdx.x; v < nheap; v += 64) hn[v] = -1;
+  __syncthreads();
+  if (threadIdx.x == 0) hn[1] = tasks[sig].slot;
+  __syncthreads();
+  for (int l = 0; l < lambda; ++l) {
+    for (int v = (1 << l) + threadIdx.x; v < (2 << l); v += 64) {
+      const int32_t u = hn[v];
+      int64_t x = kAllLeft;
+      uint8_t d = 0;
+      if (u >= 0) {
+        const Node nd = nodes[u];
+        if (nd.left >= 0) {
+          x = nd.x;
+          d = static_cast<uint8_t>(nd.dim);
+          hn[2 * v] = nd.left;
+          hn[2 * v + 1] = nd.right;
+        }
+      }
+      rx[static_cast<int64_t>(sig) * NB + v] = x;
+      rdim[static_cast<int64_t>(sig) * NB + v] = d;
+    }
+    __syncthreads();
+  }
+  for (int v = threadIdx.x; v < nheap; v += 64) hn_out[static_cast<int64_t>(sig) * nheap + v] = hn[v];
+}
+
+__device__ inline bool is_external(const Node* nodes, int32_t u, int level, int lambda) {
+  return level == lambda || nodes[u].left < 0;
+}
+
+// Buckets that end at a leaf are resolved; buckets at an interior node of
+// level lambda become the next round's routing tasks.
+__global__ void __launch_bounds__(64) k_route_emit(const Task* tasks, const Node* nodes, int lambda,
+                                                   const int32_t* hn_all, const int32_t* bsize, const int32_t* bstart,
+                                                   int dst, Task* next, int* n_next, int32_t* child_idx, Res* res,
+                                                   int* n_res) {
+  const int NB = 1 << lambda, nheap = 2 << lambda;
+  const int sig = blockIdx.x;
+  const Task q = tasks[sig];
+  const int32_t* hn = hn_all + static_cast<int64_t>(sig) * nheap;
+  for (int base = 0; base < nheap; base += 64) {
+    const int v = base + threadIdx.x;
+    bool leaf_end = false, go_on = false;
+    int32_t u = -1, start = 0, size = 0;
+    int level = 0;
+    if (v >= 1 && v < nheap) {
+      u = hn[v];
+      child_idx[static_cast<int64_t>(sig) * nheap + v] = -1;
+      if (u >= 0) {
+        level = 31 - __clz(v);
+        if (is_external(nodes, u, level, lambda)) {
+          const int label = (v << (lambda - level)) - NB;
+          size = bsize[static_cast<int64_t>(sig) * NB + label];
+          start = bstart[static_cast<int64_t>(sig) * NB + label];
+          if (size > 0) {
+            leaf_end = nodes[u].left < 0;
+            go_on = !leaf_end;
+          }
+        }
+      }
+    }
+    // wave-aggregated appends
+    unsigned long long mk = __ballot(go_on);
+    if (mk) {
+      int leader = __ffsll(static_cast<long long>(mk)) - 1;
+      int b0 = 0;
+      if (static_cast<int>(threadIdx.x & 63) == leader) b0 = atomicAdd(n_next, __popcll(mk));
+      b0 = __shfl(b0, leader);
+      if (go_on) {
+        const int at = b0 + __popcll(mk & ((1ULL << (threadIdx.x & 63)) - 1));
+        Task c;
+        c.start = start;
+        c.m = size;
+        c.slot = u;
+        c.depth = static_cast<int16_t>(q.depth + level);
+        c.buf = static_cast<int8_t>(dst);
+        c.mode = 0;
+        next[at] = c;
+        child_idx[static_cast<int64_t>(sig) * nheap + v] = at;
+      }
+    }
+    mk = __ballot(leaf_end);
+    if (mk) {
+      int leader = __ffsll(static_cast<long long>(mk)) - 1;
+      int b0 = 0;
+      if (static_cast<int>(threadIdx.x & 63) == leader) b0 = atomicAdd(n_res, __popcll(mk));
+      b0 = __shfl(b0, leader);
+      if (leaf_end) res[b0 + __popcll(mk & ((1ULL << (threadIdx.x & 63)) - 1))] = Res{u, start, size, dst};
+    }
+  }
+}
+
+// Copy every resolved slice into one buffer (same positions) and record the
+// leaf of each batch position.
+__global__ void k_gather(const Res* res, int D, Bufs wb, int64_t* out, int64_t m, int32_t* leaf_of) {
+  const Res r = res[blockIdx.x];
+  for (int i = threadIdx.x; i < r.count; i += blockDim.x) {
+    const int64_t p = r.start + i;
+    for (int d = 0; d < D; ++d) out[d * m + p] = wb.c[r.buf][d * wb.cap[r.buf] + p];
+    out[D * m + p] = wb.id[r.buf][p];
+    leaf_of[p] = r.node;
+  }
+}
+
+// Delete: each batch entry claims the stored point of its leaf with the same
+// id and coordinates (at most one entry wins a point).
+template <int D>
+__global__ void k_match(const int64_t* batch, int64_t m, const int32_t* leaf_of, const Node* nodes, const int64_t* X,
+                        int64_t cap, int32_t* delflag, int32_t* matched) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (p >= m) return;
+  int64_t c[D];
+  for (int d = 0; d < D; ++d) c[d] = batch[d * m + p];
+  const int64_t id = batch[D * m + p];
+  const Node nd = nodes[leaf_of[p]];
+  const int64_t* ids = X + static_cast<int64_t>(D) * cap;
+  int32_t got = 0;
+  for (int64_t i = nd.off; i < static_cast<int64_t>(nd.off) + nd.size; ++i) {
+    if (ids[i] != id) continue;
+    bool same = true;
+    for (int d = 0; d < D; ++d) same &= X[d * cap + i] == c[d];
+    if (!same) continue;
+    got = atomicCAS(delflag + i, 0, 1) == 0 ? 1 : 0;
+    break;
+  }
+  matched[p] = got;
+}
+
+// Exclusive prefix sums over int32 arrays: block sums, one-workgroup scan of
+// the block sums, then the per-block pass.  out[i] = sum in[0..i), out[n] = total.
+constexpr int kScanBlock = 2048;
+
+__global__ void k_scan_blocks(const int32_t* in, int64_t n, int32_t* bsum) {
+  __shared__ int32_t part[kUBlock];
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kScanBlock;
+  int32_t s = 0;
+  for (int64_t i = b0 + threadIdx.x; i < min<int64_t>(n, b0 + kScanBlock); i += kUBlock) s += in[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kUBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = part[0];
+}
+
+__global__ void k_scan_sums(int32_t* bsum, int64_t nb) {
+  __shared__ int64_t part[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t b = tid * per, e = min(nb, b + per);
+  int64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += bsum[i];
+  part[tid] = s;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t a = 0;
+    for (int i = 0; i < 1024; ++i) {
+      int64_t x = part[i];
+      part[i] = a;
+      a += x;
+    }
+  }
+  __syncthreads();
+  s = part[tid];
+  for (int64_t i = b; i < e; ++i) {
+    int32_t x = bsum[i];
+    bsum[i] = static_cast<int32_t>(s);
+    s += x;
+  }
+}
+
+__global__ void k_scan_apply(const int32_t* in, int64_t n, const int32_t* bsum, int32_t* out) {
+  __shared__ int32_t vals[kScanBlock];
+  __shared__ int32_t part[kUBlock + 1];
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kScanBlock;
+  const int len = static_cast<int>(min<int64_t>(kScanBlock, n - b0));
+  for (int i = threadIdx.x; i < kScanBlock; i += kUBlock) vals[i] = i < len ? in[b0 + i] : 0;
+  __syncthreads();
+  constexpr int per = kScanBlock / kUBlock;
+  int32_t s = 0;
+  for (int k = 0; k < per; ++k) s += vals[threadIdx.x * per + k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t a = bsum[blockIdx.x];
+    for (int i = 0; i < kUBlock; ++i) {
+      int32_t x = part[i];
+      part[i] = a;
+      a += x;
+    }
+    part[kUBlock] = a;
+  }
+  __syncthreads();
+  s = part[threadIdx.x];
+  for (int k = 0; k < per; ++k) {
+    const int i = threadIdx.x * per + k;
+    if (i < len) out[b0 + i] = s;
+    s += vals[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[kUBlock];
+}
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    a[i] = v;
+}
+
+// Replay of one routing round, top-down, with exact counts.  cnt(v) is the
+// weight of the batch slice below heap position v (1 per inserted point, 1 per
+// point actually removed); a killed task lies below a region.
+__global__ void __launch_bounds__(64) k_decide(const Task* tasks, int lambda, const int32_t* hn_all,
+                                               const int32_t* bsize, const int32_t* bstart,
+                                               const int32_t* child_idx, const int8_t* killed, int8_t* killed_next,
+                                               const int32_t* M, Node* nodes, int64_t an, int64_t ad, int insert,
+                                               Region* regions, int* n_regions) {
+  const int NB = 1 << lambda, nheap = 2 << lambda;
+  __shared__ int32_t cnt[2 << kMaxLambda], s0[2 << kMaxLambda], sz[2 << kMaxLambda];
+  __shared__ uint8_t alive[2 << kMaxLambda];
+  const int sig = blockIdx.x;
+  if (killed[sig]) return;
+  const Task q = tasks[sig];
+  const int32_t* hn = hn_all + static_cast<int64_t>(sig) * nheap;
+  for (int j = threadIdx.x; j < NB; j += 64) {
+    const int32_t st = bstart[static_cast<int64_t>(sig) * NB + j];
+    const int32_t n = bsize[static_cast<int64_t>(sig) * NB + j];
+    s0[NB + j] = st;
+    sz[NB + j] = n;
+    cnt[NB + j] = M[st + n] - M[st];
+  }
+  for (int v = threadIdx.x; v < nheap; v += 64) alive[v] = 0;
+  __syncthreads();
+  for (int l = lambda - 1; l >= 0; --l) {
+    for (int v = (1 << l) + threadIdx.x; v < (2 << l); v += 64) {
+      cnt[v] = cnt[2 * v] + cnt[2 * v + 1];
+      sz[v] = sz[2 * v] + sz[2 * v + 1];
+      s0[v] = s0[2 * v];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) alive[1] = 1;
+  __syncthreads();
+  for (int l = 0; l <= lambda; ++l) {
+    for (int v = (1 << l) + threadIdx.x; v < (2 << l); v += 64) {
+      const int32_t u = hn[v];
+      if (!alive[v] || u < 0 || cnt[v] == 0) continue;
+      const Node nd = nodes[u];
+      const int sign = insert ? 1 : -1;
+      if (nd.left < 0) {
+        if (insert) {
+          const int at = atomicAdd(n_regions, 1);
+          regions[at] = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
+        } else {
+          nodes[u].size = nd.size - cnt[v];
+        }
+      } else if (l == lambda) {
+        killed_next[child_idx[static_cast<int64_t>(sig) * nheap + v]] = 0;
+      } else {
+        const int64_t n2 = static_cast<int64_t>(nd.size) + sign * cnt[v];
+        const int64_t l2 = static_cast<int64_t>(nodes[nd.left].size) + sign * cnt[2 * v];
+        const bool bal = n2 > 0 && (ad - 2 * an) * n2 <= 2 * ad * l2 && 2 * ad * l2 <= (ad + 2 * an) * n2;
+        if (bal) {
+          nodes[u].size = static_cast<int32_t>(n2);
+          alive[2 * v] = alive[2 * v + 1] = 1;
+        } else {
+          const int at = atomicAdd(n_regions, 1);
+          regions[at] = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
+        }
+      }
+    }
+    __syncthreads();
+  }
+  (void)q;
+}
+
+// Region bookkeeping on the old positions: regid marks the points inside each
+// region; for inserts the size change of a region is noted at its end.
+__global__ void k_region_mark(const Region* regions, int32_t* regid, int32_t* delta, int insert) {
+  const Region r = regions[blockIdx.x];
+  for (int64_t o = r.a + threadIdx.x; o < r.b; o += blockDim.x) regid[o] = blockIdx.x;
+  if (insert && threadIdx.x == 0) atomicAdd(delta + r.b, r.e - r.s);
+}
+
+// New places of the old points: insert: o + S[o+1] (batch points noted at
+// region ends before o); delete: o - S[o] (removed points before o).
+template <int D>
+__global__ void k_relayout(const int64_t* X, int64_t xcap, int64_t n, const int32_t* S, const int32_t* delflag,
+                           int insert, int64_t* Y, int64_t ycap) {
+  for (int64_t o = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; o < n;
+       o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int64_t dst;
+    if (insert) {
+      dst = o + S[o + 1];
+    } else {
+      if (delflag[o]) continue;
+      dst = o - S[o];
+    }
+    for (int d = 0; d <= D; ++d) Y[d * ycap + dst] = X[d * xcap + o];
+  }
+}
+
+// Insert: batch points of each region go right after the region's old points.
+__global__ void k_place_batch(const Region* regions, int D, const int64_t* batch, int64_t m, const int32_t* S,
+                              int64_t* Y, int64_t ycap) {
+  const Region r = regions[blockIdx.x];
+  const int64_t base = static_cast<int64_t>(r.b) + (r.b > 0 ? S[r.b] : 0);
+  for (int64_t i = threadIdx.x; i < r.e - r.s; i += blockDim.x)
+    for (int d = 0; d <= D; ++d) Y[d * ycap + base + i] = batch[d * m + r.s + i];
+}
+
+// New offsets of the surviving nodes.  Live node ranges nest like the tree,
+// so a node whose first point lies inside a region and that is deeper than
+// the region's node is below it: it dies (the rebuilt subtree replaces it).
+__global__ void k_node_update(Node* nodes, int32_t n_nodes, const int32_t* regid, const Region* regions,
+                              const int32_t* S, int insert, int64_t n_old) {
+  for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_nodes; t += gridDim.x * blockDim.x) {
+    const Node nd = nodes[t];
+    if (nd.pad != 0) continue;   // dead since an earlier update
+    if (nd.off < 0 || nd.off > n_old) continue;
+    if (nd.off < n_old && nd.size > 0) {
+      const int32_t k = regid[nd.off];
+      if (k >= 0) {
+        const Region r = regions[k];
+        if (r.node == t) continue;   // overwritten by its rebuilt subtree
+        if (nd.depth > r.depth) {
+          nodes[t].pad = 1;
+          continue;
+        }
+      }
+    }
+    if (insert) nodes[t].off = nd.off + (nd.off < n_old ? S[nd.off + 1] : S[n_old]);
+    else nodes[t].off = nd.off - S[nd.off];
+  }
+}
+
+__global__ void k_region_final(Region* regions, const int32_t* S, int insert) {
+  Region& r = regions[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  if (insert) {
+    // batch points are noted at region ends, which lie after the start
+    r.new_start = r.a + S[r.a + 1];
+    r.new_size = (r.b - r.a) + (r.e - r.s);
+  } else {
+    r.new_start = r.a - S[r.a];
+    r.new_size = (r.b - r.a) - (S[r.b] - S[r.a]);
+  }
+}
+
+int exscan(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, DArr<int32_t>& bsum) {
+  const int64_t nb = std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock);
+  PKD_TRY(bsum.need(nb));
+  hipLaunchKernelGGL(k_scan_blocks, dim3(static_cast<unsigned>(nb)), dim3(kUBlock), 0, st, in, n, bsum.p);
+  PKD_TRY(kernel_status("k_scan_blocks"));
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum.p, nb);
+  PKD_TRY(kernel_status("k_scan_sums"));
+  hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nb)), dim3(kUBlock), 0, st, in, n, bsum.p, out);
+  PKD_TRY(kernel_status("k_scan_apply"));
+  return PKD_OK;
+}
+
+int fill(hipStream_t st, int32_t* a, int64_t n, int32_t v) {
+  if (n <= 0) return PKD_OK;
+  const unsigned g = static_cast<unsigned>(std::min<int64_t>(4096, (n + 255) / 256));
+  hipLaunchKernelGGL(k_fill_i32, dim3(g), dim3(256), 0, st, a, n, v);
+  return kernel_status("k_fill_i32");
+}
+
+struct RoundSave {
+  DArr<Task> tasks;
+  DArr<int32_t> hn, bsize, bstart, child;
+  int ns = 0;
+  explicit RoundSave(hipStream_t s) : tasks(s), hn(s), bsize(s), bstart(s), child(s) {}
+};
+
+template <int D>
+int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m, bool insert,
+             int64_t* removed) {
+  const Params& P = T->prm;
+  const int lambda = P.lambda, NB = 1 << lambda, nheap = 2 << lambda;
+  const int64_t n = T->n;
+  DArr<int> flags(st);
+  PKD_TRY(flags.need(8));
+  PKD_HIP(hipMemsetAsync(flags.p, 0, sizeof(int) * 8, st));
+  {
+    const unsigned g = static_cast<unsigned>(std::min<int64_t>(4096, (m + 255) / 256));
+    hipLaunchKernelGGL(k_validate<D>, dim3(g), dim3(256), 0, st, coords, m, flags.p);
+    PKD_TRY(kernel_status("k_validate"));
+    int h = 0;
+    PKD_HIP(hipMemcpyAsync(&h, flags.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    PKD_HIP(hipStreamSynchronize(st));
+    if (h & kErrRange) return PKD_ERR_RANGE;
+  }
+  if (insert && n == 0) {
+    // inserting into the empty tree is Build(P) at the root
+    if (m > T->cap) {
+      dev_free(T->buf[0], st);
+      dev_free(T->buf[1], st);
+      T->buf[0] = T->buf[1] = nullptr;
+      const int64_t cap = std::max<int64_t>(m, T->cap + T->cap / 2);
+      const size_t bytes = sizeof(int64_t) * static_cast<size_t>(D + 1) * cap;
+      void* a = nullptr;
+      void* b = nullptr;
+      PKD_TRY(dev_alloc(&a, bytes, st));
+      PKD_TRY(dev_alloc(&b, bytes, st));
+      T->buf[0] = static_cast<int64_t*>(a);
+      T->buf[1] = static_cast<int64_t*>(b);
+      T->cap = cap;
+    }
+    T->node_count = 1;
+    T->height = 0;
+    Task root{0, static_cast<int32_t>(m), 0, 0, 2, 0};
+    PKD_TRY(build_tasks(T, st, std::vector<Task>{root}, coords, ids, m));
+    T->n = m;
+    return PKD_OK;
+  }
+
+  // ---- route the batch to the leaves
+  DArr<int64_t> wb0(st), wb1(st), wf(st), rx(st);
+  DArr<uint8_t> rdim(st);
+  DArr<int8_t> mode(st);
+  DArr<Task> cur(st), nxt(st);
+  DArr<Res> res(st);
+  DArr<int> ctr(st);
+  DArr<int32_t> leaf_of(st), Mw(st), M(st), bsum(st);
+  PKD_TRY(wb0.need(static_cast<size_t>(D + 1) * m));
+  PKD_TRY(wb1.need(static_cast<size_t>(D + 1) * m));
+  PKD_TRY(wf.need(static_cast<size_t>(D + 1) * m));
+  PKD_HIP(hipMemcpyAsync(wb0.p, coords, sizeof(int64_t) * D * m, hipMemcpyDeviceToDevice, st));
+  PKD_HIP(hipMemcpyAsync(wb0.p + static_cast<int64_t>(D) * m, ids, sizeof(int64_t) * m, hipMemcpyDeviceToDevice, st));
+  Bufs wb;
+  wb.c[0] = wb0.p;
+  wb.id[0] = wb0.p + static_cast<int64_t>(D) * m;
+  wb.c[1] = wb1.p;
+  wb.id[1] = wb1.p + static_cast<int64_t>(D) * m;
+  wb.c[2] = wb.id[2] = nullptr;
+  wb.cap[0] = wb.cap[1] = m;
+  wb.cap[2] = 0;
+  PKD_TRY(ctr.need(8));
+  PKD_HIP(hipMemsetAsync(ctr.p, 0, sizeof(int) * 8, st));
+  int* d_next = ctr.p;
+  int* d_res = ctr.p + 1;
+  int* d_regions = ctr.p + 2;
+  PKD_TRY(res.need(static_cast<size_t>(m) + 1));
+
+  Node root;
+  PKD_HIP(hipMemcpyAsync(&root, T->nodes, sizeof(Node), hipMemcpyDeviceToHost, st));
+  PKD_HIP(hipStreamSynchronize(st));
+  std::vector<RoundSave*> rounds;
+  struct Cleanup {
+    std::vector<RoundSave*>& r;
+    ~Cleanup() {
+      for (auto* x : r) delete x;
+    }
+  } cleanup{rounds};
+  int nres = 0;
+  if (root.left < 0) {
+    Res r0{0, 0, static_cast<int32_t>(m), 0};
+    PKD_HIP(hipMemcpyAsync(res.p, &r0, sizeof(Res), hipMemcpyHostToDevice, st));
+    nres = 1;
+  } else {
+    PKD_TRY(cur.need(1));
+    Task t0{0, static_cast<int32_t>(m), 0, 0, 0, 0};
+    PKD_HIP(hipMemcpyAsync(cur.p, &t0, sizeof(Task), hipMemcpyHostToDevice, st));
+    int ns = 1, src = 0;
+    SieveWork W(st);
+    while (ns > 0) {
+      if (rounds.size() > 200) return PKD_ERR_INTERNAL;
+      RoundSave* R = new RoundSave(st);
+      rounds.push_back(R);
+      R->ns = ns;
+      PKD_TRY(R->tasks.need(ns));
+      PKD_HIP(hipMemcpyAsync(R->tasks.p, cur.p, sizeof(Task) * ns, hipMemcpyDeviceToDevice, st));
+      PKD_TRY(rx.need(static_cast<size_t>(ns) * NB));
+      PKD_TRY(rdim.need(static_cast<size_t>(ns) * NB));
+      PKD_TRY(mode.need(ns));
+      PKD_TRY(R->hn.need(static_cast<size_t>(ns) * nheap));
+      PKD_TRY(R->child.need(static_cast<size_t>(ns) * nheap));
+      PKD_HIP(hipMemsetAsync(mode.p, 0, ns, st));
+      hipLaunchKernelGGL(k_fetch_skeleton, dim3(ns), dim3(64), 0, st, cur.p, T->nodes, lambda, rx.p, rdim.p, R->hn.p);
+      PKD_TRY(kernel_status("k_fetch_skeleton"));
+      int64_t ntiles = 0, nchunks = 0, pts = 0;
+      PKD_TRY(sieve_layout(st, cur.p, ns, P.tile, W, P.s, 0, nullptr, &ntiles, &nchunks, &pts));
+      const int dst = 1 - src;
+      PKD_TRY(sieve_pass(st, D, lambda, P.tile, cur.p, ns, wb, src, dst, rx.p, rdim.p, mode.p, W, ntiles, nchunks,
+                         pts, 0, flags.p));
+      PKD_TRY(R->bsize.need(static_cast<size_t>(ns) * NB));
+      PKD_TRY(R->bstart.need(static_cast<size_t>(ns) * NB));
+      PKD_HIP(hipMemcpyAsync(R->bsize.p, W.bsize.p, sizeof(int32_t) * ns * NB, hipMemcpyDeviceToDevice, st));
+      PKD_HIP(hipMemcpyAsync(R->bstart.p, W.bstart.p, sizeof(int32_t) * ns * NB, hipMemcpyDeviceToDevice, st));
+      PKD_TRY(nxt.need(static_cast<size_t>(ns) * NB));
+      PKD_HIP(hipMemsetAsync(d_next, 0, sizeof(int), st));
+      hipLaunchKernelGGL(k_route_emit, dim3(ns), dim3(64), 0, st, cur.p, T->nodes, lambda, R->hn.p, W.bsize.p,
+                         W.bstart.p, dst, nxt.p, d_next, R->child.p, res.p, d_res);
+      PKD_TRY(kernel_status("k_route_emit"));
+      int h[2];
+      PKD_HIP(hipMemcpyAsync(h, ctr.p, sizeof(h), hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipStreamSynchronize(st));
+      ns = h[0];
+      nres = h[1];
+      std::swap(cur.p, nxt.p);
+      std::swap(cur.cap, nxt.cap);
+      src = dst;
+    }
+  }
+  PKD_TRY(leaf_of.need(m));
+  if (nres > 0)
+    hipLaunchKernelGGL(k_gather, dim3(nres), dim3(256), 0, st, res.p, D, wb, wf.p, m, leaf_of.p);
+  PKD_TRY(kernel_status("k_gather"));
+
+  // ---- weights: 1 per inserted point, 1 per point actually removed
+  const int64_t* X = T->buf[T->cur];
+  DArr<int32_t> delflag(st), S(st), regid(st);
+  PKD_TRY(Mw.need(m + 1));
+  PKD_TRY(M.need(m + 1));
+  int64_t n_removed = 0;
+  if (insert) {
+    PKD_TRY(fill(st, Mw.p, m, 1));
+  } else {
+    PKD_TRY(delflag.need(n + 1));
+    PKD_TRY(fill(st, delflag.p, n + 1, 0));
+    hipLaunchKernelGGL(k_match<D>, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256), 0, st, wf.p, m,
+                       leaf_of.p, T->nodes, X, T->cap, delflag.p, Mw.p);
+    PKD_TRY(kernel_status("k_match"));
+  }
+  PKD_TRY(exscan(st, Mw.p, M.p, m, bsum));
+  if (!insert) {
+    int32_t tot = 0;
+    PKD_HIP(hipMemcpyAsync(&tot, M.p + m, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PKD_HIP(hipStreamSynchronize(st));
+    n_removed = tot;
+    *removed = tot;
+    if (tot == 0) return PKD_OK;   // nothing to do
+  }
+
+  // ---- decide, round by round, top-down
+  DArr<Region> regions(st);
+  DArr<int8_t> killed(st), killed_next(st);
+  PKD_TRY(regions.need(static_cast<size_t>(m) + 1));
+  if (rounds.empty()) {
+    // the root is a leaf
+    if (insert) {
+      Region r{0, root.depth, root.off, root.off + root.size, 0, static_cast<int32_t>(m), 0, 0};
+      PKD_HIP(hipMemcpyAsync(regions.p, &r, sizeof(Region), hipMemcpyHostToDevice, st));
+      int one = 1;
+      PKD_HIP(hipMemcpyAsync(d_regions, &one, sizeof(int), hipMemcpyHostToDevice, st));
+    } else {
+      int32_t sz = root.size - static_cast<int32_t>(n_removed);
+      PKD_HIP(hipMemcpyAsync(reinterpret_cast<char*>(T->nodes) + offsetof(Node, size), &sz, sizeof(int32_t),
+                             hipMemcpyHostToDevice, st));
+    }
+  } else {
+    PKD_TRY(killed.need(1));
+    PKD_HIP(hipMemsetAsync(killed.p, 0, 1, st));
+    for (size_t r = 0; r < rounds.size(); ++r) {
+      RoundSave* R = rounds[r];
+      const int nn = r + 1 < rounds.size() ? rounds[r + 1]->ns : 0;
+      PKD_TRY(killed_next.need(static_cast<size_t>(nn) + 1));
+      PKD_HIP(hipMemsetAsync(killed_next.p, 1, nn + 1, st));
+      hipLaunchKernelGGL(k_decide, dim3(R->ns), dim3(64), 0, st, R->tasks.p, lambda, R->hn.p, R->bsize.p, R->bstart.p,
+                         R->child.p, killed.p, killed_next.p, M.p, T->nodes, P.alpha_num, P.alpha_den,
+                         insert ? 1 : 0, regions.p, d_regions);
+      PKD_TRY(kernel_status("k_decide"));
+      std::swap(killed.p, killed_next.p);
+      std::swap(killed.cap, killed_next.cap);
+    }
+  }
+  int n_regions = 0;
+  PKD_HIP(hipMemcpyAsync(&n_regions, d_regions, sizeof(int), hipMemcpyDeviceToHost, st));
+  PKD_HIP(hipStreamSynchronize(st));
+
+  // ---- new layout of the packed point array
+  const int64_t n_new = insert ? n + m : n - n_removed;
+  int64_t* Xold = T->buf[T->cur];
+  const int64_t old_cap = T->cap;
+  int64_t* Ynew = T->buf[1 - T->cur];
+  int64_t new_cap = T->cap;
+  int64_t* fresh_twin = nullptr;
+  if (n_new > T->cap) {
+    new_cap = std::max<int64_t>(n_new, T->cap + T->cap / 2);
+    const size_t bytes = sizeof(int64_t) * static_cast<size_t>(D + 1) * new_cap;
+    void* a = nullptr;
+    void* b = nullptr;
+    PKD_TRY(dev_alloc(&a, bytes, st));
+    int rc = dev_alloc(&b, bytes, st);
+    if (rc != PKD_OK) {
+      dev_free(a, st);
+      return rc;
+    }
+    Ynew = static_cast<int64_t*>(a);
+    fresh_twin = static_cast<int64_t*>(b);
+  }
+  PKD_TRY(S.need(n + 2));
+  PKD_TRY(regid.need(n + 1));
+  PKD_TRY(fill(st, regid.p, n + 1, -1));
+  if (insert) {
+    PKD_TRY(delflag.need(n + 2));
+    PKD_TRY(fill(st, delflag.p, n + 2, 0));
+    if (n_regions > 0)
+      hipLaunchKernelGGL(k_region_mark, dim3(n_regions), dim3(256), 0, st, regions.p, regid.p, delflag.p, 1);
+    PKD_TRY(kernel_status("k_region_mark"));
+    PKD_TRY(exscan(st, delflag.p, S.p, n + 1, bsum));   // S[o] = batch points noted at ends < o
+  } else {
+    if (n_regions > 0)
+      hipLaunchKernelGGL(k_region_mark, dim3(n_regions), dim3(256), 0, st, regions.p, regid.p, delflag.p, 0);
+    PKD_TRY(kernel_status("k_region_mark"));
+    PKD_TRY(exscan(st, delflag.p, S.p, n, bsum));       // S[o] = removed points before o
+  }
+  if (n > 0) {
+    const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (n + 255) / 256));
+    hipLaunchKernelGGL(k_relayout<D>, dim3(g), dim3(256), 0, st, Xold, old_cap, n, S.p, delflag.p, insert ? 1 : 0,
+                       Ynew, new_cap);
+    PKD_TRY(kernel_status("k_relayout"));
+  }
+  if (insert && n_regions > 0) {
+    hipLaunchKernelGGL(k_place_batch, dim3(n_regions), dim3(256), 0, st, regions.p, D, wf.p, m, S.p, Ynew, new_cap);
+    PKD_TRY(kernel_status("k_place_batch"));
+  }
+  if (T->node_count > 0) {
+    const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (T->node_count + 255) / 256));
+    hipLaunchKernelGGL(k_node_update, dim3(g), dim3(256), 0, st, T->nodes, T->node_count, regid.p, regions.p, S.p,
+                       insert ? 1 : 0, n);
+    PKD_TRY(kernel_status("k_node_update"));
+  }
+  if (n_regions > 0) {
+    hipLaunchKernelGGL(k_region_final, dim3(n_regions), dim3(64), 0, st, regions.p, S.p, insert ? 1 : 0);
+    PKD_TRY(kernel_status("k_region_final"));
+  }
+  std::vector<Region> hreg(n_regions);
+  if (n_regions > 0)
+    PKD_HIP(hipMemcpyAsync(hreg.data(), regions.p, sizeof(Region) * n_regions, hipMemcpyDeviceToHost, st));
+  PKD_HIP(hipStreamSynchronize(st));
+
+  // the new array becomes the tree's; the old one its twin
+  if (fresh_twin) {
+    dev_free(T->buf[0], st);
+    dev_free(T->buf[1], st);
+    T->buf[0] = Ynew;
+    T->buf[1] = fresh_twin;
+    T->cur = 0;
+    T->cap = new_cap;
+  } else {
+    T->cur = 1 - T->cur;
+  }
+  T->n = n_new;
+
+  // ---- rebuild every region (one segmented Build)
+  if (n_regions > 0) {
+    std::vector<Task> roots;
+    roots.reserve(n_regions);
+    for (const Region& r : hreg) {
+      Task t;
+      t.start = r.new_start;
+      t.m = r.new_size;
+      t.slot = r.node;
+      t.depth = static_cast<int16_t>(r.depth);
+      t.buf = static_cast<int8_t>(T->cur);
+      t.mode = 0;
+      roots.push_back(t);
+    }
+    PKD_TRY(build_tasks(T, st, roots, nullptr, nullptr, 0));
+  }
+  return PKD_OK;
+}
+
+}  // namespace
+
+int run_insert(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m) {
+  int64_t dummy = 0;
+  switch (T->prm.D) {
+    case 1: return update_d<1>(T, st, coords, ids, m, true, &dummy);
+    case 2: return update_d<2>(T, st, coords, ids, m, true, &dummy);
+    case 3: return update_d<3>(T, st, coords, ids, m, true, &dummy);
+    case 4: return update_d<4>(T, st, coords, ids, m, true, &dummy);
+    case 5: return update_d<5>(T, st, coords, ids, m, true, &dummy);
+    case 6: return update_d<6>(T, st, coords, ids, m, true, &dummy);
+    case 7: return update_d<7>(T, st, coords, ids, m, true, &dummy);
+  }
   return PKD_ERR_UNSUPPORTED;
 }
+
+int run_delete(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m, int64_t* removed) {
+  *removed = 0;
+  switch (T->prm.D) {
+    case 1: return update_d<1>(T, st, coords, ids, m, false, removed);
+    case 2: return update_d<2>(T, st, coords, ids, m, false, removed);
+    case 3: return update_d<3>(T, st, coords, ids, m, false, removed);
+    case 4: return update_d<4>(T, st, coords, ids, m, false, removed);
+    case 5: return update_d<5>(T, st, coords, ids, m, false, removed);
+    case 6: return update_d<6>(T, st, coords, ids, m, false, removed);
+    case 7: return update_d<7>(T, st, coords, ids, m, false, removed);
+  }
+  return PKD_ERR_UNSUPPORTED;
+}
+
 }  // namespace pkd

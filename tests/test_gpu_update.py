@@ -1,0 +1,191 @@
+"""GPU parity of BatchInsert / BatchDelete: after every batch the exported GPU
+tree equals the oracle's node for node, and queries equal brute force on the
+current point set.  All through the C-ABI."""
+import numpy as np
+import pytest
+
+import synth
+from tests import treecheck
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_09275_amd as pk
+    pk.lib()
+    return pk
+
+
+def _same(gt, ot, label):
+    g = gt.export()
+    o = ot.export()
+    assert g[0].shape == o[0].shape, (label, g[0].shape, o[0].shape)
+    rows_eq = np.all(g[0] == o[0], axis=1)
+    if not rows_eq.all():
+        bad = np.nonzero(~rows_eq)[0][:5]
+        raise AssertionError("%s: rows differ at %s gpu %s oracle %s" % (label, bad, g[0][bad], o[0][bad]))
+    assert np.array_equal(g[1], o[1]), label
+    assert np.array_equal(g[2], o[2]), label
+    return g
+
+
+class Pair:
+    """The same tree on the GPU and in the oracle, plus the current point set."""
+
+    def __init__(self, orc, pk, c, i, **kw):
+        D = c.shape[0]
+        self.orc, self.pk = orc, pk
+        self.op = orc.Params(D, **kw)
+        self.g = pk.Tree(pk.Params(D, **kw), c, i)
+        self.o = orc.Tree(self.op, c, i)
+        self.c, self.i = c, i
+
+    def insert(self, c, i):
+        self.g.insert(c, i)
+        self.o.insert(c, i)
+        self.c = np.concatenate([self.c, c], axis=1)
+        self.i = np.concatenate([self.i, i])
+
+    def delete(self, c, i):
+        a = self.g.delete(c, i)
+        b = self.o.delete(c, i)
+        assert a == b, (a, b)
+        # an entry only removes a point when its coordinates match too
+        self.c, self.i = self._remaining(c, i)
+        return a
+
+    def _remaining(self, c, i):
+        pos = {int(x): k for k, x in enumerate(self.i)}
+        keep = np.ones(self.i.shape[0], dtype=bool)
+        for j in range(i.shape[0]):
+            k = pos.get(int(i[j]))
+            if k is not None and keep[k] and np.array_equal(self.c[:, k], c[:, j]):
+                keep[k] = False
+        return np.ascontiguousarray(self.c[:, keep]), self.i[keep]
+
+    def check(self, label, q=None, boxes=None):
+        rows, ids, coords = _same(self.g, self.o, label)
+        treecheck.check_tree(rows, ids, coords, self.op.phi, self.c, self.i)
+        assert self.g.size() == self.i.shape[0]
+        if q is not None:
+            gi, gd = self.g.knn(q, 10)
+            bi, bd = self.orc.brute_knn(self.c, self.i, q, 10)
+            assert np.array_equal(gi.cpu().numpy(), bi) and np.array_equal(gd.cpu().numpy(), bd), label
+        if boxes is not None:
+            got = self.g.range_count(*boxes).cpu().numpy()
+            assert np.array_equal(got, self.orc.brute_range_count(self.c, *boxes)), label
+
+
+@pytest.mark.parametrize("D,kw", [(3, {}), (2, dict(lam=3, phi=4, sigma=4)), (2, dict(alpha=(1, 10)))])
+def test_insert_delete_sequence(orc, pk, D, kw):
+    c, i, state = synth.clustered_points(120000, D, seed=60, n_clusters=60)
+    P = Pair(orc, pk, c, i, **kw)
+    q = synth.uniform_queries(300, D, seed=61)
+    boxes = synth.log_uniform_boxes(300, D, seed=62)
+    P.check("build", q, boxes)
+    nid = 10 ** 7
+    for step in range(3):
+        nc, ni, state = synth.clustered_points(15000, D, seed=63 + step, continue_from=state, id_base=nid)
+        nid += 15000
+        P.insert(nc, ni)
+        P.check("insert %d" % step, q, boxes)
+        pick = synth.sample_existing(P.i, 12000, seed=70 + step)
+        assert P.delete(P.c[:, pick], P.i[pick]) == 12000
+        P.check("delete %d" % step, q, boxes)
+
+
+def test_uniform_small_batches(orc, pk):
+    c, i = synth.uniform_points(200000, 3, seed=80)
+    P = Pair(orc, pk, c, i)
+    nid = 10 ** 7
+    for step, m in enumerate([1, 7, 100, 1000]):
+        nc, ni = synth.uniform_points(m, 3, seed=81 + step, id_base=nid)
+        nid += m
+        P.insert(nc, ni)
+        P.check("insert m=%d" % m)
+        pick = synth.sample_existing(P.i, m, seed=90 + step)
+        P.delete(P.c[:, pick], P.i[pick])
+        P.check("delete m=%d" % m)
+
+
+def test_large_batches(orc, pk):
+    c, i = synth.uniform_points(100000, 2, seed=100)
+    P = Pair(orc, pk, c, i)
+    nc, ni = synth.uniform_points(150000, 2, seed=101, id_base=10 ** 7)
+    P.insert(nc, ni)
+    P.check("insert 150%")
+    pick = synth.sample_existing(P.i, 200000, seed=102)
+    P.delete(P.c[:, pick], P.i[pick])
+    P.check("delete 80%")
+
+
+def test_root_rebuild_at_balance_bound(orc, pk):
+    c, i = synth.uniform_points(3000, 2, seed=81)
+    P = Pair(orc, pk, c, i)
+    rows, _, _ = P.g.export()
+    d, x, n, l = rows[0, 1], rows[0, 2], rows[0, 3], rows[1, 3]
+    k = 4 * n - 5 * l
+    rng = np.random.default_rng(82)
+    newc = rng.integers(0, 10 ** 9, size=(2, k + 1)).astype(np.int64)
+    newc[d] = rng.integers(0, x, size=k + 1)
+    newi = np.arange(10 ** 6, 10 ** 6 + k + 1, dtype=np.int64)
+    P.insert(np.ascontiguousarray(newc[:, :k]), newi[:k])
+    P.check("at bound")
+    P.insert(np.ascontiguousarray(newc[:, k:]), newi[k:])
+    P.check("past bound")
+
+
+def test_empty_tree_and_delete_everything(orc, pk):
+    E = Pair(orc, pk, np.zeros((3, 0), dtype=np.int64), np.zeros(0, dtype=np.int64))
+    c, i = synth.uniform_points(20000, 3, seed=110)
+    E.insert(c, i)
+    E.check("insert into empty")
+    assert E.delete(c, i) == 20000
+    E.check("delete all")
+    E.insert(c[:, :50].copy(), i[:50])
+    E.check("reinsert small")
+    assert E.delete(c[:, :50].copy(), i[:50]) == 50
+    E.check("delete all small")
+
+
+def test_delete_absent_mismatched_and_repeated(orc, pk):
+    c, i = synth.uniform_points(30000, 2, seed=120)
+    P = Pair(orc, pk, c, i)
+    ac, ai = synth.uniform_points(500, 2, seed=121, id_base=10 ** 8)
+    assert P.delete(ac, ai) == 0
+    wrong = c[:, :300].copy()
+    wrong[1] += 1
+    assert P.delete(wrong, i[:300]) == 0
+    P.check("no-op deletes")
+    rc = np.concatenate([c[:, :400], c[:, :400]], axis=1)
+    ri = np.concatenate([i[:400], i[:400]])
+    assert P.delete(rc, ri) == 400
+    P.check("repeated entries")
+
+
+def test_duplicates_with_updates(orc, pk):
+    c, i = synth.duplicate_heavy_points(50000, 2, seed=130, n_distinct=20)
+    P = Pair(orc, pk, c, i)
+    nc, ni = synth.duplicate_heavy_points(20000, 2, seed=130, n_distinct=20, id_base=10 ** 7)
+    P.insert(nc, ni)
+    P.check("dup insert")
+    pick = synth.sample_existing(P.i, 30000, seed=131)
+    P.delete(P.c[:, pick], P.i[pick])
+    P.check("dup delete")
+
+
+def test_update_rejects_out_of_range(pk):
+    c, i = synth.uniform_points(5000, 2, seed=140)
+    t = pk.Tree(pk.Params(2), c, i)
+    before = t.export()
+    bad = synth.uniform_points(10, 2, seed=141, id_base=10 ** 7)[0]
+    bad[0, 3] = 1 << 30
+    with pytest.raises(pk.PkdError) as e:
+        t.insert(bad, np.arange(10 ** 7, 10 ** 7 + 10, dtype=np.int64))
+    assert e.value.code == -2
+    for a, b in zip(before, t.export()):
+        assert np.array_equal(a, b)
