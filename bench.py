@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=2048)
     ap.add_argument("--cpu-sample", type=int, default=4_000_000, help="points of the oracle's build sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 2 GiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -102,6 +104,16 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if a.copy_calibration:
+        # a plain copy of known size: reads and writes exactly 2 GiB each
+        src = torch.empty(1 << 28, dtype=torch.int64, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copy calibration: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8),
+              file=sys.stderr, flush=True)
+        del src, dst
     t0 = time.perf_counter()
     coords, ids = synth.uniform_points(a.n, a.dim, seed=3)
     q = synth.uniform_queries(a.queries, a.dim, seed=4)

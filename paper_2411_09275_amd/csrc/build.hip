@@ -57,7 +57,16 @@ __device__ inline int64_t pick(const int64_t (&c)[D], int d) {
 template <int D>
 __device__ inline int route(const int64_t (&c)[D], const int64_t* sx, const uint8_t* sdim, int lambda) {
   int v = 1;
-  for (int l = 0; l < lambda; ++l) v = 2 * v + (pick<D>(c, sdim[v]) >= sx[v] ? 1 : 0);
+  for (int l = 0; l < lambda; ++l) {
+    // compare every coordinate and keep the one of the split dimension (no
+    // dynamic register indexing)
+    const int d = sdim[v];
+    const int64_t x = sx[v];
+    int ge = 0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) ge |= (d == e) & (c[e] >= x);
+    v = 2 * v + ge;
+  }
   return v - (1 << lambda);
 }
 
@@ -231,6 +240,87 @@ __device__ void lds_presort(const uint32_t* C, uint16_t* O, uint64_t* key, int m
   }
 }
 
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int mask) {
+  const int lo = __shfl_xor(static_cast<int>(static_cast<uint32_t>(v)), mask);
+  const int hi = __shfl_xor(static_cast<int>(v >> 32), mask);
+  return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+}
+
+// Bitonic sort of NT*NPL 64-bit keys held in registers, ascending; thread t
+// holds elements t*NPL .. t*NPL+NPL-1.  Partners at distance below NPL are in
+// the same thread, below 64*NPL in the same wave (shuffles); larger distances
+// go through LDS (tmp: NT*NPL keys).
+template <int NT, int NPL>
+__device__ void block_bitonic(uint64_t (&k)[NPL], uint64_t* tmp) {
+  constexpr int N = NT * NPL;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+    for (int j = size >> 1; j > 0; j >>= 1) {
+      if (j < NPL) {
+#pragma unroll
+        for (int r = 0; r < NPL; ++r) {
+          const int pr = r ^ j;
+          if (pr > r) {
+            // ascending iff bit `size` of the element index is clear
+            const bool up = size < NPL ? (r & size) == 0 : ((tid * NPL) & size) == 0;
+            const uint64_t a = k[r], b = k[pr];
+            const bool sw = (a > b) == up;
+            k[r] = sw ? b : a;
+            k[pr] = sw ? a : b;
+          }
+        }
+      } else if (j < 64 * NPL) {
+        // partner in lane ^ (j/NPL), same register; keep the smaller key iff
+        // this element is the lower one of an ascending pair (or the upper
+        // one of a descending pair)
+        const bool keep_min = (((tid * NPL) & j) == 0) == (((tid * NPL) & size) == 0);
+#pragma unroll
+        for (int r = 0; r < NPL; ++r) {
+          const uint64_t o = shfl_xor_u64(k[r], j / NPL);
+          const bool take = (o < k[r]) == keep_min;
+          k[r] = take ? o : k[r];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < NPL; ++r) tmp[tid * NPL + r] = k[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NPL; ++r) {
+          const int e = tid * NPL + r;
+          const uint64_t o = tmp[e ^ j];
+          const bool keep_min = (((e & j) == 0) == ((e & size) == 0));
+          const uint64_t mn = k[r] < o ? k[r] : o, mx = k[r] < o ? o : k[r];
+          k[r] = keep_min ? mn : mx;
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// Per-dimension sorted orders with the register bitonic sort (m <= NT*NPL).
+template <int D, int NT, int NPL>
+__device__ void block_presort(const uint32_t* C, uint16_t* O, uint64_t* tmp, int m, int P) {
+  const int tid = threadIdx.x;
+  for (int d = 0; d < D; ++d) {
+    uint64_t k[NPL];
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int e = tid * NPL + r;
+      k[r] = e < m ? (static_cast<uint64_t>(C[d * P + e]) << 16) | static_cast<uint64_t>(e) : ~0ULL;
+    }
+    block_bitonic<NT, NPL>(k, tmp);
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int e = tid * NPL + r;
+      if (e < m) O[d * P + e] = static_cast<uint16_t>(k[r] & 0xFFFF);
+    }
+  }
+  __syncthreads();
+}
+
 // Split rule of a node that owns positions [a, a+L) (L >= 1): widest
 // dimension (max - min, lowest index on ties), upper median v[floor(L/2)],
 // moved to the next larger distinct value if it equals the minimum.
@@ -318,8 +408,8 @@ constexpr uint16_t kNone = 0xFFFF;
 template <int D>
 __device__ void lds_partition(uint16_t* O, uint16_t* Otmp, int P, int m, const uint16_t* seg_of_pt,
                               const uint8_t* splits, const uint16_t* segA, const uint16_t* segNL,
-                              const uint8_t* flag, uint8_t* fpos, uint16_t* F, uint32_t* part) {
-  for (int d = 0; d < D; ++d) {
+                              const uint8_t* flag, uint8_t* fpos, uint16_t* F, uint32_t* part, int nd = D) {
+  for (int d = 0; d < nd; ++d) {
     uint16_t* Od = O + d * P;
     for (int p = threadIdx.x; p < m; p += blockDim.x) {
       uint16_t e = Od[p];
@@ -358,7 +448,7 @@ struct SkelLayout {
   size_t key, C, O, Otmp, node_of, F, flag, fpos, end;
   __host__ __device__ SkelLayout(int D, int P) {
     size_t o = 0;
-    key = o;      o += sizeof(uint64_t) * next_pow2(P);
+    key = o;      o += sizeof(uint64_t) * (next_pow2(P) > kBlock ? next_pow2(P) : kBlock);   // block sort exchange
     C = o;        o += sizeof(uint32_t) * D * P;
     O = o;        o += sizeof(uint16_t) * D * P;
     Otmp = o;     o += sizeof(uint16_t) * P;
@@ -373,11 +463,11 @@ struct SkelLayout {
 struct FinLayout {
   size_t IDS, key, C, O, Otmp, seg, F, flag, fpos, lA0, lA1, lL0, lL1, lN0, lN1, sxs, snl, srank, sdm, ssplit, end;
   int MS;   // segments per level: splitting segments hold > phi points each
-  __host__ __device__ FinLayout(int D, int P, int phi) {
+  __host__ __device__ FinLayout(int D, int P, int phi, bool multiwave) {
     MS = min(P, 2 * P / (phi + 1) + 2);
     size_t o = 0;
     IDS = o;    o += sizeof(int64_t) * P;
-    key = o;    o += sizeof(uint64_t) * P;
+    key = o;    o += multiwave ? sizeof(uint64_t) * P : 0;   // sort exchange across waves
     lN0 = o;    o += sizeof(int32_t) * MS;
     lN1 = o;    o += sizeof(int32_t) * MS;
     sxs = o;    o += sizeof(uint32_t) * MS;
@@ -414,7 +504,7 @@ struct SelectOut {
   int* flags;
 };
 
-template <int D>
+template <int D, int NPL>
 __global__ void __launch_bounds__(kBlock) k_select_skeleton(const Task* sp, int ns, Bufs bufs, int src,
                                                             uint64_t seed, int s, int lambda,
                                                             const int8_t* shift, int small_max,
@@ -603,7 +693,7 @@ __global__ void __launch_bounds__(kBlock) k_select_skeleton(const Task* sp, int 
     splits[v] = 0;
   }
   __syncthreads();
-  lds_presort<D>(C, O, key, s, P);
+  block_presort<D, kBlock, NPL>(C, O, key, s, P);
   if (tid == 0) {
     live[1] = 1;
     segA[1] = 0;
@@ -836,7 +926,8 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
   const uint32_t lane = lane_id();
   const int wave = tid >> 6;
   const unsigned long long lt = (1ULL << lane) - 1;
-  int64_t val[PPT][D];
+  // coordinates were range-checked before this pass: 30-bit values fit 32 bits
+  uint32_t val[PPT][D];
   int lab[PPT];
   int rank[PPT];
 #pragma unroll
@@ -845,9 +936,13 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
     const bool ok = li < len;
     int label = 0;
     if (ok) {
+      int64_t c[D];
 #pragma unroll
-      for (int d = 0; d < D; ++d) val[k][d] = X[d * cap + lo + li];
-      label = route<D>(val[k], sx, sd, lambda);
+      for (int d = 0; d < D; ++d) {
+        c[d] = X[d * cap + lo + li];
+        val[k][d] = static_cast<uint32_t>(c[d]);
+      }
+      label = route<D>(c, sx, sd, lambda);
     }
     unsigned long long peers = __ballot(ok);
     for (int b = 0; b < lambda; ++b) {
@@ -896,20 +991,12 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
   const int64_t ycap = bufs.cap[dst];
   const int64_t* Iin = bufs.id[src];
   int64_t* Iout = bufs.id[dst];
+#pragma unroll
   for (int a = 0; a <= D; ++a) {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      if (lpos[k] >= 0) {
-        int64_t v;
-        if (a < D) {
-          v = val[k][0];
-#pragma unroll
-          for (int d = 1; d < D; ++d) v = (a == d) ? val[k][d] : v;
-        } else {
-          v = Iin[lo + k * kBlock + tid];
-        }
-        stage[lpos[k]] = v;
-      }
+      if (lpos[k] >= 0)
+        stage[lpos[k]] = a < D ? static_cast<int64_t>(val[k][a < D ? a : 0]) : Iin[lo + k * kBlock + tid];
     }
     __syncthreads();
     int64_t* out = a < D ? Y + a * ycap : Iout;
@@ -1025,15 +1112,18 @@ __global__ void __launch_bounds__(64) k_emit(const Task* sp, int ns, int lambda,
 // Plain construction of a subproblem of m < s points (Section 3: median split
 // on the widest dimension, one level at a time) in LDS, one workgroup per
 // subproblem; P >= m is the padded size of the launch's class.
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_finish(const Task* tasks, const int* list, int P, Bufs bufs, int final_buf,
-                                                   int phi, Node* nodes, int* node_count, int64_t node_cap,
-                                                   int* height, int* flags) {
+// Node slots: each task owns a reserved range [res_base + res_off[i],
+// res_base + res_off[i+1]) sized for distinct coordinates; a task that needs
+// more (duplicates) takes the rest from the shared overflow counter.
+template <int D, int NT, int NPL>
+__global__ void __launch_bounds__(NT) k_finish(const Task* tasks, const int* list, int P, Bufs bufs, int final_buf,
+                                                   int phi, Node* nodes, int* overflow_ctr, int64_t node_cap,
+                                                   int* height, int* flags, const int32_t* res_off, int32_t res_base) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Task q = tasks[list[blockIdx.x]];
   const int m = q.m;
   const int tid = threadIdx.x;
-  const FinLayout lay(D, P, phi);
+  const FinLayout lay(D, P, phi, NT > 64);
   int64_t* IDS = reinterpret_cast<int64_t*>(smem + lay.IDS);
   uint64_t* key = reinterpret_cast<uint64_t*>(smem + lay.key);
   uint32_t* C = reinterpret_cast<uint32_t*>(smem + lay.C);
@@ -1052,13 +1142,15 @@ __global__ void __launch_bounds__(kBlock) k_finish(const Task* tasks, const int*
   uint8_t* sdm = smem + lay.sdm;
   uint8_t* ssplit = smem + lay.ssplit;
   __shared__ uint32_t part[kBlock];
-  __shared__ int sh_nlist, sh_nsplit, sh_base, sh_over, sh_maxdepth;
+  __shared__ int sh_nlist, sh_nsplit, sh_base, sh_over, sh_maxdepth, sh_next, sh_more;
+  const int ti = list[blockIdx.x];
+  const int res_end = res_base + res_off[ti + 1];
 
   const int src = q.buf;
   const int64_t* X = bufs.c[src];
   const int64_t xcap = bufs.cap[src];
   bool bad = false;
-  for (int i = tid; i < m; i += kBlock) {
+  for (int i = tid; i < m; i += NT) {
     for (int d = 0; d < D; ++d) {
       int64_t v = X[d * xcap + q.start + i];
       bad |= static_cast<uint64_t>(v) >= static_cast<uint64_t>(kCoordLimit);
@@ -1072,22 +1164,25 @@ __global__ void __launch_bounds__(kBlock) k_finish(const Task* tasks, const int*
     sh_nlist = 1;
     sh_over = 0;
     sh_maxdepth = 0;
+    sh_next = res_base + res_off[ti];
     lA[0][0] = 0;
     lL[0][0] = static_cast<uint16_t>(m);
     lN[0][0] = q.slot;
   }
   __syncthreads();
-  if (m > phi) lds_presort<D>(C, O, key, m, P);
+  if (m > phi) block_presort<D, NT, NPL>(C, O, key, m, P);
   else
-    for (int i = tid; i < m; i += kBlock) O[i] = static_cast<uint16_t>(i);
+    for (int i = tid; i < m; i += NT) O[i] = static_cast<uint16_t>(i);
   __syncthreads();
   int cur = 0;
   int depth = q.depth;
   while (true) {
     const int nl = sh_nlist;
     if (nl == 0) break;
+    if (tid == 0) sh_more = 0;
+    __syncthreads();
     // decide every segment of this level
-    for (int k = tid; k < nl; k += kBlock) {
+    for (int k = tid; k < nl; k += NT) {
       const int a = lA[cur][k], L = lL[cur][k];
       int d = 0, nleft = 0;
       uint32_t x = 0;
@@ -1101,6 +1196,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(const Task* tasks, const int*
         sdm[k] = static_cast<uint8_t>(d);
         sxs[k] = x;
         snl[k] = static_cast<uint16_t>(nleft);
+        if (nleft > phi || L - nleft > phi) sh_more = 1;   // a child splits again
       } else {
         // leaf (at most phi points, or a heavy leaf of identical points)
         Node nd;
@@ -1125,7 +1221,15 @@ __global__ void __launch_bounds__(kBlock) k_finish(const Task* tasks, const int*
         r += ssplit[k];
       }
       sh_nsplit = r;
-      int b = r > 0 ? atomicAdd(node_count, 2 * r) : 0;
+      int b = 0;
+      if (r > 0) {
+        if (sh_next + 2 * r <= res_end) {
+          b = sh_next;
+          sh_next += 2 * r;
+        } else {
+          b = atomicAdd(overflow_ctr, 2 * r);
+        }
+      }
       if (static_cast<int64_t>(b) + 2 * r > node_cap) sh_over = 1;
       sh_base = b;
     }
@@ -1134,7 +1238,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(const Task* tasks, const int*
     const int nbase = sh_base;
     const bool over = sh_over != 0;
     const int nxt = cur ^ 1;
-    for (int k = tid; k < nl; k += kBlock) {
+    for (int k = tid; k < nl; k += NT) {
       if (!ssplit[k]) continue;
       const int a = lA[cur][k], L = lL[cur][k], r = srank[k];
       const int cl = nbase + 2 * r, cr = cl + 1;
@@ -1159,13 +1263,14 @@ __global__ void __launch_bounds__(kBlock) k_finish(const Task* tasks, const int*
     }
     if (nsplit == 0) break;
     // side flags of the points of splitting segments
-    for (int e = tid; e < m; e += kBlock) {
+    for (int e = tid; e < m; e += NT) {
       const int k = seg[e];
       flag[e] = (k != kNone && ssplit[k]) ? (C[sdm[k] * P + e] < sxs[k] ? 1 : 0) : 0;
     }
     __syncthreads();
-    lds_partition<D>(O, Otmp, P, m, seg, ssplit, lA[cur], snl, flag, fpos, F, part);
-    for (int e = tid; e < m; e += kBlock) {
+    // on the last splitting level only the order that is written out matters
+    lds_partition<D>(O, Otmp, P, m, seg, ssplit, lA[cur], snl, flag, fpos, F, part, sh_more ? D : 1);
+    for (int e = tid; e < m; e += NT) {
       const int k = seg[e];
       if (k == kNone) continue;
       seg[e] = ssplit[k] ? static_cast<uint16_t>(2 * srank[k] + (flag[e] ? 0 : 1)) : kNone;
@@ -1176,14 +1281,27 @@ __global__ void __launch_bounds__(kBlock) k_finish(const Task* tasks, const int*
     ++depth;
   }
   __syncthreads();
+  // reserved slots this task did not use become dead records
+  for (int i = sh_next + tid; i < res_end; i += NT) {
+    if (i >= node_cap) break;
+    Node dead;
+    dead.x = 0;
+    dead.size = 0;
+    dead.off = 0;
+    dead.left = dead.right = -1;
+    dead.dim = -1;
+    dead.depth = 0;
+    dead.pad = 1;
+    nodes[i] = dead;
+  }
   if (sh_over) {
     if (tid == 0) atomicOr(flags, kErrNodeOverflow);
     return;
   }
-  if (tid == 0) atomicMax(height, sh_maxdepth);
+  if (tid == 0 && sh_maxdepth > *reinterpret_cast<volatile int*>(height)) atomicMax(height, sh_maxdepth);
   int64_t* Y = bufs.c[final_buf];
   const int64_t ycap = bufs.cap[final_buf];
-  for (int p = tid; p < m; p += kBlock) {
+  for (int p = tid; p < m; p += NT) {
     const int e = O[p];
     for (int d = 0; d < D; ++d) Y[d * ycap + q.start + p] = static_cast<int64_t>(C[d * P + e]);
     bufs.id[final_buf][q.start + p] = IDS[e];
@@ -1192,6 +1310,15 @@ __global__ void __launch_bounds__(kBlock) k_finish(const Task* tasks, const int*
 
 // Heavy leaf of identical points found by the sieve (m may exceed any LDS
 // size): copy the points into the tree array and write one leaf.
+__global__ void k_fin_reserve(const Task* fin, int n_fin, int phi, int32_t* R) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_fin) return;
+  const Task t = fin[i];
+  // a plain build of m distinct points with leaves of at most phi points has
+  // at most about 2m/(phi+1) leaves, so fewer than 4m/(phi+1)+4 nodes below the root
+  R[i] = (t.mode == 1 || t.m <= phi) ? 0 : 4 * t.m / (phi + 1) + 4;
+}
+
 __global__ void k_finish_heavy(const Task* tasks, const int* list, int D, Bufs bufs, int final_buf, Node* nodes,
                                int* height) {
   const Task q = tasks[list[blockIdx.x]];
@@ -1301,7 +1428,7 @@ size_t select_lds_bytes(int s, int cap) {
 
 template <int D>
 size_t finish_lds_bytes(int P, int phi) {
-  return FinLayout(D, P, phi).end;
+  return FinLayout(D, P, phi, P > 512).end;
 }
 
 // Exact split of subproblem q whose sample was entirely identical (host-driven,
@@ -1486,10 +1613,20 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
       SelectOut so{rx.p, rdim.p, ext.p, rootext.p, d_nrootext, shift_fix.p, d_flags};
       PKD_HIP(hipMemsetAsync(d_nrootext, 0, sizeof(int), st));
       size_t lds = select_lds_bytes<D>(s, cap);
-      PKD_TRY(allow_lds(k_select_skeleton<D>, lds));
       Prof::begin(kProfSelect, st);
-      hipLaunchKernelGGL(k_select_skeleton<D>, dim3(ns), dim3(kBlock), lds, st, sieve.p, ns, bufs, src, P.seed, s,
-                         P.lambda, W.shift.p, small_max, cand_key.p, cand_pos.p, cand_cnt.p, cap, so);
+      const int p2 = next_pow2(s);
+#define PKD_SEL(NPL)                                                                                              \
+  {                                                                                                               \
+    PKD_TRY(allow_lds(k_select_skeleton<D, NPL>, lds));                                                           \
+    hipLaunchKernelGGL((k_select_skeleton<D, NPL>), dim3(ns), dim3(kBlock), lds, st, sieve.p, ns, bufs, src, P.seed, s, \
+                       P.lambda, W.shift.p, small_max, cand_key.p, cand_pos.p, cand_cnt.p, cap, so);              \
+  }
+      if (p2 <= 256) PKD_SEL(1)
+      else if (p2 <= 512) PKD_SEL(2)
+      else if (p2 <= 1024) PKD_SEL(4)
+      else if (p2 <= 2048) PKD_SEL(8)
+      else PKD_SEL(16)
+#undef PKD_SEL
       Prof::end(kProfSelect, st, 0.0);
       PKD_TRY(kernel_status("k_select_skeleton"));
       PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
@@ -1550,32 +1687,47 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
     int counts[8];
     PKD_HIP(hipMemcpyAsync(counts, d_counts, sizeof(counts), hipMemcpyDeviceToHost, st));
     PKD_HIP(hipStreamSynchronize(st));
-    // node estimate: at most 2m-1 nodes per task; start from a data-typical
-    // bound and retry with the exact count if the estimate was short
-    std::vector<Task> none;
-    int64_t fin_pts_bound = 0;
-    {
-      std::vector<Task> hf(n_fin);
-      PKD_HIP(hipMemcpyAsync(hf.data(), fin.p, sizeof(Task) * n_fin, hipMemcpyDeviceToHost, st));
-      PKD_HIP(hipStreamSynchronize(st));
-      for (const Task& t : hf) fin_pts_bound += t.mode == 1 ? 1 : (4 * static_cast<int64_t>(t.m)) / std::max(1, P.phi) + 3;
-    }
+    // node slots: a reserved range per task from a prefix sum of size bounds
+    DArr<int32_t> R(st), res_off(st), bsum(st);
+    PKD_TRY(R.need(n_fin + 1));
+    PKD_TRY(res_off.need(n_fin + 1));
+    hipLaunchKernelGGL(k_fin_reserve, dim3((n_fin + 255) / 256), dim3(256), 0, st, fin.p, n_fin, P.phi, R.p);
+    PKD_TRY(kernel_status("k_fin_reserve"));
+    PKD_TRY(exscan_i32(st, R.p, res_off.p, n_fin, bsum));
+    int32_t reserved = 0;
+    PKD_HIP(hipMemcpyAsync(&reserved, res_off.p + n_fin, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PKD_HIP(hipStreamSynchronize(st));
     const int base_nodes = node_count;
     T->node_count = base_nodes;   // the finisher's nodes are rewritten on a retry
-    int64_t want = base_nodes + fin_pts_bound;
+    int64_t want = static_cast<int64_t>(base_nodes) + reserved + 1024;
     for (int attempt = 0; attempt < 3; ++attempt) {
       PKD_TRY(ensure_nodes(T, st, want));
       int zero_flags = 0;
-      PKD_HIP(hipMemcpyAsync(d_nodes, &base_nodes, sizeof(int), hipMemcpyHostToDevice, st));
+      const int ovf_start = base_nodes + reserved;
+      PKD_HIP(hipMemcpyAsync(d_nodes, &ovf_start, sizeof(int), hipMemcpyHostToDevice, st));
       PKD_HIP(hipMemcpyAsync(d_flags, &zero_flags, sizeof(int), hipMemcpyHostToDevice, st));
       for (int cls = 0; cls < 7; ++cls) {
         if (counts[cls] == 0) continue;
         const int Pc = 64 << cls;
         size_t lds = finish_lds_bytes<D>(Pc, P.phi);
-        PKD_TRY(allow_lds(k_finish<D>, lds));
         Prof::begin(kProfFinish, st);
-        hipLaunchKernelGGL(k_finish<D>, dim3(counts[cls]), dim3(kBlock), lds, st, fin.p, lists.p + cls * n_fin, Pc,
-                           bufs, F, P.phi, T->nodes, d_nodes, T->node_cap, d_height, d_flags);
+        // up to 512 points: one wave per subproblem; larger: a 256-thread workgroup
+#define PKD_FIN(NT, NPL)                                                                                          \
+  {                                                                                                               \
+    PKD_TRY(allow_lds(k_finish<D, NT, NPL>, lds));                                                                \
+    hipLaunchKernelGGL((k_finish<D, NT, NPL>), dim3(counts[cls]), dim3(NT), lds, st, fin.p, lists.p + cls * n_fin, Pc, \
+                       bufs, F, P.phi, T->nodes, d_nodes, T->node_cap, d_height, d_flags, res_off.p, base_nodes); \
+  }
+        switch (cls) {
+          case 0: PKD_FIN(64, 1) break;
+          case 1: PKD_FIN(64, 2) break;
+          case 2: PKD_FIN(64, 4) break;
+          case 3: PKD_FIN(64, 8) break;
+          case 4: PKD_FIN(256, 4) break;
+          case 5: PKD_FIN(256, 8) break;
+          default: PKD_FIN(256, 16) break;
+        }
+#undef PKD_FIN
         Prof::end(kProfFinish, st, 0.0);
         PKD_TRY(kernel_status("k_finish"));
       }
@@ -1614,6 +1766,13 @@ int sieve_pass_d(hipStream_t st, int lambda, int tile, const Task* tasks, int ns
                      tile, bufs, src, rx, rdim, mode, lambda, W.A.p, check, d_flags);
   Prof::end(kProfCount, st, 8.0 * D * static_cast<double>(pts));
   PKD_TRY(kernel_status("k_count"));
+  if (check) {
+    // caller input: stop before anything moves if a coordinate is out of range
+    int h = 0;
+    PKD_HIP(hipMemcpyAsync(&h, d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    PKD_HIP(hipStreamSynchronize(st));
+    if (h & kErrRange) return PKD_ERR_RANGE;
+  }
   hipLaunchKernelGGL(k_chunk_sum, dim3(static_cast<unsigned>(nchunks)), dim3(kBlock), 0, st, W.chunk_off.p,
                      W.tile_off.p, ns, lambda, W.A.p, W.S.p);
   PKD_TRY(kernel_status("k_chunk_sum"));
@@ -1639,6 +1798,96 @@ int sieve_pass_d(hipStream_t st, int lambda, int tile, const Task* tasks, int ns
 }
 
 }  // namespace
+
+// ------------------------------------------------ int32 exclusive prefix sum
+constexpr int kScanThreads = 256;
+// Exclusive prefix sums over int32 arrays: block sums, one-workgroup scan of
+// the block sums, then the per-block pass.  out[i] = sum in[0..i), out[n] = total.
+constexpr int kScanBlock = 2048;
+
+__global__ void k_scan_blocks(const int32_t* in, int64_t n, int32_t* bsum) {
+  __shared__ int32_t part[kScanThreads];
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kScanBlock;
+  int32_t s = 0;
+  for (int64_t i = b0 + threadIdx.x; i < min<int64_t>(n, b0 + kScanBlock); i += kScanThreads) s += in[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kScanThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = part[0];
+}
+
+__global__ void k_scan_sums(int32_t* bsum, int64_t nb) {
+  __shared__ int64_t part[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t b = tid * per, e = min(nb, b + per);
+  int64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += bsum[i];
+  part[tid] = s;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t a = 0;
+    for (int i = 0; i < 1024; ++i) {
+      int64_t x = part[i];
+      part[i] = a;
+      a += x;
+    }
+  }
+  __syncthreads();
+  s = part[tid];
+  for (int64_t i = b; i < e; ++i) {
+    int32_t x = bsum[i];
+    bsum[i] = static_cast<int32_t>(s);
+    s += x;
+  }
+}
+
+__global__ void k_scan_apply(const int32_t* in, int64_t n, const int32_t* bsum, int32_t* out) {
+  __shared__ int32_t vals[kScanBlock];
+  __shared__ int32_t part[kScanThreads + 1];
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kScanBlock;
+  const int len = static_cast<int>(min<int64_t>(kScanBlock, n - b0));
+  for (int i = threadIdx.x; i < kScanBlock; i += kScanThreads) vals[i] = i < len ? in[b0 + i] : 0;
+  __syncthreads();
+  constexpr int per = kScanBlock / kScanThreads;
+  int32_t s = 0;
+  for (int k = 0; k < per; ++k) s += vals[threadIdx.x * per + k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t a = bsum[blockIdx.x];
+    for (int i = 0; i < kScanThreads; ++i) {
+      int32_t x = part[i];
+      part[i] = a;
+      a += x;
+    }
+    part[kScanThreads] = a;
+  }
+  __syncthreads();
+  s = part[threadIdx.x];
+  for (int k = 0; k < per; ++k) {
+    const int i = threadIdx.x * per + k;
+    if (i < len) out[b0 + i] = s;
+    s += vals[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[kScanThreads];
+}
+
+int exscan_i32(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, DArr<int32_t>& bsum) {
+  const int64_t nb = std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock);
+  PKD_TRY(bsum.need(nb));
+  hipLaunchKernelGGL(k_scan_blocks, dim3(static_cast<unsigned>(nb)), dim3(kScanThreads), 0, st, in, n, bsum.p);
+  PKD_TRY(kernel_status("k_scan_blocks"));
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum.p, nb);
+  PKD_TRY(kernel_status("k_scan_sums"));
+  hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nb)), dim3(kScanThreads), 0, st, in, n, bsum.p, out);
+  PKD_TRY(kernel_status("k_scan_apply"));
+  return PKD_OK;
+}
+
 
 int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,
                  const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts) {

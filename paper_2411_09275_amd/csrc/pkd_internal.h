@@ -156,6 +156,10 @@ struct SieveWork {
       : tile_off(s), chunk_off(s), tot(s), shift(s), A(s), S(s), B(s), bsize(s), bstart(s) {}
 };
 
+// Exclusive prefix sum of n int32 values: out[i] = in[0] + .. + in[i-1] for
+// i in [0, n]; bsum is scratch.
+int exscan_i32(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, DArr<int32_t>& bsum);
+
 // Tile layout of `ns` tasks (device array): tiles of `tile` points, scan
 // chunks; returns the numbers of tiles and chunks and the points covered.
 int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,

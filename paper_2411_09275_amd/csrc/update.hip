@@ -182,81 +182,6 @@ __global__ void k_match(const int64_t* batch, int64_t m, const int32_t* leaf_of,
   matched[p] = got;
 }
 
-// Exclusive prefix sums over int32 arrays: block sums, one-workgroup scan of
-// the block sums, then the per-block pass.  out[i] = sum in[0..i), out[n] = total.
-constexpr int kScanBlock = 2048;
-
-__global__ void k_scan_blocks(const int32_t* in, int64_t n, int32_t* bsum) {
-  __shared__ int32_t part[kUBlock];
-  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kScanBlock;
-  int32_t s = 0;
-  for (int64_t i = b0 + threadIdx.x; i < min<int64_t>(n, b0 + kScanBlock); i += kUBlock) s += in[i];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = kUBlock / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = part[0];
-}
-
-__global__ void k_scan_sums(int32_t* bsum, int64_t nb) {
-  __shared__ int64_t part[1024];
-  const int tid = threadIdx.x;
-  const int64_t per = (nb + 1023) / 1024;
-  const int64_t b = tid * per, e = min(nb, b + per);
-  int64_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += bsum[i];
-  part[tid] = s;
-  __syncthreads();
-  if (tid == 0) {
-    int64_t a = 0;
-    for (int i = 0; i < 1024; ++i) {
-      int64_t x = part[i];
-      part[i] = a;
-      a += x;
-    }
-  }
-  __syncthreads();
-  s = part[tid];
-  for (int64_t i = b; i < e; ++i) {
-    int32_t x = bsum[i];
-    bsum[i] = static_cast<int32_t>(s);
-    s += x;
-  }
-}
-
-__global__ void k_scan_apply(const int32_t* in, int64_t n, const int32_t* bsum, int32_t* out) {
-  __shared__ int32_t vals[kScanBlock];
-  __shared__ int32_t part[kUBlock + 1];
-  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kScanBlock;
-  const int len = static_cast<int>(min<int64_t>(kScanBlock, n - b0));
-  for (int i = threadIdx.x; i < kScanBlock; i += kUBlock) vals[i] = i < len ? in[b0 + i] : 0;
-  __syncthreads();
-  constexpr int per = kScanBlock / kUBlock;
-  int32_t s = 0;
-  for (int k = 0; k < per; ++k) s += vals[threadIdx.x * per + k];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int32_t a = bsum[blockIdx.x];
-    for (int i = 0; i < kUBlock; ++i) {
-      int32_t x = part[i];
-      part[i] = a;
-      a += x;
-    }
-    part[kUBlock] = a;
-  }
-  __syncthreads();
-  s = part[threadIdx.x];
-  for (int k = 0; k < per; ++k) {
-    const int i = threadIdx.x * per + k;
-    if (i < len) out[b0 + i] = s;
-    s += vals[i];
-  }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[kUBlock];
-}
-
 __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -401,18 +326,6 @@ __global__ void k_region_final(Region* regions, const int32_t* S, int insert) {
     r.new_start = r.a - S[r.a];
     r.new_size = (r.b - r.a) - (S[r.b] - S[r.a]);
   }
-}
-
-int exscan(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, DArr<int32_t>& bsum) {
-  const int64_t nb = std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock);
-  PKD_TRY(bsum.need(nb));
-  hipLaunchKernelGGL(k_scan_blocks, dim3(static_cast<unsigned>(nb)), dim3(kUBlock), 0, st, in, n, bsum.p);
-  PKD_TRY(kernel_status("k_scan_blocks"));
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum.p, nb);
-  PKD_TRY(kernel_status("k_scan_sums"));
-  hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nb)), dim3(kUBlock), 0, st, in, n, bsum.p, out);
-  PKD_TRY(kernel_status("k_scan_apply"));
-  return PKD_OK;
 }
 
 int fill(hipStream_t st, int32_t* a, int64_t n, int32_t v) {
@@ -579,7 +492,7 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
                        leaf_of.p, T->nodes, X, T->cap, delflag.p, Mw.p);
     PKD_TRY(kernel_status("k_match"));
   }
-  PKD_TRY(exscan(st, Mw.p, M.p, m, bsum));
+  PKD_TRY(exscan_i32(st, Mw.p, M.p, m, bsum));
   if (!insert) {
     int32_t tot = 0;
     PKD_HIP(hipMemcpyAsync(&tot, M.p + m, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -655,12 +568,12 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     if (n_regions > 0)
       hipLaunchKernelGGL(k_region_mark, dim3(n_regions), dim3(256), 0, st, regions.p, regid.p, delflag.p, 1);
     PKD_TRY(kernel_status("k_region_mark"));
-    PKD_TRY(exscan(st, delflag.p, S.p, n + 1, bsum));   // S[o] = batch points noted at ends < o
+    PKD_TRY(exscan_i32(st, delflag.p, S.p, n + 1, bsum));   // S[o] = batch points noted at ends < o
   } else {
     if (n_regions > 0)
       hipLaunchKernelGGL(k_region_mark, dim3(n_regions), dim3(256), 0, st, regions.p, regid.p, delflag.p, 0);
     PKD_TRY(kernel_status("k_region_mark"));
-    PKD_TRY(exscan(st, delflag.p, S.p, n, bsum));       // S[o] = removed points before o
+    PKD_TRY(exscan_i32(st, delflag.p, S.p, n, bsum));       // S[o] = removed points before o
   }
   if (n > 0) {
     const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (n + 255) / 256));
