@@ -127,6 +127,41 @@ int pkd_knn(const pkd_tree* tree, void* stream, const int64_t* queries, int64_t 
 int pkd_range_count(const pkd_tree* tree, void* stream, const int64_t* lo,
                     const int64_t* hi, int64_t nb, int64_t* out);
 
+/*
+ * Batched build of many independent trees in one pass of the segmented
+ * pipeline: every sieve round and the finisher run over the subproblems of all
+ * trees at once, so the number of launches does not grow with the number of
+ * trees.  coords/ids (device) hold the trees' points back to back: tree t owns
+ * positions [offsets[t], offsets[t+1]) (offsets: HOST int64 [n_trees+1],
+ * offsets[0] = 0, non-decreasing).  All trees share `params`.  The handle holds
+ * n_trees trees; each is exactly the tree pkd_build would make of its points.
+ * Batch handles answer pkd_knn_batch / pkd_range_count_batch and export one
+ * tree at a time; updates on a batch handle return PKD_ERR_UNSUPPORTED.
+ */
+int pkd_build_batch(const pkd_params* params, const pkd_tuning* tuning, void* stream,
+                    int32_t n_trees, const int64_t* coords, const int64_t* ids,
+                    const int64_t* offsets, pkd_tree** out);
+
+/* Number of trees held by a handle (1 for pkd_build). */
+int pkd_num_trees(const pkd_tree* tree, int32_t* n_trees);
+
+/*
+ * k-NN / range count over the trees of a batch handle: query j runs on tree
+ * tree_of[j] (device int32 [nq]; NULL means tree 0).  Other arguments and the
+ * output layout as for pkd_knn / pkd_range_count.
+ */
+int pkd_knn_batch(const pkd_tree* tree, void* stream, const int64_t* queries,
+                  const int32_t* tree_of, int64_t nq, int32_t k, int64_t* out_ids,
+                  int64_t* out_d2);
+int pkd_range_count_batch(const pkd_tree* tree, void* stream, const int64_t* lo,
+                          const int64_t* hi, const int32_t* tree_of, int64_t nb,
+                          int64_t* out);
+
+/* Canonical export of tree t of a handle (see pkd_export). */
+int pkd_export_tree_sizes(const pkd_tree* tree, int32_t t, int64_t* num_nodes, int64_t* n);
+int pkd_export_tree(const pkd_tree* tree, int32_t t, int64_t* rows, int64_t* leaf_ids,
+                    int64_t* leaf_coords, int32_t* depths);
+
 /* Number of points (host out). */
 int pkd_size(const pkd_tree* tree, int64_t* n);
 

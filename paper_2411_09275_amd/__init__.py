@@ -25,7 +25,8 @@ ERRORS = {
 # Every symbol the C header declares (checked by the ABI test).
 EXPORTS = ["pkd_default_params", "pkd_default_tuning", "pkd_build", "pkd_batch_insert", "pkd_batch_delete",
            "pkd_knn", "pkd_range_count", "pkd_size", "pkd_export_sizes", "pkd_export", "pkd_height",
-           "pkd_free", "pkd_strerror", "pkd_profile_enable", "pkd_profile_get"]
+           "pkd_free", "pkd_strerror", "pkd_profile_enable", "pkd_profile_get", "pkd_build_batch",
+           "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch", "pkd_export_tree_sizes", "pkd_export_tree"]
 
 
 class PkdError(RuntimeError):
@@ -69,9 +70,16 @@ def lib():
         L.pkd_free.restype = None
         L.pkd_profile_enable.argtypes = [i32]
         L.pkd_profile_get.argtypes = [i32, C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.pkd_build_batch.argtypes = [C.POINTER(_Params), C.POINTER(_Tuning), vp, i32, vp, vp, vp, C.POINTER(vp)]
+        L.pkd_num_trees.argtypes = [vp, C.POINTER(i32)]
+        L.pkd_knn_batch.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp]
+        L.pkd_range_count_batch.argtypes = [vp, vp, vp, vp, vp, i64, vp]
+        L.pkd_export_tree_sizes.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i64)]
+        L.pkd_export_tree.argtypes = [vp, i32, vp, vp, vp, vp]
         L.pkd_strerror.argtypes = [C.c_int]
         L.pkd_strerror.restype = C.c_char_p
-        for f in ("pkd_profile_enable", "pkd_profile_get", "pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
+        for f in ("pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
+                  "pkd_export_tree_sizes", "pkd_export_tree", "pkd_profile_enable", "pkd_profile_get", "pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
                   "pkd_height", "pkd_export_sizes", "pkd_export"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -109,6 +117,13 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr() if t.numel() > 0 else 0)
 
 
+def _to_i32(t):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.from_numpy(np.ascontiguousarray(t, dtype=np.int32))
+    return t.to(device="cuda", dtype=torch.int32).contiguous()
+
+
 PROFILE_KERNELS = {"sieve_count": 0, "sieve_scatter": 1, "select_skeleton": 2, "finisher": 3, "knn": 4,
                    "range_count": 5}
 
@@ -142,22 +157,48 @@ class Params:
         return p
 
 
-class Tree:
-    """A device-resident Pkd-tree (``pkd_tree*``)."""
+def _tuning(tile):
+    t = _Tuning()
+    lib().pkd_default_tuning(C.byref(t))
+    t.tile_points = tile
+    return t
 
-    def __init__(self, params: Params, coords, ids, tile: int = 2048, stream=None):
+
+class Tree:
+    """A device-resident Pkd-tree (``pkd_tree*``).  Tree(params, coords, ids)
+    builds one tree; Tree.batch(params, coords, ids, offsets) builds many trees
+    in one pass (tree t owns points offsets[t]:offsets[t+1])."""
+
+    def __init__(self, params: Params, coords, ids, tile: int = 2048, stream=None, _handle=None):
         self.p = params
+        if _handle is not None:
+            self.h = _handle
+            return
         c = _dev(coords)
         i = _dev(ids)
         n = i.shape[0]
         assert tuple(c.shape) == (params.dim, n)
-        t = _Tuning()
-        lib().pkd_default_tuning(C.byref(t))
-        t.tile_points = tile
         h = C.c_void_p()
-        _check(lib().pkd_build(C.byref(params._c()), C.byref(t), _stream(stream), _ptr(c), _ptr(i), n, C.byref(h)),
-               "pkd_build")
+        _check(lib().pkd_build(C.byref(params._c()), C.byref(_tuning(tile)), _stream(stream), _ptr(c), _ptr(i), n,
+                               C.byref(h)), "pkd_build")
         self.h = h
+
+    @classmethod
+    def batch(cls, params: Params, coords, ids, offsets, tile: int = 2048, stream=None):
+        c = _dev(coords)
+        i = _dev(ids)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        assert tuple(c.shape) == (params.dim, i.shape[0]) and off[-1] == i.shape[0]
+        h = C.c_void_p()
+        _check(lib().pkd_build_batch(C.byref(params._c()), C.byref(_tuning(tile)), _stream(stream),
+                                     off.shape[0] - 1, _ptr(c), _ptr(i), off.ctypes.data_as(C.c_void_p),
+                                     C.byref(h)), "pkd_build_batch")
+        return cls(params, None, None, _handle=h)
+
+    def num_trees(self) -> int:
+        n = C.c_int32()
+        _check(lib().pkd_num_trees(self.h, C.byref(n)), "pkd_num_trees")
+        return n.value
 
     def __del__(self):
         self.free()
@@ -177,22 +218,30 @@ class Tree:
         _check(lib().pkd_height(self.h, C.byref(h)), "pkd_height")
         return h.value
 
-    def knn(self, queries, k: int, stream=None):
-        """(ids, d2) as int64 CUDA tensors [nq, k]."""
+    def knn(self, queries, k: int, tree_of=None, stream=None, out=None):
+        """(ids, d2) as int64 CUDA tensors [nq, k]; tree_of (int32, per query)
+        picks the tree of a batch handle."""
         torch = _torch()
         q = _dev(queries)
         nq = q.shape[1] if q.dim() == 2 else 0
-        oi = torch.empty((nq, k), dtype=torch.int64, device="cuda")
-        od = torch.empty((nq, k), dtype=torch.int64, device="cuda")
-        _check(lib().pkd_knn(self.h, _stream(stream), _ptr(q), nq, k, _ptr(oi), _ptr(od)), "pkd_knn")
+        if out is None:
+            oi = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+            od = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+        else:
+            oi, od = out
+        to = None if tree_of is None else _to_i32(tree_of)
+        _check(lib().pkd_knn_batch(self.h, _stream(stream), _ptr(q), None if to is None else _ptr(to), nq, k,
+                                   _ptr(oi), _ptr(od)), "pkd_knn")
         return oi, od
 
-    def range_count(self, lo, hi, stream=None):
+    def range_count(self, lo, hi, tree_of=None, stream=None):
         torch = _torch()
         lo, hi = _dev(lo), _dev(hi)
         nb = lo.shape[1]
         out = torch.empty(nb, dtype=torch.int64, device="cuda")
-        _check(lib().pkd_range_count(self.h, _stream(stream), _ptr(lo), _ptr(hi), nb, _ptr(out)), "pkd_range_count")
+        to = None if tree_of is None else _to_i32(tree_of)
+        _check(lib().pkd_range_count_batch(self.h, _stream(stream), _ptr(lo), _ptr(hi),
+                                           None if to is None else _ptr(to), nb, _ptr(out)), "pkd_range_count")
         return out
 
     def insert(self, coords, ids, stream=None):
@@ -206,16 +255,17 @@ class Tree:
                "pkd_batch_delete")
         return n.value
 
-    def export(self):
-        """Canonical pre-order form: rows [N,4] (kind, dim, x, size), leaf ids
-        (ascending inside each leaf) and their coordinates [D, n]; numpy."""
+    def export(self, t: int = 0):
+        """Canonical pre-order form of tree t: rows [N,4] (kind, dim, x, size),
+        leaf ids (ascending inside each leaf) and their coordinates [D, n]; numpy."""
         N, n = C.c_int64(), C.c_int64()
-        _check(lib().pkd_export_sizes(self.h, C.byref(N), C.byref(n)), "pkd_export_sizes")
+        _check(lib().pkd_export_tree_sizes(self.h, t, C.byref(N), C.byref(n)), "pkd_export_sizes")
         rows = np.empty((N.value, 4), dtype=np.int64)
         ids = np.empty(n.value, dtype=np.int64)
         coords = np.empty((self.p.dim, n.value), dtype=np.int64)
         depths = np.empty(N.value, dtype=np.int32)
-        _check(lib().pkd_export(self.h, rows.ctypes.data_as(C.c_void_p), ids.ctypes.data_as(C.c_void_p),
-                                coords.ctypes.data_as(C.c_void_p), depths.ctypes.data_as(C.c_void_p)), "pkd_export")
+        _check(lib().pkd_export_tree(self.h, t, rows.ctypes.data_as(C.c_void_p), ids.ctypes.data_as(C.c_void_p),
+                                     coords.ctypes.data_as(C.c_void_p), depths.ctypes.data_as(C.c_void_p)),
+               "pkd_export")
         self.last_depths = depths
         return rows, ids, coords

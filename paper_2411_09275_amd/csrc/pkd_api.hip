@@ -9,10 +9,10 @@
 
 namespace pkd {
 
-int run_knn(const pkd_tree* T, hipStream_t st, const int64_t* q, int64_t nq, int k, int64_t* oi, int64_t* od,
-            int* flags);
-int run_range(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, int64_t nb, int64_t* out,
-              int* flags);
+int run_knn(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tree_of, int64_t nq, int k,
+            int64_t* oi, int64_t* od, int* flags);
+int run_range(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, const int32_t* tree_of,
+              int64_t nb, int64_t* out, int* flags);
 int run_insert(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m);
 int run_delete(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m, int64_t* removed);
 
@@ -272,23 +272,29 @@ int pkd_build(const pkd_params* params, const pkd_tuning* tuning, void* stream, 
   return PKD_OK;
 }
 
-int pkd_knn(const pkd_tree* tree, void* stream, const int64_t* queries, int64_t nq, int32_t k, int64_t* out_ids,
-            int64_t* out_d2) {
+int pkd_knn_batch(const pkd_tree* tree, void* stream, const int64_t* queries, const int32_t* tree_of, int64_t nq,
+                  int32_t k, int64_t* out_ids, int64_t* out_d2) {
   if (!tree || nq < 0 || k < 1 || k > 128) return PKD_ERR_INVALID_ARG;
   if (nq == 0) return PKD_OK;
   if (!queries || !out_ids || !out_d2) return PKD_ERR_INVALID_ARG;
+  if (!tree_of && tree->n_trees < 1) return PKD_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
   int* f = nullptr;
   PKD_TRY(flags_alloc(&f, st));
   Prof::begin(kProfKnn, st);
-  int rc = run_knn(tree, st, queries, nq, k, out_ids, out_d2, f);
+  int rc = run_knn(tree, st, queries, tree_of, nq, k, out_ids, out_d2, f);
   Prof::end(kProfKnn, st, 0.0);
   int rc2 = flags_check(f, st);
   return rc != PKD_OK ? rc : rc2;
 }
 
-int pkd_range_count(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi, int64_t nb,
-                    int64_t* out) {
+int pkd_knn(const pkd_tree* tree, void* stream, const int64_t* queries, int64_t nq, int32_t k, int64_t* out_ids,
+            int64_t* out_d2) {
+  return pkd_knn_batch(tree, stream, queries, nullptr, nq, k, out_ids, out_d2);
+}
+
+int pkd_range_count_batch(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi,
+                          const int32_t* tree_of, int64_t nb, int64_t* out) {
   if (!tree || nb < 0) return PKD_ERR_INVALID_ARG;
   if (nb == 0) return PKD_OK;
   if (!lo || !hi || !out) return PKD_ERR_INVALID_ARG;
@@ -296,14 +302,83 @@ int pkd_range_count(const pkd_tree* tree, void* stream, const int64_t* lo, const
   int* f = nullptr;
   PKD_TRY(flags_alloc(&f, st));
   Prof::begin(kProfRange, st);
-  int rc = run_range(tree, st, lo, hi, nb, out, f);
+  int rc = run_range(tree, st, lo, hi, tree_of, nb, out, f);
   Prof::end(kProfRange, st, 0.0);
   int rc2 = flags_check(f, st);
   return rc != PKD_OK ? rc : rc2;
 }
 
+int pkd_range_count(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi, int64_t nb,
+                    int64_t* out) {
+  return pkd_range_count_batch(tree, stream, lo, hi, nullptr, nb, out);
+}
+
+int pkd_build_batch(const pkd_params* params, const pkd_tuning* tuning, void* stream, int32_t n_trees,
+                    const int64_t* coords, const int64_t* ids, const int64_t* offsets, pkd_tree** out) {
+  if (!out) return PKD_ERR_INVALID_ARG;
+  *out = nullptr;
+  Params prm;
+  PKD_TRY(check_params(params, tuning, &prm));
+  if (n_trees < 1 || !offsets || offsets[0] != 0) return PKD_ERR_INVALID_ARG;
+  for (int32_t t = 0; t < n_trees; ++t)
+    if (offsets[t + 1] < offsets[t]) return PKD_ERR_INVALID_ARG;
+  const int64_t n = offsets[n_trees];
+  if (n > 0 && (!coords || !ids)) return PKD_ERR_INVALID_ARG;
+  if (n >= INT32_MAX || n_trees >= INT32_MAX / 2) return PKD_ERR_UNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  pkd_tree* T = new pkd_tree;
+  T->prm = prm;
+  T->n_trees = n_trees;
+  int rc = alloc_points(T, st, n);
+  if (rc == PKD_OK) rc = ensure_nodes(T, st, std::max<int64_t>(1024, n / 8 + n_trees));
+  std::vector<Task> roots;
+  if (rc == PKD_OK) {
+    // every root starts as an empty leaf; non-empty trees overwrite theirs
+    std::vector<Node> empty(n_trees);
+    for (int32_t t = 0; t < n_trees; ++t) {
+      std::memset(&empty[t], 0, sizeof(Node));
+      empty[t].left = empty[t].right = -1;
+      empty[t].dim = -1;
+      empty[t].off = static_cast<int32_t>(offsets[t]);
+      if (offsets[t + 1] > offsets[t]) {
+        Task r;
+        r.start = static_cast<int32_t>(offsets[t]);
+        r.m = static_cast<int32_t>(offsets[t + 1] - offsets[t]);
+        r.slot = t;
+        r.depth = 0;
+        r.buf = 2;
+        r.mode = 0;
+        roots.push_back(r);
+      }
+    }
+    int e = hipMemcpyAsync(T->nodes, empty.data(), sizeof(Node) * n_trees, hipMemcpyHostToDevice, st) == hipSuccess
+                ? PKD_OK : PKD_ERR_HIP;
+    if (e == PKD_OK) e = hipStreamSynchronize(st) == hipSuccess ? PKD_OK : PKD_ERR_HIP;
+    rc = e;
+    T->node_count = n_trees;
+    T->height = 0;
+  }
+  if (rc == PKD_OK && !roots.empty()) rc = build_tasks(T, st, roots, coords, ids, n);
+  if (rc != PKD_OK) {
+    release(T, st);
+    (void)hipStreamSynchronize(st);
+    delete T;
+    return rc;
+  }
+  T->n = n;
+  *out = T;
+  return PKD_OK;
+}
+
+int pkd_num_trees(const pkd_tree* tree, int32_t* n_trees) {
+  if (!tree || !n_trees) return PKD_ERR_INVALID_ARG;
+  *n_trees = tree->n_trees;
+  return PKD_OK;
+}
+
 int pkd_batch_insert(pkd_tree* tree, void* stream, const int64_t* coords, const int64_t* ids, int64_t m) {
   if (!tree || m < 0) return PKD_ERR_INVALID_ARG;
+  if (tree->n_trees != 1) return PKD_ERR_UNSUPPORTED;
   if (m == 0) return PKD_OK;
   if (!coords || !ids) return PKD_ERR_INVALID_ARG;
   if (tree->n + m >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
@@ -314,6 +389,7 @@ int pkd_batch_delete(pkd_tree* tree, void* stream, const int64_t* coords, const 
                      int64_t* n_deleted) {
   if (n_deleted) *n_deleted = 0;
   if (!tree || m < 0) return PKD_ERR_INVALID_ARG;
+  if (tree->n_trees != 1) return PKD_ERR_UNSUPPORTED;
   if (m == 0) return PKD_OK;
   if (!coords || !ids) return PKD_ERR_INVALID_ARG;
   if (m >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
@@ -349,10 +425,10 @@ int copy_host(const pkd_tree* T, std::vector<Node>& nodes, std::vector<int64_t>&
   return PKD_OK;
 }
 
-// Pre-order walk from the root; returns the node count or -1 when the stored
-// links do not form a tree over [0, n).
-int64_t walk(const pkd_tree* T, const std::vector<Node>& nodes, std::vector<int32_t>* order) {
-  std::vector<int32_t> stack{0};
+// Pre-order walk from a root; returns the node count or -1 when the stored
+// links do not form a tree.
+int64_t walk(const std::vector<Node>& nodes, int32_t root, std::vector<int32_t>* order) {
+  std::vector<int32_t> stack{root};
   int64_t count = 0;
   while (!stack.empty()) {
     int32_t t = stack.back();
@@ -365,32 +441,37 @@ int64_t walk(const pkd_tree* T, const std::vector<Node>& nodes, std::vector<int3
       stack.push_back(nodes[t].left);
     }
   }
-  (void)T;
   return count;
 }
 }  // namespace
 
-int pkd_export_sizes(const pkd_tree* tree, int64_t* num_nodes, int64_t* n) {
-  if (!tree || !num_nodes || !n) return PKD_ERR_INVALID_ARG;
+int pkd_export_tree_sizes(const pkd_tree* tree, int32_t t, int64_t* num_nodes, int64_t* n) {
+  if (!tree || !num_nodes || !n || t < 0 || t >= tree->n_trees) return PKD_ERR_INVALID_ARG;
   std::vector<Node> nodes(tree->node_count);
   PKD_HIP(hipDeviceSynchronize());
   PKD_HIP(hipMemcpy(nodes.data(), tree->nodes, sizeof(Node) * tree->node_count, hipMemcpyDeviceToHost));
-  int64_t c = walk(tree, nodes, nullptr);
+  int64_t c = walk(nodes, t, nullptr);
   if (c < 0) return PKD_ERR_INTERNAL;
   *num_nodes = c;
-  *n = tree->n;
+  *n = nodes[t].size;
   return PKD_OK;
 }
 
-int pkd_export(const pkd_tree* tree, int64_t* rows, int64_t* leaf_ids, int64_t* leaf_coords, int32_t* depths) {
-  if (!tree) return PKD_ERR_INVALID_ARG;
+int pkd_export_sizes(const pkd_tree* tree, int64_t* num_nodes, int64_t* n) {
+  return pkd_export_tree_sizes(tree, 0, num_nodes, n);
+}
+
+int pkd_export_tree(const pkd_tree* tree, int32_t t, int64_t* rows, int64_t* leaf_ids, int64_t* leaf_coords,
+                    int32_t* depths) {
+  if (!tree || t < 0 || t >= tree->n_trees) return PKD_ERR_INVALID_ARG;
   std::vector<Node> nodes;
   std::vector<int64_t> pts;
   PKD_TRY(copy_host(tree, nodes, pts));
   std::vector<int32_t> order;
-  if (walk(tree, nodes, &order) < 0) return PKD_ERR_INTERNAL;
+  if (walk(nodes, t, &order) < 0) return PKD_ERR_INTERNAL;
   const int D = tree->prm.D;
-  const int64_t n = tree->n;
+  const int64_t N = tree->n;          // points of all trees (host copy layout)
+  const int64_t n = nodes[t].size;    // points of tree t
   int64_t at = 0;
   std::vector<int64_t> idx;
   for (size_t r = 0; r < order.size(); ++r) {
@@ -404,19 +485,23 @@ int pkd_export(const pkd_tree* tree, int64_t* rows, int64_t* leaf_ids, int64_t* 
     }
     if (depths) depths[r] = nd.depth;
     if (!leaf) continue;
-    if (nd.off < 0 || static_cast<int64_t>(nd.off) + nd.size > n || at + nd.size > n) return PKD_ERR_INTERNAL;
+    if (nd.off < 0 || static_cast<int64_t>(nd.off) + nd.size > N || at + nd.size > n) return PKD_ERR_INTERNAL;
     idx.resize(nd.size);
     for (int32_t i = 0; i < nd.size; ++i) idx[i] = nd.off + i;
-    const int64_t* id = pts.data() + static_cast<size_t>(D) * n;
+    const int64_t* id = pts.data() + static_cast<size_t>(D) * N;
     std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return id[a] < id[b]; });
     for (int32_t i = 0; i < nd.size; ++i) {
       if (leaf_ids) leaf_ids[at + i] = id[idx[i]];
       if (leaf_coords)
-        for (int d = 0; d < D; ++d) leaf_coords[static_cast<int64_t>(d) * n + at + i] = pts[static_cast<size_t>(d) * n + idx[i]];
+        for (int d = 0; d < D; ++d) leaf_coords[static_cast<int64_t>(d) * n + at + i] = pts[static_cast<size_t>(d) * N + idx[i]];
     }
     at += nd.size;
   }
   return at == n ? PKD_OK : PKD_ERR_INTERNAL;
+}
+
+int pkd_export(const pkd_tree* tree, int64_t* rows, int64_t* leaf_ids, int64_t* leaf_coords, int32_t* depths) {
+  return pkd_export_tree(tree, 0, rows, leaf_ids, leaf_coords, depths);
 }
 
 int pkd_profile_enable(int32_t on) {

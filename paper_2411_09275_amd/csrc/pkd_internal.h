@@ -93,7 +93,8 @@ struct pkd_tree {
   pkd::Node* nodes = nullptr;
   int64_t node_cap = 0;
   int32_t node_count = 0; // nodes allocated (node 0 is the root)
-  int32_t height = 0;      // longest root-leaf path (edges)
+  int32_t height = 0;      // longest root-leaf path (edges), an upper bound after updates
+  int32_t n_trees = 1;     // trees held: their roots are nodes 0 .. n_trees-1
 };
 
 // ---- host helpers shared by the sources (defined in pkd_api.hip) -----------

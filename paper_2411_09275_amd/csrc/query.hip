@@ -28,7 +28,8 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
                                                  int64_t cap, const int64_t* __restrict__ ids,
                                                  const int64_t* __restrict__ Qry, int64_t nq, int k,
                                                  int64_t* __restrict__ out_ids, int64_t* __restrict__ out_d2,
-                                                 int* flags, int empty, int32_t n_nodes, int64_t n_pts) {
+                                                 int* flags, const int32_t* tree_of, int32_t n_trees,
+                                                 int32_t n_nodes, int64_t n_pts) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
   if (j >= nq) return;
   int64_t q[D];
@@ -55,16 +56,20 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
     int32_t off[D];
     int64_t lb;
   };
-  Ent stk[SD];
-  int sp = 0;
-  if (!empty) {
-    stk[0].node = 0;
-    stk[0].depth = 0;
-    stk[0].lb = 0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) stk[0].off[d] = 0;
-    sp = 1;
+  // the trees of a handle have their roots at nodes 0 .. n_trees-1; an empty
+  // tree's root is a leaf of size 0
+  const int32_t root = tree_of ? tree_of[j] : 0;
+  if (static_cast<uint32_t>(root) >= static_cast<uint32_t>(n_trees)) {
+    atomicOr(flags, kErrInternal);
+    return;
   }
+  Ent stk[SD];
+  stk[0].node = root;
+  stk[0].depth = 0;
+  stk[0].lb = 0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) stk[0].off[d] = 0;
+  int sp = 1;
   while (sp > 0) {
     --sp;
     int32_t node = stk[sp].node;
@@ -161,12 +166,12 @@ template <int D, int SD>
 __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ nodes, const int64_t* __restrict__ X,
                                                    int64_t cap, const int64_t* __restrict__ Lo,
                                                    const int64_t* __restrict__ Hi, int64_t nb, int64_t* out,
-                                                   int* flags, int empty, int phi, int32_t n_nodes,
-                                                   int64_t n_pts) {
+                                                   int* flags, const int32_t* tree_of, int32_t n_trees, int phi,
+                                                   int32_t n_nodes, int64_t n_pts) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
   if (j >= nb) return;
   int64_t lo[D], hi[D];
-  bool bad = false, none = empty != 0;
+  bool bad = false, none = false;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     lo[d] = Lo[d * nb + j];
@@ -187,8 +192,13 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
   };
   Ent stk[SD];
   int sp = 0;
+  const int32_t root = tree_of ? tree_of[j] : 0;
+  if (static_cast<uint32_t>(root) >= static_cast<uint32_t>(n_trees)) {
+    atomicOr(flags, kErrInternal);
+    return;
+  }
   if (!none) {
-    stk[0].node = 0;
+    stk[0].node = root;
     stk[0].depth = 0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -264,11 +274,11 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
 template <int D, int SD>
 void launch_knn(int km, dim3 g, hipStream_t st, const Node* nodes, const int64_t* X, int64_t cap,
                 const int64_t* ids, const int64_t* q, int64_t nq, int k, int64_t* oi, int64_t* od, int* flags,
-                int empty, int32_t n_nodes, int64_t n_pts) {
+                const int32_t* tree_of, int32_t n_trees, int32_t n_nodes, int64_t n_pts) {
 #define PKD_KNN_CASE(KM) \
   case KM:               \
     hipLaunchKernelGGL((k_knn<D, KM, SD>), g, dim3(kQBlock), 0, st, nodes, X, cap, ids, q, nq, k, oi, od, flags, \
-                       empty, n_nodes, n_pts); \
+                       tree_of, n_trees, n_nodes, n_pts); \
     break;
   switch (km) {
     PKD_KNN_CASE(1)
@@ -284,20 +294,22 @@ void launch_knn(int km, dim3 g, hipStream_t st, const Node* nodes, const int64_t
 }
 
 template <int D>
-int knn_d(const pkd_tree* T, hipStream_t st, const int64_t* q, int64_t nq, int k, int64_t* oi, int64_t* od,
-          int* flags) {
+int knn_d(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tree_of, int64_t nq, int k,
+          int64_t* oi, int64_t* od, int* flags) {
   int km = 1;
   while (km < k) km <<= 1;
   const dim3 g(static_cast<unsigned>((nq + kQBlock - 1) / kQBlock));
   const int64_t* X = T->buf[T->cur];
   const int64_t* ids = X + static_cast<int64_t>(D) * T->cap;
-  const int empty = T->n == 0 ? 1 : 0;
   if (T->height + 2 <= 48)
-    launch_knn<D, 48>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, empty, T->node_count, T->n);
+    launch_knn<D, 48>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
+                      T->node_count, T->n);
   else if (T->height + 2 <= 96)
-    launch_knn<D, 96>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, empty, T->node_count, T->n);
+    launch_knn<D, 96>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
+                      T->node_count, T->n);
   else if (T->height + 2 <= kMaxStack)
-    launch_knn<D, kMaxStack>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, empty, T->node_count, T->n);
+    launch_knn<D, kMaxStack>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
+                             T->node_count, T->n);
   else
     return PKD_ERR_CAPACITY;
   hipError_t e = hipGetLastError();
@@ -306,17 +318,16 @@ int knn_d(const pkd_tree* T, hipStream_t st, const int64_t* q, int64_t nq, int k
 }
 
 template <int D>
-int range_d(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, int64_t nb, int64_t* out,
-            int* flags) {
+int range_d(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, const int32_t* tree_of,
+            int64_t nb, int64_t* out, int* flags) {
   const dim3 g(static_cast<unsigned>((nb + kQBlock - 1) / kQBlock));
   const int64_t* X = T->buf[T->cur];
-  const int empty = T->n == 0 ? 1 : 0;
   if (T->height + 3 <= 48)
-    hipLaunchKernelGGL((k_range<D, 48>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags, empty,
-                       T->prm.phi, T->node_count, T->n);
+    hipLaunchKernelGGL((k_range<D, 48>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags, tree_of,
+                       T->n_trees, T->prm.phi, T->node_count, T->n);
   else if (T->height + 3 <= kMaxStack)
     hipLaunchKernelGGL((k_range<D, kMaxStack>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags,
-                       empty, T->prm.phi, T->node_count, T->n);
+                       tree_of, T->n_trees, T->prm.phi, T->node_count, T->n);
   else
     return PKD_ERR_CAPACITY;
   hipError_t e = hipGetLastError();
@@ -326,30 +337,30 @@ int range_d(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t*
 
 }  // namespace
 
-int run_knn(const pkd_tree* T, hipStream_t st, const int64_t* q, int64_t nq, int k, int64_t* oi, int64_t* od,
-            int* flags) {
+int run_knn(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tree_of, int64_t nq, int k,
+            int64_t* oi, int64_t* od, int* flags) {
   switch (T->prm.D) {
-    case 1: return knn_d<1>(T, st, q, nq, k, oi, od, flags);
-    case 2: return knn_d<2>(T, st, q, nq, k, oi, od, flags);
-    case 3: return knn_d<3>(T, st, q, nq, k, oi, od, flags);
-    case 4: return knn_d<4>(T, st, q, nq, k, oi, od, flags);
-    case 5: return knn_d<5>(T, st, q, nq, k, oi, od, flags);
-    case 6: return knn_d<6>(T, st, q, nq, k, oi, od, flags);
-    case 7: return knn_d<7>(T, st, q, nq, k, oi, od, flags);
+    case 1: return knn_d<1>(T, st, q, tree_of, nq, k, oi, od, flags);
+    case 2: return knn_d<2>(T, st, q, tree_of, nq, k, oi, od, flags);
+    case 3: return knn_d<3>(T, st, q, tree_of, nq, k, oi, od, flags);
+    case 4: return knn_d<4>(T, st, q, tree_of, nq, k, oi, od, flags);
+    case 5: return knn_d<5>(T, st, q, tree_of, nq, k, oi, od, flags);
+    case 6: return knn_d<6>(T, st, q, tree_of, nq, k, oi, od, flags);
+    case 7: return knn_d<7>(T, st, q, tree_of, nq, k, oi, od, flags);
   }
   return PKD_ERR_UNSUPPORTED;
 }
 
-int run_range(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, int64_t nb, int64_t* out,
-              int* flags) {
+int run_range(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, const int32_t* tree_of,
+              int64_t nb, int64_t* out, int* flags) {
   switch (T->prm.D) {
-    case 1: return range_d<1>(T, st, lo, hi, nb, out, flags);
-    case 2: return range_d<2>(T, st, lo, hi, nb, out, flags);
-    case 3: return range_d<3>(T, st, lo, hi, nb, out, flags);
-    case 4: return range_d<4>(T, st, lo, hi, nb, out, flags);
-    case 5: return range_d<5>(T, st, lo, hi, nb, out, flags);
-    case 6: return range_d<6>(T, st, lo, hi, nb, out, flags);
-    case 7: return range_d<7>(T, st, lo, hi, nb, out, flags);
+    case 1: return range_d<1>(T, st, lo, hi, tree_of, nb, out, flags);
+    case 2: return range_d<2>(T, st, lo, hi, tree_of, nb, out, flags);
+    case 3: return range_d<3>(T, st, lo, hi, tree_of, nb, out, flags);
+    case 4: return range_d<4>(T, st, lo, hi, tree_of, nb, out, flags);
+    case 5: return range_d<5>(T, st, lo, hi, tree_of, nb, out, flags);
+    case 6: return range_d<6>(T, st, lo, hi, tree_of, nb, out, flags);
+    case 7: return range_d<7>(T, st, lo, hi, tree_of, nb, out, flags);
   }
   return PKD_ERR_UNSUPPORTED;
 }

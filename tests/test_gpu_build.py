@@ -185,3 +185,43 @@ def test_queries_reject_out_of_range(pk):
     lo[1, 2] = -5
     with pytest.raises(pk.PkdError):
         t.range_count(lo, hi)
+
+
+# --------------------------------------------------------------------- batching
+def test_batch_build_equals_single_builds(orc, pk):
+    rng = np.random.default_rng(200)
+    sizes = synth.log_uniform_sizes(60, 1, 3e5, seed=201)
+    sizes[3] = 0                                   # an empty tree
+    offsets = np.concatenate([[0], np.cumsum(sizes)])
+    c, i = synth.uniform_points(int(offsets[-1]), 3, seed=202)
+    B = pk.Tree.batch(pk.Params(3), c, i, offsets)
+    assert B.num_trees() == 60
+    for t in range(60):
+        a, b = offsets[t], offsets[t + 1]
+        ot = orc.Tree(orc.Params(3), np.ascontiguousarray(c[:, a:b]), i[a:b])
+        g = B.export(t)
+        o = ot.export()
+        for x, y in zip(g, o):
+            assert np.array_equal(x, y), t
+    # queries routed to their trees
+    nq = 2000
+    q = synth.uniform_queries(nq, 3, seed=203)
+    tree_of = rng.integers(0, 60, size=nq).astype(np.int32)
+    for k in (1, 10, 100):
+        gi, gd = B.knn(q, k, tree_of=tree_of)
+        gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+        for t in range(0, 60, 7):
+            sel = np.nonzero(tree_of == t)[0]
+            a, b = offsets[t], offsets[t + 1]
+            bi, bd = orc.brute_knn(np.ascontiguousarray(c[:, a:b]), i[a:b], np.ascontiguousarray(q[:, sel]), k)
+            assert np.array_equal(gi[sel], bi) and np.array_equal(gd[sel], bd), (t, k)
+    lo, hi = synth.log_uniform_boxes(nq, 3, seed=204)
+    got = B.range_count(lo, hi, tree_of=tree_of).cpu().numpy()
+    for t in range(0, 60, 5):
+        sel = np.nonzero(tree_of == t)[0]
+        a, b = offsets[t], offsets[t + 1]
+        ref = orc.brute_range_count(np.ascontiguousarray(c[:, a:b]), np.ascontiguousarray(lo[:, sel]),
+                                    np.ascontiguousarray(hi[:, sel]))
+        assert np.array_equal(got[sel], ref), t
+    with pytest.raises(pk.PkdError):
+        B.insert(c[:, :5].copy(), i[:5] + 10 ** 9)
