@@ -42,6 +42,14 @@ def parse():
     ap.add_argument("--tile", type=int, default=2048)
     ap.add_argument("--cpu-sample", type=int, default=4_000_000, help="points of the oracle's build sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="build", choices=["build", "batching", "serving"],
+                    help="build: the headline (1e8 3-D build + queries); batching: 4096 trees in one pass")
+    ap.add_argument("--serve-n", type=int, default=1_000_000_000, help="points of the resident serving tree")
+    ap.add_argument("--requests", type=int, default=100, help="requests in the serving stream")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="offered Poisson rate as a fraction of the serial handler's capacity")
+    ap.add_argument("--trees", type=int, default=4096)
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 2 GiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -91,12 +99,229 @@ def cpu_baseline(coords, ids, q, lo, hi, sample_n, dim):
     }
 
 
+def bench_batching(a):
+    """Many independent trees (sizes log-uniform in [1e3, 1e6], D from {2, 3},
+    uniform int64 points) built by one batched pass per dimension, then 256
+    k-NN queries per tree with k from {1, 10, 100}; compared with one build
+    and one query call per tree, with identical results required."""
+    import torch
+
+    import paper_2411_09275_amd as pk
+    from paper_2411_09275_amd import autotune
+    import synth
+
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    T = a.trees
+    sizes = synth.log_uniform_sizes(T, 1e3, 1e6, seed=10)
+    rng = np.random.Generator(np.random.PCG64(12))
+    dims = rng.choice([2, 3], size=T)
+    ks = rng.choice([1, 10, 100], size=(T, 256))
+    g = torch.Generator(device=dev)
+    groups = {}
+    for D in (2, 3):
+        sel = np.nonzero(dims == D)[0]
+        off = np.concatenate([[0], np.cumsum(sizes[sel])]).astype(np.int64)
+        g.manual_seed(11 + D)
+        c = torch.randint(0, 10 ** 9, (D, int(off[-1])), generator=g, device=dev, dtype=torch.int64)
+        i = torch.arange(int(off[-1]), device=dev, dtype=torch.int64)
+        q = torch.randint(0, 10 ** 9, (D, sel.shape[0] * 256), generator=g, device=dev, dtype=torch.int64)
+        tree_of = np.repeat(np.arange(sel.shape[0]), 256).astype(np.int32)
+        kq = ks[sel].reshape(-1)
+        byk = {}
+        for k in (1, 10, 100):
+            idx = np.nonzero(kq == k)[0]
+            byk[k] = (torch.from_numpy(idx).to(dev), q[:, torch.from_numpy(idx).to(dev)].contiguous(),
+                      torch.from_numpy(tree_of[idx]).to(dev))
+        groups[D] = dict(sel=sel, off=off, c=c, i=i, byk=byk)
+    torch.cuda.synchronize()
+    n_total = int(sizes.sum())
+    log("batching workload: %d trees, %d points" % (T, n_total))
+
+    params = {}
+    for D, gr in groups.items():
+        if a.no_autotune:
+            params[D] = (pk.Params(D), 2048)
+            continue
+        # tune on the first 128 trees of the group
+        nt = min(128, gr["sel"].shape[0])
+        o = gr["off"][: nt + 1]
+        cs = gr["c"][:, : int(o[-1])].contiguous()
+        is_ = gr["i"][: int(o[-1])].contiguous()
+        qs = gr["byk"][10][1][:, : nt * 80].contiguous()
+        p, tile, sec = autotune.tune(D, cs, is_, offsets=o, queries=qs, k=10, log=log)
+        params[D] = (p, tile)
+        log("autotuned D=%d: lambda=%d sigma=%d phi=%d tile=%d" % (D, p.lam, p.sigma, p.phi, tile))
+
+    def batched():
+        res = {}
+        for D, gr in groups.items():
+            p, tile = params[D]
+            t = pk.Tree.batch(p, gr["c"], gr["i"], gr["off"], tile=tile)
+            for k, (idx, qk, tk) in gr["byk"].items():
+                res[(D, k)] = t.knn(qk, k, tree_of=tk)
+            t.free()
+        return res
+
+    for w in range(a.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        res = batched()
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / a.steps
+    log("batched: %.1f ms per pass" % (t_batched * 1e3))
+
+    # one build and one query call per tree (same parameters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    same = True
+    for D, gr in groups.items():
+        p, tile = params[D]
+        off = gr["off"]
+        for j in range(gr["sel"].shape[0]):
+            a0, a1 = int(off[j]), int(off[j + 1])
+            t = pk.Tree(p, gr["c"][:, a0:a1].contiguous(), gr["i"][a0:a1], tile=tile)
+            for k, (idx, qk, tk) in gr["byk"].items():
+                mine = torch.nonzero(tk == j).flatten()
+                if mine.numel() == 0:
+                    continue
+                oi, od = t.knn(qk[:, mine].contiguous(), k)
+                bi, bd = res[(D, k)]
+                same &= bool(torch.equal(oi, bi[mine]) and torch.equal(od, bd[mine]))
+            t.free()
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    log("one call per tree: %.1f ms; identical results: %s" % (t_single * 1e3, same))
+    nq = T * 256
+    out = {
+        "metric": "batched build + k-NN over many trees: Mpts/s (vs one launch per tree)",
+        "value": round(n_total / t_batched / 1e6, 2),
+        "unit": "Mpts/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(t_batched * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "%d trees, sizes log-uniform [1e3,1e6], D in {2,3}, uniform int64 in [0,1e9); "
+                               "256 k-NN queries per tree, k in {1,10,100}" % T, "points": n_total, "queries": nq,
+                   "params": {str(D): {"lambda": p.lam, "sigma": p.sigma, "phi": p.phi, "tile": tile}
+                              for D, (p, tile) in params.items()}},
+        "batched_ms": round(t_batched * 1e3, 3),
+        "one_call_per_tree_ms": round(t_single * 1e3, 3),
+        "speedup_vs_one_call_per_tree": round(t_single / t_batched, 2),
+        "identical_results": same,
+    }
+    print(json.dumps(out))
+
+
+def bench_serving(a):
+    """A resident tree of 1e9 hashed-uniform 2-D points answers a Poisson stream
+    of BatchInsert / BatchDelete / k-NN requests (1:1:8; update sizes
+    log-uniform in [1e3, 1e7], query batches in [1e2, 1e6], k in {1, 10, 100}).
+    Four passes over the same stream, each on a freshly built tree: serial and
+    continuous with every request waiting at time 0 (throughput), then serial
+    and continuous with Poisson arrivals at `load` x the serial capacity
+    (p50 / p99 latency).  Every pass must give identical results."""
+    import torch
+    import xxhash
+
+    import paper_2411_09275_amd as pk
+    from paper_2411_09275_amd.serve import Request, Server, latency_stats
+    import synth
+
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    D, n0, point_seed = 2, a.serve_n, 21
+    t0 = time.perf_counter()
+    raw = synth.request_stream(D, a.requests, seed=22, rate_hz=1.0, n_initial=n0, point_seed=point_seed)
+    kinds = [r["kind"] for r in raw]
+    log("stream: %d requests (%d insert, %d delete, %d k-NN) generated in %.1f s" % (
+        len(raw), kinds.count("insert"), kinds.count("delete"), kinds.count("knn"), time.perf_counter() - t0))
+
+    build_s = []
+
+    def fresh():
+        ids = torch.arange(n0, device=dev, dtype=torch.int64)
+        c = synth.hashed_points_torch(ids, D, point_seed)
+        torch.cuda.synchronize()
+        s = time.perf_counter()
+        t = pk.Tree(pk.Params(D), c, ids)
+        build_s.append(time.perf_counter() - s)
+        del c, ids
+        torch.cuda.empty_cache()
+        return t
+
+    def one_pass(mode, realtime, rate):
+        reqs = [Request.from_dict(dict(r, arrival=r["arrival"] / rate)) for r in raw]
+        tree = fresh()
+        srv = Server(tree, D)
+        log("pass %s realtime=%s rate=%.2f/s" % (mode, realtime, rate))
+        span = srv.run(reqs, mode=mode, realtime=realtime)
+        digest = []
+        for r in reqs:
+            if r.kind == "knn":
+                h = xxhash.xxh3_64()
+                h.update(np.ascontiguousarray(r.result[0]).data)
+                h.update(np.ascontiguousarray(r.result[1]).data)
+                digest.append(h.intdigest())
+                r.result = None
+            elif r.kind == "delete":
+                digest.append(int(r.result))
+        size = tree.size()
+        tree.free()
+        digest.append(size)
+        lat = latency_stats(reqs)
+        log("  makespan %.3f s, p50 %.2f ms, p99 %.2f ms, %d batches / %d launches" % (
+            span, lat["p50_ms"], lat["p99_ms"], srv.batches, srv.launches))
+        return span, lat, digest, srv.batches
+
+    for _ in range(a.warmup):
+        one_pass("continuous", False, 1.0)
+    span_sc, _, dig_sc, _ = one_pass("serial", False, 1.0)
+    span_cc, lat_cc, dig_cc, nb_cc = one_pass("continuous", False, 1.0)
+    rate = a.load * len(raw) / span_sc
+    span_sr, lat_sr, dig_sr, _ = one_pass("serial", True, rate)
+    span_cr, lat_cr, dig_cr, nb_cr = one_pass("continuous", True, rate)
+    same = dig_sc == dig_cc == dig_sr == dig_cr
+    n_upd = sum(r["coords"].shape[1] for r in raw if r["kind"] != "knn")
+    n_q = sum(r["coords"].shape[1] for r in raw if r["kind"] == "knn")
+    out = {
+        "metric": "serving throughput, continuous batching: requests/s (1:1:8 insert/delete/k-NN mix)",
+        "value": round(len(raw) / span_cc, 2),
+        "unit": "req/s",
+        "n_gpus": 1, "steps": 1, "warmup": a.warmup,
+        "ms_per_step": round(span_cc * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "resident tree of %.0e 2-D points (hashed uniform int64 in [0,1e9)); %d Poisson "
+                               "requests insert:delete:k-NN 1:1:8, updates log-uniform [1e3,1e7], queries "
+                               "log-uniform [1e2,1e6], k in {1,10,100}" % (n0, len(raw)),
+                   "update_points": n_upd, "queries": n_q},
+        "build_1e9_ms": round(min(build_s) * 1e3, 1),
+        "closed": {"serial_s": round(span_sc, 4), "continuous_s": round(span_cc, 4),
+                   "speedup": round(span_sc / span_cc, 3), "continuous_batches": nb_cc,
+                   "items_per_s": round((n_upd + n_q) / span_cc, 1)},
+        "open": {"rate_per_s": round(rate, 3), "load_vs_serial_capacity": a.load,
+                 "serial": lat_sr, "continuous": lat_cr, "continuous_batches": nb_cr,
+                 "serial_makespan_s": round(span_sr, 4), "continuous_makespan_s": round(span_cr, 4)},
+        "identical_results": same,
+    }
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.workload == "batching":
+        bench_batching(a)
+        return
+    if a.workload == "serving":
+        bench_serving(a)
+        return
     import torch
 
     import paper_2411_09275_amd as pk

@@ -157,6 +157,22 @@ int pkd_range_count_batch(const pkd_tree* tree, void* stream, const int64_t* lo,
                           const int64_t* hi, const int32_t* tree_of, int64_t nb,
                           int64_t* out);
 
+/*
+ * Asynchronous forms of pkd_knn_batch / pkd_range_count_batch for callers that
+ * overlap work (a serving loop): the kernel is enqueued on `stream` and the
+ * call returns without synchronizing.  Data-dependent errors are ORed into
+ * *status (device int32, zeroed by the caller beforehand) instead of being
+ * returned: 1 = a coordinate outside [0, 2^30), 16 = traversal stack too
+ * small, 32 = inconsistent tree or tree index.  Outputs and *status are valid
+ * once the stream reaches this point.  The tree must not be modified until then.
+ */
+int pkd_knn_async(const pkd_tree* tree, void* stream, const int64_t* queries,
+                  const int32_t* tree_of, int64_t nq, int32_t k, int64_t* out_ids,
+                  int64_t* out_d2, int32_t* status);
+int pkd_range_count_async(const pkd_tree* tree, void* stream, const int64_t* lo,
+                          const int64_t* hi, const int32_t* tree_of, int64_t nb,
+                          int64_t* out, int32_t* status);
+
 /* Canonical export of tree t of a handle (see pkd_export). */
 int pkd_export_tree_sizes(const pkd_tree* tree, int32_t t, int64_t* num_nodes, int64_t* n);
 int pkd_export_tree(const pkd_tree* tree, int32_t t, int64_t* rows, int64_t* leaf_ids,

@@ -26,7 +26,8 @@ ERRORS = {
 EXPORTS = ["pkd_default_params", "pkd_default_tuning", "pkd_build", "pkd_batch_insert", "pkd_batch_delete",
            "pkd_knn", "pkd_range_count", "pkd_size", "pkd_export_sizes", "pkd_export", "pkd_height",
            "pkd_free", "pkd_strerror", "pkd_profile_enable", "pkd_profile_get", "pkd_build_batch",
-           "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch", "pkd_export_tree_sizes", "pkd_export_tree"]
+           "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch", "pkd_export_tree_sizes", "pkd_export_tree",
+           "pkd_knn_async", "pkd_range_count_async"]
 
 
 class PkdError(RuntimeError):
@@ -76,9 +77,11 @@ def lib():
         L.pkd_range_count_batch.argtypes = [vp, vp, vp, vp, vp, i64, vp]
         L.pkd_export_tree_sizes.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i64)]
         L.pkd_export_tree.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.pkd_knn_async.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp]
+        L.pkd_range_count_async.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.pkd_strerror.argtypes = [C.c_int]
         L.pkd_strerror.restype = C.c_char_p
-        for f in ("pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
+        for f in ("pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
                   "pkd_export_tree_sizes", "pkd_export_tree", "pkd_profile_enable", "pkd_profile_get", "pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
                   "pkd_height", "pkd_export_sizes", "pkd_export"):
             getattr(L, f).restype = C.c_int
@@ -233,6 +236,15 @@ class Tree:
         _check(lib().pkd_knn_batch(self.h, _stream(stream), _ptr(q), None if to is None else _ptr(to), nq, k,
                                    _ptr(oi), _ptr(od)), "pkd_knn")
         return oi, od
+
+    def knn_async(self, queries, k: int, out_ids, out_d2, status, tree_of=None, stream=None):
+        """Enqueue k-NN on `stream` without waiting; errors are ORed into the
+        device int32 tensor `status` (zero it first)."""
+        q = _dev(queries)
+        nq = q.shape[1] if q.dim() == 2 else 0
+        to = None if tree_of is None else _to_i32(tree_of)
+        _check(lib().pkd_knn_async(self.h, _stream(stream), _ptr(q), None if to is None else _ptr(to), nq, k,
+                                   _ptr(out_ids), _ptr(out_d2), _ptr(status)), "pkd_knn_async")
 
     def range_count(self, lo, hi, tree_of=None, stream=None):
         torch = _torch()

@@ -288,6 +288,30 @@ int pkd_knn_batch(const pkd_tree* tree, void* stream, const int64_t* queries, co
   return rc != PKD_OK ? rc : rc2;
 }
 
+int pkd_knn_async(const pkd_tree* tree, void* stream, const int64_t* queries, const int32_t* tree_of, int64_t nq,
+                  int32_t k, int64_t* out_ids, int64_t* out_d2, int32_t* status) {
+  if (!tree || nq < 0 || k < 1 || k > 128 || !status) return PKD_ERR_INVALID_ARG;
+  if (nq == 0) return PKD_OK;
+  if (!queries || !out_ids || !out_d2) return PKD_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Prof::begin(kProfKnn, st);
+  int rc = run_knn(tree, st, queries, tree_of, nq, k, out_ids, out_d2, reinterpret_cast<int*>(status));
+  Prof::end(kProfKnn, st, 0.0);
+  return rc;
+}
+
+int pkd_range_count_async(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi,
+                          const int32_t* tree_of, int64_t nb, int64_t* out, int32_t* status) {
+  if (!tree || nb < 0 || !status) return PKD_ERR_INVALID_ARG;
+  if (nb == 0) return PKD_OK;
+  if (!lo || !hi || !out) return PKD_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Prof::begin(kProfRange, st);
+  int rc = run_range(tree, st, lo, hi, tree_of, nb, out, reinterpret_cast<int*>(status));
+  Prof::end(kProfRange, st, 0.0);
+  return rc;
+}
+
 int pkd_knn(const pkd_tree* tree, void* stream, const int64_t* queries, int64_t nq, int32_t k, int64_t* out_ids,
             int64_t* out_d2) {
   return pkd_knn_batch(tree, stream, queries, nullptr, nq, k, out_ids, out_d2);

@@ -1,0 +1,252 @@
+"""Serving loop: one resident tree answers a stream of BatchInsert, BatchDelete
+and k-NN requests with continuous batching.
+
+Semantics: serializable by arrival order.  A k-NN request sees exactly the
+updates that arrived before it, and updates apply in arrival order, so every
+result equals the one obtained when the requests are handled one at a time.
+
+Continuous batching: whenever the device can take more work, the server takes
+the longest run of waiting k-NN requests in front of the next update that fits
+the admission limits, merges it into one launch per distinct k and enqueues it
+without waiting (pkd_knn_async, errors land in a per-batch device status word).
+Admission: at most `max_inflight` batches in flight, at most
+`max_batch_queries` queries per batch, and the query, id and distance buffers
+of the batches in flight within the byte budget (free HBM less a reserve, or
+the caller's `budget_bytes` if smaller).  A request larger than the budget on
+its own runs alone once nothing else is in flight.
+
+Streams: queries go up on an upload stream, the kernels run on the compute
+stream, results come down on a download stream; events order the three.  So
+batch i+1's upload runs while batch i computes, and batch i's download while
+batch i+1 computes.  Requests that arrive while batches are in flight join the
+next batch.  An update first waits for the batches in flight to finish (it
+rewrites the tree), then runs on the compute stream with the blocking calls.
+
+The serial reference (mode "serial") handles each request alone, in arrival
+order, with the blocking calls.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    seq: int
+    kind: str                 # "insert", "delete" or "knn"
+    arrival: float            # seconds after the start of the stream
+    coords: np.ndarray        # host int64 [D, m]: points of an update, or queries
+    ids: np.ndarray = None    # host int64 [m] for updates
+    k: int = 10
+    start: float = None       # set by the server
+    done: float = None
+    result: object = None     # knn: (ids, d2) host int64 [m, k]; delete: points removed
+
+    @classmethod
+    def from_dict(cls, d):
+        return cls(seq=d["seq"], kind=d["kind"], arrival=d["arrival"], coords=d["coords"], ids=d.get("ids"),
+                   k=d.get("k", 10))
+
+    @property
+    def size(self):
+        return int(self.coords.shape[1])
+
+
+class _Batch:
+    __slots__ = ("groups", "event", "status", "nbytes")
+
+    def __init__(self, groups, event, status, nbytes):
+        self.groups = groups      # [(requests, host ids, host d2)]
+        self.event = event        # recorded on the download stream after the last copy
+        self.status = status
+        self.nbytes = nbytes
+
+
+class Server:
+    def __init__(self, tree, dim, max_inflight=3, max_batch_queries=4_000_000, hbm_reserve_bytes=4 << 30,
+                 budget_bytes=None):
+        import torch
+        self.torch = torch
+        self.tree = tree
+        self.dim = dim
+        self.max_inflight = max_inflight
+        self.max_batch_queries = max_batch_queries
+        self.reserve = hbm_reserve_bytes
+        self.budget = budget_bytes
+        self.upload = torch.cuda.Stream()
+        self.compute = torch.cuda.Stream()
+        self.download = torch.cuda.Stream()
+        self.inflight_bytes = 0
+        self.batches = 0          # k-NN batches issued by the last run
+        self.launches = 0         # k-NN launches issued by the last run
+
+    # ---------------------------------------------------------------- admission
+    def _knn_bytes(self, r):
+        return r.size * (8 * self.dim + 16 * r.k)
+
+    def _admit(self, need):
+        """May a batch of `need` more bytes be enqueued now?"""
+        free, _ = self.torch.cuda.mem_get_info()
+        limit = free - self.reserve + self.inflight_bytes   # bytes in flight are already out of `free`
+        if self.budget is not None:
+            limit = min(limit, self.budget)
+        return self.inflight_bytes + need <= limit
+
+    # ---------------------------------------------------------------- work
+    def _run_update(self, r, now):
+        torch = self.torch
+        r.start = now()
+        with torch.cuda.stream(self.compute):
+            c = torch.from_numpy(np.ascontiguousarray(r.coords)).cuda()
+            i = torch.from_numpy(np.ascontiguousarray(r.ids)).cuda()
+            if r.kind == "insert":
+                self.tree.insert(c, i, stream=self.compute)
+            else:
+                r.result = self.tree.delete(c, i, stream=self.compute)
+        self.compute.synchronize()
+        r.done = now()
+
+    def _issue(self, reqs, nbytes, now):
+        """Enqueue one batch of k-NN requests: one launch per distinct k."""
+        torch = self.torch
+        t = now()
+        for r in reqs:
+            r.start = t
+        by_k = collections.defaultdict(list)
+        for r in reqs:
+            by_k[r.k].append(r)
+        with torch.cuda.stream(self.compute):
+            status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        groups = []
+        for k, rs in by_k.items():
+            q = np.concatenate([r.coords for r in rs], axis=1) if len(rs) > 1 else np.ascontiguousarray(rs[0].coords)
+            nq = q.shape[1]
+            hq = torch.from_numpy(q).pin_memory()
+            with torch.cuda.stream(self.upload):
+                dq = hq.to("cuda", non_blocking=True)
+            up = torch.cuda.Event()
+            up.record(self.upload)
+            self.compute.wait_event(up)
+            dq.record_stream(self.compute)
+            with torch.cuda.stream(self.compute):
+                oi = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+                od = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+            self.tree.knn_async(dq, k, oi, od, status, stream=self.compute)
+            self.launches += 1
+            fin = torch.cuda.Event()
+            fin.record(self.compute)
+            self.download.wait_event(fin)
+            hi = torch.empty((nq, k), dtype=torch.int64, pin_memory=True)
+            hd = torch.empty((nq, k), dtype=torch.int64, pin_memory=True)
+            with torch.cuda.stream(self.download):
+                hi.copy_(oi, non_blocking=True)
+                hd.copy_(od, non_blocking=True)
+            oi.record_stream(self.download)
+            od.record_stream(self.download)
+            groups.append((rs, hi, hd))
+        ev = torch.cuda.Event()
+        ev.record(self.download)
+        self.inflight_bytes += nbytes
+        self.batches += 1
+        return _Batch(groups, ev, status, nbytes)
+
+    def _retire(self, b, now):
+        b.event.synchronize()
+        self.inflight_bytes -= b.nbytes
+        st = int(b.status.item())
+        if st != 0:
+            raise RuntimeError("k-NN batch reported device status %d" % st)
+        t = now()
+        for rs, hi, hd in b.groups:
+            hi, hd = hi.numpy(), hd.numpy()
+            at = 0
+            for r in rs:
+                m = r.size
+                r.result = (hi[at:at + m].copy(), hd[at:at + m].copy())
+                r.done = t
+                at += m
+
+    # ---------------------------------------------------------------- run
+    def run(self, requests, mode="continuous", realtime=True):
+        """Handle `requests`; returns the makespan in seconds.  mode
+        "continuous" batches as described above, "serial" handles one request
+        at a time.  realtime=False lets every request arrive at time 0."""
+        torch = self.torch
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.seq))
+        self.batches = self.launches = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0   # noqa: E731
+        arr = (lambda r: r.arrival) if realtime else (lambda r: 0.0)
+        if mode == "serial":
+            for r in reqs:
+                while arr(r) > now():
+                    time.sleep(min(arr(r) - now(), 1e-3) if arr(r) - now() > 2e-4 else 0)
+                if r.kind == "knn":
+                    r.start = now()
+                    oi, od = self.tree.knn(r.coords, r.k)
+                    r.result = (oi.cpu().numpy(), od.cpu().numpy())
+                    r.done = now()
+                    self.batches += 1
+                    self.launches += 1
+                else:
+                    self._run_update(r, now)
+            return now()
+        if mode != "continuous":
+            raise ValueError("mode must be 'continuous' or 'serial'")
+        ready = collections.deque()
+        inflight = collections.deque()
+        i = 0
+        while i < len(reqs) or ready or inflight:
+            t = now()
+            while i < len(reqs) and arr(reqs[i]) <= t:
+                ready.append(reqs[i])
+                i += 1
+            while inflight and inflight[0].event.query():
+                self._retire(inflight.popleft(), now)
+            if not ready:
+                if inflight:
+                    time.sleep(2e-5)
+                elif i < len(reqs):
+                    wait = arr(reqs[i]) - now()
+                    if wait > 2e-4:
+                        time.sleep(min(wait, 1e-3))
+                continue
+            if ready[0].kind != "knn":
+                while inflight:
+                    self._retire(inflight.popleft(), now)
+                self._run_update(ready.popleft(), now)
+                continue
+            if len(inflight) >= self.max_inflight:
+                self._retire(inflight.popleft(), now)
+                continue
+            batch, nq, nbytes = [], 0, 0
+            while ready and ready[0].kind == "knn":
+                r = ready[0]
+                need = self._knn_bytes(r)
+                if batch and nq + r.size > self.max_batch_queries:
+                    break
+                if not self._admit(nbytes + need) and (batch or inflight):
+                    break
+                batch.append(ready.popleft())
+                nq += r.size
+                nbytes += need
+            if not batch:
+                self._retire(inflight.popleft(), now)   # wait for memory held by batches in flight
+                continue
+            inflight.append(self._issue(batch, nbytes, now))
+        torch.cuda.synchronize()
+        return now()
+
+
+def latency_stats(requests):
+    """p50 / p99 / mean of arrival-to-result latency in milliseconds."""
+    lat = np.array([r.done - r.arrival for r in requests])
+    if lat.size == 0:
+        return {"p50_ms": None, "p99_ms": None, "mean_ms": None}
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3)}

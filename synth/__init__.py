@@ -161,3 +161,124 @@ def log_uniform_sizes(count: int, lo: float, hi: float, seed: int) -> np.ndarray
     rng = _rng(seed)
     u = rng.random(count)
     return np.floor(np.exp(np.log(lo) + u * (np.log(hi) - np.log(lo)))).astype(np.int64)
+
+
+# --------------------------------------------------------------- hashed points
+# For very large resident sets (the serving workload holds 1e9 points) the
+# coordinates of a point are a function of its id, so a stream generator can
+# name the points it deletes without holding a host copy of the set, and the
+# GPU can generate the initial set in place.  The function is MurmurHash3's
+# 64-bit finaliser (fmix64) over (id, dimension, seed); the top 63 bits of the
+# hash, reduced modulo hi, give the coordinate (the bias of the reduction is
+# below hi / 2^63).
+_FM1 = 0xFF51AFD7ED558CCD
+_FM2 = 0xC4CEB9FE1A85EC53
+_SEED_MUL = 0xD6E8FEB86659FD93
+_M64 = (1 << 64) - 1
+
+
+def _fmix64_np(h: np.ndarray) -> np.ndarray:
+    h = h ^ (h >> np.uint64(33))
+    h = h * np.uint64(_FM1)
+    h = h ^ (h >> np.uint64(33))
+    h = h * np.uint64(_FM2)
+    return h ^ (h >> np.uint64(33))
+
+
+def hashed_points(ids: np.ndarray, dim: int, seed: int, hi: int = DEFAULT_RANGE) -> np.ndarray:
+    """Coordinates [dim, m] of the points with the given ids (see above)."""
+    ids = np.asarray(ids, dtype=np.int64).astype(np.uint64)
+    salt = np.uint64((seed * _SEED_MUL) & _M64)
+    out = np.empty((dim, ids.shape[0]), dtype=np.int64)
+    with np.errstate(over="ignore"):
+        for d in range(dim):
+            h = _fmix64_np((ids << np.uint64(3)) + np.uint64(d) + salt)
+            out[d] = ((h >> np.uint64(1)) % np.uint64(hi)).astype(np.int64)
+    return out
+
+
+def hashed_points_torch(ids, dim: int, seed: int, hi: int = DEFAULT_RANGE):
+    """The same coordinates as :func:`hashed_points`, computed with torch int64
+    ops on the device of `ids` (two's-complement wrap-around; logical right
+    shifts by masking)."""
+    import torch
+
+    def s64(v):                      # an unsigned 64-bit constant as int64
+        return v - (1 << 64) if v >= (1 << 63) else v
+
+    def shr(h, s):
+        return (h >> s) & ((1 << (64 - s)) - 1)
+
+    ids = ids.to(torch.int64)
+    salt = s64((seed * _SEED_MUL) & _M64)
+    out = torch.empty((dim, ids.shape[0]), dtype=torch.int64, device=ids.device)
+    for d in range(dim):
+        h = (ids << 3) + (d + salt)
+        h = h ^ shr(h, 33)
+        h = h * s64(_FM1)
+        h = h ^ shr(h, 33)
+        h = h * s64(_FM2)
+        h = h ^ shr(h, 33)
+        out[d] = torch.remainder(shr(h, 1), hi)
+    return out
+
+
+def request_stream(dim: int, n_requests: int, seed: int, rate_hz: float, n_initial: int,
+                   point_seed: int, insert_range=(1e3, 1e7), query_range=(1e2, 1e6),
+                   mix=(1, 1, 8), k_choices=(1, 10, 100), hi: int = DEFAULT_RANGE):
+    """A Poisson stream of requests against a resident set whose points are
+    ``hashed_points(arange(n_initial), dim, point_seed)``.
+
+    Kinds insert / delete / k-NN in the ratio `mix`; update sizes log-uniform
+    in `insert_range`, query batch sizes log-uniform in `query_range`, k
+    uniform in `k_choices`.  Inserts take fresh ids (from n_initial upward,
+    coordinates by the same hash); deletes pick ids uniformly among those
+    present at their position in the stream.  Inter-arrival times are
+    exponential with mean 1/rate_hz.  Returns a list of dicts with keys seq,
+    kind, arrival, coords ([dim, m] int64), ids (updates) and k (k-NN)."""
+    rng = _rng(seed)
+    p = np.asarray(mix, dtype=float) / float(sum(mix))
+    alive = np.ones(n_initial, dtype=bool)
+    alive_count = n_initial
+    next_id = n_initial
+    t = 0.0
+    out = []
+
+    def log_size(lo, hi_):
+        return int(np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi_)))))
+
+    for s in range(n_requests):
+        t += float(rng.exponential(1.0 / rate_hz))
+        kind = ("insert", "delete", "knn")[int(rng.choice(3, p=p))]
+        if kind == "knn":
+            m = log_size(*query_range)
+            q = np.empty((dim, m), dtype=np.int64)
+            for d in range(dim):
+                q[d] = rng.integers(0, hi, size=m, dtype=np.int64)
+            out.append(dict(seq=s, kind=kind, arrival=t, coords=q, ids=None,
+                            k=int(k_choices[int(rng.integers(0, len(k_choices)))])))
+            continue
+        m = log_size(*insert_range)
+        if kind == "insert":
+            ids = np.arange(next_id, next_id + m, dtype=np.int64)
+            next_id += m
+            grow = next_id - alive.shape[0]
+            if grow > 0:
+                alive = np.concatenate([alive, np.zeros(max(grow, alive.shape[0] // 8), dtype=bool)])
+            alive[ids] = True
+            alive_count += m
+        else:
+            m = min(m, alive_count)
+            picked = np.zeros(0, dtype=np.int64)
+            while picked.shape[0] < m:          # rejection: uniform over the live ids
+                want = m - picked.shape[0]
+                cand = rng.integers(0, next_id, size=2 * want + 16, dtype=np.int64)
+                cand = cand[alive[cand]]
+                cand = np.unique(cand)
+                cand = rng.permutation(cand)[:want]
+                alive[cand] = False
+                picked = np.concatenate([picked, cand])
+            ids = picked
+            alive_count -= m
+        out.append(dict(seq=s, kind=kind, arrival=t, coords=hashed_points(ids, dim, point_seed, hi), ids=ids, k=0))
+    return out
