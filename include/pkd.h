@@ -44,7 +44,7 @@ extern "C" {
 #define PKD_OK 0
 #define PKD_ERR_INVALID_ARG (-1)   /* null pointer, negative count, bad parameter */
 #define PKD_ERR_RANGE (-2)         /* a coordinate outside [0, 2^30) */
-#define PKD_ERR_UNSUPPORTED (-3)   /* dim outside 1..7, sample size > 4096, n >= 2^31 */
+#define PKD_ERR_UNSUPPORTED (-3)   /* dim outside 1..7, sample size > 2048, n >= 2^31 */
 #define PKD_ERR_OOM (-4)           /* device allocation failed */
 #define PKD_ERR_HIP (-5)           /* a HIP runtime call failed */
 #define PKD_ERR_CAPACITY (-6)      /* a query needs a deeper traversal stack than built in */
@@ -58,7 +58,7 @@ typedef struct {
   int32_t lambda;     /* skeleton levels per sieve round (lambda), 1..8; default 6 */
   int32_t leaf_size;  /* leaf wrap phi: a leaf holds at most phi points unless all
                          its points are identical (heavy leaf); default 32 */
-  int32_t oversample; /* sigma; the sample size is s = 2^lambda * sigma <= 4096;
+  int32_t oversample; /* sigma; the sample size is s = 2^lambda * sigma <= 2048;
                          default 32 (s = 2048) */
   int32_t alpha_num;  /* balance parameter alpha = alpha_num / alpha_den with */
   int32_t alpha_den;  /* 0 <= 2*alpha_num < alpha_den; default 3/10 */

@@ -76,7 +76,7 @@ def tune(dim, coords, ids, offsets=None, queries=None, k=10, grid=None, cache=DE
         tree_of = torch.from_numpy((np.arange(queries.shape[1]) % nt).astype(np.int32)).cuda()
     best = None
     for lam, sigma, phi, tile in itertools.product(grid["lam"], grid["sigma"], grid["phi"], grid["tile"]):
-        if (sigma << lam) > 4096:
+        if (sigma << lam) > 2048:   # the library caps the sample at 2048
             continue
         p = Params(dim, lam=lam, phi=phi, sigma=sigma)
 

@@ -13,7 +13,7 @@ namespace pkd {
 
 constexpr int kMaxDim = 7;
 constexpr int kMaxLambda = 8;
-constexpr int kMaxSample = 4096;                 // s = 2^lambda * sigma
+constexpr int kMaxSample = 2048;                 // s = 2^lambda * sigma (LDS of the select and finisher kernels)
 constexpr int64_t kCoordLimit = int64_t{1} << 30;
 constexpr int64_t kCoordMax = kCoordLimit - 1;
 constexpr int64_t kAllLeft = INT64_MAX;          // splitter that sends every point left

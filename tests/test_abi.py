@@ -50,8 +50,9 @@ def test_parameter_validation_before_any_device_work(L):
     import paper_2411_09275_amd as pk
     out = C.c_void_p()
     bad = [dict(dim=0), dict(dim=8), dict(lambda_=0), dict(lambda_=9), dict(leaf_size=0), dict(oversample=0),
-           dict(alpha_num=5, alpha_den=10), dict(alpha_den=0), dict(oversample=65)]
-    expect = [-3, -3, -1, -1, -1, -1, -1, -1, -3]
+           dict(alpha_num=5, alpha_den=10), dict(alpha_den=0), dict(oversample=65),
+           dict(oversample=33), dict(lambda_=7, oversample=32), dict(lambda_=8, oversample=16)]
+    expect = [-3, -3, -1, -1, -1, -1, -1, -1, -3, -3, -3, -3]   # a sample above 2048 points is unsupported
     for change, code in zip(bad, expect):
         p = pk._Params()
         L.pkd_default_params(C.byref(p), 2)
