@@ -42,12 +42,13 @@ def parse():
     ap.add_argument("--tile", type=int, default=2048)
     ap.add_argument("--cpu-sample", type=int, default=4_000_000, help="points of the oracle's build sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="build", choices=["build", "batching", "serving"],
+    ap.add_argument("--workload", default="build", choices=["build", "batching", "serving", "updates"],
                     help="build: the headline (1e8 3-D build + queries); batching: 4096 trees in one pass")
     ap.add_argument("--serve-n", type=int, default=1_000_000_000, help="points of the resident serving tree")
     ap.add_argument("--requests", type=int, default=100, help="requests in the serving stream")
     ap.add_argument("--load", type=float, default=0.8,
                     help="offered Poisson rate as a fraction of the serial handler's capacity")
+    ap.add_argument("--batch", type=int, default=1_000_000, help="points per BatchInsert / BatchDelete (updates)")
     ap.add_argument("--trees", type=int, default=4096)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -174,26 +175,39 @@ def bench_batching(a):
     t_batched = (time.perf_counter() - t0) / a.steps
     log("batched: %.1f ms per pass" % (t_batched * 1e3))
 
-    # one build and one query call per tree (same parameters)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    same = True
+    # one build and one query call per tree (same parameters); the per-tree
+    # query selections are made before the timed region, the result checks after
+    per_tree = []
     for D, gr in groups.items():
-        p, tile = params[D]
         off = gr["off"]
+        tk_host = {k: tk.cpu().numpy() for k, (idx, qk, tk) in gr["byk"].items()}
+        order = {k: np.argsort(tk_host[k], kind="stable") for k in tk_host}
+        bounds = {k: np.searchsorted(tk_host[k][order[k]], np.arange(gr["sel"].shape[0] + 1)) for k in tk_host}
         for j in range(gr["sel"].shape[0]):
             a0, a1 = int(off[j]), int(off[j + 1])
-            t = pk.Tree(p, gr["c"][:, a0:a1].contiguous(), gr["i"][a0:a1], tile=tile)
+            qs = []
             for k, (idx, qk, tk) in gr["byk"].items():
-                mine = torch.nonzero(tk == j).flatten()
-                if mine.numel() == 0:
-                    continue
-                oi, od = t.knn(qk[:, mine].contiguous(), k)
-                bi, bd = res[(D, k)]
-                same &= bool(torch.equal(oi, bi[mine]) and torch.equal(od, bd[mine]))
-            t.free()
+                mine = order[k][bounds[k][j]:bounds[k][j + 1]]
+                if mine.shape[0]:
+                    mt = torch.from_numpy(mine).to(dev)
+                    qs.append((k, mt, qk[:, mt].contiguous()))
+            per_tree.append((D, gr["c"][:, a0:a1].contiguous(), gr["i"][a0:a1].contiguous(), qs))
+    torch.cuda.synchronize()
+    outs = []
+    t0 = time.perf_counter()
+    for D, cj, ij, qs in per_tree:
+        p, tile = params[D]
+        t = pk.Tree(p, cj, ij, tile=tile)
+        outs.append([t.knn(qq, k) for k, _, qq in qs])
+        t.free()
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
+    same = True
+    for (D, _, _, qs), o in zip(per_tree, outs):
+        for (k, mt, _), (oi, od) in zip(qs, o):
+            bi, bd = res[(D, k)]
+            same &= bool(torch.equal(oi, bi[mt]) and torch.equal(od, bd[mt]))
+    del per_tree, outs
     log("one call per tree: %.1f ms; identical results: %s" % (t_single * 1e3, same))
     nq = T * 256
     out = {
@@ -272,9 +286,14 @@ def bench_serving(a):
         size = tree.size()
         tree.free()
         digest.append(size)
+        if not realtime:
+            for r in reqs:
+                r.arrival = 0.0
         lat = latency_stats(reqs)
-        log("  makespan %.3f s, p50 %.2f ms, p99 %.2f ms, %d batches / %d launches" % (
-            span, lat["p50_ms"], lat["p99_ms"], srv.batches, srv.launches))
+        busy = {kd: sum(r.done - r.start for r in reqs if r.kind == kd) for kd in ("insert", "delete", "knn")}
+        log("  makespan %.3f s, p50 %.2f ms, p99 %.2f ms, %d batches / %d launches; service s: %s" % (
+            span, lat["p50_ms"], lat["p99_ms"], srv.batches, srv.launches,
+            ", ".join("%s %.3f" % kv for kv in busy.items())))
         return span, lat, digest, srv.batches
 
     for _ in range(a.warmup):
@@ -298,7 +317,7 @@ def bench_serving(a):
                                "requests insert:delete:k-NN 1:1:8, updates log-uniform [1e3,1e7], queries "
                                "log-uniform [1e2,1e6], k in {1,10,100}" % (n0, len(raw)),
                    "update_points": n_upd, "queries": n_q},
-        "build_1e9_ms": round(min(build_s) * 1e3, 1),
+        "build_ms": round(min(build_s) * 1e3, 1),
         "closed": {"serial_s": round(span_sc, 4), "continuous_s": round(span_cc, 4),
                    "speedup": round(span_sc / span_cc, 3), "continuous_batches": nb_cc,
                    "items_per_s": round((n_upd + n_q) / span_cc, 1)},
@@ -306,6 +325,80 @@ def bench_serving(a):
                  "serial": lat_sr, "continuous": lat_cr, "continuous_batches": nb_cr,
                  "serial_makespan_s": round(span_sr, 4), "continuous_makespan_s": round(span_cr, 4)},
         "identical_results": same,
+    }
+    print(json.dumps(out))
+
+
+def bench_updates(a):
+    """Clustered 3-D points (1e8, 1000 random-walk clusters with step lengths
+    log-uniform in [1, 1e6]), then BatchInsert of 1e6 fresh points from the same
+    walks, 10-NN of 1e6 in-distribution queries, BatchDelete of 1e6 existing
+    ids drawn uniformly, 10-NN again.  alpha = 0.3.  One step = build + the four
+    operations + free; the value is the update throughput (inserted plus
+    deleted points per second of update time)."""
+    import torch
+
+    import paper_2411_09275_amd as pk
+    import synth
+
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    torch.cuda.set_device(0)
+    n, D, nb, nq = a.n, 3, a.batch, a.queries
+    t0 = time.perf_counter()
+    c, i, state = synth.clustered_points(n, D, seed=31)
+    ci, ii, _ = synth.clustered_points(nb, D, seed=32, id_base=n, continue_from=state)
+    q, _, _ = synth.clustered_points(nq, D, seed=33, continue_from=state)
+    di = synth.sample_existing(i, nb, seed=34)
+    dc = np.ascontiguousarray(c[:, di])
+    log("clustered workload generated in %.1f s" % (time.perf_counter() - t0))
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()  # noqa: E731
+    c, i, ci, ii, q, dc, di = (dev(x) for x in (c, i, ci, ii, q, dc, di))
+    p = pk.Params(D)
+    times = {"build": [], "insert": [], "knn_after_insert": [], "delete": [], "knn_after_delete": []}
+    removed = None
+    res = None
+
+    def timed(key, fn):
+        torch.cuda.synchronize()
+        s = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        times[key].append(time.perf_counter() - s)
+        return r
+
+    for step in range(a.warmup + a.steps):
+        t = timed("build", lambda: pk.Tree(p, c, i, tile=a.tile))
+        timed("insert", lambda: t.insert(ci, ii))
+        r1 = timed("knn_after_insert", lambda: t.knn(q, 10))
+        removed = timed("delete", lambda: t.delete(dc, di))
+        r2 = timed("knn_after_delete", lambda: t.knn(q, 10))
+        h = t.height()
+        size = t.size()
+        t.free()
+        cur = (r1[0].sum().item(), r1[1].sum().item(), r2[0].sum().item(), r2[1].sum().item(), removed, size, h)
+        assert res is None or res == cur, "results differ between steps"
+        res = cur
+        if step < a.warmup:
+            for v in times.values():
+                v.clear()
+        log("step %d: %s" % (step, ", ".join("%s %.1f ms" % (k, v[-1] * 1e3) for k, v in times.items() if v)))
+    ms = {k: float(np.mean(v) * 1e3) for k, v in times.items()}
+    upd_s = (ms["insert"] + ms["delete"]) / 1e3
+    out = {
+        "metric": "batch updates on clustered 1e8 3-D: Mpts/s of BatchInsert + BatchDelete",
+        "value": round(2 * nb / upd_s / 1e6, 2),
+        "unit": "Mpts/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(sum(ms.values()), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "%.0e clustered 3-D int64 points (1000 random-walk clusters, steps log-uniform "
+                               "[1,1e6]) in [0,1e9); insert %.0e fresh clustered points, delete %.0e uniform ids, "
+                               "%.0e in-distribution 10-NN after each batch; alpha 0.3" % (n, nb, nb, nq)},
+        "ms": {k: round(v, 3) for k, v in ms.items()},
+        "insert_mpts_s": round(nb / ms["insert"] / 1e3, 2),
+        "delete_mpts_s": round(nb / ms["delete"] / 1e3, 2),
+        "knn_mq_s": round(nq / ms["knn_after_delete"] / 1e3, 2),
+        "points_removed": removed, "final_size": res[5], "final_height": res[6],
     }
     print(json.dumps(out))
 
@@ -321,6 +414,11 @@ def main():
         return
     if a.workload == "serving":
         bench_serving(a)
+        return
+    if a.workload == "updates":
+        if a.queries == 10_000_000:
+            a.queries = 1_000_000
+        bench_updates(a)
         return
     import torch
 

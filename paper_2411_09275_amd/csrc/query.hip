@@ -2,6 +2,8 @@
 // Section 5 traversals).  One lane per query; the subspace of a node is not
 // stored but derived on the way down from the splitters (no bounding boxes,
 // Section 5).
+#include <algorithm>
+
 #include "pkd_internal.h"
 
 namespace pkd {
@@ -29,9 +31,10 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
                                                  const int64_t* __restrict__ Qry, int64_t nq, int k,
                                                  int64_t* __restrict__ out_ids, int64_t* __restrict__ out_d2,
                                                  int* flags, const int32_t* tree_of, int32_t n_trees,
-                                                 int32_t n_nodes, int64_t n_pts) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
-  if (j >= nq) return;
+                                                 int32_t n_nodes, int64_t n_pts, const uint32_t* __restrict__ perm) {
+  const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
+  if (j0 >= nq) return;
+  const int64_t j = perm ? static_cast<int64_t>(perm[j0]) : j0;   // lanes of a wave take nearby queries
   int64_t q[D];
   bool bad = false;
 #pragma unroll
@@ -51,10 +54,9 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
   }
 
   struct Ent {
-    int32_t node;
-    int32_t depth;
-    int32_t off[D];
     int64_t lb;
+    int32_t node;
+    int32_t off[D];
   };
   // the trees of a handle have their roots at nodes 0 .. n_trees-1; an empty
   // tree's root is a leaf of size 0
@@ -63,26 +65,27 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
     atomicOr(flags, kErrInternal);
     return;
   }
+  // a node is stacked at most once per level of the current path, so a valid
+  // tree never needs more than its height
   Ent stk[SD];
   stk[0].node = root;
-  stk[0].depth = 0;
   stk[0].lb = 0;
 #pragma unroll
   for (int d = 0; d < D; ++d) stk[0].off[d] = 0;
   int sp = 1;
+  int32_t visits = 0;
   while (sp > 0) {
     --sp;
     int32_t node = stk[sp].node;
-    int32_t depth = stk[sp].depth;
     int64_t lb = stk[sp].lb;
     int32_t off[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) off[d] = stk[sp].off[d];
     if (lb > bd[KM - 1]) continue;
     while (true) {
-      // the links of a valid tree stay inside the node array and no path is
-      // longer than the stack: anything else stops this lane with an error
-      if (static_cast<uint32_t>(node) >= static_cast<uint32_t>(n_nodes) || depth >= SD) {
+      // the links of a valid tree stay inside the node array and a traversal
+      // visits every node at most once: anything else stops this lane
+      if (static_cast<uint32_t>(node) >= static_cast<uint32_t>(n_nodes) || ++visits > n_nodes) {
         atomicOr(flags, kErrInternal);
         return;
       }
@@ -136,14 +139,12 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
           return;
         }
         stk[sp].node = far;
-        stk[sp].depth = depth + 1;
         stk[sp].lb = flb;
 #pragma unroll
         for (int d = 0; d < D; ++d) stk[sp].off[d] = (nd.dim == d) ? static_cast<int32_t>(fo) : off[d];
         ++sp;
       }
       node = near;
-      ++depth;
     }
   }
   for (int i = 0; i < k; ++i) {
@@ -167,9 +168,10 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
                                                    int64_t cap, const int64_t* __restrict__ Lo,
                                                    const int64_t* __restrict__ Hi, int64_t nb, int64_t* out,
                                                    int* flags, const int32_t* tree_of, int32_t n_trees, int phi,
-                                                   int32_t n_nodes, int64_t n_pts) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
-  if (j >= nb) return;
+                                                   int32_t n_nodes, int64_t n_pts, const uint32_t* __restrict__ perm) {
+  const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
+  if (j0 >= nb) return;
+  const int64_t j = perm ? static_cast<int64_t>(perm[j0]) : j0;
   int64_t lo[D], hi[D];
   bool bad = false, none = false;
 #pragma unroll
@@ -271,14 +273,163 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
   out[j] = count;
 }
 
+// ------------------------------------------------ spatial order of queries
+// A batch of queries is processed in Morton order (bits of the coordinates
+// interleaved, most significant first, below the tree id of a batch handle):
+// the lanes of a wave then walk neighbouring paths of the tree, which keeps
+// them converged and their node and leaf loads in cache.  Results still go to
+// each query's own row.  The order comes from a stable LSD radix sort with
+// 8-bit digits: per-tile digit counts, one exclusive scan over (digit, tile),
+// and a scatter that ranks equal digits inside each tile with ballots.
+constexpr int kRsTile = 2048;               // 256 threads x 8 items
+constexpr int64_t kOrderMinQueries = 16384;  // smaller batches keep their order
+
+template <int D>
+__global__ void k_morton(const int64_t* __restrict__ Q, int64_t nq, const int32_t* __restrict__ tree_of, int bpd,
+                         uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= nq) return;
+  uint64_t c[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) c[d] = static_cast<uint64_t>(Q[d * nq + j]) & static_cast<uint64_t>(kCoordMax);
+  uint64_t code = tree_of ? static_cast<uint64_t>(static_cast<uint32_t>(tree_of[j])) : 0;
+  for (int b = 29; b > 29 - bpd; --b)
+#pragma unroll
+    for (int d = 0; d < D; ++d) code = (code << 1) | ((c[d] >> b) & 1);
+  key[j] = code;
+  val[j] = static_cast<uint32_t>(j);
+}
+
+__global__ void __launch_bounds__(256) k_rs_count(const uint64_t* __restrict__ key, int64_t n, int shift,
+                                                  int32_t* __restrict__ hist, int64_t nblk) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kRsTile;
+  for (int i = threadIdx.x; i < kRsTile; i += 256)
+    if (b0 + i < n) atomicAdd(&h[(key[b0 + i] >> shift) & 255], 1u);
+  __syncthreads();
+  hist[static_cast<int64_t>(threadIdx.x) * nblk + blockIdx.x] = static_cast<int32_t>(h[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(256) k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                    int64_t n, int shift, const int32_t* __restrict__ off,
+                                                    int64_t nblk, uint64_t* __restrict__ kout,
+                                                    uint32_t* __restrict__ vout) {
+  constexpr int PER = kRsTile / 256, NCH = kRsTile / 64;   // chunks of 64 consecutive items
+  __shared__ uint16_t cnt[NCH][256];
+  __shared__ int32_t base[256];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const uint32_t lane = tid & 63;
+  const unsigned long long lt = (1ULL << lane) - 1;
+  for (int i = tid; i < NCH * 256; i += 256) (&cnt[0][0])[i] = 0;
+  base[tid] = off[static_cast<int64_t>(tid) * nblk + blockIdx.x];
+  __syncthreads();
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kRsTile;
+  uint64_t kk[PER];
+  uint32_t vv[PER];
+  int dig[PER], rank[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t i = b0 + k * 256 + tid;
+    const bool ok = i < n;
+    kk[k] = ok ? kin[i] : 0;
+    vv[k] = ok ? vin[i] : 0;
+    const int d = static_cast<int>((kk[k] >> shift) & 255);
+    unsigned long long peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const unsigned long long m = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? m : ~m;
+    }
+    dig[k] = d;
+    rank[k] = __popcll(peers & lt);
+    if (ok && (peers & lt) == 0) cnt[k * 4 + wave][d] = static_cast<uint16_t>(__popcll(peers));
+  }
+  __syncthreads();
+  {
+    uint16_t run = 0;
+    for (int ch = 0; ch < NCH; ++ch) {
+      const uint16_t x = cnt[ch][tid];
+      cnt[ch][tid] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t i = b0 + k * 256 + tid;
+    if (i < n) {
+      const int64_t pos = static_cast<int64_t>(base[dig[k]]) + cnt[k * 4 + wave][dig[k]] + rank[k];
+      kout[pos] = kk[k];
+      vout[pos] = vv[k];
+    }
+  }
+}
+
+struct QueryOrder {
+  DArr<uint64_t> k0, k1;
+  DArr<uint32_t> v0, v1;
+  DArr<int32_t> hist, off, bsum;
+  explicit QueryOrder(hipStream_t st) : k0(st), k1(st), v0(st), v1(st), hist(st), off(st), bsum(st) {}
+};
+
+int bits_for(int64_t v) {   // bits needed to write 0 .. v
+  int b = 0;
+  while (b < 63 && (int64_t{1} << b) <= v) ++b;
+  return b;
+}
+
+// Fills *perm with the queries in Morton order, or leaves it null for small
+// batches.  Stream-ordered, no host synchronisation.
+template <int D>
+int order_queries(hipStream_t st, const int64_t* Q, int64_t nq, const int32_t* tree_of, int32_t n_trees,
+                  QueryOrder& W, const uint32_t** perm) {
+  *perm = nullptr;
+  if (nq < kOrderMinQueries) return PKD_OK;
+  const int tb = tree_of ? bits_for(n_trees - 1) : 0;
+  // about 64 cells per wave of queries: log2(nq) + 6 bits of position
+  int bpd = (bits_for(nq) + 6 + D - 1) / D;
+  bpd = std::min(bpd, std::min(30, (64 - tb) / D));
+  const int nbits = tb + D * bpd;
+  const int passes = (nbits + 7) / 8;
+  const int64_t nblk = (nq + kRsTile - 1) / kRsTile;
+  PKD_TRY(W.k0.need(nq));
+  PKD_TRY(W.k1.need(nq));
+  PKD_TRY(W.v0.need(nq));
+  PKD_TRY(W.v1.need(nq));
+  PKD_TRY(W.hist.need(static_cast<size_t>(256) * nblk));
+  PKD_TRY(W.off.need(static_cast<size_t>(256) * nblk + 1));
+  hipLaunchKernelGGL(k_morton<D>, dim3(static_cast<unsigned>((nq + 255) / 256)), dim3(256), 0, st, Q, nq, tree_of,
+                     bpd, W.k0.p, W.v0.p);
+  PKD_TRY(kernel_status("k_morton"));
+  uint64_t* ka = W.k0.p;
+  uint64_t* kb = W.k1.p;
+  uint32_t* va = W.v0.p;
+  uint32_t* vb = W.v1.p;
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL(k_rs_count, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, ka, nq, 8 * p, W.hist.p,
+                       nblk);
+    PKD_TRY(kernel_status("k_rs_count"));
+    PKD_TRY(exscan_i32(st, W.hist.p, W.off.p, 256 * nblk, W.bsum));
+    hipLaunchKernelGGL(k_rs_scatter, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, ka, va, nq, 8 * p,
+                       W.off.p, nblk, kb, vb);
+    PKD_TRY(kernel_status("k_rs_scatter"));
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  *perm = va;
+  return PKD_OK;
+}
+
 template <int D, int SD>
 void launch_knn(int km, dim3 g, hipStream_t st, const Node* nodes, const int64_t* X, int64_t cap,
                 const int64_t* ids, const int64_t* q, int64_t nq, int k, int64_t* oi, int64_t* od, int* flags,
-                const int32_t* tree_of, int32_t n_trees, int32_t n_nodes, int64_t n_pts) {
+                const int32_t* tree_of, int32_t n_trees, int32_t n_nodes, int64_t n_pts, const uint32_t* perm) {
 #define PKD_KNN_CASE(KM) \
   case KM:               \
     hipLaunchKernelGGL((k_knn<D, KM, SD>), g, dim3(kQBlock), 0, st, nodes, X, cap, ids, q, nq, k, oi, od, flags, \
-                       tree_of, n_trees, n_nodes, n_pts); \
+                       tree_of, n_trees, n_nodes, n_pts, perm); \
     break;
   switch (km) {
     PKD_KNN_CASE(1)
@@ -298,18 +449,21 @@ int knn_d(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tr
           int64_t* oi, int64_t* od, int* flags) {
   int km = 1;
   while (km < k) km <<= 1;
+  QueryOrder W(st);
+  const uint32_t* perm = nullptr;
+  PKD_TRY(order_queries<D>(st, q, nq, tree_of, T->n_trees, W, &perm));
   const dim3 g(static_cast<unsigned>((nq + kQBlock - 1) / kQBlock));
   const int64_t* X = T->buf[T->cur];
   const int64_t* ids = X + static_cast<int64_t>(D) * T->cap;
-  if (T->height + 2 <= 48)
-    launch_knn<D, 48>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
-                      T->node_count, T->n);
-  else if (T->height + 2 <= 96)
-    launch_knn<D, 96>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
-                      T->node_count, T->n);
+  if (T->height + 2 <= 32)
+    launch_knn<D, 32>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
+                      T->node_count, T->n, perm);
+  else if (T->height + 2 <= 64)
+    launch_knn<D, 64>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
+                      T->node_count, T->n, perm);
   else if (T->height + 2 <= kMaxStack)
     launch_knn<D, kMaxStack>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
-                             T->node_count, T->n);
+                             T->node_count, T->n, perm);
   else
     return PKD_ERR_CAPACITY;
   hipError_t e = hipGetLastError();
@@ -320,14 +474,17 @@ int knn_d(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tr
 template <int D>
 int range_d(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, const int32_t* tree_of,
             int64_t nb, int64_t* out, int* flags) {
+  QueryOrder W(st);
+  const uint32_t* perm = nullptr;
+  PKD_TRY(order_queries<D>(st, lo, nb, tree_of, T->n_trees, W, &perm));   // boxes by their low corner
   const dim3 g(static_cast<unsigned>((nb + kQBlock - 1) / kQBlock));
   const int64_t* X = T->buf[T->cur];
   if (T->height + 3 <= 48)
     hipLaunchKernelGGL((k_range<D, 48>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags, tree_of,
-                       T->n_trees, T->prm.phi, T->node_count, T->n);
+                       T->n_trees, T->prm.phi, T->node_count, T->n, perm);
   else if (T->height + 3 <= kMaxStack)
     hipLaunchKernelGGL((k_range<D, kMaxStack>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags,
-                       tree_of, T->n_trees, T->prm.phi, T->node_count, T->n);
+                       tree_of, T->n_trees, T->prm.phi, T->node_count, T->n, perm);
   else
     return PKD_ERR_CAPACITY;
   hipError_t e = hipGetLastError();

@@ -225,3 +225,53 @@ def test_batch_build_equals_single_builds(orc, pk):
         assert np.array_equal(got[sel], ref), t
     with pytest.raises(pk.PkdError):
         B.insert(c[:, :5].copy(), i[:5] + 10 ** 9)
+
+
+# ------------------------------------------------ large batches (spatial order)
+# Batches of at least 16384 queries are processed in Morton order; every
+# result must still land in its own row and equal the oracle's.
+@pytest.mark.parametrize("D,nq,k", [(3, 40000, 10), (2, 16384, 1), (5, 20000, 7), (1, 30000, 3)])
+def test_knn_large_batch_matches_oracle(orc, pk, D, nq, k):
+    c, i = synth.uniform_points(120000, D, seed=40 + D)
+    q = synth.uniform_queries(nq, D, seed=41)
+    print("knn large batch D=%d nq=%d k=%d" % (D, nq, k), flush=True)
+    t = pk.Tree(pk.Params(D), c, i)
+    gi, gd = t.knn(q, k)
+    oi, od = orc.Tree(orc.Params(D), c, i).knn(q, k)
+    assert np.array_equal(gd.cpu().numpy(), od)
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    # the same queries in small unordered pieces give the same rows
+    si, sd = t.knn(q[:, :5000].copy(), k)
+    assert np.array_equal(si.cpu().numpy(), oi[:5000]) and np.array_equal(sd.cpu().numpy(), od[:5000])
+
+
+def test_range_count_large_batch_matches_oracle(orc, pk):
+    c, i = synth.uniform_points(150000, 3, seed=50)
+    lo, hi = synth.log_uniform_boxes(30000, 3, seed=51, side_lo=1e5, side_hi=1e8)
+    print("range large batch", flush=True)
+    t = pk.Tree(pk.Params(3), c, i)
+    got = t.range_count(lo, hi).cpu().numpy()
+    assert np.array_equal(got, orc.Tree(orc.Params(3), c, i).range_count(lo, hi))
+
+
+def test_batch_handle_large_query_batch(orc, pk):
+    sizes = synth.log_uniform_sizes(40, 1, 5e4, seed=60)
+    offsets = np.concatenate([[0], np.cumsum(sizes)])
+    c, i = synth.uniform_points(int(offsets[-1]), 2, seed=61)
+    B = pk.Tree.batch(pk.Params(2), c, i, offsets)
+    nq = 50000
+    q = synth.uniform_queries(nq, 2, seed=62)
+    tree_of = np.random.default_rng(63).integers(0, 40, size=nq).astype(np.int32)
+    print("batch handle large query batch", flush=True)
+    gi, gd = B.knn(q, 10, tree_of=tree_of)
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    lo, hi = synth.log_uniform_boxes(nq, 2, seed=64)
+    rc = B.range_count(lo, hi, tree_of=tree_of).cpu().numpy()
+    for t in range(40):
+        sel = np.nonzero(tree_of == t)[0]
+        a, b = offsets[t], offsets[t + 1]
+        ot = orc.Tree(orc.Params(2), np.ascontiguousarray(c[:, a:b]), i[a:b])
+        oi, od = ot.knn(np.ascontiguousarray(q[:, sel]), 10)
+        assert np.array_equal(gi[sel], oi) and np.array_equal(gd[sel], od), t
+        ref = ot.range_count(np.ascontiguousarray(lo[:, sel]), np.ascontiguousarray(hi[:, sel]))
+        assert np.array_equal(rc[sel], ref), t
