@@ -300,6 +300,102 @@ __device__ void block_bitonic(uint64_t (&k)[NPL], uint64_t* tmp) {
   }
 }
 
+constexpr uint16_t kNone = 0xFFFF;   // "no segment"
+
+// Bitonic sort of 64*NPL 64-bit keys held by one wave, ascending; lane l
+// holds elements l*NPL .. l*NPL+NPL-1.  Partners closer than NPL are in the
+// same lane, the others one shuffle away.
+template <int NPL>
+__device__ void wave_bitonic(uint64_t (&k)[NPL]) {
+  constexpr int N = 64 * NPL;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+    for (int j = size >> 1; j > 0; j >>= 1) {
+      if (j < NPL) {
+#pragma unroll
+        for (int r = 0; r < NPL; ++r) {
+          const int pr = r ^ j;
+          if (pr > r) {
+            const bool up = size < NPL ? (r & size) == 0 : ((lane * NPL) & size) == 0;
+            const uint64_t a = k[r], b = k[pr];
+            const bool sw = (a > b) == up;
+            k[r] = sw ? b : a;
+            k[pr] = sw ? a : b;
+          }
+        }
+      } else {
+        const bool keep_min = (((lane * NPL) & j) == 0) == (((lane * NPL) & size) == 0);
+#pragma unroll
+        for (int r = 0; r < NPL; ++r) {
+          const uint64_t o = shfl_xor_u64(k[r], j / NPL);
+          const bool take = (o < k[r]) == keep_min;
+          k[r] = take ? o : k[r];
+        }
+      }
+    }
+  }
+}
+
+// Stable partition, in place, of one sorted order Od (positions 0..m-1, held
+// by one wave) inside the segments that split: flagged points go to the left
+// part.  The rank of a point among the flagged ones before it comes from
+// ballots; segF[k] records that rank at the first position of segment k.
+// Every thread of the block calls this (it holds a block barrier); only
+// `active` waves touch Od.
+template <int NPL>
+__device__ void wave_partition(bool active, uint16_t* Od, int m, const uint16_t* seg_of_pt, const uint8_t* splits,
+                               const uint16_t* segA, const uint16_t* segNL, const uint8_t* flag, uint16_t* segF) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = (1ULL << lane) - 1;
+  uint16_t ev[NPL], fp[NPL], kk[NPL];
+  bool fl[NPL];
+  if (active) {
+    int run = 0;
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      ev[r] = 0;
+      fp[r] = 0;
+      kk[r] = kNone;
+      fl[r] = false;
+      if (r * 64 < m) {
+        const int p = r * 64 + lane;
+        const bool valid = p < m;
+        const uint16_t e = valid ? Od[p] : 0;
+        const uint16_t k = valid ? seg_of_pt[e] : kNone;
+        const bool spl = k != kNone && splits[k];
+        const bool f = spl && flag[e];
+        const unsigned long long mask = __ballot(f);
+        const int F = run + __popcll(mask & lt);
+        run += __popcll(mask);
+        if (spl && p == segA[k]) segF[k] = static_cast<uint16_t>(F);
+        ev[r] = e;
+        fp[r] = static_cast<uint16_t>(F);
+        kk[r] = spl ? k : kNone;
+        fl[r] = f;
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int p = r * 64 + lane;
+      if (p < m) {
+        int np = p;
+        const uint16_t k = kk[r];
+        if (k != kNone) {
+          const int a = segA[k];
+          const int lrank = fp[r] - segF[k];
+          np = fl[r] ? a + lrank : a + segNL[k] + (p - a - lrank);
+        }
+        Od[np] = ev[r];
+      }
+    }
+  }
+}
+
 // Per-dimension sorted orders with the register bitonic sort (m <= NT*NPL).
 template <int D, int NT, int NPL>
 __device__ void block_presort(const uint32_t* C, uint16_t* O, uint64_t* tmp, int m, int P) {
@@ -403,7 +499,6 @@ __device__ void lds_exscan_u8(const uint8_t* v, uint16_t* F, int n, uint32_t* pa
 // seg_of_pt[e] is the node (segment slot) of point e or kNone; for split
 // segments segA/segNL give the start and the left count; flag[e] = 1 sends e
 // left.  Points of non-splitting segments keep their positions.
-constexpr uint16_t kNone = 0xFFFF;
 
 template <int D>
 __device__ void lds_partition(uint16_t* O, uint16_t* Otmp, int P, int m, const uint16_t* seg_of_pt,
@@ -461,29 +556,25 @@ struct SkelLayout {
 };
 
 struct FinLayout {
-  size_t IDS, key, C, O, Otmp, seg, F, flag, fpos, lA0, lA1, lL0, lL1, lN0, lN1, sxs, snl, srank, sdm, ssplit, end;
+  size_t C, O, seg, flag, lA0, lA1, lL0, lL1, lN0, lN1, sxs, snl, srank, segF, sdm, ssplit, end;
   int MS;   // segments per level: splitting segments hold > phi points each
-  __host__ __device__ FinLayout(int D, int P, int phi, bool multiwave) {
+  __host__ __device__ FinLayout(int D, int P, int phi) {
     MS = min(P, 2 * P / (phi + 1) + 2);
     size_t o = 0;
-    IDS = o;    o += sizeof(int64_t) * P;
-    key = o;    o += multiwave ? sizeof(uint64_t) * P : 0;   // sort exchange across waves
     lN0 = o;    o += sizeof(int32_t) * MS;
     lN1 = o;    o += sizeof(int32_t) * MS;
     sxs = o;    o += sizeof(uint32_t) * MS;
     C = o;      o += sizeof(uint32_t) * D * P;
     O = o;      o += sizeof(uint16_t) * D * P;
-    Otmp = o;   o += sizeof(uint16_t) * P;
     seg = o;    o += sizeof(uint16_t) * P;
-    F = o;      o += sizeof(uint16_t) * (P + 8);
     lA0 = o;    o += sizeof(uint16_t) * MS;
     lA1 = o;    o += sizeof(uint16_t) * MS;
     lL0 = o;    o += sizeof(uint16_t) * MS;
     lL1 = o;    o += sizeof(uint16_t) * MS;
     snl = o;    o += sizeof(uint16_t) * MS;
     srank = o;  o += sizeof(uint16_t) * MS;
+    segF = o;   o += sizeof(uint16_t) * D * MS;
     flag = o;   o += P;
-    fpos = o;   o += P;
     sdm = o;    o += MS;
     ssplit = o; o += MS;
     end = align8(o);
@@ -1110,40 +1201,39 @@ __global__ void __launch_bounds__(64) k_emit(const Task* sp, int ns, int lambda,
 
 // ---------------------------------------------------------------- finisher
 // Plain construction of a subproblem of m < s points (Section 3: median split
-// on the widest dimension, one level at a time) in LDS, one workgroup per
-// subproblem; P >= m is the padded size of the launch's class.
+// on the widest dimension, one level at a time) in LDS, one workgroup of D
+// waves per subproblem: wave d sorts dimension d and keeps that order
+// partitioned as the nodes split.  P >= m is the padded size of the launch's
+// class (64 * NPL).
 // Node slots: each task owns a reserved range [res_base + res_off[i],
 // res_base + res_off[i+1]) sized for distinct coordinates; a task that needs
 // more (duplicates) takes the rest from the shared overflow counter.
-template <int D, int NT, int NPL>
-__global__ void __launch_bounds__(NT) k_finish(const Task* tasks, const int* list, int P, Bufs bufs, int final_buf,
-                                                   int phi, Node* nodes, int* overflow_ctr, int64_t node_cap,
-                                                   int* height, int* flags, const int32_t* res_off, int32_t res_base) {
+template <int D, int NPL>
+__global__ void __launch_bounds__(64 * D) k_finish(const Task* tasks, const int* list, int P, Bufs bufs, int final_buf,
+                                                     int phi, Node* nodes, int* overflow_ctr, int64_t node_cap,
+                                                     int* height, int* flags, const int32_t* res_off,
+                                                     int32_t res_base) {
+  constexpr int NT = 64 * D;
   extern __shared__ __align__(16) unsigned char smem[];
-  const Task q = tasks[list[blockIdx.x]];
+  const int ti = list[blockIdx.x];
+  const Task q = tasks[ti];
   const int m = q.m;
-  const int tid = threadIdx.x;
-  const FinLayout lay(D, P, phi, NT > 64);
-  int64_t* IDS = reinterpret_cast<int64_t*>(smem + lay.IDS);
-  uint64_t* key = reinterpret_cast<uint64_t*>(smem + lay.key);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const FinLayout lay(D, P, phi);
   uint32_t* C = reinterpret_cast<uint32_t*>(smem + lay.C);
   uint16_t* O = reinterpret_cast<uint16_t*>(smem + lay.O);
-  uint16_t* Otmp = reinterpret_cast<uint16_t*>(smem + lay.Otmp);
   uint16_t* seg = reinterpret_cast<uint16_t*>(smem + lay.seg);
-  uint16_t* F = reinterpret_cast<uint16_t*>(smem + lay.F);
   uint8_t* flag = smem + lay.flag;
-  uint8_t* fpos = smem + lay.fpos;
   uint16_t* lA[2] = {reinterpret_cast<uint16_t*>(smem + lay.lA0), reinterpret_cast<uint16_t*>(smem + lay.lA1)};
   uint16_t* lL[2] = {reinterpret_cast<uint16_t*>(smem + lay.lL0), reinterpret_cast<uint16_t*>(smem + lay.lL1)};
   int32_t* lN[2] = {reinterpret_cast<int32_t*>(smem + lay.lN0), reinterpret_cast<int32_t*>(smem + lay.lN1)};
   uint32_t* sxs = reinterpret_cast<uint32_t*>(smem + lay.sxs);
   uint16_t* snl = reinterpret_cast<uint16_t*>(smem + lay.snl);
   uint16_t* srank = reinterpret_cast<uint16_t*>(smem + lay.srank);
+  uint16_t* segF = reinterpret_cast<uint16_t*>(smem + lay.segF);
   uint8_t* sdm = smem + lay.sdm;
   uint8_t* ssplit = smem + lay.ssplit;
-  __shared__ uint32_t part[kBlock];
   __shared__ int sh_nlist, sh_nsplit, sh_base, sh_over, sh_maxdepth, sh_next, sh_more;
-  const int ti = list[blockIdx.x];
   const int res_end = res_base + res_off[ti + 1];
 
   const int src = q.buf;
@@ -1151,12 +1241,12 @@ __global__ void __launch_bounds__(NT) k_finish(const Task* tasks, const int* lis
   const int64_t xcap = bufs.cap[src];
   bool bad = false;
   for (int i = tid; i < m; i += NT) {
+#pragma unroll
     for (int d = 0; d < D; ++d) {
-      int64_t v = X[d * xcap + q.start + i];
+      const int64_t v = X[d * xcap + q.start + i];
       bad |= static_cast<uint64_t>(v) >= static_cast<uint64_t>(kCoordLimit);
       C[d * P + i] = static_cast<uint32_t>(v);
     }
-    IDS[i] = bufs.id[src][q.start + i];
     seg[i] = 0;
   }
   if (bad) atomicOr(flags, kErrRange);
@@ -1170,9 +1260,23 @@ __global__ void __launch_bounds__(NT) k_finish(const Task* tasks, const int* lis
     lN[0][0] = q.slot;
   }
   __syncthreads();
-  if (m > phi) block_presort<D, NT, NPL>(C, O, key, m, P);
-  else
+  if (m > phi) {
+    // wave d: the points ordered by (coordinate d, index)
+    uint64_t k[NPL];
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int e = lane * NPL + r;
+      k[r] = e < m ? (static_cast<uint64_t>(C[wave * P + e]) << 16) | static_cast<uint64_t>(e) : ~0ULL;
+    }
+    wave_bitonic<NPL>(k);
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int e = lane * NPL + r;
+      if (e < m) O[wave * P + e] = static_cast<uint16_t>(k[r] & 0xFFFF);
+    }
+  } else {
     for (int i = tid; i < m; i += NT) O[i] = static_cast<uint16_t>(i);
+  }
   __syncthreads();
   int cur = 0;
   int depth = q.depth;
@@ -1268,8 +1372,11 @@ __global__ void __launch_bounds__(NT) k_finish(const Task* tasks, const int* lis
       flag[e] = (k != kNone && ssplit[k]) ? (C[sdm[k] * P + e] < sxs[k] ? 1 : 0) : 0;
     }
     __syncthreads();
-    // on the last splitting level only the order that is written out matters
-    lds_partition<D>(O, Otmp, P, m, seg, ssplit, lA[cur], snl, flag, fpos, F, part, sh_more ? D : 1);
+    // wave d partitions order d; on the last splitting level only the order
+    // that is written out (dimension 0) matters
+    const bool active = wave < (sh_more ? D : 1);
+    wave_partition<NPL>(active, O + wave * P, m, seg, ssplit, lA[cur], snl, flag, segF + wave * lay.MS);
+    __syncthreads();
     for (int e = tid; e < m; e += NT) {
       const int k = seg[e];
       if (k == kNone) continue;
@@ -1299,12 +1406,29 @@ __global__ void __launch_bounds__(NT) k_finish(const Task* tasks, const int* lis
     return;
   }
   if (tid == 0 && sh_maxdepth > *reinterpret_cast<volatile int*>(height)) atomicMax(height, sh_maxdepth);
+  // ids are gathered into registers before any is written: the source and
+  // destination arrays may be the same
+  constexpr int PER = (64 * NPL + NT - 1) / NT;
+  const int64_t* Isrc = bufs.id[src] + q.start;
+  int64_t idv[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int p = r * NT + tid;
+    idv[r] = p < m ? Isrc[O[p]] : 0;
+  }
+  __syncthreads();
   int64_t* Y = bufs.c[final_buf];
   const int64_t ycap = bufs.cap[final_buf];
-  for (int p = tid; p < m; p += NT) {
-    const int e = O[p];
-    for (int d = 0; d < D; ++d) Y[d * ycap + q.start + p] = static_cast<int64_t>(C[d * P + e]);
-    bufs.id[final_buf][q.start + p] = IDS[e];
+  int64_t* Iout = bufs.id[final_buf] + q.start;
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int p = r * NT + tid;
+    if (p < m) {
+      const int e = O[p];
+#pragma unroll
+      for (int d = 0; d < D; ++d) Y[d * ycap + q.start + p] = static_cast<int64_t>(C[d * P + e]);
+      Iout[p] = idv[r];
+    }
   }
 }
 
@@ -1428,7 +1552,7 @@ size_t select_lds_bytes(int s, int cap) {
 
 template <int D>
 size_t finish_lds_bytes(int P, int phi) {
-  return FinLayout(D, P, phi, P > 512).end;
+  return FinLayout(D, P, phi).end;
 }
 
 // Exact split of subproblem q whose sample was entirely identical (host-driven,
@@ -1711,21 +1835,22 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
         const int Pc = 64 << cls;
         size_t lds = finish_lds_bytes<D>(Pc, P.phi);
         Prof::begin(kProfFinish, st);
-        // up to 512 points: one wave per subproblem; larger: a 256-thread workgroup
-#define PKD_FIN(NT, NPL)                                                                                          \
+        // one workgroup of D waves per subproblem, 64*NPL = P keys per wave
+#define PKD_FIN(NPL)                                                                                              \
   {                                                                                                               \
-    PKD_TRY(allow_lds(k_finish<D, NT, NPL>, lds));                                                                \
-    hipLaunchKernelGGL((k_finish<D, NT, NPL>), dim3(counts[cls]), dim3(NT), lds, st, fin.p, lists.p + cls * n_fin, Pc, \
-                       bufs, F, P.phi, T->nodes, d_nodes, T->node_cap, d_height, d_flags, res_off.p, base_nodes); \
+    PKD_TRY(allow_lds(k_finish<D, NPL>, lds));                                                                    \
+    hipLaunchKernelGGL((k_finish<D, NPL>), dim3(counts[cls]), dim3(64 * D), lds, st, fin.p, lists.p + cls * n_fin, \
+                       Pc, bufs, F, P.phi, T->nodes, d_nodes, T->node_cap, d_height, d_flags, res_off.p,          \
+                       base_nodes);                                                                               \
   }
         switch (cls) {
-          case 0: PKD_FIN(64, 1) break;
-          case 1: PKD_FIN(64, 2) break;
-          case 2: PKD_FIN(64, 4) break;
-          case 3: PKD_FIN(64, 8) break;
-          case 4: PKD_FIN(256, 4) break;
-          case 5: PKD_FIN(256, 8) break;
-          default: PKD_FIN(256, 16) break;
+          case 0: PKD_FIN(1) break;
+          case 1: PKD_FIN(2) break;
+          case 2: PKD_FIN(4) break;
+          case 3: PKD_FIN(8) break;
+          case 4: PKD_FIN(16) break;
+          case 5: PKD_FIN(32) break;
+          default: return PKD_ERR_INTERNAL;   // base cases hold fewer than s <= 2048 points
         }
 #undef PKD_FIN
         Prof::end(kProfFinish, st, 0.0);
