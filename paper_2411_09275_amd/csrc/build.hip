@@ -154,46 +154,66 @@ __global__ void k_tile_scan(const Task* sp, int ns, int tile, int64_t* tile_off,
   }
 }
 
-// ------------------------------------------------------------- candidates
-// For subproblems larger than small_max: every point whose sampling key falls
-// below the subproblem's threshold is appended (key, position) to that
-// subproblem's candidate list.  Appends are wave-aggregated.
-__global__ void k_candidates(const Task* sp, int ns, const int64_t* tile_off, int tile, Bufs bufs, int src,
-                             uint64_t seed, const int8_t* shift, int small_max, uint64_t* cand_key,
-                             uint32_t* cand_pos, uint32_t* cand_cnt, int cap) {
+// Candidates of the sample of every subproblem that sieves this round: the
+// points whose key is at most the subproblem's threshold (Section 3: the
+// sample is the s points of smallest key).  One tile per workgroup; the tile's
+// candidates are counted first and take their slots with one atomic, so the
+// counters (one per 128-byte line) see one update per tile.
+constexpr int kCntStride = 32;   // uint32 counters, one per cache line
+
+template <int ITER>
+__global__ void __launch_bounds__(kBlock) k_candidates(const Task* sp, int ns, const int64_t* tile_off, Bufs bufs,
+                                                       int src, uint64_t seed, const int8_t* shift, int small_max,
+                                                       uint64_t* cand_key, uint32_t* cand_pos, uint32_t* cand_cnt,
+                                                       int cap) {
+  constexpr int kWaves = kBlock / 64;
   __shared__ int sig_sh;
-  int64_t t = blockIdx.x;
-  if (threadIdx.x == 0) sig_sh = find_owner(tile_off, ns, t);
+  __shared__ uint32_t wcnt[ITER][kWaves];
+  __shared__ uint32_t gbase;
+  const int64_t t = blockIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const uint32_t lane = lane_id();
+  if (tid == 0) sig_sh = find_owner(tile_off, ns, t);
   __syncthreads();
-  int sig = sig_sh;
-  Task q = sp[sig];
+  const int sig = sig_sh;
+  const Task q = sp[sig];
   if (q.m <= small_max) return;
-  int sh = shift[sig];
-  uint64_t thr = sh == 0 ? ~0ULL : (~0ULL >> sh);   // key <= thr  <=>  key < 2^(64-sh)
-  int64_t lo = (t - tile_off[sig]) * tile;
-  int64_t hi = min<int64_t>(lo + tile, q.m);
+  const int sh = shift[sig];
+  const uint64_t thr = sh == 0 ? ~0ULL : (~0ULL >> sh);   // key <= thr  <=>  key < 2^(64-sh)
+  const int64_t lo = (t - tile_off[sig]) * (kBlock * ITER);
+  const int64_t hi = min<int64_t>(lo + kBlock * ITER, q.m);
   const int64_t* ids = bufs.id[src] + q.start;
+  uint64_t key[ITER];
+  unsigned long long mask[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int64_t i = lo + it * kBlock + tid;
+    key[it] = i < hi ? sample_key(seed, q.depth, ids[i]) : ~0ULL;
+    mask[it] = __ballot(i < hi && key[it] <= thr);
+    if (lane == 0) wcnt[it][wave] = static_cast<uint32_t>(__popcll(mask[it]));
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int it = 0; it < ITER; ++it)
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t x = wcnt[it][w];
+        wcnt[it][w] = run;
+        run += x;
+      }
+    gbase = run ? atomicAdd(cand_cnt + static_cast<int64_t>(sig) * kCntStride, run) : 0;
+  }
+  __syncthreads();
   uint64_t* kout = cand_key + static_cast<int64_t>(sig) * cap;
   uint32_t* pout = cand_pos + static_cast<int64_t>(sig) * cap;
-  for (int64_t base = lo; base < hi; base += kBlock) {
-    int64_t i = base + threadIdx.x;
-    uint64_t key = 0;
-    bool take = false;
-    if (i < hi) {
-      key = sample_key(seed, q.depth, ids[i]);
-      take = key <= thr;
-    }
-    unsigned long long mask = __ballot(take);
-    if (mask == 0) continue;
-    int leader = __ffsll(static_cast<long long>(mask)) - 1;
-    uint32_t wbase = 0;
-    if (lane_id() == static_cast<uint32_t>(leader)) wbase = atomicAdd(cand_cnt + sig, static_cast<uint32_t>(__popcll(mask)));
-    wbase = __shfl(wbase, leader);
-    if (take) {
-      uint32_t k = wbase + static_cast<uint32_t>(__popcll(mask & ((1ULL << lane_id()) - 1)));
+  const unsigned long long lt = (1ULL << lane) - 1;
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    if ((mask[it] >> lane) & 1) {
+      const uint32_t k = gbase + wcnt[it][wave] + static_cast<uint32_t>(__popcll(mask[it] & lt));
       if (k < static_cast<uint32_t>(cap)) {
-        kout[k] = key;
-        pout[k] = static_cast<uint32_t>(i);
+        kout[k] = key[it];
+        pout[k] = static_cast<uint32_t>(lo + it * kBlock + tid);
       }
     }
   }
@@ -206,98 +226,10 @@ __global__ void k_candidates(const Task* sp, int ns, const int64_t* tile_off, in
 // in every O[d], so its widest dimension and its upper median are read
 // directly, and a split is a stable partition of each O[d] by the side flag.
 
-// Bitonic sort of n2 (power of two) 64-bit keys, ascending.
-__device__ void lds_bitonic(uint64_t* key, int n2) {
-  for (int k = 2; k <= n2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < (n2 >> 1); i += blockDim.x) {
-        int lo = 2 * i - (i & (j - 1));
-        int hi = lo + j;
-        bool up = (lo & k) == 0;
-        uint64_t a = key[lo], b = key[hi];
-        if ((a > b) == up) {
-          key[lo] = b;
-          key[hi] = a;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Sort each dimension: O[d][p] = index of the p-th smallest (coordinate, index).
-template <int D>
-__device__ void lds_presort(const uint32_t* C, uint16_t* O, uint64_t* key, int m, int P) {
-  int n2 = 1;
-  while (n2 < m) n2 <<= 1;
-  for (int d = 0; d < D; ++d) {
-    for (int i = threadIdx.x; i < n2; i += blockDim.x)
-      key[i] = i < m ? (static_cast<uint64_t>(C[d * P + i]) << 16) | static_cast<uint64_t>(i) : ~0ULL;
-    __syncthreads();
-    lds_bitonic(key, n2);
-    for (int i = threadIdx.x; i < m; i += blockDim.x) O[d * P + i] = static_cast<uint16_t>(key[i] & 0xFFFF);
-    __syncthreads();
-  }
-}
-
 __device__ inline uint64_t shfl_xor_u64(uint64_t v, int mask) {
   const int lo = __shfl_xor(static_cast<int>(static_cast<uint32_t>(v)), mask);
   const int hi = __shfl_xor(static_cast<int>(v >> 32), mask);
   return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
-}
-
-// Bitonic sort of NT*NPL 64-bit keys held in registers, ascending; thread t
-// holds elements t*NPL .. t*NPL+NPL-1.  Partners at distance below NPL are in
-// the same thread, below 64*NPL in the same wave (shuffles); larger distances
-// go through LDS (tmp: NT*NPL keys).
-template <int NT, int NPL>
-__device__ void block_bitonic(uint64_t (&k)[NPL], uint64_t* tmp) {
-  constexpr int N = NT * NPL;
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int size = 2; size <= N; size <<= 1) {
-#pragma unroll
-    for (int j = size >> 1; j > 0; j >>= 1) {
-      if (j < NPL) {
-#pragma unroll
-        for (int r = 0; r < NPL; ++r) {
-          const int pr = r ^ j;
-          if (pr > r) {
-            // ascending iff bit `size` of the element index is clear
-            const bool up = size < NPL ? (r & size) == 0 : ((tid * NPL) & size) == 0;
-            const uint64_t a = k[r], b = k[pr];
-            const bool sw = (a > b) == up;
-            k[r] = sw ? b : a;
-            k[pr] = sw ? a : b;
-          }
-        }
-      } else if (j < 64 * NPL) {
-        // partner in lane ^ (j/NPL), same register; keep the smaller key iff
-        // this element is the lower one of an ascending pair (or the upper
-        // one of a descending pair)
-        const bool keep_min = (((tid * NPL) & j) == 0) == (((tid * NPL) & size) == 0);
-#pragma unroll
-        for (int r = 0; r < NPL; ++r) {
-          const uint64_t o = shfl_xor_u64(k[r], j / NPL);
-          const bool take = (o < k[r]) == keep_min;
-          k[r] = take ? o : k[r];
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < NPL; ++r) tmp[tid * NPL + r] = k[r];
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < NPL; ++r) {
-          const int e = tid * NPL + r;
-          const uint64_t o = tmp[e ^ j];
-          const bool keep_min = (((e & j) == 0) == ((e & size) == 0));
-          const uint64_t mn = k[r] < o ? k[r] : o, mx = k[r] < o ? o : k[r];
-          k[r] = keep_min ? mn : mx;
-        }
-        __syncthreads();
-      }
-    }
-  }
 }
 
 constexpr uint16_t kNone = 0xFFFF;   // "no segment"
@@ -349,16 +281,14 @@ __device__ void wave_partition(bool active, uint16_t* Od, int m, const uint16_t*
                                const uint16_t* segA, const uint16_t* segNL, const uint8_t* flag, uint16_t* segF) {
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = (1ULL << lane) - 1;
-  uint16_t ev[NPL], fp[NPL], kk[NPL];
-  bool fl[NPL];
+  // per position: point | rank << 16, and segment | side << 16 (kNone: stays)
+  uint32_t pe[NPL], ks[NPL];
   if (active) {
     int run = 0;
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
-      ev[r] = 0;
-      fp[r] = 0;
-      kk[r] = kNone;
-      fl[r] = false;
+      pe[r] = 0;
+      ks[r] = kNone;
       if (r * 64 < m) {
         const int p = r * 64 + lane;
         const bool valid = p < m;
@@ -370,10 +300,8 @@ __device__ void wave_partition(bool active, uint16_t* Od, int m, const uint16_t*
         const int F = run + __popcll(mask & lt);
         run += __popcll(mask);
         if (spl && p == segA[k]) segF[k] = static_cast<uint16_t>(F);
-        ev[r] = e;
-        fp[r] = static_cast<uint16_t>(F);
-        kk[r] = spl ? k : kNone;
-        fl[r] = f;
+        pe[r] = static_cast<uint32_t>(e) | (static_cast<uint32_t>(F) << 16);
+        ks[r] = spl ? (static_cast<uint32_t>(k) | (f ? 0x10000u : 0u)) : kNone;
       }
     }
   }
@@ -384,37 +312,16 @@ __device__ void wave_partition(bool active, uint16_t* Od, int m, const uint16_t*
       const int p = r * 64 + lane;
       if (p < m) {
         int np = p;
-        const uint16_t k = kk[r];
+        const uint32_t k = ks[r] & 0xFFFF;
         if (k != kNone) {
           const int a = segA[k];
-          const int lrank = fp[r] - segF[k];
-          np = fl[r] ? a + lrank : a + segNL[k] + (p - a - lrank);
+          const int lrank = static_cast<int>(pe[r] >> 16) - segF[k];
+          np = (ks[r] >> 16) ? a + lrank : a + segNL[k] + (p - a - lrank);
         }
-        Od[np] = ev[r];
+        Od[np] = static_cast<uint16_t>(pe[r] & 0xFFFF);
       }
     }
   }
-}
-
-// Per-dimension sorted orders with the register bitonic sort (m <= NT*NPL).
-template <int D, int NT, int NPL>
-__device__ void block_presort(const uint32_t* C, uint16_t* O, uint64_t* tmp, int m, int P) {
-  const int tid = threadIdx.x;
-  for (int d = 0; d < D; ++d) {
-    uint64_t k[NPL];
-#pragma unroll
-    for (int r = 0; r < NPL; ++r) {
-      const int e = tid * NPL + r;
-      k[r] = e < m ? (static_cast<uint64_t>(C[d * P + e]) << 16) | static_cast<uint64_t>(e) : ~0ULL;
-    }
-    block_bitonic<NT, NPL>(k, tmp);
-#pragma unroll
-    for (int r = 0; r < NPL; ++r) {
-      const int e = tid * NPL + r;
-      if (e < m) O[d * P + e] = static_cast<uint16_t>(k[r] & 0xFFFF);
-    }
-  }
-  __syncthreads();
 }
 
 // Split rule of a node that owns positions [a, a+L) (L >= 1): widest
@@ -460,76 +367,6 @@ __device__ bool lds_split_rule(const uint32_t* C, const uint16_t* O, int P, int 
   return true;
 }
 
-// Block-wide exclusive scan of small non-negative counts in position order:
-// F[p] = sum of v[q] for q < p, for p in [0, n].  One value per position.
-__device__ void lds_exscan_u8(const uint8_t* v, uint16_t* F, int n, uint32_t* part) {
-  int nt = blockDim.x, tid = threadIdx.x;
-  int per = (n + nt - 1) / nt;
-  int b = tid * per, e = min(n, b + per);
-  uint32_t s = 0;
-  for (int p = b; p < e; ++p) s += v[p];
-  part[tid] = s;
-  __syncthreads();
-  if (tid < 64) {
-    // one wave scans the block partials
-    uint32_t acc = 0;
-    for (int base = 0; base < nt; base += 64) {
-      uint32_t x = (base + tid < nt) ? part[base + tid] : 0;
-      uint32_t incl = x;
-      for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(incl, o);
-        if (tid >= o) incl += y;
-      }
-      if (base + tid < nt) part[base + tid] = acc + incl - x;
-      acc += __shfl(incl, 63);
-    }
-  }
-  __syncthreads();
-  s = part[tid];
-  for (int p = b; p < e; ++p) {
-    F[p] = static_cast<uint16_t>(s);
-    s += v[p];
-  }
-  if (e == n && b < e) F[n] = static_cast<uint16_t>(s);
-  if (n == 0 && tid == 0) F[0] = 0;
-  __syncthreads();
-}
-
-// Stable partition of every O[d] inside the nodes that split at this step.
-// seg_of_pt[e] is the node (segment slot) of point e or kNone; for split
-// segments segA/segNL give the start and the left count; flag[e] = 1 sends e
-// left.  Points of non-splitting segments keep their positions.
-
-template <int D>
-__device__ void lds_partition(uint16_t* O, uint16_t* Otmp, int P, int m, const uint16_t* seg_of_pt,
-                              const uint8_t* splits, const uint16_t* segA, const uint16_t* segNL,
-                              const uint8_t* flag, uint8_t* fpos, uint16_t* F, uint32_t* part, int nd = D) {
-  for (int d = 0; d < nd; ++d) {
-    uint16_t* Od = O + d * P;
-    for (int p = threadIdx.x; p < m; p += blockDim.x) {
-      uint16_t e = Od[p];
-      uint16_t k = seg_of_pt[e];
-      fpos[p] = (k != kNone && splits[k]) ? flag[e] : 0;
-    }
-    __syncthreads();
-    lds_exscan_u8(fpos, F, m, part);
-    for (int p = threadIdx.x; p < m; p += blockDim.x) {
-      uint16_t e = Od[p];
-      uint16_t k = seg_of_pt[e];
-      int np = p;
-      if (k != kNone && splits[k]) {
-        int a = segA[k];
-        int lrank = F[p] - F[a];
-        np = flag[e] ? a + lrank : a + segNL[k] + (p - a - lrank);
-      }
-      Otmp[np] = e;
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p < m; p += blockDim.x) Od[p] = Otmp[p];
-    __syncthreads();
-  }
-}
-
 // LDS layouts (byte offsets), computed identically on host and device.  The
 // 8-byte arrays come first so every array is naturally aligned.
 __host__ __device__ inline int next_pow2(int x) {
@@ -540,17 +377,15 @@ __host__ __device__ inline int next_pow2(int x) {
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t{7}; }
 
 struct SkelLayout {
-  size_t key, C, O, Otmp, node_of, F, flag, fpos, end;
+  size_t C, pos, O, node_of, segF, flag, end;
   __host__ __device__ SkelLayout(int D, int P) {
     size_t o = 0;
-    key = o;      o += sizeof(uint64_t) * (next_pow2(P) > kBlock ? next_pow2(P) : kBlock);   // block sort exchange
     C = o;        o += sizeof(uint32_t) * D * P;
+    pos = o;      o += sizeof(uint32_t) * P;
     O = o;        o += sizeof(uint16_t) * D * P;
-    Otmp = o;     o += sizeof(uint16_t) * P;
     node_of = o;  o += sizeof(uint16_t) * P;
-    F = o;        o += sizeof(uint16_t) * (P + 8);
+    segF = o;     o += sizeof(uint16_t) * D * (2 << kMaxLambda);
     flag = o;     o += P;
-    fpos = o;     o += P;
     end = align8(o);
   }
 };
@@ -582,9 +417,12 @@ struct FinLayout {
 };
 
 // ------------------------------------------------- select sample + skeleton
-// One workgroup per sieve subproblem.  Phase 1 finds the s smallest (key, id)
-// among the candidates (radix select over the 64-bit keys, ties by id);
-// phase 2 gathers their coordinates and builds the lambda-level skeleton.
+// One workgroup of D waves per sieve subproblem.  Phase 1 finds the s
+// smallest (key, id) among the candidates by a radix select over the 64-bit
+// keys (ties by id), reading the candidates from global memory (they stay in
+// L2 across the passes).  Phase 2 gathers the sample's coordinates and builds
+// the lambda-level skeleton; wave d keeps the sample sorted by coordinate d
+// and partitions that order as the skeleton nodes split.
 struct SelectOut {
   int64_t* rx;        // [ns][2^lambda] splitters in routing form
   uint8_t* rdim;      // [ns][2^lambda]
@@ -596,36 +434,41 @@ struct SelectOut {
 };
 
 template <int D, int NPL>
-__global__ void __launch_bounds__(kBlock) k_select_skeleton(const Task* sp, int ns, Bufs bufs, int src,
-                                                            uint64_t seed, int s, int lambda,
-                                                            const int8_t* shift, int small_max,
-                                                            const uint64_t* cand_key, const uint32_t* cand_pos,
-                                                            const uint32_t* cand_cnt, int cap, SelectOut out) {
+__global__ void __launch_bounds__(64 * D) k_select_skeleton(const Task* sp, int ns, Bufs bufs, int src,
+                                                              uint64_t seed, int s, int lambda,
+                                                              const int8_t* shift, int small_max,
+                                                              const uint64_t* cand_key, const uint32_t* cand_pos,
+                                                              const uint32_t* cand_cnt, int cap, SelectOut out) {
+  constexpr int NT = 64 * D;
+  constexpr int P = 64 * NPL;   // padded stride of the per-dimension arrays (>= s)
   extern __shared__ __align__(16) unsigned char smem[];
   const int sig = blockIdx.x;
   const Task q = sp[sig];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t* ids = bufs.id[src] + q.start;
   const int64_t* X = bufs.c[src];
   const int64_t xcap = bufs.cap[src];
-  const int P = s;   // padded stride of the per-dimension arrays
+  const SkelLayout lay(D, P);
+  uint32_t* C = reinterpret_cast<uint32_t*>(smem + lay.C);
+  uint32_t* sampPos = reinterpret_cast<uint32_t*>(smem + lay.pos);
+  uint16_t* O = reinterpret_cast<uint16_t*>(smem + lay.O);
+  uint16_t* node_of = reinterpret_cast<uint16_t*>(smem + lay.node_of);
+  uint16_t* segF = reinterpret_cast<uint16_t*>(smem + lay.segF);
+  uint8_t* flag = smem + lay.flag;
 
   __shared__ uint32_t hist[256];
-  __shared__ int sh_c, sh_done, sh_pass, sh_need, sh_cnt, sh_bad;
+  __shared__ int sh_c, sh_done, sh_pass, sh_need, sh_cnt, sh_bad, sh_tie_n;
   __shared__ uint64_t sh_prefix, sh_T;
-  __shared__ int sh_tie_n;
   __shared__ uint32_t tie_pos[256];
   __shared__ int64_t tie_id[256];
 
-  // ---- phase 1: candidate keys into LDS
-  uint64_t* K = reinterpret_cast<uint64_t*>(smem);
-  uint32_t* Pos = reinterpret_cast<uint32_t*>(smem + sizeof(uint64_t) * cap);
+  // ---- phase 1: the s smallest keys
   if (tid == 0) {
     int c;
     if (q.m <= small_max) {
       c = q.m;
     } else {
-      c = static_cast<int>(cand_cnt[sig]);
+      c = static_cast<int>(cand_cnt[static_cast<int64_t>(sig) * kCntStride]);
     }
     sh_c = c;
     sh_bad = 0;
@@ -636,24 +479,6 @@ __global__ void __launch_bounds__(kBlock) k_select_skeleton(const Task* sp, int 
       atomicOr(out.flags, c > cap ? kErrCandOverflow : kErrCandUnderflow);
       sh_bad = 1;
     }
-  }
-  __syncthreads();
-  if (sh_bad) return;
-  const int c = sh_c;
-  if (q.m <= small_max) {
-    for (int i = tid; i < c; i += kBlock) {
-      K[i] = sample_key(seed, q.depth, ids[i]);
-      Pos[i] = static_cast<uint32_t>(i);
-    }
-  } else {
-    const uint64_t* kin = cand_key + static_cast<int64_t>(sig) * cap;
-    const uint32_t* pin = cand_pos + static_cast<int64_t>(sig) * cap;
-    for (int i = tid; i < c; i += kBlock) {
-      K[i] = kin[i];
-      Pos[i] = pin[i];
-    }
-  }
-  if (tid == 0) {
     sh_done = 0;
     sh_pass = 0;
     sh_need = s;
@@ -662,75 +487,109 @@ __global__ void __launch_bounds__(kBlock) k_select_skeleton(const Task* sp, int 
     sh_tie_n = 0;
   }
   __syncthreads();
-  // radix select over the 8 bytes of the key, most significant first
+  if (sh_bad) return;
+  const int c = sh_c;
+  // small subproblems sample from all their points: keys are computed on the fly
+  const bool small = q.m <= small_max;
+  const uint64_t* kin = cand_key + static_cast<int64_t>(sig) * cap;
+  const uint32_t* pin = cand_pos + static_cast<int64_t>(sig) * cap;
   for (int pass = 0; pass < 8; ++pass) {
-    for (int i = tid; i < 256; i += kBlock) hist[i] = 0;
+    for (int i = tid; i < 256; i += NT) hist[i] = 0;
     __syncthreads();
     const int shv = 56 - 8 * pass;
     const uint64_t prefix = sh_prefix;
-    for (int i = tid; i < c; i += kBlock) {
-      uint64_t k = K[i];
-      bool match = pass == 0 || (k >> (64 - 8 * pass)) == prefix;
+    for (int i = tid; i < c; i += NT) {
+      const uint64_t k = small ? sample_key(seed, q.depth, ids[i]) : kin[i];
+      const bool match = pass == 0 || (k >> (64 - 8 * pass)) == prefix;
       if (match) atomicAdd(&hist[(k >> shv) & 255], 1u);
     }
     __syncthreads();
-    if (tid == 0) {
-      int need = sh_need;
-      uint32_t cum = 0;
-      int b = 0;
-      for (; b < 255; ++b) {
-        if (cum + hist[b] >= static_cast<uint32_t>(need)) break;
-        cum += hist[b];
+    if (wave == 0) {
+      // first bin whose inclusive running count reaches `need` (bin 255 if
+      // none); lane l scans bins 4l .. 4l+3
+      const uint32_t need = static_cast<uint32_t>(sh_need);
+      uint32_t h[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) h[j] = hist[4 * lane + j];
+      const uint32_t tot = h[0] + h[1] + h[2] + h[3];
+      uint32_t incl = tot;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
       }
-      if (cum + hist[b] == static_cast<uint32_t>(need)) {
-        sh_done = 1;
-        sh_pass = pass;
-        sh_T = (prefix << 8) | static_cast<uint64_t>(b);
-      } else {
-        sh_need = need - static_cast<int>(cum);
-        sh_prefix = (prefix << 8) | static_cast<uint64_t>(b);
+      const uint32_t excl = incl - tot;
+      int b = -1;
+      uint32_t cum = 0;
+      if (excl < need && incl >= need) {
+        uint32_t run = excl;
+        for (int j = 0; j < 4; ++j) {
+          if (run + h[j] >= need) {
+            b = 4 * lane + j;
+            cum = run;
+            break;
+          }
+          run += h[j];
+        }
+      }
+      const unsigned long long found = __ballot(b >= 0);
+      if (!found && lane == 63) {
+        b = 255;
+        cum = incl - h[3];
+      }
+      if (b >= 0) {
+        const uint32_t hb = hist[b];
+        if (cum + hb == need) {
+          sh_done = 1;
+          sh_pass = pass;
+          sh_T = (prefix << 8) | static_cast<uint64_t>(b);
+        } else {
+          sh_need = static_cast<int>(need - cum);
+          sh_prefix = (prefix << 8) | static_cast<uint64_t>(b);
+        }
       }
     }
     __syncthreads();
     if (sh_done) break;
   }
-  uint16_t* samp = reinterpret_cast<uint16_t*>(smem + (sizeof(uint64_t) + sizeof(uint32_t)) * cap);
   if (sh_done) {
     const int bits = 8 * (sh_pass + 1);
     const uint64_t T = sh_T;
-    for (int i = tid; i < c; i += kBlock) {
-      if ((K[i] >> (64 - bits)) <= T) {
-        int k = atomicAdd(&sh_cnt, 1);
-        if (k < s) samp[k] = static_cast<uint16_t>(i);
+    for (int i = tid; i < c; i += NT) {
+      const uint64_t k = small ? sample_key(seed, q.depth, ids[i]) : kin[i];
+      if ((k >> (64 - bits)) <= T) {
+        const int at = atomicAdd(&sh_cnt, 1);
+        if (at < s) sampPos[at] = small ? static_cast<uint32_t>(i) : pin[i];
       }
     }
   } else {
     // All 64 key bits fixed: sh_prefix is the s-th smallest key K*; take the
     // keys below it and the sh_need smallest ids among those equal to it.
     const uint64_t Ks = sh_prefix;
-    for (int i = tid; i < c; i += kBlock) {
-      if (K[i] < Ks) {
-        int k = atomicAdd(&sh_cnt, 1);
-        if (k < s) samp[k] = static_cast<uint16_t>(i);
-      } else if (K[i] == Ks) {
-        int k = atomicAdd(&sh_tie_n, 1);
-        if (k < 256) {
-          tie_pos[k] = static_cast<uint32_t>(i);
-          tie_id[k] = ids[Pos[i]];
+    for (int i = tid; i < c; i += NT) {
+      const uint64_t k = small ? sample_key(seed, q.depth, ids[i]) : kin[i];
+      const uint32_t pos = small ? static_cast<uint32_t>(i) : pin[i];
+      if (k < Ks) {
+        const int at = atomicAdd(&sh_cnt, 1);
+        if (at < s) sampPos[at] = pos;
+      } else if (k == Ks) {
+        const int at = atomicAdd(&sh_tie_n, 1);
+        if (at < 256) {
+          tie_pos[at] = pos;
+          tie_id[at] = ids[pos];
         }
       }
     }
     __syncthreads();
     if (tid == 0) {
-      int nt = min(sh_tie_n, 256);
+      const int nt = min(sh_tie_n, 256);
       if (sh_tie_n > 256) atomicOr(out.flags, kErrInternal);
       for (int r = 0; r < sh_need; ++r) {
         int best = -1;
         for (int j = 0; j < nt; ++j)
           if (tie_pos[j] != 0xFFFFFFFFu && (best < 0 || tie_id[j] < tie_id[best])) best = j;
         if (best < 0) break;
-        int k = sh_cnt++;
-        if (k < s) samp[k] = static_cast<uint16_t>(tie_pos[best]);
+        const int at = sh_cnt++;
+        if (at < s) sampPos[at] = tie_pos[best];
         tie_pos[best] = 0xFFFFFFFFu;
       }
     }
@@ -740,51 +599,38 @@ __global__ void __launch_bounds__(kBlock) k_select_skeleton(const Task* sp, int 
     if (tid == 0) atomicOr(out.flags, kErrInternal);
     return;
   }
-  // translate candidate slots into positions inside the subproblem
-  uint32_t* sampPos = reinterpret_cast<uint32_t*>(smem + (sizeof(uint64_t) + sizeof(uint32_t)) * cap +
-                                                  sizeof(uint16_t) * s);
-  for (int i = tid; i < s; i += kBlock) sampPos[i] = Pos[samp[i]];
-  __syncthreads();
-  // keep sampPos; the rest of LDS is reused below.  Layout of phase 2:
-  uint32_t sp_copy_reg[kMaxSample / kBlock];
-#pragma unroll
-  for (int k = 0; k < kMaxSample / kBlock; ++k) {
-    const int i = tid + k * kBlock;
-    sp_copy_reg[k] = i < s ? sampPos[i] : 0;
-  }
-  __syncthreads();
 
   // ---- phase 2: skeleton on the sample
-  SkelLayout lay(D, P);
-  uint64_t* key = reinterpret_cast<uint64_t*>(smem + lay.key);
-  uint32_t* C = reinterpret_cast<uint32_t*>(smem + lay.C);
-  uint16_t* O = reinterpret_cast<uint16_t*>(smem + lay.O);
-  uint16_t* Otmp = reinterpret_cast<uint16_t*>(smem + lay.Otmp);
-  uint16_t* node_of = reinterpret_cast<uint16_t*>(smem + lay.node_of);
-  uint16_t* F = reinterpret_cast<uint16_t*>(smem + lay.F);
-  uint8_t* flag = smem + lay.flag;
-  uint8_t* fpos = smem + lay.fpos;
-  __shared__ uint32_t part[kBlock];
   __shared__ uint16_t segA[2 << kMaxLambda], segL[2 << kMaxLambda], segNL[2 << kMaxLambda];
   __shared__ uint8_t live[2 << kMaxLambda], splits[2 << kMaxLambda], sdim[1 << kMaxLambda];
   __shared__ uint32_t sx[1 << kMaxLambda];
-
+  for (int i = tid; i < s; i += NT) {
+    const int64_t pos = q.start + static_cast<int64_t>(sampPos[i]);
 #pragma unroll
-  for (int k = 0; k < kMaxSample / kBlock; ++k) {
-    const int i = tid + k * kBlock;
-    if (i < s) {
-      const int64_t pos = q.start + static_cast<int64_t>(sp_copy_reg[k]);
-      for (int d = 0; d < D; ++d) C[d * P + i] = static_cast<uint32_t>(X[d * xcap + pos]);
-      node_of[i] = 1;
-    }
+    for (int d = 0; d < D; ++d) C[d * P + i] = static_cast<uint32_t>(X[d * xcap + pos]);
+    node_of[i] = 1;
   }
   const int nheap = 2 << lambda;
-  for (int v = tid; v < nheap; v += kBlock) {
+  for (int v = tid; v < nheap; v += NT) {
     live[v] = 0;
     splits[v] = 0;
   }
   __syncthreads();
-  block_presort<D, kBlock, NPL>(C, O, key, s, P);
+  {
+    // wave d: the sample ordered by (coordinate d, index)
+    uint64_t k[NPL];
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int e = lane * NPL + r;
+      k[r] = e < s ? (static_cast<uint64_t>(C[wave * P + e]) << 16) | static_cast<uint64_t>(e) : ~0ULL;
+    }
+    wave_bitonic<NPL>(k);
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int e = lane * NPL + r;
+      if (e < s) O[wave * P + e] = static_cast<uint16_t>(k[r] & 0xFFFF);
+    }
+  }
   if (tid == 0) {
     live[1] = 1;
     segA[1] = 0;
@@ -793,7 +639,7 @@ __global__ void __launch_bounds__(kBlock) k_select_skeleton(const Task* sp, int 
   __syncthreads();
   for (int level = 0; level < lambda; ++level) {
     const int v0 = 1 << level, v1 = 2 << level;
-    for (int v = v0 + tid; v < v1; v += kBlock) {
+    for (int v = v0 + tid; v < v1; v += NT) {
       splits[v] = 0;
       if (!live[v]) continue;
       int d, nl;
@@ -811,14 +657,16 @@ __global__ void __launch_bounds__(kBlock) k_select_skeleton(const Task* sp, int 
       }
     }
     __syncthreads();
-    for (int e = tid; e < s; e += kBlock) {
-      int v = node_of[e];
+    if (level + 1 == lambda) break;   // the orders are not read after the last level
+    for (int e = tid; e < s; e += NT) {
+      const int v = node_of[e];
       flag[e] = splits[v] ? (C[sdim[v] * P + e] < sx[v] ? 1 : 0) : 0;
     }
     __syncthreads();
-    lds_partition<D>(O, Otmp, P, s, node_of, splits, segA, segNL, flag, fpos, F, part);
-    for (int e = tid; e < s; e += kBlock) {
-      int v = node_of[e];
+    wave_partition<NPL>(true, O + wave * P, s, node_of, splits, segA, segNL, flag, segF + wave * (2 << kMaxLambda));
+    __syncthreads();
+    for (int e = tid; e < s; e += NT) {
+      const int v = node_of[e];
       if (splits[v]) node_of[e] = static_cast<uint16_t>(2 * v + (flag[e] ? 0 : 1));
     }
     __syncthreads();
@@ -828,8 +676,8 @@ __global__ void __launch_bounds__(kBlock) k_select_skeleton(const Task* sp, int 
   int64_t* rx = out.rx + static_cast<int64_t>(sig) * NB;
   uint8_t* rd = out.rdim + static_cast<int64_t>(sig) * NB;
   int8_t* ex = out.ext + static_cast<int64_t>(sig) * nheap;
-  for (int v = tid; v < nheap; v += kBlock) {
-    bool interior = v < NB && live[v] && splits[v];
+  for (int v = tid; v < nheap; v += NT) {
+    const bool interior = v < NB && live[v] && splits[v];
     if (v < NB) {
       rx[v] = interior ? static_cast<int64_t>(sx[v]) : kAllLeft;
       rd[v] = interior ? sdim[v] : 0;
@@ -837,7 +685,7 @@ __global__ void __launch_bounds__(kBlock) k_select_skeleton(const Task* sp, int 
     ex[v] = (live[v] && !interior) ? 1 : 0;
   }
   if (tid == 0 && !splits[1]) {
-    int k = atomicAdd(out.n_root_ext, 1);
+    const int k = atomicAdd(out.n_root_ext, 1);
     out.root_ext_list[k] = sig;
   }
 }
@@ -1545,9 +1393,8 @@ int allow_lds(K kernel, size_t bytes) {
 }
 
 template <int D>
-size_t select_lds_bytes(int s, int cap) {
-  size_t ph1 = (sizeof(uint64_t) + sizeof(uint32_t)) * cap + sizeof(uint16_t) * s + sizeof(uint32_t) * s + 64;
-  return std::max(ph1, SkelLayout(D, s).end);
+size_t select_lds_bytes(int s) {
+  return SkelLayout(D, std::max(64, next_pow2(s))).end;
 }
 
 template <int D>
@@ -1724,32 +1571,37 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
     PKD_TRY(rdim.need(static_cast<size_t>(ns) * NB));
     PKD_TRY(ext.need(static_cast<size_t>(ns) * nheap));
     PKD_TRY(rootext.need(ns));
-    PKD_TRY(cand_cnt.need(ns));
+    PKD_TRY(cand_cnt.need(static_cast<size_t>(ns) * kCntStride));
     for (int attempt = 0;; ++attempt) {
       PKD_TRY(sieve_layout(st, sieve.p, ns, tile, W, s, small_max, override_p, &ntiles, &nchunks, &round_pts));
       PKD_TRY(cand_key.need(static_cast<size_t>(ns) * cap));
       PKD_TRY(cand_pos.need(static_cast<size_t>(ns) * cap));
-      PKD_HIP(hipMemsetAsync(cand_cnt.p, 0, sizeof(uint32_t) * ns, st));
-      hipLaunchKernelGGL(k_candidates, dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns,
-                         W.tile_off.p, tile, bufs, src, P.seed, W.shift.p, small_max, cand_key.p, cand_pos.p,
-                         cand_cnt.p, cap);
+      PKD_HIP(hipMemsetAsync(cand_cnt.p, 0, sizeof(uint32_t) * kCntStride * ns, st));
+#define PKD_CAND(ITER)                                                                                            \
+  hipLaunchKernelGGL((k_candidates<ITER>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns, \
+                     W.tile_off.p, bufs, src, P.seed, W.shift.p, small_max, cand_key.p, cand_pos.p, cand_cnt.p, cap)
+      if (tile == 1024) PKD_CAND(4);
+      else if (tile == 2048) PKD_CAND(8);
+      else PKD_CAND(16);
+#undef PKD_CAND
       PKD_TRY(kernel_status("k_candidates"));
       SelectOut so{rx.p, rdim.p, ext.p, rootext.p, d_nrootext, shift_fix.p, d_flags};
       PKD_HIP(hipMemsetAsync(d_nrootext, 0, sizeof(int), st));
-      size_t lds = select_lds_bytes<D>(s, cap);
+      size_t lds = select_lds_bytes<D>(s);
       Prof::begin(kProfSelect, st);
-      const int p2 = next_pow2(s);
+      const int p2 = std::max(64, next_pow2(s));
 #define PKD_SEL(NPL)                                                                                              \
   {                                                                                                               \
     PKD_TRY(allow_lds(k_select_skeleton<D, NPL>, lds));                                                           \
-    hipLaunchKernelGGL((k_select_skeleton<D, NPL>), dim3(ns), dim3(kBlock), lds, st, sieve.p, ns, bufs, src, P.seed, s, \
-                       P.lambda, W.shift.p, small_max, cand_key.p, cand_pos.p, cand_cnt.p, cap, so);              \
+    hipLaunchKernelGGL((k_select_skeleton<D, NPL>), dim3(ns), dim3(64 * D), lds, st, sieve.p, ns, bufs, src, P.seed, \
+                       s, P.lambda, W.shift.p, small_max, cand_key.p, cand_pos.p, cand_cnt.p, cap, so);           \
   }
-      if (p2 <= 256) PKD_SEL(1)
-      else if (p2 <= 512) PKD_SEL(2)
-      else if (p2 <= 1024) PKD_SEL(4)
-      else if (p2 <= 2048) PKD_SEL(8)
-      else PKD_SEL(16)
+      if (p2 <= 64) PKD_SEL(1)
+      else if (p2 <= 128) PKD_SEL(2)
+      else if (p2 <= 256) PKD_SEL(4)
+      else if (p2 <= 512) PKD_SEL(8)
+      else if (p2 <= 1024) PKD_SEL(16)
+      else PKD_SEL(32)
 #undef PKD_SEL
       Prof::end(kProfSelect, st, 0.0);
       PKD_TRY(kernel_status("k_select_skeleton"));
