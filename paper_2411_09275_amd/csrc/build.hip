@@ -867,12 +867,15 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
   const unsigned long long lt = (1ULL << lane) - 1;
   // coordinates were range-checked before this pass: 30-bit values fit 32 bits
   uint32_t val[PPT][D];
+  int64_t idv[PPT];   // ids are loaded with the coordinates so all loads are in flight together
   int lab[PPT];
   int rank[PPT];
+  const int64_t* Iin = bufs.id[src];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int li = k * kBlock + tid;
     const bool ok = li < len;
+    idv[k] = ok ? Iin[lo + li] : 0;
     int label = 0;
     if (ok) {
       int64_t c[D];
@@ -928,14 +931,12 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
   __syncthreads();
   int64_t* Y = bufs.c[dst];
   const int64_t ycap = bufs.cap[dst];
-  const int64_t* Iin = bufs.id[src];
   int64_t* Iout = bufs.id[dst];
 #pragma unroll
   for (int a = 0; a <= D; ++a) {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      if (lpos[k] >= 0)
-        stage[lpos[k]] = a < D ? static_cast<int64_t>(val[k][a < D ? a : 0]) : Iin[lo + k * kBlock + tid];
+      if (lpos[k] >= 0) stage[lpos[k]] = a < D ? static_cast<int64_t>(val[k][a < D ? a : 0]) : idv[k];
     }
     __syncthreads();
     int64_t* out = a < D ? Y + a * ycap : Iout;

@@ -25,6 +25,11 @@ __device__ inline bool pair_less(int64_t d2, int64_t id, int64_t cd2, int64_t ci
 // lower bound of its subspace (squared distance from q to the cell, updated
 // incrementally in the split dimension) and skipped when that bound exceeds
 // the current k-th distance (strictly: an equal distance may still win on id).
+// The lanes of a wave alternate between two loops: every lane descends until
+// it holds a leaf (or has nothing left), then all scan their leaves together,
+// so a leaf scan is paid once per round rather than once per node step.
+// Coordinates lie in [0, 2^30): differences fit 32 bits and only the low word
+// of each stored coordinate is read.
 template <int D, int KM, int SD>
 __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes, const int64_t* __restrict__ X,
                                                  int64_t cap, const int64_t* __restrict__ ids,
@@ -35,12 +40,13 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
   const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
   if (j0 >= nq) return;
   const int64_t j = perm ? static_cast<int64_t>(perm[j0]) : j0;   // lanes of a wave take nearby queries
-  int64_t q[D];
+  int32_t q[D];
   bool bad = false;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    q[d] = Qry[d * nq + j];
-    bad |= static_cast<uint64_t>(q[d]) >= static_cast<uint64_t>(kCoordLimit);
+    const int64_t v = Qry[d * nq + j];
+    bad |= static_cast<uint64_t>(v) >= static_cast<uint64_t>(kCoordLimit);
+    q[d] = static_cast<int32_t>(v);
   }
   if (bad) {
     atomicOr(flags, kErrRange);
@@ -65,64 +71,64 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
     atomicOr(flags, kErrInternal);
     return;
   }
+  const int32_t* X32 = reinterpret_cast<const int32_t*>(X);   // low words (little-endian)
   // a node is stacked at most once per level of the current path, so a valid
   // tree never needs more than its height
   Ent stk[SD];
-  stk[0].node = root;
-  stk[0].lb = 0;
+  int sp = 0;
+  int32_t node = root;      // node being descended, -1: take the next stacked one
+  int64_t lb = 0;
+  int32_t off[D];
 #pragma unroll
-  for (int d = 0; d < D; ++d) stk[0].off[d] = 0;
-  int sp = 1;
+  for (int d = 0; d < D; ++d) off[d] = 0;
+  int32_t leaf_off = 0, leaf_size = 0;
+  bool have_leaf = false, done = false;
+  int fail_bits = 0;
   int32_t visits = 0;
-  while (sp > 0) {
-    --sp;
-    int32_t node = stk[sp].node;
-    int64_t lb = stk[sp].lb;
-    int32_t off[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) off[d] = stk[sp].off[d];
-    if (lb > bd[KM - 1]) continue;
+  while (true) {
+    // descend: one pop or one node step per iteration, until every lane holds
+    // a leaf or is finished
+#pragma unroll 1
     while (true) {
+      const bool want = !done && !have_leaf;
+      if (__ballot(want) == 0) break;
+      if (!want) continue;
+      if (node < 0) {
+        if (sp == 0) {
+          done = true;
+          continue;
+        }
+        --sp;
+        node = stk[sp].node;
+        lb = stk[sp].lb;
+#pragma unroll
+        for (int d = 0; d < D; ++d) off[d] = stk[sp].off[d];
+        if (lb > bd[KM - 1]) {
+          node = -1;
+          continue;
+        }
+      }
       // the links of a valid tree stay inside the node array and a traversal
       // visits every node at most once: anything else stops this lane
       if (static_cast<uint32_t>(node) >= static_cast<uint32_t>(n_nodes) || ++visits > n_nodes) {
-        atomicOr(flags, kErrInternal);
-        return;
+        fail_bits = kErrInternal;
+        done = true;
+        continue;
       }
       const Node nd = nodes[node];
       if (nd.left < 0) {
-        const int64_t e = static_cast<int64_t>(nd.off) + nd.size;
-        if (nd.off < 0 || nd.size < 0 || e > n_pts) {
-          atomicOr(flags, kErrInternal);
-          return;
+        if (nd.off < 0 || nd.size < 0 || static_cast<int64_t>(nd.off) + nd.size > n_pts) {
+          fail_bits = kErrInternal;
+          done = true;
+          continue;
         }
-        for (int64_t i = nd.off; i < e; ++i) {
-          int64_t d2 = 0;
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-            const int64_t diff = X[d * cap + i] - q[d];
-            d2 += diff * diff;
-          }
-          if (d2 <= bd[KM - 1]) {
-            const int64_t id = ids[i];
-            if (pair_less(d2, id, bd[KM - 1], bi[KM - 1])) {
-#pragma unroll
-              for (int t = KM - 1; t > 0; --t) {
-                const bool shift = pair_less(d2, id, bd[t - 1], bi[t - 1]);
-                const bool here = !shift && pair_less(d2, id, bd[t], bi[t]);
-                bd[t] = shift ? bd[t - 1] : (here ? d2 : bd[t]);
-                bi[t] = shift ? bi[t - 1] : (here ? id : bi[t]);
-              }
-              const bool first = pair_less(d2, id, bd[0], bi[0]);
-              bd[0] = first ? d2 : bd[0];
-              bi[0] = first ? id : bi[0];
-            }
-          }
-        }
-        break;
+        leaf_off = nd.off;
+        leaf_size = nd.size;
+        have_leaf = true;
+        node = -1;
+        continue;
       }
-      int64_t qd = q[0];
-      int32_t od = off[0];
+      int32_t qd = q[0], od = off[0];
 #pragma unroll
       for (int d = 1; d < D; ++d) {
         qd = (nd.dim == d) ? q[d] : qd;
@@ -131,12 +137,15 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
       const bool go_left = qd < nd.x;
       const int32_t near = go_left ? nd.left : nd.right;
       const int32_t far = go_left ? nd.right : nd.left;
-      const int64_t fo = go_left ? nd.x - qd : qd - nd.x + 1;   // distance to the far cell in this dim
+      // distance to the far cell in this dimension (the splitter is a stored
+      // coordinate, so it fits 32 bits)
+      const int64_t fo = go_left ? nd.x - qd : static_cast<int64_t>(qd) - nd.x + 1;
       const int64_t flb = lb - static_cast<int64_t>(od) * od + fo * fo;
       if (flb <= bd[KM - 1]) {
         if (sp >= SD) {
-          atomicOr(flags, kErrStack);
-          return;
+          fail_bits = kErrStack;
+          done = true;
+          continue;
         }
         stk[sp].node = far;
         stk[sp].lb = flb;
@@ -146,6 +155,54 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
       }
       node = near;
     }
+    if (__ballot(have_leaf) == 0) break;
+    if (have_leaf) {
+      const int64_t e = static_cast<int64_t>(leaf_off) + leaf_size;
+#pragma unroll 1
+      for (int64_t i = leaf_off; i < e; ++i) {
+        int64_t d2 = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const int32_t diff = X32[2 * (d * cap + i)] - q[d];
+          d2 += static_cast<int64_t>(diff) * diff;
+        }
+        if (d2 <= bd[KM - 1]) {
+          const int64_t id = ids[i];
+          if (pair_less(d2, id, bd[KM - 1], bi[KM - 1])) {
+            if constexpr (KM <= 16) {
+              // short lists: drop the worst, then bubble the new pair down
+              bd[KM - 1] = d2;
+              bi[KM - 1] = id;
+#pragma unroll
+              for (int t = KM - 1; t > 0; --t) {
+                const bool sw = pair_less(bd[t], bi[t], bd[t - 1], bi[t - 1]);
+                const int64_t x0 = bd[t - 1], y0 = bi[t - 1];
+                bd[t - 1] = sw ? bd[t] : x0;
+                bi[t - 1] = sw ? bi[t] : y0;
+                bd[t] = sw ? x0 : bd[t];
+                bi[t] = sw ? y0 : bi[t];
+              }
+              continue;
+            }
+#pragma unroll
+            for (int t = KM - 1; t > 0; --t) {
+              const bool shift = pair_less(d2, id, bd[t - 1], bi[t - 1]);
+              const bool here = !shift && pair_less(d2, id, bd[t], bi[t]);
+              bd[t] = shift ? bd[t - 1] : (here ? d2 : bd[t]);
+              bi[t] = shift ? bi[t - 1] : (here ? id : bi[t]);
+            }
+            const bool first = pair_less(d2, id, bd[0], bi[0]);
+            bd[0] = first ? d2 : bd[0];
+            bi[0] = first ? id : bi[0];
+          }
+        }
+      }
+      have_leaf = false;
+    }
+  }
+  if (fail_bits) {
+    atomicOr(flags, fail_bits);
+    return;
   }
   for (int i = 0; i < k; ++i) {
     // slot KM-k+i holds the i-th nearest; unfilled slots are +inf
@@ -162,7 +219,9 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
 }
 
 // Range count: a node whose cell lies inside the box contributes its stored
-// subtree size; a disjoint cell contributes nothing; leaves are scanned.
+// subtree size; a disjoint cell contributes nothing; leaves are scanned.  As
+// in k-NN, the lanes descend until each holds a leaf that straddles its box,
+// then scan those leaves together.
 template <int D, int SD>
 __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ nodes, const int64_t* __restrict__ X,
                                                    int64_t cap, const int64_t* __restrict__ Lo,
@@ -172,36 +231,36 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
   const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
   if (j0 >= nb) return;
   const int64_t j = perm ? static_cast<int64_t>(perm[j0]) : j0;
-  int64_t lo[D], hi[D];
+  int32_t lo[D], hi[D];
   bool bad = false, none = false;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    lo[d] = Lo[d * nb + j];
-    hi[d] = Hi[d * nb + j];
-    bad |= static_cast<uint64_t>(lo[d]) >= static_cast<uint64_t>(kCoordLimit);
-    bad |= static_cast<uint64_t>(hi[d]) >= static_cast<uint64_t>(kCoordLimit);
-    none |= lo[d] > hi[d];
+    const int64_t l = Lo[d * nb + j], h = Hi[d * nb + j];
+    bad |= static_cast<uint64_t>(l) >= static_cast<uint64_t>(kCoordLimit);
+    bad |= static_cast<uint64_t>(h) >= static_cast<uint64_t>(kCoordLimit);
+    none |= l > h;
+    lo[d] = static_cast<int32_t>(l);
+    hi[d] = static_cast<int32_t>(h);
   }
   if (bad) {
     atomicOr(flags, kErrRange);
     return;
   }
-  int64_t count = 0;
-  struct Ent {
-    int32_t node;
-    int32_t depth;
-    int32_t clo[D], chi[D];
-  };
-  Ent stk[SD];
-  int sp = 0;
   const int32_t root = tree_of ? tree_of[j] : 0;
   if (static_cast<uint32_t>(root) >= static_cast<uint32_t>(n_trees)) {
     atomicOr(flags, kErrInternal);
     return;
   }
+  const int32_t* X32 = reinterpret_cast<const int32_t*>(X);   // low words (little-endian)
+  int64_t count = 0;
+  struct Ent {
+    int32_t node;
+    int32_t clo[D], chi[D];
+  };
+  Ent stk[SD];
+  int sp = 0;
   if (!none) {
     stk[0].node = root;
-    stk[0].depth = 0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       stk[0].clo[d] = 0;
@@ -209,66 +268,92 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
     }
     sp = 1;
   }
-  while (sp > 0) {
-    --sp;
-    const int32_t node = stk[sp].node;
-    const int32_t depth = stk[sp].depth;
-    if (static_cast<uint32_t>(node) >= static_cast<uint32_t>(n_nodes) || depth >= SD) {
-      atomicOr(flags, kErrInternal);
-      return;
-    }
-    int32_t clo[D], chi[D];
-    bool inside = true, disjoint = false;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      clo[d] = stk[sp].clo[d];
-      chi[d] = stk[sp].chi[d];
-      disjoint |= chi[d] < lo[d] || clo[d] > hi[d];
-      inside &= clo[d] >= lo[d] && chi[d] <= hi[d];
-    }
-    if (disjoint) continue;
-    const Node nd = nodes[node];
-    if (inside) {
-      count += nd.size;
-      continue;
-    }
-    if (nd.left < 0) {
-      if (nd.off < 0 || nd.size < 0 || static_cast<int64_t>(nd.off) + nd.size > n_pts) {
-        atomicOr(flags, kErrInternal);
-        return;
+  int32_t leaf_off = 0, leaf_size = 0;
+  bool have_leaf = false, done = false;
+  int fail_bits = 0;
+  int32_t visits = 0;
+  while (true) {
+#pragma unroll 1
+    while (true) {
+      const bool want = !done && !have_leaf;
+      if (__ballot(want) == 0) break;
+      if (!want) continue;
+      if (sp == 0) {
+        done = true;
+        continue;
       }
+      --sp;
+      const int32_t node = stk[sp].node;
+      if (static_cast<uint32_t>(node) >= static_cast<uint32_t>(n_nodes) || ++visits > n_nodes) {
+        fail_bits = kErrInternal;
+        done = true;
+        continue;
+      }
+      int32_t clo[D], chi[D];
+      bool inside = true, disjoint = false;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        clo[d] = stk[sp].clo[d];
+        chi[d] = stk[sp].chi[d];
+        disjoint |= chi[d] < lo[d] || clo[d] > hi[d];
+        inside &= clo[d] >= lo[d] && chi[d] <= hi[d];
+      }
+      if (disjoint) continue;
+      const Node nd = nodes[node];
+      if (inside) {
+        count += nd.size;
+        continue;
+      }
+      if (nd.left < 0) {
+        if (nd.off < 0 || nd.size < 0 || static_cast<int64_t>(nd.off) + nd.size > n_pts) {
+          fail_bits = kErrInternal;
+          done = true;
+          continue;
+        }
+        leaf_off = nd.off;
+        leaf_size = nd.size;
+        have_leaf = true;
+        continue;
+      }
+      if (sp + 2 > SD) {
+        fail_bits = kErrStack;
+        done = true;
+        continue;
+      }
+      // right child: lo[dim] = x; left child: hi[dim] = x - 1
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        stk[sp].clo[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x) : clo[d];
+        stk[sp].chi[d] = chi[d];
+        stk[sp + 1].clo[d] = clo[d];
+        stk[sp + 1].chi[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x - 1) : chi[d];
+      }
+      stk[sp].node = nd.right;
+      stk[sp + 1].node = nd.left;
+      sp += 2;
+    }
+    if (__ballot(have_leaf) == 0) break;
+    if (have_leaf) {
       // a leaf larger than phi holds identical points: test one of them
-      const int64_t e = nd.size > phi ? static_cast<int64_t>(nd.off) + 1 : static_cast<int64_t>(nd.off) + nd.size;
+      const int64_t e = leaf_size > phi ? static_cast<int64_t>(leaf_off) + 1 : static_cast<int64_t>(leaf_off) + leaf_size;
       int64_t c = 0;
-      for (int64_t i = nd.off; i < e; ++i) {
+#pragma unroll 1
+      for (int64_t i = leaf_off; i < e; ++i) {
         bool in = true;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          const int64_t v = X[d * cap + i];
+          const int32_t v = X32[2 * (d * cap + i)];
           in &= v >= lo[d] && v <= hi[d];
         }
         c += in ? 1 : 0;
       }
-      count += nd.size > phi ? c * nd.size : c;
-      continue;
+      count += leaf_size > phi ? c * leaf_size : c;
+      have_leaf = false;
     }
-    if (sp + 2 > SD) {
-      atomicOr(flags, kErrStack);
-      return;
-    }
-    // right child: lo[dim] = x; left child: hi[dim] = x - 1
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      stk[sp].clo[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x) : clo[d];
-      stk[sp].chi[d] = chi[d];
-      stk[sp + 1].clo[d] = clo[d];
-      stk[sp + 1].chi[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x - 1) : chi[d];
-    }
-    stk[sp].node = nd.right;
-    stk[sp + 1].node = nd.left;
-    stk[sp].depth = depth + 1;
-    stk[sp + 1].depth = depth + 1;
-    sp += 2;
+  }
+  if (fail_bits) {
+    atomicOr(flags, fail_bits);
+    return;
   }
   out[j] = count;
 }
