@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=1_000_000, help="points per BatchInsert / BatchDelete (updates)")
     ap.add_argument("--trees", type=int, default=4096)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-single", action="store_true", help="batching: skip the one-call-per-tree comparison")
+    ap.add_argument("--params", default=None, help="batching: fixed lambda,sigma,phi,tile instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 2 GiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -142,6 +144,10 @@ def bench_batching(a):
 
     params = {}
     for D, gr in groups.items():
+        if a.params:
+            lam, sigma, phi, tile = (int(x) for x in a.params.split(","))
+            params[D] = (pk.Params(D, lam=lam, sigma=sigma, phi=phi), tile)
+            continue
         if a.no_autotune:
             params[D] = (pk.Params(D), 2048)
             continue
@@ -150,8 +156,12 @@ def bench_batching(a):
         o = gr["off"][: nt + 1]
         cs = gr["c"][:, : int(o[-1])].contiguous()
         is_ = gr["i"][: int(o[-1])].contiguous()
-        qs = gr["byk"][10][1][:, : nt * 80].contiguous()
-        p, tile, sec = autotune.tune(D, cs, is_, offsets=o, queries=qs, k=10, log=log)
+        # the sample's own query mix: every k, the queries of its trees
+        mix = []
+        for k, (idx, qk, tk) in gr["byk"].items():
+            mine = torch.nonzero(tk < nt).flatten()
+            mix.append((qk[:, mine].contiguous(), k, tk[mine].contiguous()))
+        p, tile, sec = autotune.tune(D, cs, is_, offsets=o, queries=mix, log=log)
         params[D] = (p, tile)
         log("autotuned D=%d: lambda=%d sigma=%d phi=%d tile=%d" % (D, p.lam, p.sigma, p.phi, tile))
 
@@ -175,6 +185,10 @@ def bench_batching(a):
     t_batched = (time.perf_counter() - t0) / a.steps
     log("batched: %.1f ms per pass" % (t_batched * 1e3))
 
+    if a.no_single:
+        print(json.dumps({"metric": "batched build + k-NN over many trees", "batched_ms": round(t_batched * 1e3, 3),
+                          "points": n_total}))
+        return
     # one build and one query call per tree (same parameters); the per-tree
     # query selections are made before the timed region, the result checks after
     per_tree = []

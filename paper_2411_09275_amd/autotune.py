@@ -56,24 +56,34 @@ def tune(dim, coords, ids, offsets=None, queries=None, k=10, grid=None, cache=DE
 
     coords/ids: device or host int64 points of the sample (one tree, or many
     trees back to back with host `offsets`); queries: optional [dim, nq]
-    (with offsets, query j goes to tree j % n_trees).
-    Returns (Params, tile, seconds of the best setting)."""
+    (with offsets, query j goes to tree j % n_trees), or a list of
+    (queries, k, tree_of) triples that together make the sample's query mix
+    (tree_of may be None).  Returns (Params, tile, seconds of the best
+    setting)."""
     import numpy as np
     import torch
 
     grid = grid or GRID
     n_points = int(ids.shape[0])
     key = _key(dim, n_points)
+    if isinstance(queries, (list, tuple)):
+        key += "|k=" + ",".join(str(kk) for _, kk, _ in queries)
     if not force and cache and os.path.exists(cache):
         with open(cache) as f:
             stored = json.load(f)
         if key in stored:
             c = stored[key]
             return Params(dim, lam=c["lam"], phi=c["phi"], sigma=c["sigma"]), c["tile"], c["seconds"]
-    tree_of = None
-    if offsets is not None and queries is not None:
-        nt = len(offsets) - 1
-        tree_of = torch.from_numpy((np.arange(queries.shape[1]) % nt).astype(np.int32)).cuda()
+    if queries is None:
+        mix = []
+    elif isinstance(queries, (list, tuple)):
+        mix = list(queries)
+    else:
+        tree_of = None
+        if offsets is not None:
+            nt = len(offsets) - 1
+            tree_of = torch.from_numpy((np.arange(queries.shape[1]) % nt).astype(np.int32)).cuda()
+        mix = [(queries, k, tree_of)]
     best = None
     for lam, sigma, phi, tile in itertools.product(grid["lam"], grid["sigma"], grid["phi"], grid["tile"]):
         if (sigma << lam) > 2048:   # the library caps the sample at 2048
@@ -82,8 +92,8 @@ def tune(dim, coords, ids, offsets=None, queries=None, k=10, grid=None, cache=DE
 
         def run():
             t = Tree(p, coords, ids, tile=tile) if offsets is None else Tree.batch(p, coords, ids, offsets, tile=tile)
-            if queries is not None:
-                t.knn(queries, k, tree_of=tree_of)
+            for qq, kk, to in mix:
+                t.knn(qq, kk, tree_of=to)
             t.free()
 
         sec = _time(run)

@@ -3,6 +3,9 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "pkd_internal.h"
@@ -23,39 +26,101 @@ int hip_status(hipError_t e, const char* what) {
 }
 
 namespace {
-int g_pool_mode = -1;   // 1: stream-ordered pool allocations, 0: plain hipMalloc
+// Device memory cache.  Builds and updates allocate and free large scratch
+// arrays on every call; a tree's buffers come and go with the tree.  Freed
+// blocks are kept per size class (sizes rounded up by at most 1/8) with an
+// event recorded on the freeing stream: a later request of the same class
+// takes the block back (on another stream it first waits for that event),
+// so steady-state calls map no new memory.  The cache holds at most a quarter
+// of device memory; beyond that the oldest blocks are returned.
+struct Cached {
+  void* p;
+  hipStream_t st;
+  hipEvent_t ev;
+  uint64_t age;
+};
 
-void init_pool() {
-  if (g_pool_mode >= 0) return;
-  int dev = 0, ok = 0;
-  g_pool_mode = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return;
-  if (hipDeviceGetAttribute(&ok, hipDeviceAttributeMemoryPoolsSupported, dev) != hipSuccess || !ok) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
-  // keep freed blocks in the pool: repeated builds reuse them without remapping
-  uint64_t keep = UINT64_MAX;
-  (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-  g_pool_mode = 1;
+std::mutex g_mu;
+std::multimap<size_t, Cached> g_free;        // size class -> freed blocks
+std::unordered_map<void*, size_t> g_size;    // live and cached blocks -> size class
+size_t g_cached = 0, g_limit = 0;
+uint64_t g_clock = 0;
+
+size_t size_class(size_t b) {
+  if (b <= 4096) return 4096;
+  const int lg = 63 - __builtin_clzll(static_cast<unsigned long long>(b));
+  const size_t unit = size_t{1} << (lg - 3);
+  return (b + unit - 1) / unit * unit;
+}
+
+// Returns one cached block to the device (caller holds g_mu).
+void evict(std::multimap<size_t, Cached>::iterator it) {
+  (void)hipEventSynchronize(it->second.ev);
+  (void)hipEventDestroy(it->second.ev);
+  (void)hipFree(it->second.p);
+  g_size.erase(it->second.p);
+  g_cached -= it->first;
+  g_free.erase(it);
+}
+
+void evict_oldest_until(size_t limit) {
+  while (g_cached > limit && !g_free.empty()) {
+    auto old = g_free.begin();
+    for (auto it = g_free.begin(); it != g_free.end(); ++it)
+      if (it->second.age < old->second.age) old = it;
+    evict(old);
+  }
 }
 }  // namespace
 
 int dev_alloc(void** p, size_t bytes, hipStream_t s) {
-  init_pool();
   *p = nullptr;
-  if (bytes == 0) bytes = 8;
-  hipError_t e = g_pool_mode == 1 ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
+  const size_t cls = size_class(bytes);
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (g_limit == 0) {
+    size_t free_b = 0, total_b = 0;
+    g_limit = hipMemGetInfo(&free_b, &total_b) == hipSuccess && total_b > 0 ? total_b / 4 : (size_t{8} << 30);
+  }
+  auto range = g_free.equal_range(cls);
+  for (auto it = range.first; it != range.second; ++it) {
+    if (it->second.st != s && hipStreamWaitEvent(s, it->second.ev, 0) != hipSuccess) continue;
+    *p = it->second.p;
+    (void)hipEventDestroy(it->second.ev);
+    g_cached -= cls;
+    g_free.erase(it);
+    return PKD_OK;
+  }
+  hipError_t e = hipMalloc(p, cls);
+  if (e != hipSuccess) {
+    // out of memory: return every cached block and try once more
+    (void)hipGetLastError();
+    evict_oldest_until(0);
+    e = hipMalloc(p, cls);
+  }
   if (e != hipSuccess) {
     *p = nullptr;
     return hip_status(e, "device allocation");
   }
+  g_size[*p] = cls;
   return PKD_OK;
 }
 
 void dev_free(void* p, hipStream_t s) {
   if (!p) return;
-  if (g_pool_mode == 1) (void)hipFreeAsync(p, s);
-  else (void)hipFree(p);
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto sz = g_size.find(p);
+  if (sz == g_size.end()) return;
+  hipEvent_t ev;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, s) != hipSuccess) {
+    // cannot order a reuse after the last use: wait and return the block
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(p);
+    g_size.erase(sz);
+    return;
+  }
+  g_free.emplace(sz->second, Cached{p, s, ev, ++g_clock});
+  g_cached += sz->second;
+  evict_oldest_until(g_limit);
 }
 
 // ---- kernel timing -------------------------------------------------------

@@ -52,11 +52,26 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
     atomicOr(flags, kErrRange);
     return;
   }
-  int64_t bd[KM], bi[KM];
+  // KM > 0: the k best pairs sorted in registers (slots 0..KM-k-1 hold
+  // sentinels smaller than any pair).  KM == 0 (k > 16): a binary max-heap of
+  // the k best pairs kept in the query's own output row, root = the worst.
+  constexpr int KR = KM > 0 ? KM : 1;
+  int64_t bd[KR], bi[KR];
+  int64_t* Hd = out_d2 + j * k;
+  int64_t* Hi = out_ids + j * k;
+  if constexpr (KM > 0) {
 #pragma unroll
-  for (int i = 0; i < KM; ++i) {
-    bd[i] = (i < KM - k) ? -1 : INT64_MAX;
-    bi[i] = (i < KM - k) ? INT64_MIN : INT64_MAX;
+    for (int i = 0; i < KM; ++i) {
+      bd[i] = (i < KM - k) ? -1 : INT64_MAX;
+      bi[i] = (i < KM - k) ? INT64_MIN : INT64_MAX;
+    }
+  } else {
+    for (int i = 0; i < k; ++i) {
+      Hd[i] = INT64_MAX;
+      Hi[i] = INT64_MAX;
+    }
+    bd[0] = INT64_MAX;   // the root (k-th best so far)
+    bi[0] = INT64_MAX;
   }
 
   struct Ent {
@@ -103,7 +118,7 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
         lb = stk[sp].lb;
 #pragma unroll
         for (int d = 0; d < D; ++d) off[d] = stk[sp].off[d];
-        if (lb > bd[KM - 1]) {
+        if (lb > bd[KR - 1]) {
           node = -1;
           continue;
         }
@@ -141,7 +156,7 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
       // coordinate, so it fits 32 bits)
       const int64_t fo = go_left ? nd.x - qd : static_cast<int64_t>(qd) - nd.x + 1;
       const int64_t flb = lb - static_cast<int64_t>(od) * od + fo * fo;
-      if (flb <= bd[KM - 1]) {
+      if (flb <= bd[KR - 1]) {
         if (sp >= SD) {
           fail_bits = kErrStack;
           done = true;
@@ -166,15 +181,41 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
           const int32_t diff = X32[2 * (d * cap + i)] - q[d];
           d2 += static_cast<int64_t>(diff) * diff;
         }
-        if (d2 <= bd[KM - 1]) {
+        if (d2 <= bd[KR - 1]) {
           const int64_t id = ids[i];
-          if (pair_less(d2, id, bd[KM - 1], bi[KM - 1])) {
-            if constexpr (KM <= 16) {
+          if (pair_less(d2, id, bd[KR - 1], bi[KR - 1])) {
+            if constexpr (KM == 0) {
+              // replace the root and sift the new pair down
+              int p = 0;
+              while (true) {
+                int c = 2 * p + 1;
+                if (c >= k) break;
+                int64_t cd = Hd[c], ci = Hi[c];
+                if (c + 1 < k) {
+                  const int64_t rd = Hd[c + 1], ri = Hi[c + 1];
+                  if (pair_less(cd, ci, rd, ri)) {
+                    c = c + 1;
+                    cd = rd;
+                    ci = ri;
+                  }
+                }
+                if (!pair_less(d2, id, cd, ci)) break;
+                Hd[p] = cd;
+                Hi[p] = ci;
+                p = c;
+              }
+              Hd[p] = d2;
+              Hi[p] = id;
+              bd[0] = Hd[0];
+              bi[0] = Hi[0];
+              continue;
+            }
+            if constexpr (KM > 0 && KM <= 16) {
               // short lists: drop the worst, then bubble the new pair down
-              bd[KM - 1] = d2;
-              bi[KM - 1] = id;
+              bd[KR - 1] = d2;
+              bi[KR - 1] = id;
 #pragma unroll
-              for (int t = KM - 1; t > 0; --t) {
+              for (int t = KR - 1; t > 0; --t) {
                 const bool sw = pair_less(bd[t], bi[t], bd[t - 1], bi[t - 1]);
                 const int64_t x0 = bd[t - 1], y0 = bi[t - 1];
                 bd[t - 1] = sw ? bd[t] : x0;
@@ -185,7 +226,7 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
               continue;
             }
 #pragma unroll
-            for (int t = KM - 1; t > 0; --t) {
+            for (int t = KR - 1; t > 0; --t) {
               const bool shift = pair_less(d2, id, bd[t - 1], bi[t - 1]);
               const bool here = !shift && pair_less(d2, id, bd[t], bi[t]);
               bd[t] = shift ? bd[t - 1] : (here ? d2 : bd[t]);
@@ -204,17 +245,53 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
     atomicOr(flags, fail_bits);
     return;
   }
-  for (int i = 0; i < k; ++i) {
-    // slot KM-k+i holds the i-th nearest; unfilled slots are +inf
-    int64_t cd = bd[0], ci = bi[0];
-#pragma unroll
-    for (int t = 1; t < KM; ++t) {
-      cd = (t == KM - k + i) ? bd[t] : cd;
-      ci = (t == KM - k + i) ? bi[t] : ci;
+  if constexpr (KM == 0) {
+    // heapsort in place: ascending pairs, unfilled slots (+inf) last
+    for (int end = k - 1; end > 0; --end) {
+      const int64_t td = Hd[0], ti = Hi[0];
+      const int64_t xd = Hd[end], xi = Hi[end];
+      Hd[end] = td;
+      Hi[end] = ti;
+      int p = 0;
+      while (true) {
+        int c = 2 * p + 1;
+        if (c >= end) break;
+        int64_t cd = Hd[c], ci = Hi[c];
+        if (c + 1 < end) {
+          const int64_t rd = Hd[c + 1], ri = Hi[c + 1];
+          if (pair_less(cd, ci, rd, ri)) {
+            c = c + 1;
+            cd = rd;
+            ci = ri;
+          }
+        }
+        if (!pair_less(xd, xi, cd, ci)) break;
+        Hd[p] = cd;
+        Hi[p] = ci;
+        p = c;
+      }
+      Hd[p] = xd;
+      Hi[p] = xi;
     }
-    const bool have = cd != INT64_MAX;
-    out_d2[j * k + i] = have ? cd : -1;
-    out_ids[j * k + i] = have ? ci : -1;
+    for (int i = 0; i < k; ++i) {
+      if (Hd[i] == INT64_MAX) {
+        Hd[i] = -1;
+        Hi[i] = -1;
+      }
+    }
+  } else {
+    for (int i = 0; i < k; ++i) {
+      // slot KM-k+i holds the i-th nearest; unfilled slots are +inf
+      int64_t cd = bd[0], ci = bi[0];
+#pragma unroll
+      for (int t = 1; t < KM; ++t) {
+        cd = (t == KM - k + i) ? bd[t] : cd;
+        ci = (t == KM - k + i) ? bi[t] : ci;
+      }
+      const bool have = cd != INT64_MAX;
+      out_d2[j * k + i] = have ? cd : -1;
+      out_ids[j * k + i] = have ? ci : -1;
+    }
   }
 }
 
@@ -522,9 +599,8 @@ void launch_knn(int km, dim3 g, hipStream_t st, const Node* nodes, const int64_t
     PKD_KNN_CASE(4)
     PKD_KNN_CASE(8)
     PKD_KNN_CASE(16)
-    PKD_KNN_CASE(32)
-    PKD_KNN_CASE(64)
-    PKD_KNN_CASE(128)
+    default:
+      PKD_KNN_CASE(0)
   }
 #undef PKD_KNN_CASE
 }
