@@ -31,8 +31,9 @@ namespace {
 // blocks are kept per size class (sizes rounded up by at most 1/8) with an
 // event recorded on the freeing stream: a later request of the same class
 // takes the block back (on another stream it first waits for that event),
-// so steady-state calls map no new memory.  The cache holds at most a quarter
-// of device memory; beyond that the oldest blocks are returned.
+// so steady-state calls map no new memory (mapping runs at a few tens of GB/s,
+// so a fresh tree-sized block costs seconds at 1e9 points).  The cache holds
+// at most half of device memory; beyond that the oldest blocks are returned.
 struct Cached {
   void* p;
   hipStream_t st;
@@ -46,13 +47,16 @@ std::unordered_map<void*, size_t> g_size;    // live and cached blocks -> size c
 size_t g_cached = 0, g_limit = 0;
 uint64_t g_clock = 0;
 
-size_t size_class(size_t b) {
+}  // namespace
+
+size_t dev_size_class(size_t b) {
   if (b <= 4096) return 4096;
   const int lg = 63 - __builtin_clzll(static_cast<unsigned long long>(b));
   const size_t unit = size_t{1} << (lg - 3);
   return (b + unit - 1) / unit * unit;
 }
 
+namespace {
 // Returns one cached block to the device (caller holds g_mu).
 void evict(std::multimap<size_t, Cached>::iterator it) {
   (void)hipEventSynchronize(it->second.ev);
@@ -75,11 +79,11 @@ void evict_oldest_until(size_t limit) {
 
 int dev_alloc(void** p, size_t bytes, hipStream_t s) {
   *p = nullptr;
-  const size_t cls = size_class(bytes);
+  const size_t cls = dev_size_class(bytes);
   std::lock_guard<std::mutex> lock(g_mu);
   if (g_limit == 0) {
     size_t free_b = 0, total_b = 0;
-    g_limit = hipMemGetInfo(&free_b, &total_b) == hipSuccess && total_b > 0 ? total_b / 4 : (size_t{8} << 30);
+    g_limit = hipMemGetInfo(&free_b, &total_b) == hipSuccess && total_b > 0 ? total_b / 2 : (size_t{8} << 30);
   }
   auto range = g_free.equal_range(cls);
   for (auto it = range.first; it != range.second; ++it) {
@@ -218,9 +222,13 @@ int check_params(const pkd_params* p, const pkd_tuning* t, Params* out) {
 }
 
 // Allocate both point buffers of the tree with capacity `cap`.
+// Point buffers for at least `cap` points; the capacity is whatever the
+// rounded allocation holds.
 int alloc_points(pkd_tree* T, hipStream_t st, int64_t cap) {
   cap = std::max<int64_t>(cap, 1);
-  const size_t bytes = sizeof(int64_t) * static_cast<size_t>(T->prm.D + 1) * static_cast<size_t>(cap);
+  const size_t per = sizeof(int64_t) * static_cast<size_t>(T->prm.D + 1);
+  const size_t bytes = dev_size_class(per * static_cast<size_t>(cap));
+  cap = static_cast<int64_t>(bytes / per);
   void* a = nullptr;
   void* b = nullptr;
   PKD_TRY(dev_alloc(&a, bytes, st));
@@ -308,7 +316,9 @@ int pkd_build(const pkd_params* params, const pkd_tuning* tuning, void* stream, 
   hipStream_t st = static_cast<hipStream_t>(stream);
   pkd_tree* T = new pkd_tree;
   T->prm = prm;
-  int rc = alloc_points(T, st, n);
+  // room for later inserts: a sixteenth more than the points (plus what the
+  // rounded allocation holds), so moderate batches never reallocate
+  int rc = alloc_points(T, st, n + n / 16);
   if (rc == PKD_OK) rc = ensure_nodes(T, st, std::max<int64_t>(1024, n / 8));
   if (rc == PKD_OK) {
     if (n == 0) {

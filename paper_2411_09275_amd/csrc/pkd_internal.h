@@ -112,6 +112,7 @@ int hip_status(hipError_t e, const char* what);
   } while (0)
 
 int dev_alloc(void** p, size_t bytes, hipStream_t s);
+size_t dev_size_class(size_t bytes);   // bytes a dev_alloc of `bytes` actually provides
 void dev_free(void* p, hipStream_t s);
 
 inline int kernel_status(const char* what) {

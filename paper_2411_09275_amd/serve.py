@@ -18,9 +18,13 @@ its own runs alone once nothing else is in flight.
 Streams: queries go up on an upload stream, the kernels run on the compute
 stream, results come down on a download stream; events order the three.  So
 batch i+1's upload runs while batch i computes, and batch i's download while
-batch i+1 computes.  Requests that arrive while batches are in flight join the
-next batch.  An update first waits for the batches in flight to finish (it
-rewrites the tree), then runs on the compute stream with the blocking calls.
+batch i+1 computes.  Each in-flight slot owns pinned staging buffers for
+queries and results that grow when a batch needs more and are otherwise
+reused (batch i uses slot i mod max_inflight, which batch i - max_inflight
+has released), so no pinned memory is allocated per batch.  Requests that
+arrive while batches are in flight join the next batch.  An update first
+waits for the batches in flight to finish (it rewrites the tree), then runs on
+the compute stream with the blocking calls.
 
 The serial reference (mode "serial") handles each request alone, in arrival
 order, with the blocking calls.
@@ -83,6 +87,17 @@ class Server:
         self.inflight_bytes = 0
         self.batches = 0          # k-NN batches issued by the last run
         self.launches = 0         # k-NN launches issued by the last run
+        self._stage = [dict() for _ in range(max_inflight)]
+        self._issued = 0
+
+    def _pinned(self, slot, name, n):
+        """A pinned int64 buffer of at least n elements owned by `slot`."""
+        buf = self._stage[slot].get(name)
+        if buf is None or buf.numel() < n:
+            cap = max(n, int(1.5 * (buf.numel() if buf is not None else 0)), 1 << 16)
+            buf = self.torch.empty(cap, dtype=self.torch.int64, pin_memory=True)
+            self._stage[slot][name] = buf
+        return buf
 
     # ---------------------------------------------------------------- admission
     def _knn_bytes(self, r):
@@ -116,21 +131,33 @@ class Server:
         t = now()
         for r in reqs:
             r.start = t
+        slot = self._issued % self.max_inflight
+        self._issued += 1
         by_k = collections.defaultdict(list)
         for r in reqs:
             by_k[r.k].append(r)
+        nq_all = sum(r.size for r in reqs)
+        nres = sum(r.size * r.k for r in reqs)
+        up = self._pinned(slot, "up", self.dim * nq_all)
+        hi_all = self._pinned(slot, "ids", nres)
+        hd_all = self._pinned(slot, "d2", nres)
         with torch.cuda.stream(self.compute):
             status = torch.zeros(1, dtype=torch.int32, device="cuda")
         groups = []
+        q_at = r_at = 0
         for k, rs in by_k.items():
-            q = np.concatenate([r.coords for r in rs], axis=1) if len(rs) > 1 else np.ascontiguousarray(rs[0].coords)
-            nq = q.shape[1]
-            hq = torch.from_numpy(q).pin_memory()
+            nq = sum(r.size for r in rs)
+            hq = up[q_at:q_at + self.dim * nq].view(self.dim, nq)
+            col = 0
+            for r in rs:
+                hq[:, col:col + r.size].numpy()[...] = r.coords
+                col += r.size
+            q_at += self.dim * nq
             with torch.cuda.stream(self.upload):
                 dq = hq.to("cuda", non_blocking=True)
-            up = torch.cuda.Event()
-            up.record(self.upload)
-            self.compute.wait_event(up)
+            ev_up = torch.cuda.Event()
+            ev_up.record(self.upload)
+            self.compute.wait_event(ev_up)
             dq.record_stream(self.compute)
             with torch.cuda.stream(self.compute):
                 oi = torch.empty((nq, k), dtype=torch.int64, device="cuda")
@@ -140,8 +167,9 @@ class Server:
             fin = torch.cuda.Event()
             fin.record(self.compute)
             self.download.wait_event(fin)
-            hi = torch.empty((nq, k), dtype=torch.int64, pin_memory=True)
-            hd = torch.empty((nq, k), dtype=torch.int64, pin_memory=True)
+            hi = hi_all[r_at:r_at + nq * k].view(nq, k)
+            hd = hd_all[r_at:r_at + nq * k].view(nq, k)
+            r_at += nq * k
             with torch.cuda.stream(self.download):
                 hi.copy_(oi, non_blocking=True)
                 hd.copy_(od, non_blocking=True)
@@ -178,6 +206,7 @@ class Server:
         torch = self.torch
         reqs = sorted(requests, key=lambda r: (r.arrival, r.seq))
         self.batches = self.launches = 0
+        self._issued = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0   # noqa: E731
