@@ -28,8 +28,11 @@
  *     PKD_ERR_RANGE and leave any tree unchanged.
  *   - Ids are caller-chosen int64 values and must be unique within a tree
  *     (precondition; not checked).
- *   - A tree owns its device storage (allocated with stream-ordered
- *     hipMallocAsync).  A tree must not be used by two calls concurrently.
+ *   - A tree owns its device storage.  The library takes device memory from
+ *     its own block cache (hipMalloc'd blocks of rounded sizes, kept after a
+ *     free for reuse, a reuse on another stream ordered after the freeing
+ *     stream by an event); the cache keeps at most half of device memory.
+ *     A tree must not be used by two calls concurrently.
  *   - On any error a mutating call leaves the tree as it was.
  */
 #ifndef PKD_H
