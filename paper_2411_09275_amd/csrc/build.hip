@@ -344,26 +344,32 @@ __device__ bool lds_split_rule(const uint32_t* C, const uint16_t* O, int P, int 
   if (best < 0) return false;
   const uint32_t* Cd = C + best * P;
   const uint16_t* Od = O + best * P;
-  uint32_t mn = Cd[Od[a]];
+  const uint32_t mn = Cd[Od[a]];
   uint32_t x = Cd[Od[a + L / 2]];
+  int nl;
   if (x == mn) {
-    // first position with value > mn
+    // the next larger distinct value: first position with value > mn
     int lo = a, hi = a + L - 1;   // Cd[Od[hi]] > mn since the width is positive
     while (lo < hi) {
-      int mid = (lo + hi) >> 1;
+      const int mid = (lo + hi) >> 1;
       if (Cd[Od[mid]] > mn) hi = mid; else lo = mid + 1;
     }
     x = Cd[Od[lo]];
-  }
-  // number of values < x
-  int lo = a, hi = a + L;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (Cd[Od[mid]] < x) lo = mid + 1; else hi = mid;
+    nl = lo - a;
+  } else if (Cd[Od[a + L / 2 - 1]] < x) {
+    nl = L / 2;   // no copy of x before the median position
+  } else {
+    // copies of x before the median: first position with value >= x
+    int lo = a, hi = a + L / 2;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (Cd[Od[mid]] < x) lo = mid + 1; else hi = mid;
+    }
+    nl = lo - a;
   }
   *od = best;
   *ox = x;
-  *onl = lo - a;
+  *onl = nl;
   return true;
 }
 
@@ -1167,24 +1173,31 @@ __global__ void __launch_bounds__(64 * D) k_finish(const Task* tasks, const int*
       }
     }
     __syncthreads();
-    if (tid == 0) {
+    if (wave == 0) {
+      // ranks of the splitting segments among themselves (ballot prefix)
+      const unsigned long long lt = (1ULL << lane) - 1;
       int r = 0;
-      for (int k = 0; k < nl; ++k) {
-        srank[k] = static_cast<uint16_t>(r);
-        r += ssplit[k];
+      for (int base = 0; base < nl; base += 64) {
+        const int k = base + lane;
+        const bool spl = k < nl && ssplit[k];
+        const unsigned long long mk = __ballot(spl);
+        if (k < nl) srank[k] = static_cast<uint16_t>(r + __popcll(mk & lt));
+        r += __popcll(mk);
       }
-      sh_nsplit = r;
-      int b = 0;
-      if (r > 0) {
-        if (sh_next + 2 * r <= res_end) {
-          b = sh_next;
-          sh_next += 2 * r;
-        } else {
-          b = atomicAdd(overflow_ctr, 2 * r);
+      if (lane == 0) {
+        sh_nsplit = r;
+        int b = 0;
+        if (r > 0) {
+          if (sh_next + 2 * r <= res_end) {
+            b = sh_next;
+            sh_next += 2 * r;
+          } else {
+            b = atomicAdd(overflow_ctr, 2 * r);
+          }
         }
+        if (static_cast<int64_t>(b) + 2 * r > node_cap) sh_over = 1;
+        sh_base = b;
       }
-      if (static_cast<int64_t>(b) + 2 * r > node_cap) sh_over = 1;
-      sh_base = b;
     }
     __syncthreads();
     const int nsplit = sh_nsplit;
