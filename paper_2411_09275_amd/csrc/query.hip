@@ -74,8 +74,9 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
     bi[0] = INT64_MAX;
   }
 
+  // a stacked cell: its node and its per-dimension distances from q; the
+  // lower bound is their sum of squares, recomputed when the entry is taken
   struct Ent {
-    int64_t lb;
     int32_t node;
     int32_t off[D];
   };
@@ -115,9 +116,12 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
         }
         --sp;
         node = stk[sp].node;
-        lb = stk[sp].lb;
+        lb = 0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) off[d] = stk[sp].off[d];
+        for (int d = 0; d < D; ++d) {
+          off[d] = stk[sp].off[d];
+          lb += static_cast<int64_t>(off[d]) * off[d];
+        }
         if (lb > bd[KR - 1]) {
           node = -1;
           continue;
@@ -163,7 +167,6 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
           continue;
         }
         stk[sp].node = far;
-        stk[sp].lb = flb;
 #pragma unroll
         for (int d = 0; d < D; ++d) stk[sp].off[d] = (nd.dim == d) ? static_cast<int32_t>(fo) : off[d];
         ++sp;
