@@ -70,8 +70,12 @@ typedef struct {
 
 /* Parameters that never change any result (work decomposition only). */
 typedef struct {
-  int32_t tile_points;  /* points per sieve tile: 1024, 2048 or 4096; default 2048 */
-  int32_t reserved[7];
+  int32_t tile_points;      /* points per sieve tile: 1024, 2048 or 4096; default 2048 */
+  int32_t cand_shift_bias;  /* test knob, default 0, |bias| <= 4: added to the exponent of
+                               every sieving subproblem's sample-candidate threshold, so the
+                               sampler's overflow (bias < 0) or underflow (bias > 0) retry
+                               runs; the tree never changes */
+  int32_t reserved[6];
 } pkd_tuning;
 
 /* Fill defaults for dimension `dim`. */

@@ -104,7 +104,8 @@ __global__ void k_classify(const Task* front, int n_front, int s, Task* sieve, i
 // ------------------------------------------------------------ tile layout
 // Single workgroup: exclusive prefix sums of tiles and chunks per subproblem.
 __global__ void k_tile_scan(const Task* sp, int ns, int tile, int64_t* tile_off, int64_t* chunk_off,
-                            int8_t* shift, int s, int small_max, const int8_t* shift_override, int64_t* total_pts) {
+                            int8_t* shift, int s, int small_max, const int8_t* shift_override, int64_t* total_pts,
+                            int cand_bias) {
   __shared__ int64_t part_t[1024], part_c[1024];
   __shared__ unsigned long long pts;
   if (threadIdx.x == 0) pts = 0;
@@ -148,7 +149,7 @@ __global__ void k_tile_scan(const Task* sp, int ns, int tile, int64_t* tile_off,
     int64_t tiles = (sp[i].m + tile - 1) / tile;
     st += tiles;
     sc += (tiles + kChunkTiles - 1) / kChunkTiles;
-    int sh = sp[i].m <= small_max ? 0 : cand_shift(sp[i].m, s);
+    int sh = sp[i].m <= small_max ? 0 : max(0, cand_shift(sp[i].m, s) + cand_bias);
     if (shift_override && shift_override[i] >= 0) sh = shift_override[i];
     shift[i] = static_cast<int8_t>(sh);
   }
@@ -1587,7 +1588,8 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
     PKD_TRY(rootext.need(ns));
     PKD_TRY(cand_cnt.need(static_cast<size_t>(ns) * kCntStride));
     for (int attempt = 0;; ++attempt) {
-      PKD_TRY(sieve_layout(st, sieve.p, ns, tile, W, s, small_max, override_p, &ntiles, &nchunks, &round_pts));
+      PKD_TRY(sieve_layout(st, sieve.p, ns, tile, W, s, small_max, override_p, &ntiles, &nchunks, &round_pts,
+                           P.cand_bias));
       PKD_TRY(cand_key.need(static_cast<size_t>(ns) * cap));
       PKD_TRY(cand_pos.need(static_cast<size_t>(ns) * cap));
       PKD_HIP(hipMemsetAsync(cand_cnt.p, 0, sizeof(uint32_t) * kCntStride * ns, st));
@@ -1881,13 +1883,13 @@ int exscan_i32(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, DArr<
 
 
 int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,
-                 const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts) {
+                 const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts, int cand_bias) {
   PKD_TRY(W.tile_off.need(ns + 1));
   PKD_TRY(W.chunk_off.need(ns + 1));
   PKD_TRY(W.shift.need(ns));
   PKD_TRY(W.tot.need(4));
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, tasks, ns, tile, W.tile_off.p, W.chunk_off.p, W.shift.p,
-                     s, small_max, shift_override, W.tot.p + 2);
+                     s, small_max, shift_override, W.tot.p + 2, cand_bias);
   PKD_TRY(kernel_status("k_tile_scan"));
   PKD_HIP(hipMemcpyAsync(W.tot.p, W.tile_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
   PKD_HIP(hipMemcpyAsync(W.tot.p + 1, W.chunk_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToDevice, st));

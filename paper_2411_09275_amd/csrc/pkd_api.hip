@@ -209,6 +209,8 @@ int check_params(const pkd_params* p, const pkd_tuning* t, Params* out) {
   if (s > kMaxSample) return PKD_ERR_UNSUPPORTED;
   int tile = t ? t->tile_points : 2048;
   if (tile != 1024 && tile != 2048 && tile != 4096) return PKD_ERR_INVALID_ARG;
+  const int bias = t ? t->cand_shift_bias : 0;
+  if (bias < -4 || bias > 4) return PKD_ERR_INVALID_ARG;
   out->D = p->dim;
   out->lambda = p->lambda;
   out->phi = p->leaf_size;
@@ -218,6 +220,7 @@ int check_params(const pkd_params* p, const pkd_tuning* t, Params* out) {
   out->alpha_den = p->alpha_den;
   out->seed = p->seed;
   out->tile = tile;
+  out->cand_bias = bias;
   return PKD_OK;
 }
 

@@ -70,6 +70,7 @@ struct Params {
   int64_t alpha_num, alpha_den;
   uint64_t seed;
   int tile;
+  int cand_bias;   // test knob: shifts every candidate threshold (results unchanged)
 };
 
 // Device-side error flags (bitmask in one int).
@@ -165,7 +166,7 @@ int exscan_i32(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, DArr<
 // Tile layout of `ns` tasks (device array): tiles of `tile` points, scan
 // chunks; returns the numbers of tiles and chunks and the points covered.
 int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,
-                 const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts);
+                 const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts, int cand_bias = 0);
 // Count, column-major scan and stable scatter of the tasks' points from
 // buffer src to dst through per-task routing skeletons rx/rdim ([ns][2^lambda]).
 // Bucket sizes and starts land in W.bsize / W.bstart ([ns][2^lambda]).

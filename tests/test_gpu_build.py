@@ -275,3 +275,26 @@ def test_batch_handle_large_query_batch(orc, pk):
         assert np.array_equal(gi[sel], oi) and np.array_equal(gd[sel], od), t
         ref = ot.range_count(np.ascontiguousarray(lo[:, sel]), np.ascontiguousarray(hi[:, sel]))
         assert np.array_equal(rc[sel], ref), t
+
+
+# ------------------------------------------------ forced sampler retries
+# A biased candidate threshold makes the sampler overflow (negative bias: too
+# many candidates) or underflow (positive: fewer than s) on every sieving
+# subproblem; the retry must converge to the same sample, so the tree is the
+# same as without the bias.
+@pytest.mark.parametrize("bias", [-4, -1, 2, 4])
+def test_sampler_retry_keeps_the_tree(orc, pk, bias):
+    c, i = synth.uniform_points(600000, 3, seed=70)
+    ref = pk.Tree(pk.Params(3), c, i).export()
+    print("cand bias", bias, flush=True)
+    got = pk.Tree(pk.Params(3), c, i, cand_bias=bias).export()
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y)
+    sizes = np.array([300000, 0, 5000, 120000], dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    cb, ib = synth.clustered_points(int(off[-1]), 2, seed=71, n_clusters=20)[:2]
+    B0 = pk.Tree.batch(pk.Params(2), cb, ib, off)
+    B1 = pk.Tree.batch(pk.Params(2), cb, ib, off, cand_bias=bias)
+    for t in range(4):
+        for x, y in zip(B0.export(t), B1.export(t)):
+            assert np.array_equal(x, y)
