@@ -1882,6 +1882,120 @@ int exscan_i32(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, DArr<
 }
 
 
+// ------------------------------------------------ LSD radix sort of pairs
+// Stable sort of (uint64 key, uint32 value) pairs by the low `nbits` bits of
+// the key, 8 bits per pass: per-tile digit counts, one exclusive scan over
+// (digit, tile), and a scatter that ranks equal digits inside each tile with
+// ballots (chunks of 64 consecutive items in order, so equal keys keep their
+// order).
+namespace {
+constexpr int kRsTile = 2048;   // 256 threads x 8 items
+
+__global__ void __launch_bounds__(256) k_rs_count(const uint64_t* __restrict__ key, int64_t n, int shift,
+                                                  int32_t* __restrict__ hist, int64_t nblk) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kRsTile;
+  for (int i = threadIdx.x; i < kRsTile; i += 256)
+    if (b0 + i < n) atomicAdd(&h[(key[b0 + i] >> shift) & 255], 1u);
+  __syncthreads();
+  hist[static_cast<int64_t>(threadIdx.x) * nblk + blockIdx.x] = static_cast<int32_t>(h[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(256) k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                    int64_t n, int shift, const int32_t* __restrict__ off,
+                                                    int64_t nblk, uint64_t* __restrict__ kout,
+                                                    uint32_t* __restrict__ vout) {
+  constexpr int PER = kRsTile / 256, NCH = kRsTile / 64;   // chunks of 64 consecutive items
+  __shared__ uint16_t cnt[NCH][256];
+  __shared__ int32_t base[256];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const uint32_t lane = tid & 63;
+  const unsigned long long lt = (1ULL << lane) - 1;
+  for (int i = tid; i < NCH * 256; i += 256) (&cnt[0][0])[i] = 0;
+  base[tid] = off[static_cast<int64_t>(tid) * nblk + blockIdx.x];
+  __syncthreads();
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kRsTile;
+  uint64_t kk[PER];
+  uint32_t vv[PER];
+  int dig[PER], rank[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t i = b0 + k * 256 + tid;
+    const bool ok = i < n;
+    kk[k] = ok ? kin[i] : 0;
+    vv[k] = ok ? vin[i] : 0;
+    const int d = static_cast<int>((kk[k] >> shift) & 255);
+    unsigned long long peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const unsigned long long m = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? m : ~m;
+    }
+    dig[k] = d;
+    rank[k] = __popcll(peers & lt);
+    if (ok && (peers & lt) == 0) cnt[k * 4 + wave][d] = static_cast<uint16_t>(__popcll(peers));
+  }
+  __syncthreads();
+  {
+    uint16_t run = 0;
+    for (int ch = 0; ch < NCH; ++ch) {
+      const uint16_t x = cnt[ch][tid];
+      cnt[ch][tid] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t i = b0 + k * 256 + tid;
+    if (i < n) {
+      const int64_t pos = static_cast<int64_t>(base[dig[k]]) + cnt[k * 4 + wave][dig[k]] + rank[k];
+      kout[pos] = kk[k];
+      vout[pos] = vv[k];
+    }
+  }
+}
+
+}  // namespace
+
+int bits_for(int64_t v) {
+  int b = 0;
+  while (b < 63 && (int64_t{1} << b) <= v) ++b;
+  return b;
+}
+
+int radix_sort_pairs(hipStream_t st, uint64_t* keys, uint32_t* vals, int64_t n, int nbits, SortWork& W,
+                     uint64_t** kout, uint32_t** vout) {
+  *kout = keys;
+  *vout = vals;
+  if (n <= 1 || nbits <= 0) return PKD_OK;
+  const int passes = (nbits + 7) / 8;
+  const int64_t nblk = (n + kRsTile - 1) / kRsTile;
+  PKD_TRY(W.k1.need(n));
+  PKD_TRY(W.v1.need(n));
+  PKD_TRY(W.hist.need(static_cast<size_t>(256) * nblk));
+  PKD_TRY(W.off.need(static_cast<size_t>(256) * nblk + 1));
+  uint64_t* ka = keys;
+  uint64_t* kb = W.k1.p;
+  uint32_t* va = vals;
+  uint32_t* vb = W.v1.p;
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL(k_rs_count, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, ka, n, 8 * p, W.hist.p, nblk);
+    PKD_TRY(kernel_status("k_rs_count"));
+    PKD_TRY(exscan_i32(st, W.hist.p, W.off.p, 256 * nblk, W.bsum));
+    hipLaunchKernelGGL(k_rs_scatter, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, ka, va, n, 8 * p, W.off.p,
+                       nblk, kb, vb);
+    PKD_TRY(kernel_status("k_rs_scatter"));
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  *kout = ka;
+  *vout = va;
+  return PKD_OK;
+}
+
 int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,
                  const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts, int cand_bias) {
   PKD_TRY(W.tile_off.need(ns + 1));

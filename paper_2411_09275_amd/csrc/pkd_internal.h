@@ -163,6 +163,19 @@ struct SieveWork {
 // i in [0, n]; bsum is scratch.
 int exscan_i32(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, DArr<int32_t>& bsum);
 
+// Stable LSD radix sort of (key, value) pairs by the low nbits bits of the
+// keys (8 bits per pass).  The sorted pairs end either in the input arrays or
+// in the work arrays; *kout / *vout point at them.
+struct SortWork {
+  DArr<uint64_t> k1;
+  DArr<uint32_t> v1;
+  DArr<int32_t> hist, off, bsum;
+  explicit SortWork(hipStream_t st) : k1(st), v1(st), hist(st), off(st), bsum(st) {}
+};
+int radix_sort_pairs(hipStream_t st, uint64_t* keys, uint32_t* vals, int64_t n, int nbits, SortWork& W,
+                     uint64_t** kout, uint32_t** vout);
+int bits_for(int64_t v);   // bits needed to write 0 .. v
+
 // Tile layout of `ns` tasks (device array): tiles of `tile` points, scan
 // chunks; returns the numbers of tiles and chunks and the points covered.
 int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,

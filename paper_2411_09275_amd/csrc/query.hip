@@ -443,10 +443,8 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
 // interleaved, most significant first, below the tree id of a batch handle):
 // the lanes of a wave then walk neighbouring paths of the tree, which keeps
 // them converged and their node and leaf loads in cache.  Results still go to
-// each query's own row.  The order comes from a stable LSD radix sort with
-// 8-bit digits: per-tile digit counts, one exclusive scan over (digit, tile),
-// and a scatter that ranks equal digits inside each tile with ballots.
-constexpr int kRsTile = 2048;               // 256 threads x 8 items
+// each query's own row.  The order comes from a stable LSD radix sort
+// (radix_sort_pairs).
 constexpr int64_t kOrderMinQueries = 16384;  // smaller batches keep their order
 
 template <int D>
@@ -465,85 +463,12 @@ __global__ void k_morton(const int64_t* __restrict__ Q, int64_t nq, const int32_
   val[j] = static_cast<uint32_t>(j);
 }
 
-__global__ void __launch_bounds__(256) k_rs_count(const uint64_t* __restrict__ key, int64_t n, int shift,
-                                                  int32_t* __restrict__ hist, int64_t nblk) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kRsTile;
-  for (int i = threadIdx.x; i < kRsTile; i += 256)
-    if (b0 + i < n) atomicAdd(&h[(key[b0 + i] >> shift) & 255], 1u);
-  __syncthreads();
-  hist[static_cast<int64_t>(threadIdx.x) * nblk + blockIdx.x] = static_cast<int32_t>(h[threadIdx.x]);
-}
-
-__global__ void __launch_bounds__(256) k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                    int64_t n, int shift, const int32_t* __restrict__ off,
-                                                    int64_t nblk, uint64_t* __restrict__ kout,
-                                                    uint32_t* __restrict__ vout) {
-  constexpr int PER = kRsTile / 256, NCH = kRsTile / 64;   // chunks of 64 consecutive items
-  __shared__ uint16_t cnt[NCH][256];
-  __shared__ int32_t base[256];
-  const int tid = threadIdx.x, wave = tid >> 6;
-  const uint32_t lane = tid & 63;
-  const unsigned long long lt = (1ULL << lane) - 1;
-  for (int i = tid; i < NCH * 256; i += 256) (&cnt[0][0])[i] = 0;
-  base[tid] = off[static_cast<int64_t>(tid) * nblk + blockIdx.x];
-  __syncthreads();
-  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kRsTile;
-  uint64_t kk[PER];
-  uint32_t vv[PER];
-  int dig[PER], rank[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int64_t i = b0 + k * 256 + tid;
-    const bool ok = i < n;
-    kk[k] = ok ? kin[i] : 0;
-    vv[k] = ok ? vin[i] : 0;
-    const int d = static_cast<int>((kk[k] >> shift) & 255);
-    unsigned long long peers = __ballot(ok);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const unsigned long long m = __ballot((d >> b) & 1);
-      peers &= ((d >> b) & 1) ? m : ~m;
-    }
-    dig[k] = d;
-    rank[k] = __popcll(peers & lt);
-    if (ok && (peers & lt) == 0) cnt[k * 4 + wave][d] = static_cast<uint16_t>(__popcll(peers));
-  }
-  __syncthreads();
-  {
-    uint16_t run = 0;
-    for (int ch = 0; ch < NCH; ++ch) {
-      const uint16_t x = cnt[ch][tid];
-      cnt[ch][tid] = run;
-      run += x;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int64_t i = b0 + k * 256 + tid;
-    if (i < n) {
-      const int64_t pos = static_cast<int64_t>(base[dig[k]]) + cnt[k * 4 + wave][dig[k]] + rank[k];
-      kout[pos] = kk[k];
-      vout[pos] = vv[k];
-    }
-  }
-}
-
 struct QueryOrder {
-  DArr<uint64_t> k0, k1;
-  DArr<uint32_t> v0, v1;
-  DArr<int32_t> hist, off, bsum;
-  explicit QueryOrder(hipStream_t st) : k0(st), k1(st), v0(st), v1(st), hist(st), off(st), bsum(st) {}
+  DArr<uint64_t> k0;
+  DArr<uint32_t> v0;
+  SortWork sort;
+  explicit QueryOrder(hipStream_t st) : k0(st), v0(st), sort(st) {}
 };
-
-int bits_for(int64_t v) {   // bits needed to write 0 .. v
-  int b = 0;
-  while (b < 63 && (int64_t{1} << b) <= v) ++b;
-  return b;
-}
 
 // Fills *perm with the queries in Morton order, or leaves it null for small
 // batches.  Stream-ordered, no host synchronisation.
@@ -557,33 +482,15 @@ int order_queries(hipStream_t st, const int64_t* Q, int64_t nq, const int32_t* t
   int bpd = (bits_for(nq) + 6 + D - 1) / D;
   bpd = std::min(bpd, std::min(30, (64 - tb) / D));
   const int nbits = tb + D * bpd;
-  const int passes = (nbits + 7) / 8;
-  const int64_t nblk = (nq + kRsTile - 1) / kRsTile;
   PKD_TRY(W.k0.need(nq));
-  PKD_TRY(W.k1.need(nq));
   PKD_TRY(W.v0.need(nq));
-  PKD_TRY(W.v1.need(nq));
-  PKD_TRY(W.hist.need(static_cast<size_t>(256) * nblk));
-  PKD_TRY(W.off.need(static_cast<size_t>(256) * nblk + 1));
   hipLaunchKernelGGL(k_morton<D>, dim3(static_cast<unsigned>((nq + 255) / 256)), dim3(256), 0, st, Q, nq, tree_of,
                      bpd, W.k0.p, W.v0.p);
   PKD_TRY(kernel_status("k_morton"));
-  uint64_t* ka = W.k0.p;
-  uint64_t* kb = W.k1.p;
-  uint32_t* va = W.v0.p;
-  uint32_t* vb = W.v1.p;
-  for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(k_rs_count, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, ka, nq, 8 * p, W.hist.p,
-                       nblk);
-    PKD_TRY(kernel_status("k_rs_count"));
-    PKD_TRY(exscan_i32(st, W.hist.p, W.off.p, 256 * nblk, W.bsum));
-    hipLaunchKernelGGL(k_rs_scatter, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, ka, va, nq, 8 * p,
-                       W.off.p, nblk, kb, vb);
-    PKD_TRY(kernel_status("k_rs_scatter"));
-    std::swap(ka, kb);
-    std::swap(va, vb);
-  }
-  *perm = va;
+  uint64_t* ks = nullptr;
+  uint32_t* vs = nullptr;
+  PKD_TRY(radix_sort_pairs(st, W.k0.p, W.v0.p, nq, nbits, W.sort, &ks, &vs));
+  *perm = vs;
   return PKD_OK;
 }
 

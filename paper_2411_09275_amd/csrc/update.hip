@@ -80,10 +80,6 @@ __global__ void __launch_bounds__(64) k_fetch_skeleton(const Task* tasks, const 
   for (int v = threadIdx.x; v < nheap; v += 64) hn_out[static_cast<int64_t>(sig) * nheap + v] = hn[v];
 }
 
-__device__ inline bool is_external(const Node* nodes, int32_t u, int level, int lambda) {
-  return level == lambda || nodes[u].left < 0;
-}
-
 // Buckets that end at a leaf are resolved; buckets at an interior node of
 // level lambda become the next round's routing tasks.
 __global__ void __launch_bounds__(64) k_route_emit(const Task* tasks, const Node* nodes, int lambda,
@@ -104,12 +100,14 @@ __global__ void __launch_bounds__(64) k_route_emit(const Task* tasks, const Node
       child_idx[static_cast<int64_t>(sig) * nheap + v] = -1;
       if (u >= 0) {
         level = 31 - __clz(v);
-        if (is_external(nodes, u, level, lambda)) {
+        // external: the skeleton's last level, or a leaf above it (whose
+        // children the fetched skeleton left empty)
+        if (level == lambda || hn[2 * v] < 0) {
           const int label = (v << (lambda - level)) - NB;
           size = bsize[static_cast<int64_t>(sig) * NB + label];
           start = bstart[static_cast<int64_t>(sig) * NB + label];
           if (size > 0) {
-            leaf_end = nodes[u].left < 0;
+            leaf_end = level < lambda || nodes[u].left < 0;
             go_on = !leaf_end;
           }
         }
@@ -143,6 +141,90 @@ __global__ void __launch_bounds__(64) k_route_emit(const Task* tasks, const Node
       b0 = __shfl(b0, leader);
       if (leaf_end) res[b0 + __popcll(mk & ((1ULL << (threadIdx.x & 63)) - 1))] = Res{u, start, size, dst};
     }
+  }
+}
+
+// ---- routing rounds with many small subproblems: one stable radix sort of
+// the batch by (subproblem start, bucket label) gives the order the tiled
+// sieve gives (stable by position inside each subproblem) without a tile,
+// a scan and a workgroup per subproblem.
+__global__ void k_task_fill(const Task* tasks, int32_t* task_of) {
+  const Task t = tasks[blockIdx.x];
+  for (int i = threadIdx.x; i < t.m; i += blockDim.x) task_of[t.start + i] = blockIdx.x;
+}
+
+template <int D>
+__global__ void k_route_keys(const int64_t* X, int64_t xcap, int64_t m, const int32_t* task_of, const Task* tasks,
+                             const int64_t* rx, const uint8_t* rdim, int lambda, uint64_t* key, uint32_t* val) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (p >= m) return;
+  const int32_t t = task_of[p];
+  uint64_t k;
+  if (t < 0) {
+    k = static_cast<uint64_t>(p) << lambda;   // not routed this round: keeps its own place in the order
+  } else {
+    const int NB = 1 << lambda;
+    const int64_t* sx = rx + static_cast<int64_t>(t) * NB;
+    const uint8_t* sd = rdim + static_cast<int64_t>(t) * NB;
+    int64_t c[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) c[d] = X[d * xcap + p];
+    int v = 1;
+    for (int l = 0; l < lambda; ++l) {
+      const int d = sd[v];
+      const int64_t x = sx[v];
+      int ge = 0;
+#pragma unroll
+      for (int e = 0; e < D; ++e) ge |= (d == e) & (c[e] >= x);
+      v = 2 * v + ge;
+    }
+    k = (static_cast<uint64_t>(tasks[t].start) << lambda) | static_cast<uint64_t>(v - NB);
+  }
+  key[p] = k;
+  val[p] = static_cast<uint32_t>(p);
+}
+
+__device__ inline int64_t lower_bound_u64(const uint64_t* a, int64_t n, uint64_t x) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Sorted item i of a subproblem starting at P goes to P + (i - first item of
+// that subproblem); the last item of each (subproblem, bucket) run records the
+// bucket size.
+template <int D>
+__global__ void k_route_place(const uint64_t* ks, const uint32_t* vs, int64_t m, const int32_t* task_of, int lambda,
+                              Bufs wb, int src, int dst, int32_t* bsize) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t key = ks[i];
+  const uint32_t p = vs[i];
+  const int32_t t = task_of[p];
+  if (t < 0) return;
+  const uint64_t P = key >> lambda;
+  const int64_t out = static_cast<int64_t>(P) + (i - lower_bound_u64(ks, m, P << lambda));
+#pragma unroll
+  for (int d = 0; d < D; ++d) wb.c[dst][d * wb.cap[dst] + out] = wb.c[src][d * wb.cap[src] + p];
+  wb.id[dst][out] = wb.id[src][p];
+  if (i == m - 1 || ks[i + 1] != key) {
+    const int64_t run = lower_bound_u64(ks, m, key);
+    bsize[static_cast<int64_t>(t) * (1 << lambda) + static_cast<int>(key & ((1u << lambda) - 1))] =
+        static_cast<int32_t>(i - run + 1);
+  }
+}
+
+__global__ void k_route_bstart(const Task* tasks, int ns, int lambda, const int32_t* bsize, int32_t* bstart) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ns) return;
+  const int NB = 1 << lambda;
+  int32_t run = tasks[t].start;
+  for (int j = 0; j < NB; ++j) {
+    bstart[static_cast<int64_t>(t) * NB + j] = run;
+    run += bsize[static_cast<int64_t>(t) * NB + j];
   }
 }
 
@@ -342,6 +424,47 @@ struct RoundSave {
   explicit RoundSave(hipStream_t s) : tasks(s), hn(s), bsize(s), bstart(s), child(s) {}
 };
 
+// Rounds with at least this many subproblems route by one sort of the batch
+// instead of the tiled sieve (which needs a tile and a workgroup per
+// subproblem, however few points it holds).
+constexpr int kSortRouteMin = 512;
+
+struct SortRoute {
+  DArr<int32_t> task_of;
+  DArr<uint64_t> keys;
+  DArr<uint32_t> vals;
+  SortWork sort;
+  explicit SortRoute(hipStream_t s) : task_of(s), keys(s), vals(s), sort(s) {}
+};
+
+// One routing round by sort: the points of the ns tasks move from buffer src
+// to dst grouped by bucket (stable), bsize/bstart ([ns][2^lambda]) as the
+// sieve pass would leave them.
+template <int D>
+int route_by_sort(hipStream_t st, const Task* tasks, int ns, int64_t m, const Bufs& wb, int src, int dst,
+                  const int64_t* rx, const uint8_t* rdim, int lambda, SortRoute& W, int32_t* bsize,
+                  int32_t* bstart) {
+  const int NB = 1 << lambda;
+  PKD_TRY(W.task_of.need(m));
+  PKD_TRY(W.keys.need(m));
+  PKD_TRY(W.vals.need(m));
+  PKD_TRY(fill(st, W.task_of.p, m, -1));
+  hipLaunchKernelGGL(k_task_fill, dim3(ns), dim3(64), 0, st, tasks, W.task_of.p);
+  PKD_TRY(kernel_status("k_task_fill"));
+  const unsigned g = static_cast<unsigned>((m + 255) / 256);
+  hipLaunchKernelGGL(k_route_keys<D>, dim3(g), dim3(256), 0, st, wb.c[src], wb.cap[src], m, W.task_of.p, tasks, rx,
+                     rdim, lambda, W.keys.p, W.vals.p);
+  PKD_TRY(kernel_status("k_route_keys"));
+  uint64_t* ks = nullptr;
+  uint32_t* vs = nullptr;
+  PKD_TRY(radix_sort_pairs(st, W.keys.p, W.vals.p, m, bits_for(m - 1) + lambda, W.sort, &ks, &vs));
+  PKD_TRY(fill(st, bsize, static_cast<int64_t>(ns) * NB, 0));
+  hipLaunchKernelGGL(k_route_place<D>, dim3(g), dim3(256), 0, st, ks, vs, m, W.task_of.p, lambda, wb, src, dst, bsize);
+  PKD_TRY(kernel_status("k_route_place"));
+  hipLaunchKernelGGL(k_route_bstart, dim3((ns + 255) / 256), dim3(256), 0, st, tasks, ns, lambda, bsize, bstart);
+  return kernel_status("k_route_bstart");
+}
+
 template <int D>
 int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m, bool insert,
              int64_t* removed) {
@@ -433,6 +556,7 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     PKD_HIP(hipMemcpyAsync(cur.p, &t0, sizeof(Task), hipMemcpyHostToDevice, st));
     int ns = 1, src = 0;
     SieveWork W(st);
+    SortRoute SR(st);
     while (ns > 0) {
       if (rounds.size() > 200) return PKD_ERR_INTERNAL;
       RoundSave* R = new RoundSave(st);
@@ -448,19 +572,24 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
       PKD_HIP(hipMemsetAsync(mode.p, 0, ns, st));
       hipLaunchKernelGGL(k_fetch_skeleton, dim3(ns), dim3(64), 0, st, cur.p, T->nodes, lambda, rx.p, rdim.p, R->hn.p);
       PKD_TRY(kernel_status("k_fetch_skeleton"));
-      int64_t ntiles = 0, nchunks = 0, pts = 0;
-      PKD_TRY(sieve_layout(st, cur.p, ns, P.tile, W, P.s, 0, nullptr, &ntiles, &nchunks, &pts));
       const int dst = 1 - src;
-      PKD_TRY(sieve_pass(st, D, lambda, P.tile, cur.p, ns, wb, src, dst, rx.p, rdim.p, mode.p, W, ntiles, nchunks,
-                         pts, 0, flags.p));
       PKD_TRY(R->bsize.need(static_cast<size_t>(ns) * NB));
       PKD_TRY(R->bstart.need(static_cast<size_t>(ns) * NB));
-      PKD_HIP(hipMemcpyAsync(R->bsize.p, W.bsize.p, sizeof(int32_t) * ns * NB, hipMemcpyDeviceToDevice, st));
-      PKD_HIP(hipMemcpyAsync(R->bstart.p, W.bstart.p, sizeof(int32_t) * ns * NB, hipMemcpyDeviceToDevice, st));
+      if (ns >= kSortRouteMin) {
+        PKD_TRY(route_by_sort<D>(st, cur.p, ns, m, wb, src, dst, rx.p, rdim.p, lambda, SR, R->bsize.p,
+                                 R->bstart.p));
+      } else {
+        int64_t ntiles = 0, nchunks = 0, pts = 0;
+        PKD_TRY(sieve_layout(st, cur.p, ns, P.tile, W, P.s, 0, nullptr, &ntiles, &nchunks, &pts));
+        PKD_TRY(sieve_pass(st, D, lambda, P.tile, cur.p, ns, wb, src, dst, rx.p, rdim.p, mode.p, W, ntiles, nchunks,
+                           pts, 0, flags.p));
+        PKD_HIP(hipMemcpyAsync(R->bsize.p, W.bsize.p, sizeof(int32_t) * ns * NB, hipMemcpyDeviceToDevice, st));
+        PKD_HIP(hipMemcpyAsync(R->bstart.p, W.bstart.p, sizeof(int32_t) * ns * NB, hipMemcpyDeviceToDevice, st));
+      }
       PKD_TRY(nxt.need(static_cast<size_t>(ns) * NB));
       PKD_HIP(hipMemsetAsync(d_next, 0, sizeof(int), st));
-      hipLaunchKernelGGL(k_route_emit, dim3(ns), dim3(64), 0, st, cur.p, T->nodes, lambda, R->hn.p, W.bsize.p,
-                         W.bstart.p, dst, nxt.p, d_next, R->child.p, res.p, d_res);
+      hipLaunchKernelGGL(k_route_emit, dim3(ns), dim3(64), 0, st, cur.p, T->nodes, lambda, R->hn.p, R->bsize.p,
+                         R->bstart.p, dst, nxt.p, d_next, R->child.p, res.p, d_res);
       PKD_TRY(kernel_status("k_route_emit"));
       int h[2];
       PKD_HIP(hipMemcpyAsync(h, ctr.p, sizeof(h), hipMemcpyDeviceToHost, st));

@@ -189,3 +189,22 @@ def test_update_rejects_out_of_range(pk):
     assert e.value.code == -2
     for a, b in zip(before, t.export()):
         assert np.array_equal(a, b)
+
+
+def test_scattered_batches_route_by_sort(orc, pk):
+    # uniform batches spread over thousands of subtrees: the deeper routing
+    # rounds hold many small subproblems and take the sort path
+    c, i = synth.uniform_points(400000, 3, seed=110)
+    P = Pair(orc, pk, c, i)
+    q = synth.uniform_queries(200, 3, seed=111)
+    nc, ni = synth.uniform_points(60000, 3, seed=112, id_base=10 ** 7)
+    P.insert(nc, ni)
+    P.check("scattered insert", q)
+    pick = synth.sample_existing(P.i, 60000, seed=113)
+    assert P.delete(P.c[:, pick], P.i[pick]) == 60000
+    P.check("scattered delete", q)
+    # entries that match nothing and repeated entries
+    extra_c = np.concatenate([P.c[:, :50], nc[:, :50] + 1], axis=1)
+    extra_i = np.concatenate([P.i[:50], ni[:50]])
+    P.delete(np.ascontiguousarray(extra_c), extra_i)
+    P.check("partial matches", q)
