@@ -46,101 +46,146 @@ __global__ void k_validate(const int64_t* coords, int64_t m, int* flags) {
   if (bad) atomicOr(flags, kErrRange);
 }
 
+// Kernels that work per routing subproblem give each subproblem one wave and
+// put several waves in a workgroup: a late routing round can hold hundreds of
+// thousands of subproblems with a handful of points each, and one workgroup
+// per subproblem would be bound by workgroup dispatch.
+constexpr int kWaves = 4;
+
 // Skeleton of the top lambda levels below each routing node, in heap order:
 // hn[v] is the tree node at heap position v (-1 below a leaf); interior
 // positions above level lambda route by their splitter, the rest send left.
-__global__ void __launch_bounds__(64) k_fetch_skeleton(const Task* tasks, const Node* nodes, int lambda, int64_t* rx,
-                                                       uint8_t* rdim, int32_t* hn_out) {
+__global__ void __launch_bounds__(64 * kWaves) k_fetch_skeleton(const Task* tasks, int ns, const Node* nodes,
+                                                                int lambda, int64_t* rx, uint8_t* rdim,
+                                                                int32_t* hn_out) {
   const int NB = 1 << lambda, nheap = 2 << lambda;
-  __shared__ int32_t hn[2 << kMaxLambda];
-  const int sig = blockIdx.x;
-  for (int v = threadIdx.x; v < nheap; v += 64) hn[v] = -1;
+  __shared__ int32_t hn_w[kWaves][2 << kMaxLambda];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sig = blockIdx.x * kWaves + w;
+  const bool active = sig < ns;
+  int32_t* hn = hn_w[w];
+  for (int v = lane; v < nheap; v += 64) hn[v] = -1;
   __syncthreads();
-  if (threadIdx.x == 0) hn[1] = tasks[sig].slot;
+  if (active && lane == 0) hn[1] = tasks[sig].slot;
   __syncthreads();
   for (int l = 0; l < lambda; ++l) {
-    for (int v = (1 << l) + threadIdx.x; v < (2 << l); v += 64) {
-      const int32_t u = hn[v];
-      int64_t x = kAllLeft;
-      uint8_t d = 0;
-      if (u >= 0) {
-        const Node nd = nodes[u];
-        if (nd.left >= 0) {
-          x = nd.x;
-          d = static_cast<uint8_t>(nd.dim);
-          hn[2 * v] = nd.left;
-          hn[2 * v + 1] = nd.right;
+    if (active) {
+      for (int v = (1 << l) + lane; v < (2 << l); v += 64) {
+        const int32_t u = hn[v];
+        int64_t x = kAllLeft;
+        uint8_t d = 0;
+        if (u >= 0) {
+          const Node nd = nodes[u];
+          if (nd.left >= 0) {
+            x = nd.x;
+            d = static_cast<uint8_t>(nd.dim);
+            hn[2 * v] = nd.left;
+            hn[2 * v + 1] = nd.right;
+          }
         }
+        rx[static_cast<int64_t>(sig) * NB + v] = x;
+        rdim[static_cast<int64_t>(sig) * NB + v] = d;
       }
-      rx[static_cast<int64_t>(sig) * NB + v] = x;
-      rdim[static_cast<int64_t>(sig) * NB + v] = d;
     }
     __syncthreads();
   }
-  for (int v = threadIdx.x; v < nheap; v += 64) hn_out[static_cast<int64_t>(sig) * nheap + v] = hn[v];
+  if (active)
+    for (int v = lane; v < nheap; v += 64) hn_out[static_cast<int64_t>(sig) * nheap + v] = hn[v];
 }
 
 // Buckets that end at a leaf are resolved; buckets at an interior node of
-// level lambda become the next round's routing tasks.
-__global__ void __launch_bounds__(64) k_route_emit(const Task* tasks, const Node* nodes, int lambda,
-                                                   const int32_t* hn_all, const int32_t* bsize, const int32_t* bstart,
-                                                   int dst, Task* next, int* n_next, int32_t* child_idx, Res* res,
-                                                   int* n_res) {
+// level lambda become the next round's routing tasks.  Two passes: count the
+// outcomes per subproblem, then (after an exclusive scan over subproblems)
+// write them at fixed places, so there is no contended counter and the order
+// of tasks and resolved slices follows the subproblems.
+struct Outcome {
+  int32_t u, start, size;
+  int level;
+  bool go_on, leaf_end;
+};
+
+__device__ inline Outcome route_outcome(const Node* nodes, int lambda, const int32_t* hn, const int32_t* bsize_t,
+                                        const int32_t* bstart_t, int v) {
   const int NB = 1 << lambda, nheap = 2 << lambda;
-  const int sig = blockIdx.x;
+  Outcome o{-1, 0, 0, 0, false, false};
+  if (v < 1 || v >= nheap) return o;
+  o.u = hn[v];
+  if (o.u < 0) return o;
+  o.level = 31 - __clz(v);
+  // external: the skeleton's last level, or a leaf above it (whose children
+  // the fetched skeleton left empty)
+  if (o.level == lambda || hn[2 * v] < 0) {
+    const int label = (v << (lambda - o.level)) - NB;
+    o.size = bsize_t[label];
+    o.start = bstart_t[label];
+    if (o.size > 0) {
+      o.leaf_end = o.level < lambda || nodes[o.u].left < 0;
+      o.go_on = !o.leaf_end;
+    }
+  }
+  return o;
+}
+
+__global__ void __launch_bounds__(64 * kWaves) k_route_count(const Task* tasks, int ns, const Node* nodes, int lambda,
+                                                             const int32_t* hn_all, const int32_t* bsize,
+                                                             const int32_t* bstart, int32_t* n_go, int32_t* n_leaf) {
+  const int NB = 1 << lambda, nheap = 2 << lambda;
+  const int lane = threadIdx.x & 63;
+  const int sig = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (sig >= ns) return;
+  const int32_t* hn = hn_all + static_cast<int64_t>(sig) * nheap;
+  int go = 0, leaf = 0;
+  for (int base = 0; base < nheap; base += 64) {
+    const Outcome o = route_outcome(nodes, lambda, hn, bsize + static_cast<int64_t>(sig) * NB,
+                                    bstart + static_cast<int64_t>(sig) * NB, base + lane);
+    go += __popcll(__ballot(o.go_on));
+    leaf += __popcll(__ballot(o.leaf_end));
+  }
+  if (lane == 0) {
+    n_go[sig] = go;
+    n_leaf[sig] = leaf;
+  }
+  (void)tasks;
+}
+
+__global__ void __launch_bounds__(64 * kWaves) k_route_emit(const Task* tasks, int ns, const Node* nodes, int lambda,
+                                                            const int32_t* hn_all, const int32_t* bsize,
+                                                            const int32_t* bstart, int dst, const int32_t* off_go,
+                                                            const int32_t* off_leaf, int res_base, Task* next,
+                                                            int32_t* child_idx, Res* res) {
+  const int NB = 1 << lambda, nheap = 2 << lambda;
+  const int lane = threadIdx.x & 63;
+  const int sig = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (sig >= ns) return;
+  const unsigned long long lt = (1ULL << lane) - 1;
   const Task q = tasks[sig];
   const int32_t* hn = hn_all + static_cast<int64_t>(sig) * nheap;
+  int go_at = off_go[sig], leaf_at = res_base + off_leaf[sig];
   for (int base = 0; base < nheap; base += 64) {
-    const int v = base + threadIdx.x;
-    bool leaf_end = false, go_on = false;
-    int32_t u = -1, start = 0, size = 0;
-    int level = 0;
+    const int v = base + lane;
+    const Outcome o = route_outcome(nodes, lambda, hn, bsize + static_cast<int64_t>(sig) * NB,
+                                    bstart + static_cast<int64_t>(sig) * NB, v);
+    const unsigned long long mg = __ballot(o.go_on);
+    const unsigned long long ml = __ballot(o.leaf_end);
     if (v >= 1 && v < nheap) {
-      u = hn[v];
-      child_idx[static_cast<int64_t>(sig) * nheap + v] = -1;
-      if (u >= 0) {
-        level = 31 - __clz(v);
-        // external: the skeleton's last level, or a leaf above it (whose
-        // children the fetched skeleton left empty)
-        if (level == lambda || hn[2 * v] < 0) {
-          const int label = (v << (lambda - level)) - NB;
-          size = bsize[static_cast<int64_t>(sig) * NB + label];
-          start = bstart[static_cast<int64_t>(sig) * NB + label];
-          if (size > 0) {
-            leaf_end = level < lambda || nodes[u].left < 0;
-            go_on = !leaf_end;
-          }
-        }
-      }
-    }
-    // wave-aggregated appends
-    unsigned long long mk = __ballot(go_on);
-    if (mk) {
-      int leader = __ffsll(static_cast<long long>(mk)) - 1;
-      int b0 = 0;
-      if (static_cast<int>(threadIdx.x & 63) == leader) b0 = atomicAdd(n_next, __popcll(mk));
-      b0 = __shfl(b0, leader);
-      if (go_on) {
-        const int at = b0 + __popcll(mk & ((1ULL << (threadIdx.x & 63)) - 1));
+      int32_t child = -1;
+      if (o.go_on) {
+        const int at = go_at + __popcll(mg & lt);
         Task c;
-        c.start = start;
-        c.m = size;
-        c.slot = u;
-        c.depth = static_cast<int16_t>(q.depth + level);
+        c.start = o.start;
+        c.m = o.size;
+        c.slot = o.u;
+        c.depth = static_cast<int16_t>(q.depth + o.level);
         c.buf = static_cast<int8_t>(dst);
         c.mode = 0;
         next[at] = c;
-        child_idx[static_cast<int64_t>(sig) * nheap + v] = at;
+        child = at;
       }
+      child_idx[static_cast<int64_t>(sig) * nheap + v] = child;
+      if (o.leaf_end) res[leaf_at + __popcll(ml & lt)] = Res{o.u, o.start, o.size, dst};
     }
-    mk = __ballot(leaf_end);
-    if (mk) {
-      int leader = __ffsll(static_cast<long long>(mk)) - 1;
-      int b0 = 0;
-      if (static_cast<int>(threadIdx.x & 63) == leader) b0 = atomicAdd(n_res, __popcll(mk));
-      b0 = __shfl(b0, leader);
-      if (leaf_end) res[b0 + __popcll(mk & ((1ULL << (threadIdx.x & 63)) - 1))] = Res{u, start, size, dst};
-    }
+    go_at += __popcll(mg);
+    leaf_at += __popcll(ml);
   }
 }
 
@@ -148,9 +193,11 @@ __global__ void __launch_bounds__(64) k_route_emit(const Task* tasks, const Node
 // the batch by (subproblem start, bucket label) gives the order the tiled
 // sieve gives (stable by position inside each subproblem) without a tile,
 // a scan and a workgroup per subproblem.
-__global__ void k_task_fill(const Task* tasks, int32_t* task_of) {
-  const Task t = tasks[blockIdx.x];
-  for (int i = threadIdx.x; i < t.m; i += blockDim.x) task_of[t.start + i] = blockIdx.x;
+__global__ void __launch_bounds__(64 * kWaves) k_task_fill(const Task* tasks, int ns, int32_t* task_of) {
+  const int sig = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (sig >= ns) return;
+  const Task t = tasks[sig];
+  for (int i = threadIdx.x & 63; i < t.m; i += 64) task_of[t.start + i] = sig;
 }
 
 template <int D>
@@ -217,22 +264,35 @@ __global__ void k_route_place(const uint64_t* ks, const uint32_t* vs, int64_t m,
   }
 }
 
-__global__ void k_route_bstart(const Task* tasks, int ns, int lambda, const int32_t* bsize, int32_t* bstart) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ns) return;
+__global__ void __launch_bounds__(64 * kWaves) k_route_bstart(const Task* tasks, int ns, int lambda,
+                                                              const int32_t* bsize, int32_t* bstart) {
+  const int sig = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (sig >= ns) return;
+  const int lane = threadIdx.x & 63;
   const int NB = 1 << lambda;
-  int32_t run = tasks[t].start;
-  for (int j = 0; j < NB; ++j) {
-    bstart[static_cast<int64_t>(t) * NB + j] = run;
-    run += bsize[static_cast<int64_t>(t) * NB + j];
+  // exclusive scan of the bucket sizes from the subproblem's start
+  int32_t carry = tasks[sig].start;
+  for (int base = 0; base < NB; base += 64) {
+    const int j = base + lane;
+    const int32_t x = j < NB ? bsize[static_cast<int64_t>(sig) * NB + j] : 0;
+    int32_t incl = x;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    if (j < NB) bstart[static_cast<int64_t>(sig) * NB + j] = carry + incl - x;
+    carry += __shfl(incl, 63);
   }
 }
 
 // Copy every resolved slice into one buffer (same positions) and record the
 // leaf of each batch position.
-__global__ void k_gather(const Res* res, int D, Bufs wb, int64_t* out, int64_t m, int32_t* leaf_of) {
-  const Res r = res[blockIdx.x];
-  for (int i = threadIdx.x; i < r.count; i += blockDim.x) {
+__global__ void __launch_bounds__(64 * kWaves) k_gather(const Res* res, int nres, int D, Bufs wb, int64_t* out,
+                                                        int64_t m, int32_t* leaf_of) {
+  const int rid = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (rid >= nres) return;
+  const Res r = res[rid];
+  for (int i = threadIdx.x & 63; i < r.count; i += 64) {
     const int64_t p = r.start + i;
     for (int d = 0; d < D; ++d) out[d * m + p] = wb.c[r.buf][d * wb.cap[r.buf] + p];
     out[D * m + p] = wb.id[r.buf][p];
@@ -273,68 +333,77 @@ __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
 // Replay of one routing round, top-down, with exact counts.  cnt(v) is the
 // weight of the batch slice below heap position v (1 per inserted point, 1 per
 // point actually removed); a killed task lies below a region.
-__global__ void __launch_bounds__(64) k_decide(const Task* tasks, int lambda, const int32_t* hn_all,
-                                               const int32_t* bsize, const int32_t* bstart,
-                                               const int32_t* child_idx, const int8_t* killed, int8_t* killed_next,
-                                               const int32_t* M, Node* nodes, int64_t an, int64_t ad, int insert,
-                                               Region* regions, int* n_regions) {
+__global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int ns, int lambda, const int32_t* hn_all,
+                                                        const int32_t* bsize, const int32_t* bstart,
+                                                        const int32_t* child_idx, const int8_t* killed,
+                                                        int8_t* killed_next, const int32_t* M, Node* nodes, int64_t an,
+                                                        int64_t ad, int insert, Region* regions, int* n_regions) {
   const int NB = 1 << lambda, nheap = 2 << lambda;
-  __shared__ int32_t cnt[2 << kMaxLambda], s0[2 << kMaxLambda], sz[2 << kMaxLambda];
-  __shared__ uint8_t alive[2 << kMaxLambda];
-  const int sig = blockIdx.x;
-  if (killed[sig]) return;
-  const Task q = tasks[sig];
+  __shared__ int32_t cnt_w[kWaves][2 << kMaxLambda], s0_w[kWaves][2 << kMaxLambda], sz_w[kWaves][2 << kMaxLambda];
+  __shared__ uint8_t alive_w[kWaves][2 << kMaxLambda];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sig = blockIdx.x * kWaves + w;
+  const bool active = sig < ns && !killed[sig];
+  int32_t* cnt = cnt_w[w];
+  int32_t* s0 = s0_w[w];
+  int32_t* sz = sz_w[w];
+  uint8_t* alive = alive_w[w];
   const int32_t* hn = hn_all + static_cast<int64_t>(sig) * nheap;
-  for (int j = threadIdx.x; j < NB; j += 64) {
-    const int32_t st = bstart[static_cast<int64_t>(sig) * NB + j];
-    const int32_t n = bsize[static_cast<int64_t>(sig) * NB + j];
-    s0[NB + j] = st;
-    sz[NB + j] = n;
-    cnt[NB + j] = M[st + n] - M[st];
+  if (active) {
+    for (int j = lane; j < NB; j += 64) {
+      const int32_t st = bstart[static_cast<int64_t>(sig) * NB + j];
+      const int32_t n = bsize[static_cast<int64_t>(sig) * NB + j];
+      s0[NB + j] = st;
+      sz[NB + j] = n;
+      cnt[NB + j] = M[st + n] - M[st];
+    }
+    for (int v = lane; v < nheap; v += 64) alive[v] = 0;
   }
-  for (int v = threadIdx.x; v < nheap; v += 64) alive[v] = 0;
   __syncthreads();
   for (int l = lambda - 1; l >= 0; --l) {
-    for (int v = (1 << l) + threadIdx.x; v < (2 << l); v += 64) {
-      cnt[v] = cnt[2 * v] + cnt[2 * v + 1];
-      sz[v] = sz[2 * v] + sz[2 * v + 1];
-      s0[v] = s0[2 * v];
+    if (active) {
+      for (int v = (1 << l) + lane; v < (2 << l); v += 64) {
+        cnt[v] = cnt[2 * v] + cnt[2 * v + 1];
+        sz[v] = sz[2 * v] + sz[2 * v + 1];
+        s0[v] = s0[2 * v];
+      }
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) alive[1] = 1;
+  if (active && lane == 0) alive[1] = 1;
   __syncthreads();
   for (int l = 0; l <= lambda; ++l) {
-    for (int v = (1 << l) + threadIdx.x; v < (2 << l); v += 64) {
-      const int32_t u = hn[v];
-      if (!alive[v] || u < 0 || cnt[v] == 0) continue;
-      const Node nd = nodes[u];
-      const int sign = insert ? 1 : -1;
-      if (nd.left < 0) {
-        if (insert) {
-          const int at = atomicAdd(n_regions, 1);
-          regions[at] = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
+    if (active) {
+      for (int v = (1 << l) + lane; v < (2 << l); v += 64) {
+        const int32_t u = hn[v];
+        if (!alive[v] || u < 0 || cnt[v] == 0) continue;
+        const Node nd = nodes[u];
+        const int sign = insert ? 1 : -1;
+        if (nd.left < 0) {
+          if (insert) {
+            const int at = atomicAdd(n_regions, 1);
+            regions[at] = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
+          } else {
+            nodes[u].size = nd.size - cnt[v];
+          }
+        } else if (l == lambda) {
+          killed_next[child_idx[static_cast<int64_t>(sig) * nheap + v]] = 0;
         } else {
-          nodes[u].size = nd.size - cnt[v];
-        }
-      } else if (l == lambda) {
-        killed_next[child_idx[static_cast<int64_t>(sig) * nheap + v]] = 0;
-      } else {
-        const int64_t n2 = static_cast<int64_t>(nd.size) + sign * cnt[v];
-        const int64_t l2 = static_cast<int64_t>(nodes[nd.left].size) + sign * cnt[2 * v];
-        const bool bal = n2 > 0 && (ad - 2 * an) * n2 <= 2 * ad * l2 && 2 * ad * l2 <= (ad + 2 * an) * n2;
-        if (bal) {
-          nodes[u].size = static_cast<int32_t>(n2);
-          alive[2 * v] = alive[2 * v + 1] = 1;
-        } else {
-          const int at = atomicAdd(n_regions, 1);
-          regions[at] = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
+          const int64_t n2 = static_cast<int64_t>(nd.size) + sign * cnt[v];
+          const int64_t l2 = static_cast<int64_t>(nodes[nd.left].size) + sign * cnt[2 * v];
+          const bool bal = n2 > 0 && (ad - 2 * an) * n2 <= 2 * ad * l2 && 2 * ad * l2 <= (ad + 2 * an) * n2;
+          if (bal) {
+            nodes[u].size = static_cast<int32_t>(n2);
+            alive[2 * v] = alive[2 * v + 1] = 1;
+          } else {
+            const int at = atomicAdd(n_regions, 1);
+            regions[at] = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
+          }
         }
       }
     }
     __syncthreads();
   }
-  (void)q;
 }
 
 // Region bookkeeping on the old positions: regid marks the points inside each
@@ -449,7 +518,7 @@ int route_by_sort(hipStream_t st, const Task* tasks, int ns, int64_t m, const Bu
   PKD_TRY(W.keys.need(m));
   PKD_TRY(W.vals.need(m));
   PKD_TRY(fill(st, W.task_of.p, m, -1));
-  hipLaunchKernelGGL(k_task_fill, dim3(ns), dim3(64), 0, st, tasks, W.task_of.p);
+  hipLaunchKernelGGL(k_task_fill, dim3((ns + kWaves - 1) / kWaves), dim3(64 * kWaves), 0, st, tasks, ns, W.task_of.p);
   PKD_TRY(kernel_status("k_task_fill"));
   const unsigned g = static_cast<unsigned>((m + 255) / 256);
   hipLaunchKernelGGL(k_route_keys<D>, dim3(g), dim3(256), 0, st, wb.c[src], wb.cap[src], m, W.task_of.p, tasks, rx,
@@ -461,7 +530,8 @@ int route_by_sort(hipStream_t st, const Task* tasks, int ns, int64_t m, const Bu
   PKD_TRY(fill(st, bsize, static_cast<int64_t>(ns) * NB, 0));
   hipLaunchKernelGGL(k_route_place<D>, dim3(g), dim3(256), 0, st, ks, vs, m, W.task_of.p, lambda, wb, src, dst, bsize);
   PKD_TRY(kernel_status("k_route_place"));
-  hipLaunchKernelGGL(k_route_bstart, dim3((ns + 255) / 256), dim3(256), 0, st, tasks, ns, lambda, bsize, bstart);
+  hipLaunchKernelGGL(k_route_bstart, dim3((ns + kWaves - 1) / kWaves), dim3(64 * kWaves), 0, st, tasks, ns, lambda,
+                     bsize, bstart);
   return kernel_status("k_route_bstart");
 }
 
@@ -514,7 +584,7 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   DArr<Task> cur(st), nxt(st);
   DArr<Res> res(st);
   DArr<int> ctr(st);
-  DArr<int32_t> leaf_of(st), Mw(st), M(st), bsum(st);
+  DArr<int32_t> leaf_of(st), Mw(st), M(st), bsum(st), n_go(st), n_leaf(st), off_go(st), off_leaf(st);
   PKD_TRY(wb0.need(static_cast<size_t>(D + 1) * m));
   PKD_TRY(wb1.need(static_cast<size_t>(D + 1) * m));
   PKD_TRY(wf.need(static_cast<size_t>(D + 1) * m));
@@ -530,8 +600,6 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   wb.cap[2] = 0;
   PKD_TRY(ctr.need(8));
   PKD_HIP(hipMemsetAsync(ctr.p, 0, sizeof(int) * 8, st));
-  int* d_next = ctr.p;
-  int* d_res = ctr.p + 1;
   int* d_regions = ctr.p + 2;
   PKD_TRY(res.need(static_cast<size_t>(m) + 1));
 
@@ -570,7 +638,8 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
       PKD_TRY(R->hn.need(static_cast<size_t>(ns) * nheap));
       PKD_TRY(R->child.need(static_cast<size_t>(ns) * nheap));
       PKD_HIP(hipMemsetAsync(mode.p, 0, ns, st));
-      hipLaunchKernelGGL(k_fetch_skeleton, dim3(ns), dim3(64), 0, st, cur.p, T->nodes, lambda, rx.p, rdim.p, R->hn.p);
+      hipLaunchKernelGGL(k_fetch_skeleton, dim3((ns + kWaves - 1) / kWaves), dim3(64 * kWaves), 0, st, cur.p, ns,
+                         T->nodes, lambda, rx.p, rdim.p, R->hn.p);
       PKD_TRY(kernel_status("k_fetch_skeleton"));
       const int dst = 1 - src;
       PKD_TRY(R->bsize.need(static_cast<size_t>(ns) * NB));
@@ -587,15 +656,25 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
         PKD_HIP(hipMemcpyAsync(R->bstart.p, W.bstart.p, sizeof(int32_t) * ns * NB, hipMemcpyDeviceToDevice, st));
       }
       PKD_TRY(nxt.need(static_cast<size_t>(ns) * NB));
-      PKD_HIP(hipMemsetAsync(d_next, 0, sizeof(int), st));
-      hipLaunchKernelGGL(k_route_emit, dim3(ns), dim3(64), 0, st, cur.p, T->nodes, lambda, R->hn.p, R->bsize.p,
-                         R->bstart.p, dst, nxt.p, d_next, R->child.p, res.p, d_res);
-      PKD_TRY(kernel_status("k_route_emit"));
+      PKD_TRY(n_go.need(ns));
+      PKD_TRY(n_leaf.need(ns));
+      PKD_TRY(off_go.need(ns + 1));
+      PKD_TRY(off_leaf.need(ns + 1));
+      const unsigned gw = static_cast<unsigned>((ns + kWaves - 1) / kWaves);
+      hipLaunchKernelGGL(k_route_count, dim3(gw), dim3(64 * kWaves), 0, st, cur.p, ns, T->nodes, lambda, R->hn.p,
+                         R->bsize.p, R->bstart.p, n_go.p, n_leaf.p);
+      PKD_TRY(kernel_status("k_route_count"));
+      PKD_TRY(exscan_i32(st, n_go.p, off_go.p, ns, bsum));
+      PKD_TRY(exscan_i32(st, n_leaf.p, off_leaf.p, ns, bsum));
       int h[2];
-      PKD_HIP(hipMemcpyAsync(h, ctr.p, sizeof(h), hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipMemcpyAsync(&h[0], off_go.p + ns, sizeof(int), hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipMemcpyAsync(&h[1], off_leaf.p + ns, sizeof(int), hipMemcpyDeviceToHost, st));
+      hipLaunchKernelGGL(k_route_emit, dim3(gw), dim3(64 * kWaves), 0, st, cur.p, ns, T->nodes, lambda, R->hn.p,
+                         R->bsize.p, R->bstart.p, dst, off_go.p, off_leaf.p, nres, nxt.p, R->child.p, res.p);
+      PKD_TRY(kernel_status("k_route_emit"));
       PKD_HIP(hipStreamSynchronize(st));
       ns = h[0];
-      nres = h[1];
+      nres += h[1];
       std::swap(cur.p, nxt.p);
       std::swap(cur.cap, nxt.cap);
       src = dst;
@@ -603,7 +682,8 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   }
   PKD_TRY(leaf_of.need(m));
   if (nres > 0)
-    hipLaunchKernelGGL(k_gather, dim3(nres), dim3(256), 0, st, res.p, D, wb, wf.p, m, leaf_of.p);
+    hipLaunchKernelGGL(k_gather, dim3((nres + kWaves - 1) / kWaves), dim3(64 * kWaves), 0, st, res.p, nres, D, wb,
+                       wf.p, m, leaf_of.p);
   PKD_TRY(kernel_status("k_gather"));
 
   // ---- weights: 1 per inserted point, 1 per point actually removed
@@ -655,9 +735,9 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
       const int nn = r + 1 < rounds.size() ? rounds[r + 1]->ns : 0;
       PKD_TRY(killed_next.need(static_cast<size_t>(nn) + 1));
       PKD_HIP(hipMemsetAsync(killed_next.p, 1, nn + 1, st));
-      hipLaunchKernelGGL(k_decide, dim3(R->ns), dim3(64), 0, st, R->tasks.p, lambda, R->hn.p, R->bsize.p, R->bstart.p,
-                         R->child.p, killed.p, killed_next.p, M.p, T->nodes, P.alpha_num, P.alpha_den,
-                         insert ? 1 : 0, regions.p, d_regions);
+      hipLaunchKernelGGL(k_decide, dim3((R->ns + kWaves - 1) / kWaves), dim3(64 * kWaves), 0, st, R->tasks.p, R->ns,
+                         lambda, R->hn.p, R->bsize.p, R->bstart.p, R->child.p, killed.p, killed_next.p, M.p, T->nodes,
+                         P.alpha_num, P.alpha_den, insert ? 1 : 0, regions.p, d_regions);
       PKD_TRY(kernel_status("k_decide"));
       std::swap(killed.p, killed_next.p);
       std::swap(killed.cap, killed_next.cap);
