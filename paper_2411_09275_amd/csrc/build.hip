@@ -1812,61 +1812,70 @@ __global__ void k_scan_blocks(const int32_t* in, int64_t n, int32_t* bsum) {
   if (threadIdx.x == 0) bsum[blockIdx.x] = part[0];
 }
 
-__global__ void k_scan_sums(int32_t* bsum, int64_t nb) {
-  __shared__ int64_t part[1024];
-  const int tid = threadIdx.x;
+__global__ void __launch_bounds__(1024) k_scan_sums(int32_t* bsum, int64_t nb) {
+  // exclusive scan of the block sums: each thread sums a contiguous run, the
+  // 1024 run totals are scanned by wave shuffles (16 waves, then their totals)
+  __shared__ int32_t wtot[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t per = (nb + 1023) / 1024;
   const int64_t b = tid * per, e = min(nb, b + per);
-  int64_t s = 0;
+  int32_t s = 0;
   for (int64_t i = b; i < e; ++i) s += bsum[i];
-  part[tid] = s;
+  int32_t incl = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wtot[w] = incl;
   __syncthreads();
-  if (tid == 0) {
-    int64_t a = 0;
-    for (int i = 0; i < 1024; ++i) {
-      int64_t x = part[i];
-      part[i] = a;
-      a += x;
+  if (w == 0) {
+    const int32_t x = lane < 16 ? wtot[lane] : 0;
+    int32_t wi = x;
+    for (int o = 1; o < 16; o <<= 1) {
+      const int32_t y = __shfl_up(wi, o);
+      if (lane >= o) wi += y;
     }
+    if (lane < 16) wtot[lane] = wi - x;
   }
   __syncthreads();
-  s = part[tid];
+  int32_t run = wtot[w] + incl - s;
   for (int64_t i = b; i < e; ++i) {
-    int32_t x = bsum[i];
-    bsum[i] = static_cast<int32_t>(s);
-    s += x;
+    const int32_t x = bsum[i];
+    bsum[i] = run;
+    run += x;
   }
 }
 
-__global__ void k_scan_apply(const int32_t* in, int64_t n, const int32_t* bsum, int32_t* out) {
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int32_t* in, int64_t n, const int32_t* bsum,
+                                                            int32_t* out) {
   __shared__ int32_t vals[kScanBlock];
-  __shared__ int32_t part[kScanThreads + 1];
+  __shared__ int32_t wtot[kScanThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kScanBlock;
   const int len = static_cast<int>(min<int64_t>(kScanBlock, n - b0));
-  for (int i = threadIdx.x; i < kScanBlock; i += kScanThreads) vals[i] = i < len ? in[b0 + i] : 0;
+  for (int i = tid; i < kScanBlock; i += kScanThreads) vals[i] = i < len ? in[b0 + i] : 0;
   __syncthreads();
   constexpr int per = kScanBlock / kScanThreads;
   int32_t s = 0;
-  for (int k = 0; k < per; ++k) s += vals[threadIdx.x * per + k];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int32_t a = bsum[blockIdx.x];
-    for (int i = 0; i < kScanThreads; ++i) {
-      int32_t x = part[i];
-      part[i] = a;
-      a += x;
-    }
-    part[kScanThreads] = a;
+  for (int k = 0; k < per; ++k) s += vals[tid * per + k];
+  // exclusive scan of the per-thread sums: shuffles inside each wave, then
+  // the wave totals
+  int32_t incl = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
   }
+  if (lane == 63) wtot[w] = incl;
   __syncthreads();
-  s = part[threadIdx.x];
+  int32_t before = bsum[blockIdx.x];
+  for (int j = 0; j < w; ++j) before += wtot[j];
+  int32_t run = before + incl - s;
   for (int k = 0; k < per; ++k) {
-    const int i = threadIdx.x * per + k;
-    if (i < len) out[b0 + i] = s;
-    s += vals[i];
+    const int i = tid * per + k;
+    if (i < len) out[b0 + i] = run;
+    run += vals[i];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[kScanThreads];
+  if (blockIdx.x == gridDim.x - 1 && tid == kScanThreads - 1) out[n] = run;
 }
 
 int exscan_i32(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, DArr<int32_t>& bsum) {
