@@ -1289,7 +1289,10 @@ __global__ void __launch_bounds__(64 * D) k_finish(const Task* tasks, const int*
     if (p < m) {
       const int e = O[p];
 #pragma unroll
-      for (int d = 0; d < D; ++d) Y[d * ycap + q.start + p] = static_cast<int64_t>(C[d * P + e]);
+      for (int d = 0; d < D; ++d) {
+        Y[d * ycap + q.start + p] = static_cast<int64_t>(C[d * P + e]);
+        bufs.c32[d * bufs.c32cap + q.start + p] = static_cast<int32_t>(C[d * P + e]);
+      }
       Iout[p] = idv[r];
     }
   }
@@ -1310,12 +1313,13 @@ __global__ void k_finish_heavy(const Task* tasks, const int* list, int D, Bufs b
                                int* height) {
   const Task q = tasks[list[blockIdx.x]];
   const int src = q.buf;
-  if (src != final_buf) {
-    for (int64_t i = threadIdx.x; i < q.m; i += blockDim.x) {
-      for (int d = 0; d < D; ++d)
-        bufs.c[final_buf][d * bufs.cap[final_buf] + q.start + i] = bufs.c[src][d * bufs.cap[src] + q.start + i];
-      bufs.id[final_buf][q.start + i] = bufs.id[src][q.start + i];
+  for (int64_t i = threadIdx.x; i < q.m; i += blockDim.x) {
+    for (int d = 0; d < D; ++d) {
+      const int64_t v = bufs.c[src][d * bufs.cap[src] + q.start + i];
+      if (src != final_buf) bufs.c[final_buf][d * bufs.cap[final_buf] + q.start + i] = v;
+      bufs.c32[d * bufs.c32cap + q.start + i] = static_cast<int32_t>(v);
     }
+    if (src != final_buf) bufs.id[final_buf][q.start + i] = bufs.id[src][q.start + i];
   }
   if (threadIdx.x == 0) {
     Node nd;
@@ -1521,6 +1525,9 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
   bufs.c[2] = const_cast<int64_t*>(in_c);
   bufs.id[2] = const_cast<int64_t*>(in_id);
   bufs.cap[2] = in_cap;
+  PKD_TRY(ensure_c32(T, st));
+  bufs.c32 = T->c32;
+  bufs.c32cap = T->c32_cap;
 
   DArr<Task> front(st), next(st), sieve(st), fin(st);
   DArr<int64_t> rx(st);
@@ -1968,6 +1975,42 @@ __global__ void __launch_bounds__(256) k_rs_scatter(const uint64_t* __restrict__
 }
 
 }  // namespace
+
+namespace {
+template <int D>
+__global__ void k_make_c32(const int64_t* X, int64_t cap, int64_t n, int32_t* c32) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+#pragma unroll
+    for (int d = 0; d < D; ++d) c32[d * cap + i] = static_cast<int32_t>(X[d * cap + i]);
+}
+}  // namespace
+
+int ensure_c32(pkd_tree* T, hipStream_t st) {
+  if (T->c32 && T->c32_cap == T->cap) return PKD_OK;
+  dev_free(T->c32, st);
+  T->c32 = nullptr;
+  T->c32_cap = 0;
+  void* p = nullptr;
+  PKD_TRY(dev_alloc(&p, sizeof(int32_t) * static_cast<size_t>(T->prm.D) * static_cast<size_t>(T->cap), st));
+  T->c32 = static_cast<int32_t*>(p);
+  T->c32_cap = T->cap;
+  return PKD_OK;
+}
+
+int refresh_c32(pkd_tree* T, hipStream_t st) {
+  PKD_TRY(ensure_c32(T, st));
+  if (T->n == 0) return PKD_OK;
+  const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (T->n + 255) / 256));
+  switch (T->prm.D) {
+#define PKD_C32(DD) \
+  case DD: hipLaunchKernelGGL(k_make_c32<DD>, dim3(g), dim3(256), 0, st, T->buf[T->cur], T->cap, T->n, T->c32); break;
+    PKD_C32(1) PKD_C32(2) PKD_C32(3) PKD_C32(4) PKD_C32(5) PKD_C32(6) PKD_C32(7)
+#undef PKD_C32
+    default: return PKD_ERR_UNSUPPORTED;
+  }
+  return kernel_status("k_make_c32");
+}
 
 int bits_for(int64_t v) {
   int b = 0;

@@ -252,8 +252,11 @@ void release(pkd_tree* T, hipStream_t st) {
   dev_free(T->buf[0], st);
   dev_free(T->buf[1], st);
   dev_free(T->nodes, st);
+  dev_free(T->c32, st);
   T->buf[0] = T->buf[1] = nullptr;
   T->nodes = nullptr;
+  T->c32 = nullptr;
+  T->c32_cap = 0;
 }
 
 int write_empty_root(pkd_tree* T, hipStream_t st) {

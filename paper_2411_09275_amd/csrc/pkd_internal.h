@@ -63,6 +63,8 @@ struct Bufs {
   int64_t* c[3];
   int64_t* id[3];
   int64_t cap[3];
+  int32_t* c32;    // the tree's packed 32-bit coordinates [D][c32cap] (written by the finisher)
+  int64_t c32cap;
 };
 
 struct Params {
@@ -91,6 +93,10 @@ struct pkd_tree {
   int64_t cap = 0;        // capacity of each point buffer
   int64_t* buf[2] = {nullptr, nullptr};  // buf[cur] holds the tree's points; the other is the twin
   int cur = 0;
+  // coordinates of buf[cur] as int32 [D][cap] (coordinates are below 2^30):
+  // what the query kernels scan, at half the bytes of the int64 rows
+  int32_t* c32 = nullptr;
+  int64_t c32_cap = 0;
   pkd::Node* nodes = nullptr;
   int64_t node_cap = 0;
   int32_t node_count = 0; // nodes allocated (node 0 is the root)
@@ -175,6 +181,11 @@ struct SortWork {
 int radix_sort_pairs(hipStream_t st, uint64_t* keys, uint32_t* vals, int64_t n, int nbits, SortWork& W,
                      uint64_t** kout, uint32_t** vout);
 int bits_for(int64_t v);   // bits needed to write 0 .. v
+
+// (Re)allocate the packed 32-bit coordinates for the tree's capacity, and
+// rewrite them from buf[cur] for all n points.
+int ensure_c32(pkd_tree* T, hipStream_t st);
+int refresh_c32(pkd_tree* T, hipStream_t st);
 
 // Tile layout of `ns` tasks (device array): tiles of `tile` points, scan
 // chunks; returns the numbers of tiles and chunks and the points covered.

@@ -28,10 +28,10 @@ __device__ inline bool pair_less(int64_t d2, int64_t id, int64_t cd2, int64_t ci
 // The lanes of a wave alternate between two loops: every lane descends until
 // it holds a leaf (or has nothing left), then all scan their leaves together,
 // so a leaf scan is paid once per round rather than once per node step.
-// Coordinates lie in [0, 2^30): differences fit 32 bits and only the low word
-// of each stored coordinate is read.
+// Coordinates lie in [0, 2^30): differences fit 32 bits, and the leaves are
+// scanned in the tree's packed 32-bit copy of its coordinates.
 template <int D, int KM, int SD>
-__global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes, const int64_t* __restrict__ X,
+__global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes, const int32_t* __restrict__ C32,
                                                  int64_t cap, const int64_t* __restrict__ ids,
                                                  const int64_t* __restrict__ Qry, int64_t nq, int k,
                                                  int64_t* __restrict__ out_ids, int64_t* __restrict__ out_d2,
@@ -87,7 +87,6 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
     atomicOr(flags, kErrInternal);
     return;
   }
-  const int32_t* X32 = reinterpret_cast<const int32_t*>(X);   // low words (little-endian)
   // a node is stacked at most once per level of the current path, so a valid
   // tree never needs more than its height
   Ent stk[SD];
@@ -181,7 +180,7 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
         int64_t d2 = 0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          const int32_t diff = X32[2 * (d * cap + i)] - q[d];
+          const int32_t diff = C32[d * cap + i] - q[d];
           d2 += static_cast<int64_t>(diff) * diff;
         }
         if (d2 <= bd[KR - 1]) {
@@ -303,7 +302,7 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
 // in k-NN, the lanes descend until each holds a leaf that straddles its box,
 // then scan those leaves together.
 template <int D, int SD>
-__global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ nodes, const int64_t* __restrict__ X,
+__global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ nodes, const int32_t* __restrict__ C32,
                                                    int64_t cap, const int64_t* __restrict__ Lo,
                                                    const int64_t* __restrict__ Hi, int64_t nb, int64_t* out,
                                                    int* flags, const int32_t* tree_of, int32_t n_trees, int phi,
@@ -331,7 +330,6 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
     atomicOr(flags, kErrInternal);
     return;
   }
-  const int32_t* X32 = reinterpret_cast<const int32_t*>(X);   // low words (little-endian)
   int64_t count = 0;
   struct Ent {
     int32_t node;
@@ -422,7 +420,7 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
         bool in = true;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          const int32_t v = X32[2 * (d * cap + i)];
+          const int32_t v = C32[d * cap + i];
           in &= v >= lo[d] && v <= hi[d];
         }
         c += in ? 1 : 0;
@@ -495,7 +493,7 @@ int order_queries(hipStream_t st, const int64_t* Q, int64_t nq, const int32_t* t
 }
 
 template <int D, int SD>
-void launch_knn(int km, dim3 g, hipStream_t st, const Node* nodes, const int64_t* X, int64_t cap,
+void launch_knn(int km, dim3 g, hipStream_t st, const Node* nodes, const int32_t* X, int64_t cap,
                 const int64_t* ids, const int64_t* q, int64_t nq, int k, int64_t* oi, int64_t* od, int* flags,
                 const int32_t* tree_of, int32_t n_trees, int32_t n_nodes, int64_t n_pts, const uint32_t* perm) {
 #define PKD_KNN_CASE(KM) \
@@ -524,8 +522,8 @@ int knn_d(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tr
   const uint32_t* perm = nullptr;
   PKD_TRY(order_queries<D>(st, q, nq, tree_of, T->n_trees, W, &perm));
   const dim3 g(static_cast<unsigned>((nq + kQBlock - 1) / kQBlock));
-  const int64_t* X = T->buf[T->cur];
-  const int64_t* ids = X + static_cast<int64_t>(D) * T->cap;
+  const int32_t* X = T->c32;
+  const int64_t* ids = T->buf[T->cur] + static_cast<int64_t>(D) * T->cap;
   if (T->height + 2 <= 32)
     launch_knn<D, 32>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
                       T->node_count, T->n, perm);
@@ -549,7 +547,7 @@ int range_d(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t*
   const uint32_t* perm = nullptr;
   PKD_TRY(order_queries<D>(st, lo, nb, tree_of, T->n_trees, W, &perm));   // boxes by their low corner
   const dim3 g(static_cast<unsigned>((nb + kQBlock - 1) / kQBlock));
-  const int64_t* X = T->buf[T->cur];
+  const int32_t* X = T->c32;
   if (T->height + 3 <= 48)
     hipLaunchKernelGGL((k_range<D, 48>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags, tree_of,
                        T->n_trees, T->prm.phi, T->node_count, T->n, perm);

@@ -838,7 +838,8 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     }
     PKD_TRY(build_tasks(T, st, roots, nullptr, nullptr, 0));
   }
-  return PKD_OK;
+  // the packed copy for the queries: the relayout moved every point
+  return refresh_c32(T, st);
 }
 
 }  // namespace
