@@ -70,6 +70,16 @@ __device__ inline int route(const int64_t (&c)[D], const int64_t* sx, const uint
   return v - (1 << lambda);
 }
 
+// Workgroups are handed to the 8 XCDs round robin (workgroup b runs on XCD
+// b % 8).  This maps workgroup b to a tile so that each XCD takes one
+// contiguous range of tiles: neighbouring tiles, whose output runs share
+// cache lines at their ends, then meet in the same L2.  Bijective on
+// [0, n) for any n.
+__device__ inline int64_t xcd_tile(int64_t b, int64_t n) {
+  const int64_t x = b & 7, per = n >> 3, rem = n & 7;
+  return x * per + (x < rem ? x : rem) + (b >> 3);
+}
+
 __device__ inline int find_owner(const int64_t* off, int n, int64_t t) {
   // largest s with off[s] <= t
   int lo = 0, hi = n - 1;
@@ -851,7 +861,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
   __shared__ uint8_t slab[T];
   __shared__ int sig_sh;
   const int NB = 1 << lambda;
-  const int64_t t = blockIdx.x;
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   if (tid == 0) sig_sh = find_owner(tile_off, ns, t);
   for (int i = tid; i < NCH * (1 << kMaxLambda); i += kBlock) (&cnt[0][0])[i] = 0;
