@@ -842,6 +842,39 @@ __global__ void k_apply(const int64_t* chunk_off, const int64_t* tile_off, int n
 }
 
 // ---------------------------------------------------------------- scatter
+// Same walk as route() on 32-bit values: the coordinates were range-checked
+// (below 2^30) and the all-left splitter becomes 0xFFFFFFFF, above every one.
+template <int D>
+__device__ inline int route32(const uint32_t (&c)[D], const uint32_t* sx, const uint8_t* sdim, int lambda) {
+  int v = 1;
+  for (int l = 0; l < lambda; ++l) {
+    const int d = sdim[v];
+    const uint32_t x = sx[v];
+    int ge = 0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) ge |= (d == e) & (c[e] >= x);
+    v = 2 * v + ge;
+  }
+  return v - (1 << lambda);
+}
+
+// LDS of one scatter workgroup, sized for 2^lambda buckets.
+struct ScatterLayout {
+  size_t stage, sx, cur, cnt, ls, sd, slab, end;
+  __host__ __device__ ScatterLayout(int T, int lambda) {
+    const int NB = 1 << lambda, NCH = T / 64;
+    size_t o = 0;
+    stage = o; o += sizeof(int64_t) * T;
+    sx = o;    o += sizeof(uint32_t) * NB;
+    cur = o;   o += sizeof(int32_t) * NB;
+    cnt = o;   o += sizeof(uint16_t) * NCH * NB;
+    ls = o;    o += sizeof(uint16_t) * (NB + 2);
+    sd = o;    o += NB;
+    slab = o;  o += T;
+    end = (o + 15) & ~size_t{15};
+  }
+};
+
 // Stable distribution of one tile.  Each wave ranks its 64 consecutive points
 // among equal labels with ballots; chunk counts are scanned in LDS; every
 // array (D coordinates, then ids) is staged in LDS in bucket order and written
@@ -852,25 +885,28 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
                                                     const int8_t* mode, int lambda, const int32_t* B) {
   constexpr int T = kBlock * PPT;
   constexpr int NCH = T / 64;
-  __shared__ int64_t sx[1 << kMaxLambda];
-  __shared__ uint8_t sd[1 << kMaxLambda];
-  __shared__ int32_t cur[1 << kMaxLambda];
-  __shared__ uint16_t cnt[NCH][1 << kMaxLambda];
-  __shared__ uint16_t ls[(1 << kMaxLambda) + 1];
-  __shared__ int64_t stage[T];
-  __shared__ uint8_t slab[T];
+  extern __shared__ __align__(16) unsigned char smem[];
+  const ScatterLayout lay(T, lambda);
+  int64_t* stage = reinterpret_cast<int64_t*>(smem + lay.stage);
+  uint32_t* sx = reinterpret_cast<uint32_t*>(smem + lay.sx);
+  int32_t* cur = reinterpret_cast<int32_t*>(smem + lay.cur);
+  uint16_t* cnt = reinterpret_cast<uint16_t*>(smem + lay.cnt);   // [NCH][NB]
+  uint16_t* ls = reinterpret_cast<uint16_t*>(smem + lay.ls);
+  uint8_t* sd = smem + lay.sd;
+  uint8_t* slab = smem + lay.slab;
   __shared__ int sig_sh;
   const int NB = 1 << lambda;
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   if (tid == 0) sig_sh = find_owner(tile_off, ns, t);
-  for (int i = tid; i < NCH * (1 << kMaxLambda); i += kBlock) (&cnt[0][0])[i] = 0;
+  for (int i = tid; i < NCH * NB; i += kBlock) cnt[i] = 0;
   __syncthreads();
   const int sig = sig_sh;
   if (mode[sig] == 1) return;
   const Task q = sp[sig];
   for (int j = tid; j < NB; j += kBlock) {
-    sx[j] = rx[static_cast<int64_t>(sig) * NB + j];
+    const int64_t x = rx[static_cast<int64_t>(sig) * NB + j];
+    sx[j] = x == kAllLeft ? 0xFFFFFFFFu : static_cast<uint32_t>(x);
     sd[j] = rdim[static_cast<int64_t>(sig) * NB + j];
     cur[j] = B[t * NB + j];
   }
@@ -885,40 +921,36 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
   // coordinates were range-checked before this pass: 30-bit values fit 32 bits
   uint32_t val[PPT][D];
   int64_t idv[PPT];   // ids are loaded with the coordinates so all loads are in flight together
-  int lab[PPT];
-  int rank[PPT];
+  int lr[PPT];        // label << 8 | rank among equal labels of the wave
   const int64_t* Iin = bufs.id[src];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int li = k * kBlock + tid;
     const bool ok = li < len;
     idv[k] = ok ? Iin[lo + li] : 0;
-    int label = 0;
-    if (ok) {
-      int64_t c[D];
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        c[d] = X[d * cap + lo + li];
-        val[k][d] = static_cast<uint32_t>(c[d]);
-      }
-      label = route<D>(c, sx, sd, lambda);
-    }
+    for (int d = 0; d < D; ++d) val[k][d] = ok ? static_cast<uint32_t>(X[d * cap + lo + li]) : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int li = k * kBlock + tid;
+    const bool ok = li < len;
+    const int label = ok ? route32<D>(val[k], sx, sd, lambda) : 0;
     unsigned long long peers = __ballot(ok);
     for (int b = 0; b < lambda; ++b) {
       unsigned long long m = __ballot((label >> b) & 1);
       peers &= ((label >> b) & 1) ? m : ~m;
     }
-    lab[k] = label;
-    rank[k] = __popcll(peers & lt);
+    lr[k] = (label << 8) | __popcll(peers & lt);
     const int ch = k * (kBlock / 64) + wave;
-    if (ok && (peers & lt) == 0) cnt[ch][label] = static_cast<uint16_t>(__popcll(peers));
+    if (ok && (peers & lt) == 0) cnt[ch * NB + label] = static_cast<uint16_t>(__popcll(peers));
   }
   __syncthreads();
   for (int j = tid; j < NB; j += kBlock) {
     uint16_t run = 0;
     for (int ch = 0; ch < NCH; ++ch) {
-      uint16_t x = cnt[ch][j];
-      cnt[ch][j] = run;
+      uint16_t x = cnt[ch * NB + j];
+      cnt[ch * NB + j] = run;
       run += x;
     }
     ls[j] = run;   // total of bucket j in this tile, scanned below
@@ -941,8 +973,9 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
     const int ch = k * (kBlock / 64) + wave;
     lpos[k] = -1;
     if (li < len) {
-      lpos[k] = ls[lab[k]] + cnt[ch][lab[k]] + rank[k];
-      slab[lpos[k]] = static_cast<uint8_t>(lab[k]);
+      const int label = lr[k] >> 8;
+      lpos[k] = ls[label] + cnt[ch * NB + label] + (lr[k] & 0xFF);
+      slab[lpos[k]] = static_cast<uint8_t>(label);
     }
   }
   __syncthreads();
@@ -1793,15 +1826,20 @@ int sieve_pass_d(hipStream_t st, int lambda, int tile, const Task* tasks, int ns
                      ns, lambda, W.A.p, W.S.p, W.bstart.p, W.B.p);
   PKD_TRY(kernel_status("k_apply"));
   Prof::begin(kProfScatter, st);
+#define PKD_SCATTER(PPT)                                                                                          \
+  {                                                                                                               \
+    const size_t lds = ScatterLayout(kBlock * (PPT), lambda).end;                                               \
+    PKD_TRY(allow_lds(k_scatter<D, PPT>, lds));                                                                   \
+    hipLaunchKernelGGL((k_scatter<D, PPT>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), lds, st, tasks, ns, \
+                       W.tile_off.p, bufs, src, dst, rx, rdim, mode, lambda, W.B.p);                               \
+  }
   if (tile == 2048)
-    hipLaunchKernelGGL((k_scatter<D, 8>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, tasks, ns,
-                       W.tile_off.p, bufs, src, dst, rx, rdim, mode, lambda, W.B.p);
+    PKD_SCATTER(8)
   else if (tile == 1024)
-    hipLaunchKernelGGL((k_scatter<D, 4>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, tasks, ns,
-                       W.tile_off.p, bufs, src, dst, rx, rdim, mode, lambda, W.B.p);
+    PKD_SCATTER(4)
   else
-    hipLaunchKernelGGL((k_scatter<D, 16>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, tasks, ns,
-                       W.tile_off.p, bufs, src, dst, rx, rdim, mode, lambda, W.B.p);
+    PKD_SCATTER(16)
+#undef PKD_SCATTER
   Prof::end(kProfScatter, st, 2.0 * (8.0 * D + 8.0) * static_cast<double>(pts));
   PKD_TRY(kernel_status("k_scatter"));
   return PKD_OK;
