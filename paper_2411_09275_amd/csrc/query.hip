@@ -18,7 +18,8 @@ __device__ inline bool pair_less(int64_t d2, int64_t id, int64_t cd2, int64_t ci
   return d2 < cd2 || (d2 == cd2 && id < cid);
 }
 
-// Exact k nearest (squared distance, id) pairs, k <= KM, candidates kept as a
+// Exact k nearest (squared distance, id) pairs for k <= 16, one lane per
+// query: k <= KM (a power of two up to 16), candidates kept as a
 // sorted array in registers.  The first KM-k slots hold sentinels that are
 // smaller than any real pair, so the k-th best is always slot KM-1.
 // Depth-first: the nearer child first; the farther child is stacked with the
@@ -52,26 +53,14 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
     atomicOr(flags, kErrRange);
     return;
   }
-  // KM > 0: the k best pairs sorted in registers (slots 0..KM-k-1 hold
-  // sentinels smaller than any pair).  KM == 0 (k > 16): a binary max-heap of
-  // the k best pairs kept in the query's own output row, root = the worst.
-  constexpr int KR = KM > 0 ? KM : 1;
+  // the k best pairs sorted in registers; slots 0..KM-k-1 hold sentinels
+  // smaller than any pair
+  constexpr int KR = KM;
   int64_t bd[KR], bi[KR];
-  int64_t* Hd = out_d2 + j * k;
-  int64_t* Hi = out_ids + j * k;
-  if constexpr (KM > 0) {
 #pragma unroll
-    for (int i = 0; i < KM; ++i) {
-      bd[i] = (i < KM - k) ? -1 : INT64_MAX;
-      bi[i] = (i < KM - k) ? INT64_MIN : INT64_MAX;
-    }
-  } else {
-    for (int i = 0; i < k; ++i) {
-      Hd[i] = INT64_MAX;
-      Hi[i] = INT64_MAX;
-    }
-    bd[0] = INT64_MAX;   // the root (k-th best so far)
-    bi[0] = INT64_MAX;
+  for (int i = 0; i < KM; ++i) {
+    bd[i] = (i < KM - k) ? -1 : INT64_MAX;
+    bi[i] = (i < KM - k) ? INT64_MIN : INT64_MAX;
   }
 
   // a stacked cell: its node and its per-dimension distances from q; the
@@ -186,57 +175,18 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
         if (d2 <= bd[KR - 1]) {
           const int64_t id = ids[i];
           if (pair_less(d2, id, bd[KR - 1], bi[KR - 1])) {
-            if constexpr (KM == 0) {
-              // replace the root and sift the new pair down
-              int p = 0;
-              while (true) {
-                int c = 2 * p + 1;
-                if (c >= k) break;
-                int64_t cd = Hd[c], ci = Hi[c];
-                if (c + 1 < k) {
-                  const int64_t rd = Hd[c + 1], ri = Hi[c + 1];
-                  if (pair_less(cd, ci, rd, ri)) {
-                    c = c + 1;
-                    cd = rd;
-                    ci = ri;
-                  }
-                }
-                if (!pair_less(d2, id, cd, ci)) break;
-                Hd[p] = cd;
-                Hi[p] = ci;
-                p = c;
-              }
-              Hd[p] = d2;
-              Hi[p] = id;
-              bd[0] = Hd[0];
-              bi[0] = Hi[0];
-              continue;
-            }
-            if constexpr (KM > 0 && KM <= 16) {
-              // short lists: drop the worst, then bubble the new pair down
-              bd[KR - 1] = d2;
-              bi[KR - 1] = id;
-#pragma unroll
-              for (int t = KR - 1; t > 0; --t) {
-                const bool sw = pair_less(bd[t], bi[t], bd[t - 1], bi[t - 1]);
-                const int64_t x0 = bd[t - 1], y0 = bi[t - 1];
-                bd[t - 1] = sw ? bd[t] : x0;
-                bi[t - 1] = sw ? bi[t] : y0;
-                bd[t] = sw ? x0 : bd[t];
-                bi[t] = sw ? y0 : bi[t];
-              }
-              continue;
-            }
+            // drop the worst, then bubble the new pair down
+            bd[KR - 1] = d2;
+            bi[KR - 1] = id;
 #pragma unroll
             for (int t = KR - 1; t > 0; --t) {
-              const bool shift = pair_less(d2, id, bd[t - 1], bi[t - 1]);
-              const bool here = !shift && pair_less(d2, id, bd[t], bi[t]);
-              bd[t] = shift ? bd[t - 1] : (here ? d2 : bd[t]);
-              bi[t] = shift ? bi[t - 1] : (here ? id : bi[t]);
+              const bool sw = pair_less(bd[t], bi[t], bd[t - 1], bi[t - 1]);
+              const int64_t x0 = bd[t - 1], y0 = bi[t - 1];
+              bd[t - 1] = sw ? bd[t] : x0;
+              bi[t - 1] = sw ? bi[t] : y0;
+              bd[t] = sw ? x0 : bd[t];
+              bi[t] = sw ? y0 : bi[t];
             }
-            const bool first = pair_less(d2, id, bd[0], bi[0]);
-            bd[0] = first ? d2 : bd[0];
-            bi[0] = first ? id : bi[0];
           }
         }
       }
@@ -247,53 +197,249 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
     atomicOr(flags, fail_bits);
     return;
   }
-  if constexpr (KM == 0) {
-    // heapsort in place: ascending pairs, unfilled slots (+inf) last
-    for (int end = k - 1; end > 0; --end) {
-      const int64_t td = Hd[0], ti = Hi[0];
-      const int64_t xd = Hd[end], xi = Hi[end];
-      Hd[end] = td;
-      Hi[end] = ti;
-      int p = 0;
-      while (true) {
-        int c = 2 * p + 1;
-        if (c >= end) break;
-        int64_t cd = Hd[c], ci = Hi[c];
-        if (c + 1 < end) {
-          const int64_t rd = Hd[c + 1], ri = Hi[c + 1];
-          if (pair_less(cd, ci, rd, ri)) {
-            c = c + 1;
-            cd = rd;
-            ci = ri;
-          }
-        }
-        if (!pair_less(xd, xi, cd, ci)) break;
-        Hd[p] = cd;
-        Hi[p] = ci;
-        p = c;
-      }
-      Hd[p] = xd;
-      Hi[p] = xi;
-    }
-    for (int i = 0; i < k; ++i) {
-      if (Hd[i] == INT64_MAX) {
-        Hd[i] = -1;
-        Hi[i] = -1;
-      }
-    }
-  } else {
-    for (int i = 0; i < k; ++i) {
-      // slot KM-k+i holds the i-th nearest; unfilled slots are +inf
-      int64_t cd = bd[0], ci = bi[0];
+  for (int i = 0; i < k; ++i) {
+    // slot KM-k+i holds the i-th nearest; unfilled slots are +inf
+    int64_t cd = bd[0], ci = bi[0];
 #pragma unroll
-      for (int t = 1; t < KM; ++t) {
-        cd = (t == KM - k + i) ? bd[t] : cd;
-        ci = (t == KM - k + i) ? bi[t] : ci;
-      }
-      const bool have = cd != INT64_MAX;
-      out_d2[j * k + i] = have ? cd : -1;
-      out_ids[j * k + i] = have ? ci : -1;
+    for (int t = 1; t < KM; ++t) {
+      cd = (t == KM - k + i) ? bd[t] : cd;
+      ci = (t == KM - k + i) ? bi[t] : ci;
     }
+    const bool have = cd != INT64_MAX;
+    out_d2[j * k + i] = have ? cd : -1;
+    out_ids[j * k + i] = have ? ci : -1;
+  }
+}
+
+// --------------------------------------------------------- k-NN, larger k
+// k = 17..128: one wave answers one query.  The wave walks a single
+// path (every lane takes the same branch, so nothing diverges), its 64 lanes
+// scan a leaf's points together, and the k best pairs are one sorted list in
+// the wave's LDS.  A leaf's accepted pairs are sorted across the wave by a
+// bitonic network and merged into the list (each pair's new place is its own
+// index plus its rank in the other sorted sequence).  Traversal order, the
+// pruning bound and the tie rule are those of k_knn, so the results are the
+// same (the k best pairs are unique).
+struct WaveKnnLayout {
+  size_t ld0, li0, ld1, li1, cd, ci, stk, end;   // byte offsets inside one wave's slice
+  __host__ __device__ WaveKnnLayout(int D, int SD, int k) {
+    size_t o = 0;
+    ld0 = o; o += sizeof(int64_t) * k;
+    li0 = o; o += sizeof(int64_t) * k;
+    ld1 = o; o += sizeof(int64_t) * k;
+    li1 = o; o += sizeof(int64_t) * k;
+    cd = o;  o += sizeof(int64_t) * 64;
+    ci = o;  o += sizeof(int64_t) * 64;
+    stk = o; o += sizeof(int32_t) * SD * (1 + D);
+    end = (o + 15) & ~size_t{15};
+  }
+};
+
+// Orders the LDS accesses of one wave: what a lane wrote is seen by every
+// lane of the wave after this point.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int64_t shfl_xor_i64(int64_t v, int mask) {
+  const int lo = __shfl_xor(static_cast<int>(static_cast<uint32_t>(v)), mask);
+  const int hi = __shfl_xor(static_cast<int>(static_cast<uint64_t>(v) >> 32), mask);
+  return static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo));
+}
+
+// Ascending bitonic sort of one (d2, id) pair per lane across the wave.
+__device__ inline void wave_sort_pairs(int64_t& d2, int64_t& id) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+    for (int j = size >> 1; j > 0; j >>= 1) {
+      const int64_t od = shfl_xor_i64(d2, j), oi = shfl_xor_i64(id, j);
+      const bool keep_min = ((lane & j) == 0) == ((lane & size) == 0);
+      const bool take = keep_min ? pair_less(od, oi, d2, id) : pair_less(d2, id, od, oi);
+      d2 = take ? od : d2;
+      id = take ? oi : id;
+    }
+  }
+}
+
+template <int D, int SD>
+__global__ void __launch_bounds__(kQBlock) k_knn_wave(const Node* __restrict__ nodes, const int32_t* __restrict__ C32,
+                                                      int64_t cap, const int64_t* __restrict__ ids,
+                                                      const int64_t* __restrict__ Qry, int64_t nq, int k,
+                                                      int64_t* __restrict__ out_ids, int64_t* __restrict__ out_d2,
+                                                      int* flags, const int32_t* tree_of, int32_t n_trees,
+                                                      int32_t n_nodes, int64_t n_pts, const uint32_t* __restrict__ perm) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int WPB = kQBlock / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const WaveKnnLayout lay(D, SD, k);
+  unsigned char* mine = smem + wave * lay.end;
+  int64_t* Ld[2] = {reinterpret_cast<int64_t*>(mine + lay.ld0), reinterpret_cast<int64_t*>(mine + lay.ld1)};
+  int64_t* Li[2] = {reinterpret_cast<int64_t*>(mine + lay.li0), reinterpret_cast<int64_t*>(mine + lay.li1)};
+  int64_t* Cd = reinterpret_cast<int64_t*>(mine + lay.cd);
+  int64_t* Ci = reinterpret_cast<int64_t*>(mine + lay.ci);
+  int32_t* stk = reinterpret_cast<int32_t*>(mine + lay.stk);   // [SD][1 + D]: node, then offsets
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * WPB;
+  for (int64_t j0 = static_cast<int64_t>(blockIdx.x) * WPB + wave; j0 < nq; j0 += waves) {
+    const int64_t j = perm ? static_cast<int64_t>(perm[j0]) : j0;
+    int32_t q[D];
+    bool bad = false;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int64_t v = Qry[d * nq + j];
+      bad |= static_cast<uint64_t>(v) >= static_cast<uint64_t>(kCoordLimit);
+      q[d] = static_cast<int32_t>(v);
+    }
+    if (bad) {
+      if (lane == 0) atomicOr(flags, kErrRange);
+      continue;
+    }
+    const int32_t root = tree_of ? tree_of[j] : 0;
+    if (static_cast<uint32_t>(root) >= static_cast<uint32_t>(n_trees)) {
+      if (lane == 0) atomicOr(flags, kErrInternal);
+      continue;
+    }
+    int cur = 0;
+    for (int e = lane; e < k; e += 64) {
+      Ld[0][e] = INT64_MAX;
+      Li[0][e] = INT64_MAX;
+    }
+    wave_sync();
+    int64_t wd = INT64_MAX, wi = INT64_MAX;   // the k-th best pair so far
+    int sp = 0;
+    int32_t node = root;
+    int64_t lb = 0;
+    int32_t off[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) off[d] = 0;
+    int32_t visits = 0;
+    int fail_bits = 0;
+    while (true) {
+      if (node < 0) {
+        if (sp == 0) break;
+        --sp;
+        node = stk[sp * (1 + D)];
+        lb = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          off[d] = stk[sp * (1 + D) + 1 + d];
+          lb += static_cast<int64_t>(off[d]) * off[d];
+        }
+        if (lb > wd) {
+          node = -1;
+          continue;
+        }
+      }
+      if (static_cast<uint32_t>(node) >= static_cast<uint32_t>(n_nodes) || ++visits > n_nodes) {
+        fail_bits = kErrInternal;
+        break;
+      }
+      const Node nd = nodes[node];
+      if (nd.left < 0) {
+        if (nd.off < 0 || nd.size < 0 || static_cast<int64_t>(nd.off) + nd.size > n_pts) {
+          fail_bits = kErrInternal;
+          break;
+        }
+        const int64_t e = static_cast<int64_t>(nd.off) + nd.size;
+        for (int64_t b = nd.off; b < e; b += 64) {
+          const int64_t i = b + lane;
+          int64_t d2 = INT64_MAX, id = INT64_MAX;
+          bool acc = false;
+          if (i < e) {
+            int64_t s = 0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              const int32_t diff = C32[d * cap + i] - q[d];
+              s += static_cast<int64_t>(diff) * diff;
+            }
+            if (s <= wd) {
+              const int64_t x = ids[i];
+              if (pair_less(s, x, wd, wi)) {
+                acc = true;
+                d2 = s;
+                id = x;
+              }
+            }
+          }
+          const unsigned long long am = __ballot(acc);
+          if (am == 0) continue;
+          const int c = __popcll(am);
+          wave_sort_pairs(d2, id);   // the c accepted pairs come first
+          Cd[lane] = d2;
+          Ci[lane] = id;
+          wave_sync();
+          const int nx = cur ^ 1;
+          for (int t = lane; t < k; t += 64) {
+            // list entry t moves up by the candidates below it
+            const int64_t xd = Ld[cur][t], xi = Li[cur][t];
+            int lo = 0, hi = c;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (pair_less(Cd[mid], Ci[mid], xd, xi)) lo = mid + 1; else hi = mid;
+            }
+            if (t + lo < k) {
+              Ld[nx][t + lo] = xd;
+              Li[nx][t + lo] = xi;
+            }
+          }
+          if (lane < c) {
+            // candidate `lane` goes after every list entry not above it
+            int lo = 0, hi = k;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (pair_less(d2, id, Ld[cur][mid], Li[cur][mid])) hi = mid; else lo = mid + 1;
+            }
+            if (lane + lo < k) {
+              Ld[nx][lane + lo] = d2;
+              Li[nx][lane + lo] = id;
+            }
+          }
+          wave_sync();
+          cur = nx;
+          wd = Ld[cur][k - 1];
+          wi = Li[cur][k - 1];
+        }
+        node = -1;
+        continue;
+      }
+      int32_t qd = q[0], od = off[0];
+#pragma unroll
+      for (int d = 1; d < D; ++d) {
+        qd = (nd.dim == d) ? q[d] : qd;
+        od = (nd.dim == d) ? off[d] : od;
+      }
+      const bool go_left = qd < nd.x;
+      const int32_t near = go_left ? nd.left : nd.right;
+      const int32_t far = go_left ? nd.right : nd.left;
+      const int64_t fo = go_left ? nd.x - qd : static_cast<int64_t>(qd) - nd.x + 1;
+      const int64_t flb = lb - static_cast<int64_t>(od) * od + fo * fo;
+      if (flb <= wd) {
+        if (sp >= SD) {
+          fail_bits = kErrStack;
+          break;
+        }
+        stk[sp * (1 + D)] = far;
+#pragma unroll
+        for (int d = 0; d < D; ++d) stk[sp * (1 + D) + 1 + d] = (nd.dim == d) ? static_cast<int32_t>(fo) : off[d];
+        ++sp;
+      }
+      node = near;
+    }
+    if (fail_bits) {
+      if (lane == 0) atomicOr(flags, fail_bits);
+      wave_sync();
+      continue;
+    }
+    for (int t = lane; t < k; t += 64) {
+      const int64_t cd = Ld[cur][t];
+      const bool have = cd != INT64_MAX;
+      out_d2[j * k + t] = have ? cd : -1;
+      out_ids[j * k + t] = have ? Li[cur][t] : -1;
+    }
+    wave_sync();   // the next query rewrites the list
   }
 }
 
@@ -507,8 +653,16 @@ void launch_knn(int km, dim3 g, hipStream_t st, const Node* nodes, const int32_t
     PKD_KNN_CASE(4)
     PKD_KNN_CASE(8)
     PKD_KNN_CASE(16)
-    default:
-      PKD_KNN_CASE(0)
+    default: {
+      // k > 16: one wave per query (measured faster than a persistent grid
+      // sized to the resident workgroups: the dispatcher balances the uneven
+      // query costs); the kernel still strides if the grid is capped
+      const size_t lds = (kQBlock / 64) * WaveKnnLayout(D, SD, k).end;
+      const int64_t need = (nq + kQBlock / 64 - 1) / (kQBlock / 64);
+      const dim3 gw(static_cast<unsigned>(std::min<int64_t>(need, INT32_MAX)));
+      hipLaunchKernelGGL((k_knn_wave<D, SD>), gw, dim3(kQBlock), lds, st, nodes, X, cap, ids, q, nq, k, oi, od,
+                         flags, tree_of, n_trees, n_nodes, n_pts, perm);
+    }
   }
 #undef PKD_KNN_CASE
 }

@@ -136,7 +136,9 @@ def test_out_of_range_coordinates_rejected(pk):
 # --------------------------------------------------------------------- queries
 @pytest.mark.parametrize("D,n,k,hi", [(2, 100000, 10, 10 ** 9), (3, 200000, 1, 10 ** 9), (3, 100000, 16, 10 ** 9),
                                       (2, 50000, 7, 300), (1, 20000, 5, 1000), (5, 40000, 10, 10 ** 6),
-                                      (3, 30000, 100, 10 ** 9), (2, 20, 10, 10 ** 9), (3, 50000, 33, 10 ** 9)])
+                                      (3, 30000, 100, 10 ** 9), (2, 20, 10, 10 ** 9), (3, 50000, 33, 10 ** 9),
+                                      (2, 20, 100, 10 ** 9), (3, 50000, 128, 10 ** 9), (2, 50000, 17, 300),
+                                      (4, 30000, 64, 10 ** 9)])
 def test_knn_matches_definition(orc, pk, D, n, k, hi):
     c, i = synth.uniform_points(n, D, seed=20 + D, hi=hi)
     q = synth.uniform_queries(500, D, seed=21, hi=hi)
@@ -150,13 +152,16 @@ def test_knn_matches_definition(orc, pk, D, n, k, hi):
 def test_knn_empty_tree_and_duplicates(orc, pk):
     q = synth.uniform_queries(50, 2, seed=22)
     t = pk.Tree(pk.Params(2), np.zeros((2, 0), dtype=np.int64), np.zeros(0, dtype=np.int64))
-    gi, gd = t.knn(q, 5)
-    assert (gi.cpu().numpy() == -1).all() and (gd.cpu().numpy() == -1).all()
+    for k in (5, 40):
+        gi, gd = t.knn(q, k)
+        assert (gi.cpu().numpy() == -1).all() and (gd.cpu().numpy() == -1).all()
+    # heavy leaves of identical points, scanned in several passes of 64 by the wave kernel
     c, i = synth.duplicate_heavy_points(30000, 2, seed=23, n_distinct=30)
     t = pk.Tree(pk.Params(2), c, i)
-    gi, gd = t.knn(q, 10)
-    bi, bd = orc.brute_knn(c, i, q, 10)
-    assert np.array_equal(gi.cpu().numpy(), bi) and np.array_equal(gd.cpu().numpy(), bd)
+    for k in (10, 100):
+        gi, gd = t.knn(q, k)
+        bi, bd = orc.brute_knn(c, i, q, k)
+        assert np.array_equal(gi.cpu().numpy(), bi) and np.array_equal(gd.cpu().numpy(), bd), k
 
 
 @pytest.mark.parametrize("D,hi,dups", [(2, 10 ** 9, 0), (3, 10 ** 9, 0), (2, 60, 0), (2, 10 ** 9, 25)])
@@ -230,7 +235,7 @@ def test_batch_build_equals_single_builds(orc, pk):
 # ------------------------------------------------ large batches (spatial order)
 # Batches of at least 16384 queries are processed in Morton order; every
 # result must still land in its own row and equal the oracle's.
-@pytest.mark.parametrize("D,nq,k", [(3, 40000, 10), (2, 16384, 1), (5, 20000, 7), (1, 30000, 3)])
+@pytest.mark.parametrize("D,nq,k", [(3, 40000, 10), (2, 16384, 1), (5, 20000, 7), (1, 30000, 3), (3, 40000, 100)])
 def test_knn_large_batch_matches_oracle(orc, pk, D, nq, k):
     c, i = synth.uniform_points(120000, D, seed=40 + D)
     q = synth.uniform_queries(nq, D, seed=41)
