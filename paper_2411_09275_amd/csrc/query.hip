@@ -265,6 +265,8 @@ __device__ inline void wave_sort_pairs(int64_t& d2, int64_t& id) {
   }
 }
 
+constexpr int kFewPairs = 4;   // a leaf adding at most this many pairs skips the sort
+
 template <int D, int SD>
 __global__ void __launch_bounds__(kQBlock) k_knn_wave(const Node* __restrict__ nodes, const int32_t* __restrict__ C32,
                                                       int64_t cap, const int64_t* __restrict__ ids,
@@ -367,11 +369,73 @@ __global__ void __launch_bounds__(kQBlock) k_knn_wave(const Node* __restrict__ n
           const unsigned long long am = __ballot(acc);
           if (am == 0) continue;
           const int c = __popcll(am);
+          const int nx = cur ^ 1;
+          if (c <= kFewPairs) {
+            // few pairs: no sort.  They are compacted to slots 0..c-1; every
+            // list entry moves up by the pairs below it, and pair u lands
+            // after the list entries not above it and the pairs before it
+            // (ties: list entries first, then pairs by slot).  k <= 128, so
+            // lane l holds list entries l and l + 64.
+            if (acc) {
+              const int r = __popcll(am & ((1ULL << lane) - 1));
+              Cd[r] = d2;
+              Ci[r] = id;
+            }
+            wave_sync();
+            int64_t pd[kFewPairs], pi[kFewPairs];
+#pragma unroll
+            for (int u = 0; u < kFewPairs; ++u) {
+              pd[u] = u < c ? Cd[u] : INT64_MAX;
+              pi[u] = u < c ? Ci[u] : INT64_MAX;
+            }
+            int mypos = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int t = lane + 64 * h;
+              const bool have = t < k;
+              const int64_t xd = have ? Ld[cur][t] : INT64_MAX, xi = have ? Li[cur][t] : INT64_MAX;
+              int below = 0;
+#pragma unroll
+              for (int u = 0; u < kFewPairs; ++u) below += (u < c && pair_less(pd[u], pi[u], xd, xi)) ? 1 : 0;
+              if (have && t + below < k) {
+                Ld[nx][t + below] = xd;
+                Li[nx][t + below] = xi;
+              }
+#pragma unroll
+              for (int u = 0; u < kFewPairs; ++u) {
+                if (u < c) {
+                  const int n_le = __popcll(__ballot(have && !pair_less(pd[u], pi[u], xd, xi)));
+                  mypos += lane == u ? n_le : 0;
+                }
+              }
+            }
+            if (lane < c) {
+              int64_t sd = pd[0], si = pi[0];
+#pragma unroll
+              for (int u = 1; u < kFewPairs; ++u) {
+                sd = lane == u ? pd[u] : sd;
+                si = lane == u ? pi[u] : si;
+              }
+              int before = 0;
+#pragma unroll
+              for (int u = 0; u < kFewPairs; ++u)
+                before += (u < c && (pair_less(pd[u], pi[u], sd, si) || (u < lane && pd[u] == sd && pi[u] == si)))
+                              ? 1 : 0;
+              if (mypos + before < k) {
+                Ld[nx][mypos + before] = sd;
+                Li[nx][mypos + before] = si;
+              }
+            }
+            wave_sync();
+            cur = nx;
+            wd = Ld[cur][k - 1];
+            wi = Li[cur][k - 1];
+            continue;
+          }
           wave_sort_pairs(d2, id);   // the c accepted pairs come first
           Cd[lane] = d2;
           Ci[lane] = id;
           wave_sync();
-          const int nx = cur ^ 1;
           for (int t = lane; t < k; t += 64) {
             // list entry t moves up by the candidates below it
             const int64_t xd = Ld[cur][t], xi = Li[cur][t];
