@@ -19,7 +19,7 @@ __device__ inline bool pair_less(int64_t d2, int64_t id, int64_t cd2, int64_t ci
 }
 
 // Exact k nearest (squared distance, id) pairs for k <= 16, one lane per
-// query: k <= KM (a power of two up to 16), candidates kept as a
+// query: k <= KM (10 for k = 9, 10, else a power of two up to 16), candidates kept as a
 // sorted array in registers.  The first KM-k slots hold sentinels that are
 // smaller than any real pair, so the k-th best is always slot KM-1.
 // Depth-first: the nearer child first; the farther child is stacked with the
@@ -716,6 +716,7 @@ void launch_knn(int km, dim3 g, hipStream_t st, const Node* nodes, const int32_t
     PKD_KNN_CASE(2)
     PKD_KNN_CASE(4)
     PKD_KNN_CASE(8)
+    PKD_KNN_CASE(10)
     PKD_KNN_CASE(16)
     default: {
       // k > 16: one wave per query (measured faster than a persistent grid
@@ -736,6 +737,7 @@ int knn_d(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tr
           int64_t* oi, int64_t* od, int* flags) {
   int km = 1;
   while (km < k) km <<= 1;
+  if (k == 9 || k == 10) km = 10;   // the common k = 10 without six idle slots
   QueryOrder W(st);
   const uint32_t* perm = nullptr;
   PKD_TRY(order_queries<D>(st, q, nq, tree_of, T->n_trees, W, &perm));

@@ -138,7 +138,7 @@ def test_out_of_range_coordinates_rejected(pk):
                                       (2, 50000, 7, 300), (1, 20000, 5, 1000), (5, 40000, 10, 10 ** 6),
                                       (3, 30000, 100, 10 ** 9), (2, 20, 10, 10 ** 9), (3, 50000, 33, 10 ** 9),
                                       (2, 20, 100, 10 ** 9), (3, 50000, 128, 10 ** 9), (2, 50000, 17, 300),
-                                      (4, 30000, 64, 10 ** 9)])
+                                      (4, 30000, 64, 10 ** 9), (3, 60000, 9, 10 ** 9), (2, 40000, 10, 200)])
 def test_knn_matches_definition(orc, pk, D, n, k, hi):
     c, i = synth.uniform_points(n, D, seed=20 + D, hi=hi)
     q = synth.uniform_queries(500, D, seed=21, hi=hi)
