@@ -305,7 +305,7 @@ def bench_serving(a):
                 r.arrival = 0.0
         lat = latency_stats(reqs)
         busy = {kd: sum(r.done - r.start for r in reqs if r.kind == kd) for kd in ("insert", "delete", "knn")}
-        log("  makespan %.3f s, p50 %.2f ms, p99 %.2f ms, %d batches / %d launches; service s: %s" % (
+        log("  makespan %.3f s, p50 %.2f ms, p99 %.2f ms, %d batches / %d launches; sum of per-request start-to-done s: %s" % (
             span, lat["p50_ms"], lat["p99_ms"], srv.batches, srv.launches,
             ", ".join("%s %.3f" % kv for kv in busy.items())))
         return span, lat, digest, srv.batches

@@ -21,10 +21,16 @@ batch i+1's upload runs while batch i computes, and batch i's download while
 batch i+1 computes.  Each in-flight slot owns pinned staging buffers for
 queries and results that grow when a batch needs more and are otherwise
 reused (batch i uses slot i mod max_inflight, which batch i - max_inflight
-has released), so no pinned memory is allocated per batch.  Requests that
-arrive while batches are in flight join the next batch.  An update first
-waits for the batches in flight to finish (it rewrites the tree), then runs on
-the compute stream with the blocking calls.
+has released), so no pinned memory is allocated per batch.  A retire thread
+waits for each batch's download and copies every request's rows out of the
+slot's buffers into the request's own host arrays, in row chunks spread over
+a few copy threads (the copy is bound by the first touch of those fresh
+pages); it overlaps the next batches' transfers and kernels instead of
+holding up the issuing loop.  A batch stays in flight,
+holding its slot, until its copy is done.  Requests that arrive while batches
+are in flight join the next batch.  An update first waits for the batches in
+flight to finish (it rewrites the tree), then runs on the compute stream with
+the blocking calls.
 
 The serial reference (mode "serial") handles each request alone, in arrival
 order, with the blocking calls.
@@ -32,6 +38,7 @@ order, with the blocking calls.
 from __future__ import annotations
 
 import collections
+import concurrent.futures
 import time
 from dataclasses import dataclass
 
@@ -61,16 +68,20 @@ class Request:
 
 
 class _Batch:
-    __slots__ = ("groups", "event", "status", "nbytes")
+    __slots__ = ("groups", "event", "status", "nbytes", "retired")
 
     def __init__(self, groups, event, status, nbytes):
         self.groups = groups      # [(requests, host ids, host d2)]
         self.event = event        # recorded on the download stream after the last copy
         self.status = status
         self.nbytes = nbytes
+        self.retired = None       # future of the retire thread's copy-out
 
 
 class Server:
+    COPY_THREADS = 8
+    COPY_CHUNK_BYTES = 16 << 20
+
     def __init__(self, tree, dim, max_inflight=3, max_batch_queries=4_000_000, hbm_reserve_bytes=4 << 30,
                  budget_bytes=None):
         import torch
@@ -89,6 +100,10 @@ class Server:
         self.launches = 0         # k-NN launches issued by the last run
         self._stage = [dict() for _ in range(max_inflight)]
         self._issued = 0
+        self._retirer = concurrent.futures.ThreadPoolExecutor(max_workers=1)
+        # copying results out of the pinned buffers into fresh host arrays is
+        # bound by first-touch page faults: several threads copy row chunks
+        self._copiers = concurrent.futures.ThreadPoolExecutor(max_workers=self.COPY_THREADS)
 
     def _pinned(self, slot, name, n):
         """A pinned int64 buffer of at least n elements owned by `slot`."""
@@ -180,23 +195,44 @@ class Server:
         ev.record(self.download)
         self.inflight_bytes += nbytes
         self.batches += 1
-        return _Batch(groups, ev, status, nbytes)
+        b = _Batch(groups, ev, status, nbytes)
+        b.retired = self._retirer.submit(self._copy_out, b, now)
+        return b
 
-    def _retire(self, b, now):
+    def _copy_out(self, b, now):
+        """Retire thread: wait for the batch's download, check its status and
+        copy each request's rows into arrays of its own."""
         b.event.synchronize()
-        self.inflight_bytes -= b.nbytes
         st = int(b.status.item())
         if st != 0:
             raise RuntimeError("k-NN batch reported device status %d" % st)
-        t = now()
+        jobs = []
         for rs, hi, hd in b.groups:
             hi, hd = hi.numpy(), hd.numpy()
+            k = hi.shape[1]
+            rows = max(1, self.COPY_CHUNK_BYTES // (8 * k))
             at = 0
             for r in rs:
                 m = r.size
-                r.result = (hi[at:at + m].copy(), hd[at:at + m].copy())
-                r.done = t
+                oi = np.empty((m, k), dtype=np.int64)
+                od = np.empty((m, k), dtype=np.int64)
+                r.result = (oi, od)
+                for a in range(0, m, rows):
+                    e = min(m, a + rows)
+                    jobs.append(self._copiers.submit(np.copyto, oi[a:e], hi[at + a:at + e]))
+                    jobs.append(self._copiers.submit(np.copyto, od[a:e], hd[at + a:at + e]))
                 at += m
+        for j in jobs:
+            j.result()
+        t = now()
+        for rs, _, _ in b.groups:
+            for r in rs:
+                r.done = t
+
+    def _retire(self, b):
+        """Wait until the batch's results are copied out; frees its slot."""
+        b.retired.result()        # re-raises what the retire thread raised
+        self.inflight_bytes -= b.nbytes
 
     # ---------------------------------------------------------------- run
     def run(self, requests, mode="continuous", realtime=True):
@@ -235,8 +271,8 @@ class Server:
             while i < len(reqs) and arr(reqs[i]) <= t:
                 ready.append(reqs[i])
                 i += 1
-            while inflight and inflight[0].event.query():
-                self._retire(inflight.popleft(), now)
+            while inflight and inflight[0].retired.done():
+                self._retire(inflight.popleft())
             if not ready:
                 if inflight:
                     time.sleep(2e-5)
@@ -247,11 +283,11 @@ class Server:
                 continue
             if ready[0].kind != "knn":
                 while inflight:
-                    self._retire(inflight.popleft(), now)
+                    self._retire(inflight.popleft())
                 self._run_update(ready.popleft(), now)
                 continue
             if len(inflight) >= self.max_inflight:
-                self._retire(inflight.popleft(), now)
+                self._retire(inflight.popleft())
                 continue
             batch, nq, nbytes = [], 0, 0
             while ready and ready[0].kind == "knn":
@@ -265,7 +301,7 @@ class Server:
                 nq += r.size
                 nbytes += need
             if not batch:
-                self._retire(inflight.popleft(), now)   # wait for memory held by batches in flight
+                self._retire(inflight.popleft())   # wait for memory held by batches in flight
                 continue
             inflight.append(self._issue(batch, nbytes, now))
         torch.cuda.synchronize()
