@@ -510,36 +510,14 @@ __global__ void __launch_bounds__(kQBlock) k_knn_wave(const Node* __restrict__ n
 // Range count: a node whose cell lies inside the box contributes its stored
 // subtree size; a disjoint cell contributes nothing; leaves are scanned.  As
 // in k-NN, the lanes descend until each holds a leaf that straddles its box,
-// then scan those leaves together.
+// then scan those leaves together.  range_walk counts the box's points in the
+// subtree of one starting cell per lane (start = false: nothing to count);
+// every lane of the wave calls it.
 template <int D, int SD>
-__global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ nodes, const int32_t* __restrict__ C32,
-                                                   int64_t cap, const int64_t* __restrict__ Lo,
-                                                   const int64_t* __restrict__ Hi, int64_t nb, int64_t* out,
-                                                   int* flags, const int32_t* tree_of, int32_t n_trees, int phi,
-                                                   int32_t n_nodes, int64_t n_pts, const uint32_t* __restrict__ perm) {
-  const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
-  if (j0 >= nb) return;
-  const int64_t j = perm ? static_cast<int64_t>(perm[j0]) : j0;
-  int32_t lo[D], hi[D];
-  bool bad = false, none = false;
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    const int64_t l = Lo[d * nb + j], h = Hi[d * nb + j];
-    bad |= static_cast<uint64_t>(l) >= static_cast<uint64_t>(kCoordLimit);
-    bad |= static_cast<uint64_t>(h) >= static_cast<uint64_t>(kCoordLimit);
-    none |= l > h;
-    lo[d] = static_cast<int32_t>(l);
-    hi[d] = static_cast<int32_t>(h);
-  }
-  if (bad) {
-    atomicOr(flags, kErrRange);
-    return;
-  }
-  const int32_t root = tree_of ? tree_of[j] : 0;
-  if (static_cast<uint32_t>(root) >= static_cast<uint32_t>(n_trees)) {
-    atomicOr(flags, kErrInternal);
-    return;
-  }
+__device__ int64_t range_walk(const Node* __restrict__ nodes, const int32_t* __restrict__ C32, int64_t cap,
+                              const int32_t (&lo)[D], const int32_t (&hi)[D], int phi, int32_t n_nodes,
+                              int64_t n_pts, bool start, int32_t node0, const int32_t (&clo0)[D],
+                              const int32_t (&chi0)[D], int* fail_out) {
   int64_t count = 0;
   struct Ent {
     int32_t node;
@@ -547,12 +525,12 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
   };
   Ent stk[SD];
   int sp = 0;
-  if (!none) {
-    stk[0].node = root;
+  if (start) {
+    stk[0].node = node0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      stk[0].clo[d] = 0;
-      stk[0].chi[d] = static_cast<int32_t>(kCoordMax);
+      stk[0].clo[d] = clo0[d];
+      stk[0].chi[d] = chi0[d];
     }
     sp = 1;
   }
@@ -639,11 +617,197 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
       have_leaf = false;
     }
   }
+  *fail_out |= fail_bits;
+  return count;
+}
+
+// Reads box j; false (and the error flagged) if a corner is out of range.
+template <int D>
+__device__ inline bool load_box(const int64_t* __restrict__ Lo, const int64_t* __restrict__ Hi, int64_t nb, int64_t j,
+                                int32_t (&lo)[D], int32_t (&hi)[D], bool* none) {
+  bool bad = false;
+  *none = false;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int64_t l = Lo[d * nb + j], h = Hi[d * nb + j];
+    bad |= static_cast<uint64_t>(l) >= static_cast<uint64_t>(kCoordLimit);
+    bad |= static_cast<uint64_t>(h) >= static_cast<uint64_t>(kCoordLimit);
+    *none |= l > h;
+    lo[d] = static_cast<int32_t>(l);
+    hi[d] = static_cast<int32_t>(h);
+  }
+  return !bad;
+}
+
+// One lane per box (large batches).
+template <int D, int SD>
+__global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ nodes, const int32_t* __restrict__ C32,
+                                                   int64_t cap, const int64_t* __restrict__ Lo,
+                                                   const int64_t* __restrict__ Hi, int64_t nb, int64_t* out,
+                                                   int* flags, const int32_t* tree_of, int32_t n_trees, int phi,
+                                                   int32_t n_nodes, int64_t n_pts, const uint32_t* __restrict__ perm) {
+  const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
+  if (j0 >= nb) return;
+  const int64_t j = perm ? static_cast<int64_t>(perm[j0]) : j0;
+  int32_t lo[D], hi[D];
+  bool none;
+  if (!load_box<D>(Lo, Hi, nb, j, lo, hi, &none)) {
+    atomicOr(flags, kErrRange);
+    return;
+  }
+  const int32_t root = tree_of ? tree_of[j] : 0;
+  if (static_cast<uint32_t>(root) >= static_cast<uint32_t>(n_trees)) {
+    atomicOr(flags, kErrInternal);
+    return;
+  }
+  int32_t clo[D], chi[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    clo[d] = 0;
+    chi[d] = static_cast<int32_t>(kCoordMax);
+  }
+  int fail_bits = 0;
+  const int64_t count = range_walk<D, SD>(nodes, C32, cap, lo, hi, phi, n_nodes, n_pts, !none, root, clo, chi,
+                                          &fail_bits);
   if (fail_bits) {
     atomicOr(flags, fail_bits);
     return;
   }
   out[j] = count;
+}
+
+constexpr int64_t kRangeWaveMax = int64_t{1} << 20;
+
+// One wave per box (smaller batches, where one lane per box would leave most
+// of the chip idle and the largest box's walk would set the time).  The wave
+// first expands the box's straddling cells breadth-first, one cell per lane,
+// while the next level still fits in 64 lanes (contained cells add their
+// size, leaves are scanned, disjoint cells drop out); then every lane walks
+// the subtree of its cell with range_walk, and the lane counts are summed.
+template <int D, int SD>
+__global__ void __launch_bounds__(kQBlock) k_range_wave(const Node* __restrict__ nodes,
+                                                        const int32_t* __restrict__ C32, int64_t cap,
+                                                        const int64_t* __restrict__ Lo,
+                                                        const int64_t* __restrict__ Hi, int64_t nb, int64_t* out,
+                                                        int* flags, const int32_t* tree_of, int32_t n_trees, int phi,
+                                                        int32_t n_nodes, int64_t n_pts,
+                                                        const uint32_t* __restrict__ perm) {
+  constexpr int WPB = kQBlock / 64;
+  constexpr int EW = 1 + 2 * D;   // words of a frontier cell: node, lo[D], hi[D]
+  __shared__ int32_t frontier[WPB][64 * EW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t* F = frontier[wave];
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * WPB;
+  for (int64_t j0 = static_cast<int64_t>(blockIdx.x) * WPB + wave; j0 < nb; j0 += waves) {
+    const int64_t j = perm ? static_cast<int64_t>(perm[j0]) : j0;
+    int32_t lo[D], hi[D];
+    bool none;
+    if (!load_box<D>(Lo, Hi, nb, j, lo, hi, &none)) {
+      if (lane == 0) atomicOr(flags, kErrRange);
+      continue;
+    }
+    const int32_t root = tree_of ? tree_of[j] : 0;
+    if (static_cast<uint32_t>(root) >= static_cast<uint32_t>(n_trees)) {
+      if (lane == 0) atomicOr(flags, kErrInternal);
+      continue;
+    }
+    // this lane's cell
+    bool have = lane == 0 && !none;
+    int32_t node = root, clo[D], chi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      clo[d] = 0;
+      chi[d] = static_cast<int32_t>(kCoordMax);
+    }
+    int64_t count = 0;
+    int fail_bits = 0;
+    int32_t steps = 0;
+    while (true) {
+      bool expand = false;
+      Node nd;
+      if (have) {
+        bool inside = true, disjoint = false;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          disjoint |= chi[d] < lo[d] || clo[d] > hi[d];
+          inside &= clo[d] >= lo[d] && chi[d] <= hi[d];
+        }
+        if (static_cast<uint32_t>(node) >= static_cast<uint32_t>(n_nodes)) {
+          fail_bits = kErrInternal;
+          have = false;
+        } else if (disjoint) {
+          have = false;
+        } else {
+          nd = nodes[node];
+          if (inside) {
+            count += nd.size;
+            have = false;
+          } else if (nd.left < 0) {
+            if (nd.off < 0 || nd.size < 0 || static_cast<int64_t>(nd.off) + nd.size > n_pts) {
+              fail_bits = kErrInternal;
+            } else {
+              const int64_t e = nd.size > phi ? static_cast<int64_t>(nd.off) + 1 : static_cast<int64_t>(nd.off) + nd.size;
+              int64_t c = 0;
+              for (int64_t i = nd.off; i < e; ++i) {
+                bool in = true;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                  const int32_t v = C32[d * cap + i];
+                  in &= v >= lo[d] && v <= hi[d];
+                }
+                c += in ? 1 : 0;
+              }
+              count += nd.size > phi ? c * nd.size : c;
+            }
+            have = false;
+          } else {
+            expand = true;
+          }
+        }
+      }
+      const unsigned long long em = __ballot(expand);
+      const int total = 2 * __popcll(em);
+      // a valid tree has at most n_nodes levels: the bound only stops a
+      // corrupt one
+      if (total == 0 || total > 64 || ++steps > n_nodes) break;
+      if (expand) {
+        const int at = 2 * __popcll(em & ((1ULL << lane) - 1));
+        int32_t* r = F + at * EW;        // right child: lo[dim] = x
+        int32_t* l = F + (at + 1) * EW;  // left child: hi[dim] = x - 1
+        r[0] = nd.right;
+        l[0] = nd.left;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          r[1 + d] = (nd.dim == d) ? static_cast<int32_t>(nd.x) : clo[d];
+          r[1 + D + d] = chi[d];
+          l[1 + d] = clo[d];
+          l[1 + D + d] = (nd.dim == d) ? static_cast<int32_t>(nd.x - 1) : chi[d];
+        }
+      }
+      wave_sync();
+      have = lane < total;
+      if (have) {
+        const int32_t* e = F + lane * EW;
+        node = e[0];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          clo[d] = e[1 + d];
+          chi[d] = e[1 + D + d];
+        }
+      }
+      wave_sync();
+    }
+    // the remaining cells (more than 64 children wanted): one subtree walk per lane
+    count += range_walk<D, SD>(nodes, C32, cap, lo, hi, phi, n_nodes, n_pts, have, node, clo, chi, &fail_bits);
+    const unsigned long long fm = __ballot(fail_bits != 0);
+    if (fm) {
+      if (fail_bits) atomicOr(flags, fail_bits);
+      continue;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) count += shfl_xor_i64(count, o);
+    if (lane == 0) out[j] = count;
+  }
 }
 
 // ------------------------------------------------ spatial order of queries
@@ -766,16 +930,26 @@ int range_d(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t*
   QueryOrder W(st);
   const uint32_t* perm = nullptr;
   PKD_TRY(order_queries<D>(st, lo, nb, tree_of, T->n_trees, W, &perm));   // boxes by their low corner
-  const dim3 g(static_cast<unsigned>((nb + kQBlock - 1) / kQBlock));
   const int32_t* X = T->c32;
-  if (T->height + 3 <= 48)
-    hipLaunchKernelGGL((k_range<D, 48>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags, tree_of,
-                       T->n_trees, T->prm.phi, T->node_count, T->n, perm);
-  else if (T->height + 3 <= kMaxStack)
-    hipLaunchKernelGGL((k_range<D, kMaxStack>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags,
+  // below kRangeWaveMax boxes one lane per box would fill too little of the chip
+  const bool per_wave = nb < kRangeWaveMax;
+  const int64_t per_block = per_wave ? kQBlock / 64 : kQBlock;
+  const dim3 g(static_cast<unsigned>(std::min<int64_t>((nb + per_block - 1) / per_block, INT32_MAX)));
+#define PKD_RANGE(SD)                                                                                             \
+  if (per_wave)                                                                                                   \
+    hipLaunchKernelGGL((k_range_wave<D, SD>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags, \
+                       tree_of, T->n_trees, T->prm.phi, T->node_count, T->n, perm);                                \
+  else                                                                                                            \
+    hipLaunchKernelGGL((k_range<D, SD>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags,      \
                        tree_of, T->n_trees, T->prm.phi, T->node_count, T->n, perm);
-  else
+  if (T->height + 3 <= 48) {
+    PKD_RANGE(48)
+  } else if (T->height + 3 <= kMaxStack) {
+    PKD_RANGE(kMaxStack)
+  } else {
     return PKD_ERR_CAPACITY;
+  }
+#undef PKD_RANGE
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_status(e, "k_range");
   return PKD_OK;

@@ -259,6 +259,22 @@ def test_range_count_large_batch_matches_oracle(orc, pk):
     assert np.array_equal(got, orc.Tree(orc.Params(3), c, i).range_count(lo, hi))
 
 
+def test_range_count_lane_and_wave_kernels_agree(orc, pk):
+    # 2^20 boxes take the one-lane-per-box kernel, a smaller batch the
+    # one-wave-per-box kernel: the same boxes give the same counts
+    c, i = synth.uniform_points(150000, 3, seed=52)
+    nb = 1 << 20
+    lo, hi = synth.log_uniform_boxes(nb, 3, seed=53, side_lo=1e5, side_hi=1e8)
+    print("range lane vs wave", flush=True)
+    t = pk.Tree(pk.Params(3), c, i)
+    big = t.range_count(lo, hi).cpu().numpy()
+    part = t.range_count(np.ascontiguousarray(lo[:, :200000]), np.ascontiguousarray(hi[:, :200000])).cpu().numpy()
+    assert np.array_equal(big[:200000], part)
+    rows = np.sort(np.random.default_rng(54).choice(nb, size=3000, replace=False))
+    ref = orc.Tree(orc.Params(3), c, i).range_count(np.ascontiguousarray(lo[:, rows]), np.ascontiguousarray(hi[:, rows]))
+    assert np.array_equal(big[rows], ref)
+
+
 def test_batch_handle_large_query_batch(orc, pk):
     sizes = synth.log_uniform_sizes(40, 1, 5e4, seed=60)
     offsets = np.concatenate([[0], np.cumsum(sizes)])
