@@ -1108,7 +1108,7 @@ __global__ void __launch_bounds__(64) k_emit(const Task* sp, int ns, int lambda,
 // res_base + res_off[i+1]) sized for distinct coordinates; a task that needs
 // more (duplicates) takes the rest from the shared overflow counter.
 template <int D, int NPL>
-__global__ void __launch_bounds__(64 * D) k_finish(const Task* tasks, const int* list, int P, Bufs bufs, int final_buf,
+__global__ void __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(NPL <= 8 ? 8 : 1))) k_finish(const Task* tasks, const int* list, int P, Bufs bufs, int final_buf,
                                                      int phi, Node* nodes, int* overflow_ctr, int64_t node_cap,
                                                      int* height, int* flags, const int32_t* res_off,
                                                      int32_t res_base) {
