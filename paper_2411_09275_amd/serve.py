@@ -265,6 +265,18 @@ class Server:
             raise ValueError("mode must be 'continuous' or 'serial'")
         ready = collections.deque()
         inflight = collections.deque()
+        try:
+            self._continuous(reqs, ready, inflight, arr, now)
+        except BaseException:
+            # leave nothing running on the device or in the retire thread
+            torch.cuda.synchronize()
+            for b in inflight:
+                concurrent.futures.wait([b.retired])
+            raise
+        torch.cuda.synchronize()
+        return now()
+
+    def _continuous(self, reqs, ready, inflight, arr, now):
         i = 0
         while i < len(reqs) or ready or inflight:
             t = now()
@@ -304,8 +316,6 @@ class Server:
                 self._retire(inflight.popleft())   # wait for memory held by batches in flight
                 continue
             inflight.append(self._issue(batch, nbytes, now))
-        torch.cuda.synchronize()
-        return now()
 
 
 def latency_stats(requests):

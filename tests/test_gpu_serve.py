@@ -107,3 +107,19 @@ def test_forced_queueing_keeps_results(orc, pk):
     print("batch cap 300 queries", flush=True)
     _serve(pk, reqs, "continuous", realtime=False, max_batch_queries=300, max_inflight=2)
     _check_against(reqs, _oracle_replay(orc, reqs))
+
+
+def test_device_error_reaches_the_caller(pk):
+    # a query coordinate out of range makes the batch's device status nonzero;
+    # the retire thread raises and run() re-raises it
+    from paper_2411_09275_amd.serve import Request, Server
+    reqs = _stream(seed=8, n=12)
+    bad = next(r for r in reqs if r.kind == "knn")
+    bad.coords = bad.coords.copy()
+    bad.coords[0, 0] = 1 << 30
+    c, i = _initial()
+    t = pk.Tree(pk.Params(D), c, i)
+    print("device status error", flush=True)
+    with pytest.raises(RuntimeError):
+        Server(t, D).run(reqs, mode="continuous", realtime=False)
+    t.free()
