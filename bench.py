@@ -488,7 +488,8 @@ def main():
     t_start = time.perf_counter()
     for k in range(a.steps):
         step(rec)
-        print("step %d: build %.2f ms, 10-NN %.2f ms, range %.2f ms" % ((k,) + rec[-1]), file=sys.stderr, flush=True)
+        print("step %d: build %.2f ms, %d-NN %.2f ms, range %.2f ms" % (k, rec[-1][0], a.k, rec[-1][1], rec[-1][2]),
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
 
@@ -515,8 +516,8 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "build %.0e uniform %d-D int64 points in [0,1e9) + %.0e uniform 10-NN queries + "
-                               "%.0e range counts (sides log-uniform [1e5,1e8])" % (a.n, a.dim, a.queries, a.boxes),
+        "config": {"workload": "build %.0e uniform %d-D int64 points in [0,1e9) + %.0e uniform %d-NN queries + "
+                               "%.0e range counts (sides log-uniform [1e5,1e8])" % (a.n, a.dim, a.queries, a.k, a.boxes),
                    "n": a.n, "dim": a.dim, "queries": a.queries, "k": a.k, "boxes": a.boxes,
                    "lambda": params.lam, "phi": params.phi, "sigma": params.sigma, "tile": a.tile},
         "build_ms": round(build_ms, 3),

@@ -105,6 +105,17 @@ class Server:
         # bound by first-touch page faults: several threads copy row chunks
         self._copiers = concurrent.futures.ThreadPoolExecutor(max_workers=self.COPY_THREADS)
 
+    def close(self):
+        """Stop the retire and copy threads (the server is not used afterwards)."""
+        self._retirer.shutdown(wait=True)
+        self._copiers.shutdown(wait=True)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def _pinned(self, slot, name, n):
         """A pinned int64 buffer of at least n elements owned by `slot`."""
         buf = self._stage[slot].get(name)

@@ -67,8 +67,8 @@ def _serve(pk, reqs, mode, realtime, **kw):
     from paper_2411_09275_amd.serve import Server
     c, i = _initial()
     t = pk.Tree(pk.Params(D), c, i)
-    s = Server(t, D, **kw)
-    s.run(reqs, mode=mode, realtime=realtime)
+    with Server(t, D, **kw) as s:
+        s.run(reqs, mode=mode, realtime=realtime)
     size = t.size()
     t.free()
     return s, size
