@@ -2134,6 +2134,11 @@ int sieve_pass(hipStream_t st, int D, int lambda, int tile, const Task* tasks, i
   return PKD_ERR_UNSUPPORTED;
 }
 
+size_t build_lds_need(int D, int s, int phi) {
+  const int P = std::max(64, next_pow2(s));   // the largest finisher class holds fewer than s points
+  return std::max(SkelLayout(D, P).end, FinLayout(D, P, phi).end);
+}
+
 int build_tasks(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, const int64_t* in_c,
                 const int64_t* in_id, int64_t input_cap) {
   const int D = T->prm.D;

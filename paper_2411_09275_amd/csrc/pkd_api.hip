@@ -207,6 +207,7 @@ int check_params(const pkd_params* p, const pkd_tuning* t, Params* out) {
     return PKD_ERR_INVALID_ARG;
   int64_t s = static_cast<int64_t>(p->oversample) << p->lambda;
   if (s > kMaxSample) return PKD_ERR_UNSUPPORTED;
+  if (build_lds_need(p->dim, static_cast<int>(s), p->leaf_size) > kMaxLdsBytes) return PKD_ERR_UNSUPPORTED;
   int tile = t ? t->tile_points : 2048;
   if (tile != 1024 && tile != 2048 && tile != 4096) return PKD_ERR_INVALID_ARG;
   const int bias = t ? t->cand_shift_bias : 0;

@@ -187,6 +187,12 @@ int bits_for(int64_t v);   // bits needed to write 0 .. v
 int ensure_c32(pkd_tree* T, hipStream_t st);
 int refresh_c32(pkd_tree* T, hipStream_t st);
 
+// LDS bytes that one workgroup of the skeleton and finisher kernels needs at
+// most for D dimensions, sample size s and leaf size phi (both must fit one
+// workgroup's LDS, kMaxLdsBytes).
+size_t build_lds_need(int D, int s, int phi);
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
 // Tile layout of `ns` tasks (device array): tiles of `tile` points, scan
 // chunks; returns the numbers of tiles and chunks and the points covered.
 int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,

@@ -51,11 +51,14 @@ def test_parameter_validation_before_any_device_work(L):
     out = C.c_void_p()
     bad = [dict(dim=0), dict(dim=8), dict(lambda_=0), dict(lambda_=9), dict(leaf_size=0), dict(oversample=0),
            dict(alpha_num=5, alpha_den=10), dict(alpha_den=0), dict(oversample=65),
-           dict(oversample=33), dict(lambda_=7, oversample=32), dict(lambda_=8, oversample=16)]
-    expect = [-3, -3, -1, -1, -1, -1, -1, -1, -3, -3, -3, -3]   # a sample above 2048 points is unsupported
+           dict(oversample=33), dict(lambda_=7, oversample=32), dict(lambda_=8, oversample=16),
+           dict(dim=7, leaf_size=1)]
+    # a sample above 2048 points is unsupported, and so is a 7-D sample of 2048
+    # with leaves of one point (its finisher workgroup would need over 160 KB of LDS)
+    expect = [-3, -3, -1, -1, -1, -1, -1, -1, -3, -3, -3, -3, -3]
     for change, code in zip(bad, expect):
         p = pk._Params()
-        L.pkd_default_params(C.byref(p), 2)
+        L.pkd_default_params(C.byref(p), 7 if change.get("dim") == 7 else 2)
         for k, v in change.items():
             setattr(p, k, v)
         assert L.pkd_build(C.byref(p), None, None, None, None, 10, C.byref(out)) == code, change
