@@ -31,6 +31,8 @@ __device__ inline bool pair_less(int64_t d2, int64_t id, int64_t cd2, int64_t ci
 // so a leaf scan is paid once per round rather than once per node step.
 // Coordinates lie in [0, 2^30): differences fit 32 bits, and the leaves are
 // scanned in the tree's packed 32-bit copy of its coordinates.
+constexpr int kLeafBatch = 4;
+
 template <int D, int KM, int SD>
 __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes, const int32_t* __restrict__ C32,
                                                  int64_t cap, const int64_t* __restrict__ ids,
@@ -163,15 +165,7 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
     }
     if (__ballot(have_leaf) == 0) break;
     if (have_leaf) {
-      const int64_t e = static_cast<int64_t>(leaf_off) + leaf_size;
-#pragma unroll 1
-      for (int64_t i = leaf_off; i < e; ++i) {
-        int64_t d2 = 0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          const int32_t diff = C32[d * cap + i] - q[d];
-          d2 += static_cast<int64_t>(diff) * diff;
-        }
+      auto consider = [&](int64_t d2, int64_t i) {
         if (d2 <= bd[KR - 1]) {
           const int64_t id = ids[i];
           if (pair_less(d2, id, bd[KR - 1], bi[KR - 1])) {
@@ -189,6 +183,36 @@ __global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes,
             }
           }
         }
+      };
+      const int64_t e = static_cast<int64_t>(leaf_off) + leaf_size;
+      int64_t i = leaf_off;
+      // kLeafBatch points' coordinates are loaded before the first is tested,
+      // so their loads are in flight together
+#pragma unroll 1
+      for (; i + kLeafBatch <= e; i += kLeafBatch) {
+        int64_t d2[kLeafBatch];
+#pragma unroll
+        for (int u = 0; u < kLeafBatch; ++u) d2[u] = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+#pragma unroll
+          for (int u = 0; u < kLeafBatch; ++u) {
+            const int32_t diff = C32[d * cap + i + u] - q[d];
+            d2[u] += static_cast<int64_t>(diff) * diff;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kLeafBatch; ++u) consider(d2[u], i + u);
+      }
+#pragma unroll 1
+      for (; i < e; ++i) {
+        int64_t d2 = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const int32_t diff = C32[d * cap + i] - q[d];
+          d2 += static_cast<int64_t>(diff) * diff;
+        }
+        consider(d2, i);
       }
       have_leaf = false;
     }
@@ -513,6 +537,42 @@ __global__ void __launch_bounds__(kQBlock) k_knn_wave(const Node* __restrict__ n
 // then scan those leaves together.  range_walk counts the box's points in the
 // subtree of one starting cell per lane (start = false: nothing to count);
 // every lane of the wave calls it.
+// Points among [off, off+n) of the packed coordinates that lie in the box;
+// kLeafBatch points' loads are issued before the first is tested.
+template <int D>
+__device__ inline int64_t count_in_box(const int32_t* __restrict__ C32, int64_t cap, int64_t off, int64_t n,
+                                       const int32_t (&lo)[D], const int32_t (&hi)[D]) {
+  const int64_t e = off + n;
+  int64_t c = 0, i = off;
+#pragma unroll 1
+  for (; i + kLeafBatch <= e; i += kLeafBatch) {
+    bool in[kLeafBatch];
+#pragma unroll
+    for (int u = 0; u < kLeafBatch; ++u) in[u] = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+      for (int u = 0; u < kLeafBatch; ++u) {
+        const int32_t v = C32[d * cap + i + u];
+        in[u] &= v >= lo[d] && v <= hi[d];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLeafBatch; ++u) c += in[u] ? 1 : 0;
+  }
+#pragma unroll 1
+  for (; i < e; ++i) {
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int32_t v = C32[d * cap + i];
+      in &= v >= lo[d] && v <= hi[d];
+    }
+    c += in ? 1 : 0;
+  }
+  return c;
+}
+
 template <int D, int SD>
 __device__ int64_t range_walk(const Node* __restrict__ nodes, const int32_t* __restrict__ C32, int64_t cap,
                               const int32_t (&lo)[D], const int32_t (&hi)[D], int phi, int32_t n_nodes,
@@ -601,18 +661,7 @@ __device__ int64_t range_walk(const Node* __restrict__ nodes, const int32_t* __r
     if (__ballot(have_leaf) == 0) break;
     if (have_leaf) {
       // a leaf larger than phi holds identical points: test one of them
-      const int64_t e = leaf_size > phi ? static_cast<int64_t>(leaf_off) + 1 : static_cast<int64_t>(leaf_off) + leaf_size;
-      int64_t c = 0;
-#pragma unroll 1
-      for (int64_t i = leaf_off; i < e; ++i) {
-        bool in = true;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          const int32_t v = C32[d * cap + i];
-          in &= v >= lo[d] && v <= hi[d];
-        }
-        c += in ? 1 : 0;
-      }
+      const int64_t c = count_in_box<D>(C32, cap, leaf_off, leaf_size > phi ? 1 : leaf_size, lo, hi);
       count += leaf_size > phi ? c * leaf_size : c;
       have_leaf = false;
     }
@@ -746,17 +795,7 @@ __global__ void __launch_bounds__(kQBlock) k_range_wave(const Node* __restrict__
             if (nd.off < 0 || nd.size < 0 || static_cast<int64_t>(nd.off) + nd.size > n_pts) {
               fail_bits = kErrInternal;
             } else {
-              const int64_t e = nd.size > phi ? static_cast<int64_t>(nd.off) + 1 : static_cast<int64_t>(nd.off) + nd.size;
-              int64_t c = 0;
-              for (int64_t i = nd.off; i < e; ++i) {
-                bool in = true;
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                  const int32_t v = C32[d * cap + i];
-                  in &= v >= lo[d] && v <= hi[d];
-                }
-                c += in ? 1 : 0;
-              }
+              const int64_t c = count_in_box<D>(C32, cap, nd.off, nd.size > phi ? 1 : nd.size, lo, hi);
               count += nd.size > phi ? c * nd.size : c;
             }
             have = false;
