@@ -34,7 +34,7 @@ __device__ inline bool pair_less(int64_t d2, int64_t id, int64_t cd2, int64_t ci
 constexpr int kLeafBatch = 4;
 
 template <int D, int KM, int SD>
-__global__ void __launch_bounds__(kQBlock) k_knn(const Node* __restrict__ nodes, const int32_t* __restrict__ C32,
+__global__ void __launch_bounds__(kQBlock) __attribute__((amdgpu_waves_per_eu(KM == 16 ? 3 : 1))) k_knn(const Node* __restrict__ nodes, const int32_t* __restrict__ C32,
                                                  int64_t cap, const int64_t* __restrict__ ids,
                                                  const int64_t* __restrict__ Qry, int64_t nq, int k,
                                                  int64_t* __restrict__ out_ids, int64_t* __restrict__ out_d2,
