@@ -18,8 +18,8 @@ __device__ inline bool pair_less(int64_t d2, int64_t id, int64_t cd2, int64_t ci
   return d2 < cd2 || (d2 == cd2 && id < cid);
 }
 
-// Exact k nearest (squared distance, id) pairs for k <= 16, one lane per
-// query: k <= KM (10 for k = 9, 10, else a power of two up to 16), candidates kept as a
+// Exact k nearest (squared distance, id) pairs for k <= 32, one lane per
+// query: k <= KM (10 for k = 9, 10, else a power of two up to 32), candidates kept as a
 // sorted array in registers.  The first KM-k slots hold sentinels that are
 // smaller than any real pair, so the k-th best is always slot KM-1.
 // Depth-first: the nearer child first; the farther child is stacked with the
@@ -34,7 +34,7 @@ __device__ inline bool pair_less(int64_t d2, int64_t id, int64_t cd2, int64_t ci
 constexpr int kLeafBatch = 4;
 
 template <int D, int KM, int SD>
-__global__ void __launch_bounds__(kQBlock) __attribute__((amdgpu_waves_per_eu(KM == 16 ? 3 : 1))) k_knn(const Node* __restrict__ nodes, const int32_t* __restrict__ C32,
+__global__ void __launch_bounds__(kQBlock) __attribute__((amdgpu_waves_per_eu(KM == 16 ? 3 : (KM == 32 ? 2 : 1)))) k_knn(const Node* __restrict__ nodes, const int32_t* __restrict__ C32,
                                                  int64_t cap, const int64_t* __restrict__ ids,
                                                  const int64_t* __restrict__ Qry, int64_t nq, int k,
                                                  int64_t* __restrict__ out_ids, int64_t* __restrict__ out_d2,
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(kQBlock) __attribute__((amdgpu_waves_per_eu(KM
 }
 
 // --------------------------------------------------------- k-NN, larger k
-// k = 17..128: one wave answers one query.  The wave walks a single
+// k = 33..128: one wave answers one query.  The wave walks a single
 // path (every lane takes the same branch, so nothing diverges), its 64 lanes
 // scan a leaf's points together, and the k best pairs are one sorted list in
 // the wave's LDS.  A leaf's accepted pairs are sorted across the wave by a
@@ -921,8 +921,9 @@ void launch_knn(int km, dim3 g, hipStream_t st, const Node* nodes, const int32_t
     PKD_KNN_CASE(8)
     PKD_KNN_CASE(10)
     PKD_KNN_CASE(16)
+    PKD_KNN_CASE(32)
     default: {
-      // k > 16: one wave per query (measured faster than a persistent grid
+      // k > 32: one wave per query (measured faster than a persistent grid
       // sized to the resident workgroups: the dispatcher balances the uneven
       // query costs); the kernel still strides if the grid is capped
       const size_t lds = (kQBlock / 64) * WaveKnnLayout(D, SD, k).end;
