@@ -393,13 +393,21 @@ __host__ __device__ inline int next_pow2(int x) {
 }
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t{7}; }
 
+// The select phase's tie and histogram arrays (kSelScratch bytes) live in
+// the C region, which is written only after them; the sample positions share
+// their region with the orders O, which are written only after the positions
+// have been read.
+constexpr size_t kSelScratch = 256 * (sizeof(int64_t) + sizeof(uint32_t) + sizeof(uint32_t));
+
 struct SkelLayout {
   size_t C, pos, O, node_of, segF, flag, end;
   __host__ __device__ SkelLayout(int D, int P) {
     size_t o = 0;
-    C = o;        o += sizeof(uint32_t) * D * P;
-    pos = o;      o += sizeof(uint32_t) * P;
-    O = o;        o += sizeof(uint16_t) * D * P;
+    const size_t c_bytes = sizeof(uint32_t) * D * P;
+    C = o;        o += c_bytes > kSelScratch ? c_bytes : kSelScratch;
+    const size_t pos_bytes = sizeof(uint32_t) * P, o_bytes = sizeof(uint16_t) * D * P;
+    pos = o;
+    O = o;        o += pos_bytes > o_bytes ? pos_bytes : o_bytes;
     node_of = o;  o += sizeof(uint16_t) * P;
     segF = o;     o += sizeof(uint16_t) * D * (2 << kMaxLambda);
     flag = o;     o += P;
@@ -473,11 +481,11 @@ __global__ void __launch_bounds__(64 * D) k_select_skeleton(const Task* sp, int 
   uint16_t* segF = reinterpret_cast<uint16_t*>(smem + lay.segF);
   uint8_t* flag = smem + lay.flag;
 
-  __shared__ uint32_t hist[256];
+  int64_t* tie_id = reinterpret_cast<int64_t*>(smem + lay.C);   // [256]; phase 1 only (see SkelLayout)
+  uint32_t* hist = reinterpret_cast<uint32_t*>(smem + lay.C + 256 * sizeof(int64_t));
+  uint32_t* tie_pos = hist + 256;
   __shared__ int sh_c, sh_done, sh_pass, sh_need, sh_cnt, sh_bad, sh_tie_n;
   __shared__ uint64_t sh_prefix, sh_T;
-  __shared__ uint32_t tie_pos[256];
-  __shared__ int64_t tie_id[256];
 
   // ---- phase 1: the s smallest keys
   if (tid == 0) {

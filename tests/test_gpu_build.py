@@ -138,7 +138,8 @@ def test_out_of_range_coordinates_rejected(pk):
                                       (2, 50000, 7, 300), (1, 20000, 5, 1000), (5, 40000, 10, 10 ** 6),
                                       (3, 30000, 100, 10 ** 9), (2, 20, 10, 10 ** 9), (3, 50000, 33, 10 ** 9),
                                       (2, 20, 100, 10 ** 9), (3, 50000, 128, 10 ** 9), (2, 50000, 17, 300),
-                                      (4, 30000, 64, 10 ** 9), (3, 60000, 9, 10 ** 9), (2, 40000, 10, 200)])
+                                      (4, 30000, 64, 10 ** 9), (3, 60000, 9, 10 ** 9), (2, 40000, 10, 200),
+                                      (3, 40000, 32, 10 ** 9)])
 def test_knn_matches_definition(orc, pk, D, n, k, hi):
     c, i = synth.uniform_points(n, D, seed=20 + D, hi=hi)
     q = synth.uniform_queries(500, D, seed=21, hi=hi)
@@ -235,7 +236,8 @@ def test_batch_build_equals_single_builds(orc, pk):
 # ------------------------------------------------ large batches (spatial order)
 # Batches of at least 16384 queries are processed in Morton order; every
 # result must still land in its own row and equal the oracle's.
-@pytest.mark.parametrize("D,nq,k", [(3, 40000, 10), (2, 16384, 1), (5, 20000, 7), (1, 30000, 3), (3, 40000, 100)])
+@pytest.mark.parametrize("D,nq,k", [(3, 40000, 10), (2, 16384, 1), (5, 20000, 7), (1, 30000, 3), (3, 40000, 100),
+                                    (2, 30000, 24)])
 def test_knn_large_batch_matches_oracle(orc, pk, D, nq, k):
     c, i = synth.uniform_points(120000, D, seed=40 + D)
     q = synth.uniform_queries(nq, D, seed=41)
