@@ -1,7 +1,8 @@
 // k-NN and range-count queries on a built Pkd-tree (Section 2 definitions,
-// Section 5 traversals).  One lane per query; the subspace of a node is not
-// stored but derived on the way down from the splitters (no bounding boxes,
-// Section 5).
+// Section 5 traversals).  k-NN with k <= 32 and large batches of range counts
+// run one lane per query; k-NN with larger k and smaller batches of range
+// counts run one wave per query.  The subspace of a node is not stored but
+// derived on the way down from the splitters (no bounding boxes, Section 5).
 #include <algorithm>
 
 #include "pkd_internal.h"
