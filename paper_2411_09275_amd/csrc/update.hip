@@ -416,9 +416,11 @@ __global__ void k_region_mark(const Region* regions, int32_t* regid, int32_t* de
 
 // New places of the old points: insert: o + S[o+1] (batch points noted at
 // region ends before o); delete: o - S[o] (removed points before o).
+// The tree's packed 32-bit coordinates are written at the new places too
+// (the points of rebuilt regions get theirs again from the rebuild).
 template <int D>
 __global__ void k_relayout(const int64_t* X, int64_t xcap, int64_t n, const int32_t* S, const int32_t* delflag,
-                           int insert, int64_t* Y, int64_t ycap) {
+                           int insert, int64_t* Y, int64_t ycap, int32_t* C32) {
   for (int64_t o = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; o < n;
        o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     int64_t dst;
@@ -428,7 +430,13 @@ __global__ void k_relayout(const int64_t* X, int64_t xcap, int64_t n, const int3
       if (delflag[o]) continue;
       dst = o - S[o];
     }
-    for (int d = 0; d <= D; ++d) Y[d * ycap + dst] = X[d * xcap + o];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int64_t v = X[d * xcap + o];
+      Y[d * ycap + dst] = v;
+      C32[d * ycap + dst] = static_cast<int32_t>(v);
+    }
+    Y[D * ycap + dst] = X[D * xcap + o];
   }
 }
 
@@ -768,6 +776,20 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     Ynew = static_cast<int64_t*>(a);
     fresh_twin = static_cast<int64_t*>(b);
   }
+  // the packed coordinate copy at the new capacity (the relayout writes it)
+  int32_t* c32_new = T->c32;
+  if (new_cap > 0 && (!T->c32 || T->c32_cap != new_cap)) {
+    void* p = nullptr;
+    const int rc = dev_alloc(&p, sizeof(int32_t) * static_cast<size_t>(D) * static_cast<size_t>(new_cap), st);
+    if (rc != PKD_OK) {
+      if (fresh_twin) {
+        dev_free(Ynew, st);
+        dev_free(fresh_twin, st);
+      }
+      return rc;
+    }
+    c32_new = static_cast<int32_t*>(p);
+  }
   PKD_TRY(S.need(n + 2));
   PKD_TRY(regid.need(n + 1));
   PKD_TRY(fill(st, regid.p, n + 1, -1));
@@ -787,7 +809,7 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   if (n > 0) {
     const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (n + 255) / 256));
     hipLaunchKernelGGL(k_relayout<D>, dim3(g), dim3(256), 0, st, Xold, old_cap, n, S.p, delflag.p, insert ? 1 : 0,
-                       Ynew, new_cap);
+                       Ynew, new_cap, c32_new);
     PKD_TRY(kernel_status("k_relayout"));
   }
   if (insert && n_regions > 0) {
@@ -820,6 +842,11 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   } else {
     T->cur = 1 - T->cur;
   }
+  if (c32_new != T->c32) {
+    dev_free(T->c32, st);
+    T->c32 = c32_new;
+    T->c32_cap = new_cap;
+  }
   T->n = n_new;
 
   // ---- rebuild every region (one segmented Build)
@@ -838,8 +865,9 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     }
     PKD_TRY(build_tasks(T, st, roots, nullptr, nullptr, 0));
   }
-  // the packed copy for the queries: the relayout moved every point
-  return refresh_c32(T, st);
+  // the packed copy for the queries: the relayout wrote the moved points,
+  // the rebuild the points of every region
+  return PKD_OK;
 }
 
 }  // namespace

@@ -71,6 +71,13 @@ class Pair:
         rows, ids, coords = _same(self.g, self.o, label)
         treecheck.check_tree(rows, ids, coords, self.op.phi, self.c, self.i)
         assert self.g.size() == self.i.shape[0]
+        # the queries read the tree's packed coordinate copy, which every
+        # update must leave equal to the point array
+        D = self.c.shape[0]
+        if q is None:
+            q = synth.uniform_queries(200, D, seed=990)
+        if boxes is None:
+            boxes = synth.log_uniform_boxes(200, D, seed=991)
         if q is not None:
             gi, gd = self.g.knn(q, 10)
             bi, bd = self.orc.brute_knn(self.c, self.i, q, 10)
