@@ -187,23 +187,25 @@ __global__ void __launch_bounds__(kQBlock) __attribute__((amdgpu_waves_per_eu(KM
       };
       const int64_t e = static_cast<int64_t>(leaf_off) + leaf_size;
       int64_t i = leaf_off;
-      // kLeafBatch points' coordinates are loaded before the first is tested,
-      // so their loads are in flight together
+      // LB points' coordinates are loaded before the first is tested, so
+      // their loads are in flight together (more of them when the list is
+      // short and registers are free)
+      constexpr int LB = KM <= 4 ? 2 * kLeafBatch : kLeafBatch;
 #pragma unroll 1
-      for (; i + kLeafBatch <= e; i += kLeafBatch) {
-        int64_t d2[kLeafBatch];
+      for (; i + LB <= e; i += LB) {
+        int64_t d2[LB];
 #pragma unroll
-        for (int u = 0; u < kLeafBatch; ++u) d2[u] = 0;
+        for (int u = 0; u < LB; ++u) d2[u] = 0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
 #pragma unroll
-          for (int u = 0; u < kLeafBatch; ++u) {
+          for (int u = 0; u < LB; ++u) {
             const int32_t diff = C32[d * cap + i + u] - q[d];
             d2[u] += static_cast<int64_t>(diff) * diff;
           }
         }
 #pragma unroll
-        for (int u = 0; u < kLeafBatch; ++u) consider(d2[u], i + u);
+        for (int u = 0; u < LB; ++u) consider(d2[u], i + u);
       }
 #pragma unroll 1
       for (; i < e; ++i) {
