@@ -247,6 +247,16 @@ class Tree:
         _check(lib().pkd_knn_async(self.h, _stream(stream), _ptr(q), None if to is None else _ptr(to), nq, k,
                                    _ptr(out_ids), _ptr(out_d2), _ptr(status)), "pkd_knn_async")
 
+    def range_count_async(self, lo, hi, out, status, tree_of=None, stream=None):
+        """Enqueue range counts on `stream` without waiting; errors are ORed
+        into the device int32 tensor `status` (zero it first)."""
+        lo, hi = _dev(lo), _dev(hi)
+        nb = lo.shape[1] if lo.dim() == 2 else 0
+        to = None if tree_of is None else _to_i32(tree_of)
+        _check(lib().pkd_range_count_async(self.h, _stream(stream), _ptr(lo), _ptr(hi),
+                                           None if to is None else _ptr(to), nb, _ptr(out), _ptr(status)),
+               "pkd_range_count_async")
+
     def range_count(self, lo, hi, tree_of=None, stream=None):
         torch = _torch()
         lo, hi = _dev(lo), _dev(hi)

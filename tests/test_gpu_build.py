@@ -321,3 +321,35 @@ def test_sampler_retry_keeps_the_tree(orc, pk, bias):
     for t in range(4):
         for x, y in zip(B0.export(t), B1.export(t)):
             assert np.array_equal(x, y)
+
+
+# ------------------------------------------------ asynchronous entry points
+def test_async_queries_match_and_report_errors_in_status(pk):
+    import torch
+    c, i = synth.uniform_points(80000, 3, seed=80)
+    t = pk.Tree(pk.Params(3), c, i)
+    q = synth.uniform_queries(20000, 3, seed=81)
+    lo, hi = synth.log_uniform_boxes(20000, 3, seed=82)
+    ri, rd = t.knn(q, 10)
+    rc = t.range_count(lo, hi)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        oi = torch.empty((20000, 10), dtype=torch.int64, device="cuda")
+        od = torch.empty((20000, 10), dtype=torch.int64, device="cuda")
+        oc = torch.empty(20000, dtype=torch.int64, device="cuda")
+        dq, dlo, dhi = (torch.from_numpy(x).cuda() for x in (q, lo, hi))
+    t.knn_async(dq, 10, oi, od, st, stream=s)
+    t.range_count_async(dlo, dhi, oc, st, stream=s)
+    s.synchronize()
+    assert int(st.item()) == 0
+    assert torch.equal(oi, ri) and torch.equal(od, rd) and torch.equal(oc, rc)
+    # a coordinate out of range is reported in the status word, not raised
+    bad = q.copy()
+    bad[1, 7] = 1 << 30
+    with torch.cuda.stream(s):
+        st2 = torch.zeros(1, dtype=torch.int32, device="cuda")
+        dbad = torch.from_numpy(bad).cuda()
+    t.knn_async(dbad, 10, oi, od, st2, stream=s)
+    s.synchronize()
+    assert int(st2.item()) & 1
