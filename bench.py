@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--tile", type=int, default=2048)
     ap.add_argument("--cpu-sample", type=int, default=4_000_000, help="points of the oracle's build sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="build", choices=["build", "batching", "serving", "updates"],
+    ap.add_argument("--workload", default="build", choices=["build", "batching", "serving", "updates", "large_updates"],
                     help="build: the headline (1e8 3-D build + queries); batching: 4096 trees in one pass")
     ap.add_argument("--serve-n", type=int, default=1_000_000_000, help="points of the resident serving tree")
     ap.add_argument("--requests", type=int, default=100, help="requests in the serving stream")
@@ -417,6 +417,65 @@ def bench_updates(a):
     print(json.dumps(out))
 
 
+def bench_large_updates(a):
+    """Batch updates on a resident tree of --serve-n hashed-uniform 2-D points
+    (1e9 by default, as in the paper's update table): for each batch size in
+    1e3, 1e5, 1e6, 1e7, BatchInsert of fresh hashed points, then BatchDelete of
+    the same points (the tree returns to its original set).  Reports the time of
+    each; the value is the update throughput over all batches."""
+    import torch
+
+    import paper_2411_09275_amd as pk
+    import synth
+
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    torch.cuda.set_device(0)
+    D, n0 = 2, a.serve_n
+    ids = torch.arange(n0, device="cuda", dtype=torch.int64)
+    c = synth.hashed_points_torch(ids, D, 21)
+    torch.cuda.synchronize()
+    s = time.perf_counter()
+    t = pk.Tree(pk.Params(D), c, ids)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - s) * 1e3
+    del c, ids
+    torch.cuda.empty_cache()
+    sizes = (1000, 100000, 1000000, 10000000)
+    rows = {}
+    for rep in range(a.warmup + 1):
+        for m in sizes:
+            nid = torch.arange(2 * n0 + m, 2 * n0 + 2 * m, device="cuda", dtype=torch.int64)
+            nc = synth.hashed_points_torch(nid, D, 99)
+            torch.cuda.synchronize()
+            s = time.perf_counter()
+            t.insert(nc, nid)
+            torch.cuda.synchronize()
+            ti = time.perf_counter() - s
+            s = time.perf_counter()
+            k = t.delete(nc, nid)
+            torch.cuda.synchronize()
+            td = time.perf_counter() - s
+            assert k == m and t.size() == n0, (k, t.size())
+            if rep >= a.warmup:
+                rows[str(m)] = {"insert_ms": round(ti * 1e3, 2), "delete_ms": round(td * 1e3, 2)}
+            log("batch %d: insert %.1f ms, delete %.1f ms" % (m, ti * 1e3, td * 1e3))
+    t.free()
+    total_s = sum(r["insert_ms"] + r["delete_ms"] for r in rows.values()) / 1e3
+    out = {
+        "metric": "batch updates on a resident %.0e-point 2-D tree: Mpts/s of BatchInsert + BatchDelete" % n0,
+        "value": round(2 * sum(sizes) / total_s / 1e6, 2),
+        "unit": "Mpts/s",
+        "n_gpus": 1, "steps": 1, "warmup": a.warmup,
+        "ms_per_step": round(total_s * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "resident tree of %.0e hashed uniform 2-D int64 points in [0,1e9); insert then "
+                               "delete batches of 1e3, 1e5, 1e6, 1e7 fresh points" % n0},
+        "build_ms": round(build_ms, 1),
+        "batches": rows,
+    }
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -425,6 +484,9 @@ def main():
         sys.exit(2)
     if a.workload == "batching":
         bench_batching(a)
+        return
+    if a.workload == "large_updates":
+        bench_large_updates(a)
         return
     if a.workload == "serving":
         bench_serving(a)
