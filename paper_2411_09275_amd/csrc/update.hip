@@ -333,21 +333,27 @@ __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
 // Replay of one routing round, top-down, with exact counts.  cnt(v) is the
 // weight of the batch slice below heap position v (1 per inserted point, 1 per
 // point actually removed); a killed task lies below a region.
+__host__ __device__ inline size_t decide_lds_per_wave(int lambda) {
+  return (static_cast<size_t>(2 << lambda) * (3 * sizeof(int32_t) + 1) + 15) & ~size_t{15};
+}
+
 __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int ns, int lambda, const int32_t* hn_all,
                                                         const int32_t* bsize, const int32_t* bstart,
                                                         const int32_t* child_idx, const int8_t* killed,
                                                         int8_t* killed_next, const int32_t* M, Node* nodes, int64_t an,
                                                         int64_t ad, int insert, Region* regions, int* n_regions) {
   const int NB = 1 << lambda, nheap = 2 << lambda;
-  __shared__ int32_t cnt_w[kWaves][2 << kMaxLambda], s0_w[kWaves][2 << kMaxLambda], sz_w[kWaves][2 << kMaxLambda];
-  __shared__ uint8_t alive_w[kWaves][2 << kMaxLambda];
+  // per wave: cnt, s0, sz [nheap] int32, alive [nheap] bytes (dynamic LDS,
+  // sized for this lambda)
+  extern __shared__ __align__(16) unsigned char smem[];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int sig = blockIdx.x * kWaves + w;
   const bool active = sig < ns && !killed[sig];
-  int32_t* cnt = cnt_w[w];
-  int32_t* s0 = s0_w[w];
-  int32_t* sz = sz_w[w];
-  uint8_t* alive = alive_w[w];
+  unsigned char* mine = smem + static_cast<size_t>(w) * decide_lds_per_wave(lambda);
+  int32_t* cnt = reinterpret_cast<int32_t*>(mine);
+  int32_t* s0 = cnt + nheap;
+  int32_t* sz = s0 + nheap;
+  uint8_t* alive = reinterpret_cast<uint8_t*>(sz + nheap);
   const int32_t* hn = hn_all + static_cast<int64_t>(sig) * nheap;
   if (active) {
     for (int j = lane; j < NB; j += 64) {
@@ -743,7 +749,8 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
       const int nn = r + 1 < rounds.size() ? rounds[r + 1]->ns : 0;
       PKD_TRY(killed_next.need(static_cast<size_t>(nn) + 1));
       PKD_HIP(hipMemsetAsync(killed_next.p, 1, nn + 1, st));
-      hipLaunchKernelGGL(k_decide, dim3((R->ns + kWaves - 1) / kWaves), dim3(64 * kWaves), 0, st, R->tasks.p, R->ns,
+      hipLaunchKernelGGL(k_decide, dim3((R->ns + kWaves - 1) / kWaves), dim3(64 * kWaves),
+                         kWaves * decide_lds_per_wave(lambda), st, R->tasks.p, R->ns,
                          lambda, R->hn.p, R->bsize.p, R->bstart.p, R->child.p, killed.p, killed_next.p, M.p, T->nodes,
                          P.alpha_num, P.alpha_den, insert ? 1 : 0, regions.p, d_regions);
       PKD_TRY(kernel_status("k_decide"));
