@@ -382,29 +382,42 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
     if (active) {
       for (int v = (1 << l) + lane; v < (2 << l); v += 64) {
         const int32_t u = hn[v];
-        if (!alive[v] || u < 0 || cnt[v] == 0) continue;
-        const Node nd = nodes[u];
-        const int sign = insert ? 1 : -1;
-        if (nd.left < 0) {
-          if (insert) {
-            const int at = atomicAdd(n_regions, 1);
-            regions[at] = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
+        bool add = false;   // node u becomes a region to rebuild
+        Region reg{};
+        if (alive[v] && u >= 0 && cnt[v] != 0) {
+          const Node nd = nodes[u];
+          const int sign = insert ? 1 : -1;
+          if (nd.left < 0) {
+            if (insert) {
+              add = true;
+              reg = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
+            } else {
+              nodes[u].size = nd.size - cnt[v];
+            }
+          } else if (l == lambda) {
+            killed_next[child_idx[static_cast<int64_t>(sig) * nheap + v]] = 0;
           } else {
-            nodes[u].size = nd.size - cnt[v];
+            const int64_t n2 = static_cast<int64_t>(nd.size) + sign * cnt[v];
+            const int64_t l2 = static_cast<int64_t>(nodes[nd.left].size) + sign * cnt[2 * v];
+            const bool bal = n2 > 0 && (ad - 2 * an) * n2 <= 2 * ad * l2 && 2 * ad * l2 <= (ad + 2 * an) * n2;
+            if (bal) {
+              nodes[u].size = static_cast<int32_t>(n2);
+              alive[2 * v] = alive[2 * v + 1] = 1;
+            } else {
+              add = true;
+              reg = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
+            }
           }
-        } else if (l == lambda) {
-          killed_next[child_idx[static_cast<int64_t>(sig) * nheap + v]] = 0;
-        } else {
-          const int64_t n2 = static_cast<int64_t>(nd.size) + sign * cnt[v];
-          const int64_t l2 = static_cast<int64_t>(nodes[nd.left].size) + sign * cnt[2 * v];
-          const bool bal = n2 > 0 && (ad - 2 * an) * n2 <= 2 * ad * l2 && 2 * ad * l2 <= (ad + 2 * an) * n2;
-          if (bal) {
-            nodes[u].size = static_cast<int32_t>(n2);
-            alive[2 * v] = alive[2 * v + 1] = 1;
-          } else {
-            const int at = atomicAdd(n_regions, 1);
-            regions[at] = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
-          }
+        }
+        // one atomic per wave for the regions its lanes add (a batch that
+        // touches millions of leaves would otherwise serialize on the counter)
+        const unsigned long long rm = __ballot(add);
+        if (rm) {
+          const int leader = __ffsll(static_cast<long long>(rm)) - 1;
+          int base = 0;
+          if (lane == leader) base = atomicAdd(n_regions, __popcll(rm));
+          base = __shfl(base, leader);
+          if (add) regions[base + __popcll(rm & ((1ULL << lane) - 1))] = reg;
         }
       }
     }
