@@ -333,6 +333,14 @@ __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
 // Replay of one routing round, top-down, with exact counts.  cnt(v) is the
 // weight of the batch slice below heap position v (1 per inserted point, 1 per
 // point actually removed); a killed task lies below a region.
+// For inserts (a region for every leaf that receives points) the decisions
+// run twice per round: apply = 0 only counts the regions each subproblem adds
+// (rcount[sig]) and writes nothing else; after an exclusive scan (roff),
+// apply = 1 makes the same decisions, updates the nodes and writes subproblem
+// sig's regions at n_regions + roff[sig] onwards, in a fixed order.  (A single
+// counter serialized millions of atomics when a batch touched millions of
+// leaves.)  Deletes add few regions and run apply = 1 alone with roff null:
+// one counter atomic per wave.
 __host__ __device__ inline size_t decide_lds_per_wave(int lambda) {
   return (static_cast<size_t>(2 << lambda) * (3 * sizeof(int32_t) + 1) + 15) & ~size_t{15};
 }
@@ -341,7 +349,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
                                                         const int32_t* bsize, const int32_t* bstart,
                                                         const int32_t* child_idx, const int8_t* killed,
                                                         int8_t* killed_next, const int32_t* M, Node* nodes, int64_t an,
-                                                        int64_t ad, int insert, Region* regions, int* n_regions) {
+                                                        int64_t ad, int insert, Region* regions, int* n_regions,
+                                                        int apply, int32_t* rcount, const int32_t* roff) {
   const int NB = 1 << lambda, nheap = 2 << lambda;
   // per wave: cnt, s0, sz [nheap] int32, alive [nheap] bytes (dynamic LDS,
   // sized for this lambda)
@@ -378,30 +387,35 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
   }
   if (active && lane == 0) alive[1] = 1;
   __syncthreads();
+  int added = 0;   // regions this wave has added so far (uniform)
+  const int32_t base = (apply && active && roff) ? *n_regions + roff[sig] : 0;
   for (int l = 0; l <= lambda; ++l) {
     if (active) {
-      for (int v = (1 << l) + lane; v < (2 << l); v += 64) {
-        const int32_t u = hn[v];
+      // every lane runs every step (the ballot keeps `added` uniform)
+      for (int v0 = 1 << l; v0 < (2 << l); v0 += 64) {
+        const int v = v0 + lane;
+        const bool in = v < (2 << l);
+        const int32_t u = in ? hn[v] : -1;
         bool add = false;   // node u becomes a region to rebuild
         Region reg{};
-        if (alive[v] && u >= 0 && cnt[v] != 0) {
+        if (in && alive[v] && u >= 0 && cnt[v] != 0) {
           const Node nd = nodes[u];
           const int sign = insert ? 1 : -1;
           if (nd.left < 0) {
             if (insert) {
               add = true;
               reg = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
-            } else {
+            } else if (apply) {
               nodes[u].size = nd.size - cnt[v];
             }
           } else if (l == lambda) {
-            killed_next[child_idx[static_cast<int64_t>(sig) * nheap + v]] = 0;
+            if (apply) killed_next[child_idx[static_cast<int64_t>(sig) * nheap + v]] = 0;
           } else {
             const int64_t n2 = static_cast<int64_t>(nd.size) + sign * cnt[v];
             const int64_t l2 = static_cast<int64_t>(nodes[nd.left].size) + sign * cnt[2 * v];
             const bool bal = n2 > 0 && (ad - 2 * an) * n2 <= 2 * ad * l2 && 2 * ad * l2 <= (ad + 2 * an) * n2;
             if (bal) {
-              nodes[u].size = static_cast<int32_t>(n2);
+              if (apply) nodes[u].size = static_cast<int32_t>(n2);
               alive[2 * v] = alive[2 * v + 1] = 1;
             } else {
               add = true;
@@ -409,21 +423,30 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
             }
           }
         }
-        // one atomic per wave for the regions its lanes add (a batch that
-        // touches millions of leaves would otherwise serialize on the counter)
         const unsigned long long rm = __ballot(add);
-        if (rm) {
-          const int leader = __ffsll(static_cast<long long>(rm)) - 1;
-          int base = 0;
-          if (lane == leader) base = atomicAdd(n_regions, __popcll(rm));
-          base = __shfl(base, leader);
-          if (add) regions[base + __popcll(rm & ((1ULL << lane) - 1))] = reg;
+        if (apply && rm) {
+          const int rank = __popcll(rm & ((1ULL << lane) - 1));
+          if (roff) {
+            if (add) regions[base + added + rank] = reg;
+          } else {
+            // few regions (deletes add them only where balance breaks): one
+            // atomic per wave
+            const int leader = __ffsll(static_cast<long long>(rm)) - 1;
+            int at = 0;
+            if (lane == leader) at = atomicAdd(n_regions, __popcll(rm));
+            at = __shfl(at, leader);
+            if (add) regions[at + rank] = reg;
+          }
         }
+        added += __popcll(rm);
       }
     }
     __syncthreads();
   }
+  if (!apply && lane == 0 && sig < ns) rcount[sig] = active ? added : 0;
 }
+
+__global__ void k_add_regions(int* n_regions, const int32_t* roff, int ns) { *n_regions += roff[ns]; }
 
 // Region bookkeeping on the old positions: regid marks the points inside each
 // region; for inserts the size change of a region is noted at its end.
@@ -741,6 +764,7 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   // ---- decide, round by round, top-down
   DArr<Region> regions(st);
   DArr<int8_t> killed(st), killed_next(st);
+  DArr<int32_t> rcount(st), roff(st);
   PKD_TRY(regions.need(static_cast<size_t>(m) + 1));
   if (rounds.empty()) {
     // the root is a leaf
@@ -762,11 +786,22 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
       const int nn = r + 1 < rounds.size() ? rounds[r + 1]->ns : 0;
       PKD_TRY(killed_next.need(static_cast<size_t>(nn) + 1));
       PKD_HIP(hipMemsetAsync(killed_next.p, 1, nn + 1, st));
-      hipLaunchKernelGGL(k_decide, dim3((R->ns + kWaves - 1) / kWaves), dim3(64 * kWaves),
-                         kWaves * decide_lds_per_wave(lambda), st, R->tasks.p, R->ns,
-                         lambda, R->hn.p, R->bsize.p, R->bstart.p, R->child.p, killed.p, killed_next.p, M.p, T->nodes,
-                         P.alpha_num, P.alpha_den, insert ? 1 : 0, regions.p, d_regions);
-      PKD_TRY(kernel_status("k_decide"));
+      if (insert) {
+        PKD_TRY(rcount.need(static_cast<size_t>(R->ns) + 1));
+        PKD_TRY(roff.need(static_cast<size_t>(R->ns) + 1));
+      }
+      for (int apply = insert ? 0 : 1; apply < 2; ++apply) {
+        hipLaunchKernelGGL(k_decide, dim3((R->ns + kWaves - 1) / kWaves), dim3(64 * kWaves),
+                           kWaves * decide_lds_per_wave(lambda), st, R->tasks.p, R->ns, lambda, R->hn.p, R->bsize.p,
+                           R->bstart.p, R->child.p, killed.p, killed_next.p, M.p, T->nodes, P.alpha_num, P.alpha_den,
+                           insert ? 1 : 0, regions.p, d_regions, apply, rcount.p, insert ? roff.p : nullptr);
+        PKD_TRY(kernel_status("k_decide"));
+        if (apply == 0) PKD_TRY(exscan_i32(st, rcount.p, roff.p, R->ns, bsum));
+      }
+      if (insert) {
+        hipLaunchKernelGGL(k_add_regions, dim3(1), dim3(1), 0, st, d_regions, roff.p, R->ns);
+        PKD_TRY(kernel_status("k_add_regions"));
+      }
       std::swap(killed.p, killed_next.p);
       std::swap(killed.cap, killed_next.cap);
     }
