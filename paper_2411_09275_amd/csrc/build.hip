@@ -1941,13 +1941,22 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int32_t* in, 
   if (blockIdx.x == gridDim.x - 1 && tid == kScanThreads - 1) out[n] = run;
 }
 
+// Up to this many block sums are scanned by the one-workgroup kernel; more
+// (inputs above 2^27) are scanned by this same three-pass scheme, in place.
+constexpr int64_t kScanSumsMax = int64_t{1} << 16;
+
 int exscan_i32(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, DArr<int32_t>& bsum) {
   const int64_t nb = std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock);
-  PKD_TRY(bsum.need(nb));
+  PKD_TRY(bsum.need(nb + 1));
   hipLaunchKernelGGL(k_scan_blocks, dim3(static_cast<unsigned>(nb)), dim3(kScanThreads), 0, st, in, n, bsum.p);
   PKD_TRY(kernel_status("k_scan_blocks"));
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum.p, nb);
-  PKD_TRY(kernel_status("k_scan_sums"));
+  if (nb <= kScanSumsMax) {
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum.p, nb);
+    PKD_TRY(kernel_status("k_scan_sums"));
+  } else {
+    DArr<int32_t> b2(st);
+    PKD_TRY(exscan_i32(st, bsum.p, bsum.p, nb, b2));   // each block reads its range before writing it
+  }
   hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nb)), dim3(kScanThreads), 0, st, in, n, bsum.p, out);
   PKD_TRY(kernel_status("k_scan_apply"));
   return PKD_OK;

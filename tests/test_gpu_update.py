@@ -215,3 +215,40 @@ def test_scattered_batches_route_by_sort(orc, pk):
     extra_i = np.concatenate([P.i[:50], ni[:50]])
     P.delete(np.ascontiguousarray(extra_c), extra_i)
     P.check("partial matches", q)
+
+
+def test_updates_on_a_tree_above_2_27_points(pk):
+    # the prefix sums over all points of an update then take their recursive
+    # form; answers are checked against brute force over the current set on
+    # the device (exact int64 arithmetic)
+    import torch
+    D, n0, m = 2, 150_000_000, 100_000
+    ids = torch.arange(n0, device="cuda", dtype=torch.int64)
+    c = synth.hashed_points_torch(ids, D, 21)
+    print("large tree build", flush=True)
+    t = pk.Tree(pk.Params(D), c, ids)
+    nid = torch.arange(n0, n0 + m, device="cuda", dtype=torch.int64)
+    nc = synth.hashed_points_torch(nid, D, 99)
+    t.insert(nc, nid)
+    assert t.size() == n0 + m
+    # delete every third original point of the first 3m
+    did = torch.arange(0, 3 * m, 3, device="cuda", dtype=torch.int64)
+    assert t.delete(c[:, did].contiguous(), did) == m
+    assert t.size() == n0
+    keep = torch.ones(n0, dtype=torch.bool, device="cuda")
+    keep[did] = False
+    allc = torch.cat([c[:, keep], nc], dim=1)
+    alli = torch.cat([ids[keep], nid])
+    q = torch.from_numpy(synth.uniform_queries(6, D, seed=5)).cuda()
+    gi, gd = t.knn(q, 10)
+    for j in range(q.shape[1]):
+        d2 = ((allc - q[:, j:j + 1]) ** 2).sum(0)
+        top = torch.topk(-d2, 64).indices
+        cand = sorted(zip(d2[top].tolist(), alli[top].tolist()))[:10]
+        assert gd[j].tolist() == [x for x, _ in cand] and gi[j].tolist() == [y for _, y in cand], j
+    lo, hi = (torch.from_numpy(x).cuda() for x in synth.log_uniform_boxes(6, D, seed=6))
+    rc = t.range_count(lo, hi)
+    for j in range(lo.shape[1]):
+        inside = ((allc >= lo[:, j:j + 1]) & (allc <= hi[:, j:j + 1])).all(0).sum().item()
+        assert rc[j].item() == inside, j
+    t.free()
