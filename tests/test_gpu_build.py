@@ -159,7 +159,7 @@ def test_knn_empty_tree_and_duplicates(orc, pk):
     # heavy leaves of identical points, scanned in several passes of 64 by the wave kernel
     c, i = synth.duplicate_heavy_points(30000, 2, seed=23, n_distinct=30)
     t = pk.Tree(pk.Params(2), c, i)
-    for k in (10, 100):
+    for k in (1, 3, 10, 24, 100):
         gi, gd = t.knn(q, k)
         bi, bd = orc.brute_knn(c, i, q, k)
         assert np.array_equal(gi.cpu().numpy(), bi) and np.array_equal(gd.cpu().numpy(), bd), k
