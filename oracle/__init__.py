@@ -27,7 +27,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with g++ into ``oracle/liboracle.so``."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -50,6 +50,13 @@ def lib():
         L.orc_build.restype = C.c_void_p
         L.orc_build.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int64, C.c_uint64,
                                 _i64p, _i64p, C.c_int64]
+        L.orc_build_at.restype = C.c_void_p
+        L.orc_build_at.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int64, C.c_uint64,
+                                   _i64p, _i64p, C.c_int64, C.c_int]
+        L.orc_update_log.argtypes = [C.c_void_p, _i64p]
+        L.orc_knn_threads.argtypes = [C.c_void_p, _i64p, C.c_int64, C.c_int, _i64p, _i64p, C.c_int]
+        L.orc_knn_visits.argtypes = [C.c_void_p, _i64p, C.c_int64, C.c_int, _i64p, _i64p, _i64p]
+        L.orc_range_report.argtypes = [C.c_void_p, _i64p, _i64p, C.c_int64, _i64p, _i64p]
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_size.restype = C.c_int64
         L.orc_size.argtypes = [C.c_void_p]
@@ -94,13 +101,15 @@ class Params:
 class Tree:
     """A sequential Pkd-tree held by the oracle library."""
 
-    def __init__(self, params: Params, coords, ids):
+    def __init__(self, params: Params, coords, ids, depth: int = 0):
+        """Build(P); `depth` places the root at that depth of an enclosing
+        tree (the depth salts the samples, as for a rebuilt node)."""
         coords, ids = _c(coords), _c(ids)
         assert coords.shape == (params.dim, ids.shape[0])
         self.p = params
-        self.h = lib().orc_build(params.dim, params.lam, params.phi, params.sigma, params.alpha[0],
-                                 params.alpha[1], C.c_uint64(params.seed & (2 ** 64 - 1)), coords, ids,
-                                 ids.shape[0])
+        self.h = lib().orc_build_at(params.dim, params.lam, params.phi, params.sigma, params.alpha[0],
+                                    params.alpha[1], C.c_uint64(params.seed & (2 ** 64 - 1)), coords, ids,
+                                    ids.shape[0], int(depth))
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -132,11 +141,48 @@ class Tree:
         lib().orc_knn(self.h, q, nq, k, ids, d2)
         return ids, d2
 
+    def knn_threads(self, q, k, threads):
+        """knn() with the queries split over `threads` host threads."""
+        q = _c(q)
+        nq = q.shape[1]
+        ids = np.empty((nq, k), dtype=np.int64)
+        d2 = np.empty((nq, k), dtype=np.int64)
+        lib().orc_knn_threads(self.h, q, nq, k, ids, d2, int(threads))
+        return ids, d2
+
+    def knn_visits(self, q, k):
+        """Per-query work of the search: (nodes read, leaves scanned, points
+        scanned), each int64 [nq]."""
+        q = _c(q)
+        nq = q.shape[1]
+        out = [np.empty(nq, dtype=np.int64) for _ in range(3)]
+        lib().orc_knn_visits(self.h, q, nq, k, *out)
+        return tuple(out)
+
     def range_count(self, lo, hi):
         lo, hi = _c(lo), _c(hi)
         out = np.empty(lo.shape[1], dtype=np.int64)
         lib().orc_range_count(self.h, lo, hi, lo.shape[1], out)
         return out
+
+    def range_report(self, lo, hi):
+        """(offsets [nb+1], ids): box j's point ids are ids[offsets[j]:offsets[j+1]],
+        in the tree's in-order."""
+        lo, hi = _c(lo), _c(hi)
+        cnt = self.range_count(lo, hi)
+        off = np.zeros(cnt.shape[0] + 1, dtype=np.int64)
+        np.cumsum(cnt, out=off[1:])
+        ids = np.empty(int(off[-1]), dtype=np.int64)
+        lib().orc_range_report(self.h, lo, hi, lo.shape[1], off, ids)
+        return off, ids
+
+    def update_log(self):
+        """What the last insert/delete rebuilt: dict with interior_rebuilds,
+        interior_points, leaf_rebuilds, leaf_points, kept."""
+        out = np.zeros(5, dtype=np.int64)
+        lib().orc_update_log(self.h, out)
+        keys = ("interior_rebuilds", "interior_points", "leaf_rebuilds", "leaf_points", "kept")
+        return dict(zip(keys, (int(v) for v in out)))
 
     def export(self):
         """Pre-order canonical form: rows [N,4] = (kind, dim, x, size) with kind

@@ -19,9 +19,15 @@
 //   * BatchDelete     -- Section 4.2, two rounds: sieve the batch to the leaves and
 //                        drop absent points, then rebuild the topmost subtrees that
 //                        are unbalanced under the exact new sizes.
-//   * k-NN, range count -- Section 2 (query definitions) and Section 5 (DFS with
-//                        on-the-fly subspaces, subtree sizes for counts).  The brute
-//                        force functions are the plain definitions themselves.
+//   * k-NN, range count, range report -- Section 2 (query definitions) and
+//                        Section 5 (DFS with on-the-fly subspaces, subtree sizes for
+//                        counts, flattened subtrees for reports).  The brute force
+//                        functions are the plain definitions themselves.
+//   * instrumentation  -- per-query work of the k-NN search (nodes read, leaves and
+//                        points scanned; the counts Appendix H reports) and what
+//                        each batch update rebuilt (the cost that the update
+//                        theorem of Section 4.3 amortizes).  Neither changes a
+//                        result.
 //
 // Readings where the paper is silent (all integer, so results are exact):
 //   split side: coordinate < x goes left, the rest right (Section 2);
@@ -49,6 +55,7 @@
 #include <cstdint>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -103,11 +110,22 @@ struct Node {
   std::vector<int64_t> pts;  // leaf only: point handles, in their stable order
 };
 
+// What the last batch update rebuilt (for the amortized-cost check of the
+// update theorem, Section 4.3): interior subtrees rebuilt because they became
+// unbalanced, leaves rebuilt because they received points, and kept interior
+// nodes whose size changed.
+struct UpdateLog {
+  int64_t interior_rebuilds = 0, interior_points = 0;
+  int64_t leaf_rebuilds = 0, leaf_points = 0;
+  int64_t kept = 0;
+};
+
 struct Tree {
   Params p;
   Store st;
   std::vector<Node> nodes;
   int root = -1;
+  UpdateLog log;
 };
 
 using Set = std::vector<int64_t>;  // a sequence of point handles
@@ -317,6 +335,8 @@ int insert_rec(Tree& T, int t, const Set& P, int h) {
   if (T.nodes[t].leaf) {
     Set all = T.nodes[t].pts;
     all.insert(all.end(), P.begin(), P.end());
+    T.log.leaf_rebuilds += 1;
+    T.log.leaf_points += static_cast<int64_t>(all.size());
     return build(T, all, h);
   }
   Set PL, PR;
@@ -327,8 +347,11 @@ int insert_rec(Tree& T, int t, const Set& P, int h) {
     Set all;
     collect(T, t, all);
     all.insert(all.end(), P.begin(), P.end());
+    T.log.interior_rebuilds += 1;
+    T.log.interior_points += static_cast<int64_t>(all.size());
     return build(T, all, h);
   }
+  T.log.kept += 1;
   int l = insert_rec(T, T.nodes[t].left, PL, h + 1);
   int r = insert_rec(T, T.nodes[t].right, PR, h + 1);
   T.nodes[t].left = l;
@@ -368,8 +391,11 @@ int delete_rec(Tree& T, int t, const std::vector<char>& marked, const std::vecto
     collect(T, t, all);
     for (int64_t q : all)
       if (!marked[q]) keep.push_back(q);
+    T.log.interior_rebuilds += 1;
+    T.log.interior_points += static_cast<int64_t>(keep.size());
     return build(T, keep, h);
   }
+  T.log.kept += 1;
   int l = delete_rec(T, T.nodes[t].left, marked, del, h + 1);
   int r = delete_rec(T, T.nodes[t].right, marked, del, h + 1);
   T.nodes[t].left = l;
@@ -396,6 +422,9 @@ struct KnnState {
   int64_t qs, j;
   size_t k;
   std::vector<Cand> best;  // sorted ascending, at most k entries
+  // work of the search (the per-query counts of Appendix H): nodes whose
+  // record is read (not pruned), leaves scanned, points scanned in them
+  int64_t nodes = 0, leaves = 0, points = 0;
   void offer(int64_t p) {
     Cand c{sqdist(T->st, p, q, qs, j), T->st.id[p]};
     if (best.size() == k && !(c < best.back())) return;
@@ -422,7 +451,10 @@ int64_t cell_bound(const KnnState& S, const std::vector<int64_t>& lo, const std:
 void knn_rec(KnnState& S, int t, std::vector<int64_t>& lo, std::vector<int64_t>& hi) {
   const Node& n = S.T->nodes[t];
   if (S.prune(cell_bound(S, lo, hi))) return;
+  S.nodes += 1;
   if (n.leaf) {
+    S.leaves += 1;
+    S.points += static_cast<int64_t>(n.pts.size());
     for (int64_t p : n.pts) S.offer(p);
     return;
   }
@@ -473,6 +505,47 @@ int64_t range_rec(const Tree& T, int t, std::vector<int64_t>& clo, std::vector<i
   total += range_rec(T, n.right, clo, chi, lo, hi, bs, j);
   clo[d] = save;
   return total;
+}
+
+// Range report (Section 5): the points of a closed box.  A cell inside the box
+// contributes its whole subtree (flattened); a leaf that straddles the box
+// contributes the points that lie in it; disjoint cells nothing.  Points are
+// appended in the tree's in-order.
+void range_report_rec(const Tree& T, int t, std::vector<int64_t>& clo, std::vector<int64_t>& chi,
+                      const int64_t* lo, const int64_t* hi, int64_t bs, int64_t j, std::vector<int64_t>& out) {
+  const Node& n = T.nodes[t];
+  int D = T.st.D;
+  bool inside = true;
+  for (int d = 0; d < D; ++d) {
+    if (chi[d] < lo[d * bs + j] || clo[d] > hi[d * bs + j]) return;   // disjoint
+    if (clo[d] < lo[d * bs + j] || chi[d] > hi[d * bs + j]) inside = false;
+  }
+  if (inside) {
+    Set all;
+    collect(T, t, all);
+    for (int64_t p : all) out.push_back(T.st.id[p]);
+    return;
+  }
+  if (n.leaf) {
+    for (int64_t p : n.pts) {
+      bool in = true;
+      for (int d = 0; d < D; ++d) {
+        int64_t v = T.st.coord(p, d);
+        if (v < lo[d * bs + j] || v > hi[d * bs + j]) in = false;
+      }
+      if (in) out.push_back(T.st.id[p]);
+    }
+    return;
+  }
+  int d = n.dim;
+  int64_t save = chi[d];
+  chi[d] = n.x - 1;
+  if (clo[d] <= chi[d]) range_report_rec(T, n.left, clo, chi, lo, hi, bs, j, out);
+  chi[d] = save;
+  save = clo[d];
+  clo[d] = n.x;
+  range_report_rec(T, n.right, clo, chi, lo, hi, bs, j, out);
+  clo[d] = save;
 }
 
 // --- Canonical export (pre-order) -----------------------------------------------
@@ -532,15 +605,34 @@ int orc_balanced(int64_t l, int64_t n, int64_t alpha_num, int64_t alpha_den) {
 }
 uint64_t orc_sample_key(uint64_t seed, int64_t h, int64_t id) { return sample_key(seed, h, id); }
 
-orc_tree* orc_build(int D, int lambda, int phi, int sigma, int64_t alpha_num, int64_t alpha_den,
-                    uint64_t seed, const int64_t* coords, const int64_t* ids, int64_t n) {
+// Build(P) with its root at depth h of an enclosing tree (h salts the samples;
+// a rebuild of a node at depth h is Build of its points at depth h).
+orc_tree* orc_build_at(int D, int lambda, int phi, int sigma, int64_t alpha_num, int64_t alpha_den,
+                       uint64_t seed, const int64_t* coords, const int64_t* ids, int64_t n, int h) {
   orc_tree* o = new orc_tree;
   o->t.p = make_params(D, lambda, phi, sigma, alpha_num, alpha_den, seed);
   o->t.st.D = D;
   Set Q;
   for (int64_t j = 0; j < n; ++j) Q.push_back(o->t.st.add(coords, n, j, ids[j]));
-  o->t.root = build(o->t, Q, 0);
+  o->t.root = build(o->t, Q, h);
   return o;
+}
+
+orc_tree* orc_build(int D, int lambda, int phi, int sigma, int64_t alpha_num, int64_t alpha_den,
+                    uint64_t seed, const int64_t* coords, const int64_t* ids, int64_t n) {
+  return orc_build_at(D, lambda, phi, sigma, alpha_num, alpha_den, seed, coords, ids, n, 0);
+}
+
+// What the last orc_insert / orc_delete rebuilt: out[0] interior subtrees
+// rebuilt, out[1] their points, out[2] leaves rebuilt, out[3] their points,
+// out[4] kept interior nodes that the batch reached.
+void orc_update_log(const orc_tree* o, int64_t* out) {
+  const UpdateLog& L = o->t.log;
+  out[0] = L.interior_rebuilds;
+  out[1] = L.interior_points;
+  out[2] = L.leaf_rebuilds;
+  out[3] = L.leaf_points;
+  out[4] = L.kept;
 }
 
 void orc_free(orc_tree* o) { delete o; }
@@ -552,6 +644,7 @@ int orc_height(const orc_tree* o) { return height_rec(o->t, o->t.root); }
 void orc_insert(orc_tree* o, const int64_t* coords, const int64_t* ids, int64_t m) {
   Set P;
   for (int64_t j = 0; j < m; ++j) P.push_back(o->t.st.add(coords, m, j, ids[j]));
+  o->t.log = UpdateLog();
   o->t.root = insert_rec(o->t, o->t.root, P, 0);
 }
 
@@ -581,6 +674,7 @@ int64_t orc_delete(orc_tree* o, const int64_t* coords, const int64_t* ids, int64
     }
   }
   std::vector<int64_t> del(T.nodes.size(), 0);
+  T.log = UpdateLog();
   count_marked(T, T.root, marked, del);
   T.root = delete_rec(T, T.root, marked, del, 0);
   return removed;
@@ -600,11 +694,65 @@ void orc_knn(const orc_tree* o, const int64_t* q, int64_t nq, int k, int64_t* ou
   }
 }
 
+// The same queries split into `threads` contiguous ranges, each answered by
+// orc_knn on its own thread (for timing the oracle on all host cores; the
+// per-query search is unchanged).
+void orc_knn_threads(const orc_tree* o, const int64_t* q, int64_t nq, int k, int64_t* out_ids, int64_t* out_d2,
+                     int threads) {
+  if (threads < 1) threads = 1;
+  const int64_t per = (nq + threads - 1) / threads;
+  std::vector<std::vector<int64_t>> qs(threads);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < threads; ++t) {
+    const int64_t a = std::min<int64_t>(nq, t * per), b = std::min<int64_t>(nq, a + per);
+    if (a >= b) break;
+    // the query block as its own [D][b-a] array
+    const int D = o->t.st.D;
+    qs[t].resize(static_cast<size_t>(D) * (b - a));
+    for (int d = 0; d < D; ++d)
+      for (int64_t j = a; j < b; ++j) qs[t][d * (b - a) + (j - a)] = q[d * nq + j];
+    pool.emplace_back([o, &qs, t, a, b, k, out_ids, out_d2]() {
+      orc_knn(o, qs[t].data(), b - a, k, out_ids + a * k, out_d2 + a * k);
+    });
+  }
+  for (auto& th : pool) th.join();
+}
+
+// Per-query work of the k-NN search: nodes read (not pruned), leaves scanned
+// and points scanned in them.
+void orc_knn_visits(const orc_tree* o, const int64_t* q, int64_t nq, int k, int64_t* nodes, int64_t* leaves,
+                    int64_t* points) {
+  const Tree& T = o->t;
+  for (int64_t j = 0; j < nq; ++j) {
+    KnnState S{&T, q, nq, j, static_cast<size_t>(k), {}};
+    std::vector<int64_t> lo(T.st.D, 0), hi(T.st.D, kCoordMax);
+    knn_rec(S, T.root, lo, hi);
+    nodes[j] = S.nodes;
+    leaves[j] = S.leaves;
+    points[j] = S.points;
+  }
+}
+
 void orc_range_count(const orc_tree* o, const int64_t* lo, const int64_t* hi, int64_t nb, int64_t* out) {
   const Tree& T = o->t;
   for (int64_t j = 0; j < nb; ++j) {
     std::vector<int64_t> clo(T.st.D, 0), chi(T.st.D, kCoordMax);
     out[j] = range_rec(T, T.root, clo, chi, lo, hi, nb, j);
+  }
+}
+
+// Range report: box j's point ids, in the tree's in-order, written from
+// out_ids[off[j]] on (off: prefix sums of the box counts, which the caller
+// takes from orc_range_count).
+void orc_range_report(const orc_tree* o, const int64_t* lo, const int64_t* hi, int64_t nb, const int64_t* off,
+                      int64_t* out_ids) {
+  const Tree& T = o->t;
+  std::vector<int64_t> ids;
+  for (int64_t j = 0; j < nb; ++j) {
+    std::vector<int64_t> clo(T.st.D, 0), chi(T.st.D, kCoordMax);
+    ids.clear();
+    range_report_rec(T, T.root, clo, chi, lo, hi, nb, j, ids);
+    std::copy(ids.begin(), ids.end(), out_ids + off[j]);
   }
 }
 
