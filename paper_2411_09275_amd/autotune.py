@@ -8,11 +8,14 @@ settings on a sample of the caller's workload (build plus its queries) on the
 GPU and returns the fastest; every caller that checks results against the CPU
 oracle must pass the chosen parameters to the oracle as well.
 
-The choice is cached in a JSON file keyed by device name, dimension and the
-decade of the tree size.
+The choice is cached in a JSON file keyed by device name, dimension, the
+decade of the sample size, whether the sample is one tree or a batch handle
+(and how many trees), the query mix (k of each query set) and a hash of the
+searched grid, so a stored choice is reused only for the same kind of workload.
 """
 from __future__ import annotations
 
+import hashlib
 import itertools
 import json
 import os
@@ -30,11 +33,13 @@ GRID = {
 }
 
 
-def _key(dim, n_points):
+def _key(dim, n_points, n_trees, ks, grid):
     import torch
     dev = torch.cuda.get_device_name(0)
     decade = len(str(max(1, int(n_points))))
-    return "%s|D=%d|n~1e%d" % (dev, dim, decade - 1)
+    shape = "single" if n_trees is None else "batch%d" % n_trees
+    g = hashlib.sha256(json.dumps({k: list(v) for k, v in sorted(grid.items())}).encode()).hexdigest()[:12]
+    return "%s|D=%d|n~1e%d|%s|k=%s|grid=%s" % (dev, dim, decade - 1, shape, ",".join(str(k) for k in ks) or "-", g)
 
 
 def _time(fn, reps=2):
@@ -65,9 +70,13 @@ def tune(dim, coords, ids, offsets=None, queries=None, k=10, grid=None, cache=DE
 
     grid = grid or GRID
     n_points = int(ids.shape[0])
-    key = _key(dim, n_points)
-    if isinstance(queries, (list, tuple)):
-        key += "|k=" + ",".join(str(kk) for _, kk, _ in queries)
+    if queries is None:
+        ks = []
+    elif isinstance(queries, (list, tuple)):
+        ks = [kk for _, kk, _ in queries]
+    else:
+        ks = [k]
+    key = _key(dim, n_points, None if offsets is None else len(offsets) - 1, ks, grid)
     if not force and cache and os.path.exists(cache):
         with open(cache) as f:
             stored = json.load(f)

@@ -353,3 +353,36 @@ def test_async_queries_match_and_report_errors_in_status(pk):
     t.knn_async(dbad, 10, oi, od, st2, stream=s)
     s.synchronize()
     assert int(st2.item()) & 1
+
+
+def test_direct_knn_and_range_count_entry_points(orc, pk):
+    # pkd_knn / pkd_range_count themselves (the binding's Tree methods go
+    # through the batch forms); results against the plain definitions
+    import ctypes as C
+    import torch
+    D = 3
+    c, i = synth.uniform_points(200000, D, seed=130)
+    op, gp = _params(orc, pk, D)
+    t = pk.Tree(gp, c, i)
+    L = pk.lib()
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for nq, k in ((1000, 10), (20000, 1), (3000, 100)):
+        q = torch.from_numpy(synth.uniform_queries(nq, D, seed=131 + k)).cuda()
+        oi = torch.full((nq, k), -7, dtype=torch.int64, device="cuda")
+        od = torch.full((nq, k), -7, dtype=torch.int64, device="cuda")
+        assert L.pkd_knn(t.h, s, C.c_void_p(q.data_ptr()), nq, k, C.c_void_p(oi.data_ptr()),
+                         C.c_void_p(od.data_ptr())) == 0
+        rows = np.arange(0, nq, max(1, nq // 300))
+        bi, bd = orc.brute_knn(c, i, np.ascontiguousarray(q.cpu().numpy()[:, rows]), k)
+        assert np.array_equal(oi.cpu().numpy()[rows], bi) and np.array_equal(od.cpu().numpy()[rows], bd), (nq, k)
+    lo, hi = (torch.from_numpy(x).cuda() for x in synth.log_uniform_boxes(500, D, seed=135))
+    out = torch.full((500,), -7, dtype=torch.int64, device="cuda")
+    assert L.pkd_range_count(t.h, s, C.c_void_p(lo.data_ptr()), C.c_void_p(hi.data_ptr()), 500,
+                             C.c_void_p(out.data_ptr())) == 0
+    assert np.array_equal(out.cpu().numpy(), orc.brute_range_count(c, lo.cpu().numpy(), hi.cpu().numpy()))
+    # a query outside [0, 2^30) is refused with PKD_ERR_RANGE
+    bad = torch.zeros((D, 4), dtype=torch.int64, device="cuda")
+    bad[1, 2] = 2 ** 30
+    assert L.pkd_knn(t.h, s, C.c_void_p(bad.data_ptr()), 4, 10, C.c_void_p(oi.data_ptr()),
+                     C.c_void_p(od.data_ptr())) == -2
+    t.free()

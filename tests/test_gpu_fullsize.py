@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import synth
+from tests import progress
 
 pytestmark = pytest.mark.gpu
 
@@ -17,7 +18,7 @@ N, DIM, NQ, NB = 100_000_000, 3, 10_000_000, 100_000
 
 
 def _log(msg, t0):
-    print("[fullsize %.1f s] %s" % (time.perf_counter() - t0, msg), flush=True)
+    progress.log("fullsize", msg)
 
 
 @pytest.fixture(scope="module")
