@@ -125,6 +125,22 @@ int pkd_knn(const pkd_tree* tree, void* stream, const int64_t* queries, int64_t 
             int32_t k, int64_t* out_ids, int64_t* out_d2);
 
 /*
+ * k-NN that allocates no device memory, for callers that cannot allocate while
+ * they run: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Arguments, results and errors as for pkd_knn, with
+ * nq <= PKD_KNN_NOALLOC_MAX_QUERIES (larger batches return
+ * PKD_ERR_UNSUPPORTED before any work is enqueued).  The scratch pkd_knn takes
+ * from the block cache (error flags, Morton keys, radix sort work arrays;
+ * 24 bytes per query) comes from one statically allocated device array of
+ * 25 MiB + 64 KiB per GPU, held until the process ends.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialized by the caller.  Synchronizes `stream`.
+ */
+#define PKD_KNN_NOALLOC_MAX_QUERIES 1048576
+int pkd_knn_noalloc(const pkd_tree* tree, void* stream, const int64_t* queries, int64_t nq,
+                    int32_t k, int64_t* out_ids, int64_t* out_d2);
+
+/*
  * Range count (Section 2; traversal with subtree sizes, Section 5).  For each
  * closed box [lo, hi] (device int64 [dim][nb] each) writes the number of stored
  * points p with lo_d <= p_d <= hi_d in every dimension into out (device int64

@@ -27,7 +27,7 @@ EXPORTS = ["pkd_default_params", "pkd_default_tuning", "pkd_build", "pkd_batch_i
            "pkd_knn", "pkd_range_count", "pkd_size", "pkd_export_sizes", "pkd_export", "pkd_height",
            "pkd_free", "pkd_strerror", "pkd_profile_enable", "pkd_profile_get", "pkd_build_batch",
            "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch", "pkd_export_tree_sizes", "pkd_export_tree",
-           "pkd_knn_async", "pkd_range_count_async"]
+           "pkd_knn_async", "pkd_range_count_async", "pkd_knn_noalloc"]
 
 
 class PkdError(RuntimeError):
@@ -78,10 +78,11 @@ def lib():
         L.pkd_export_tree_sizes.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i64)]
         L.pkd_export_tree.argtypes = [vp, i32, vp, vp, vp, vp]
         L.pkd_knn_async.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp]
+        L.pkd_knn_noalloc.argtypes = [vp, vp, vp, i64, i32, vp, vp]
         L.pkd_range_count_async.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.pkd_strerror.argtypes = [C.c_int]
         L.pkd_strerror.restype = C.c_char_p
-        for f in ("pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
+        for f in ("pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
                   "pkd_export_tree_sizes", "pkd_export_tree", "pkd_profile_enable", "pkd_profile_get", "pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
                   "pkd_height", "pkd_export_sizes", "pkd_export"):
             getattr(L, f).restype = C.c_int

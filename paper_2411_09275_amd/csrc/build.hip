@@ -1945,18 +1945,27 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int32_t* in, 
 // (inputs above 2^27) are scanned by this same three-pass scheme, in place.
 constexpr int64_t kScanSumsMax = int64_t{1} << 16;
 
+int64_t exscan_bsum_need(int64_t n) { return std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock) + 1; }
+
+int exscan_i32_raw(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, int32_t* bsum) {
+  const int64_t nb = std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock);
+  if (nb > kScanSumsMax) return PKD_ERR_INTERNAL;   // callers with larger inputs use exscan_i32
+  hipLaunchKernelGGL(k_scan_blocks, dim3(static_cast<unsigned>(nb)), dim3(kScanThreads), 0, st, in, n, bsum);
+  PKD_TRY(kernel_status("k_scan_blocks"));
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum, nb);
+  PKD_TRY(kernel_status("k_scan_sums"));
+  hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nb)), dim3(kScanThreads), 0, st, in, n, bsum, out);
+  return kernel_status("k_scan_apply");
+}
+
 int exscan_i32(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, DArr<int32_t>& bsum) {
   const int64_t nb = std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock);
   PKD_TRY(bsum.need(nb + 1));
+  if (nb <= kScanSumsMax) return exscan_i32_raw(st, in, out, n, bsum.p);
   hipLaunchKernelGGL(k_scan_blocks, dim3(static_cast<unsigned>(nb)), dim3(kScanThreads), 0, st, in, n, bsum.p);
   PKD_TRY(kernel_status("k_scan_blocks"));
-  if (nb <= kScanSumsMax) {
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum.p, nb);
-    PKD_TRY(kernel_status("k_scan_sums"));
-  } else {
-    DArr<int32_t> b2(st);
-    PKD_TRY(exscan_i32(st, bsum.p, bsum.p, nb, b2));   // each block reads its range before writing it
-  }
+  DArr<int32_t> b2(st);
+  PKD_TRY(exscan_i32(st, bsum.p, bsum.p, nb, b2));   // each block reads its range before writing it
   hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nb)), dim3(kScanThreads), 0, st, in, n, bsum.p, out);
   PKD_TRY(kernel_status("k_scan_apply"));
   return PKD_OK;
@@ -2083,26 +2092,27 @@ int bits_for(int64_t v) {
   return b;
 }
 
-int radix_sort_pairs(hipStream_t st, uint64_t* keys, uint32_t* vals, int64_t n, int nbits, SortWork& W,
-                     uint64_t** kout, uint32_t** vout) {
-  *kout = keys;
-  *vout = vals;
-  if (n <= 1 || nbits <= 0) return PKD_OK;
+int64_t radix_sort_blocks(int64_t n) { return (n + kRsTile - 1) / kRsTile; }
+
+namespace {
+// The passes of the sort over caller-provided work arrays: k1/v1 [n],
+// hist [256 * nblk], off [256 * nblk + 1]; the scans of the digit counts take
+// their block sums from `scan` (DArr) or, when it is null, from bsum_raw.
+int radix_passes(hipStream_t st, uint64_t* keys, uint32_t* vals, int64_t n, int nbits, uint64_t* k1, uint32_t* v1,
+                 int32_t* hist, int32_t* off, DArr<int32_t>* scan, int32_t* bsum_raw, uint64_t** kout,
+                 uint32_t** vout) {
   const int passes = (nbits + 7) / 8;
-  const int64_t nblk = (n + kRsTile - 1) / kRsTile;
-  PKD_TRY(W.k1.need(n));
-  PKD_TRY(W.v1.need(n));
-  PKD_TRY(W.hist.need(static_cast<size_t>(256) * nblk));
-  PKD_TRY(W.off.need(static_cast<size_t>(256) * nblk + 1));
+  const int64_t nblk = radix_sort_blocks(n);
   uint64_t* ka = keys;
-  uint64_t* kb = W.k1.p;
+  uint64_t* kb = k1;
   uint32_t* va = vals;
-  uint32_t* vb = W.v1.p;
+  uint32_t* vb = v1;
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(k_rs_count, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, ka, n, 8 * p, W.hist.p, nblk);
+    hipLaunchKernelGGL(k_rs_count, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, ka, n, 8 * p, hist, nblk);
     PKD_TRY(kernel_status("k_rs_count"));
-    PKD_TRY(exscan_i32(st, W.hist.p, W.off.p, 256 * nblk, W.bsum));
-    hipLaunchKernelGGL(k_rs_scatter, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, ka, va, n, 8 * p, W.off.p,
+    if (scan) PKD_TRY(exscan_i32(st, hist, off, 256 * nblk, *scan));
+    else PKD_TRY(exscan_i32_raw(st, hist, off, 256 * nblk, bsum_raw));
+    hipLaunchKernelGGL(k_rs_scatter, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, ka, va, n, 8 * p, off,
                        nblk, kb, vb);
     PKD_TRY(kernel_status("k_rs_scatter"));
     std::swap(ka, kb);
@@ -2111,6 +2121,28 @@ int radix_sort_pairs(hipStream_t st, uint64_t* keys, uint32_t* vals, int64_t n, 
   *kout = ka;
   *vout = va;
   return PKD_OK;
+}
+}  // namespace
+
+int radix_sort_pairs(hipStream_t st, uint64_t* keys, uint32_t* vals, int64_t n, int nbits, SortWork& W,
+                     uint64_t** kout, uint32_t** vout) {
+  *kout = keys;
+  *vout = vals;
+  if (n <= 1 || nbits <= 0) return PKD_OK;
+  const int64_t nblk = radix_sort_blocks(n);
+  PKD_TRY(W.k1.need(n));
+  PKD_TRY(W.v1.need(n));
+  PKD_TRY(W.hist.need(static_cast<size_t>(256) * nblk));
+  PKD_TRY(W.off.need(static_cast<size_t>(256) * nblk + 1));
+  return radix_passes(st, keys, vals, n, nbits, W.k1.p, W.v1.p, W.hist.p, W.off.p, &W.bsum, nullptr, kout, vout);
+}
+
+int radix_sort_pairs_raw(hipStream_t st, uint64_t* keys, uint32_t* vals, int64_t n, int nbits, const SortBufs& B,
+                         uint64_t** kout, uint32_t** vout) {
+  *kout = keys;
+  *vout = vals;
+  if (n <= 1 || nbits <= 0) return PKD_OK;
+  return radix_passes(st, keys, vals, n, nbits, B.k1, B.v1, B.hist, B.off, nullptr, B.bsum, kout, vout);
 }
 
 int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,

@@ -16,6 +16,8 @@ int run_knn(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* 
             int64_t* oi, int64_t* od, int* flags);
 int run_range(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, const int32_t* tree_of,
               int64_t nb, int64_t* out, int* flags);
+int run_knn_static(const pkd_tree* T, hipStream_t st, const int64_t* q, int64_t nq, int k, int64_t* oi,
+                   int64_t* od);
 int run_insert(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m);
 int run_delete(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m, int64_t* removed);
 
@@ -397,6 +399,15 @@ int pkd_range_count_async(const pkd_tree* tree, void* stream, const int64_t* lo,
 int pkd_knn(const pkd_tree* tree, void* stream, const int64_t* queries, int64_t nq, int32_t k, int64_t* out_ids,
             int64_t* out_d2) {
   return pkd_knn_batch(tree, stream, queries, nullptr, nq, k, out_ids, out_d2);
+}
+
+int pkd_knn_noalloc(const pkd_tree* tree, void* stream, const int64_t* queries, int64_t nq, int32_t k,
+                    int64_t* out_ids, int64_t* out_d2) {
+  if (!tree || nq < 0 || k < 1 || k > 128) return PKD_ERR_INVALID_ARG;
+  if (nq == 0) return PKD_OK;
+  if (!queries || !out_ids || !out_d2) return PKD_ERR_INVALID_ARG;
+  if (nq > PKD_KNN_NOALLOC_MAX_QUERIES) return PKD_ERR_UNSUPPORTED;
+  return run_knn_static(tree, static_cast<hipStream_t>(stream), queries, nq, k, out_ids, out_d2);
 }
 
 int pkd_range_count_batch(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi,

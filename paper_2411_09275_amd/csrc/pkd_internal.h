@@ -182,6 +182,21 @@ int radix_sort_pairs(hipStream_t st, uint64_t* keys, uint32_t* vals, int64_t n, 
                      uint64_t** kout, uint32_t** vout);
 int bits_for(int64_t v);   // bits needed to write 0 .. v
 
+// The same scan and sort over work arrays the caller provides (nothing is
+// allocated): exscan_i32_raw needs bsum [exscan_bsum_need(n)] and n below
+// 2^27; the sort needs k1/v1 [n], hist [256 * radix_sort_blocks(n)],
+// off [256 * radix_sort_blocks(n) + 1] and bsum [exscan_bsum_need(256 * blocks)].
+int64_t exscan_bsum_need(int64_t n);
+int exscan_i32_raw(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, int32_t* bsum);
+int64_t radix_sort_blocks(int64_t n);
+struct SortBufs {
+  uint64_t* k1;
+  uint32_t* v1;
+  int32_t *hist, *off, *bsum;
+};
+int radix_sort_pairs_raw(hipStream_t st, uint64_t* keys, uint32_t* vals, int64_t n, int nbits, const SortBufs& B,
+                         uint64_t** kout, uint32_t** vout);
+
 // (Re)allocate the packed 32-bit coordinates for the tree's capacity, and
 // rewrite them from buf[cur] for all n points.
 int ensure_c32(pkd_tree* T, hipStream_t st);

@@ -4,6 +4,7 @@
 // counts run one wave per query.  The subspace of a node is not stored but
 // derived on the way down from the splitters (no bounding boxes, Section 5).
 #include <algorithm>
+#include <mutex>
 
 #include "pkd_internal.h"
 
@@ -886,16 +887,24 @@ struct QueryOrder {
 
 // Fills *perm with the queries in Morton order, or leaves it null for small
 // batches.  Stream-ordered, no host synchronisation.
+// Bits of position per dimension and key bits of the Morton order.
+template <int D>
+void morton_bits(int64_t nq, const int32_t* tree_of, int32_t n_trees, int* bpd_out, int* nbits_out) {
+  const int tb = tree_of ? bits_for(n_trees - 1) : 0;
+  // about 64 cells per wave of queries: log2(nq) + 6 bits of position
+  int bpd = (bits_for(nq) + 6 + D - 1) / D;
+  bpd = std::min(bpd, std::min(30, (64 - tb) / D));
+  *bpd_out = bpd;
+  *nbits_out = tb + D * bpd;
+}
+
 template <int D>
 int order_queries(hipStream_t st, const int64_t* Q, int64_t nq, const int32_t* tree_of, int32_t n_trees,
                   QueryOrder& W, const uint32_t** perm) {
   *perm = nullptr;
   if (nq < kOrderMinQueries) return PKD_OK;
-  const int tb = tree_of ? bits_for(n_trees - 1) : 0;
-  // about 64 cells per wave of queries: log2(nq) + 6 bits of position
-  int bpd = (bits_for(nq) + 6 + D - 1) / D;
-  bpd = std::min(bpd, std::min(30, (64 - tb) / D));
-  const int nbits = tb + D * bpd;
+  int bpd = 0, nbits = 0;
+  morton_bits<D>(nq, tree_of, n_trees, &bpd, &nbits);
   PKD_TRY(W.k0.need(nq));
   PKD_TRY(W.v0.need(nq));
   hipLaunchKernelGGL(k_morton<D>, dim3(static_cast<unsigned>((nq + 255) / 256)), dim3(256), 0, st, Q, nq, tree_of,
@@ -939,15 +948,13 @@ void launch_knn(int km, dim3 g, hipStream_t st, const Node* nodes, const int32_t
 #undef PKD_KNN_CASE
 }
 
+// Launches the k-NN kernel for the queries in the order `perm` (null: as given).
 template <int D>
-int knn_d(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tree_of, int64_t nq, int k,
-          int64_t* oi, int64_t* od, int* flags) {
+int knn_launch(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tree_of, int64_t nq, int k,
+               int64_t* oi, int64_t* od, int* flags, const uint32_t* perm) {
   int km = 1;
   while (km < k) km <<= 1;
   if (k == 9 || k == 10) km = 10;   // the common k = 10 without six idle slots
-  QueryOrder W(st);
-  const uint32_t* perm = nullptr;
-  PKD_TRY(order_queries<D>(st, q, nq, tree_of, T->n_trees, W, &perm));
   const dim3 g(static_cast<unsigned>((nq + kQBlock - 1) / kQBlock));
   const int32_t* X = T->c32;
   const int64_t* ids = T->buf[T->cur] + static_cast<int64_t>(D) * T->cap;
@@ -965,6 +972,15 @@ int knn_d(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tr
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_status(e, "k_knn");
   return PKD_OK;
+}
+
+template <int D>
+int knn_d(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tree_of, int64_t nq, int k,
+          int64_t* oi, int64_t* od, int* flags) {
+  QueryOrder W(st);
+  const uint32_t* perm = nullptr;
+  PKD_TRY(order_queries<D>(st, q, nq, tree_of, T->n_trees, W, &perm));
+  return knn_launch<D>(T, st, q, tree_of, nq, k, oi, od, flags, perm);
 }
 
 template <int D>
@@ -998,7 +1014,120 @@ int range_d(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t*
   return PKD_OK;
 }
 
+// ------------------------------------------------ allocation-free k-NN
+// pkd_knn_static takes every scratch array of pkd_knn (error flags, Morton
+// keys and the radix sort's work arrays) from one statically allocated device
+// array instead of the block cache.  Layout for nq queries, each part aligned
+// to 256 bytes.
+struct StaticLayout {
+  size_t flags, k0, v0, k1, v1, hist, off, bsum, end;
+  explicit StaticLayout(int64_t nq) {
+    const int64_t nblk = radix_sort_blocks(std::max<int64_t>(nq, 1));
+    size_t at = 0;
+    auto take = [&at](size_t bytes) {
+      const size_t here = at;
+      at = (at + bytes + 255) & ~size_t{255};
+      return here;
+    };
+    flags = take(4 * sizeof(int));
+    k0 = take(sizeof(uint64_t) * nq);
+    v0 = take(sizeof(uint32_t) * nq);
+    k1 = take(sizeof(uint64_t) * nq);
+    v1 = take(sizeof(uint32_t) * nq);
+    hist = take(sizeof(int32_t) * 256 * nblk);
+    off = take(sizeof(int32_t) * (256 * nblk + 1));
+    bsum = take(sizeof(int32_t) * exscan_bsum_need(256 * nblk));
+    end = at;
+  }
+};
+
+__global__ void k_clear_i32(int32_t* a, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = 0;
+}
+
+template <int D>
+int knn_static_d(const pkd_tree* T, hipStream_t st, const int64_t* q, int64_t nq, int k, int64_t* oi, int64_t* od,
+                 unsigned char* base, const StaticLayout& L) {
+  int* flags = reinterpret_cast<int*>(base + L.flags);
+  const uint32_t* perm = nullptr;
+  if (nq >= kOrderMinQueries) {
+    int bpd = 0, nbits = 0;
+    morton_bits<D>(nq, nullptr, T->n_trees, &bpd, &nbits);
+    uint64_t* k0 = reinterpret_cast<uint64_t*>(base + L.k0);
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(base + L.v0);
+    hipLaunchKernelGGL(k_morton<D>, dim3(static_cast<unsigned>((nq + 255) / 256)), dim3(256), 0, st, q, nq,
+                       nullptr, bpd, k0, v0);
+    PKD_TRY(kernel_status("k_morton"));
+    SortBufs B{reinterpret_cast<uint64_t*>(base + L.k1), reinterpret_cast<uint32_t*>(base + L.v1),
+               reinterpret_cast<int32_t*>(base + L.hist), reinterpret_cast<int32_t*>(base + L.off),
+               reinterpret_cast<int32_t*>(base + L.bsum)};
+    uint64_t* ks = nullptr;
+    uint32_t* vs = nullptr;
+    PKD_TRY(radix_sort_pairs_raw(st, k0, v0, nq, nbits, B, &ks, &vs));
+    perm = vs;
+  }
+  return knn_launch<D>(T, st, q, nullptr, nq, k, oi, od, flags, perm);
+}
+
 }  // namespace
+
+// The array itself; host code never passes its name to a kernel, only the
+// per-device address that hipGetSymbolAddress returns for it.
+constexpr int64_t kStaticMaxQueries = PKD_KNN_NOALLOC_MAX_QUERIES;
+constexpr size_t kStaticScratchBytes = (size_t{25} << 20) + (size_t{64} << 10);   // 25 MiB + 64 KiB
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The array's address on the current device (looked up once per device).
+int static_scratch(unsigned char** out) {
+  int dev = 0;
+  PKD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return PKD_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    PKD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return PKD_ERR_HIP;
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return PKD_OK;
+}
+}  // namespace
+
+int run_knn_static(const pkd_tree* T, hipStream_t st, const int64_t* q, int64_t nq, int k, int64_t* oi,
+                   int64_t* od) {
+  if (nq > kStaticMaxQueries) return PKD_ERR_UNSUPPORTED;
+  const StaticLayout L(nq);
+  if (L.end > kStaticScratchBytes) return PKD_ERR_INTERNAL;
+  unsigned char* base = nullptr;
+  PKD_TRY(static_scratch(&base));
+  int* flags = reinterpret_cast<int*>(base + L.flags);
+  hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, st, flags, 4);
+  PKD_TRY(kernel_status("k_clear_i32"));
+  int rc = PKD_ERR_UNSUPPORTED;
+  switch (T->prm.D) {
+    case 1: rc = knn_static_d<1>(T, st, q, nq, k, oi, od, base, L); break;
+    case 2: rc = knn_static_d<2>(T, st, q, nq, k, oi, od, base, L); break;
+    case 3: rc = knn_static_d<3>(T, st, q, nq, k, oi, od, base, L); break;
+    case 4: rc = knn_static_d<4>(T, st, q, nq, k, oi, od, base, L); break;
+    case 5: rc = knn_static_d<5>(T, st, q, nq, k, oi, od, base, L); break;
+    case 6: rc = knn_static_d<6>(T, st, q, nq, k, oi, od, base, L); break;
+    case 7: rc = knn_static_d<7>(T, st, q, nq, k, oi, od, base, L); break;
+  }
+  if (rc != PKD_OK) return rc;
+  int h = 0;
+  PKD_HIP(hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  PKD_HIP(hipStreamSynchronize(st));
+  if (h & kErrRange) return PKD_ERR_RANGE;
+  if (h & kErrStack) return PKD_ERR_CAPACITY;
+  if (h) return PKD_ERR_INTERNAL;
+  return PKD_OK;
+}
 
 int run_knn(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tree_of, int64_t nq, int k,
             int64_t* oi, int64_t* od, int* flags) {
