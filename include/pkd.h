@@ -29,15 +29,21 @@
  *   - Ids are caller-chosen int64 values and must be unique within a tree
  *     (precondition; not checked).
  *   - A tree owns its device storage.  The library takes device memory from
+ *     the allocator the caller installed with pkd_set_allocator, else from
  *     its own block cache (hipMalloc'd blocks of rounded sizes, kept after a
  *     free for reuse, a reuse on another stream ordered after the freeing
  *     stream by an event); the cache keeps at most half of device memory.
  *     A tree must not be used by two calls concurrently.
- *   - On any error a mutating call leaves the tree as it was.
+ *   - A mutating call (pkd_batch_insert, pkd_batch_delete) that fails leaves
+ *     the tree as it was: it allocates everything it needs, and builds the
+ *     subtrees it replaces in memory of its own, before it changes the tree.
+ *     (PKD_ERR_HIP from a failing device is the exception: the device state
+ *     is then unknown.)
  */
 #ifndef PKD_H
 #define PKD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -77,6 +83,31 @@ typedef struct {
                                runs; the tree never changes */
   int32_t reserved[6];
 } pkd_tuning;
+
+/*
+ * Device memory supplied by the caller (for example a framework's caching
+ * allocator).  alloc returns at least `bytes` bytes of device memory usable in
+ * work ordered on `stream` (a hipStream_t as void*), or NULL when it cannot;
+ * the library then fails the call with PKD_ERR_OOM.  free returns a block the
+ * library no longer needs; work enqueued on `stream` before the free may still
+ * use it, so the allocator must not hand it to other streams before that work
+ * is done.  Both may be called from any thread that calls into the library,
+ * without library locks held.
+ */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, size_t bytes, void* stream, void* ctx);
+  void* ctx;
+} pkd_allocator;
+
+/*
+ * Install `a` (copied) as the source of all later device allocations of the
+ * library, or go back to the library's block cache with NULL.  Blocks always
+ * return to the allocator that made them, so its functions and ctx must stay
+ * valid as long as the library holds any block they returned (for example a
+ * tree built while it was installed).  Trees may exist while it changes.
+ */
+int pkd_set_allocator(const pkd_allocator* a);
 
 /* Fill defaults for dimension `dim`. */
 void pkd_default_params(pkd_params* p, int32_t dim);
@@ -236,8 +267,20 @@ int pkd_height(const pkd_tree* tree, int32_t* height);
 int pkd_profile_enable(int32_t on);
 int pkd_profile_get(int32_t kernel, int64_t* launches, double* total_ms, double* alg_bytes);
 
-/* Release a tree (NULL is ignored). */
+/* Release a tree (NULL is ignored).  Waits for all work on the device first. */
 void pkd_free(pkd_tree* tree);
+
+/*
+ * Release a tree in stream order: its memory is reused only by work ordered
+ * after what was enqueued on `stream` before this call; the caller must not
+ * have work that uses the tree on other streams still in flight.  Does not
+ * synchronize.
+ */
+int pkd_free_async(pkd_tree* tree, void* stream);
+
+/* Node records the tree holds, live and dead (updates leave the records of
+ * replaced nodes dead until a compaction drops them; a diagnostic). */
+int pkd_node_slots(const pkd_tree* tree, int64_t* slots);
 
 const char* pkd_strerror(int code);
 

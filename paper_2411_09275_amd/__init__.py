@@ -27,7 +27,8 @@ EXPORTS = ["pkd_default_params", "pkd_default_tuning", "pkd_build", "pkd_batch_i
            "pkd_knn", "pkd_range_count", "pkd_size", "pkd_export_sizes", "pkd_export", "pkd_height",
            "pkd_free", "pkd_strerror", "pkd_profile_enable", "pkd_profile_get", "pkd_build_batch",
            "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch", "pkd_export_tree_sizes", "pkd_export_tree",
-           "pkd_knn_async", "pkd_range_count_async", "pkd_knn_noalloc"]
+           "pkd_knn_async", "pkd_range_count_async", "pkd_knn_noalloc", "pkd_set_allocator", "pkd_free_async",
+           "pkd_node_slots"]
 
 
 class PkdError(RuntimeError):
@@ -39,6 +40,14 @@ class PkdError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("lambda_", C.c_int32), ("leaf_size", C.c_int32), ("oversample", C.c_int32),
                 ("alpha_num", C.c_int32), ("alpha_den", C.c_int32), ("seed", C.c_uint64)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
 
 
 class _Tuning(C.Structure):
@@ -79,10 +88,13 @@ def lib():
         L.pkd_export_tree.argtypes = [vp, i32, vp, vp, vp, vp]
         L.pkd_knn_async.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp]
         L.pkd_knn_noalloc.argtypes = [vp, vp, vp, i64, i32, vp, vp]
+        L.pkd_set_allocator.argtypes = [C.POINTER(_Allocator)]
+        L.pkd_free_async.argtypes = [vp, vp]
+        L.pkd_node_slots.argtypes = [vp, C.POINTER(i64)]
         L.pkd_range_count_async.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.pkd_strerror.argtypes = [C.c_int]
         L.pkd_strerror.restype = C.c_char_p
-        for f in ("pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
+        for f in ("pkd_set_allocator", "pkd_free_async", "pkd_node_slots", "pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
                   "pkd_export_tree_sizes", "pkd_export_tree", "pkd_profile_enable", "pkd_profile_get", "pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
                   "pkd_height", "pkd_export_sizes", "pkd_export"):
             getattr(L, f).restype = C.c_int
@@ -142,6 +154,46 @@ def profile_get(name: str):
     n, ms, b = C.c_int64(), C.c_double(), C.c_double()
     _check(lib().pkd_profile_get(PROFILE_KERNELS[name], C.byref(n), C.byref(ms), C.byref(b)), "pkd_profile_get")
     return n.value, ms.value, b.value
+
+
+# every allocator ever installed: blocks go back to the allocator that made
+# them, also after another one was installed, so its ctypes callbacks must
+# outlive it
+_installed = []
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the library's device allocations through Python callables:
+    alloc(bytes, stream_handle) -> device pointer (int) or 0, and
+    free(ptr, bytes, stream_handle).  With no arguments the library's own
+    block cache is used again."""
+    if alloc is None:
+        _check(lib().pkd_set_allocator(None), "pkd_set_allocator")
+        return
+
+    def _a(nbytes, stream, ctx):
+        try:
+            return int(alloc(int(nbytes), stream or 0)) or None
+        except Exception:   # an exception cannot cross the C boundary
+            return None
+
+    def _f(ptr, nbytes, stream, ctx):
+        try:
+            free(int(ptr), int(nbytes), stream or 0)
+        except Exception:
+            pass
+
+    a = _Allocator(ALLOC_FN(_a), FREE_FN(_f), None)
+    _installed.append(a)
+    _check(lib().pkd_set_allocator(C.byref(a)), "pkd_set_allocator")
+
+
+def use_torch_allocator():
+    """Take the library's device memory from PyTorch's caching allocator."""
+    torch = _torch()
+    dev = torch.cuda.current_device()
+    set_allocator(lambda n, s: torch.cuda.caching_allocator_alloc(n, dev, s),
+                  lambda p, n, s: torch.cuda.caching_allocator_delete(p))
 
 
 class Params:
@@ -208,10 +260,20 @@ class Tree:
     def __del__(self):
         self.free()
 
-    def free(self):
+    def free(self, stream=None):
+        """Release the tree; with a stream, in stream order without waiting
+        (pkd_free_async), else after all device work (pkd_free)."""
         if getattr(self, "h", None) is not None and self.h.value:
-            lib().pkd_free(self.h)
+            if stream is None:
+                lib().pkd_free(self.h)
+            else:
+                _check(lib().pkd_free_async(self.h, _stream(stream)), "pkd_free_async")
         self.h = None
+
+    def node_slots(self) -> int:
+        n = C.c_int64()
+        _check(lib().pkd_node_slots(self.h, C.byref(n)), "pkd_node_slots")
+        return n.value
 
     def size(self) -> int:
         n = C.c_int64()

@@ -49,6 +49,17 @@ std::unordered_map<void*, size_t> g_size;    // live and cached blocks -> size c
 size_t g_cached = 0, g_limit = 0;
 uint64_t g_clock = 0;
 
+// A caller-installed allocator (pkd_set_allocator) replaces the cache for new
+// blocks; every block remembers the allocator that made it, so it goes back
+// there even after the caller switched allocators.
+bool g_ext_on = false;
+pkd_allocator g_ext;
+struct ExtBlock {
+  pkd_allocator a;
+  size_t bytes;
+};
+std::unordered_map<void*, ExtBlock> g_ext_blocks;
+
 }  // namespace
 
 size_t dev_size_class(size_t b) {
@@ -82,6 +93,23 @@ void evict_oldest_until(size_t limit) {
 int dev_alloc(void** p, size_t bytes, hipStream_t s) {
   *p = nullptr;
   const size_t cls = dev_size_class(bytes);
+  pkd_allocator ext;
+  bool use_ext = false;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    use_ext = g_ext_on;
+    ext = g_ext;
+  }
+  if (use_ext) {
+    // the callback runs without the library's lock held (it may call back
+    // into a runtime that takes locks of its own)
+    void* q = ext.alloc(cls, static_cast<void*>(s), ext.ctx);
+    if (!q) return PKD_ERR_OOM;
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_ext_blocks[q] = ExtBlock{ext, cls};
+    *p = q;
+    return PKD_OK;
+  }
   std::lock_guard<std::mutex> lock(g_mu);
   if (g_limit == 0) {
     size_t free_b = 0, total_b = 0;
@@ -113,6 +141,23 @@ int dev_alloc(void** p, size_t bytes, hipStream_t s) {
 
 void dev_free(void* p, hipStream_t s) {
   if (!p) return;
+  {
+    ExtBlock blk;
+    bool found = false;
+    {
+      std::lock_guard<std::mutex> lock(g_mu);
+      auto it = g_ext_blocks.find(p);
+      if (it != g_ext_blocks.end()) {
+        blk = it->second;
+        g_ext_blocks.erase(it);
+        found = true;
+      }
+    }
+    if (found) {
+      blk.a.free(p, blk.bytes, static_cast<void*>(s), blk.a.ctx);
+      return;
+    }
+  }
   std::lock_guard<std::mutex> lock(g_mu);
   auto sz = g_size.find(p);
   if (sz == g_size.end()) return;
@@ -256,10 +301,31 @@ void release(pkd_tree* T, hipStream_t st) {
   dev_free(T->buf[1], st);
   dev_free(T->nodes, st);
   dev_free(T->c32, st);
+  dev_free(T->c32_twin, st);
   T->buf[0] = T->buf[1] = nullptr;
   T->nodes = nullptr;
-  T->c32 = nullptr;
-  T->c32_cap = 0;
+  T->c32 = T->c32_twin = nullptr;
+  T->c32_cap = T->c32_twin_cap = 0;
+  T->node_cap = 0;
+  T->node_count = 0;
+}
+
+void swap_storage(pkd_tree* a, pkd_tree* b) {
+  std::swap(a->n, b->n);
+  std::swap(a->cap, b->cap);
+  std::swap(a->buf[0], b->buf[0]);
+  std::swap(a->buf[1], b->buf[1]);
+  std::swap(a->cur, b->cur);
+  std::swap(a->c32, b->c32);
+  std::swap(a->c32_cap, b->c32_cap);
+  std::swap(a->c32_twin, b->c32_twin);
+  std::swap(a->c32_twin_cap, b->c32_twin_cap);
+  std::swap(a->nodes, b->nodes);
+  std::swap(a->node_cap, b->node_cap);
+  std::swap(a->node_count, b->node_count);
+  std::swap(a->compact_mark, b->compact_mark);
+  std::swap(a->height, b->height);
+  std::swap(a->n_trees, b->n_trees);
 }
 
 int write_empty_root(pkd_tree* T, hipStream_t st) {
@@ -288,6 +354,43 @@ int flags_check(int* f, hipStream_t st) {
   if (h & kErrRange) return PKD_ERR_RANGE;
   if (h & kErrStack) return PKD_ERR_CAPACITY;
   if (h) return PKD_ERR_INTERNAL;
+  return PKD_OK;
+}
+
+int build_new(const Params& prm, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t n,
+              bool headroom, pkd_tree** out) {
+  *out = nullptr;
+  pkd_tree* T = new pkd_tree;
+  T->prm = prm;
+  // room for later inserts: a sixteenth more than the points (plus what the
+  // rounded allocation holds), so moderate batches never reallocate
+  int rc = alloc_points(T, st, headroom ? n + n / 16 : n);
+  if (rc == PKD_OK) rc = ensure_nodes(T, st, std::max<int64_t>(1024, n / 8));
+  if (rc == PKD_OK) {
+    if (n == 0) {
+      rc = write_empty_root(T, st);
+    } else {
+      T->node_count = 1;
+      T->height = 0;
+      Task root;
+      root.start = 0;
+      root.m = static_cast<int32_t>(n);
+      root.slot = 0;
+      root.depth = 0;
+      root.buf = 2;
+      root.mode = 0;
+      rc = build_tasks(T, st, std::vector<Task>{root}, coords, ids, n);
+    }
+  }
+  if (rc != PKD_OK) {
+    release(T, st);
+    (void)hipStreamSynchronize(st);
+    delete T;
+    return rc;
+  }
+  T->n = n;
+  T->compact_mark = T->node_count;
+  *out = T;
   return PKD_OK;
 }
 
@@ -322,38 +425,7 @@ int pkd_build(const pkd_params* params, const pkd_tuning* tuning, void* stream, 
   PKD_TRY(check_params(params, tuning, &prm));
   if (n < 0 || (n > 0 && (!coords || !ids))) return PKD_ERR_INVALID_ARG;
   if (n >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  pkd_tree* T = new pkd_tree;
-  T->prm = prm;
-  // room for later inserts: a sixteenth more than the points (plus what the
-  // rounded allocation holds), so moderate batches never reallocate
-  int rc = alloc_points(T, st, n + n / 16);
-  if (rc == PKD_OK) rc = ensure_nodes(T, st, std::max<int64_t>(1024, n / 8));
-  if (rc == PKD_OK) {
-    if (n == 0) {
-      rc = write_empty_root(T, st);
-    } else {
-      T->node_count = 1;
-      T->height = 0;
-      Task root;
-      root.start = 0;
-      root.m = static_cast<int32_t>(n);
-      root.slot = 0;
-      root.depth = 0;
-      root.buf = 2;
-      root.mode = 0;
-      rc = build_tasks(T, st, std::vector<Task>{root}, coords, ids, n);
-    }
-  }
-  if (rc != PKD_OK) {
-    release(T, st);
-    (void)hipStreamSynchronize(st);
-    delete T;
-    return rc;
-  }
-  T->n = n;
-  *out = T;
-  return PKD_OK;
+  return build_new(prm, static_cast<hipStream_t>(stream), coords, ids, n, true, out);
 }
 
 int pkd_knn_batch(const pkd_tree* tree, void* stream, const int64_t* queries, const int32_t* tree_of, int64_t nq,
@@ -483,6 +555,7 @@ int pkd_build_batch(const pkd_params* params, const pkd_tuning* tuning, void* st
     return rc;
   }
   T->n = n;
+  T->compact_mark = T->node_count;
   *out = T;
   return PKD_OK;
 }
@@ -647,6 +720,29 @@ void pkd_free(pkd_tree* tree) {
   release(tree, nullptr);
   (void)hipDeviceSynchronize();
   delete tree;
+}
+
+int pkd_free_async(pkd_tree* tree, void* stream) {
+  if (!tree) return PKD_OK;
+  // every block goes back with an event on `stream`: its next user waits for
+  // the work enqueued on `stream` before this call
+  release(tree, static_cast<hipStream_t>(stream));
+  delete tree;
+  return PKD_OK;
+}
+
+int pkd_set_allocator(const pkd_allocator* a) {
+  if (a && (!a->alloc || !a->free)) return PKD_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_ext_on = a != nullptr;
+  if (a) g_ext = *a;
+  return PKD_OK;
+}
+
+int pkd_node_slots(const pkd_tree* tree, int64_t* slots) {
+  if (!tree || !slots) return PKD_ERR_INVALID_ARG;
+  *slots = tree->node_count;
+  return PKD_OK;
 }
 
 const char* pkd_strerror(int code) {

@@ -97,9 +97,14 @@ struct pkd_tree {
   // what the query kernels scan, at half the bytes of the int64 rows
   int32_t* c32 = nullptr;
   int64_t c32_cap = 0;
+  // the second packed copy an update writes its new layout into (swapped
+  // with c32 when the update commits)
+  int32_t* c32_twin = nullptr;
+  int64_t c32_twin_cap = 0;
   pkd::Node* nodes = nullptr;
   int64_t node_cap = 0;
-  int32_t node_count = 0; // nodes allocated (node 0 is the root)
+  int32_t node_count = 0; // node records in use, live or dead (node 0 is the root)
+  int32_t compact_mark = 0;  // node_count after the last build or compaction
   int32_t height = 0;      // longest root-leaf path (edges), an upper bound after updates
   int32_t n_trees = 1;     // trees held: their roots are nodes 0 .. n_trees-1
 };
@@ -225,6 +230,21 @@ int sieve_pass(hipStream_t st, int D, int lambda, int tile, const Task* tasks, i
 int build_tasks(pkd_tree* tree, hipStream_t st, const std::vector<Task>& roots,
                 const int64_t* in_coords, const int64_t* in_ids, int64_t input_cap);
 int ensure_nodes(pkd_tree* tree, hipStream_t st, int64_t need);
+
+// Tree storage (pkd_api.hip): both point buffers for at least `cap` points;
+// release every device array of a tree (the object itself stays); a new tree
+// built from caller input (headroom: room for a sixteenth more points);
+// exchange the storage of two trees.
+int alloc_points(pkd_tree* T, hipStream_t st, int64_t cap);
+void release(pkd_tree* T, hipStream_t st);
+int build_new(const Params& prm, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t n,
+              bool headroom, pkd_tree** out);
+void swap_storage(pkd_tree* a, pkd_tree* b);
+// Drop the records of dead nodes when they outnumber the rest (update.hip):
+// live records keep their order (the roots stay first), links are renumbered.
+// Returns PKD_OK also when it skips the compaction (nothing to gain, or no
+// memory for the new array); the tree is valid either way.
+int compact_nodes(pkd_tree* T, hipStream_t st);
 
 // Per-kernel timing (pkd_profile_*): Prof::begin/end bracket one launch with
 // events on its stream; the elapsed time is collected at the next flush.

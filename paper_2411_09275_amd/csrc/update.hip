@@ -348,9 +348,10 @@ __host__ __device__ inline size_t decide_lds_per_wave(int lambda) {
 __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int ns, int lambda, const int32_t* hn_all,
                                                         const int32_t* bsize, const int32_t* bstart,
                                                         const int32_t* child_idx, const int8_t* killed,
-                                                        int8_t* killed_next, const int32_t* M, Node* nodes, int64_t an,
-                                                        int64_t ad, int insert, Region* regions, int* n_regions,
-                                                        int apply, int32_t* rcount, const int32_t* roff) {
+                                                        int8_t* killed_next, const int32_t* M, const Node* nodes,
+                                                        int64_t an, int64_t ad, int insert, Region* regions,
+                                                        int* n_regions, int apply, int32_t* rcount, const int32_t* roff,
+                                                        int2* sizes, int* n_sizes) {
   const int NB = 1 << lambda, nheap = 2 << lambda;
   // per wave: cnt, s0, sz [nheap] int32, alive [nheap] bytes (dynamic LDS,
   // sized for this lambda)
@@ -397,6 +398,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
         const bool in = v < (2 << l);
         const int32_t u = in ? hn[v] : -1;
         bool add = false;   // node u becomes a region to rebuild
+        bool setsz = false; // node u keeps its place and takes size newsz
+        int32_t newsz = 0;
         Region reg{};
         if (in && alive[v] && u >= 0 && cnt[v] != 0) {
           const Node nd = nodes[u];
@@ -405,8 +408,9 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
             if (insert) {
               add = true;
               reg = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
-            } else if (apply) {
-              nodes[u].size = nd.size - cnt[v];
+            } else {
+              setsz = true;
+              newsz = nd.size - cnt[v];
             }
           } else if (l == lambda) {
             if (apply) killed_next[child_idx[static_cast<int64_t>(sig) * nheap + v]] = 0;
@@ -415,13 +419,24 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
             const int64_t l2 = static_cast<int64_t>(nodes[nd.left].size) + sign * cnt[2 * v];
             const bool bal = n2 > 0 && (ad - 2 * an) * n2 <= 2 * ad * l2 && 2 * ad * l2 <= (ad + 2 * an) * n2;
             if (bal) {
-              if (apply) nodes[u].size = static_cast<int32_t>(n2);
+              setsz = true;
+              newsz = static_cast<int32_t>(n2);
               alive[2 * v] = alive[2 * v + 1] = 1;
             } else {
               add = true;
               reg = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
             }
           }
+        }
+        // new sizes are recorded, not written: the tree changes only once the
+        // whole update has its memory (commit)
+        const unsigned long long sm = __ballot(setsz);
+        if (apply && sm) {
+          const int leader = __ffsll(static_cast<long long>(sm)) - 1;
+          int at = 0;
+          if (lane == leader) at = atomicAdd(n_sizes, __popcll(sm));
+          at = __shfl(at, leader);
+          if (setsz) sizes[at + __popcll(sm & ((1ULL << lane) - 1))] = make_int2(u, newsz);
         }
         const unsigned long long rm = __ballot(add);
         if (apply && rm) {
@@ -449,22 +464,26 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
 __global__ void k_add_regions(int* n_regions, const int32_t* roff, int ns) { *n_regions += roff[ns]; }
 
 // Region bookkeeping on the old positions: regid marks the points inside each
-// region; for inserts the size change of a region is noted at its end.
+// region; for inserts the size change of a region is noted at its end.  Grid
+// (regions, y): the y blocks of a region share its range.
 __global__ void k_region_mark(const Region* regions, int32_t* regid, int32_t* delta, int insert) {
   const Region r = regions[blockIdx.x];
-  for (int64_t o = r.a + threadIdx.x; o < r.b; o += blockDim.x) regid[o] = blockIdx.x;
-  if (insert && threadIdx.x == 0) atomicAdd(delta + r.b, r.e - r.s);
+  const int64_t stride = static_cast<int64_t>(gridDim.y) * blockDim.x;
+  for (int64_t o = r.a + static_cast<int64_t>(blockIdx.y) * blockDim.x + threadIdx.x; o < r.b; o += stride)
+    regid[o] = blockIdx.x;
+  if (insert && blockIdx.y == 0 && threadIdx.x == 0) atomicAdd(delta + r.b, r.e - r.s);
 }
 
-// New places of the old points: insert: o + S[o+1] (batch points noted at
-// region ends before o); delete: o - S[o] (removed points before o).
-// The tree's packed 32-bit coordinates are written at the new places too
-// (the points of rebuilt regions get theirs again from the rebuild).
+// New places of the old points outside every region: insert: o + S[o+1]
+// (batch points noted at region ends before o); delete: o - S[o] (removed
+// points before o).  The packed 32-bit coordinates go to the new layout's own
+// array.  Points of regions are left to the rebuild.
 template <int D>
 __global__ void k_relayout(const int64_t* X, int64_t xcap, int64_t n, const int32_t* S, const int32_t* delflag,
-                           int insert, int64_t* Y, int64_t ycap, int32_t* C32) {
+                           const int32_t* regid, int insert, int64_t* Y, int64_t ycap, int32_t* C32) {
   for (int64_t o = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; o < n;
        o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (regid[o] >= 0) continue;
     int64_t dst;
     if (insert) {
       dst = o + S[o + 1];
@@ -480,15 +499,6 @@ __global__ void k_relayout(const int64_t* X, int64_t xcap, int64_t n, const int3
     }
     Y[D * ycap + dst] = X[D * xcap + o];
   }
-}
-
-// Insert: batch points of each region go right after the region's old points.
-__global__ void k_place_batch(const Region* regions, int D, const int64_t* batch, int64_t m, const int32_t* S,
-                              int64_t* Y, int64_t ycap) {
-  const Region r = regions[blockIdx.x];
-  const int64_t base = static_cast<int64_t>(r.b) + (r.b > 0 ? S[r.b] : 0);
-  for (int64_t i = threadIdx.x; i < r.e - r.s; i += blockDim.x)
-    for (int d = 0; d <= D; ++d) Y[d * ycap + base + i] = batch[d * m + r.s + i];
 }
 
 // New offsets of the surviving nodes.  Live node ranges nest like the tree,
@@ -527,6 +537,98 @@ __global__ void k_region_final(Region* regions, const int32_t* S, int insert) {
     r.new_start = r.a - S[r.a];
     r.new_size = (r.b - r.a) - (S[r.b] - S[r.a]);
   }
+}
+
+// The points of every region after the update, packed region after region
+// (region r from comp[r]) as the input of the rebuild: the old points of the
+// region that survive, then (insert) its batch points.  Grid (regions, y).
+template <int D>
+__global__ void k_gather_regions(const Region* regions, const int64_t* comp, const int64_t* X, int64_t xcap,
+                                 const int32_t* S, const int32_t* delflag, const int64_t* batch, int64_t m,
+                                 int insert, int64_t* cin, int64_t ccap) {
+  const Region r = regions[blockIdx.x];
+  const int64_t c0 = comp[blockIdx.x];
+  const int64_t stride = static_cast<int64_t>(gridDim.y) * blockDim.x;
+  const int64_t first = static_cast<int64_t>(blockIdx.y) * blockDim.x + threadIdx.x;
+  for (int64_t o = r.a + first; o < r.b; o += stride) {
+    int64_t at;
+    if (insert) {
+      at = c0 + (o - r.a);
+    } else {
+      if (delflag[o]) continue;
+      at = c0 + (o - S[o]) - r.new_start;
+    }
+#pragma unroll
+    for (int d = 0; d <= D; ++d) cin[d * ccap + at] = X[d * xcap + o];
+  }
+  if (insert) {
+    const int64_t base = c0 + (r.b - r.a) - r.s;
+    for (int64_t i = r.s + first; i < r.e; i += stride)
+#pragma unroll
+      for (int d = 0; d <= D; ++d) cin[d * ccap + base + i] = batch[d * m + i];
+  }
+}
+
+// ---- commit: the kernels below run only after every allocation of the
+// update has succeeded, so a failed update never reaches them.
+__global__ void k_apply_sizes(Node* nodes, const int2* sizes, const int* n_sizes) {
+  const int n = *n_sizes;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    nodes[sizes[i].x].size = sizes[i].y;
+}
+
+__device__ inline int region_of(const int64_t* comp, int nreg, int64_t p) {
+  int lo = 0, hi = nreg;   // last region whose packed range starts at or before p
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (comp[mid] <= p) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Rebuilt points back from the packed rebuild to their regions' ranges.
+template <int D>
+__global__ void k_scatter_back(const Region* regions, const int64_t* comp, int nreg, const int64_t* Z, int64_t zcap,
+                               int64_t total, int64_t* Y, int64_t ycap, int32_t* C32) {
+  for (int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; p < total;
+       p += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int r = region_of(comp, nreg, p);
+    const int64_t dst = regions[r].new_start + (p - comp[r]);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int64_t v = Z[d * zcap + p];
+      Y[d * ycap + dst] = v;
+      C32[d * ycap + dst] = static_cast<int32_t>(v);
+    }
+    Y[D * ycap + dst] = Z[D * zcap + p];
+  }
+}
+
+// A node of the rebuild as a node of the tree: rebuild node j >= nreg goes to
+// base + j - nreg, rebuild root r to the region's node; offsets move from the
+// packed range to the region's range.
+__device__ inline Node translate(Node nd, const Region* regions, const int64_t* comp, int nreg, int region,
+                                 int32_t base) {
+  if (nd.pad != 0) return nd;
+  if (nd.left >= 0) {
+    nd.left = base + (nd.left - nreg);
+    nd.right = base + (nd.right - nreg);
+  }
+  const int r = region >= 0 ? region : region_of(comp, nreg, nd.off);
+  nd.off = static_cast<int32_t>(regions[r].new_start + (nd.off - comp[r]));
+  return nd;
+}
+
+__global__ void k_append_nodes(Node* nodes, int32_t base, const Node* tmp, int32_t tmp_count, const Region* regions,
+                               const int64_t* comp, int nreg) {
+  for (int32_t j = nreg + blockIdx.x * blockDim.x + threadIdx.x; j < tmp_count; j += gridDim.x * blockDim.x)
+    nodes[base + (j - nreg)] = translate(tmp[j], regions, comp, nreg, -1, base);
+}
+
+__global__ void k_copy_roots(Node* nodes, int32_t base, const Node* tmp, const Region* regions, const int64_t* comp,
+                             int nreg) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nreg; r += gridDim.x * blockDim.x)
+    nodes[regions[r].node] = translate(tmp[r], regions, comp, nreg, r, base);
 }
 
 int fill(hipStream_t st, int32_t* a, int64_t n, int32_t v) {
@@ -604,26 +706,13 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     if (h & kErrRange) return PKD_ERR_RANGE;
   }
   if (insert && n == 0) {
-    // inserting into the empty tree is Build(P) at the root
-    if (m > T->cap) {
-      dev_free(T->buf[0], st);
-      dev_free(T->buf[1], st);
-      T->buf[0] = T->buf[1] = nullptr;
-      const int64_t cap = std::max<int64_t>(m, T->cap + T->cap / 2);
-      const size_t bytes = sizeof(int64_t) * static_cast<size_t>(D + 1) * cap;
-      void* a = nullptr;
-      void* b = nullptr;
-      PKD_TRY(dev_alloc(&a, bytes, st));
-      PKD_TRY(dev_alloc(&b, bytes, st));
-      T->buf[0] = static_cast<int64_t*>(a);
-      T->buf[1] = static_cast<int64_t*>(b);
-      T->cap = cap;
-    }
-    T->node_count = 1;
-    T->height = 0;
-    Task root{0, static_cast<int32_t>(m), 0, 0, 2, 0};
-    PKD_TRY(build_tasks(T, st, std::vector<Task>{root}, coords, ids, m));
-    T->n = m;
+    // inserting into the empty tree is Build(P) at the root: built as a new
+    // tree whose storage replaces the tree's only once it is complete
+    pkd_tree* fresh = nullptr;
+    PKD_TRY(build_new(T->prm, st, coords, ids, m, 1, &fresh));
+    swap_storage(T, fresh);
+    release(fresh, st);
+    delete fresh;
     return PKD_OK;
   }
 
@@ -761,11 +850,19 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     if (tot == 0) return PKD_OK;   // nothing to do
   }
 
-  // ---- decide, round by round, top-down
+  // ---- decide, round by round, top-down.  Nothing is written to the tree
+  // until the commit below: new sizes and regions are recorded in scratch.
   DArr<Region> regions(st);
+  DArr<int2> sizes(st);
   DArr<int8_t> killed(st), killed_next(st);
   DArr<int32_t> rcount(st), roff(st);
   PKD_TRY(regions.need(static_cast<size_t>(m) + 1));
+  {
+    size_t most = 2;
+    for (auto* R : rounds) most += static_cast<size_t>(R->ns) * nheap;
+    PKD_TRY(sizes.need(most));
+  }
+  int* d_sizes = ctr.p + 3;
   if (rounds.empty()) {
     // the root is a leaf
     if (insert) {
@@ -774,9 +871,10 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
       int one = 1;
       PKD_HIP(hipMemcpyAsync(d_regions, &one, sizeof(int), hipMemcpyHostToDevice, st));
     } else {
-      int32_t sz = root.size - static_cast<int32_t>(n_removed);
-      PKD_HIP(hipMemcpyAsync(reinterpret_cast<char*>(T->nodes) + offsetof(Node, size), &sz, sizeof(int32_t),
-                             hipMemcpyHostToDevice, st));
+      const int2 sz = make_int2(0, root.size - static_cast<int32_t>(n_removed));
+      PKD_HIP(hipMemcpyAsync(sizes.p, &sz, sizeof(int2), hipMemcpyHostToDevice, st));
+      int one = 1;
+      PKD_HIP(hipMemcpyAsync(d_sizes, &one, sizeof(int), hipMemcpyHostToDevice, st));
     }
   } else {
     PKD_TRY(killed.need(1));
@@ -794,7 +892,8 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
         hipLaunchKernelGGL(k_decide, dim3((R->ns + kWaves - 1) / kWaves), dim3(64 * kWaves),
                            kWaves * decide_lds_per_wave(lambda), st, R->tasks.p, R->ns, lambda, R->hn.p, R->bsize.p,
                            R->bstart.p, R->child.p, killed.p, killed_next.p, M.p, T->nodes, P.alpha_num, P.alpha_den,
-                           insert ? 1 : 0, regions.p, d_regions, apply, rcount.p, insert ? roff.p : nullptr);
+                           insert ? 1 : 0, regions.p, d_regions, apply, rcount.p, insert ? roff.p : nullptr,
+                           sizes.p, d_sizes);
         PKD_TRY(kernel_status("k_decide"));
         if (apply == 0) PKD_TRY(exscan_i32(st, rcount.p, roff.p, R->ns, bsum));
       }
@@ -810,67 +909,127 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   PKD_HIP(hipMemcpyAsync(&n_regions, d_regions, sizeof(int), hipMemcpyDeviceToHost, st));
   PKD_HIP(hipStreamSynchronize(st));
 
-  // ---- new layout of the packed point array
+  // ---- new layout of the packed point array, written into the twin buffer
+  // (or fresh buffers when the capacity grows) and a second packed 32-bit
+  // copy: the tree's own arrays stay as they are until the commit
   const int64_t n_new = insert ? n + m : n - n_removed;
   int64_t* Xold = T->buf[T->cur];
   const int64_t old_cap = T->cap;
-  int64_t* Ynew = T->buf[1 - T->cur];
   int64_t new_cap = T->cap;
+  struct Owned {   // device blocks this update allocated; freed unless committed
+    hipStream_t st;
+    void* p[3] = {nullptr, nullptr, nullptr};
+    ~Owned() {
+      for (void* q : p) dev_free(q, st);
+    }
+  } own{st};
+  int64_t* Ynew = T->buf[1 - T->cur];
   int64_t* fresh_twin = nullptr;
   if (n_new > T->cap) {
     new_cap = std::max<int64_t>(n_new, T->cap + T->cap / 2);
     const size_t bytes = sizeof(int64_t) * static_cast<size_t>(D + 1) * new_cap;
-    void* a = nullptr;
-    void* b = nullptr;
-    PKD_TRY(dev_alloc(&a, bytes, st));
-    int rc = dev_alloc(&b, bytes, st);
-    if (rc != PKD_OK) {
-      dev_free(a, st);
-      return rc;
-    }
-    Ynew = static_cast<int64_t*>(a);
-    fresh_twin = static_cast<int64_t*>(b);
+    PKD_TRY(dev_alloc(&own.p[0], bytes, st));
+    PKD_TRY(dev_alloc(&own.p[1], bytes, st));
+    Ynew = static_cast<int64_t*>(own.p[0]);
+    fresh_twin = static_cast<int64_t*>(own.p[1]);
   }
-  // the packed coordinate copy at the new capacity (the relayout writes it)
-  int32_t* c32_new = T->c32;
-  if (new_cap > 0 && (!T->c32 || T->c32_cap != new_cap)) {
-    void* p = nullptr;
-    const int rc = dev_alloc(&p, sizeof(int32_t) * static_cast<size_t>(D) * static_cast<size_t>(new_cap), st);
-    if (rc != PKD_OK) {
-      if (fresh_twin) {
-        dev_free(Ynew, st);
-        dev_free(fresh_twin, st);
-      }
-      return rc;
-    }
-    c32_new = static_cast<int32_t*>(p);
+  int32_t* c32_new = T->c32_twin;
+  if (!c32_new || T->c32_twin_cap != new_cap) {
+    PKD_TRY(dev_alloc(&own.p[2], sizeof(int32_t) * static_cast<size_t>(D) * static_cast<size_t>(new_cap), st));
+    c32_new = static_cast<int32_t*>(own.p[2]);
   }
   PKD_TRY(S.need(n + 2));
   PKD_TRY(regid.need(n + 1));
   PKD_TRY(fill(st, regid.p, n + 1, -1));
+  // region ranges share out over y blocks in proportion to the points per region
+  const unsigned ry = static_cast<unsigned>(
+      std::min<int64_t>(1024, std::max<int64_t>(1, (n + m) / (std::max(n_regions, 1) * int64_t{8192}))));
   if (insert) {
     PKD_TRY(delflag.need(n + 2));
     PKD_TRY(fill(st, delflag.p, n + 2, 0));
     if (n_regions > 0)
-      hipLaunchKernelGGL(k_region_mark, dim3(n_regions), dim3(256), 0, st, regions.p, regid.p, delflag.p, 1);
+      hipLaunchKernelGGL(k_region_mark, dim3(n_regions, ry), dim3(256), 0, st, regions.p, regid.p, delflag.p, 1);
     PKD_TRY(kernel_status("k_region_mark"));
     PKD_TRY(exscan_i32(st, delflag.p, S.p, n + 1, bsum));   // S[o] = batch points noted at ends < o
   } else {
     if (n_regions > 0)
-      hipLaunchKernelGGL(k_region_mark, dim3(n_regions), dim3(256), 0, st, regions.p, regid.p, delflag.p, 0);
+      hipLaunchKernelGGL(k_region_mark, dim3(n_regions, ry), dim3(256), 0, st, regions.p, regid.p, delflag.p, 0);
     PKD_TRY(kernel_status("k_region_mark"));
     PKD_TRY(exscan_i32(st, delflag.p, S.p, n, bsum));       // S[o] = removed points before o
   }
   if (n > 0) {
     const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (n + 255) / 256));
-    hipLaunchKernelGGL(k_relayout<D>, dim3(g), dim3(256), 0, st, Xold, old_cap, n, S.p, delflag.p, insert ? 1 : 0,
-                       Ynew, new_cap, c32_new);
+    hipLaunchKernelGGL(k_relayout<D>, dim3(g), dim3(256), 0, st, Xold, old_cap, n, S.p, delflag.p, regid.p,
+                       insert ? 1 : 0, Ynew, new_cap, c32_new);
     PKD_TRY(kernel_status("k_relayout"));
   }
-  if (insert && n_regions > 0) {
-    hipLaunchKernelGGL(k_place_batch, dim3(n_regions), dim3(256), 0, st, regions.p, D, wf.p, m, S.p, Ynew, new_cap);
-    PKD_TRY(kernel_status("k_place_batch"));
+  std::vector<Region> hreg(n_regions);
+  if (n_regions > 0) {
+    hipLaunchKernelGGL(k_region_final, dim3(n_regions), dim3(64), 0, st, regions.p, S.p, insert ? 1 : 0);
+    PKD_TRY(kernel_status("k_region_final"));
+    PKD_HIP(hipMemcpyAsync(hreg.data(), regions.p, sizeof(Region) * n_regions, hipMemcpyDeviceToHost, st));
   }
+  int n_sizes = 0;
+  PKD_HIP(hipMemcpyAsync(&n_sizes, d_sizes, sizeof(int), hipMemcpyDeviceToHost, st));
+  PKD_HIP(hipStreamSynchronize(st));
+
+  // ---- rebuild every region (one segmented Build, Algorithm 1) into a
+  // temporary tree: roots 0 .. n_regions-1, each at its node's depth, over the
+  // regions' points packed back to back
+  struct TmpTree {
+    pkd_tree* t = nullptr;
+    hipStream_t st;
+    ~TmpTree() {
+      if (t) {
+        release(t, st);
+        delete t;
+      }
+    }
+  } tmp{nullptr, st};
+  std::vector<int64_t> comp(static_cast<size_t>(n_regions) + 1, 0);
+  for (int r = 0; r < n_regions; ++r) comp[r + 1] = comp[r] + hreg[r].new_size;
+  const int64_t R_pts = comp[n_regions];
+  DArr<int64_t> dcomp(st), cin(st);
+  int32_t appended = 0;
+  if (n_regions > 0) {
+    tmp.t = new pkd_tree;
+    tmp.t->prm = T->prm;
+    tmp.t->n_trees = n_regions;
+    PKD_TRY(alloc_points(tmp.t, st, R_pts));
+    PKD_TRY(ensure_nodes(tmp.t, st, std::max<int64_t>(1024, n_regions + R_pts / 8)));
+    PKD_TRY(dcomp.need(static_cast<size_t>(n_regions) + 1));
+    PKD_HIP(hipMemcpyAsync(dcomp.p, comp.data(), sizeof(int64_t) * (n_regions + 1), hipMemcpyHostToDevice, st));
+    PKD_TRY(cin.need(static_cast<size_t>(D + 1) * std::max<int64_t>(R_pts, 1)));
+    const int64_t ccap = std::max<int64_t>(R_pts, 1);
+    hipLaunchKernelGGL(k_gather_regions<D>, dim3(n_regions, ry), dim3(256), 0, st, regions.p, dcomp.p, Xold, old_cap,
+                       S.p, delflag.p, wf.p, m, insert ? 1 : 0, cin.p, ccap);
+    PKD_TRY(kernel_status("k_gather_regions"));
+    std::vector<Task> roots;
+    roots.reserve(n_regions);
+    for (int r = 0; r < n_regions; ++r) {
+      Task t;
+      t.start = static_cast<int32_t>(comp[r]);
+      t.m = hreg[r].new_size;
+      t.slot = r;
+      t.depth = static_cast<int16_t>(hreg[r].depth);
+      t.buf = 2;
+      t.mode = 0;
+      roots.push_back(t);
+    }
+    tmp.t->node_count = n_regions;
+    tmp.t->height = 0;
+    PKD_TRY(build_tasks(tmp.t, st, roots, cin.p, cin.p + static_cast<int64_t>(D) * ccap, ccap));
+    tmp.t->n = R_pts;
+    appended = tmp.t->node_count - n_regions;
+    if (static_cast<int64_t>(T->node_count) + appended >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
+    PKD_TRY(ensure_nodes(T, st, static_cast<int64_t>(T->node_count) + appended));
+  }
+
+  // ---- commit (kernels only; every allocation above has succeeded)
+  if (n_sizes > 0)
+    hipLaunchKernelGGL(k_apply_sizes, dim3(std::min(1024, (n_sizes + 255) / 256)), dim3(256), 0, st, T->nodes,
+                       sizes.p, d_sizes);
+  PKD_TRY(kernel_status("k_apply_sizes"));
   if (T->node_count > 0) {
     const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (T->node_count + 255) / 256));
     hipLaunchKernelGGL(k_node_update, dim3(g), dim3(256), 0, st, T->nodes, T->node_count, regid.p, regions.p, S.p,
@@ -878,54 +1037,103 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     PKD_TRY(kernel_status("k_node_update"));
   }
   if (n_regions > 0) {
-    hipLaunchKernelGGL(k_region_final, dim3(n_regions), dim3(64), 0, st, regions.p, S.p, insert ? 1 : 0);
-    PKD_TRY(kernel_status("k_region_final"));
+    pkd_tree* Z = tmp.t;
+    if (R_pts > 0) {
+      const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (R_pts + 255) / 256));
+      hipLaunchKernelGGL(k_scatter_back<D>, dim3(g), dim3(256), 0, st, regions.p, dcomp.p, n_regions,
+                         Z->buf[Z->cur], Z->cap, R_pts, Ynew, new_cap, c32_new);
+      PKD_TRY(kernel_status("k_scatter_back"));
+    }
+    const int32_t base = T->node_count;
+    if (appended > 0) {
+      const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (appended + 255) / 256));
+      hipLaunchKernelGGL(k_append_nodes, dim3(g), dim3(256), 0, st, T->nodes, base, Z->nodes, Z->node_count,
+                         regions.p, dcomp.p, n_regions);
+      PKD_TRY(kernel_status("k_append_nodes"));
+    }
+    hipLaunchKernelGGL(k_copy_roots, dim3((n_regions + 255) / 256), dim3(256), 0, st, T->nodes, base, Z->nodes,
+                       regions.p, dcomp.p, n_regions);
+    PKD_TRY(kernel_status("k_copy_roots"));
+    T->node_count = base + appended;
+    T->height = std::max(T->height, Z->height);
   }
-  std::vector<Region> hreg(n_regions);
-  if (n_regions > 0)
-    PKD_HIP(hipMemcpyAsync(hreg.data(), regions.p, sizeof(Region) * n_regions, hipMemcpyDeviceToHost, st));
   PKD_HIP(hipStreamSynchronize(st));
-
-  // the new array becomes the tree's; the old one its twin
+  // the new arrays become the tree's; the old ones its twins
   if (fresh_twin) {
     dev_free(T->buf[0], st);
     dev_free(T->buf[1], st);
     T->buf[0] = Ynew;
     T->buf[1] = fresh_twin;
+    own.p[0] = own.p[1] = nullptr;
     T->cur = 0;
     T->cap = new_cap;
   } else {
     T->cur = 1 - T->cur;
   }
-  if (c32_new != T->c32) {
-    dev_free(T->c32, st);
-    T->c32 = c32_new;
-    T->c32_cap = new_cap;
+  if (own.p[2]) {
+    dev_free(T->c32_twin, st);
+    own.p[2] = nullptr;
   }
+  std::swap(T->c32, c32_new);
+  T->c32_twin = c32_new;
+  T->c32_twin_cap = T->c32_cap;
+  T->c32_cap = new_cap;
   T->n = n_new;
-
-  // ---- rebuild every region (one segmented Build)
-  if (n_regions > 0) {
-    std::vector<Task> roots;
-    roots.reserve(n_regions);
-    for (const Region& r : hreg) {
-      Task t;
-      t.start = r.new_start;
-      t.m = r.new_size;
-      t.slot = r.node;
-      t.depth = static_cast<int16_t>(r.depth);
-      t.buf = static_cast<int8_t>(T->cur);
-      t.mode = 0;
-      roots.push_back(t);
-    }
-    PKD_TRY(build_tasks(T, st, roots, nullptr, nullptr, 0));
-  }
-  // the packed copy for the queries: the relayout wrote the moved points,
-  // the rebuild the points of every region
+  // reclaim the records of replaced nodes once they outnumber the rest
+  // (optional: a tree that cannot get the memory keeps them)
+  (void)compact_nodes(T, st);
   return PKD_OK;
 }
 
+// ---- node compaction: live records move down in order, links renumbered
+__global__ void k_live_flags(const Node* nodes, int32_t n, int32_t* live) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    live[i] = nodes[i].pad == 0 ? 1 : 0;
+}
+
+__global__ void k_compact(const Node* src, int32_t n, const int32_t* newid, Node* dst) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    Node nd = src[i];
+    if (nd.pad != 0) continue;
+    if (nd.left >= 0 && nd.left < n && nd.right >= 0 && nd.right < n) {
+      nd.left = newid[nd.left];
+      nd.right = newid[nd.right];
+    }
+    dst[newid[i]] = nd;
+  }
+}
+
 }  // namespace
+
+int compact_nodes(pkd_tree* T, hipStream_t st) {
+  const int32_t n = T->node_count;
+  if (n < 2 * std::max<int32_t>(T->compact_mark, 1024)) return PKD_OK;
+  DArr<int32_t> live(st), newid(st), bsum(st);
+  if (live.need(n) != PKD_OK || newid.need(static_cast<size_t>(n) + 1) != PKD_OK) return PKD_OK;
+  const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (n + 255) / 256));
+  hipLaunchKernelGGL(k_live_flags, dim3(g), dim3(256), 0, st, T->nodes, n, live.p);
+  PKD_TRY(kernel_status("k_live_flags"));
+  if (exscan_i32(st, live.p, newid.p, n, bsum) != PKD_OK) return PKD_OK;
+  int32_t total = 0;
+  PKD_HIP(hipMemcpyAsync(&total, newid.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  PKD_HIP(hipStreamSynchronize(st));
+  if (total < T->n_trees || total > n) return PKD_ERR_INTERNAL;
+  const int64_t cap = std::max<int64_t>(1024, static_cast<int64_t>(total) + total / 4);
+  void* q = nullptr;
+  if (dev_alloc(&q, sizeof(Node) * cap, st) != PKD_OK) return PKD_OK;
+  hipLaunchKernelGGL(k_compact, dim3(g), dim3(256), 0, st, T->nodes, n, newid.p, static_cast<Node*>(q));
+  const int rc = kernel_status("k_compact");
+  if (rc != PKD_OK) {
+    dev_free(q, st);
+    return rc;
+  }
+  dev_free(T->nodes, st);
+  T->nodes = static_cast<Node*>(q);
+  T->node_cap = cap;
+  T->node_count = total;
+  T->compact_mark = total;
+  return PKD_OK;
+}
 
 int run_insert(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m) {
   int64_t dummy = 0;
