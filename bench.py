@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=2048)
     ap.add_argument("--cpu-sample", type=int, default=4_000_000, help="points of the oracle's build sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="build", choices=["build", "batching", "serving", "updates", "large_updates"],
+    ap.add_argument("--workload", default="build",
+                    choices=["build", "batching", "serving", "updates", "large_updates", "range_report"],
                     help="build: the headline (1e8 3-D build + queries); batching: 4096 trees in one pass")
     ap.add_argument("--serve-n", type=int, default=1_000_000_000, help="points of the resident serving tree")
     ap.add_argument("--requests", type=int, default=100, help="requests in the serving stream")
@@ -476,6 +477,75 @@ def bench_large_updates(a):
     print(json.dumps(out))
 
 
+def bench_range_report(a):
+    """Range report on the 1e8 uniform 3-D tree (seed 3): 1e4 cubes whose
+    outputs are log-uniform in [1e4, 1e6] points (seed 6), all in one call,
+    into a preallocated id buffer.  The tree is built once; a step is one
+    report call.  The roofline is that of the report phase (walk + copy):
+    16 bytes per reported id (read from the tree's point array, written to
+    the output) over its duration, from HIP events on the launch stream."""
+    import torch
+
+    import paper_2411_09275_amd as pk
+    import synth
+
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    nb = 10_000
+    coords, ids = synth.uniform_points(a.n, a.dim, seed=3)
+    lo, hi = synth.report_boxes(nb, a.dim, a.n, seed=6)
+    t = pk.Tree(pk.Params(a.dim), torch.from_numpy(coords).to(dev), torch.from_numpy(ids).to(dev), tile=a.tile)
+    glo, ghi = torch.from_numpy(lo).to(dev), torch.from_numpy(hi).to(dev)
+    _, total = t.range_report_size(glo, ghi)
+    buf = torch.empty(total, dtype=torch.int64, device=dev)
+    log("range report workload: %d boxes, %d ids (%.1f GB of ids)" % (nb, total, total * 8 / 1e9))
+    for _ in range(a.warmup):
+        t.range_report(glo, ghi, out=buf)
+    torch.cuda.synchronize()
+    pk.profile_enable(True)
+    times, sums = [], set()
+    for k in range(a.steps):
+        s0 = time.perf_counter()
+        o, r = t.range_report(glo, ghi, out=buf)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - s0)
+        sums.add(int(r.sum()))
+        log("step %d: %.2f ms" % (k, times[-1] * 1e3))
+    rn, rms, rbytes = pk.profile_get("range_report")
+    pk.profile_enable(False)
+    ms = float(np.mean(times) * 1e3)
+    gbs = rbytes / (rms * 1e-3) / 1e9 if rms > 0 else 0.0
+    out = {
+        "metric": "range report: reported ids/s (1e4 boxes, outputs log-uniform [1e4,1e6], 1e8 pts 3D)",
+        "value": round(total / (ms * 1e-3) / 1e6, 2),
+        "unit": "M ids/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "tree of %.0e uniform %d-D int64 points in [0,1e9); %d cubes with outputs log-uniform "
+                               "in [1e4,1e6] points, one call" % (a.n, a.dim, nb), "ids": total},
+        "identical_results": len(sums) == 1,
+        "roofline": {"kernel": "k_report_walk + k_report_copy", "bound": "hbm", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launches": rn, "alg_bytes_per_launch": round(rbytes / max(rn, 1))},
+    }
+    t.free()
+    if not a.no_cpu_baseline:
+        import oracle
+        n2 = 10_000_000
+        c2, i2 = np.ascontiguousarray(coords[:, :n2]), ids[:n2]
+        T2 = oracle.Tree(oracle.Params(a.dim), c2, i2)
+        l2, h2 = synth.report_boxes(100, a.dim, n2, seed=7)
+        s0 = time.perf_counter()
+        o2, r2 = T2.range_report(l2, h2)
+        sec = time.perf_counter() - s0
+        out["cpu_baseline"] = {"value": round(r2.shape[0] / sec / 1e6, 3), "unit": "M ids/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "sequential oracle report of 100 boxes (same output law) on a tree of the "
+                                         "first 1e7 points: %d ids in %.2f s" % (r2.shape[0], sec)}
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -487,6 +557,9 @@ def main():
         return
     if a.workload == "large_updates":
         bench_large_updates(a)
+        return
+    if a.workload == "range_report":
+        bench_range_report(a)
         return
     if a.workload == "serving":
         bench_serving(a)

@@ -7,7 +7,8 @@
  *   Build        -- Algorithm 1, Section 3.1
  *   BatchInsert  -- Algorithm 2, Section 4.1
  *   BatchDelete  -- Section 4.2
- *   k-NN, range count -- Section 2 (definitions), Section 5 (traversals)
+ *   k-NN, range count, range report -- Section 2 (definitions), Section 5
+ *                (traversals)
  * Every step runs in HIP kernels on the GPU; this header holds only plain C
  * types.
  *
@@ -182,6 +183,21 @@ int pkd_range_count(const pkd_tree* tree, void* stream, const int64_t* lo,
                     const int64_t* hi, int64_t nb, int64_t* out);
 
 /*
+ * Range report (Section 2; Section 5: a subtree whose cell lies inside the box
+ * is reported whole, a straddling leaf is filtered).  For each closed box j
+ * (lo, hi: device int64 [dim][nb]; lo_d > hi_d in some dimension reports
+ * nothing) the ids of the stored points in it go to out_ids[offsets[j] ..
+ * offsets[j+1]) (device), in no particular order.  offsets (device int64
+ * [nb+1]) receives the
+ * exclusive prefix sum of the box counts and *total (host) their sum.  With
+ * out_ids NULL only offsets and *total are computed (to size the output);
+ * if *total > cap nothing is written to out_ids and PKD_ERR_CAPACITY is
+ * returned.  Synchronizes `stream`.
+ */
+int pkd_range_report(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi,
+                     int64_t nb, int64_t* offsets, int64_t* out_ids, int64_t cap, int64_t* total);
+
+/*
  * Batched build of many independent trees in one pass of the segmented
  * pipeline: every sieve round and the finisher run over the subproblems of all
  * trees at once, so the number of launches does not grow with the number of
@@ -210,6 +226,9 @@ int pkd_knn_batch(const pkd_tree* tree, void* stream, const int64_t* queries,
 int pkd_range_count_batch(const pkd_tree* tree, void* stream, const int64_t* lo,
                           const int64_t* hi, const int32_t* tree_of, int64_t nb,
                           int64_t* out);
+int pkd_range_report_batch(const pkd_tree* tree, void* stream, const int64_t* lo,
+                           const int64_t* hi, const int32_t* tree_of, int64_t nb,
+                           int64_t* offsets, int64_t* out_ids, int64_t cap, int64_t* total);
 
 /*
  * Asynchronous forms of pkd_knn_batch / pkd_range_count_batch for callers that
@@ -262,7 +281,8 @@ int pkd_height(const pkd_tree* tree, int32_t* height);
  * algorithmic bytes (what the method must move: for the sieve count pass 8*D
  * bytes per point, for the scatter pass 2*(8*D+8) bytes per point).
  * kernel: 0 sieve count, 1 sieve scatter, 2 sample select + skeleton,
- * 3 finisher, 4 k-NN, 5 range count.  Host outs; any may be NULL.
+ * 3 finisher, 4 k-NN, 5 range count, 6 range report (walk and copy; 16 bytes
+ * per reported id).  Host outs; any may be NULL.
  */
 int pkd_profile_enable(int32_t on);
 int pkd_profile_get(int32_t kernel, int64_t* launches, double* total_ms, double* alg_bytes);

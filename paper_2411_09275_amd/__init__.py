@@ -28,7 +28,7 @@ EXPORTS = ["pkd_default_params", "pkd_default_tuning", "pkd_build", "pkd_batch_i
            "pkd_free", "pkd_strerror", "pkd_profile_enable", "pkd_profile_get", "pkd_build_batch",
            "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch", "pkd_export_tree_sizes", "pkd_export_tree",
            "pkd_knn_async", "pkd_range_count_async", "pkd_knn_noalloc", "pkd_set_allocator", "pkd_free_async",
-           "pkd_node_slots"]
+           "pkd_node_slots", "pkd_range_report", "pkd_range_report_batch"]
 
 
 class PkdError(RuntimeError):
@@ -91,10 +91,12 @@ def lib():
         L.pkd_set_allocator.argtypes = [C.POINTER(_Allocator)]
         L.pkd_free_async.argtypes = [vp, vp]
         L.pkd_node_slots.argtypes = [vp, C.POINTER(i64)]
+        L.pkd_range_report.argtypes = [vp, vp, vp, vp, i64, vp, vp, i64, C.POINTER(i64)]
+        L.pkd_range_report_batch.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, i64, C.POINTER(i64)]
         L.pkd_range_count_async.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.pkd_strerror.argtypes = [C.c_int]
         L.pkd_strerror.restype = C.c_char_p
-        for f in ("pkd_set_allocator", "pkd_free_async", "pkd_node_slots", "pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
+        for f in ("pkd_range_report", "pkd_range_report_batch", "pkd_set_allocator", "pkd_free_async", "pkd_node_slots", "pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
                   "pkd_export_tree_sizes", "pkd_export_tree", "pkd_profile_enable", "pkd_profile_get", "pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
                   "pkd_height", "pkd_export_sizes", "pkd_export"):
             getattr(L, f).restype = C.c_int
@@ -141,7 +143,7 @@ def _to_i32(t):
 
 
 PROFILE_KERNELS = {"sieve_count": 0, "sieve_scatter": 1, "select_skeleton": 2, "finisher": 3, "knn": 4,
-                   "range_count": 5}
+                   "range_count": 5, "range_report": 6}
 
 
 def profile_enable(on: bool = True):
@@ -329,6 +331,48 @@ class Tree:
         _check(lib().pkd_range_count_batch(self.h, _stream(stream), _ptr(lo), _ptr(hi),
                                            None if to is None else _ptr(to), nb, _ptr(out)), "pkd_range_count")
         return out
+
+    def range_report(self, lo, hi, tree_of=None, stream=None, out=None):
+        """(offsets [nb+1], ids [total]) as int64 CUDA tensors: box j's point
+        ids are ids[offsets[j]:offsets[j+1]] (in no particular order).  `out`
+        may supply an id buffer; it is used when large enough."""
+        torch = _torch()
+        lo, hi = _dev(lo), _dev(hi)
+        nb = lo.shape[1]
+        off = torch.empty(nb + 1, dtype=torch.int64, device="cuda")
+        to = None if tree_of is None else _to_i32(tree_of)
+        total = C.c_int64()
+        L = lib()
+
+        def call(buf, cap):
+            return L.pkd_range_report_batch(self.h, _stream(stream), _ptr(lo), _ptr(hi),
+                                            None if to is None else _ptr(to), nb, _ptr(off),
+                                            None if buf is None else _ptr(buf), cap, C.byref(total))
+
+        if out is not None:
+            rc = call(out, out.numel())
+            if rc == PKD_OK:
+                return off, out[: total.value]
+            if rc != -6:
+                _check(rc, "pkd_range_report")
+        else:
+            _check(call(None, 0), "pkd_range_report")
+        ids = torch.empty(max(total.value, 1), dtype=torch.int64, device="cuda")
+        _check(call(ids, ids.numel()), "pkd_range_report")
+        return off, ids[: total.value]
+
+    def range_report_size(self, lo, hi, tree_of=None, stream=None):
+        """(offsets [nb+1] CUDA tensor, total ids) without reporting."""
+        torch = _torch()
+        lo, hi = _dev(lo), _dev(hi)
+        nb = lo.shape[1]
+        off = torch.empty(nb + 1, dtype=torch.int64, device="cuda")
+        to = None if tree_of is None else _to_i32(tree_of)
+        total = C.c_int64()
+        _check(lib().pkd_range_report_batch(self.h, _stream(stream), _ptr(lo), _ptr(hi),
+                                            None if to is None else _ptr(to), nb, _ptr(off), None, 0,
+                                            C.byref(total)), "pkd_range_report")
+        return off, total.value
 
     def insert(self, coords, ids, stream=None):
         c, i = _dev(coords), _dev(ids)

@@ -12,10 +12,6 @@
 
 namespace pkd {
 
-int run_knn(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tree_of, int64_t nq, int k,
-            int64_t* oi, int64_t* od, int* flags);
-int run_range(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, const int32_t* tree_of,
-              int64_t nb, int64_t* out, int* flags);
 int run_knn_static(const pkd_tree* T, hipStream_t st, const int64_t* q, int64_t nq, int k, int64_t* oi,
                    int64_t* od);
 int run_insert(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m);
@@ -500,6 +496,28 @@ int pkd_range_count_batch(const pkd_tree* tree, void* stream, const int64_t* lo,
 int pkd_range_count(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi, int64_t nb,
                     int64_t* out) {
   return pkd_range_count_batch(tree, stream, lo, hi, nullptr, nb, out);
+}
+
+int pkd_range_report_batch(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi,
+                           const int32_t* tree_of, int64_t nb, int64_t* offsets, int64_t* out_ids, int64_t cap,
+                           int64_t* total) {
+  if (total) *total = 0;
+  if (!tree || nb < 0 || cap < 0 || !total) return PKD_ERR_INVALID_ARG;
+  if (nb > 0 && (!lo || !hi)) return PKD_ERR_INVALID_ARG;
+  if (!offsets) return PKD_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (nb == 0) {
+    const int64_t zero = 0;
+    PKD_HIP(hipMemcpyAsync(offsets, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+    PKD_HIP(hipStreamSynchronize(st));
+    return PKD_OK;
+  }
+  return run_range_report(tree, st, lo, hi, tree_of, nb, offsets, out_ids, cap, total);
+}
+
+int pkd_range_report(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi, int64_t nb,
+                     int64_t* offsets, int64_t* out_ids, int64_t cap, int64_t* total) {
+  return pkd_range_report_batch(tree, stream, lo, hi, nullptr, nb, offsets, out_ids, cap, total);
 }
 
 int pkd_build_batch(const pkd_params* params, const pkd_tuning* tuning, void* stream, int32_t n_trees,

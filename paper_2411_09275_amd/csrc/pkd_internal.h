@@ -107,6 +107,8 @@ struct pkd_tree {
   int32_t compact_mark = 0;  // node_count after the last build or compaction
   int32_t height = 0;      // longest root-leaf path (edges), an upper bound after updates
   int32_t n_trees = 1;     // trees held: their roots are nodes 0 .. n_trees-1
+  // copy items the last range report needed (sizes the next one's list)
+  mutable int64_t report_items_hint = 0;
 };
 
 // ---- host helpers shared by the sources (defined in pkd_api.hip) -----------
@@ -246,9 +248,20 @@ void swap_storage(pkd_tree* a, pkd_tree* b);
 // memory for the new array); the tree is valid either way.
 int compact_nodes(pkd_tree* T, hipStream_t st);
 
+// Query launches (query.hip): k-NN and range counts over the trees of a
+// handle (tree_of: per query, or null for tree 0); device errors are ORed
+// into *flags.
+int run_knn(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* tree_of, int64_t nq, int k,
+            int64_t* oi, int64_t* od, int* flags);
+int run_range(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, const int32_t* tree_of,
+              int64_t nb, int64_t* out, int* flags);
+// Range report (report.hip): counts, offsets and (with out_ids) the ids.
+int run_range_report(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, const int32_t* tree_of,
+                     int64_t nb, int64_t* offsets, int64_t* out_ids, int64_t cap, int64_t* total);
+
 // Per-kernel timing (pkd_profile_*): Prof::begin/end bracket one launch with
 // events on its stream; the elapsed time is collected at the next flush.
-enum ProfKernel { kProfCount = 0, kProfScatter, kProfSelect, kProfFinish, kProfKnn, kProfRange, kProfN };
+enum ProfKernel { kProfCount = 0, kProfScatter, kProfSelect, kProfFinish, kProfKnn, kProfRange, kProfReport, kProfN };
 struct Prof {
   static bool on();
   static void begin(int kernel, hipStream_t st);

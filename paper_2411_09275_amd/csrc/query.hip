@@ -10,8 +10,6 @@
 
 namespace pkd {
 
-int dev_alloc(void** p, size_t bytes, hipStream_t s);
-
 namespace {
 
 constexpr int kQBlock = 256;

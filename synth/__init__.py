@@ -150,6 +150,24 @@ def log_uniform_boxes(nb: int, dim: int, seed: int, side_lo: float = 1e5,
     return lo, up
 
 
+def report_boxes(nb: int, dim: int, n: int, seed: int, out_lo: float = 1e4, out_hi: float = 1e6,
+                 hi: int = DEFAULT_RANGE):
+    """Cubes whose expected number of points of n uniform points in [0, hi)^dim
+    is log-uniform in [out_lo, out_hi] (the range-report workload: outputs of
+    1e4..1e6 points).  Per box: target t = exp(U * ln(out_hi/out_lo)) * out_lo,
+    side L = floor(hi * (t/n)^(1/dim)) clipped to [1, hi], then per dimension
+    lo uniform in [0, hi - L], hi = lo + L - 1."""
+    rng = _rng(seed)
+    t = np.exp(rng.random(nb) * np.log(out_hi / out_lo)) * out_lo
+    side = np.clip(np.floor(hi * (t / float(n)) ** (1.0 / dim)).astype(np.int64), 1, hi)
+    lo = np.empty((dim, nb), dtype=np.int64)
+    up = np.empty((dim, nb), dtype=np.int64)
+    for d in range(dim):
+        lo[d] = rng.integers(0, hi - side + 1, dtype=np.int64)
+        up[d] = lo[d] + side - 1
+    return lo, up
+
+
 def sample_existing(ids: np.ndarray, m: int, seed: int) -> np.ndarray:
     """m distinct positions chosen uniformly without replacement from ids."""
     rng = _rng(seed)

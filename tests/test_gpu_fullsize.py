@@ -87,3 +87,28 @@ def test_full_size_queries_sampled(full, orc):
     assert np.array_equal(gd[torch.from_numpy(few).cuda()].cpu().numpy(), bd)
     _log("queries compared", t0)
 
+
+
+@pytest.mark.timeout(900)
+def test_full_size_range_report_sampled(full, orc):
+    # the range-report workload on the full tree: 1e4 cubes whose outputs are
+    # log-uniform in [1e4, 1e6] points (about 2e9 ids in one call)
+    import torch
+    pk, gt, ot, coords, ids, t0 = full
+    lo, hi = synth.report_boxes(10_000, DIM, N, seed=6)
+    glo, ghi = torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda()
+    off, rid = gt.range_report(glo, ghi)
+    torch.cuda.synchronize()
+    _log("GPU range report done: %d ids" % rid.numel(), t0)
+    cnt = gt.range_count(glo, ghi)
+    assert torch.equal(off[1:] - off[:-1], cnt) and int(off[0]) == 0
+    rng = np.random.default_rng(8)
+    boxes = np.concatenate([rng.choice(10_000, size=24, replace=False), [0, 9_999]])
+    o_off, o_ids = ot.range_report(np.ascontiguousarray(lo[:, boxes]), np.ascontiguousarray(hi[:, boxes]))
+    offh = off.cpu().numpy()
+    for k, j in enumerate(boxes):
+        g = np.sort(rid[int(offh[j]):int(offh[j + 1])].cpu().numpy())
+        assert np.array_equal(g, np.sort(o_ids[o_off[k]:o_off[k + 1]])), j
+    del rid
+    torch.cuda.empty_cache()
+    _log("range report compared", t0)

@@ -52,3 +52,16 @@ def test_request_stream_contract():
             assert len(set(s)) == m and all(x in alive for x in s)
             alive.difference_update(s)
     assert abs(last / 400 - 1 / 50.0) < 0.3 / 50.0   # mean inter-arrival 1/rate
+
+
+def test_report_boxes_hit_their_output_sizes():
+    # cubes sized for log-uniform expected counts in [1e4, 1e6] of n uniform points
+    n, D = 2_000_000, 3
+    c, _ = synth.uniform_points(n, D, seed=1)
+    lo, hi = synth.report_boxes(200, D, n, seed=2, out_lo=1e3, out_hi=1e5)
+    inside = np.array([np.all((c >= lo[:, j:j + 1]) & (c <= hi[:, j:j + 1]), axis=0).sum() for j in range(200)])
+    side = hi[0] - lo[0] + 1
+    expect = n * (side / 1e9) ** D
+    assert np.all(np.abs(inside - expect) <= 6 * np.sqrt(expect) + 2)
+    assert inside.min() >= 500 and inside.max() <= 2e5
+    assert np.all(hi - lo + 1 == side)      # cubes
