@@ -40,10 +40,12 @@ def parse():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--boxes", type=int, default=100_000)
     ap.add_argument("--tile", type=int, default=2048)
-    ap.add_argument("--cpu-sample", type=int, default=4_000_000, help="points of the oracle's build sample")
+    ap.add_argument("--cpu-sample", type=int, default=100_000_000,
+                    help="points of the oracle's Build (default: the whole benchmark point set)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="build",
-                    choices=["build", "batching", "serving", "updates", "large_updates", "range_report"],
+                    choices=["build", "batching", "serving", "updates", "large_updates", "range_report",
+                             "alpha_sweep", "sliding_window"],
                     help="build: the headline (1e8 3-D build + queries); batching: 4096 trees in one pass")
     ap.add_argument("--serve-n", type=int, default=1_000_000_000, help="points of the resident serving tree")
     ap.add_argument("--requests", type=int, default=100, help="requests in the serving stream")
@@ -51,6 +53,11 @@ def parse():
                     help="offered Poisson rate as a fraction of the serial handler's capacity")
     ap.add_argument("--batch", type=int, default=1_000_000, help="points per BatchInsert / BatchDelete (updates)")
     ap.add_argument("--trees", type=int, default=4096)
+    ap.add_argument("--batches", type=int, default=1000, help="alpha_sweep: batches the stream is cut into")
+    ap.add_argument("--alphas", default="1/100,5/100,1/10,2/10,3/10,4/10,1/2",
+                    help="alpha_sweep: balance parameters num/den")
+    ap.add_argument("--years", type=int, default=20, help="sliding_window: batches (years) in the stream")
+    ap.add_argument("--window", type=int, default=5, help="sliding_window: years the tree holds")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="batching: skip the one-call-per-tree comparison")
     ap.add_argument("--params", default=None, help="batching: fixed lambda,sigma,phi,tile instead of autotuning")
@@ -59,9 +66,14 @@ def parse():
     return ap.parse_args()
 
 
-def source_hash():
+# the sources a kernel's counter figures depend on
+TRAFFIC_SOURCES = {"sieve_scatter": ("build.hip", "pkd_internal.h"), "knn": ("query.hip", "pkd_internal.h"),
+                   "finisher": ("build.hip", "pkd_internal.h")}
+
+
+def source_hash(kernel="sieve_scatter"):
     h = hashlib.sha256()
-    for f in ("build.hip", "pkd_internal.h"):
+    for f in TRAFFIC_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2411_09275_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -75,32 +87,89 @@ def load_traffic(kernel: str):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_hash") != source_hash():
+    if t.get("source_hash") != source_hash(kernel):
         return None
     return t.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(coords, ids, q, lo, hi, sample_n, dim):
+def host_info():
+    """Threads this process may use and the host CPU model."""
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return threads, model
+
+
+def knn_bytes_per_query(work, dim, k):
+    """Algorithmic bytes of one k-NN query from its search work: every node
+    record read (32 B), the packed 32-bit coordinates of every point scanned
+    (4 B per dimension), the query (8 B per dimension) and its k (id, d2)
+    results (16 B each)."""
+    return 32.0 * work["nodes"] + 4.0 * dim * work["points"] + 8.0 * dim + 16.0 * k
+
+
+def stored_knn_work(n, dim, k):
+    """Per-query k-NN work of the benchmark's tree from the committed oracle
+    count (oracle/knn_work.py), when it covers this workload."""
+    path = os.path.join(ROOT, "profiles", "knn_work_1e8_3d.json")
+    if n != 100_000_000 or dim != 3 or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        w = json.load(f)
+    return w["per_query"].get(str(k))
+
+
+def cpu_baseline(coords, ids, q, dim, k, build_sample):
+    """The sequential oracle on the host cores: Build of the benchmark's own
+    point set (or its first build_sample points) on one thread, then its
+    k-NN on that tree with one thread and with every thread this process may
+    use (queries split over threads, the per-query search unchanged); also the
+    search work of a query sample (nodes read, points scanned)."""
     import oracle
-    n = min(sample_n, ids.shape[0])
-    c = np.ascontiguousarray(coords[:, :n])
-    i = ids[:n]
+    threads, model = host_info()
+    n = min(build_sample, ids.shape[0])
+    c = np.ascontiguousarray(coords[:, :n]) if n < ids.shape[0] else coords
     t0 = time.perf_counter()
-    T = oracle.Tree(oracle.Params(dim), c, i)
+    T = oracle.Tree(oracle.Params(dim), c, ids[:n])
     t_build = time.perf_counter() - t0
-    nq = min(100_000, q.shape[1])
+    nq1 = min(100_000, q.shape[1])
     t0 = time.perf_counter()
-    T.knn(np.ascontiguousarray(q[:, :nq]), 10)
-    t_knn = time.perf_counter() - t0
+    T.knn(np.ascontiguousarray(q[:, :nq1]), k)
+    t1 = time.perf_counter() - t0
+    nqt = min(1_000_000, q.shape[1])
+    qt = np.ascontiguousarray(q[:, :nqt])
+    t0 = time.perf_counter()
+    T.knn_threads(qt, k, threads)
+    tt = time.perf_counter() - t0
+    rows = np.sort(np.random.default_rng(77).choice(q.shape[1], size=min(20000, q.shape[1]), replace=False))
+    nodes, leaves, points = T.knn_visits(np.ascontiguousarray(q[:, rows]), k)
+    work = {"nodes": float(nodes.mean()), "leaves": float(leaves.mean()), "points": float(points.mean())}
+    del T
     return {
         "value": round(n / t_build / 1e6, 3),
         "unit": "Mpts/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": "sequential oracle build of the first %d of the %d points (%.1f s); "
-                  "oracle tree 10-NN of %d of the queries: %.0f q/s" % (n, ids.shape[0], t_build, nq, nq / t_knn),
-        "knn_qps": round(nq / t_knn, 1),
-    }
+        "sample": "sequential oracle Build of %s (%d points, %.1f s, one thread); %d-NN of %d queries on one "
+                  "thread and of %d queries on %d threads on that tree" % (
+                      "the whole benchmark point set" if n == ids.shape[0] else "the first %d points" % n, n,
+                      t_build, k, nq1, nqt, threads),
+        "knn_qps_1_thread": round(nq1 / t1, 1),
+        "knn_qps_all_threads": round(nqt / tt, 1),
+        "knn_threads": threads,
+        "host_threads": threads,
+        "cpu_model": model,
+    }, work
 
 
 def bench_batching(a):
@@ -546,6 +615,163 @@ def bench_range_report(a):
     print(json.dumps(out))
 
 
+def _stream_type(kind, n, dim):
+    """TYPE I: clustered points in cluster order (1000 random-walk clusters,
+    dense regions arrive one after another); TYPE II: a tenth uniform, then
+    clustered points."""
+    import synth
+    if kind == "I":
+        c, i, _ = synth.clustered_points(n, dim, seed=51)
+        return c, i
+    u, _ = synth.uniform_points(n // 10, dim, seed=52)
+    c, _, _ = synth.clustered_points(n - n // 10, dim, seed=53)
+    return np.ascontiguousarray(np.concatenate([u, c], axis=1)), np.arange(n, dtype=np.int64)
+
+
+def bench_alpha_sweep(a):
+    """Section 6.5 / Appendix G on one GPU: a 3-D stream of --n points (TYPE I
+    and TYPE II) cut into --batches batches and inserted into an empty tree,
+    for each alpha; after every batch 1-NN of 1e6 uniform queries.  Reported
+    per alpha: incremental insertion time over the time of one Build of all
+    points, rebuild volume (points in rebuilt subtrees, summed) over the final
+    size, final height, and the 1-NN times over those on a fresh Build of the
+    same points (checked every tenth of the stream: geometric mean and
+    maximum).  The value is the TYPE I insertion throughput at alpha = 0.3."""
+    import torch
+
+    import paper_2411_09275_amd as pk
+    import synth
+
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    D, n, B = 3, a.n, a.batches
+    alphas = [tuple(int(v) for v in x.split("/")) for x in a.alphas.split(",")]
+    q = torch.from_numpy(synth.uniform_queries(1_000_000, D, seed=54)).to(dev)
+    step = n // B
+    checks = set(range(B // 10 - 1, B, max(1, B // 10)))
+    res = {}
+    value = None
+    for kind in ("I", "II"):
+        c, i = _stream_type(kind, n, D)
+        gc, gi = torch.from_numpy(c).to(dev), torch.from_numpy(i).to(dev)
+        del c, i
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        t = pk.Tree(pk.Params(D), gc, gi)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - s0
+        t.free()
+        res[kind] = {"build_s": round(build_s, 4)}
+        for al in alphas:
+            p = pk.Params(D, alpha=al)
+            t = pk.Tree(p, gc[:, :0], gi[:0])
+            ins, vol, ratios, capacity = 0.0, 0, [], None
+            for b in range(B):
+                torch.cuda.synchronize()
+                s0 = time.perf_counter()
+                t.insert(gc[:, b * step:(b + 1) * step], gi[b * step:(b + 1) * step])
+                torch.cuda.synchronize()
+                ins += time.perf_counter() - s0
+                vol += t.update_stats()[1]
+                try:
+                    s0 = time.perf_counter()
+                    t.knn(q, 1)
+                    torch.cuda.synchronize()
+                    tq = time.perf_counter() - s0
+                except pk.PkdError as e:
+                    if e.code != -6:
+                        raise
+                    capacity = capacity if capacity is not None else b   # deeper than the traversal stack
+                    continue
+                if b in checks:
+                    f = pk.Tree(pk.Params(D), gc[:, :(b + 1) * step], gi[:(b + 1) * step])
+                    f.knn(q, 1)   # warm
+                    torch.cuda.synchronize()
+                    s0 = time.perf_counter()
+                    f.knn(q, 1)
+                    torch.cuda.synchronize()
+                    ratios.append(tq / (time.perf_counter() - s0))
+                    f.free()
+            row = {"insert_over_build": round(ins / build_s, 3), "insert_s": round(ins, 4),
+                   "rebuild_volume_over_n": round(vol / (step * B), 3), "height": t.height(),
+                   "knn1_over_fresh_geomean": round(float(np.exp(np.mean(np.log(ratios)))), 3) if ratios else None,
+                   "knn1_over_fresh_max": round(float(max(ratios)), 3) if ratios else None,
+                   "knn1_stack_exceeded_from_batch": capacity}
+            res[kind]["%d/%d" % al] = row
+            log("TYPE %s alpha %d/%d: %s" % (kind, al[0], al[1], row))
+            if kind == "I" and al == (3, 10):
+                value = step * B / ins / 1e6
+            t.free()
+        del gc, gi
+        torch.cuda.empty_cache()
+    out = {"metric": "incremental insertion of a %.0e-point stream in %d batches: Mpts/s at alpha 0.3 (TYPE I)"
+                     % (n, B),
+           "value": round(value, 2) if value is not None else None, "unit": "Mpts/s",
+           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "3-D int64 stream of %.0e points cut into %d batches, inserted into an empty tree; "
+                                  "TYPE I clustered in cluster order, TYPE II a uniform tenth then clustered; 1-NN "
+                                  "of 1e6 uniform queries after each batch" % (n, B),
+                      "alphas": a.alphas},
+           "results": res}
+    print(json.dumps(out))
+
+
+def bench_sliding_window(a):
+    """Section 6.2 on synthetic data: --years batches of clustered 2-D points
+    (the walks continue from year to year, 1e6 points per year by default
+    through --n / --years); the tree holds the last --window years: each step
+    inserts the newest year and deletes the oldest, then answers 1e6 10-NN of
+    in-distribution queries.  The value is the update throughput."""
+    import torch
+
+    import paper_2411_09275_amd as pk
+    import synth
+
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    D, Y, W = 2, a.years, a.window
+    per = a.n // Y
+    state = None
+    years = []
+    for y in range(Y):
+        c, i, state = synth.clustered_points(per, D, seed=60 + y, continue_from=state, id_base=y * per)
+        years.append((torch.from_numpy(c).to(dev), torch.from_numpy(i).to(dev)))
+    q, _, _ = synth.clustered_points(1_000_000, D, seed=59, continue_from=state)
+    q = torch.from_numpy(q).to(dev)
+    t = pk.Tree(pk.Params(D), *years[0])
+    upd, qry, steps = 0.0, 0.0, 0
+    for y in range(1, Y):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        t.insert(*years[y])
+        if y >= W:
+            assert t.delete(*years[y - W]) == per
+        torch.cuda.synchronize()
+        du = time.perf_counter() - s0
+        s0 = time.perf_counter()
+        t.knn(q, 10)
+        torch.cuda.synchronize()
+        dq = time.perf_counter() - s0
+        if y >= W:
+            upd += du
+            qry += dq
+            steps += 1
+        log("year %d: size %d, update %.1f ms, 10-NN %.1f ms" % (y, t.size(), du * 1e3, dq * 1e3))
+    out = {"metric": "sliding window over a clustered 2-D stream: Mpts/s of insert + delete",
+           "value": round(2 * per * steps / upd / 1e6, 2), "unit": "Mpts/s",
+           "n_gpus": 1, "steps": steps, "warmup": W - 1, "ms_per_step": round((upd + qry) / steps * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "%d years of %d clustered 2-D int64 points; window of %d years (insert the "
+                                  "newest, delete the oldest); 1e6 in-distribution 10-NN per step" % (Y, per, W)},
+           "update_ms_per_step": round(upd / steps * 1e3, 3), "knn_ms_per_step": round(qry / steps * 1e3, 3),
+           "final_size": t.size(), "final_height": t.height()}
+    t.free()
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -560,6 +786,12 @@ def main():
         return
     if a.workload == "range_report":
         bench_range_report(a)
+        return
+    if a.workload == "alpha_sweep":
+        bench_alpha_sweep(a)
+        return
+    if a.workload == "sliding_window":
+        bench_sliding_window(a)
         return
     if a.workload == "serving":
         bench_serving(a)
@@ -634,6 +866,7 @@ def main():
     ct_n, ct_ms, ct_bytes = pk.profile_get("sieve_count")
     sel_n, sel_ms, _ = pk.profile_get("select_skeleton")
     fin_n, fin_ms, _ = pk.profile_get("finisher")
+    kn_n, kn_ms, _ = pk.profile_get("knn")
     pk.profile_enable(False)
     scatter_gbs = sc_bytes / (sc_ms * 1e-3) / 1e9 if sc_ms > 0 else 0.0
     sieve_gbs = (sc_bytes + ct_bytes) / ((sc_ms + ct_ms) * 1e-3) / 1e9 if sc_ms + ct_ms > 0 else 0.0
@@ -669,11 +902,23 @@ def main():
                      "traffic": traffic,
                      "launches": sc_n, "alg_bytes_per_launch": round(sc_bytes / max(sc_n, 1))},
     }
+    # k-NN: algorithmic bytes from the search work of the oracle on the same
+    # tree (live with the CPU baseline, else the committed count)
+    work = None
     if not a.no_cpu_baseline:
-        print("timing the CPU oracle on a sample ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(coords, ids, q, lo, hi, a.cpu_sample, a.dim)
+        print("timing the CPU oracle ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"], work = cpu_baseline(coords, ids, q, a.dim, a.k, a.cpu_sample)
     else:
         out["cpu_baseline"] = None
+        work = stored_knn_work(a.n, a.dim, a.k)
+    if work is not None and kn_ms > 0:
+        per_q = knn_bytes_per_query(work, a.dim, a.k)
+        kn_gbs = per_q * a.queries / (kn_ms / kn_n * 1e-3) / 1e9
+        out["roofline_knn"] = {"kernel": "k_knn (%d-NN, one lane per query)" % a.k, "bound": "hbm",
+                               "achieved": round(kn_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(kn_gbs / HBM_PEAK_GBS, 4), "traffic": load_traffic("knn"),
+                               "launches": kn_n, "alg_bytes_per_launch": round(per_q * a.queries),
+                               "work_per_query": work}
     print(json.dumps(out))
 
 

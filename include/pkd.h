@@ -71,7 +71,8 @@ typedef struct {
   int32_t oversample; /* sigma; the sample size is s = 2^lambda * sigma <= 2048;
                          default 32 (s = 2048) */
   int32_t alpha_num;  /* balance parameter alpha = alpha_num / alpha_den with */
-  int32_t alpha_den;  /* 0 <= 2*alpha_num < alpha_den; default 3/10 */
+  int32_t alpha_den;  /* 0 <= 2*alpha_num <= alpha_den (alpha = 1/2: nothing is ever
+                         rebuilt for balance); default 3/10 */
   uint64_t seed;      /* seed of the sampling hash; default 42 */
 } pkd_params;
 
@@ -297,6 +298,15 @@ void pkd_free(pkd_tree* tree);
  * synchronize.
  */
 int pkd_free_async(pkd_tree* tree, void* stream);
+
+/*
+ * What the last pkd_batch_insert / pkd_batch_delete on the tree rebuilt (a
+ * diagnostic; the cost the update theorem of Section 4.3 amortizes): the
+ * number of subtrees rebuilt by Build (leaves that received points, and the
+ * topmost nodes that became unbalanced) and the points in them.  Host outs;
+ * either may be NULL.
+ */
+int pkd_update_stats(const pkd_tree* tree, int64_t* regions, int64_t* points);
 
 /* Node records the tree holds, live and dead (updates leave the records of
  * replaced nodes dead until a compaction drops them; a diagnostic). */

@@ -28,7 +28,8 @@ EXPORTS = ["pkd_default_params", "pkd_default_tuning", "pkd_build", "pkd_batch_i
            "pkd_free", "pkd_strerror", "pkd_profile_enable", "pkd_profile_get", "pkd_build_batch",
            "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch", "pkd_export_tree_sizes", "pkd_export_tree",
            "pkd_knn_async", "pkd_range_count_async", "pkd_knn_noalloc", "pkd_set_allocator", "pkd_free_async",
-           "pkd_node_slots", "pkd_range_report", "pkd_range_report_batch"]
+           "pkd_node_slots", "pkd_range_report", "pkd_range_report_batch",
+           "pkd_update_stats"]
 
 
 class PkdError(RuntimeError):
@@ -91,12 +92,13 @@ def lib():
         L.pkd_set_allocator.argtypes = [C.POINTER(_Allocator)]
         L.pkd_free_async.argtypes = [vp, vp]
         L.pkd_node_slots.argtypes = [vp, C.POINTER(i64)]
+        L.pkd_update_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
         L.pkd_range_report.argtypes = [vp, vp, vp, vp, i64, vp, vp, i64, C.POINTER(i64)]
         L.pkd_range_report_batch.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, i64, C.POINTER(i64)]
         L.pkd_range_count_async.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.pkd_strerror.argtypes = [C.c_int]
         L.pkd_strerror.restype = C.c_char_p
-        for f in ("pkd_range_report", "pkd_range_report_batch", "pkd_set_allocator", "pkd_free_async", "pkd_node_slots", "pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
+        for f in ("pkd_update_stats", "pkd_range_report", "pkd_range_report_batch", "pkd_set_allocator", "pkd_free_async", "pkd_node_slots", "pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
                   "pkd_export_tree_sizes", "pkd_export_tree", "pkd_profile_enable", "pkd_profile_get", "pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
                   "pkd_height", "pkd_export_sizes", "pkd_export"):
             getattr(L, f).restype = C.c_int
@@ -271,6 +273,12 @@ class Tree:
             else:
                 _check(lib().pkd_free_async(self.h, _stream(stream)), "pkd_free_async")
         self.h = None
+
+    def update_stats(self):
+        """(subtrees rebuilt, points in them) by the last insert or delete."""
+        r, p = C.c_int64(), C.c_int64()
+        _check(lib().pkd_update_stats(self.h, C.byref(r), C.byref(p)), "pkd_update_stats")
+        return r.value, p.value
 
     def node_slots(self) -> int:
         n = C.c_int64()

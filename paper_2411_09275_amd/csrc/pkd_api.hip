@@ -246,7 +246,7 @@ int check_params(const pkd_params* p, const pkd_tuning* t, Params* out) {
   if (!p) return PKD_ERR_INVALID_ARG;
   if (p->dim < 1 || p->dim > kMaxDim) return PKD_ERR_UNSUPPORTED;
   if (p->lambda < 1 || p->lambda > kMaxLambda || p->leaf_size < 1 || p->oversample < 1) return PKD_ERR_INVALID_ARG;
-  if (p->alpha_den <= 0 || p->alpha_num < 0 || 2 * static_cast<int64_t>(p->alpha_num) >= p->alpha_den)
+  if (p->alpha_den <= 0 || p->alpha_num < 0 || 2 * static_cast<int64_t>(p->alpha_num) > p->alpha_den)
     return PKD_ERR_INVALID_ARG;
   int64_t s = static_cast<int64_t>(p->oversample) << p->lambda;
   if (s > kMaxSample) return PKD_ERR_UNSUPPORTED;
@@ -322,6 +322,8 @@ void swap_storage(pkd_tree* a, pkd_tree* b) {
   std::swap(a->compact_mark, b->compact_mark);
   std::swap(a->height, b->height);
   std::swap(a->n_trees, b->n_trees);
+  std::swap(a->last_regions, b->last_regions);
+  std::swap(a->last_rebuilt, b->last_rebuilt);
 }
 
 int write_empty_root(pkd_tree* T, hipStream_t st) {
@@ -754,6 +756,13 @@ int pkd_set_allocator(const pkd_allocator* a) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_ext_on = a != nullptr;
   if (a) g_ext = *a;
+  return PKD_OK;
+}
+
+int pkd_update_stats(const pkd_tree* tree, int64_t* regions, int64_t* points) {
+  if (!tree) return PKD_ERR_INVALID_ARG;
+  if (regions) *regions = tree->last_regions;
+  if (points) *points = tree->last_rebuilt;
   return PKD_OK;
 }
 

@@ -109,6 +109,8 @@ struct pkd_tree {
   int32_t n_trees = 1;     // trees held: their roots are nodes 0 .. n_trees-1
   // copy items the last range report needed (sizes the next one's list)
   mutable int64_t report_items_hint = 0;
+  // what the last update rebuilt: subtrees (regions) and their points
+  int64_t last_regions = 0, last_rebuilt = 0;
 };
 
 // ---- host helpers shared by the sources (defined in pkd_api.hip) -----------

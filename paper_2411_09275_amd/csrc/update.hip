@@ -713,6 +713,8 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     swap_storage(T, fresh);
     release(fresh, st);
     delete fresh;
+    T->last_regions = 1;
+    T->last_rebuilt = m;
     return PKD_OK;
   }
 
@@ -765,7 +767,8 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     SieveWork W(st);
     SortRoute SR(st);
     while (ns > 0) {
-      if (rounds.size() > 200) return PKD_ERR_INTERNAL;
+      // every round descends lambda levels of a tree no higher than T->height
+      if (static_cast<int64_t>(rounds.size()) > T->height / lambda + 4) return PKD_ERR_INTERNAL;
       RoundSave* R = new RoundSave(st);
       rounds.push_back(R);
       R->ns = ns;
@@ -847,7 +850,10 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     PKD_HIP(hipStreamSynchronize(st));
     n_removed = tot;
     *removed = tot;
-    if (tot == 0) return PKD_OK;   // nothing to do
+    if (tot == 0) {   // nothing to do
+      T->last_regions = T->last_rebuilt = 0;
+      return PKD_OK;
+    }
   }
 
   // ---- decide, round by round, top-down.  Nothing is written to the tree
@@ -1079,6 +1085,8 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   T->c32_twin_cap = T->c32_cap;
   T->c32_cap = new_cap;
   T->n = n_new;
+  T->last_regions = n_regions;
+  T->last_rebuilt = R_pts;
   // reclaim the records of replaced nodes once they outnumber the rest
   // (optional: a tree that cannot get the memory keeps them)
   (void)compact_nodes(T, st);
