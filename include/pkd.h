@@ -69,7 +69,10 @@ typedef struct {
   int32_t leaf_size;  /* leaf wrap phi: a leaf holds at most phi points unless all
                          its points are identical (heavy leaf); default 32 */
   int32_t oversample; /* sigma; the sample size is s = 2^lambda * sigma <= 2048;
-                         default 32 (s = 2048) */
+                         default 32 (s = 2048).  0 (with lambda = 1): no sampling --
+                         every node is split at the exact median of all its points
+                         (the plain construction of Section 3 at every level, the
+                         comparison of Section 6.4) */
   int32_t alpha_num;  /* balance parameter alpha = alpha_num / alpha_den with */
   int32_t alpha_den;  /* 0 <= 2*alpha_num <= alpha_den (alpha = 1/2: nothing is ever
                          rebuilt for balance); default 3/10 */

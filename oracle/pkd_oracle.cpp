@@ -299,6 +299,7 @@ int build(Tree& T, const Set& Q, int h) {
   if (Q.size() <= static_cast<size_t>(p.phi)) return new_leaf(T, Q, h);
   if (all_identical(T.st, Q)) return new_leaf(T, Q, h);      // heavy leaf
   if (Q.size() < s) return split_node(T, Q, h);               // plain construction
+  if (p.sigma == 0) return split_node(T, Q, h);               // no sampling: exact medians everywhere
   Set S = take_sample(T, Q, h, s);
   Skeleton sk = build_skeleton(T.st, S, p.lambda);
   if (sk.external[1]) return split_node(T, Q, h);             // degenerate sample

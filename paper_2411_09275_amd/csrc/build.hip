@@ -1407,51 +1407,188 @@ __global__ void k_bin_finish(const Task* fin, int n_fin, int* lists, int stride,
   }
 }
 
-// ------------------------------------------- exact split of a large subproblem
-// Used when a subproblem's sample is entirely identical: per-dimension min and
-// max, then an exact radix selection of the upper median.
+// ------------------------------------------- segmented exact split
+// For every subproblem of a list at once (the rounds of the exact-median
+// construction, or the subproblems whose sample was entirely identical): the
+// split rule on all of the subproblem's points.  Per-dimension min and max;
+// the widest dimension, lowest index on ties (none: all points identical, a
+// heavy leaf); the upper median v[floor(m/2)] on it by a radix selection
+// (digits of 8, 8, 8 and 6 bits of the 30-bit coordinates, one counting pass
+// each); if that equals the minimum, the next larger distinct value.  The
+// result is written as a skeleton whose root splits and whose two children
+// are external (buckets 0 and 2^(lambda-1)).
 template <int D>
-__global__ void k_minmax(const int64_t* X, int64_t cap, int64_t start, int64_t m, unsigned long long* mn,
-                         unsigned long long* mx) {
-  unsigned long long lo[D], hi[D];
+__global__ void __launch_bounds__(kBlock) k_seg_minmax(const Task* sp, int ns, const int64_t* tile_off, int tile,
+                                                       Bufs bufs, int src, unsigned long long* mn,
+                                                       unsigned long long* mx) {
+  __shared__ int sig_sh;
+  const int64_t t = blockIdx.x;
+  if (threadIdx.x == 0) sig_sh = find_owner(tile_off, ns, t);
+  __syncthreads();
+  const int sig = sig_sh;
+  const Task q = sp[sig];
+  const int64_t lo = q.start + (t - tile_off[sig]) * tile;
+  const int64_t hi = min<int64_t>(lo + tile, static_cast<int64_t>(q.start) + q.m);
+  const int64_t* X = bufs.c[src];
+  const int64_t cap = bufs.cap[src];
+  unsigned long long a[D], b[D];
+#pragma unroll
   for (int d = 0; d < D; ++d) {
-    lo[d] = ~0ULL;
-    hi[d] = 0;
+    a[d] = ~0ULL;
+    b[d] = 0;
   }
-  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+#pragma unroll
     for (int d = 0; d < D; ++d) {
-      unsigned long long v = static_cast<unsigned long long>(X[d * cap + start + i]);
-      lo[d] = v < lo[d] ? v : lo[d];
-      hi[d] = v > hi[d] ? v : hi[d];
+      const unsigned long long v = static_cast<unsigned long long>(X[d * cap + i]);
+      a[d] = v < a[d] ? v : a[d];
+      b[d] = v > b[d] ? v : b[d];
     }
   }
+#pragma unroll
   for (int d = 0; d < D; ++d) {
-    atomicMin(mn + d, lo[d]);
-    atomicMax(mx + d, hi[d]);
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long x = __shfl_xor(a[d], o), y = __shfl_xor(b[d], o);
+      a[d] = x < a[d] ? x : a[d];
+      b[d] = y > b[d] ? y : b[d];
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicMin(mn + static_cast<int64_t>(sig) * D + d, a[d]);
+      atomicMax(mx + static_cast<int64_t>(sig) * D + d, b[d]);
+    }
   }
 }
 
-__global__ void k_digit_hist(const int64_t* Xd, int64_t start, int64_t m, int pshift, uint64_t prefix,
-                             int dshift, int dmask, unsigned int* hist) {
+__global__ void k_seg_init(int ns, int D, unsigned long long* mn, unsigned long long* mx, unsigned long long* above,
+                           unsigned int* hist) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < static_cast<int64_t>(ns) * 256;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    hist[i] = 0;
+    if (i < static_cast<int64_t>(ns) * D) {
+      mn[i] = ~0ULL;
+      mx[i] = 0;
+    }
+    if (i < ns) above[i] = ~0ULL;
+  }
+}
+
+__global__ void k_seg_pick(const Task* sp, int ns, int D, const unsigned long long* mn, const unsigned long long* mx,
+                           int32_t* sdim, int64_t* rank, unsigned long long* prefix) {
+  const int sig = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sig >= ns) return;
+  int best = -1;
+  unsigned long long bw = 0;
+  for (int d = 0; d < D; ++d) {
+    const unsigned long long w = mx[static_cast<int64_t>(sig) * D + d] - mn[static_cast<int64_t>(sig) * D + d];
+    if (w > bw) {
+      bw = w;
+      best = d;
+    }
+  }
+  sdim[sig] = best;   // -1: every point identical
+  rank[sig] = sp[sig].m / 2;
+  prefix[sig] = 0;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_seg_hist(const Task* sp, int ns, const int64_t* tile_off, int tile,
+                                                     Bufs bufs, int src, const int32_t* sdim,
+                                                     const unsigned long long* prefix, int pshift, int dshift,
+                                                     int dmask, unsigned int* hist) {
   __shared__ unsigned int h[256];
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
+  __shared__ int sig_sh;
+  const int64_t t = blockIdx.x;
+  if (threadIdx.x == 0) sig_sh = find_owner(tile_off, ns, t);
+  for (int i = threadIdx.x; i < 256; i += kBlock) h[i] = 0;
   __syncthreads();
-  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    uint64_t v = static_cast<uint64_t>(Xd[start + i]);
-    if (pshift >= 64 || (v >> pshift) == prefix) atomicAdd(&h[(v >> dshift) & dmask], 1u);
+  const int sig = sig_sh;
+  const int d = sdim[sig];
+  if (d < 0) return;
+  const Task q = sp[sig];
+  const int64_t lo = q.start + (t - tile_off[sig]) * tile;
+  const int64_t hi = min<int64_t>(lo + tile, static_cast<int64_t>(q.start) + q.m);
+  const int64_t* Xd = bufs.c[src] + d * bufs.cap[src];
+  const unsigned long long pre = prefix[sig];
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+    const unsigned long long v = static_cast<unsigned long long>(Xd[i]);
+    if (pshift >= 64 || (v >> pshift) == pre) atomicAdd(&h[(v >> dshift) & dmask], 1u);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 256; i += blockDim.x)
-    if (h[i]) atomicAdd(hist + i, h[i]);
+  for (int i = threadIdx.x; i < 256; i += kBlock)
+    if (h[i]) atomicAdd(hist + static_cast<int64_t>(sig) * 256 + i, h[i]);
 }
 
-__global__ void k_min_above(const int64_t* Xd, int64_t start, int64_t m, uint64_t v0, unsigned long long* out) {
+__global__ void k_seg_digit(int ns, const int32_t* sdim, unsigned int* hist, int nbins, int bits, int64_t* rank,
+                            unsigned long long* prefix) {
+  const int sig = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sig >= ns || sdim[sig] < 0) return;
+  unsigned int* hs = hist + static_cast<int64_t>(sig) * 256;
+  int64_t r = rank[sig];
+  int b = 0;
+  for (; b < nbins - 1; ++b) {
+    if (r < static_cast<int64_t>(hs[b])) break;
+    r -= hs[b];
+  }
+  rank[sig] = r;
+  prefix[sig] = (prefix[sig] << bits) | static_cast<unsigned long long>(b);
+  for (int i = 0; i < 256; ++i) hs[i] = 0;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_seg_min_above(const Task* sp, int ns, const int64_t* tile_off, int tile,
+                                                          Bufs bufs, int src, const int32_t* sdim,
+                                                          const unsigned long long* mn,
+                                                          const unsigned long long* prefix,
+                                                          unsigned long long* above) {
+  __shared__ int sig_sh;
+  const int64_t t = blockIdx.x;
+  if (threadIdx.x == 0) sig_sh = find_owner(tile_off, ns, t);
+  __syncthreads();
+  const int sig = sig_sh;
+  const int d = sdim[sig];
+  if (d < 0) return;
+  const unsigned long long v0 = mn[static_cast<int64_t>(sig) * D + d];
+  if (prefix[sig] != v0) return;   // the median already exceeds the minimum
+  const Task q = sp[sig];
+  const int64_t lo = q.start + (t - tile_off[sig]) * tile;
+  const int64_t hi = min<int64_t>(lo + tile, static_cast<int64_t>(q.start) + q.m);
+  const int64_t* Xd = bufs.c[src] + d * bufs.cap[src];
   unsigned long long best = ~0ULL;
-  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    unsigned long long v = static_cast<unsigned long long>(Xd[start + i]);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+    const unsigned long long v = static_cast<unsigned long long>(Xd[i]);
     if (v > v0 && v < best) best = v;
   }
-  atomicMin(out, best);
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long x = __shfl_xor(best, o);
+    best = x < best ? x : best;
+  }
+  if ((threadIdx.x & 63) == 0 && best != ~0ULL) atomicMin(above + sig, best);
+}
+
+// The split as a skeleton row of subproblem map[i] (or i): root splits,
+// children 2 and 3 external; mode 1 (heavy leaf) when all points are equal.
+__global__ void k_seg_finish(int ns, int D, int lambda, const int* map, const int32_t* sdim,
+                             const unsigned long long* mn, const unsigned long long* prefix,
+                             const unsigned long long* above, int64_t* rx, uint8_t* rdim, int8_t* ext, int8_t* mode) {
+  const int i = blockIdx.x;
+  const int sig = map ? map[i] : i;
+  const int NB = 1 << lambda, nheap = 2 << lambda;
+  const int d = sdim[i];
+  unsigned long long x = prefix[i];
+  if (d >= 0 && x == mn[static_cast<int64_t>(i) * D + d]) x = above[i];
+  for (int v = threadIdx.x; v < nheap; v += blockDim.x) {
+    if (v < NB) {
+      rx[static_cast<int64_t>(sig) * NB + v] = (v == 1 && d >= 0) ? static_cast<int64_t>(x) : kAllLeft;
+      rdim[static_cast<int64_t>(sig) * NB + v] = (v == 1 && d >= 0) ? static_cast<uint8_t>(d) : 0;
+    }
+    ext[static_cast<int64_t>(sig) * nheap + v] = (v == 2 || v == 3) ? 1 : 0;
+  }
+  if (threadIdx.x == 0) mode[sig] = d >= 0 ? 2 : 1;
+}
+
+__global__ void k_gather_tasks(const Task* all, const int* list, int n, Task* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = all[list[i]];
 }
 
 // ------------------------------------------------------------ host helpers
@@ -1472,88 +1609,74 @@ size_t finish_lds_bytes(int P, int phi) {
   return FinLayout(D, P, phi).end;
 }
 
-// Exact split of subproblem q whose sample was entirely identical (host-driven,
-// rare).  Returns mode 1 (heavy: all points identical) or 2 (skeleton set to a
-// single exact split at the root).
+// Scratch of the segmented exact split.
+struct ExactWork {
+  DArr<Task> sub;
+  DArr<unsigned long long> mn, mx, prefix, above;
+  DArr<int64_t> rank;
+  DArr<int32_t> sdim;
+  DArr<unsigned int> hist;
+  SieveWork W;
+  explicit ExactWork(hipStream_t s) : sub(s), mn(s), mx(s), prefix(s), above(s), rank(s), sdim(s), hist(s), W(s) {}
+};
+
+// The split rule on all points of ns subproblems at once (tasks: device;
+// list: optional device indices of the subproblems within `tasks`, whose rows
+// of rx / rdim / ext / mode receive the result).
 template <int D>
-int exact_split(hipStream_t st, const Task& q, const int64_t* X, int64_t cap, int lambda, int64_t* rx,
-                uint8_t* rdim, int8_t* ext, int8_t* mode_dev, int sig, unsigned long long* scratch) {
-  const int NB = 1 << lambda;
-  unsigned long long h_init[2 * kMaxDim];
-  for (int d = 0; d < D; ++d) {
-    h_init[d] = ~0ULL;
-    h_init[D + d] = 0;
+int seg_exact_split(hipStream_t st, const Task* tasks, const int* list, int ns, int tile, int lambda, int s,
+                    const Bufs& bufs, int src, int64_t* rx, uint8_t* rdim, int8_t* ext, int8_t* mode, ExactWork& E) {
+  if (ns <= 0) return PKD_OK;
+  const Task* sub = tasks;
+  if (list) {
+    PKD_TRY(E.sub.need(ns));
+    hipLaunchKernelGGL(k_gather_tasks, dim3((ns + 255) / 256), dim3(256), 0, st, tasks, list, ns, E.sub.p);
+    PKD_TRY(kernel_status("k_gather_tasks"));
+    sub = E.sub.p;
   }
-  PKD_HIP(hipMemcpyAsync(scratch, h_init, sizeof(unsigned long long) * 2 * D, hipMemcpyHostToDevice, st));
-  int grid = static_cast<int>(std::min<int64_t>(1024, (q.m + 255) / 256));
-  hipLaunchKernelGGL(k_minmax<D>, dim3(grid), dim3(256), 0, st, X, cap, int64_t{q.start}, int64_t{q.m}, scratch,
-                     scratch + D);
-  PKD_TRY(kernel_status("k_minmax"));
-  unsigned long long mm[2 * kMaxDim];
-  PKD_HIP(hipMemcpyAsync(mm, scratch, sizeof(unsigned long long) * 2 * D, hipMemcpyDeviceToHost, st));
-  PKD_HIP(hipStreamSynchronize(st));
-  int best = -1;
-  unsigned long long bw = 0;
-  for (int d = 0; d < D; ++d) {
-    unsigned long long w = mm[D + d] - mm[d];
-    if (w > bw) {
-      bw = w;
-      best = d;
-    }
+  int64_t ntiles = 0, nchunks = 0, pts = 0;
+  PKD_TRY(sieve_layout(st, sub, ns, tile, E.W, s, 0, nullptr, &ntiles, &nchunks, &pts));
+  PKD_TRY(E.mn.need(static_cast<size_t>(ns) * D));
+  PKD_TRY(E.mx.need(static_cast<size_t>(ns) * D));
+  PKD_TRY(E.prefix.need(ns));
+  PKD_TRY(E.above.need(ns));
+  PKD_TRY(E.rank.need(ns));
+  PKD_TRY(E.sdim.need(ns));
+  PKD_TRY(E.hist.need(static_cast<size_t>(ns) * 256));
+  const unsigned gi = static_cast<unsigned>(std::min<int64_t>(65536, (static_cast<int64_t>(ns) * 256 + 255) / 256));
+  hipLaunchKernelGGL(k_seg_init, dim3(gi), dim3(256), 0, st, ns, D, E.mn.p, E.mx.p, E.above.p, E.hist.p);
+  PKD_TRY(kernel_status("k_seg_init"));
+  const dim3 gt(static_cast<unsigned>(ntiles));
+  if (ntiles > 0) {
+    hipLaunchKernelGGL(k_seg_minmax<D>, gt, dim3(kBlock), 0, st, sub, ns, E.W.tile_off.p, tile, bufs, src, E.mn.p,
+                       E.mx.p);
+    PKD_TRY(kernel_status("k_seg_minmax"));
   }
-  int8_t mode = 1;
-  if (best >= 0) {
-    // upper median: the value of rank floor(m/2) (0-based) on dimension best
-    const int64_t* Xd = X + best * cap;
-    int64_t r = q.m / 2;
-    uint64_t prefix = 0;
-    const int shifts[4] = {22, 14, 6, 0};
-    const int bits[4] = {8, 8, 8, 6};
-    unsigned int* hist = reinterpret_cast<unsigned int*>(scratch + 2 * kMaxDim);
-    for (int pass = 0; pass < 4; ++pass) {
-      PKD_HIP(hipMemsetAsync(hist, 0, 256 * sizeof(unsigned int), st));
-      int pshift = pass == 0 ? 64 : shifts[pass] + bits[pass];
-      hipLaunchKernelGGL(k_digit_hist, dim3(grid), dim3(256), 0, st, Xd, int64_t{q.start}, int64_t{q.m}, pshift,
-                         prefix, shifts[pass], (1 << bits[pass]) - 1, hist);
-      PKD_TRY(kernel_status("k_digit_hist"));
-      unsigned int h[256];
-      PKD_HIP(hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, st));
-      PKD_HIP(hipStreamSynchronize(st));
-      int b = 0;
-      for (; b < (1 << bits[pass]); ++b) {
-        if (r < static_cast<int64_t>(h[b])) break;
-        r -= h[b];
-      }
-      prefix = (prefix << bits[pass]) | static_cast<uint64_t>(b);
+  const unsigned gs = static_cast<unsigned>((ns + 255) / 256);
+  hipLaunchKernelGGL(k_seg_pick, dim3(gs), dim3(256), 0, st, sub, ns, D, E.mn.p, E.mx.p, E.sdim.p, E.rank.p,
+                     E.prefix.p);
+  PKD_TRY(kernel_status("k_seg_pick"));
+  const int shifts[4] = {22, 14, 6, 0};
+  const int bits[4] = {8, 8, 8, 6};
+  for (int pass = 0; pass < 4; ++pass) {
+    const int pshift = pass == 0 ? 64 : shifts[pass] + bits[pass];
+    if (ntiles > 0) {
+      hipLaunchKernelGGL(k_seg_hist<D>, gt, dim3(kBlock), 0, st, sub, ns, E.W.tile_off.p, tile, bufs, src, E.sdim.p,
+                         E.prefix.p, pshift, shifts[pass], (1 << bits[pass]) - 1, E.hist.p);
+      PKD_TRY(kernel_status("k_seg_hist"));
     }
-    uint64_t x = prefix;
-    if (x == mm[best]) {
-      unsigned long long init = ~0ULL;
-      PKD_HIP(hipMemcpyAsync(scratch, &init, sizeof(init), hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(k_min_above, dim3(grid), dim3(256), 0, st, Xd, int64_t{q.start}, int64_t{q.m},
-                         static_cast<uint64_t>(mm[best]), scratch);
-      PKD_TRY(kernel_status("k_min_above"));
-      PKD_HIP(hipMemcpyAsync(&x, scratch, sizeof(x), hipMemcpyDeviceToHost, st));
-      PKD_HIP(hipStreamSynchronize(st));
-    }
-    std::vector<int64_t> hx(NB, kAllLeft);
-    std::vector<uint8_t> hd(NB, 0);
-    std::vector<int8_t> he(2 * NB, 0);
-    hx[1] = static_cast<int64_t>(x);
-    hd[1] = static_cast<uint8_t>(best);
-    he[2] = he[3] = 1;
-    PKD_HIP(hipMemcpyAsync(rx + static_cast<int64_t>(sig) * NB, hx.data(), sizeof(int64_t) * NB,
-                           hipMemcpyHostToDevice, st));
-    PKD_HIP(hipMemcpyAsync(rdim + static_cast<int64_t>(sig) * NB, hd.data(), NB, hipMemcpyHostToDevice, st));
-    PKD_HIP(hipMemcpyAsync(ext + static_cast<int64_t>(sig) * 2 * NB, he.data(), 2 * NB, hipMemcpyHostToDevice, st));
-    mode = 2;
-    PKD_HIP(hipMemcpyAsync(mode_dev + sig, &mode, 1, hipMemcpyHostToDevice, st));
-    PKD_HIP(hipStreamSynchronize(st));
-    return PKD_OK;
+    hipLaunchKernelGGL(k_seg_digit, dim3(gs), dim3(256), 0, st, ns, E.sdim.p, E.hist.p, 1 << bits[pass], bits[pass],
+                       E.rank.p, E.prefix.p);
+    PKD_TRY(kernel_status("k_seg_digit"));
   }
-  PKD_HIP(hipMemcpyAsync(mode_dev + sig, &mode, 1, hipMemcpyHostToDevice, st));
-  PKD_HIP(hipStreamSynchronize(st));
-  return PKD_OK;
+  if (ntiles > 0) {
+    hipLaunchKernelGGL(k_seg_min_above<D>, gt, dim3(kBlock), 0, st, sub, ns, E.W.tile_off.p, tile, bufs, src,
+                       E.sdim.p, E.mn.p, E.prefix.p, E.above.p);
+    PKD_TRY(kernel_status("k_seg_min_above"));
+  }
+  hipLaunchKernelGGL(k_seg_finish, dim3(ns), dim3(64), 0, st, ns, D, lambda, list, E.sdim.p, E.mn.p, E.prefix.p,
+                     E.above.p, rx, rdim, ext, mode);
+  return kernel_status("k_seg_finish");
 }
 
 template <int D>
@@ -1587,12 +1710,11 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
   DArr<uint8_t> rdim(st);
   DArr<int8_t> ext(st), mode(st), shift_fix(st);
   DArr<int> ctr(st), lists(st), rootext(st);
-  DArr<unsigned long long> scratch(st);
   SieveWork W(st);
+  ExactWork EW(st);
 
   // counters: 0 n_sieve, 1 n_fin, 2 n_next, 3 node_count, 4 flags, 5 n_root_ext, 6 height, 7 spare
   PKD_TRY(ctr.need(16));
-  PKD_TRY(scratch.need(2 * kMaxDim + 128));
   int hc[16] = {0};
   hc[3] = T->node_count;
   hc[6] = T->height;
@@ -1645,7 +1767,7 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
     PKD_TRY(ext.need(static_cast<size_t>(ns) * nheap));
     PKD_TRY(rootext.need(ns));
     PKD_TRY(cand_cnt.need(static_cast<size_t>(ns) * kCntStride));
-    for (int attempt = 0;; ++attempt) {
+    for (int attempt = 0; P.sigma > 0; ++attempt) {
       PKD_TRY(sieve_layout(st, sieve.p, ns, tile, W, s, small_max, override_p, &ntiles, &nchunks, &round_pts,
                            P.cand_bias));
       PKD_TRY(cand_key.need(static_cast<size_t>(ns) * cap));
@@ -1688,17 +1810,18 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
       PKD_HIP(hipMemcpyAsync(d_flags, &clear, sizeof(int), hipMemcpyHostToDevice, st));
       override_p = shift_fix.p;
     }
-    // exact splits where a sample was entirely identical (rare)
-    const int n_root_ext = hc[5];
-    if (n_root_ext > 0) {
-      std::vector<int> ids(n_root_ext);
-      std::vector<Task> tq(ns);
-      PKD_HIP(hipMemcpyAsync(ids.data(), rootext.p, sizeof(int) * n_root_ext, hipMemcpyDeviceToHost, st));
-      PKD_HIP(hipMemcpyAsync(tq.data(), sieve.p, sizeof(Task) * ns, hipMemcpyDeviceToHost, st));
-      PKD_HIP(hipStreamSynchronize(st));
-      for (int sig : ids)
-        PKD_TRY(exact_split<D>(st, tq[sig], bufs.c[src], bufs.cap[src], P.lambda, rx.p, rdim.p, ext.p, mode.p, sig,
-                               scratch.p));
+    if (P.sigma == 0) {
+      // exact medians, one level per round (no sampling): the split rule on
+      // all points of every subproblem
+      PKD_TRY(seg_exact_split<D>(st, sieve.p, nullptr, ns, tile, P.lambda, s, bufs, src, rx.p, rdim.p, ext.p,
+                                 mode.p, EW));
+      PKD_TRY(sieve_layout(st, sieve.p, ns, tile, W, s, small_max, nullptr, &ntiles, &nchunks, &round_pts,
+                           P.cand_bias));
+    } else if (hc[5] > 0) {
+      // subproblems whose sample was entirely identical (rare): the split
+      // rule on all their points
+      PKD_TRY(seg_exact_split<D>(st, sieve.p, rootext.p, hc[5], tile, P.lambda, s, bufs, src, rx.p, rdim.p, ext.p,
+                                 mode.p, EW));
     }
     // sieve: count, column-major scan, stable scatter
     PKD_TRY(sieve_pass(st, D, P.lambda, tile, sieve.p, ns, bufs, src, dst, rx.p, rdim.p, mode.p, W, ntiles, nchunks,

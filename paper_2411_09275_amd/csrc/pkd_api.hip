@@ -245,10 +245,12 @@ int ensure_nodes(pkd_tree* T, hipStream_t st, int64_t need) {
 int check_params(const pkd_params* p, const pkd_tuning* t, Params* out) {
   if (!p) return PKD_ERR_INVALID_ARG;
   if (p->dim < 1 || p->dim > kMaxDim) return PKD_ERR_UNSUPPORTED;
-  if (p->lambda < 1 || p->lambda > kMaxLambda || p->leaf_size < 1 || p->oversample < 1) return PKD_ERR_INVALID_ARG;
+  if (p->lambda < 1 || p->lambda > kMaxLambda || p->leaf_size < 1 || p->oversample < 0) return PKD_ERR_INVALID_ARG;
+  // oversample 0: exact medians at every node, one level per round (no sampling)
+  if (p->oversample == 0 && p->lambda != 1) return PKD_ERR_INVALID_ARG;
   if (p->alpha_den <= 0 || p->alpha_num < 0 || 2 * static_cast<int64_t>(p->alpha_num) > p->alpha_den)
     return PKD_ERR_INVALID_ARG;
-  int64_t s = static_cast<int64_t>(p->oversample) << p->lambda;
+  int64_t s = p->oversample == 0 ? kMaxSample : static_cast<int64_t>(p->oversample) << p->lambda;
   if (s > kMaxSample) return PKD_ERR_UNSUPPORTED;
   if (build_lds_need(p->dim, static_cast<int>(s), p->leaf_size) > kMaxLdsBytes) return PKD_ERR_UNSUPPORTED;
   int tile = t ? t->tile_points : 2048;

@@ -68,7 +68,8 @@ struct Bufs {
 };
 
 struct Params {
-  int D, lambda, phi, sigma, s;
+  int D, lambda, phi, sigma, s;   // sigma 0: exact medians at every node (lambda 1, no sampling);
+                                  // s is then the size below which the finisher takes over
   int64_t alpha_num, alpha_den;
   uint64_t seed;
   int tile;

@@ -386,3 +386,33 @@ def test_direct_knn_and_range_count_entry_points(orc, pk):
     assert L.pkd_knn(t.h, s, C.c_void_p(bad.data_ptr()), 4, 10, C.c_void_p(oi.data_ptr()),
                      C.c_void_p(od.data_ptr())) == -2
     t.free()
+
+
+@pytest.mark.parametrize("D,n,gen", [(1, 50000, "uniform"), (2, 300000, "uniform"), (3, 200000, "clustered"),
+                                     (5, 60000, "uniform"), (2, 120000, "dups")])
+def test_exact_median_mode_matches_oracle(orc, pk, D, n, gen):
+    # oversample 0: every node split at the exact median of all its points,
+    # one level per round, by the segmented device split (Section 6.4's
+    # comparison of sampling against exact medians)
+    if gen == "uniform":
+        c, i = synth.uniform_points(n, D, seed=600 + D)
+    elif gen == "clustered":
+        c, i, _ = synth.clustered_points(n, D, seed=601, n_clusters=40)
+    else:
+        c, i = synth.duplicate_heavy_points(n, D, seed=602, n_distinct=500, hot_fraction=0.3)
+    gt = pk.Tree(pk.Params(D, lam=1, sigma=0), c, i)
+    ot = orc.Tree(orc.Params(D, lam=1, sigma=0), c, i)
+    _same_tree(gt, ot, "exact %s D=%d" % (gen, D))
+    # updates rebuild with exact medians too
+    nc, ni = synth.uniform_points(n // 10, D, seed=603, id_base=10 ** 8)
+    gt.insert(nc, ni)
+    ot.insert(nc, ni)
+    assert gt.delete(c[:, : n // 7], i[: n // 7]) == ot.delete(c[:, : n // 7], i[: n // 7])
+    _same_tree(gt, ot, "exact after updates")
+    gt.free()
+
+
+def test_exact_median_mode_rejects_lambda_above_one(pk):
+    with pytest.raises(pk.PkdError) as e:
+        pk.Tree(pk.Params(2, lam=6, sigma=0), *synth.uniform_points(100, 2, seed=1))
+    assert e.value.code == -1

@@ -773,3 +773,42 @@ def test_threaded_oracle_knn_equals_sequential(orc):
     q = synth.uniform_queries(777, 3, seed=123)
     a, b = T.knn(q, 10), T.knn_threads(q, 10, 5)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def _plain_tree_by_definition(coords, ids, phi):
+    """The plain construction (Section 3) written out: split every node of
+    more than phi points, unless its points are identical, on the widest
+    dimension at the upper median (moved up to the next larger distinct value
+    when it equals the minimum); rows in pre-order, leaves as sorted id lists."""
+    rows, leaves = [], []
+
+    def rec(idx):
+        c = coords[:, idx]
+        if idx.shape[0] <= phi or np.all(c == c[:, :1]):
+            rows.append((1, -1, 0, idx.shape[0]))
+            leaves.append(np.sort(ids[idx]))
+            return
+        width = c.max(axis=1) - c.min(axis=1)
+        d = int(np.argmax(width))            # first maximum: lowest index on ties
+        v = np.sort(c[d])
+        x = v[v.shape[0] // 2]
+        if x == v[0]:
+            x = v[v > v[0]].min()
+        rows.append((0, d, int(x), idx.shape[0]))
+        rec(idx[c[d] < x])
+        rec(idx[c[d] >= x])
+
+    rec(np.arange(ids.shape[0]))
+    return np.array(rows, dtype=np.int64), np.concatenate(leaves)
+
+
+@pytest.mark.parametrize("D,n", [(1, 3000), (2, 5000), (3, 9000)])
+def test_exact_median_mode_is_the_plain_construction(orc, D, n):
+    # sigma = 0: no sampling, every node split at the exact median of all its
+    # points (the construction Section 6.4 compares sampling with)
+    c, i = synth.uniform_points(n, D, seed=140 + D)
+    c[:, :200] = c[:, :1]                    # a heavy leaf as well
+    T = orc.Tree(orc.Params(D, lam=1, sigma=0), c, i)
+    rows, ids, _ = T.export()
+    erows, eids = _plain_tree_by_definition(c, i, 32)
+    assert np.array_equal(rows, erows) and np.array_equal(ids, eids)
