@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="build",
                     choices=["build", "batching", "serving", "updates", "large_updates", "range_report",
-                             "alpha_sweep", "sliding_window"],
+                             "alpha_sweep", "sliding_window", "pkd_bb", "ablation"],
                     help="build: the headline (1e8 3-D build + queries); batching: 4096 trees in one pass")
     ap.add_argument("--serve-n", type=int, default=1_000_000_000, help="points of the resident serving tree")
     ap.add_argument("--requests", type=int, default=100, help="requests in the serving stream")
@@ -772,6 +772,138 @@ def bench_sliding_window(a):
     print(json.dumps(out))
 
 
+def bench_pkd_bb(a):
+    """Section 6.3 on synthetic data: the Pkd-tree (cells derived from the
+    splitters) against the Pkd-bb variant (stored node boxes) on the same
+    trees: 1e7 points, D in {2, 3, 7}, uniform and clustered; 1e6 10-NN
+    queries, 1e5 range counts and a range report of 1e3 cubes with outputs
+    log-uniform in [1e3, 1e5].  Reported: milliseconds of each query kind with
+    cells and with boxes (identical results required) and the time to compute
+    the boxes."""
+    import torch
+
+    import paper_2411_09275_amd as pk
+    import synth
+
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n = 10_000_000
+    rows = {}
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            s0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - s0)
+        return best * 1e3, r
+
+    for D in (2, 3, 7):
+        for gen in ("uniform", "clustered"):
+            if gen == "uniform":
+                c, i = synth.uniform_points(n, D, seed=80 + D)
+                q = synth.uniform_queries(1_000_000, D, seed=81)
+            else:
+                c, i, st = synth.clustered_points(n, D, seed=82 + D)
+                q, _, _ = synth.clustered_points(1_000_000, D, seed=83, continue_from=st)
+            lo, hi = synth.log_uniform_boxes(100_000, D, seed=84)
+            rlo, rhi = synth.report_boxes(1000, D, n, seed=85, out_lo=1e3, out_hi=1e5)
+            gq, glo, ghi, grlo, grhi = (torch.from_numpy(x).to(dev) for x in (q, lo, hi, rlo, rhi))
+            t = pk.Tree(pk.Params(D), torch.from_numpy(c).to(dev), torch.from_numpy(i).to(dev))
+            _, total = t.range_report_size(grlo, grhi)
+            buf = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
+            res = {}
+            for mode in ("cells", "boxes"):
+                if mode == "boxes":
+                    torch.cuda.synchronize()
+                    s0 = time.perf_counter()
+                    t.set_bbox(True)
+                    res["bbox_compute_ms"] = round((time.perf_counter() - s0) * 1e3, 3)
+                kms, kr = timed(lambda: t.knn(gq, 10))
+                cms, cr = timed(lambda: t.range_count(glo, ghi))
+                rms, rr = timed(lambda: t.range_report(grlo, grhi, out=buf))
+                res[mode] = {"knn10_ms": round(kms, 3), "range_count_ms": round(cms, 3),
+                             "range_report_ms": round(rms, 3)}
+                res[mode + "_digest"] = (int(kr[0].sum()), int(kr[1].sum()), int(cr.sum()),
+                                         int(torch.sort(rr[1])[0].sum()))
+            same = res.pop("cells_digest") == res.pop("boxes_digest")
+            res["identical_results"] = same
+            res["speedup"] = {k: round(res["cells"][k] / res["boxes"][k], 3) for k in res["cells"]}
+            rows["D=%d %s" % (D, gen)] = res
+            log("D=%d %s: %s" % (D, gen, res))
+            t.free()
+            del buf
+            torch.cuda.empty_cache()
+    out = {"metric": "Pkd-bb (stored node boxes) against Pkd (derived cells): query time ratios, 1e7 points",
+           "value": rows["D=7 uniform"]["speedup"]["range_report_ms"], "unit": "x (range report, D=7 uniform)",
+           "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "1e7 int64 points, D in {2,3,7}, uniform and clustered; 1e6 10-NN, 1e5 range "
+                                  "counts, 1e3 range reports with outputs log-uniform [1e3,1e5]; best of 3"},
+           "results": rows}
+    print(json.dumps(out))
+
+
+def bench_ablation(a):
+    """Section 6.4 on one GPU: Build of 1e8 3-D points (uniform and clustered)
+    three ways: the sieve with sampling and lambda = 6 (the method), the sieve
+    with sampling one level at a time (lambda = 1, sample 2048), and one level
+    at a time at exact medians without sampling.  All hand subproblems below
+    2048 points to the same finisher.  Reported: build milliseconds (mean of
+    --steps after --warmup) and the ratios."""
+    import torch
+
+    import paper_2411_09275_amd as pk
+    import synth
+
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n, D = a.n, 3
+    variants = {"lambda6_sampling": dict(lam=6, sigma=32), "lambda1_sampling": dict(lam=1, sigma=1024),
+                "lambda1_exact_median": dict(lam=1, sigma=0)}
+    res = {}
+    for gen in ("uniform", "clustered"):
+        if gen == "uniform":
+            c, i = synth.uniform_points(n, D, seed=3)
+        else:
+            c, i, _ = synth.clustered_points(n, D, seed=31)
+        gc, gi = torch.from_numpy(c).to(dev), torch.from_numpy(i).to(dev)
+        del c, i
+        row = {}
+        for name, kw in variants.items():
+            p = pk.Params(D, **kw)
+            times = []
+            for s in range(a.warmup + a.steps):
+                torch.cuda.synchronize()
+                s0 = time.perf_counter()
+                t = pk.Tree(p, gc, gi)
+                torch.cuda.synchronize()
+                if s >= a.warmup:
+                    times.append(time.perf_counter() - s0)
+                h = t.height()
+                t.free()
+            row[name] = {"build_ms": round(float(np.mean(times)) * 1e3, 3), "height": h}
+            log("%s %s: %s" % (gen, name, row[name]))
+        row["lambda1_over_lambda6"] = round(row["lambda1_sampling"]["build_ms"] / row["lambda6_sampling"]["build_ms"], 3)
+        row["exact_over_sampling"] = round(row["lambda1_exact_median"]["build_ms"] / row["lambda1_sampling"]["build_ms"], 3)
+        res[gen] = row
+        del gc, gi
+        torch.cuda.empty_cache()
+    out = {"metric": "technique ablation of Build (1e8 3-D): time of lambda=1 over lambda=6, exact medians over sampling",
+           "value": res["uniform"]["lambda1_over_lambda6"], "unit": "x (lambda=1 / lambda=6, uniform)",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "Build of %.0e 3-D int64 points (uniform seed 3; clustered seed 31) with lambda 6 "
+                                  "and sampling, lambda 1 and sampling (sample 2048), lambda 1 at exact medians" % n},
+           "results": res}
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -789,6 +921,12 @@ def main():
         return
     if a.workload == "alpha_sweep":
         bench_alpha_sweep(a)
+        return
+    if a.workload == "pkd_bb":
+        bench_pkd_bb(a)
+        return
+    if a.workload == "ablation":
+        bench_ablation(a)
         return
     if a.workload == "sliding_window":
         bench_sliding_window(a)

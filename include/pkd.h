@@ -303,6 +303,22 @@ void pkd_free(pkd_tree* tree);
 int pkd_free_async(pkd_tree* tree, void* stream);
 
 /*
+ * Bounding boxes (the Pkd-bb variant of Section 6.3).  With on != 0 the tree
+ * computes the tight box of every node's points (2 * dim int32 per node) and
+ * keeps it current across updates; range counts, range reports and k-NN with
+ * k <= 32 then prune with the boxes instead of the cells derived from the
+ * splitters (Section 5).  Results are identical either way; the boxes cost
+ * memory and box loads and save visited nodes.  on = 0 drops them.
+ * Synchronizes `stream`.
+ */
+int pkd_set_bbox(pkd_tree* tree, void* stream, int32_t on);
+
+/* The boxes of tree t of a handle in the pre-order of pkd_export: int32
+ * [num_nodes][2 * dim] = (lo_0..lo_{D-1}, hi_0..hi_{D-1}); an empty node's
+ * box has lo = 2^31-1, hi = -1.  Needs pkd_set_bbox(.., 1).  A test aid. */
+int pkd_export_bbox(const pkd_tree* tree, int32_t t, int32_t* boxes);
+
+/*
  * What the last pkd_batch_insert / pkd_batch_delete on the tree rebuilt (a
  * diagnostic; the cost the update theorem of Section 4.3 amortizes): the
  * number of subtrees rebuilt by Build (leaves that received points, and the

@@ -29,7 +29,7 @@ EXPORTS = ["pkd_default_params", "pkd_default_tuning", "pkd_build", "pkd_batch_i
            "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch", "pkd_export_tree_sizes", "pkd_export_tree",
            "pkd_knn_async", "pkd_range_count_async", "pkd_knn_noalloc", "pkd_set_allocator", "pkd_free_async",
            "pkd_node_slots", "pkd_range_report", "pkd_range_report_batch",
-           "pkd_update_stats"]
+           "pkd_update_stats", "pkd_set_bbox", "pkd_export_bbox"]
 
 
 class PkdError(RuntimeError):
@@ -93,12 +93,14 @@ def lib():
         L.pkd_free_async.argtypes = [vp, vp]
         L.pkd_node_slots.argtypes = [vp, C.POINTER(i64)]
         L.pkd_update_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+        L.pkd_set_bbox.argtypes = [vp, vp, i32]
+        L.pkd_export_bbox.argtypes = [vp, i32, vp]
         L.pkd_range_report.argtypes = [vp, vp, vp, vp, i64, vp, vp, i64, C.POINTER(i64)]
         L.pkd_range_report_batch.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, i64, C.POINTER(i64)]
         L.pkd_range_count_async.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.pkd_strerror.argtypes = [C.c_int]
         L.pkd_strerror.restype = C.c_char_p
-        for f in ("pkd_update_stats", "pkd_range_report", "pkd_range_report_batch", "pkd_set_allocator", "pkd_free_async", "pkd_node_slots", "pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
+        for f in ("pkd_set_bbox", "pkd_export_bbox", "pkd_update_stats", "pkd_range_report", "pkd_range_report_batch", "pkd_set_allocator", "pkd_free_async", "pkd_node_slots", "pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
                   "pkd_export_tree_sizes", "pkd_export_tree", "pkd_profile_enable", "pkd_profile_get", "pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
                   "pkd_height", "pkd_export_sizes", "pkd_export"):
             getattr(L, f).restype = C.c_int
@@ -273,6 +275,18 @@ class Tree:
             else:
                 _check(lib().pkd_free_async(self.h, _stream(stream)), "pkd_free_async")
         self.h = None
+
+    def set_bbox(self, on: bool = True, stream=None):
+        """Keep node bounding boxes and prune queries with them (Pkd-bb)."""
+        _check(lib().pkd_set_bbox(self.h, _stream(stream), 1 if on else 0), "pkd_set_bbox")
+
+    def export_bbox(self, t: int = 0):
+        """Node boxes in export pre-order: int32 [N, 2*dim] (lo..., hi...)."""
+        N, n = C.c_int64(), C.c_int64()
+        _check(lib().pkd_export_tree_sizes(self.h, t, C.byref(N), C.byref(n)), "pkd_export_sizes")
+        out = np.empty((N.value, 2 * self.p.dim), dtype=np.int32)
+        _check(lib().pkd_export_bbox(self.h, t, out.ctypes.data_as(C.c_void_p)), "pkd_export_bbox")
+        return out
 
     def update_stats(self):
         """(subtrees rebuilt, points in them) by the last insert or delete."""

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpkd.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["build.hip", "query.hip", "update.hip", "report.hip", "pkd_api.hip"]
+SOURCES = ["build.hip", "query.hip", "update.hip", "report.hip", "bbox.hip", "pkd_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed-FP32 instructions anywhere in the device code

@@ -300,6 +300,9 @@ void release(pkd_tree* T, hipStream_t st) {
   dev_free(T->nodes, st);
   dev_free(T->c32, st);
   dev_free(T->c32_twin, st);
+  dev_free(T->bbox, st);
+  T->bbox = nullptr;
+  T->bbox_cap = 0;
   T->buf[0] = T->buf[1] = nullptr;
   T->nodes = nullptr;
   T->c32 = T->c32_twin = nullptr;
@@ -758,6 +761,37 @@ int pkd_set_allocator(const pkd_allocator* a) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_ext_on = a != nullptr;
   if (a) g_ext = *a;
+  return PKD_OK;
+}
+
+int pkd_set_bbox(pkd_tree* tree, void* stream, int32_t on) {
+  if (!tree) return PKD_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!on) {
+    tree->bbox_on = false;
+    dev_free(tree->bbox, st);
+    tree->bbox = nullptr;
+    tree->bbox_cap = 0;
+    return PKD_OK;
+  }
+  PKD_TRY(compute_bbox(tree, st));
+  tree->bbox_on = true;
+  return PKD_OK;
+}
+
+int pkd_export_bbox(const pkd_tree* tree, int32_t t, int32_t* boxes) {
+  if (!tree || !boxes || t < 0 || t >= tree->n_trees) return PKD_ERR_INVALID_ARG;
+  if (!tree->bbox_on) return PKD_ERR_INVALID_ARG;
+  const int D = tree->prm.D;
+  std::vector<Node> nodes(tree->node_count);
+  std::vector<int32_t> bb(static_cast<size_t>(tree->node_count) * 2 * D);
+  PKD_HIP(hipDeviceSynchronize());
+  PKD_HIP(hipMemcpy(nodes.data(), tree->nodes, sizeof(Node) * tree->node_count, hipMemcpyDeviceToHost));
+  PKD_HIP(hipMemcpy(bb.data(), tree->bbox, sizeof(int32_t) * bb.size(), hipMemcpyDeviceToHost));
+  std::vector<int32_t> order;
+  if (walk(nodes, t, &order) < 0) return PKD_ERR_INTERNAL;
+  for (size_t r = 0; r < order.size(); ++r)
+    for (int c = 0; c < 2 * D; ++c) boxes[r * 2 * D + c] = bb[static_cast<size_t>(order[r]) * 2 * D + c];
   return PKD_OK;
 }
 

@@ -112,6 +112,11 @@ struct pkd_tree {
   mutable int64_t report_items_hint = 0;
   // what the last update rebuilt: subtrees (regions) and their points
   int64_t last_regions = 0, last_rebuilt = 0;
+  // bounding boxes of the nodes (int32 [node][lo D, hi D]) while bbox_on:
+  // the query kernels then prune with them (recomputed after every update)
+  int32_t* bbox = nullptr;
+  int64_t bbox_cap = 0;
+  bool bbox_on = false;
 };
 
 // ---- host helpers shared by the sources (defined in pkd_api.hip) -----------
@@ -250,6 +255,20 @@ void swap_storage(pkd_tree* a, pkd_tree* b);
 // Returns PKD_OK also when it skips the compaction (nothing to gain, or no
 // memory for the new array); the tree is valid either way.
 int compact_nodes(pkd_tree* T, hipStream_t st);
+
+// Bounding boxes of every live node (bbox.hip).
+int compute_bbox(pkd_tree* T, hipStream_t st);
+
+// The box of a node: from the stored boxes when there are any, else the
+// caller's cell.
+template <int D>
+__device__ inline void node_box(const int32_t* __restrict__ bbox, int32_t node, int32_t (&lo)[D], int32_t (&hi)[D]) {
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    lo[d] = bbox[static_cast<int64_t>(node) * 2 * D + d];
+    hi[d] = bbox[static_cast<int64_t>(node) * 2 * D + D + d];
+  }
+}
 
 // Query launches (query.hip): k-NN and range counts over the trees of a
 // handle (tree_of: per query, or null for tree 0); device errors are ORed

@@ -39,7 +39,8 @@ __global__ void __launch_bounds__(kQBlock) __attribute__((amdgpu_waves_per_eu(KM
                                                  const int64_t* __restrict__ Qry, int64_t nq, int k,
                                                  int64_t* __restrict__ out_ids, int64_t* __restrict__ out_d2,
                                                  int* flags, const int32_t* tree_of, int32_t n_trees,
-                                                 int32_t n_nodes, int64_t n_pts, const uint32_t* __restrict__ perm) {
+                                                 int32_t n_nodes, int64_t n_pts, const uint32_t* __restrict__ perm,
+                                                 const int32_t* __restrict__ bbox) {
   const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
   if (j0 >= nq) return;
   const int64_t j = perm ? static_cast<int64_t>(perm[j0]) : j0;   // lanes of a wave take nearby queries
@@ -85,8 +86,20 @@ __global__ void __launch_bounds__(kQBlock) __attribute__((amdgpu_waves_per_eu(KM
   int32_t node = root;      // node being descended, -1: take the next stacked one
   int64_t lb = 0;
   int32_t off[D];
+  // per-dimension distance from q to a box (0 inside its range)
+  auto box_off = [&](int32_t v, int32_t (&o)[D]) -> int64_t {
+    int64_t s2 = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int32_t lo = bbox[static_cast<int64_t>(v) * 2 * D + d], hi = bbox[static_cast<int64_t>(v) * 2 * D + D + d];
+      o[d] = q[d] < lo ? lo - q[d] : (q[d] > hi ? q[d] - hi : 0);
+      s2 += static_cast<int64_t>(o[d]) * o[d];
+    }
+    return s2;
+  };
 #pragma unroll
   for (int d = 0; d < D; ++d) off[d] = 0;
+  if (bbox) lb = box_off(root, off);
   int32_t leaf_off = 0, leaf_size = 0;
   bool have_leaf = false, done = false;
   int fail_bits = 0;
@@ -146,6 +159,26 @@ __global__ void __launch_bounds__(kQBlock) __attribute__((amdgpu_waves_per_eu(KM
       const bool go_left = qd < nd.x;
       const int32_t near = go_left ? nd.left : nd.right;
       const int32_t far = go_left ? nd.right : nd.left;
+      if (bbox) {
+        // both children by their own boxes: the far one is stacked, the near
+        // one descended, each only while its bound can still win
+        int32_t fo_[D];
+        const int64_t fl = box_off(far, fo_);
+        if (fl <= bd[KR - 1]) {
+          if (sp >= SD) {
+            fail_bits = kErrStack;
+            done = true;
+            continue;
+          }
+          stk[sp].node = far;
+#pragma unroll
+          for (int d = 0; d < D; ++d) stk[sp].off[d] = fo_[d];
+          ++sp;
+        }
+        lb = box_off(near, off);
+        node = lb > bd[KR - 1] ? -1 : near;
+        continue;
+      }
       // distance to the far cell in this dimension (the splitter is a stored
       // coordinate, so it fits 32 bits)
       const int64_t fo = go_left ? nd.x - qd : static_cast<int64_t>(qd) - nd.x + 1;
@@ -579,7 +612,7 @@ template <int D, int SD>
 __device__ int64_t range_walk(const Node* __restrict__ nodes, const int32_t* __restrict__ C32, int64_t cap,
                               const int32_t (&lo)[D], const int32_t (&hi)[D], int phi, int32_t n_nodes,
                               int64_t n_pts, bool start, int32_t node0, const int32_t (&clo0)[D],
-                              const int32_t (&chi0)[D], int* fail_out) {
+                              const int32_t (&chi0)[D], int* fail_out, const int32_t* __restrict__ bbox) {
   int64_t count = 0;
   struct Ent {
     int32_t node;
@@ -648,13 +681,19 @@ __device__ int64_t range_walk(const Node* __restrict__ nodes, const int32_t* __r
         done = true;
         continue;
       }
-      // right child: lo[dim] = x; left child: hi[dim] = x - 1
+      if (bbox) {
+        // the children's own boxes
+        node_box<D>(bbox, nd.right, stk[sp].clo, stk[sp].chi);
+        node_box<D>(bbox, nd.left, stk[sp + 1].clo, stk[sp + 1].chi);
+      } else {
+        // right child: lo[dim] = x; left child: hi[dim] = x - 1
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        stk[sp].clo[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x) : clo[d];
-        stk[sp].chi[d] = chi[d];
-        stk[sp + 1].clo[d] = clo[d];
-        stk[sp + 1].chi[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x - 1) : chi[d];
+        for (int d = 0; d < D; ++d) {
+          stk[sp].clo[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x) : clo[d];
+          stk[sp].chi[d] = chi[d];
+          stk[sp + 1].clo[d] = clo[d];
+          stk[sp + 1].chi[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x - 1) : chi[d];
+        }
       }
       stk[sp].node = nd.right;
       stk[sp + 1].node = nd.left;
@@ -696,7 +735,8 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
                                                    int64_t cap, const int64_t* __restrict__ Lo,
                                                    const int64_t* __restrict__ Hi, int64_t nb, int64_t* out,
                                                    int* flags, const int32_t* tree_of, int32_t n_trees, int phi,
-                                                   int32_t n_nodes, int64_t n_pts, const uint32_t* __restrict__ perm) {
+                                                   int32_t n_nodes, int64_t n_pts, const uint32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ bbox) {
   const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kQBlock + threadIdx.x;
   if (j0 >= nb) return;
   const int64_t j = perm ? static_cast<int64_t>(perm[j0]) : j0;
@@ -717,9 +757,10 @@ __global__ void __launch_bounds__(kQBlock) k_range(const Node* __restrict__ node
     clo[d] = 0;
     chi[d] = static_cast<int32_t>(kCoordMax);
   }
+  if (bbox) node_box<D>(bbox, root, clo, chi);
   int fail_bits = 0;
   const int64_t count = range_walk<D, SD>(nodes, C32, cap, lo, hi, phi, n_nodes, n_pts, !none, root, clo, chi,
-                                          &fail_bits);
+                                          &fail_bits, bbox);
   if (fail_bits) {
     atomicOr(flags, fail_bits);
     return;
@@ -742,7 +783,8 @@ __global__ void __launch_bounds__(kQBlock) k_range_wave(const Node* __restrict__
                                                         const int64_t* __restrict__ Hi, int64_t nb, int64_t* out,
                                                         int* flags, const int32_t* tree_of, int32_t n_trees, int phi,
                                                         int32_t n_nodes, int64_t n_pts,
-                                                        const uint32_t* __restrict__ perm) {
+                                                        const uint32_t* __restrict__ perm,
+                                                        const int32_t* __restrict__ bbox) {
   constexpr int WPB = kQBlock / 64;
   constexpr int EW = 1 + 2 * D;   // words of a frontier cell: node, lo[D], hi[D]
   __shared__ int32_t frontier[WPB][64 * EW];
@@ -770,6 +812,7 @@ __global__ void __launch_bounds__(kQBlock) k_range_wave(const Node* __restrict__
       clo[d] = 0;
       chi[d] = static_cast<int32_t>(kCoordMax);
     }
+    if (bbox) node_box<D>(bbox, root, clo, chi);
     int64_t count = 0;
     int fail_bits = 0;
     int32_t steps = 0;
@@ -817,12 +860,22 @@ __global__ void __launch_bounds__(kQBlock) k_range_wave(const Node* __restrict__
         int32_t* l = F + (at + 1) * EW;  // left child: hi[dim] = x - 1
         r[0] = nd.right;
         l[0] = nd.left;
+        if (bbox) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-          r[1 + d] = (nd.dim == d) ? static_cast<int32_t>(nd.x) : clo[d];
-          r[1 + D + d] = chi[d];
-          l[1 + d] = clo[d];
-          l[1 + D + d] = (nd.dim == d) ? static_cast<int32_t>(nd.x - 1) : chi[d];
+          for (int d = 0; d < D; ++d) {
+            r[1 + d] = bbox[static_cast<int64_t>(nd.right) * 2 * D + d];
+            r[1 + D + d] = bbox[static_cast<int64_t>(nd.right) * 2 * D + D + d];
+            l[1 + d] = bbox[static_cast<int64_t>(nd.left) * 2 * D + d];
+            l[1 + D + d] = bbox[static_cast<int64_t>(nd.left) * 2 * D + D + d];
+          }
+        } else {
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            r[1 + d] = (nd.dim == d) ? static_cast<int32_t>(nd.x) : clo[d];
+            r[1 + D + d] = chi[d];
+            l[1 + d] = clo[d];
+            l[1 + D + d] = (nd.dim == d) ? static_cast<int32_t>(nd.x - 1) : chi[d];
+          }
         }
       }
       wave_sync();
@@ -839,7 +892,8 @@ __global__ void __launch_bounds__(kQBlock) k_range_wave(const Node* __restrict__
       wave_sync();
     }
     // the remaining cells (more than 64 children wanted): one subtree walk per lane
-    count += range_walk<D, SD>(nodes, C32, cap, lo, hi, phi, n_nodes, n_pts, have, node, clo, chi, &fail_bits);
+    count += range_walk<D, SD>(nodes, C32, cap, lo, hi, phi, n_nodes, n_pts, have, node, clo, chi, &fail_bits,
+                               bbox);
     const unsigned long long fm = __ballot(fail_bits != 0);
     if (fm) {
       if (fail_bits) atomicOr(flags, fail_bits);
@@ -918,11 +972,12 @@ int order_queries(hipStream_t st, const int64_t* Q, int64_t nq, const int32_t* t
 template <int D, int SD>
 void launch_knn(int km, dim3 g, hipStream_t st, const Node* nodes, const int32_t* X, int64_t cap,
                 const int64_t* ids, const int64_t* q, int64_t nq, int k, int64_t* oi, int64_t* od, int* flags,
-                const int32_t* tree_of, int32_t n_trees, int32_t n_nodes, int64_t n_pts, const uint32_t* perm) {
+                const int32_t* tree_of, int32_t n_trees, int32_t n_nodes, int64_t n_pts, const uint32_t* perm,
+                const int32_t* bbox) {
 #define PKD_KNN_CASE(KM) \
   case KM:               \
     hipLaunchKernelGGL((k_knn<D, KM, SD>), g, dim3(kQBlock), 0, st, nodes, X, cap, ids, q, nq, k, oi, od, flags, \
-                       tree_of, n_trees, n_nodes, n_pts, perm); \
+                       tree_of, n_trees, n_nodes, n_pts, perm, bbox); \
     break;
   switch (km) {
     PKD_KNN_CASE(1)
@@ -956,15 +1011,18 @@ int knn_launch(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_
   const dim3 g(static_cast<unsigned>((nq + kQBlock - 1) / kQBlock));
   const int32_t* X = T->c32;
   const int64_t* ids = T->buf[T->cur] + static_cast<int64_t>(D) * T->cap;
+  // stored boxes prune the one-lane kernel (k <= 32); the one-wave kernel
+  // keeps the cells derived from the splitters (same results)
+  const int32_t* bb = T->bbox_on ? T->bbox : nullptr;
   if (T->height + 2 <= 32)
     launch_knn<D, 32>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
-                      T->node_count, T->n, perm);
+                      T->node_count, T->n, perm, bb);
   else if (T->height + 2 <= 64)
     launch_knn<D, 64>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
-                      T->node_count, T->n, perm);
+                      T->node_count, T->n, perm, bb);
   else if (T->height + 2 <= kMaxStack)
     launch_knn<D, kMaxStack>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
-                             T->node_count, T->n, perm);
+                             T->node_count, T->n, perm, bb);
   else
     return PKD_ERR_CAPACITY;
   hipError_t e = hipGetLastError();
@@ -988,6 +1046,7 @@ int range_d(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t*
   const uint32_t* perm = nullptr;
   PKD_TRY(order_queries<D>(st, lo, nb, tree_of, T->n_trees, W, &perm));   // boxes by their low corner
   const int32_t* X = T->c32;
+  const int32_t* bb = T->bbox_on ? T->bbox : nullptr;
   // below kRangeWaveMax boxes one lane per box would fill too little of the chip
   const bool per_wave = nb < kRangeWaveMax;
   const int64_t per_block = per_wave ? kQBlock / 64 : kQBlock;
@@ -995,10 +1054,10 @@ int range_d(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t*
 #define PKD_RANGE(SD)                                                                                             \
   if (per_wave)                                                                                                   \
     hipLaunchKernelGGL((k_range_wave<D, SD>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags, \
-                       tree_of, T->n_trees, T->prm.phi, T->node_count, T->n, perm);                                \
+                       tree_of, T->n_trees, T->prm.phi, T->node_count, T->n, perm, bb);                            \
   else                                                                                                            \
     hipLaunchKernelGGL((k_range<D, SD>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags,      \
-                       tree_of, T->n_trees, T->prm.phi, T->node_count, T->n, perm);
+                       tree_of, T->n_trees, T->prm.phi, T->node_count, T->n, perm, bb);
   if (T->height + 3 <= 48) {
     PKD_RANGE(48)
   } else if (T->height + 3 <= kMaxStack) {

@@ -250,7 +250,8 @@ __global__ void __launch_bounds__(kBlock) k_report_walk(const Node* __restrict__
                                                         const int32_t* tree_of, int32_t n_trees, int phi,
                                                         int32_t n_nodes, int64_t n_pts, int64_t* counts, Item* items,
                                                         unsigned long long* n_items, int64_t item_cap,
-                                                        unsigned long long* next_box, int* flags) {
+                                                        unsigned long long* next_box, int* flags,
+                                                        const int32_t* __restrict__ bbox) {
   constexpr int WPB = kBlock / 64;
   constexpr int EW = 1 + 2 * D;   // words of a frontier cell: node, lo[D], hi[D]
   __shared__ int32_t frontier[WPB][64 * EW];
@@ -292,6 +293,7 @@ __global__ void __launch_bounds__(kBlock) k_report_walk(const Node* __restrict__
       clo[d] = 0;
       chi[d] = static_cast<int32_t>(kCoordMax);
     }
+    if (bbox) node_box<D>(bbox, root, clo, chi);
     int fail = 0;
     int32_t steps = 0;
     Node nd;
@@ -330,12 +332,22 @@ __global__ void __launch_bounds__(kBlock) k_report_walk(const Node* __restrict__
         int32_t* r = F + (at + 1) * EW;  // right child: lo[dim] = x
         l[0] = nd.left;
         r[0] = nd.right;
+        if (bbox) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-          l[1 + d] = clo[d];
-          l[1 + D + d] = (nd.dim == d) ? static_cast<int32_t>(nd.x - 1) : chi[d];
-          r[1 + d] = (nd.dim == d) ? static_cast<int32_t>(nd.x) : clo[d];
-          r[1 + D + d] = chi[d];
+          for (int d = 0; d < D; ++d) {
+            l[1 + d] = bbox[static_cast<int64_t>(nd.left) * 2 * D + d];
+            l[1 + D + d] = bbox[static_cast<int64_t>(nd.left) * 2 * D + D + d];
+            r[1 + d] = bbox[static_cast<int64_t>(nd.right) * 2 * D + d];
+            r[1 + D + d] = bbox[static_cast<int64_t>(nd.right) * 2 * D + D + d];
+          }
+        } else {
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            l[1 + d] = clo[d];
+            l[1 + D + d] = (nd.dim == d) ? static_cast<int32_t>(nd.x - 1) : chi[d];
+            r[1 + d] = (nd.dim == d) ? static_cast<int32_t>(nd.x) : clo[d];
+            r[1 + D + d] = chi[d];
+          }
         }
       }
       wave_sync_r();
@@ -360,12 +372,17 @@ __global__ void __launch_bounds__(kBlock) k_report_walk(const Node* __restrict__
     Ent stk[SD];
     int sp = 0;
     if (have) {
+      if (bbox) {
+        node_box<D>(bbox, nd.right, stk[0].clo, stk[0].chi);
+        node_box<D>(bbox, nd.left, stk[1].clo, stk[1].chi);
+      } else {
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        stk[0].clo[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x) : clo[d];
-        stk[0].chi[d] = chi[d];
-        stk[1].clo[d] = clo[d];
-        stk[1].chi[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x - 1) : chi[d];
+        for (int d = 0; d < D; ++d) {
+          stk[0].clo[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x) : clo[d];
+          stk[0].chi[d] = chi[d];
+          stk[1].clo[d] = clo[d];
+          stk[1].chi[d] = (nd.dim == d) ? static_cast<int32_t>(nd.x - 1) : chi[d];
+        }
       }
       stk[0].node = nd.right;
       stk[1].node = nd.left;
@@ -414,12 +431,17 @@ __global__ void __launch_bounds__(kBlock) k_report_walk(const Node* __restrict__
           done = true;
           continue;
         }
+        if (bbox) {
+          node_box<D>(bbox, w.right, stk[sp].clo, stk[sp].chi);
+          node_box<D>(bbox, w.left, stk[sp + 1].clo, stk[sp + 1].chi);
+        } else {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-          stk[sp].clo[d] = (w.dim == d) ? static_cast<int32_t>(w.x) : a[d];
-          stk[sp].chi[d] = b[d];
-          stk[sp + 1].clo[d] = a[d];
-          stk[sp + 1].chi[d] = (w.dim == d) ? static_cast<int32_t>(w.x - 1) : b[d];
+          for (int d = 0; d < D; ++d) {
+            stk[sp].clo[d] = (w.dim == d) ? static_cast<int32_t>(w.x) : a[d];
+            stk[sp].chi[d] = b[d];
+            stk[sp + 1].clo[d] = a[d];
+            stk[sp + 1].chi[d] = (w.dim == d) ? static_cast<int32_t>(w.x - 1) : b[d];
+          }
         }
         stk[sp].node = w.right;
         stk[sp + 1].node = w.left;
@@ -469,7 +491,7 @@ int report_walk_d(const pkd_tree* T, hipStream_t st, const int64_t* lo, const in
 #define PKD_WALK(SD)                                                                                              \
   hipLaunchKernelGGL((k_report_walk<D, SD>), g, dim3(kBlock), 0, st, T->nodes, T->c32, T->cap, lo, hi, nb,       \
                      tree_of, T->n_trees, T->prm.phi, T->node_count, T->n, counts, items, n_items, item_cap,    \
-                     next_box, flags);
+                     next_box, flags, T->bbox_on ? T->bbox : nullptr);
   if (T->height + 3 <= 48) {
     PKD_WALK(48)
   } else if (T->height + 3 <= kMaxStack) {

@@ -631,6 +631,18 @@ __global__ void k_copy_roots(Node* nodes, int32_t base, const Node* tmp, const R
     nodes[regions[r].node] = translate(tmp[r], regions, comp, nreg, r, base);
 }
 
+// After an update the stored boxes (if any) are recomputed; a tree that
+// cannot get the memory for them drops them (queries then derive the cells
+// from the splitters, with the same results).
+void refresh_boxes(pkd_tree* T, hipStream_t st) {
+  if (T->bbox_on && compute_bbox(T, st) != PKD_OK) {
+    T->bbox_on = false;
+    dev_free(T->bbox, st);
+    T->bbox = nullptr;
+    T->bbox_cap = 0;
+  }
+}
+
 int fill(hipStream_t st, int32_t* a, int64_t n, int32_t v) {
   if (n <= 0) return PKD_OK;
   const unsigned g = static_cast<unsigned>(std::min<int64_t>(4096, (n + 255) / 256));
@@ -715,6 +727,7 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     delete fresh;
     T->last_regions = 1;
     T->last_rebuilt = m;
+    refresh_boxes(T, st);
     return PKD_OK;
   }
 
@@ -1090,6 +1103,7 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   // reclaim the records of replaced nodes once they outnumber the rest
   // (optional: a tree that cannot get the memory keeps them)
   (void)compact_nodes(T, st);
+  refresh_boxes(T, st);
   return PKD_OK;
 }
 
