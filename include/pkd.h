@@ -209,12 +209,24 @@ int pkd_range_report(const pkd_tree* tree, void* stream, const int64_t* lo, cons
  * positions [offsets[t], offsets[t+1]) (offsets: HOST int64 [n_trees+1],
  * offsets[0] = 0, non-decreasing).  All trees share `params`.  The handle holds
  * n_trees trees; each is exactly the tree pkd_build would make of its points.
- * Batch handles answer pkd_knn_batch / pkd_range_count_batch and export one
- * tree at a time; updates on a batch handle return PKD_ERR_UNSUPPORTED.
+ * Batch handles answer pkd_knn_batch / pkd_range_count_batch, export one
+ * tree at a time and take updates tree by tree (pkd_batch_insert_tree /
+ * pkd_batch_delete_tree).
  */
 int pkd_build_batch(const pkd_params* params, const pkd_tuning* tuning, void* stream,
                     int32_t n_trees, const int64_t* coords, const int64_t* ids,
                     const int64_t* offsets, pkd_tree** out);
+
+/*
+ * BatchInsert / BatchDelete on tree t of a handle (t = 0 for a single tree:
+ * pkd_batch_insert / pkd_batch_delete are these with t = 0).  Semantics,
+ * arguments and errors as for those calls; the other trees of the handle do
+ * not change.
+ */
+int pkd_batch_insert_tree(pkd_tree* tree, int32_t t, void* stream, const int64_t* coords,
+                          const int64_t* ids, int64_t m);
+int pkd_batch_delete_tree(pkd_tree* tree, int32_t t, void* stream, const int64_t* coords,
+                          const int64_t* ids, int64_t m, int64_t* n_deleted);
 
 /* Number of trees held by a handle (1 for pkd_build). */
 int pkd_num_trees(const pkd_tree* tree, int32_t* n_trees);

@@ -29,7 +29,8 @@ EXPORTS = ["pkd_default_params", "pkd_default_tuning", "pkd_build", "pkd_batch_i
            "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch", "pkd_export_tree_sizes", "pkd_export_tree",
            "pkd_knn_async", "pkd_range_count_async", "pkd_knn_noalloc", "pkd_set_allocator", "pkd_free_async",
            "pkd_node_slots", "pkd_range_report", "pkd_range_report_batch",
-           "pkd_update_stats", "pkd_set_bbox", "pkd_export_bbox"]
+           "pkd_update_stats", "pkd_set_bbox", "pkd_export_bbox", "pkd_batch_insert_tree",
+           "pkd_batch_delete_tree"]
 
 
 class PkdError(RuntimeError):
@@ -94,13 +95,15 @@ def lib():
         L.pkd_node_slots.argtypes = [vp, C.POINTER(i64)]
         L.pkd_update_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
         L.pkd_set_bbox.argtypes = [vp, vp, i32]
+        L.pkd_batch_insert_tree.argtypes = [vp, i32, vp, vp, vp, i64]
+        L.pkd_batch_delete_tree.argtypes = [vp, i32, vp, vp, vp, i64, C.POINTER(i64)]
         L.pkd_export_bbox.argtypes = [vp, i32, vp]
         L.pkd_range_report.argtypes = [vp, vp, vp, vp, i64, vp, vp, i64, C.POINTER(i64)]
         L.pkd_range_report_batch.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, i64, C.POINTER(i64)]
         L.pkd_range_count_async.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.pkd_strerror.argtypes = [C.c_int]
         L.pkd_strerror.restype = C.c_char_p
-        for f in ("pkd_set_bbox", "pkd_export_bbox", "pkd_update_stats", "pkd_range_report", "pkd_range_report_batch", "pkd_set_allocator", "pkd_free_async", "pkd_node_slots", "pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
+        for f in ("pkd_batch_insert_tree", "pkd_batch_delete_tree", "pkd_set_bbox", "pkd_export_bbox", "pkd_update_stats", "pkd_range_report", "pkd_range_report_batch", "pkd_set_allocator", "pkd_free_async", "pkd_node_slots", "pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
                   "pkd_export_tree_sizes", "pkd_export_tree", "pkd_profile_enable", "pkd_profile_get", "pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
                   "pkd_height", "pkd_export_sizes", "pkd_export"):
             getattr(L, f).restype = C.c_int
@@ -396,15 +399,18 @@ class Tree:
                                             C.byref(total)), "pkd_range_report")
         return off, total.value
 
-    def insert(self, coords, ids, stream=None):
+    def insert(self, coords, ids, stream=None, tree: int = 0):
+        """BatchInsert into tree `tree` of the handle (0 for a single tree)."""
         c, i = _dev(coords), _dev(ids)
-        _check(lib().pkd_batch_insert(self.h, _stream(stream), _ptr(c), _ptr(i), i.shape[0]), "pkd_batch_insert")
+        _check(lib().pkd_batch_insert_tree(self.h, tree, _stream(stream), _ptr(c), _ptr(i), i.shape[0]),
+               "pkd_batch_insert")
 
-    def delete(self, coords, ids, stream=None) -> int:
+    def delete(self, coords, ids, stream=None, tree: int = 0) -> int:
+        """BatchDelete from tree `tree` of the handle; returns the points removed."""
         c, i = _dev(coords), _dev(ids)
         n = C.c_int64()
-        _check(lib().pkd_batch_delete(self.h, _stream(stream), _ptr(c), _ptr(i), i.shape[0], C.byref(n)),
-               "pkd_batch_delete")
+        _check(lib().pkd_batch_delete_tree(self.h, tree, _stream(stream), _ptr(c), _ptr(i), i.shape[0],
+                                           C.byref(n)), "pkd_batch_delete")
         return n.value
 
     def export(self, t: int = 0):

@@ -14,8 +14,9 @@ namespace pkd {
 
 int run_knn_static(const pkd_tree* T, hipStream_t st, const int64_t* q, int64_t nq, int k, int64_t* oi,
                    int64_t* od);
-int run_insert(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m);
-int run_delete(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m, int64_t* removed);
+int run_insert(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m);
+int run_delete(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m,
+               int64_t* removed);
 
 int hip_status(hipError_t e, const char* what) {
   if (std::getenv("PKD_VERBOSE")) std::fprintf(stderr, "libpkd: %s failed: %s\n", what, hipGetErrorString(e));
@@ -591,27 +592,35 @@ int pkd_num_trees(const pkd_tree* tree, int32_t* n_trees) {
   return PKD_OK;
 }
 
-int pkd_batch_insert(pkd_tree* tree, void* stream, const int64_t* coords, const int64_t* ids, int64_t m) {
-  if (!tree || m < 0) return PKD_ERR_INVALID_ARG;
-  if (tree->n_trees != 1) return PKD_ERR_UNSUPPORTED;
+int pkd_batch_insert_tree(pkd_tree* tree, int32_t t, void* stream, const int64_t* coords, const int64_t* ids,
+                          int64_t m) {
+  if (!tree || m < 0 || t < 0 || t >= tree->n_trees) return PKD_ERR_INVALID_ARG;
   if (m == 0) return PKD_OK;
   if (!coords || !ids) return PKD_ERR_INVALID_ARG;
   if (tree->n + m >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
-  return run_insert(tree, static_cast<hipStream_t>(stream), coords, ids, m);
+  return run_insert(tree, t, static_cast<hipStream_t>(stream), coords, ids, m);
 }
 
-int pkd_batch_delete(pkd_tree* tree, void* stream, const int64_t* coords, const int64_t* ids, int64_t m,
-                     int64_t* n_deleted) {
+int pkd_batch_insert(pkd_tree* tree, void* stream, const int64_t* coords, const int64_t* ids, int64_t m) {
+  return pkd_batch_insert_tree(tree, 0, stream, coords, ids, m);
+}
+
+int pkd_batch_delete_tree(pkd_tree* tree, int32_t t, void* stream, const int64_t* coords, const int64_t* ids,
+                          int64_t m, int64_t* n_deleted) {
   if (n_deleted) *n_deleted = 0;
-  if (!tree || m < 0) return PKD_ERR_INVALID_ARG;
-  if (tree->n_trees != 1) return PKD_ERR_UNSUPPORTED;
+  if (!tree || m < 0 || t < 0 || t >= tree->n_trees) return PKD_ERR_INVALID_ARG;
   if (m == 0) return PKD_OK;
   if (!coords || !ids) return PKD_ERR_INVALID_ARG;
   if (m >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
   int64_t removed = 0;
-  int rc = run_delete(tree, static_cast<hipStream_t>(stream), coords, ids, m, &removed);
+  int rc = run_delete(tree, t, static_cast<hipStream_t>(stream), coords, ids, m, &removed);
   if (rc == PKD_OK && n_deleted) *n_deleted = removed;
   return rc;
+}
+
+int pkd_batch_delete(pkd_tree* tree, void* stream, const int64_t* coords, const int64_t* ids, int64_t m,
+                     int64_t* n_deleted) {
+  return pkd_batch_delete_tree(tree, 0, stream, coords, ids, m, n_deleted);
 }
 
 int pkd_size(const pkd_tree* tree, int64_t* n) {

@@ -530,8 +530,10 @@ __global__ void k_region_final(Region* regions, const int32_t* S, int insert) {
   Region& r = regions[blockIdx.x];
   if (threadIdx.x != 0) return;
   if (insert) {
-    // batch points are noted at region ends, which lie after the start
-    r.new_start = r.a + S[r.a + 1];
+    // batch points are noted at region ends; for a region with old points
+    // the end lies after its start, for an empty one (an empty tree of a
+    // batch handle) on it, and its own batch points are not before it
+    r.new_start = r.a + (r.a < r.b ? S[r.a + 1] : S[r.a]);
     r.new_size = (r.b - r.a) + (r.e - r.s);
   } else {
     r.new_start = r.a - S[r.a];
@@ -700,8 +702,8 @@ int route_by_sort(hipStream_t st, const Task* tasks, int ns, int64_t m, const Bu
 }
 
 template <int D>
-int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m, bool insert,
-             int64_t* removed) {
+int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m,
+             bool insert, int64_t* removed) {
   const Params& P = T->prm;
   const int lambda = P.lambda, NB = 1 << lambda, nheap = 2 << lambda;
   const int64_t n = T->n;
@@ -717,7 +719,7 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
     PKD_HIP(hipStreamSynchronize(st));
     if (h & kErrRange) return PKD_ERR_RANGE;
   }
-  if (insert && n == 0) {
+  if (insert && n == 0 && T->n_trees == 1) {
     // inserting into the empty tree is Build(P) at the root: built as a new
     // tree whose storage replaces the tree's only once it is complete
     pkd_tree* fresh = nullptr;
@@ -758,7 +760,8 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   PKD_TRY(res.need(static_cast<size_t>(m) + 1));
 
   Node root;
-  PKD_HIP(hipMemcpyAsync(&root, T->nodes, sizeof(Node), hipMemcpyDeviceToHost, st));
+  // the tree's root: node `tree` (the trees of a handle have their roots first)
+  PKD_HIP(hipMemcpyAsync(&root, T->nodes + tree, sizeof(Node), hipMemcpyDeviceToHost, st));
   PKD_HIP(hipStreamSynchronize(st));
   std::vector<RoundSave*> rounds;
   struct Cleanup {
@@ -769,12 +772,12 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   } cleanup{rounds};
   int nres = 0;
   if (root.left < 0) {
-    Res r0{0, 0, static_cast<int32_t>(m), 0};
+    Res r0{tree, 0, static_cast<int32_t>(m), 0};
     PKD_HIP(hipMemcpyAsync(res.p, &r0, sizeof(Res), hipMemcpyHostToDevice, st));
     nres = 1;
   } else {
     PKD_TRY(cur.need(1));
-    Task t0{0, static_cast<int32_t>(m), 0, 0, 0, 0};
+    Task t0{0, static_cast<int32_t>(m), tree, root.depth, 0, 0};
     PKD_HIP(hipMemcpyAsync(cur.p, &t0, sizeof(Task), hipMemcpyHostToDevice, st));
     int ns = 1, src = 0;
     SieveWork W(st);
@@ -885,12 +888,12 @@ int update_d(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* 
   if (rounds.empty()) {
     // the root is a leaf
     if (insert) {
-      Region r{0, root.depth, root.off, root.off + root.size, 0, static_cast<int32_t>(m), 0, 0};
+      Region r{tree, root.depth, root.off, root.off + root.size, 0, static_cast<int32_t>(m), 0, 0};
       PKD_HIP(hipMemcpyAsync(regions.p, &r, sizeof(Region), hipMemcpyHostToDevice, st));
       int one = 1;
       PKD_HIP(hipMemcpyAsync(d_regions, &one, sizeof(int), hipMemcpyHostToDevice, st));
     } else {
-      const int2 sz = make_int2(0, root.size - static_cast<int32_t>(n_removed));
+      const int2 sz = make_int2(tree, root.size - static_cast<int32_t>(n_removed));
       PKD_HIP(hipMemcpyAsync(sizes.p, &sz, sizeof(int2), hipMemcpyHostToDevice, st));
       int one = 1;
       PKD_HIP(hipMemcpyAsync(d_sizes, &one, sizeof(int), hipMemcpyHostToDevice, st));
@@ -1157,30 +1160,31 @@ int compact_nodes(pkd_tree* T, hipStream_t st) {
   return PKD_OK;
 }
 
-int run_insert(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m) {
+int run_insert(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m) {
   int64_t dummy = 0;
   switch (T->prm.D) {
-    case 1: return update_d<1>(T, st, coords, ids, m, true, &dummy);
-    case 2: return update_d<2>(T, st, coords, ids, m, true, &dummy);
-    case 3: return update_d<3>(T, st, coords, ids, m, true, &dummy);
-    case 4: return update_d<4>(T, st, coords, ids, m, true, &dummy);
-    case 5: return update_d<5>(T, st, coords, ids, m, true, &dummy);
-    case 6: return update_d<6>(T, st, coords, ids, m, true, &dummy);
-    case 7: return update_d<7>(T, st, coords, ids, m, true, &dummy);
+    case 1: return update_d<1>(T, tree, st, coords, ids, m, true, &dummy);
+    case 2: return update_d<2>(T, tree, st, coords, ids, m, true, &dummy);
+    case 3: return update_d<3>(T, tree, st, coords, ids, m, true, &dummy);
+    case 4: return update_d<4>(T, tree, st, coords, ids, m, true, &dummy);
+    case 5: return update_d<5>(T, tree, st, coords, ids, m, true, &dummy);
+    case 6: return update_d<6>(T, tree, st, coords, ids, m, true, &dummy);
+    case 7: return update_d<7>(T, tree, st, coords, ids, m, true, &dummy);
   }
   return PKD_ERR_UNSUPPORTED;
 }
 
-int run_delete(pkd_tree* T, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m, int64_t* removed) {
+int run_delete(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t m,
+               int64_t* removed) {
   *removed = 0;
   switch (T->prm.D) {
-    case 1: return update_d<1>(T, st, coords, ids, m, false, removed);
-    case 2: return update_d<2>(T, st, coords, ids, m, false, removed);
-    case 3: return update_d<3>(T, st, coords, ids, m, false, removed);
-    case 4: return update_d<4>(T, st, coords, ids, m, false, removed);
-    case 5: return update_d<5>(T, st, coords, ids, m, false, removed);
-    case 6: return update_d<6>(T, st, coords, ids, m, false, removed);
-    case 7: return update_d<7>(T, st, coords, ids, m, false, removed);
+    case 1: return update_d<1>(T, tree, st, coords, ids, m, false, removed);
+    case 2: return update_d<2>(T, tree, st, coords, ids, m, false, removed);
+    case 3: return update_d<3>(T, tree, st, coords, ids, m, false, removed);
+    case 4: return update_d<4>(T, tree, st, coords, ids, m, false, removed);
+    case 5: return update_d<5>(T, tree, st, coords, ids, m, false, removed);
+    case 6: return update_d<6>(T, tree, st, coords, ids, m, false, removed);
+    case 7: return update_d<7>(T, tree, st, coords, ids, m, false, removed);
   }
   return PKD_ERR_UNSUPPORTED;
 }

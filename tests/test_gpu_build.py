@@ -229,8 +229,16 @@ def test_batch_build_equals_single_builds(orc, pk):
         ref = orc.brute_range_count(np.ascontiguousarray(c[:, a:b]), np.ascontiguousarray(lo[:, sel]),
                                     np.ascontiguousarray(hi[:, sel]))
         assert np.array_equal(got[sel], ref), t
+    # updates go to one tree of the handle (tree 0 here); the others stay
+    extra_c, extra_i = c[:, :5].copy(), i[:5] + 10 ** 9
+    B.insert(extra_c, extra_i, tree=0)
+    a, b = offsets[0], offsets[1]
+    ot = orc.Tree(orc.Params(3), np.ascontiguousarray(c[:, a:b]), i[a:b])
+    ot.insert(extra_c, extra_i)
+    for x, y in zip(B.export(0), ot.export()):
+        assert np.array_equal(x, y)
     with pytest.raises(pk.PkdError):
-        B.insert(c[:, :5].copy(), i[:5] + 10 ** 9)
+        B.insert(extra_c, extra_i + 1, tree=60)     # no such tree
 
 
 # ------------------------------------------------ large batches (spatial order)
