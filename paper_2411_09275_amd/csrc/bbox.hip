@@ -65,7 +65,7 @@ __global__ void k_bb_level(const Node* nodes, const uint32_t* order, int32_t cou
       for (int32_t i = 0; i < nd.size; ++i) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          const int32_t c = C32[d * cap + nd.off + i];
+          const int32_t c = C32[(static_cast<int64_t>(nd.off) + i) * D + d];
           lo[d] = min(lo[d], c);
           hi[d] = max(hi[d], c);
         }

@@ -70,15 +70,6 @@ __device__ inline int route(const int64_t (&c)[D], const int64_t* sx, const uint
   return v - (1 << lambda);
 }
 
-// Workgroups are handed to the 8 XCDs round robin (workgroup b runs on XCD
-// b % 8).  This maps workgroup b to a tile so that each XCD takes one
-// contiguous range of tiles: neighbouring tiles, whose output runs share
-// cache lines at their ends, then meet in the same L2.  Bijective on
-// [0, n) for any n.
-__device__ inline int64_t xcd_tile(int64_t b, int64_t n) {
-  const int64_t x = b & 7, per = n >> 3, rem = n & 7;
-  return x * per + (x < rem ? x : rem) + (b >> 3);
-}
 
 __device__ inline int find_owner(const int64_t* off, int n, int64_t t) {
   // largest s with off[s] <= t
@@ -1342,7 +1333,7 @@ __global__ void __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(NPL
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         Y[d * ycap + q.start + p] = static_cast<int64_t>(C[d * P + e]);
-        bufs.c32[d * bufs.c32cap + q.start + p] = static_cast<int32_t>(C[d * P + e]);
+        bufs.c32[(static_cast<int64_t>(q.start) + p) * D + d] = static_cast<int32_t>(C[d * P + e]);
       }
       Iout[p] = idv[r];
     }
@@ -1368,7 +1359,7 @@ __global__ void k_finish_heavy(const Task* tasks, const int* list, int D, Bufs b
     for (int d = 0; d < D; ++d) {
       const int64_t v = bufs.c[src][d * bufs.cap[src] + q.start + i];
       if (src != final_buf) bufs.c[final_buf][d * bufs.cap[final_buf] + q.start + i] = v;
-      bufs.c32[d * bufs.c32cap + q.start + i] = static_cast<int32_t>(v);
+      bufs.c32[(static_cast<int64_t>(q.start) + i) * D + d] = static_cast<int32_t>(v);
     }
     if (src != final_buf) bufs.id[final_buf][q.start + i] = bufs.id[src][q.start + i];
   }
@@ -2179,7 +2170,7 @@ __global__ void k_make_c32(const int64_t* X, int64_t cap, int64_t n, int32_t* c3
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
 #pragma unroll
-    for (int d = 0; d < D; ++d) c32[d * cap + i] = static_cast<int32_t>(X[d * cap + i]);
+    for (int d = 0; d < D; ++d) c32[i * D + d] = static_cast<int32_t>(X[d * cap + i]);
 }
 }  // namespace
 

@@ -63,7 +63,7 @@ struct Bufs {
   int64_t* c[3];
   int64_t* id[3];
   int64_t cap[3];
-  int32_t* c32;    // the tree's packed 32-bit coordinates [D][c32cap] (written by the finisher)
+  int32_t* c32;    // the tree's packed 32-bit coordinates [c32cap][D], point by point (written by the finisher)
   int64_t c32cap;
 };
 
@@ -75,6 +75,17 @@ struct Params {
   int tile;
   int cand_bias;   // test knob: shifts every candidate threshold (results unchanged)
 };
+
+// Workgroups are handed to the 8 XCDs round robin (workgroup b runs on XCD
+// b % 8), and each XCD has its own L2.  This maps workgroup b to a work item
+// (a sieve tile, a block of spatially ordered queries) so that each XCD takes
+// one contiguous range of them: neighbouring items, which share cache lines
+// (the ends of bucket runs, the nodes and leaves of nearby queries), then
+// meet in the same L2.  Bijective on [0, n) for any n.
+__device__ inline int64_t xcd_tile(int64_t b, int64_t n) {
+  const int64_t x = b & 7, per = n >> 3, rem = n & 7;
+  return x * per + (x < rem ? x : rem) + (b >> 3);
+}
 
 // Device-side error flags (bitmask in one int).
 enum : int {
@@ -94,8 +105,10 @@ struct pkd_tree {
   int64_t cap = 0;        // capacity of each point buffer
   int64_t* buf[2] = {nullptr, nullptr};  // buf[cur] holds the tree's points; the other is the twin
   int cur = 0;
-  // coordinates of buf[cur] as int32 [D][cap] (coordinates are below 2^30):
-  // what the query kernels scan, at half the bytes of the int64 rows
+  // coordinates of buf[cur] as int32 [cap][D], the D coordinates of a point
+  // side by side (coordinates are below 2^30): what the query kernels scan,
+  // at half the bytes of the int64 rows and with a leaf's points in few
+  // cache lines
   int32_t* c32 = nullptr;
   int64_t c32_cap = 0;
   // the second packed copy an update writes its new layout into (swapped

@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(kQBlock) __attribute__((amdgpu_waves_per_eu(KM
         for (int d = 0; d < D; ++d) {
 #pragma unroll
           for (int u = 0; u < LB; ++u) {
-            const int32_t diff = C32[d * cap + i + u] - q[d];
+            const int32_t diff = C32[(i + u) * D + d] - q[d];
             d2[u] += static_cast<int64_t>(diff) * diff;
           }
         }
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(kQBlock) __attribute__((amdgpu_waves_per_eu(KM
         int64_t d2 = 0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          const int32_t diff = C32[d * cap + i] - q[d];
+          const int32_t diff = C32[i * D + d] - q[d];
           d2 += static_cast<int64_t>(diff) * diff;
         }
         consider(d2, i);
@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(kQBlock) k_knn_wave(const Node* __restrict__ n
             int64_t s = 0;
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-              const int32_t diff = C32[d * cap + i] - q[d];
+              const int32_t diff = C32[i * D + d] - q[d];
               s += static_cast<int64_t>(diff) * diff;
             }
             if (s <= wd) {
@@ -588,7 +588,7 @@ __device__ inline int64_t count_in_box(const int32_t* __restrict__ C32, int64_t 
     for (int d = 0; d < D; ++d) {
 #pragma unroll
       for (int u = 0; u < kLeafBatch; ++u) {
-        const int32_t v = C32[d * cap + i + u];
+        const int32_t v = C32[(i + u) * D + d];
         in[u] &= v >= lo[d] && v <= hi[d];
       }
     }
@@ -600,7 +600,7 @@ __device__ inline int64_t count_in_box(const int32_t* __restrict__ C32, int64_t 
     bool in = true;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      const int32_t v = C32[d * cap + i];
+      const int32_t v = C32[i * D + d];
       in &= v >= lo[d] && v <= hi[d];
     }
     c += in ? 1 : 0;

@@ -141,7 +141,7 @@ __device__ inline bool point_in(const int32_t* __restrict__ C32, int64_t cap, in
   bool in = true;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    const int32_t v = C32[d * cap + i];
+    const int32_t v = C32[i * D + d];
     in &= v >= lo[d] && v <= hi[d];
   }
   return in;

@@ -495,7 +495,7 @@ __global__ void k_relayout(const int64_t* X, int64_t xcap, int64_t n, const int3
     for (int d = 0; d < D; ++d) {
       const int64_t v = X[d * xcap + o];
       Y[d * ycap + dst] = v;
-      C32[d * ycap + dst] = static_cast<int32_t>(v);
+      C32[dst * D + d] = static_cast<int32_t>(v);
     }
     Y[D * ycap + dst] = X[D * xcap + o];
   }
@@ -600,7 +600,7 @@ __global__ void k_scatter_back(const Region* regions, const int64_t* comp, int n
     for (int d = 0; d < D; ++d) {
       const int64_t v = Z[d * zcap + p];
       Y[d * ycap + dst] = v;
-      C32[d * ycap + dst] = static_cast<int32_t>(v);
+      C32[dst * D + d] = static_cast<int32_t>(v);
     }
     Y[D * ycap + dst] = Z[D * zcap + p];
   }
