@@ -1728,8 +1728,11 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
   bool first = true;
 
   int rounds = 0;
+  static const char* const kRoundNames[] = {"sieve round 1", "sieve round 2", "sieve round 3", "sieve round 4",
+                                             "sieve round 5", "sieve round 6", "sieve round 7", "sieve round 8+"};
   while (n_front > 0) {
     if (++rounds > 200) return PKD_ERR_INTERNAL;   // every round shrinks every subproblem
+    TraceRange tr(kRoundNames[std::min(rounds, 8) - 1]);
     PKD_TRY(fin.need(static_cast<size_t>(n_fin) + n_front + 1, true));
     PKD_TRY(sieve.need(n_front));
     PKD_HIP(hipMemsetAsync(d_nsieve, 0, sizeof(int), st));
@@ -1842,6 +1845,7 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
 
   // finisher over every small subproblem, by size class
   if (n_fin > 0) {
+    TraceRange tr("finisher");
     PKD_TRY(lists.need(static_cast<size_t>(8) * n_fin + 8));
     int* d_counts = ctr.p + 8;
     PKD_HIP(hipMemsetAsync(d_counts, 0, sizeof(int) * 8, st));

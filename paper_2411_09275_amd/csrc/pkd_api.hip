@@ -423,6 +423,7 @@ void pkd_default_tuning(pkd_tuning* t) {
 
 int pkd_build(const pkd_params* params, const pkd_tuning* tuning, void* stream, const int64_t* coords,
               const int64_t* ids, int64_t n, pkd_tree** out) {
+  TraceRange tr("pkd_build");
   if (!out) return PKD_ERR_INVALID_ARG;
   *out = nullptr;
   Params prm;
@@ -434,6 +435,7 @@ int pkd_build(const pkd_params* params, const pkd_tuning* tuning, void* stream, 
 
 int pkd_knn_batch(const pkd_tree* tree, void* stream, const int64_t* queries, const int32_t* tree_of, int64_t nq,
                   int32_t k, int64_t* out_ids, int64_t* out_d2) {
+  TraceRange tr("pkd_knn");
   if (!tree || nq < 0 || k < 1 || k > 128) return PKD_ERR_INVALID_ARG;
   if (nq == 0) return PKD_OK;
   if (!queries || !out_ids || !out_d2) return PKD_ERR_INVALID_ARG;
@@ -488,6 +490,7 @@ int pkd_knn_noalloc(const pkd_tree* tree, void* stream, const int64_t* queries, 
 
 int pkd_range_count_batch(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi,
                           const int32_t* tree_of, int64_t nb, int64_t* out) {
+  TraceRange tr("pkd_range_count");
   if (!tree || nb < 0) return PKD_ERR_INVALID_ARG;
   if (nb == 0) return PKD_OK;
   if (!lo || !hi || !out) return PKD_ERR_INVALID_ARG;
@@ -509,6 +512,7 @@ int pkd_range_count(const pkd_tree* tree, void* stream, const int64_t* lo, const
 int pkd_range_report_batch(const pkd_tree* tree, void* stream, const int64_t* lo, const int64_t* hi,
                            const int32_t* tree_of, int64_t nb, int64_t* offsets, int64_t* out_ids, int64_t cap,
                            int64_t* total) {
+  TraceRange tr("pkd_range_report");
   if (total) *total = 0;
   if (!tree || nb < 0 || cap < 0 || !total) return PKD_ERR_INVALID_ARG;
   if (nb > 0 && (!lo || !hi)) return PKD_ERR_INVALID_ARG;
@@ -530,6 +534,7 @@ int pkd_range_report(const pkd_tree* tree, void* stream, const int64_t* lo, cons
 
 int pkd_build_batch(const pkd_params* params, const pkd_tuning* tuning, void* stream, int32_t n_trees,
                     const int64_t* coords, const int64_t* ids, const int64_t* offsets, pkd_tree** out) {
+  TraceRange tr("pkd_build_batch");
   if (!out) return PKD_ERR_INVALID_ARG;
   *out = nullptr;
   Params prm;
@@ -594,6 +599,7 @@ int pkd_num_trees(const pkd_tree* tree, int32_t* n_trees) {
 
 int pkd_batch_insert_tree(pkd_tree* tree, int32_t t, void* stream, const int64_t* coords, const int64_t* ids,
                           int64_t m) {
+  TraceRange tr("pkd_batch_insert");
   if (!tree || m < 0 || t < 0 || t >= tree->n_trees) return PKD_ERR_INVALID_ARG;
   if (m == 0) return PKD_OK;
   if (!coords || !ids) return PKD_ERR_INVALID_ARG;
@@ -607,6 +613,7 @@ int pkd_batch_insert(pkd_tree* tree, void* stream, const int64_t* coords, const 
 
 int pkd_batch_delete_tree(pkd_tree* tree, int32_t t, void* stream, const int64_t* coords, const int64_t* ids,
                           int64_t m, int64_t* n_deleted) {
+  TraceRange tr("pkd_batch_delete");
   if (n_deleted) *n_deleted = 0;
   if (!tree || m < 0 || t < 0 || t >= tree->n_trees) return PKD_ERR_INVALID_ARG;
   if (m == 0) return PKD_OK;

@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/pkd.h"
 
 namespace pkd {
@@ -293,6 +295,15 @@ int run_range(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_
 // Range report (report.hip): counts, offsets and (with out_ids) the ids.
 int run_range_report(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t* hi, const int32_t* tree_of,
                      int64_t nb, int64_t* offsets, int64_t* out_ids, int64_t cap, int64_t* total);
+
+// A named range for profilers (roctx): shown around the library's calls and
+// the rounds of a build in a rocprofv3 trace with --marker-trace.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // Per-kernel timing (pkd_profile_*): Prof::begin/end bracket one launch with
 // events on its stream; the elapsed time is collected at the next flush.
