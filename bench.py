@@ -48,9 +48,9 @@ def parse():
                              "alpha_sweep", "sliding_window", "pkd_bb", "ablation"],
                     help="build: the headline (1e8 3-D build + queries); batching: 4096 trees in one pass")
     ap.add_argument("--serve-n", type=int, default=1_000_000_000, help="points of the resident serving tree")
-    ap.add_argument("--requests", type=int, default=100, help="requests in the serving stream")
-    ap.add_argument("--load", type=float, default=0.8,
-                    help="offered Poisson rate as a fraction of the serial handler's capacity")
+    ap.add_argument("--requests", type=int, default=300, help="requests in the serving stream")
+    ap.add_argument("--loads", default="0.5,0.8,0.95",
+                    help="offered Poisson rates as fractions of the serial handler's capacity")
     ap.add_argument("--batch", type=int, default=1_000_000, help="points per BatchInsert / BatchDelete (updates)")
     ap.add_argument("--trees", type=int, default=4096)
     ap.add_argument("--batches", type=int, default=1000, help="alpha_sweep: batches the stream is cut into")
@@ -317,10 +317,11 @@ def bench_serving(a):
     """A resident tree of 1e9 hashed-uniform 2-D points answers a Poisson stream
     of BatchInsert / BatchDelete / k-NN requests (1:1:8; update sizes
     log-uniform in [1e3, 1e7], query batches in [1e2, 1e6], k in {1, 10, 100}).
-    Four passes over the same stream, each on a freshly built tree: serial and
-    continuous with every request waiting at time 0 (throughput), then serial
-    and continuous with Poisson arrivals at `load` x the serial capacity
-    (p50 / p99 latency).  Every pass must give identical results."""
+    Passes over the same stream, each on a freshly built tree: serial and
+    continuous with every request waiting at time 0 (throughput), then, for
+    each offered load, serial and continuous with Poisson arrivals at that
+    fraction of the serial capacity (p50 / p99 latency).  Every pass must give
+    identical results."""
     import torch
     import xxhash
 
@@ -384,10 +385,16 @@ def bench_serving(a):
         one_pass("continuous", False, 1.0)
     span_sc, _, dig_sc, _ = one_pass("serial", False, 1.0)
     span_cc, lat_cc, dig_cc, nb_cc = one_pass("continuous", False, 1.0)
-    rate = a.load * len(raw) / span_sc
-    span_sr, lat_sr, dig_sr, _ = one_pass("serial", True, rate)
-    span_cr, lat_cr, dig_cr, nb_cr = one_pass("continuous", True, rate)
-    same = dig_sc == dig_cc == dig_sr == dig_cr
+    same = dig_sc == dig_cc
+    opened = []
+    for load in [float(x) for x in a.loads.split(",")]:
+        rate = load * len(raw) / span_sc
+        span_sr, lat_sr, dig_sr, _ = one_pass("serial", True, rate)
+        span_cr, lat_cr, dig_cr, nb_cr = one_pass("continuous", True, rate)
+        same = same and dig_sr == dig_sc and dig_cr == dig_sc
+        opened.append({"load_vs_serial_capacity": load, "rate_per_s": round(rate, 3),
+                       "serial": lat_sr, "continuous": lat_cr, "continuous_batches": nb_cr,
+                       "serial_makespan_s": round(span_sr, 4), "continuous_makespan_s": round(span_cr, 4)})
     n_upd = sum(r["coords"].shape[1] for r in raw if r["kind"] != "knn")
     n_q = sum(r["coords"].shape[1] for r in raw if r["kind"] == "knn")
     out = {
@@ -405,9 +412,7 @@ def bench_serving(a):
         "closed": {"serial_s": round(span_sc, 4), "continuous_s": round(span_cc, 4),
                    "speedup": round(span_sc / span_cc, 3), "continuous_batches": nb_cc,
                    "items_per_s": round((n_upd + n_q) / span_cc, 1)},
-        "open": {"rate_per_s": round(rate, 3), "load_vs_serial_capacity": a.load,
-                 "serial": lat_sr, "continuous": lat_cr, "continuous_batches": nb_cr,
-                 "serial_makespan_s": round(span_sr, 4), "continuous_makespan_s": round(span_cr, 4)},
+        "open": opened,
         "identical_results": same,
     }
     print(json.dumps(out))

@@ -28,9 +28,13 @@ a few copy threads (the copy is bound by the first touch of those fresh
 pages); it overlaps the next batches' transfers and kernels instead of
 holding up the issuing loop.  A batch stays in flight,
 holding its slot, until its copy is done.  Requests that arrive while batches
-are in flight join the next batch.  An update first waits for the batches in
-flight to finish (it rewrites the tree), then runs on the compute stream with
-the blocking calls.
+are in flight join the next batch.  An update runs on the compute stream with
+the blocking calls as soon as it reaches the front of the queue, without
+draining the batches in flight: their k-NN kernels precede it on the compute
+stream, so they have read the tree before the update's first kernel rewrites
+it, while their downloads and copy-outs go on beside the update.  Should the
+update run out of device memory (it then leaves the tree as it was), the
+batches in flight are retired, releasing their buffers, and it runs again.
 
 The serial reference (mode "serial") handles each request alone, in arrival
 order, with the blocking calls.
@@ -138,9 +142,8 @@ class Server:
         return self.inflight_bytes + need <= limit
 
     # ---------------------------------------------------------------- work
-    def _run_update(self, r, now):
+    def _apply(self, r):
         torch = self.torch
-        r.start = now()
         with torch.cuda.stream(self.compute):
             c = torch.from_numpy(np.ascontiguousarray(r.coords)).cuda()
             i = torch.from_numpy(np.ascontiguousarray(r.ids)).cuda()
@@ -148,6 +151,18 @@ class Server:
                 self.tree.insert(c, i, stream=self.compute)
             else:
                 r.result = self.tree.delete(c, i, stream=self.compute)
+
+    def _run_update(self, r, now, inflight=None):
+        from . import PkdError
+        r.start = now()
+        try:
+            self._apply(r)
+        except PkdError as e:
+            if e.code != -4 or not inflight:          # -4: PKD_ERR_OOM
+                raise
+            while inflight:                           # the tree is unchanged: free what the batches hold
+                self._retire(inflight.popleft())
+            self._apply(r)
         self.compute.synchronize()
         r.done = now()
 
@@ -305,9 +320,7 @@ class Server:
                         time.sleep(min(wait, 1e-3))
                 continue
             if ready[0].kind != "knn":
-                while inflight:
-                    self._retire(inflight.popleft())
-                self._run_update(ready.popleft(), now)
+                self._run_update(ready.popleft(), now, inflight)
                 continue
             if len(inflight) >= self.max_inflight:
                 self._retire(inflight.popleft())

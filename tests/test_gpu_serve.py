@@ -123,3 +123,45 @@ def test_device_error_reaches_the_caller(pk):
     with pytest.raises(RuntimeError):
         Server(t, D).run(reqs, mode="continuous", realtime=False)
     t.free()
+
+
+def test_update_out_of_memory_with_batches_in_flight(orc, pk):
+    # an update no longer drains the batches in flight; when it runs out of
+    # device memory (forced here: the allocation after arming returns NULL) the
+    # tree is unchanged, the server retires the batches and runs it again
+    import torch
+    from paper_2411_09275_amd.serve import Server
+    dev = torch.cuda.current_device()
+    state = {"armed": False, "failed": 0}
+
+    def alloc(n, stream):
+        if state["armed"]:
+            state["armed"] = False
+            state["failed"] += 1
+            return 0
+        return torch.cuda.caching_allocator_alloc(n, dev, stream)
+
+    def free(p, n, stream):
+        torch.cuda.caching_allocator_delete(p)
+
+    class ArmedServer(Server):
+        def _run_update(self, r, now, inflight=None):
+            state["armed"] = bool(inflight)
+            try:
+                super()._run_update(r, now, inflight)
+            finally:
+                state["armed"] = False
+
+    reqs = _stream(seed=9, n=40)
+    c, i = _initial()
+    pk.set_allocator(alloc, free)
+    try:
+        t = pk.Tree(pk.Params(D), c, i)
+        print("updates fail once with batches in flight", flush=True)
+        with ArmedServer(t, D, max_batch_queries=400) as s:
+            s.run(reqs, mode="continuous", realtime=False)
+        t.free()
+    finally:
+        pk.set_allocator()
+    assert state["failed"] >= 1
+    _check_against(reqs, _oracle_replay(orc, reqs))
