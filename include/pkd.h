@@ -24,9 +24,11 @@
  *     point, query and output pointers given to a call are DEVICE pointers
  *     owned by the caller; the library only reads inputs and only writes
  *     outputs during the call's stream work.
- *   - Coordinates (points, queries, box corners) must lie in [0, 2^30); this
- *     keeps squared distances exact in int64 for dim <= 7.  Violations return
- *     PKD_ERR_RANGE and leave any tree unchanged.
+ *   - Coordinates (points, queries, box corners) must lie in [0, 2^30), and
+ *     point and query coordinates for dim = 9 in [0, 1012333500): squared
+ *     distances, sums of dim squared differences, are then exact in int64
+ *     (dim * (bound - 1)^2 < 2^63).  Violations return PKD_ERR_RANGE and leave
+ *     any tree unchanged.
  *   - Ids are caller-chosen int64 values and must be unique within a tree
  *     (precondition; not checked).
  *   - A tree owns its device storage.  The library takes device memory from
@@ -53,8 +55,8 @@ extern "C" {
 
 #define PKD_OK 0
 #define PKD_ERR_INVALID_ARG (-1)   /* null pointer, negative count, bad parameter */
-#define PKD_ERR_RANGE (-2)         /* a coordinate outside [0, 2^30) */
-#define PKD_ERR_UNSUPPORTED (-3)   /* dim outside 1..7, sample size > 2048, n >= 2^31 */
+#define PKD_ERR_RANGE (-2)         /* a coordinate outside its bound (see above) */
+#define PKD_ERR_UNSUPPORTED (-3)   /* dim outside 1..9, sample size > 2048, n >= 2^31 */
 #define PKD_ERR_OOM (-4)           /* device allocation failed */
 #define PKD_ERR_HIP (-5)           /* a HIP runtime call failed */
 #define PKD_ERR_CAPACITY (-6)      /* a query needs a deeper traversal stack than built in */
@@ -64,7 +66,7 @@ typedef struct pkd_tree pkd_tree;   /* opaque; device-resident */
 
 /* Parameters that change the tree (Section 5 gives the defaults). */
 typedef struct {
-  int32_t dim;        /* D, 1..7 */
+  int32_t dim;        /* D, 1..9 */
   int32_t lambda;     /* skeleton levels per sieve round (lambda), 1..8; default 6 */
   int32_t leaf_size;  /* leaf wrap phi: a leaf holds at most phi points unless all
                          its points are identical (heavy leaf); default 32 */
@@ -251,7 +253,7 @@ int pkd_range_report_batch(const pkd_tree* tree, void* stream, const int64_t* lo
  * overlap work (a serving loop): the kernel is enqueued on `stream` and the
  * call returns without synchronizing.  Data-dependent errors are ORed into
  * *status (device int32, zeroed by the caller beforehand) instead of being
- * returned: 1 = a coordinate outside [0, 2^30), 16 = traversal stack too
+ * returned: 1 = a coordinate outside its bound, 16 = traversal stack too
  * small, 32 = inconsistent tree or tree index.  Outputs and *status are valid
  * once the stream reaches this point.  The tree must not be modified until then.
  */

@@ -135,6 +135,8 @@ int compute_bbox(pkd_tree* T, hipStream_t st) {
     case 5: return compute_bbox_d<5>(T, st);
     case 6: return compute_bbox_d<6>(T, st);
     case 7: return compute_bbox_d<7>(T, st);
+    case 8: return compute_bbox_d<8>(T, st);
+    case 9: return compute_bbox_d<9>(T, st);
   }
   return PKD_ERR_UNSUPPORTED;
 }

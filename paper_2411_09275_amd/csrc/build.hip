@@ -742,7 +742,7 @@ __global__ void __launch_bounds__(kBlock) k_count(const Task* sp, int ns, const 
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       c[d] = X[d * cap + i];
-      bad |= static_cast<uint64_t>(c[d]) >= static_cast<uint64_t>(kCoordLimit);
+      bad |= static_cast<uint64_t>(c[d]) >= static_cast<uint64_t>(coord_limit(D));
     }
     atomicAdd(&hist[route<D>(c, sx, sd, lambda)], 1u);
   }
@@ -1142,7 +1142,7 @@ __global__ void __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(NPL
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int64_t v = X[d * xcap + q.start + i];
-      bad |= static_cast<uint64_t>(v) >= static_cast<uint64_t>(kCoordLimit);
+      bad |= static_cast<uint64_t>(v) >= static_cast<uint64_t>(coord_limit(D));
       C[d * P + i] = static_cast<uint32_t>(v);
     }
     seg[i] = 0;
@@ -2197,7 +2197,7 @@ int refresh_c32(pkd_tree* T, hipStream_t st) {
   switch (T->prm.D) {
 #define PKD_C32(DD) \
   case DD: hipLaunchKernelGGL(k_make_c32<DD>, dim3(g), dim3(256), 0, st, T->buf[T->cur], T->cap, T->n, T->c32); break;
-    PKD_C32(1) PKD_C32(2) PKD_C32(3) PKD_C32(4) PKD_C32(5) PKD_C32(6) PKD_C32(7)
+    PKD_C32(1) PKD_C32(2) PKD_C32(3) PKD_C32(4) PKD_C32(5) PKD_C32(6) PKD_C32(7) PKD_C32(8) PKD_C32(9)
 #undef PKD_C32
     default: return PKD_ERR_UNSUPPORTED;
   }
@@ -2296,6 +2296,8 @@ int sieve_pass(hipStream_t st, int D, int lambda, int tile, const Task* tasks, i
     PKD_SIEVE_CASE(5)
     PKD_SIEVE_CASE(6)
     PKD_SIEVE_CASE(7)
+    PKD_SIEVE_CASE(8)
+    PKD_SIEVE_CASE(9)
 #undef PKD_SIEVE_CASE
   }
   return PKD_ERR_UNSUPPORTED;
@@ -2317,6 +2319,8 @@ int build_tasks(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, con
     case 5: return build_tasks_d<5>(T, st, roots, in_c, in_id, input_cap);
     case 6: return build_tasks_d<6>(T, st, roots, in_c, in_id, input_cap);
     case 7: return build_tasks_d<7>(T, st, roots, in_c, in_id, input_cap);
+    case 8: return build_tasks_d<8>(T, st, roots, in_c, in_id, input_cap);
+    case 9: return build_tasks_d<9>(T, st, roots, in_c, in_id, input_cap);
     default: return PKD_ERR_UNSUPPORTED;
   }
 }

@@ -13,11 +13,20 @@
 
 namespace pkd {
 
-constexpr int kMaxDim = 7;
+constexpr int kMaxDim = 9;
 constexpr int kMaxLambda = 8;
 constexpr int kMaxSample = 2048;                 // s = 2^lambda * sigma (LDS of the select and finisher kernels)
-constexpr int64_t kCoordLimit = int64_t{1} << 30;
+constexpr int64_t kCoordLimit = int64_t{1} << 30;   // 32-bit copies, splitters and box bounds
 constexpr int64_t kCoordMax = kCoordLimit - 1;
+// Exclusive bound of a point's (or query's) coordinates in D dimensions: below
+// 2^30, and small enough that D squared differences sum exactly in int64
+// (D * (limit - 1)^2 <= 2^63 - 1; only D = 9 is below 2^30).
+__host__ __device__ constexpr int64_t coord_limit(int D) {
+  return D <= 8 ? kCoordLimit : int64_t{1012333500};
+}
+static_assert((coord_limit(9) - 1) * (coord_limit(9) - 1) <= INT64_MAX / 9 &&
+                  coord_limit(9) * coord_limit(9) > INT64_MAX / 9,
+              "the largest bound for nine dimensions");
 constexpr int64_t kAllLeft = INT64_MAX;          // splitter that sends every point left
 constexpr int kMaxStack = 160;                   // traversal stack of the query kernels
 

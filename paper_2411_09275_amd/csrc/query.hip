@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(kQBlock) __attribute__((amdgpu_waves_per_eu(KM
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     const int64_t v = Qry[d * nq + j];
-    bad |= static_cast<uint64_t>(v) >= static_cast<uint64_t>(kCoordLimit);
+    bad |= static_cast<uint64_t>(v) >= static_cast<uint64_t>(coord_limit(D));
     q[d] = static_cast<int32_t>(v);
   }
   if (bad) {
@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(kQBlock) k_knn_wave(const Node* __restrict__ n
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int64_t v = Qry[d * nq + j];
-      bad |= static_cast<uint64_t>(v) >= static_cast<uint64_t>(kCoordLimit);
+      bad |= static_cast<uint64_t>(v) >= static_cast<uint64_t>(coord_limit(D));
       q[d] = static_cast<int32_t>(v);
     }
     if (bad) {
@@ -1175,6 +1175,8 @@ int run_knn_static(const pkd_tree* T, hipStream_t st, const int64_t* q, int64_t 
     case 5: rc = knn_static_d<5>(T, st, q, nq, k, oi, od, base, L); break;
     case 6: rc = knn_static_d<6>(T, st, q, nq, k, oi, od, base, L); break;
     case 7: rc = knn_static_d<7>(T, st, q, nq, k, oi, od, base, L); break;
+    case 8: rc = knn_static_d<8>(T, st, q, nq, k, oi, od, base, L); break;
+    case 9: rc = knn_static_d<9>(T, st, q, nq, k, oi, od, base, L); break;
   }
   if (rc != PKD_OK) return rc;
   int h = 0;
@@ -1196,6 +1198,8 @@ int run_knn(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_t* 
     case 5: return knn_d<5>(T, st, q, tree_of, nq, k, oi, od, flags);
     case 6: return knn_d<6>(T, st, q, tree_of, nq, k, oi, od, flags);
     case 7: return knn_d<7>(T, st, q, tree_of, nq, k, oi, od, flags);
+    case 8: return knn_d<8>(T, st, q, tree_of, nq, k, oi, od, flags);
+    case 9: return knn_d<9>(T, st, q, tree_of, nq, k, oi, od, flags);
   }
   return PKD_ERR_UNSUPPORTED;
 }
@@ -1210,6 +1214,8 @@ int run_range(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_
     case 5: return range_d<5>(T, st, lo, hi, tree_of, nb, out, flags);
     case 6: return range_d<6>(T, st, lo, hi, tree_of, nb, out, flags);
     case 7: return range_d<7>(T, st, lo, hi, tree_of, nb, out, flags);
+    case 8: return range_d<8>(T, st, lo, hi, tree_of, nb, out, flags);
+    case 9: return range_d<9>(T, st, lo, hi, tree_of, nb, out, flags);
   }
   return PKD_ERR_UNSUPPORTED;
 }

@@ -539,7 +539,7 @@ int run_range_report(const pkd_tree* T, hipStream_t st, const int64_t* lo, const
   case DD:                                                                                                \
     rc = report_walk_d<DD>(T, st, lo, hi, tree_of, nb, cnt.p, items.p, nitems.p, item_cap, nitems.p + 1, flags.p); \
     break;
-      PKD_RW(1) PKD_RW(2) PKD_RW(3) PKD_RW(4) PKD_RW(5) PKD_RW(6) PKD_RW(7)
+      PKD_RW(1) PKD_RW(2) PKD_RW(3) PKD_RW(4) PKD_RW(5) PKD_RW(6) PKD_RW(7) PKD_RW(8) PKD_RW(9)
 #undef PKD_RW
     }
     PKD_TRY(rc);

@@ -42,7 +42,7 @@ __global__ void k_validate(const int64_t* coords, int64_t m, int* flags) {
   bool bad = false;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < m;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    for (int d = 0; d < D; ++d) bad |= static_cast<uint64_t>(coords[d * m + i]) >= static_cast<uint64_t>(kCoordLimit);
+    for (int d = 0; d < D; ++d) bad |= static_cast<uint64_t>(coords[d * m + i]) >= static_cast<uint64_t>(coord_limit(D));
   if (bad) atomicOr(flags, kErrRange);
 }
 
@@ -1170,6 +1170,8 @@ int run_insert(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords,
     case 5: return update_d<5>(T, tree, st, coords, ids, m, true, &dummy);
     case 6: return update_d<6>(T, tree, st, coords, ids, m, true, &dummy);
     case 7: return update_d<7>(T, tree, st, coords, ids, m, true, &dummy);
+    case 8: return update_d<8>(T, tree, st, coords, ids, m, true, &dummy);
+    case 9: return update_d<9>(T, tree, st, coords, ids, m, true, &dummy);
   }
   return PKD_ERR_UNSUPPORTED;
 }
@@ -1185,6 +1187,8 @@ int run_delete(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords,
     case 5: return update_d<5>(T, tree, st, coords, ids, m, false, removed);
     case 6: return update_d<6>(T, tree, st, coords, ids, m, false, removed);
     case 7: return update_d<7>(T, tree, st, coords, ids, m, false, removed);
+    case 8: return update_d<8>(T, tree, st, coords, ids, m, false, removed);
+    case 9: return update_d<9>(T, tree, st, coords, ids, m, false, removed);
   }
   return PKD_ERR_UNSUPPORTED;
 }

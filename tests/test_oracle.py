@@ -812,3 +812,47 @@ def test_exact_median_mode_is_the_plain_construction(orc, D, n):
     rows, ids, _ = T.export()
     erows, eids = _plain_tree_by_definition(c, i, 32)
     assert np.array_equal(rows, erows) and np.array_equal(ids, eids)
+
+
+# ------------------------------------------------------------ nine dimensions
+BOUND9 = 1012333500     # exclusive coordinate bound for D = 9: 9 * (bound - 1)^2 < 2^63
+
+
+def test_nine_dim_bound_is_the_largest_exact_one():
+    # Python integers: the bound keeps nine squared differences below 2^63,
+    # one more does not
+    assert 9 * (BOUND9 - 1) ** 2 <= 2 ** 63 - 1 < 9 * BOUND9 ** 2
+
+
+def test_nine_dim_knn_and_counts_exact_at_the_bound(orc):
+    D, n = 9, 400
+    rng = np.random.default_rng(960)
+    c = rng.integers(0, BOUND9, size=(D, n), dtype=np.int64)
+    corner = rng.random((D, n)) < 0.5
+    c[:, ::3] = np.where(corner[:, ::3], 0, BOUND9 - 1)      # a third of the points at corners
+    i = rng.permutation(n).astype(np.int64) + 5
+    T, p = _build(orc, c, i, phi=4)
+    rows, ids, coords = T.export()
+    treecheck.check_tree(rows, ids, coords, p.phi, c, i)
+    q = rng.integers(0, BOUND9, size=(D, 40), dtype=np.int64)
+    q[:, 0] = 0
+    q[:, 1] = BOUND9 - 1
+    got_i, got_d = T.knn(q, 12)
+    pts = [[int(v) for v in c[:, j]] for j in range(n)]
+    for j in range(q.shape[1]):
+        qq = [int(v) for v in q[:, j]]
+        pairs = sorted((sum((a - b) ** 2 for a, b in zip(pt, qq)), int(i[t])) for t, pt in enumerate(pts))[:12]
+        assert [int(x) for x in got_d[j]] == [d for d, _ in pairs], j
+        assert [int(x) for x in got_i[j]] == [t for _, t in pairs], j
+    # every point from the two corner queries: the farthest are near 2^63
+    all_i, all_d = T.knn(np.ascontiguousarray(q[:, :2]), n)
+    for j in range(2):
+        qq = [int(v) for v in q[:, j]]
+        pairs = sorted((sum((a - b) ** 2 for a, b in zip(pt, qq)), int(i[t])) for t, pt in enumerate(pts))
+        assert [int(x) for x in all_d[j]] == [d for d, _ in pairs]
+        assert [int(x) for x in all_i[j]] == [t for _, t in pairs]
+        assert pairs[-1][0] > 2 ** 62
+    lo = rng.integers(0, BOUND9 // 2, size=(D, 30), dtype=np.int64)
+    hi = lo + rng.integers(BOUND9 // 3, BOUND9 // 2, size=(D, 30), dtype=np.int64)
+    want = [sum(all(lo[d, j] <= pts[t][d] <= hi[d, j] for d in range(D)) for t in range(n)) for j in range(30)]
+    assert list(T.range_count(lo, hi)) == want
