@@ -49,7 +49,7 @@ def test_defaults_and_strerror(L):
 def test_parameter_validation_before_any_device_work(L):
     import paper_2411_09275_amd as pk
     out = C.c_void_p()
-    bad = [dict(dim=0), dict(dim=8), dict(lambda_=0), dict(lambda_=9), dict(leaf_size=0), dict(oversample=0),
+    bad = [dict(dim=0), dict(dim=10), dict(lambda_=0), dict(lambda_=9), dict(leaf_size=0), dict(oversample=0),
            dict(alpha_num=5, alpha_den=10), dict(alpha_den=0), dict(oversample=65),
            dict(oversample=33), dict(lambda_=7, oversample=32), dict(lambda_=8, oversample=16),
            dict(dim=7, leaf_size=1)]
