@@ -1671,8 +1671,8 @@ int seg_exact_split(hipStream_t st, const Task* tasks, const int* list, int ns, 
 }
 
 template <int D>
-int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, const int64_t* in_c,
-                  const int64_t* in_id, int64_t in_cap) {
+int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, bool roots_on_device, int src_buf,
+                  const int64_t* in_c, const int64_t* in_id, int64_t in_cap) {
   const Params& P = T->prm;
   const int NB = 1 << P.lambda;
   const int nheap = 2 << P.lambda;
@@ -1718,10 +1718,12 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, c
   int* d_nrootext = ctr.p + 5;
   int* d_height = ctr.p + 6;
 
-  int n_front = static_cast<int>(roots.size());
+  int n_front = n_roots;
   PKD_TRY(front.need(n_front));
-  PKD_HIP(hipMemcpyAsync(front.p, roots.data(), sizeof(Task) * n_front, hipMemcpyHostToDevice, st));
-  int src = roots.empty() ? 2 : roots[0].buf;
+  if (n_front > 0)
+    PKD_HIP(hipMemcpyAsync(front.p, roots, sizeof(Task) * n_front,
+                           roots_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  int src = n_roots == 0 ? 2 : src_buf;
   int dst = 1 - F;
   int n_fin = 0;
   int node_count = T->node_count;
@@ -2308,21 +2310,28 @@ size_t build_lds_need(int D, int s, int phi) {
   return std::max(SkelLayout(D, P).end, FinLayout(D, P, phi).end);
 }
 
-int build_tasks(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, const int64_t* in_c,
-                const int64_t* in_id, int64_t input_cap) {
-  const int D = T->prm.D;
-  switch (D) {
-    case 1: return build_tasks_d<1>(T, st, roots, in_c, in_id, input_cap);
-    case 2: return build_tasks_d<2>(T, st, roots, in_c, in_id, input_cap);
-    case 3: return build_tasks_d<3>(T, st, roots, in_c, in_id, input_cap);
-    case 4: return build_tasks_d<4>(T, st, roots, in_c, in_id, input_cap);
-    case 5: return build_tasks_d<5>(T, st, roots, in_c, in_id, input_cap);
-    case 6: return build_tasks_d<6>(T, st, roots, in_c, in_id, input_cap);
-    case 7: return build_tasks_d<7>(T, st, roots, in_c, in_id, input_cap);
-    case 8: return build_tasks_d<8>(T, st, roots, in_c, in_id, input_cap);
-    case 9: return build_tasks_d<9>(T, st, roots, in_c, in_id, input_cap);
+namespace {
+int build_tasks_any(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, bool on_device, int src_buf,
+                    const int64_t* in_c, const int64_t* in_id, int64_t input_cap) {
+  switch (T->prm.D) {
+#define PKD_BT(DD) \
+  case DD: return build_tasks_d<DD>(T, st, roots, n_roots, on_device, src_buf, in_c, in_id, input_cap);
+    PKD_BT(1) PKD_BT(2) PKD_BT(3) PKD_BT(4) PKD_BT(5) PKD_BT(6) PKD_BT(7) PKD_BT(8) PKD_BT(9)
+#undef PKD_BT
     default: return PKD_ERR_UNSUPPORTED;
   }
+}
+}  // namespace
+
+int build_tasks(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, const int64_t* in_c,
+                const int64_t* in_id, int64_t input_cap) {
+  return build_tasks_any(T, st, roots.data(), static_cast<int>(roots.size()), false,
+                         roots.empty() ? 2 : roots[0].buf, in_c, in_id, input_cap);
+}
+
+int build_tasks_dev(pkd_tree* T, hipStream_t st, const Task* d_roots, int n_roots, int src_buf,
+                    const int64_t* in_c, const int64_t* in_id, int64_t input_cap) {
+  return build_tasks_any(T, st, d_roots, n_roots, true, src_buf, in_c, in_id, input_cap);
 }
 
 }  // namespace pkd

@@ -30,6 +30,14 @@ static_assert((coord_limit(9) - 1) * (coord_limit(9) - 1) <= INT64_MAX / 9 &&
 constexpr int64_t kAllLeft = INT64_MAX;          // splitter that sends every point left
 constexpr int kMaxStack = 160;                   // traversal stack of the query kernels
 
+// Orders the LDS accesses of one wave: what a lane wrote is seen by every
+// lane of the wave after this point.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Tree node, 32 bytes.  Subtrees are contiguous slices [off, off+size) of the
 // tree's point array (points are kept in in-order leaf order).
 struct Node {
@@ -263,6 +271,10 @@ int sieve_pass(hipStream_t st, int D, int lambda, int tile, const Task* tasks, i
 // buffer named by Task::buf; results go to tree->buf[tree->cur].
 int build_tasks(pkd_tree* tree, hipStream_t st, const std::vector<Task>& roots,
                 const int64_t* in_coords, const int64_t* in_ids, int64_t input_cap);
+// The same with the root tasks in device memory (n_roots of them, all in
+// buffer src_buf).
+int build_tasks_dev(pkd_tree* tree, hipStream_t st, const Task* d_roots, int n_roots, int src_buf,
+                    const int64_t* in_coords, const int64_t* in_ids, int64_t input_cap);
 int ensure_nodes(pkd_tree* tree, hipStream_t st, int64_t need);
 
 // Tree storage (pkd_api.hip): both point buffers for at least `cap` points;

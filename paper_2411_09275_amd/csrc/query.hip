@@ -294,14 +294,6 @@ struct WaveKnnLayout {
   }
 };
 
-// Orders the LDS accesses of one wave: what a lane wrote is seen by every
-// lane of the wave after this point.
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ inline int64_t shfl_xor_i64(int64_t v, int mask) {
   const int lo = __shfl_xor(static_cast<int>(static_cast<uint32_t>(v)), mask);
   const int hi = __shfl_xor(static_cast<int>(static_cast<uint64_t>(v) >> 32), mask);

@@ -333,14 +333,13 @@ __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
 // Replay of one routing round, top-down, with exact counts.  cnt(v) is the
 // weight of the batch slice below heap position v (1 per inserted point, 1 per
 // point actually removed); a killed task lies below a region.
-// For inserts (a region for every leaf that receives points) the decisions
-// run twice per round: apply = 0 only counts the regions each subproblem adds
-// (rcount[sig]) and writes nothing else; after an exclusive scan (roff),
-// apply = 1 makes the same decisions, updates the nodes and writes subproblem
-// sig's regions at n_regions + roff[sig] onwards, in a fixed order.  (A single
-// counter serialized millions of atomics when a batch touched millions of
-// leaves.)  Deletes add few regions and run apply = 1 alone with roff null:
-// one counter atomic per wave.
+// The decisions run twice per round: apply = 0 only counts the regions and the
+// recorded sizes each subproblem adds (rcount[sig], scount[sig]) and writes
+// nothing else; after exclusive scans (roff, soff), apply = 1 makes the same
+// decisions and writes subproblem sig's regions at n_regions + roff[sig] and
+// its sizes at n_sizes + soff[sig] onwards, in a fixed order.  (A counter
+// shared by all waves serialized tens of millions of atomics when a batch
+// touched millions of nodes.)
 __host__ __device__ inline size_t decide_lds_per_wave(int lambda) {
   return (static_cast<size_t>(2 << lambda) * (3 * sizeof(int32_t) + 1) + 15) & ~size_t{15};
 }
@@ -350,8 +349,9 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
                                                         const int32_t* child_idx, const int8_t* killed,
                                                         int8_t* killed_next, const int32_t* M, const Node* nodes,
                                                         int64_t an, int64_t ad, int insert, Region* regions,
-                                                        int* n_regions, int apply, int32_t* rcount, const int32_t* roff,
-                                                        int2* sizes, int* n_sizes) {
+                                                        const int* n_regions, int apply, int32_t* rcount,
+                                                        const int32_t* roff, int2* sizes, const int* n_sizes,
+                                                        int32_t* scount, const int32_t* soff) {
   const int NB = 1 << lambda, nheap = 2 << lambda;
   // per wave: cnt, s0, sz [nheap] int32, alive [nheap] bytes (dynamic LDS,
   // sized for this lambda)
@@ -359,39 +359,45 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int sig = blockIdx.x * kWaves + w;
   const bool active = sig < ns && !killed[sig];
+  if (!active) {
+    // every wave works in its own LDS slice and synchronizes only itself
+    if (!apply && lane == 0 && sig < ns) rcount[sig] = scount[sig] = 0;
+    return;
+  }
   unsigned char* mine = smem + static_cast<size_t>(w) * decide_lds_per_wave(lambda);
   int32_t* cnt = reinterpret_cast<int32_t*>(mine);
   int32_t* s0 = cnt + nheap;
   int32_t* sz = s0 + nheap;
   uint8_t* alive = reinterpret_cast<uint8_t*>(sz + nheap);
   const int32_t* hn = hn_all + static_cast<int64_t>(sig) * nheap;
-  if (active) {
-    for (int j = lane; j < NB; j += 64) {
-      const int32_t st = bstart[static_cast<int64_t>(sig) * NB + j];
-      const int32_t n = bsize[static_cast<int64_t>(sig) * NB + j];
-      s0[NB + j] = st;
-      sz[NB + j] = n;
-      cnt[NB + j] = M[st + n] - M[st];
-    }
-    for (int v = lane; v < nheap; v += 64) alive[v] = 0;
+  for (int j = lane; j < NB; j += 64) {
+    const int32_t st = bstart[static_cast<int64_t>(sig) * NB + j];
+    const int32_t n = bsize[static_cast<int64_t>(sig) * NB + j];
+    s0[NB + j] = st;
+    sz[NB + j] = n;
+    cnt[NB + j] = M[st + n] - M[st];
   }
-  __syncthreads();
+  for (int v = lane; v < nheap; v += 64) alive[v] = v == 1 ? 1 : 0;
+  wave_sync();
   for (int l = lambda - 1; l >= 0; --l) {
-    if (active) {
-      for (int v = (1 << l) + lane; v < (2 << l); v += 64) {
-        cnt[v] = cnt[2 * v] + cnt[2 * v + 1];
-        sz[v] = sz[2 * v] + sz[2 * v + 1];
-        s0[v] = s0[2 * v];
-      }
+    for (int v = (1 << l) + lane; v < (2 << l); v += 64) {
+      cnt[v] = cnt[2 * v] + cnt[2 * v + 1];
+      sz[v] = sz[2 * v] + sz[2 * v + 1];
+      s0[v] = s0[2 * v];
     }
-    __syncthreads();
+    wave_sync();
   }
-  if (active && lane == 0) alive[1] = 1;
-  __syncthreads();
   int added = 0;   // regions this wave has added so far (uniform)
-  const int32_t base = (apply && active && roff) ? *n_regions + roff[sig] : 0;
+  int sized = 0;   // sizes this wave has recorded so far (uniform)
+  const int32_t base = apply ? *n_regions + roff[sig] : 0;
+  const int32_t sbase = apply ? *n_sizes + soff[sig] : 0;
   for (int l = 0; l <= lambda; ++l) {
-    if (active) {
+    {
+      // a level without a live node ends the walk: nodes below it are
+      // reached only through live ones
+      bool any = false;
+      for (int v = (1 << l) + lane; v < (2 << l); v += 64) any |= alive[v] != 0;
+      if (__ballot(any) == 0) break;
       // every lane runs every step (the ballot keeps `added` uniform)
       for (int v0 = 1 << l; v0 < (2 << l); v0 += 64) {
         const int v = v0 + lane;
@@ -431,37 +437,25 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
         // new sizes are recorded, not written: the tree changes only once the
         // whole update has its memory (commit)
         const unsigned long long sm = __ballot(setsz);
-        if (apply && sm) {
-          const int leader = __ffsll(static_cast<long long>(sm)) - 1;
-          int at = 0;
-          if (lane == leader) at = atomicAdd(n_sizes, __popcll(sm));
-          at = __shfl(at, leader);
-          if (setsz) sizes[at + __popcll(sm & ((1ULL << lane) - 1))] = make_int2(u, newsz);
-        }
+        if (apply && setsz) sizes[sbase + sized + __popcll(sm & ((1ULL << lane) - 1))] = make_int2(u, newsz);
+        sized += __popcll(sm);
         const unsigned long long rm = __ballot(add);
-        if (apply && rm) {
-          const int rank = __popcll(rm & ((1ULL << lane) - 1));
-          if (roff) {
-            if (add) regions[base + added + rank] = reg;
-          } else {
-            // few regions (deletes add them only where balance breaks): one
-            // atomic per wave
-            const int leader = __ffsll(static_cast<long long>(rm)) - 1;
-            int at = 0;
-            if (lane == leader) at = atomicAdd(n_regions, __popcll(rm));
-            at = __shfl(at, leader);
-            if (add) regions[at + rank] = reg;
-          }
-        }
+        if (apply && add) regions[base + added + __popcll(rm & ((1ULL << lane) - 1))] = reg;
         added += __popcll(rm);
       }
     }
-    __syncthreads();
+    wave_sync();
   }
-  if (!apply && lane == 0 && sig < ns) rcount[sig] = active ? added : 0;
+  if (!apply && lane == 0) {
+    rcount[sig] = added;
+    scount[sig] = sized;
+  }
 }
 
-__global__ void k_add_regions(int* n_regions, const int32_t* roff, int ns) { *n_regions += roff[ns]; }
+__global__ void k_add_regions(int* n_regions, const int32_t* roff, int* n_sizes, const int32_t* soff, int ns) {
+  *n_regions += roff[ns];
+  *n_sizes += soff[ns];
+}
 
 // Region bookkeeping on the old positions: regid marks the points inside each
 // region; for inserts the size change of a region is noted at its end.  Grid
@@ -526,18 +520,38 @@ __global__ void k_node_update(Node* nodes, int32_t n_nodes, const int32_t* regid
   }
 }
 
-__global__ void k_region_final(Region* regions, const int32_t* S, int insert) {
-  Region& r = regions[blockIdx.x];
-  if (threadIdx.x != 0) return;
-  if (insert) {
-    // batch points are noted at region ends; for a region with old points
-    // the end lies after its start, for an empty one (an empty tree of a
-    // batch handle) on it, and its own batch points are not before it
-    r.new_start = r.a + (r.a < r.b ? S[r.a + 1] : S[r.a]);
-    r.new_size = (r.b - r.a) + (r.e - r.s);
-  } else {
-    r.new_start = r.a - S[r.a];
-    r.new_size = (r.b - r.a) - (S[r.b] - S[r.a]);
+__global__ void k_region_final(Region* regions, int n_regions, const int32_t* S, int insert, int32_t* new_size) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_regions; k += gridDim.x * blockDim.x) {
+    Region& r = regions[k];
+    if (insert) {
+      // batch points are noted at region ends; for a region with old points
+      // the end lies after its start, for an empty one (an empty tree of a
+      // batch handle) on it, and its own batch points are not before it
+      r.new_start = r.a + (r.a < r.b ? S[r.a + 1] : S[r.a]);
+      r.new_size = (r.b - r.a) + (r.e - r.s);
+    } else {
+      r.new_start = r.a - S[r.a];
+      r.new_size = (r.b - r.a) - (S[r.b] - S[r.a]);
+    }
+    new_size[k] = r.new_size;
+  }
+}
+
+// Root task of every region's rebuild (its points at comp[k] in the packed
+// gather, its subtree at the region node's depth) and the int64 offsets.
+__global__ void k_region_roots(const Region* regions, int n_regions, const int32_t* comp32, int64_t* comp,
+                               Task* roots) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= n_regions; k += gridDim.x * blockDim.x) {
+    comp[k] = comp32[k];
+    if (k == n_regions) continue;
+    Task t;
+    t.start = comp32[k];
+    t.m = regions[k].new_size;
+    t.slot = k;
+    t.depth = static_cast<int16_t>(regions[k].depth);
+    t.buf = 2;
+    t.mode = 0;
+    roots[k] = t;
   }
 }
 
@@ -656,6 +670,7 @@ struct RoundSave {
   DArr<Task> tasks;
   DArr<int32_t> hn, bsize, bstart, child;
   int ns = 0;
+  int lambda = 0;   // levels this round descends
   explicit RoundSave(hipStream_t s) : tasks(s), hn(s), bsize(s), bstart(s), child(s) {}
 };
 
@@ -780,46 +795,53 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     Task t0{0, static_cast<int32_t>(m), tree, root.depth, 0, 0};
     PKD_HIP(hipMemcpyAsync(cur.p, &t0, sizeof(Task), hipMemcpyHostToDevice, st));
     int ns = 1, src = 0;
+    int depth_r = root.depth;   // depth of this round's subproblem roots
     SieveWork W(st);
     SortRoute SR(st);
     while (ns > 0) {
-      // every round descends lambda levels of a tree no higher than T->height
-      if (static_cast<int64_t>(rounds.size()) > T->height / lambda + 4) return PKD_ERR_INTERNAL;
+      // every round descends at least one level of a tree no higher than T->height
+      if (static_cast<int64_t>(rounds.size()) > T->height + 4) return PKD_ERR_INTERNAL;
+      // lambda levels per round, fewer where the tree ends sooner (a round's
+      // per-subproblem arrays have 2^levels entries, and the last rounds hold
+      // the most subproblems)
+      const int lr = std::max(1, std::min(lambda, T->height - depth_r));
+      const int NBr = 1 << lr, nheapr = 2 << lr;
       RoundSave* R = new RoundSave(st);
       rounds.push_back(R);
       R->ns = ns;
+      R->lambda = lr;
       PKD_TRY(R->tasks.need(ns));
       PKD_HIP(hipMemcpyAsync(R->tasks.p, cur.p, sizeof(Task) * ns, hipMemcpyDeviceToDevice, st));
-      PKD_TRY(rx.need(static_cast<size_t>(ns) * NB));
-      PKD_TRY(rdim.need(static_cast<size_t>(ns) * NB));
+      PKD_TRY(rx.need(static_cast<size_t>(ns) * NBr));
+      PKD_TRY(rdim.need(static_cast<size_t>(ns) * NBr));
       PKD_TRY(mode.need(ns));
-      PKD_TRY(R->hn.need(static_cast<size_t>(ns) * nheap));
-      PKD_TRY(R->child.need(static_cast<size_t>(ns) * nheap));
+      PKD_TRY(R->hn.need(static_cast<size_t>(ns) * nheapr));
+      PKD_TRY(R->child.need(static_cast<size_t>(ns) * nheapr));
       PKD_HIP(hipMemsetAsync(mode.p, 0, ns, st));
       hipLaunchKernelGGL(k_fetch_skeleton, dim3((ns + kWaves - 1) / kWaves), dim3(64 * kWaves), 0, st, cur.p, ns,
-                         T->nodes, lambda, rx.p, rdim.p, R->hn.p);
+                         T->nodes, lr, rx.p, rdim.p, R->hn.p);
       PKD_TRY(kernel_status("k_fetch_skeleton"));
       const int dst = 1 - src;
-      PKD_TRY(R->bsize.need(static_cast<size_t>(ns) * NB));
-      PKD_TRY(R->bstart.need(static_cast<size_t>(ns) * NB));
+      PKD_TRY(R->bsize.need(static_cast<size_t>(ns) * NBr));
+      PKD_TRY(R->bstart.need(static_cast<size_t>(ns) * NBr));
       if (ns >= kSortRouteMin) {
-        PKD_TRY(route_by_sort<D>(st, cur.p, ns, m, wb, src, dst, rx.p, rdim.p, lambda, SR, R->bsize.p,
+        PKD_TRY(route_by_sort<D>(st, cur.p, ns, m, wb, src, dst, rx.p, rdim.p, lr, SR, R->bsize.p,
                                  R->bstart.p));
       } else {
         int64_t ntiles = 0, nchunks = 0, pts = 0;
         PKD_TRY(sieve_layout(st, cur.p, ns, P.tile, W, P.s, 0, nullptr, &ntiles, &nchunks, &pts));
-        PKD_TRY(sieve_pass(st, D, lambda, P.tile, cur.p, ns, wb, src, dst, rx.p, rdim.p, mode.p, W, ntiles, nchunks,
+        PKD_TRY(sieve_pass(st, D, lr, P.tile, cur.p, ns, wb, src, dst, rx.p, rdim.p, mode.p, W, ntiles, nchunks,
                            pts, 0, flags.p));
-        PKD_HIP(hipMemcpyAsync(R->bsize.p, W.bsize.p, sizeof(int32_t) * ns * NB, hipMemcpyDeviceToDevice, st));
-        PKD_HIP(hipMemcpyAsync(R->bstart.p, W.bstart.p, sizeof(int32_t) * ns * NB, hipMemcpyDeviceToDevice, st));
+        PKD_HIP(hipMemcpyAsync(R->bsize.p, W.bsize.p, sizeof(int32_t) * ns * NBr, hipMemcpyDeviceToDevice, st));
+        PKD_HIP(hipMemcpyAsync(R->bstart.p, W.bstart.p, sizeof(int32_t) * ns * NBr, hipMemcpyDeviceToDevice, st));
       }
-      PKD_TRY(nxt.need(static_cast<size_t>(ns) * NB));
+      PKD_TRY(nxt.need(static_cast<size_t>(ns) * NBr));
       PKD_TRY(n_go.need(ns));
       PKD_TRY(n_leaf.need(ns));
       PKD_TRY(off_go.need(ns + 1));
       PKD_TRY(off_leaf.need(ns + 1));
       const unsigned gw = static_cast<unsigned>((ns + kWaves - 1) / kWaves);
-      hipLaunchKernelGGL(k_route_count, dim3(gw), dim3(64 * kWaves), 0, st, cur.p, ns, T->nodes, lambda, R->hn.p,
+      hipLaunchKernelGGL(k_route_count, dim3(gw), dim3(64 * kWaves), 0, st, cur.p, ns, T->nodes, lr, R->hn.p,
                          R->bsize.p, R->bstart.p, n_go.p, n_leaf.p);
       PKD_TRY(kernel_status("k_route_count"));
       PKD_TRY(exscan_i32(st, n_go.p, off_go.p, ns, bsum));
@@ -827,12 +849,13 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
       int h[2];
       PKD_HIP(hipMemcpyAsync(&h[0], off_go.p + ns, sizeof(int), hipMemcpyDeviceToHost, st));
       PKD_HIP(hipMemcpyAsync(&h[1], off_leaf.p + ns, sizeof(int), hipMemcpyDeviceToHost, st));
-      hipLaunchKernelGGL(k_route_emit, dim3(gw), dim3(64 * kWaves), 0, st, cur.p, ns, T->nodes, lambda, R->hn.p,
+      hipLaunchKernelGGL(k_route_emit, dim3(gw), dim3(64 * kWaves), 0, st, cur.p, ns, T->nodes, lr, R->hn.p,
                          R->bsize.p, R->bstart.p, dst, off_go.p, off_leaf.p, nres, nxt.p, R->child.p, res.p);
       PKD_TRY(kernel_status("k_route_emit"));
       PKD_HIP(hipStreamSynchronize(st));
       ns = h[0];
       nres += h[1];
+      depth_r += lr;
       std::swap(cur.p, nxt.p);
       std::swap(cur.cap, nxt.cap);
       src = dst;
@@ -877,11 +900,11 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
   DArr<Region> regions(st);
   DArr<int2> sizes(st);
   DArr<int8_t> killed(st), killed_next(st);
-  DArr<int32_t> rcount(st), roff(st);
+  DArr<int32_t> rcount(st), roff(st), scount(st), soff(st);
   PKD_TRY(regions.need(static_cast<size_t>(m) + 1));
   {
     size_t most = 2;
-    for (auto* R : rounds) most += static_cast<size_t>(R->ns) * nheap;
+    for (auto* R : rounds) most += static_cast<size_t>(R->ns) * (2 << R->lambda);
     PKD_TRY(sizes.need(most));
   }
   int* d_sizes = ctr.p + 3;
@@ -906,23 +929,25 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
       const int nn = r + 1 < rounds.size() ? rounds[r + 1]->ns : 0;
       PKD_TRY(killed_next.need(static_cast<size_t>(nn) + 1));
       PKD_HIP(hipMemsetAsync(killed_next.p, 1, nn + 1, st));
-      if (insert) {
-        PKD_TRY(rcount.need(static_cast<size_t>(R->ns) + 1));
-        PKD_TRY(roff.need(static_cast<size_t>(R->ns) + 1));
-      }
-      for (int apply = insert ? 0 : 1; apply < 2; ++apply) {
+      PKD_TRY(rcount.need(static_cast<size_t>(R->ns) + 1));
+      PKD_TRY(roff.need(static_cast<size_t>(R->ns) + 1));
+      PKD_TRY(scount.need(static_cast<size_t>(R->ns) + 1));
+      PKD_TRY(soff.need(static_cast<size_t>(R->ns) + 1));
+      for (int apply = 0; apply < 2; ++apply) {
         hipLaunchKernelGGL(k_decide, dim3((R->ns + kWaves - 1) / kWaves), dim3(64 * kWaves),
-                           kWaves * decide_lds_per_wave(lambda), st, R->tasks.p, R->ns, lambda, R->hn.p, R->bsize.p,
+                           kWaves * decide_lds_per_wave(R->lambda), st, R->tasks.p, R->ns, R->lambda, R->hn.p,
+                           R->bsize.p,
                            R->bstart.p, R->child.p, killed.p, killed_next.p, M.p, T->nodes, P.alpha_num, P.alpha_den,
-                           insert ? 1 : 0, regions.p, d_regions, apply, rcount.p, insert ? roff.p : nullptr,
-                           sizes.p, d_sizes);
+                           insert ? 1 : 0, regions.p, d_regions, apply, rcount.p, roff.p, sizes.p, d_sizes,
+                           scount.p, soff.p);
         PKD_TRY(kernel_status("k_decide"));
-        if (apply == 0) PKD_TRY(exscan_i32(st, rcount.p, roff.p, R->ns, bsum));
+        if (apply == 0) {
+          PKD_TRY(exscan_i32(st, rcount.p, roff.p, R->ns, bsum));
+          PKD_TRY(exscan_i32(st, scount.p, soff.p, R->ns, bsum));
+        }
       }
-      if (insert) {
-        hipLaunchKernelGGL(k_add_regions, dim3(1), dim3(1), 0, st, d_regions, roff.p, R->ns);
-        PKD_TRY(kernel_status("k_add_regions"));
-      }
+      hipLaunchKernelGGL(k_add_regions, dim3(1), dim3(1), 0, st, d_regions, roff.p, d_sizes, soff.p, R->ns);
+      PKD_TRY(kernel_status("k_add_regions"));
       std::swap(killed.p, killed_next.p);
       std::swap(killed.cap, killed_next.cap);
     }
@@ -985,11 +1010,26 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
                        insert ? 1 : 0, Ynew, new_cap, c32_new);
     PKD_TRY(kernel_status("k_relayout"));
   }
-  std::vector<Region> hreg(n_regions);
+  // region sizes and places after the update, their packed offsets in the
+  // rebuild's input (comp) and the rebuild's root tasks, all on the device
+  DArr<int32_t> rsize(st), comp32(st);
+  DArr<int64_t> dcomp(st), cin(st);
+  DArr<Task> roots(st);
+  int32_t R_pts32 = 0;
   if (n_regions > 0) {
-    hipLaunchKernelGGL(k_region_final, dim3(n_regions), dim3(64), 0, st, regions.p, S.p, insert ? 1 : 0);
+    PKD_TRY(rsize.need(static_cast<size_t>(n_regions) + 1));
+    PKD_TRY(comp32.need(static_cast<size_t>(n_regions) + 1));
+    PKD_TRY(dcomp.need(static_cast<size_t>(n_regions) + 1));
+    PKD_TRY(roots.need(static_cast<size_t>(n_regions)));
+    const unsigned gr = static_cast<unsigned>(std::min<int64_t>(65536, (n_regions + 256) / 256));
+    hipLaunchKernelGGL(k_region_final, dim3(gr), dim3(256), 0, st, regions.p, n_regions, S.p, insert ? 1 : 0,
+                       rsize.p);
     PKD_TRY(kernel_status("k_region_final"));
-    PKD_HIP(hipMemcpyAsync(hreg.data(), regions.p, sizeof(Region) * n_regions, hipMemcpyDeviceToHost, st));
+    PKD_TRY(exscan_i32(st, rsize.p, comp32.p, n_regions, bsum));
+    hipLaunchKernelGGL(k_region_roots, dim3(gr), dim3(256), 0, st, regions.p, n_regions, comp32.p, dcomp.p,
+                       roots.p);
+    PKD_TRY(kernel_status("k_region_roots"));
+    PKD_HIP(hipMemcpyAsync(&R_pts32, comp32.p + n_regions, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   }
   int n_sizes = 0;
   PKD_HIP(hipMemcpyAsync(&n_sizes, d_sizes, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1008,10 +1048,7 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
       }
     }
   } tmp{nullptr, st};
-  std::vector<int64_t> comp(static_cast<size_t>(n_regions) + 1, 0);
-  for (int r = 0; r < n_regions; ++r) comp[r + 1] = comp[r] + hreg[r].new_size;
-  const int64_t R_pts = comp[n_regions];
-  DArr<int64_t> dcomp(st), cin(st);
+  const int64_t R_pts = R_pts32;
   int32_t appended = 0;
   if (n_regions > 0) {
     tmp.t = new pkd_tree;
@@ -1019,28 +1056,14 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     tmp.t->n_trees = n_regions;
     PKD_TRY(alloc_points(tmp.t, st, R_pts));
     PKD_TRY(ensure_nodes(tmp.t, st, std::max<int64_t>(1024, n_regions + R_pts / 8)));
-    PKD_TRY(dcomp.need(static_cast<size_t>(n_regions) + 1));
-    PKD_HIP(hipMemcpyAsync(dcomp.p, comp.data(), sizeof(int64_t) * (n_regions + 1), hipMemcpyHostToDevice, st));
     PKD_TRY(cin.need(static_cast<size_t>(D + 1) * std::max<int64_t>(R_pts, 1)));
     const int64_t ccap = std::max<int64_t>(R_pts, 1);
     hipLaunchKernelGGL(k_gather_regions<D>, dim3(n_regions, ry), dim3(256), 0, st, regions.p, dcomp.p, Xold, old_cap,
                        S.p, delflag.p, wf.p, m, insert ? 1 : 0, cin.p, ccap);
     PKD_TRY(kernel_status("k_gather_regions"));
-    std::vector<Task> roots;
-    roots.reserve(n_regions);
-    for (int r = 0; r < n_regions; ++r) {
-      Task t;
-      t.start = static_cast<int32_t>(comp[r]);
-      t.m = hreg[r].new_size;
-      t.slot = r;
-      t.depth = static_cast<int16_t>(hreg[r].depth);
-      t.buf = 2;
-      t.mode = 0;
-      roots.push_back(t);
-    }
     tmp.t->node_count = n_regions;
     tmp.t->height = 0;
-    PKD_TRY(build_tasks(tmp.t, st, roots, cin.p, cin.p + static_cast<int64_t>(D) * ccap, ccap));
+    PKD_TRY(build_tasks_dev(tmp.t, st, roots.p, n_regions, 2, cin.p, cin.p + static_cast<int64_t>(D) * ccap, ccap));
     tmp.t->n = R_pts;
     appended = tmp.t->node_count - n_regions;
     if (static_cast<int64_t>(T->node_count) + appended >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
