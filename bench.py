@@ -254,10 +254,11 @@ def bench_batching(a):
     torch.cuda.synchronize()
     t_batched = (time.perf_counter() - t0) / a.steps
     log("batched: %.1f ms per pass" % (t_batched * 1e3))
+    graph = query_graph(groups, params, a, log)
 
     if a.no_single:
         print(json.dumps({"metric": "batched build + k-NN over many trees", "batched_ms": round(t_batched * 1e3, 3),
-                          "points": n_total}))
+                          "points": n_total, "query_phase": graph}))
         return
     # one build and one query call per tree (same parameters); the per-tree
     # query selections are made before the timed region, the result checks after
@@ -309,8 +310,62 @@ def bench_batching(a):
         "one_call_per_tree_ms": round(t_single * 1e3, 3),
         "speedup_vs_one_call_per_tree": round(t_single / t_batched, 2),
         "identical_results": same,
+        "query_phase": graph,
     }
     print(json.dumps(out))
+
+
+def query_graph(groups, params, a, log):
+    """The query phase of the batching workload (k-NN over the batch handles,
+    one launch per dimension and k) eagerly and as one captured hipGraph
+    replayed; both timed over the same handles, results compared."""
+    import torch
+
+    import paper_2411_09275_amd as pk
+    handles = {D: pk.Tree.batch(params[D][0], gr["c"], gr["i"], gr["off"], tile=params[D][1])
+               for D, gr in groups.items()}
+    calls = [(D, k, qk, tk) for D, gr in groups.items() for k, (idx, qk, tk) in gr["byk"].items()]
+    outs = {(D, k): (torch.empty((qk.shape[1], k), dtype=torch.int64, device="cuda"),
+                     torch.empty((qk.shape[1], k), dtype=torch.int64, device="cuda")) for D, k, qk, tk in calls}
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def eager():
+        return {(D, k): handles[D].knn(qk, k, tree_of=tk) for D, k, qk, tk in calls}
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for D, k, qk, tk in calls:
+            handles[D].knn_async(qk, k, *outs[(D, k)], status, tree_of=tk, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        status.zero_()
+        for D, k, qk, tk in calls:
+            handles[D].knn_async(qk, k, *outs[(D, k)], status, tree_of=tk, stream=side)
+    reps = max(3, a.steps)
+    for _ in range(2):
+        ref = eager()
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ref = eager()
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    same = int(status.item()) == 0 and all(torch.equal(outs[key][0], ref[key][0]) and
+                                           torch.equal(outs[key][1], ref[key][1]) for key in ref)
+    for h in handles.values():
+        h.free()
+    log("query phase: eager %.2f ms, graph replay %.2f ms, identical %s" % (t_eager * 1e3, t_graph * 1e3, same))
+    return {"launches": len(calls), "eager_ms": round(t_eager * 1e3, 3), "graph_replay_ms": round(t_graph * 1e3, 3),
+            "identical_results": same}
 
 
 def bench_serving(a):

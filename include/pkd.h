@@ -256,6 +256,11 @@ int pkd_range_report_batch(const pkd_tree* tree, void* stream, const int64_t* lo
  * returned: 1 = a coordinate outside its bound, 16 = traversal stack too
  * small, 32 = inconsistent tree or tree index.  Outputs and *status are valid
  * once the stream reaches this point.  The tree must not be modified until then.
+ * While `stream` is being captured into a graph (hipStreamBeginCapture) these
+ * two calls enqueue kernels only, with no allocation and no event: large
+ * batches then skip the spatial ordering of the queries, which changes only
+ * the speed.  A sequence of query batches can so be captured once and
+ * replayed with new data in the same buffers.
  */
 int pkd_knn_async(const pkd_tree* tree, void* stream, const int64_t* queries,
                   const int32_t* tree_of, int64_t nq, int32_t k, int64_t* out_ids,

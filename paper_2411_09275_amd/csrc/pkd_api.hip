@@ -202,7 +202,7 @@ ProfState g_prof;
 
 bool Prof::on() { return g_prof.on; }
 void Prof::begin(int kernel, hipStream_t st) {
-  if (!g_prof.on) return;
+  if (!g_prof.on || capturing(st)) return;
   hipEvent_t e = g_prof.get();
   (void)hipEventRecord(e, st);
   g_prof.open_ev[kernel] = e;

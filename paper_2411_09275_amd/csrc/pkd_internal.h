@@ -30,6 +30,13 @@ static_assert((coord_limit(9) - 1) * (coord_limit(9) - 1) <= INT64_MAX / 9 &&
 constexpr int64_t kAllLeft = INT64_MAX;          // splitter that sends every point left
 constexpr int kMaxStack = 160;                   // traversal stack of the query kernels
 
+// True while work enqueued on `st` is being captured into a graph: calls then
+// only enqueue kernels (no allocation, no event, no readback).
+inline bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
+
 // Orders the LDS accesses of one wave: what a lane wrote is seen by every
 // lane of the wave after this point.
 __device__ inline void wave_sync() {

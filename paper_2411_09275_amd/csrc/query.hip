@@ -946,7 +946,9 @@ template <int D>
 int order_queries(hipStream_t st, const int64_t* Q, int64_t nq, const int32_t* tree_of, int32_t n_trees,
                   QueryOrder& W, const uint32_t** perm) {
   *perm = nullptr;
-  if (nq < kOrderMinQueries) return PKD_OK;
+  // under graph capture the queries run in input order: the order would need
+  // sort buffers, and it changes only the speed, never a result
+  if (nq < kOrderMinQueries || capturing(st)) return PKD_OK;
   int bpd = 0, nbits = 0;
   morton_bits<D>(nq, tree_of, n_trees, &bpd, &nbits);
   PKD_TRY(W.k0.need(nq));
