@@ -745,6 +745,7 @@ def bench_alpha_sweep(a):
                     capacity = capacity if capacity is not None else b   # deeper than the traversal stack
                     continue
                 if b in checks:
+                    log("TYPE %s alpha %d/%d: batch %d of %d, insertion %.2f s" % (kind, al[0], al[1], b + 1, B, ins))
                     f = pk.Tree(pk.Params(D), gc[:, :(b + 1) * step], gi[:(b + 1) * step])
                     f.knn(q, 1)   # warm
                     torch.cuda.synchronize()
@@ -1016,6 +1017,7 @@ def main():
         print("copy calibration: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8),
               file=sys.stderr, flush=True)
         del src, dst
+    copy_gbs = stream_copy_gbps(torch, dev)
     t0 = time.perf_counter()
     coords, ids = synth.uniform_points(a.n, a.dim, seed=3)
     q = synth.uniform_queries(a.queries, a.dim, seed=4)
@@ -1068,7 +1070,9 @@ def main():
     pk.profile_enable(False)
     scatter_gbs = sc_bytes / (sc_ms * 1e-3) / 1e9 if sc_ms > 0 else 0.0
     sieve_gbs = (sc_bytes + ct_bytes) / ((sc_ms + ct_ms) * 1e-3) / 1e9 if sc_ms + ct_ms > 0 else 0.0
-    traffic = load_traffic("sieve_scatter")
+    # the committed counters cover the default workload only
+    measured = a.n == 100_000_000 and a.dim == 3 and a.tile == 2048 and params.lam == 6
+    traffic = load_traffic("sieve_scatter") if measured else None
     out = {
         "metric": "build Mpts/s + sieve HBM GB/s (% peak); 10-NN queries/s; 1e8 pts 3D",
         "value": round(a.n / (build_ms * 1e-3) / 1e6, 2),
@@ -1087,12 +1091,15 @@ def main():
                    "n": a.n, "dim": a.dim, "queries": a.queries, "k": a.k, "boxes": a.boxes,
                    "lambda": params.lam, "phi": params.phi, "sigma": params.sigma, "tile": a.tile},
         "build_ms": round(build_ms, 3),
+        "build_ms_median": round(float(np.median(rec[:, 0])), 3),
         "knn_qps": round(a.queries / (knn_ms * 1e-3), 1),
         "knn_ms": round(knn_ms, 3),
         "range_qps": round(a.boxes / (range_ms * 1e-3), 1),
         "range_ms": round(range_ms, 3),
         "sieve_gbps": round(sieve_gbs, 1),
         "sieve_frac_peak": round(sieve_gbs / HBM_PEAK_GBS, 4),
+        "stream_copy_gbps": round(copy_gbs, 1),
+        "sieve_frac_of_copy": round(sieve_gbs / copy_gbs, 4) if copy_gbs > 0 else None,
         "kernel_ms_per_step": {"sieve_count": round(ct_ms / a.steps, 3), "sieve_scatter": round(sc_ms / a.steps, 3),
                                "select_skeleton": round(sel_ms / a.steps, 3), "finisher": round(fin_ms / a.steps, 3)},
         "roofline": {"kernel": "k_scatter (sieve scatter)", "bound": "hbm", "achieved": round(scatter_gbs, 1),
@@ -1114,10 +1121,33 @@ def main():
         kn_gbs = per_q * a.queries / (kn_ms / kn_n * 1e-3) / 1e9
         out["roofline_knn"] = {"kernel": "k_knn (%d-NN, one lane per query)" % a.k, "bound": "hbm",
                                "achieved": round(kn_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": round(kn_gbs / HBM_PEAK_GBS, 4), "traffic": load_traffic("knn"),
+                               "frac": round(kn_gbs / HBM_PEAK_GBS, 4),
+                               "traffic": load_traffic("knn") if measured and a.k == 10 and a.queries == 10 ** 7 else None,
                                "launches": kn_n, "alg_bytes_per_launch": round(per_q * a.queries),
                                "work_per_query": work}
     print(json.dumps(out))
+
+
+def stream_copy_gbps(torch, dev, nbytes=2 << 30, reps=5):
+    """Device-to-device copy of nbytes (read nbytes, write nbytes), timed
+    with events on the current stream: the practical HBM rate of a plain
+    streaming kernel on this GPU, beside the nominal peak."""
+    src = torch.empty(nbytes // 8, dtype=torch.int64, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = None
+    for _ in range(reps):
+        e0.record(s)
+        dst.copy_(src)
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (best * 1e-3) / 1e9
 
 
 if __name__ == "__main__":
