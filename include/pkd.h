@@ -234,6 +234,45 @@ int pkd_batch_delete_tree(pkd_tree* tree, int32_t t, void* stream, const int64_t
 int pkd_num_trees(const pkd_tree* tree, int32_t* n_trees);
 
 /*
+ * Build plans: the batch build above (Algorithm 1 for every tree) enqueued
+ * without any host read, so that one build can be captured into a hipGraph
+ * and the graph replayed on new points of the same trees (with query launches
+ * captured after it, see pkd_knn_async).  Every sieve round is launched with
+ * grids sized for the most work it can hold and reads its counts from device
+ * memory; the base cases run in persistent grids that walk their lists.
+ *
+ * pkd_build_plan_create: params and tuning as for pkd_build (oversample 0,
+ *   the exact-median mode, returns PKD_ERR_UNSUPPORTED); n_trees and offsets
+ *   (HOST int64 [n_trees+1], as for pkd_build_batch) fix the trees' sizes for
+ *   every build of the plan.  Allocates the plan's tree and a workspace sized
+ *   for the worst case (about 3 sample-size candidate slots per sieve
+ *   subproblem and the node records the rounds can make); synchronizes.
+ * pkd_build_plan_enqueue: enqueues one build of the trees over coords / ids
+ *   (device, layout of pkd_build_batch) on `stream`: kernel launches only (no
+ *   allocation, no host read, no event), so the call may be captured; every
+ *   replay rebuilds from what the same buffers then hold.
+ * pkd_build_plan_finish: waits for `stream`, checks the build and makes the
+ *   plan's tree valid.  Cases the sized launches do not cover (a sampler retry,
+ *   a sample of identical points, more rounds than planned, more node records
+ *   than reserved) are built again the usual way into the same arrays, with
+ *   *redone (optional) set to 1; the tree is the same either way.  Returns
+ *   PKD_ERR_RANGE for a coordinate outside its bound (the tree is then empty).
+ * pkd_build_plan_tree: the plan's tree, owned by the plan.  It holds the last
+ *   finished build until the next enqueue; it answers queries, while updates,
+ *   bounding boxes and pkd_free_async return PKD_ERR_INVALID_ARG and pkd_free
+ *   does nothing.
+ * pkd_build_plan_free: frees the plan and its tree (waits for the device).
+ */
+typedef struct pkd_build_plan pkd_build_plan;
+int pkd_build_plan_create(const pkd_params* params, const pkd_tuning* tuning, int32_t n_trees,
+                          const int64_t* offsets, pkd_build_plan** out);
+int pkd_build_plan_enqueue(pkd_build_plan* plan, void* stream, const int64_t* coords,
+                           const int64_t* ids);
+int pkd_build_plan_finish(pkd_build_plan* plan, void* stream, int32_t* redone);
+int pkd_build_plan_tree(pkd_build_plan* plan, pkd_tree** tree);
+void pkd_build_plan_free(pkd_build_plan* plan);
+
+/*
  * k-NN / range count over the trees of a batch handle: query j runs on tree
  * tree_of[j] (device int32 [nq]; NULL means tree 0).  Other arguments and the
  * output layout as for pkd_knn / pkd_range_count.

@@ -30,7 +30,8 @@ EXPORTS = ["pkd_default_params", "pkd_default_tuning", "pkd_build", "pkd_batch_i
            "pkd_knn_async", "pkd_range_count_async", "pkd_knn_noalloc", "pkd_set_allocator", "pkd_free_async",
            "pkd_node_slots", "pkd_range_report", "pkd_range_report_batch",
            "pkd_update_stats", "pkd_set_bbox", "pkd_export_bbox", "pkd_batch_insert_tree",
-           "pkd_batch_delete_tree"]
+           "pkd_batch_delete_tree", "pkd_build_plan_create", "pkd_build_plan_enqueue", "pkd_build_plan_finish",
+           "pkd_build_plan_tree", "pkd_build_plan_free"]
 
 
 class PkdError(RuntimeError):
@@ -101,9 +102,16 @@ def lib():
         L.pkd_range_report.argtypes = [vp, vp, vp, vp, i64, vp, vp, i64, C.POINTER(i64)]
         L.pkd_range_report_batch.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, i64, C.POINTER(i64)]
         L.pkd_range_count_async.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+        L.pkd_build_plan_create.argtypes = [C.POINTER(_Params), C.POINTER(_Tuning), i32, vp, C.POINTER(vp)]
+        L.pkd_build_plan_enqueue.argtypes = [vp, vp, vp, vp]
+        L.pkd_build_plan_finish.argtypes = [vp, vp, C.POINTER(i32)]
+        L.pkd_build_plan_tree.argtypes = [vp, C.POINTER(vp)]
+        L.pkd_build_plan_free.argtypes = [vp]
+        L.pkd_build_plan_free.restype = None
         L.pkd_strerror.argtypes = [C.c_int]
         L.pkd_strerror.restype = C.c_char_p
-        for f in ("pkd_batch_insert_tree", "pkd_batch_delete_tree", "pkd_set_bbox", "pkd_export_bbox", "pkd_update_stats", "pkd_range_report", "pkd_range_report_batch", "pkd_set_allocator", "pkd_free_async", "pkd_node_slots", "pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
+        for f in ("pkd_build_plan_create", "pkd_build_plan_enqueue", "pkd_build_plan_finish", "pkd_build_plan_tree",
+                  "pkd_batch_insert_tree", "pkd_batch_delete_tree", "pkd_set_bbox", "pkd_export_bbox", "pkd_update_stats", "pkd_range_report", "pkd_range_report_batch", "pkd_set_allocator", "pkd_free_async", "pkd_node_slots", "pkd_knn_noalloc", "pkd_knn_async", "pkd_range_count_async", "pkd_build_batch", "pkd_num_trees", "pkd_knn_batch", "pkd_range_count_batch",
                   "pkd_export_tree_sizes", "pkd_export_tree", "pkd_profile_enable", "pkd_profile_get", "pkd_build", "pkd_batch_insert", "pkd_batch_delete", "pkd_knn", "pkd_range_count", "pkd_size",
                   "pkd_height", "pkd_export_sizes", "pkd_export"):
             getattr(L, f).restype = C.c_int
@@ -271,7 +279,11 @@ class Tree:
 
     def free(self, stream=None):
         """Release the tree; with a stream, in stream order without waiting
-        (pkd_free_async), else after all device work (pkd_free)."""
+        (pkd_free_async), else after all device work (pkd_free).  The tree of
+        a build plan belongs to the plan and is left alone."""
+        if getattr(self, "_borrowed", False):
+            self.h = None
+            return
         if getattr(self, "h", None) is not None and self.h.value:
             if stream is None:
                 lib().pkd_free(self.h)
@@ -427,3 +439,46 @@ class Tree:
                "pkd_export")
         self.last_depths = depths
         return rows, ids, coords
+
+
+class BuildPlan:
+    """A batch build enqueued without host reads (pkd_build_plan_*): create it
+    for fixed tree sizes, enqueue builds (also inside a captured graph), call
+    finish() after each, then query tree().  finish() returns True when the
+    build had to be redone the usual way (the tree is the same)."""
+
+    def __init__(self, params: Params, offsets, tile: int = 2048, cand_bias: int = 0):
+        self.p = params
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        h = C.c_void_p()
+        _check(lib().pkd_build_plan_create(C.byref(params._c()), C.byref(_tuning(tile, cand_bias)),
+                                           self.offsets.shape[0] - 1, self.offsets.ctypes.data_as(C.c_void_p),
+                                           C.byref(h)), "pkd_build_plan_create")
+        self.h = h
+        t = C.c_void_p()
+        _check(lib().pkd_build_plan_tree(self.h, C.byref(t)), "pkd_build_plan_tree")
+        self._tree = Tree(params, None, None, _handle=t)
+        self._tree._borrowed = True
+
+    def enqueue(self, coords, ids, stream=None):
+        """Enqueue one build over device buffers (kept alive by the caller)."""
+        assert tuple(coords.shape) == (self.p.dim, int(self.offsets[-1])) and coords.is_contiguous()
+        _check(lib().pkd_build_plan_enqueue(self.h, _stream(stream), _ptr(coords), _ptr(ids)),
+               "pkd_build_plan_enqueue")
+
+    def finish(self, stream=None) -> bool:
+        redone = C.c_int32(0)
+        _check(lib().pkd_build_plan_finish(self.h, _stream(stream), C.byref(redone)), "pkd_build_plan_finish")
+        return bool(redone.value)
+
+    def tree(self) -> Tree:
+        return self._tree
+
+    def free(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self._tree.h = None
+            lib().pkd_build_plan_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        self.free()

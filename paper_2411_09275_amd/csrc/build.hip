@@ -89,9 +89,15 @@ __host__ __device__ inline int cand_shift(int64_t m, int s) {
   return t;
 }
 
+// A count the host passes (eager launches, sized exactly) or, when `d` is
+// set, the one in device memory (launches enqueued without host reads, sized
+// for the largest count; blocks past the count return at once).
+__device__ inline int dev_count(const int* d, int h) { return d ? *d : h; }
+
 // ---------------------------------------------------------------- classify
 __global__ void k_classify(const Task* front, int n_front, int s, Task* sieve, int* n_sieve, Task* fin,
-                           int* n_fin) {
+                           int* n_fin, const int* dn = nullptr) {
+  n_front = dev_count(dn, n_front);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = i < n_front;
   Task t{};
@@ -106,7 +112,8 @@ __global__ void k_classify(const Task* front, int n_front, int s, Task* sieve, i
 // Single workgroup: exclusive prefix sums of tiles and chunks per subproblem.
 __global__ void k_tile_scan(const Task* sp, int ns, int tile, int64_t* tile_off, int64_t* chunk_off,
                             int8_t* shift, int s, int small_max, const int8_t* shift_override, int64_t* total_pts,
-                            int cand_bias) {
+                            int cand_bias, const int* dns = nullptr) {
+  ns = dev_count(dns, ns);
   __shared__ int64_t part_t[1024], part_c[1024];
   __shared__ unsigned long long pts;
   if (threadIdx.x == 0) pts = 0;
@@ -167,12 +174,14 @@ template <int ITER>
 __global__ void __launch_bounds__(kBlock) k_candidates(const Task* sp, int ns, const int64_t* tile_off, Bufs bufs,
                                                        int src, uint64_t seed, const int8_t* shift, int small_max,
                                                        uint64_t* cand_key, uint32_t* cand_pos, uint32_t* cand_cnt,
-                                                       int cap) {
+                                                       int cap, const int* dns = nullptr) {
   constexpr int kWaves = kBlock / 64;
   __shared__ int sig_sh;
   __shared__ uint32_t wcnt[ITER][kWaves];
   __shared__ uint32_t gbase;
   const int64_t t = blockIdx.x;
+  ns = dev_count(dns, ns);
+  if (dns && t >= tile_off[ns]) return;
   const int tid = threadIdx.x, wave = tid >> 6;
   const uint32_t lane = lane_id();
   if (tid == 0) sig_sh = find_owner(tile_off, ns, t);
@@ -454,11 +463,13 @@ __global__ void __launch_bounds__(64 * D) k_select_skeleton(const Task* sp, int 
                                                               uint64_t seed, int s, int lambda,
                                                               const int8_t* shift, int small_max,
                                                               const uint64_t* cand_key, const uint32_t* cand_pos,
-                                                              const uint32_t* cand_cnt, int cap, SelectOut out) {
+                                                              const uint32_t* cand_cnt, int cap, SelectOut out,
+                                                              const int* dns = nullptr) {
   constexpr int NT = 64 * D;
   constexpr int P = 64 * NPL;   // padded stride of the per-dimension arrays (>= s)
   extern __shared__ __align__(16) unsigned char smem[];
   const int sig = blockIdx.x;
+  if (dns && sig >= *dns) return;
   const Task q = sp[sig];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t* ids = bufs.id[src] + q.start;
@@ -711,13 +722,15 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_count(const Task* sp, int ns, const int64_t* tile_off, int tile,
                                                   Bufs bufs, int src, const int64_t* rx, const uint8_t* rdim,
                                                   const int8_t* mode, int lambda, uint32_t* A, int check,
-                                                  int* flags) {
+                                                  int* flags, const int* dns = nullptr) {
   __shared__ int64_t sx[1 << kMaxLambda];
   __shared__ uint8_t sd[1 << kMaxLambda];
   __shared__ uint32_t hist[1 << kMaxLambda];
   __shared__ int sig_sh;
   const int NB = 1 << lambda;
   const int64_t t = blockIdx.x;
+  ns = dev_count(dns, ns);
+  if (dns && t >= tile_off[ns]) return;
   if (threadIdx.x == 0) sig_sh = find_owner(tile_off, ns, t);
   for (int j = threadIdx.x; j < NB; j += kBlock) hist[j] = 0;
   __syncthreads();
@@ -754,11 +767,13 @@ __global__ void __launch_bounds__(kBlock) k_count(const Task* sp, int ns, const 
 // ------------------------------------------------------------------- scan
 // Column sums of each chunk of kChunkTiles tiles.
 __global__ void k_chunk_sum(const int64_t* chunk_off, const int64_t* tile_off, int ns, int lambda,
-                            const uint32_t* A, uint32_t* S) {
+                            const uint32_t* A, uint32_t* S, const int* dns = nullptr) {
   __shared__ int sig_sh;
   __shared__ uint32_t part[kBlock];
   const int NB = 1 << lambda;
   const int64_t c = blockIdx.x;
+  ns = dev_count(dns, ns);
+  if (dns && c >= chunk_off[ns]) return;
   if (threadIdx.x == 0) sig_sh = find_owner(chunk_off, ns, c);
   __syncthreads();
   const int sig = sig_sh;
@@ -779,11 +794,12 @@ __global__ void k_chunk_sum(const int64_t* chunk_off, const int64_t* tile_off, i
 // Per subproblem: exclusive prefix of the chunk sums over chunks (per bucket),
 // bucket sizes and bucket starts (prefix over buckets, offset by the start).
 __global__ void k_sp_scan(const Task* sp, const int64_t* chunk_off, int lambda, uint32_t* S, int32_t* bsize,
-                          int32_t* bstart) {
+                          int32_t* bstart, const int* dns = nullptr) {
   __shared__ uint32_t part[kBlock];
   __shared__ uint32_t tot[1 << kMaxLambda];
   const int NB = 1 << lambda;
   const int sig = blockIdx.x;
+  if (dns && sig >= *dns) return;
   const int64_t c0 = chunk_off[sig], c1 = chunk_off[sig + 1];
   const int j = threadIdx.x % NB, lane = threadIdx.x / NB, lanes = kBlock / NB;
   const int64_t nc = c1 - c0;
@@ -822,10 +838,12 @@ __global__ void k_sp_scan(const Task* sp, const int64_t* chunk_off, int lambda, 
 // B[t][j] = bucket start + prefix over earlier chunks + prefix over earlier
 // tiles of the chunk: the write cursor of tile t for bucket j.
 __global__ void k_apply(const int64_t* chunk_off, const int64_t* tile_off, int ns, int lambda, const uint32_t* A,
-                        const uint32_t* S, const int32_t* bstart, int32_t* B) {
+                        const uint32_t* S, const int32_t* bstart, int32_t* B, const int* dns = nullptr) {
   __shared__ int sig_sh;
   const int NB = 1 << lambda;
   const int64_t c = blockIdx.x;
+  ns = dev_count(dns, ns);
+  if (dns && c >= chunk_off[ns]) return;
   if (threadIdx.x == 0) sig_sh = find_owner(chunk_off, ns, c);
   __syncthreads();
   const int sig = sig_sh;
@@ -881,7 +899,8 @@ struct ScatterLayout {
 template <int D, int PPT>
 __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, const int64_t* tile_off, Bufs bufs,
                                                     int src, int dst, const int64_t* rx, const uint8_t* rdim,
-                                                    const int8_t* mode, int lambda, const int32_t* B) {
+                                                    const int8_t* mode, int lambda, const int32_t* B,
+                                                    const int* dns = nullptr) {
   constexpr int T = kBlock * PPT;
   constexpr int NCH = T / 64;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -895,7 +914,15 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
   uint8_t* slab = smem + lay.slab;
   __shared__ int sig_sh;
   const int NB = 1 << lambda;
-  const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+  int64_t ntiles = gridDim.x;
+  if (dns) {
+    // the grid is sized for the most tiles a round can have: the blocks past
+    // this round's tiles leave, the others map as in an exact grid
+    ns = *dns;
+    ntiles = tile_off[ns];
+    if (static_cast<int64_t>(blockIdx.x) >= ntiles) return;
+  }
+  const int64_t t = xcd_tile(blockIdx.x, ntiles);
   const int tid = threadIdx.x;
   if (tid == 0) sig_sh = find_owner(tile_off, ns, t);
   for (int i = tid; i < NCH * NB; i += kBlock) cnt[i] = 0;
@@ -1005,7 +1032,8 @@ __global__ void __launch_bounds__(64) k_emit(const Task* sp, int ns, int lambda,
                                              const uint8_t* rdim, const int8_t* ext, const int8_t* mode,
                                              const int32_t* bsize, const int32_t* bstart, int dst, Node* nodes,
                                              int* node_count, Task* front, int* n_front, Task* fin, int* n_fin,
-                                             int* flags) {
+                                             int* flags, const int* dns = nullptr) {
+  if (dns && static_cast<int>(blockIdx.x) >= *dns) return;
   const int NB = 1 << lambda;
   const int nheap = 2 << lambda;
   __shared__ int32_t size[2 << kMaxLambda], off[2 << kMaxLambda], idx[2 << kMaxLambda];
@@ -1106,14 +1134,13 @@ __global__ void __launch_bounds__(64) k_emit(const Task* sp, int ns, int lambda,
 // Node slots: each task owns a reserved range [res_base + res_off[i],
 // res_base + res_off[i+1]) sized for distinct coordinates; a task that needs
 // more (duplicates) takes the rest from the shared overflow counter.
+// One task (every thread of the workgroup calls it).
 template <int D, int NPL>
-__global__ void __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(NPL <= 8 ? 8 : 1))) k_finish(const Task* tasks, const int* list, int P, Bufs bufs, int final_buf,
-                                                     int phi, Node* nodes, int* overflow_ctr, int64_t node_cap,
-                                                     int* height, int* flags, const int32_t* res_off,
-                                                     int32_t res_base) {
+__device__ __forceinline__ void finish_task(int ti, const Task* tasks, int P, Bufs bufs, int final_buf, int phi,
+                                            Node* nodes, int* overflow_ctr, int64_t node_cap, int* height,
+                                            int* flags, const int32_t* res_off, int32_t res_base) {
   constexpr int NT = 64 * D;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int ti = list[blockIdx.x];
   const Task q = tasks[ti];
   const int m = q.m;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1340,47 +1367,84 @@ __global__ void __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(NPL
   }
 }
 
+template <int D, int NPL>
+__global__ void __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(NPL <= 8 ? 8 : 1))) k_finish(const Task* tasks, const int* list, int P, Bufs bufs, int final_buf,
+                                                     int phi, Node* nodes, int* overflow_ctr, int64_t node_cap,
+                                                     int* height, int* flags, const int32_t* res_off,
+                                                     int32_t res_base) {
+  finish_task<D, NPL>(list[blockIdx.x], tasks, P, bufs, final_buf, phi, nodes, overflow_ctr, node_cap, height, flags,
+                      res_off, res_base);
+}
+
+// Persistent form for launches enqueued without host reads: a fixed grid
+// walks the class list up to its count in device memory; the base of the
+// node reservations is read from device memory too.
+template <int D, int NPL>
+__global__ void __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(NPL <= 8 ? 8 : 1))) k_finish_persist(const Task* tasks, const int* list, const int* count, int P, Bufs bufs,
+                                                     int final_buf, int phi, Node* nodes, int* overflow_ctr,
+                                                     int64_t node_cap, int* height, int* flags,
+                                                     const int32_t* res_off, const int* res_base) {
+  const int n = *count;
+  const int32_t base = *res_base;
+  for (int b = blockIdx.x; b < n; b += gridDim.x) {
+    finish_task<D, NPL>(list[b], tasks, P, bufs, final_buf, phi, nodes, overflow_ctr, node_cap, height, flags,
+                        res_off, base);
+    __syncthreads();   // the next task reuses the LDS
+  }
+}
+
 // Heavy leaf of identical points found by the sieve (m may exceed any LDS
 // size): copy the points into the tree array and write one leaf.
-__global__ void k_fin_reserve(const Task* fin, int n_fin, int phi, int32_t* R) {
+// With `dn` set the launch covers n_fin slots of which the first *dn are
+// tasks; the others get 0.
+__global__ void k_fin_reserve(const Task* fin, int n_fin, int phi, int32_t* R, const int* dn = nullptr) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_fin) return;
+  if (dn && i >= *dn) {
+    R[i] = 0;
+    return;
+  }
   const Task t = fin[i];
   // a plain build of m distinct points with leaves of at most phi points has
   // at most about 2m/(phi+1) leaves, so fewer than 4m/(phi+1)+4 nodes below the root
   R[i] = (t.mode == 1 || t.m <= phi) ? 0 : 4 * t.m / (phi + 1) + 4;
 }
 
+// With `count` set, a fixed grid walks the list up to *count.
 __global__ void k_finish_heavy(const Task* tasks, const int* list, int D, Bufs bufs, int final_buf, Node* nodes,
-                               int* height) {
-  const Task q = tasks[list[blockIdx.x]];
-  const int src = q.buf;
-  for (int64_t i = threadIdx.x; i < q.m; i += blockDim.x) {
-    for (int d = 0; d < D; ++d) {
-      const int64_t v = bufs.c[src][d * bufs.cap[src] + q.start + i];
-      if (src != final_buf) bufs.c[final_buf][d * bufs.cap[final_buf] + q.start + i] = v;
-      bufs.c32[(static_cast<int64_t>(q.start) + i) * D + d] = static_cast<int32_t>(v);
+                               int* height, const int* count = nullptr) {
+  const int n = count ? *count : static_cast<int>(gridDim.x);
+  for (int b = blockIdx.x; b < n; b += gridDim.x) {
+    const Task q = tasks[list[b]];
+    const int src = q.buf;
+    for (int64_t i = threadIdx.x; i < q.m; i += blockDim.x) {
+      for (int d = 0; d < D; ++d) {
+        const int64_t v = bufs.c[src][d * bufs.cap[src] + q.start + i];
+        if (src != final_buf) bufs.c[final_buf][d * bufs.cap[final_buf] + q.start + i] = v;
+        bufs.c32[(static_cast<int64_t>(q.start) + i) * D + d] = static_cast<int32_t>(v);
+      }
+      if (src != final_buf) bufs.id[final_buf][q.start + i] = bufs.id[src][q.start + i];
     }
-    if (src != final_buf) bufs.id[final_buf][q.start + i] = bufs.id[src][q.start + i];
-  }
-  if (threadIdx.x == 0) {
-    Node nd;
-    nd.x = 0;
-    nd.size = q.m;
-    nd.off = q.start;
-    nd.left = -1;
-    nd.right = -1;
-    nd.dim = -1;
-    nd.depth = q.depth;
-    nd.pad = 0;
-    nodes[q.slot] = nd;
-    atomicMax(height, static_cast<int>(q.depth));
+    if (threadIdx.x == 0) {
+      Node nd;
+      nd.x = 0;
+      nd.size = q.m;
+      nd.off = q.start;
+      nd.left = -1;
+      nd.right = -1;
+      nd.dim = -1;
+      nd.depth = q.depth;
+      nd.pad = 0;
+      nodes[q.slot] = nd;
+      atomicMax(height, static_cast<int>(q.depth));
+    }
   }
 }
 
 // Sort finisher tasks into classes by padded size (64, 128, ..., 4096) and
 // heavy leaves (class 7).
-__global__ void k_bin_finish(const Task* fin, int n_fin, int* lists, int stride, int* counts) {
+__global__ void k_bin_finish(const Task* fin, int n_fin, int* lists, int stride, int* counts, const int* dn = nullptr) {
+  n_fin = dev_count(dn, n_fin);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = i < n_fin;
   int cls = -1;
@@ -2327,6 +2391,278 @@ int build_tasks(pkd_tree* T, hipStream_t st, const std::vector<Task>& roots, con
                 const int64_t* in_id, int64_t input_cap) {
   return build_tasks_any(T, st, roots.data(), static_cast<int>(roots.size()), false,
                          roots.empty() ? 2 : roots[0].buf, in_c, in_id, input_cap);
+}
+
+// ------------------------------------------------ graph build plans
+namespace {
+// Counter slots of a plan (G->ctr).
+enum : int {
+  kGSieve = 0, kGFin = 1, kGNext = 2, kGNodes = 3, kGFlags = 4, kGRootExt = 5, kGHeight = 6, kGFront = 7,
+  kGClass = 8,      // 8 class counts of the finisher
+  kGBase = 16,      // node records before the finisher (base of its reservations)
+  kGSlots = 32
+};
+constexpr int kErrPlan = 64;   // flag: the sized launches did not cover this input
+
+// The roots of the non-empty trees form the first front; node records
+// 0 .. n_slots-1 are the trees' roots.
+__global__ void k_plan_start(int* ctr, int n_roots, int n_slots, const Task* roots, Task* front) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_roots) front[i] = roots[i];
+  if (i < kGSlots) ctr[i] = i == kGNodes ? n_slots : (i == kGFront ? n_roots : 0);
+}
+
+// Before a round: the round's append counters start at zero.
+__global__ void k_plan_round(int* ctr) {
+  if (threadIdx.x == 0) {
+    ctr[kGSieve] = 0;
+    ctr[kGNext] = 0;
+    ctr[kGRootExt] = 0;
+  }
+}
+
+// After a round: the buckets become the next front; a sample of identical
+// points needs the exact split the sized launches do not make.
+__global__ void k_plan_round_end(int* ctr) {
+  if (threadIdx.x == 0) {
+    ctr[kGFront] = ctr[kGNext];
+    if (ctr[kGRootExt] > 0) ctr[kGFlags] |= kErrPlan;
+  }
+}
+
+// After the last round: no subproblem may be left for another round.
+__global__ void k_plan_rounds_done(int* ctr) {
+  if (threadIdx.x == 0 && ctr[kGSieve] > 0) ctr[kGFlags] |= kErrPlan;
+}
+
+// The finisher's node reservations start after the records made so far.
+__global__ void k_plan_fin_base(int* ctr, const int32_t* res_off, int64_t fin_max) {
+  if (threadIdx.x == 0) {
+    ctr[kGBase] = ctr[kGNodes];
+    ctr[kGNodes] = ctr[kGNodes] + res_off[fin_max];
+  }
+}
+
+__global__ void k_fill_u8(uint8_t* a, int64_t n, uint8_t v) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    a[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* a, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    a[i] = v;
+}
+
+unsigned grid_for(int64_t n, int block) {
+  return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((n + block - 1) / block, INT32_MAX)));
+}
+
+template <int D>
+int plan_enqueue_d(pkd_build_plan* G, hipStream_t st) {
+  pkd_tree* T = G->T;
+  const Params& P = T->prm;
+  const int NB = 1 << P.lambda;
+  const int nheap = 2 << P.lambda;
+  const int s = P.s;
+  const int tile = P.tile;
+  const int cap = 3 * s;
+  const int small_max = 3 * s;
+  const int F = T->cur;
+  const int n_roots = static_cast<int>(G->roots.size());
+  Bufs bufs;
+  for (int b = 0; b < 2; ++b) {
+    bufs.c[b] = T->buf[b];
+    bufs.id[b] = T->buf[b] + static_cast<int64_t>(D) * T->cap;
+    bufs.cap[b] = T->cap;
+  }
+  bufs.c[2] = const_cast<int64_t*>(G->in_c);
+  bufs.id[2] = const_cast<int64_t*>(G->in_id);
+  bufs.cap[2] = G->n;
+  bufs.c32 = T->c32;
+  bufs.c32cap = T->c32_cap;
+  int* ctr = G->ctr;
+  int* d_flags = ctr + kGFlags;
+
+  hipLaunchKernelGGL(k_plan_start, dim3(grid_for(std::max(n_roots, static_cast<int>(kGSlots)), 256)), dim3(256), 0, st,
+                     ctr, n_roots, T->n_trees, G->roots_d, G->front);
+  PKD_TRY(kernel_status("k_plan_start"));
+  Task* front = G->front;
+  Task* next = G->next;
+  int src = 2, dst = 1 - F;
+  const size_t sel_lds = select_lds_bytes<D>(s);
+  const int p2 = std::max(64, next_pow2(s));
+  for (int r = 0; r < G->rounds; ++r) {
+    TraceRange tr("planned sieve round");
+    hipLaunchKernelGGL(k_plan_round, dim3(1), dim3(64), 0, st, ctr);
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(G->front_max, 256)), dim3(256), 0, st, front,
+                       static_cast<int>(G->front_max), s, G->sieve, ctr + kGSieve, G->fin, ctr + kGFin,
+                       ctr + kGFront);
+    PKD_TRY(kernel_status("k_classify"));
+    const int* dns = ctr + kGSieve;
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, G->sieve, 0, tile, G->tile_off, G->chunk_off,
+                       G->shift, s, small_max, static_cast<const int8_t*>(nullptr), G->tot, P.cand_bias, dns);
+    PKD_TRY(kernel_status("k_tile_scan"));
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(G->ns_max, 256)), dim3(256), 0, st,
+                       reinterpret_cast<uint8_t*>(G->shift_fix), G->ns_max, static_cast<uint8_t>(0xFF));
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(G->ns_max, 256)), dim3(256), 0, st,
+                       reinterpret_cast<uint8_t*>(G->mode), G->ns_max, static_cast<uint8_t>(0));
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(G->ns_max * kCntStride, 256)), dim3(256), 0, st, G->cand_cnt,
+                       G->ns_max * kCntStride, 0u);
+    PKD_TRY(kernel_status("k_fill"));
+    const unsigned gt = static_cast<unsigned>(G->ntiles_max);
+    if (tile == 1024)
+      hipLaunchKernelGGL((k_candidates<4>), dim3(gt), dim3(kBlock), 0, st, G->sieve, 0, G->tile_off, bufs, src, P.seed,
+                         G->shift, small_max, G->cand_key, G->cand_pos, G->cand_cnt, cap, dns);
+    else if (tile == 2048)
+      hipLaunchKernelGGL((k_candidates<8>), dim3(gt), dim3(kBlock), 0, st, G->sieve, 0, G->tile_off, bufs, src, P.seed,
+                         G->shift, small_max, G->cand_key, G->cand_pos, G->cand_cnt, cap, dns);
+    else
+      hipLaunchKernelGGL((k_candidates<16>), dim3(gt), dim3(kBlock), 0, st, G->sieve, 0, G->tile_off, bufs, src,
+                         P.seed, G->shift, small_max, G->cand_key, G->cand_pos, G->cand_cnt, cap, dns);
+    PKD_TRY(kernel_status("k_candidates"));
+    SelectOut so{G->rx, G->rdim, G->ext, G->rootext, ctr + kGRootExt, G->shift_fix, d_flags};
+    const unsigned gs = static_cast<unsigned>(G->ns_max);
+#define PKD_PSEL(NPL)                                                                                             \
+  {                                                                                                               \
+    PKD_TRY(allow_lds(k_select_skeleton<D, NPL>, sel_lds));                                                       \
+    hipLaunchKernelGGL((k_select_skeleton<D, NPL>), dim3(gs), dim3(64 * D), sel_lds, st, G->sieve, 0, bufs, src,   \
+                       P.seed, s, P.lambda, G->shift, small_max, G->cand_key, G->cand_pos, G->cand_cnt, cap, so,  \
+                       dns);                                                                                      \
+  }
+    if (p2 <= 64) PKD_PSEL(1)
+    else if (p2 <= 128) PKD_PSEL(2)
+    else if (p2 <= 256) PKD_PSEL(4)
+    else if (p2 <= 512) PKD_PSEL(8)
+    else if (p2 <= 1024) PKD_PSEL(16)
+    else PKD_PSEL(32)
+#undef PKD_PSEL
+    PKD_TRY(kernel_status("k_select_skeleton"));
+    // sieve: count, column-major scan, stable scatter
+    hipLaunchKernelGGL(k_count<D>, dim3(gt), dim3(kBlock), 0, st, G->sieve, 0, G->tile_off, tile, bufs, src, G->rx,
+                       G->rdim, G->mode, P.lambda, G->A, r == 0 ? 1 : 0, d_flags, dns);
+    PKD_TRY(kernel_status("k_count"));
+    const unsigned gc = static_cast<unsigned>(G->nchunks_max);
+    hipLaunchKernelGGL(k_chunk_sum, dim3(gc), dim3(kBlock), 0, st, G->chunk_off, G->tile_off, 0, P.lambda, G->A,
+                       G->S, dns);
+    PKD_TRY(kernel_status("k_chunk_sum"));
+    hipLaunchKernelGGL(k_sp_scan, dim3(gs), dim3(kBlock), 0, st, G->sieve, G->chunk_off, P.lambda, G->S, G->bsize,
+                       G->bstart, dns);
+    PKD_TRY(kernel_status("k_sp_scan"));
+    hipLaunchKernelGGL(k_apply, dim3(gc), dim3(kBlock), 0, st, G->chunk_off, G->tile_off, 0, P.lambda, G->A, G->S,
+                       G->bstart, G->B, dns);
+    PKD_TRY(kernel_status("k_apply"));
+#define PKD_PSCATTER(PPT)                                                                                         \
+  {                                                                                                               \
+    const size_t lds = ScatterLayout(kBlock * (PPT), P.lambda).end;                                              \
+    PKD_TRY(allow_lds(k_scatter<D, PPT>, lds));                                                                   \
+    hipLaunchKernelGGL((k_scatter<D, PPT>), dim3(gt), dim3(kBlock), lds, st, G->sieve, 0, G->tile_off, bufs, src,  \
+                       dst, G->rx, G->rdim, G->mode, P.lambda, G->B, dns);                                        \
+  }
+    if (tile == 2048)
+      PKD_PSCATTER(8)
+    else if (tile == 1024)
+      PKD_PSCATTER(4)
+    else
+      PKD_PSCATTER(16)
+#undef PKD_PSCATTER
+    PKD_TRY(kernel_status("k_scatter"));
+    hipLaunchKernelGGL(k_emit, dim3(gs), dim3(64), 0, st, G->sieve, 0, P.lambda, G->rx, G->rdim, G->ext, G->mode,
+                       G->bsize, G->bstart, dst, T->nodes, ctr + kGNodes, next, ctr + kGNext, G->fin, ctr + kGFin,
+                       d_flags, dns);
+    PKD_TRY(kernel_status("k_emit"));
+    hipLaunchKernelGGL(k_plan_round_end, dim3(1), dim3(64), 0, st, ctr);
+    std::swap(front, next);
+    src = dst;
+    dst = (dst == F) ? 1 - F : F;
+  }
+  // the front left after the last round goes to the finisher; nothing may
+  // still need a sieve round
+  hipLaunchKernelGGL(k_plan_round, dim3(1), dim3(64), 0, st, ctr);
+  hipLaunchKernelGGL(k_classify, dim3(grid_for(G->front_max, 256)), dim3(256), 0, st, front,
+                     static_cast<int>(G->front_max), s, G->sieve, ctr + kGSieve, G->fin, ctr + kGFin, ctr + kGFront);
+  hipLaunchKernelGGL(k_plan_rounds_done, dim3(1), dim3(64), 0, st, ctr);
+  PKD_TRY(kernel_status("k_plan_rounds_done"));
+
+  // finisher over every small subproblem, by size class, in persistent grids
+  TraceRange tr("planned finisher");
+  const int fin_max = static_cast<int>(G->fin_max);
+  hipLaunchKernelGGL(k_bin_finish, dim3(grid_for(fin_max, 256)), dim3(256), 0, st, G->fin, fin_max, G->lists, fin_max,
+                     ctr + kGClass, ctr + kGFin);
+  PKD_TRY(kernel_status("k_bin_finish"));
+  hipLaunchKernelGGL(k_fin_reserve, dim3(grid_for(fin_max, 256)), dim3(256), 0, st, G->fin, fin_max, P.phi, G->R,
+                     ctr + kGFin);
+  PKD_TRY(kernel_status("k_fin_reserve"));
+  PKD_TRY(exscan_i32_raw(st, G->R, G->res_off, fin_max, G->bsum));
+  hipLaunchKernelGGL(k_plan_fin_base, dim3(1), dim3(64), 0, st, ctr, G->res_off, G->fin_max);
+  PKD_TRY(kernel_status("k_plan_fin_base"));
+  for (int cls = 0; cls < 6; ++cls) {
+    const int Pc = 64 << cls;
+    if (Pc / 2 >= s) break;   // classes above the sample size hold no task
+    const size_t lds = finish_lds_bytes<D>(Pc, P.phi);
+    const unsigned gf = static_cast<unsigned>(std::min<int64_t>(G->fin_max, 8192));
+#define PKD_PFIN(NPL)                                                                                             \
+  {                                                                                                               \
+    PKD_TRY(allow_lds(k_finish_persist<D, NPL>, lds));                                                            \
+    hipLaunchKernelGGL((k_finish_persist<D, NPL>), dim3(gf), dim3(64 * D), lds, st, G->fin, G->lists + cls * fin_max, \
+                       ctr + kGClass + cls, Pc, bufs, F, P.phi, T->nodes, ctr + kGNodes, T->node_cap,             \
+                       ctr + kGHeight, d_flags, G->res_off, ctr + kGBase);                                        \
+  }
+    switch (cls) {
+      case 0: PKD_PFIN(1) break;
+      case 1: PKD_PFIN(2) break;
+      case 2: PKD_PFIN(4) break;
+      case 3: PKD_PFIN(8) break;
+      case 4: PKD_PFIN(16) break;
+      case 5: PKD_PFIN(32) break;
+    }
+#undef PKD_PFIN
+    PKD_TRY(kernel_status("k_finish_persist"));
+  }
+  hipLaunchKernelGGL(k_finish_heavy, dim3(static_cast<unsigned>(std::min<int64_t>(G->fin_max, 4096))), dim3(256), 0,
+                     st, G->fin, G->lists + 7 * fin_max, D, bufs, F, T->nodes, ctr + kGHeight, ctr + kGClass + 7);
+  return kernel_status("k_finish_heavy");
+}
+}  // namespace
+
+int plan_size(pkd_build_plan* G) {
+  const Params& P = G->T->prm;
+  if (P.sigma == 0) return PKD_ERR_UNSUPPORTED;   // exact medians split by host-sized passes
+  const int s = P.s;
+  const int64_t NB = int64_t{1} << P.lambda;
+  const int64_t nheap = int64_t{2} << P.lambda;
+  int64_t m_max = 0;
+  for (const Task& t : G->roots) m_max = std::max<int64_t>(m_max, t.m);
+  // rounds: every round divides a subproblem by about 2^lambda; the plan
+  // allows for buckets twice the expected size and one round more
+  int R = 0;
+  for (double m = static_cast<double>(m_max); m >= s; m /= static_cast<double>(NB) / 2.0) ++R;
+  if (R > 0) ++R;
+  G->rounds = R;
+  const int64_t n = G->n, nt = G->T->n_trees;
+  const int64_t sigma = std::max<int64_t>(1, s / NB);
+  G->ns_max = n / s + 1;                                       // sieve subproblems hold at least s points
+  G->front_max = std::max<int64_t>(nt, n / sigma + 1);          // at most 2^lambda buckets per subproblem
+  G->fin_max = std::min<int64_t>(n + 1, nt + static_cast<int64_t>(R + 1) * (n / sigma + 1)) + 1;
+  G->ntiles_max = n / P.tile + G->ns_max + 1;
+  G->nchunks_max = G->ntiles_max / kChunkTiles + G->ns_max + 1;
+  G->cand_len = G->ns_max * 3 * s;
+  const int64_t nodes = nt + static_cast<int64_t>(R) * G->ns_max * nheap + 4 * (n / (P.phi + 1)) + 4 * G->fin_max +
+                        1024;
+  if (nodes >= INT32_MAX || G->fin_max >= INT32_MAX / 8 || G->front_max >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
+  if ((G->fin_max + kScanBlock - 1) / kScanBlock > kScanSumsMax) return PKD_ERR_UNSUPPORTED;
+  PKD_TRY(ensure_nodes(G->T, nullptr, nodes));
+  return PKD_OK;
+}
+
+int plan_enqueue(pkd_build_plan* G, hipStream_t st) {
+  switch (G->T->prm.D) {
+#define PKD_PE(DD) \
+  case DD: return plan_enqueue_d<DD>(G, st);
+    PKD_PE(1) PKD_PE(2) PKD_PE(3) PKD_PE(4) PKD_PE(5) PKD_PE(6) PKD_PE(7) PKD_PE(8) PKD_PE(9)
+#undef PKD_PE
+    default: return PKD_ERR_UNSUPPORTED;
+  }
 }
 
 int build_tasks_dev(pkd_tree* T, hipStream_t st, const Task* d_roots, int n_roots, int src_buf,

@@ -591,6 +591,215 @@ int pkd_build_batch(const pkd_params* params, const pkd_tuning* tuning, void* st
   return PKD_OK;
 }
 
+// ------------------------------------------------ graph build plans
+namespace {
+int plan_block(pkd_build_plan* G, void** p, size_t elem, int64_t count) {
+  void* q = nullptr;
+  PKD_TRY(dev_alloc(&q, elem * static_cast<size_t>(std::max<int64_t>(count, 1)), nullptr));
+  G->blocks.push_back(q);
+  *p = q;
+  return PKD_OK;
+}
+#define PKD_PLAN_ALLOC(G, field, count) \
+  plan_block((G), reinterpret_cast<void**>(&(G)->field), sizeof(*(G)->field), (count))
+
+void plan_release(pkd_build_plan* G) {
+  (void)hipDeviceSynchronize();
+  for (void* q : G->blocks) dev_free(q, nullptr);
+  G->blocks.clear();
+  if (G->T) {
+    release(G->T, nullptr);
+    delete G->T;
+    G->T = nullptr;
+  }
+  (void)hipDeviceSynchronize();
+}
+}  // namespace
+
+int pkd_build_plan_create(const pkd_params* params, const pkd_tuning* tuning, int32_t n_trees, const int64_t* offsets,
+                          pkd_build_plan** out) {
+  TraceRange tr("pkd_build_plan_create");
+  if (!out) return PKD_ERR_INVALID_ARG;
+  *out = nullptr;
+  Params prm;
+  PKD_TRY(check_params(params, tuning, &prm));
+  if (n_trees < 1 || !offsets || offsets[0] != 0) return PKD_ERR_INVALID_ARG;
+  for (int32_t t = 0; t < n_trees; ++t)
+    if (offsets[t + 1] < offsets[t]) return PKD_ERR_INVALID_ARG;
+  const int64_t n = offsets[n_trees];
+  if (n >= INT32_MAX || n_trees >= INT32_MAX / 2) return PKD_ERR_UNSUPPORTED;
+  pkd_build_plan* G = new pkd_build_plan;
+  G->n = n;
+  G->T = new pkd_tree;
+  pkd_tree* T = G->T;
+  T->prm = prm;
+  T->n_trees = n_trees;
+  T->plan_owned = true;
+  std::vector<Node> empty(n_trees);
+  for (int32_t t = 0; t < n_trees; ++t) {
+    std::memset(&empty[t], 0, sizeof(Node));
+    empty[t].left = empty[t].right = -1;
+    empty[t].dim = -1;
+    empty[t].off = static_cast<int32_t>(offsets[t]);
+    if (offsets[t + 1] > offsets[t]) {
+      Task r;
+      r.start = static_cast<int32_t>(offsets[t]);
+      r.m = static_cast<int32_t>(offsets[t + 1] - offsets[t]);
+      r.slot = t;
+      r.depth = 0;
+      r.buf = 2;
+      r.mode = 0;
+      G->roots.push_back(r);
+    }
+  }
+  const int D = prm.D;
+  const int64_t NB = int64_t{1} << prm.lambda;
+  int rc = alloc_points(T, nullptr, std::max<int64_t>(n, 1));
+  if (rc == PKD_OK) rc = ensure_c32(T, nullptr);
+  if (rc == PKD_OK) rc = plan_size(G);   // also sizes the node array
+  if (rc == PKD_OK)
+    rc = hipMemcpy(T->nodes, empty.data(), sizeof(Node) * n_trees, hipMemcpyHostToDevice) == hipSuccess
+             ? PKD_OK : PKD_ERR_HIP;
+  const int64_t nb = (G->fin_max + 2047) / 2048 + 2;
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, roots_d, static_cast<int64_t>(G->roots.size()));
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, front, G->front_max);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, next, G->front_max);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, sieve, G->ns_max);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, fin, G->fin_max);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, ctr, 64);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, rx, G->ns_max * NB);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, tile_off, G->ns_max + 1);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, chunk_off, G->ns_max + 1);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, tot, 2);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, rdim, G->ns_max * NB);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, ext, G->ns_max * 2 * NB);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, mode, G->ns_max);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, shift, G->ns_max);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, shift_fix, G->ns_max);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, rootext, G->ns_max);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, cand_key, G->cand_len);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, cand_pos, G->cand_len);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, cand_cnt, G->ns_max * 32);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, A, G->ntiles_max * NB);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, B, G->ntiles_max * NB);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, S, G->nchunks_max * NB);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, bsize, G->ns_max * NB);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, bstart, G->ns_max * NB);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, R, G->fin_max + 1);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, res_off, G->fin_max + 1);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, bsum, nb);
+  if (rc == PKD_OK) rc = PKD_PLAN_ALLOC(G, lists, 8 * G->fin_max);
+  if (rc == PKD_OK && !G->roots.empty())
+    rc = hipMemcpy(G->roots_d, G->roots.data(), sizeof(Task) * G->roots.size(), hipMemcpyHostToDevice) == hipSuccess
+             ? PKD_OK : PKD_ERR_HIP;
+  if (rc == PKD_OK) rc = hipDeviceSynchronize() == hipSuccess ? PKD_OK : PKD_ERR_HIP;
+  (void)D;
+  T->n = n;                    // fixed for the plan: the trees' sizes
+  T->node_count = n_trees;     // the roots, until the first build is finished
+  T->compact_mark = n_trees;
+  if (rc != PKD_OK) {
+    plan_release(G);
+    delete G;
+    return rc;
+  }
+  *out = G;
+  return PKD_OK;
+}
+
+int pkd_build_plan_enqueue(pkd_build_plan* plan, void* stream, const int64_t* coords, const int64_t* ids) {
+  TraceRange tr("pkd_build_plan_enqueue");
+  if (!plan) return PKD_ERR_INVALID_ARG;
+  if (plan->n > 0 && (!coords || !ids)) return PKD_ERR_INVALID_ARG;
+  plan->in_c = coords;
+  plan->in_id = ids;
+  return plan_enqueue(plan, static_cast<hipStream_t>(stream));
+}
+
+int pkd_build_plan_finish(pkd_build_plan* plan, void* stream, int32_t* redone) {
+  TraceRange tr("pkd_build_plan_finish");
+  if (redone) *redone = 0;
+  if (!plan) return PKD_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  pkd_tree* T = plan->T;
+  int h[8] = {0};
+  PKD_HIP(hipMemcpyAsync(h, plan->ctr, sizeof(h), hipMemcpyDeviceToHost, st));
+  PKD_HIP(hipStreamSynchronize(st));
+  const int flags = h[4];
+  if (flags & kErrRange) {
+    T->node_count = T->n_trees;   // no tree: the roots only (as created)
+    return PKD_ERR_RANGE;
+  }
+  // any other flag but an internal error alone marks a case the sized
+  // launches do not cover (the rounds after it may then have found empty
+  // buckets too): the usual build redoes it and reports its own errors
+  if (flags == kErrInternal) {
+    T->node_count = T->n_trees;
+    return PKD_ERR_INTERNAL;
+  }
+  if (flags) {
+    // a case the sized launches do not cover: build the usual way, then copy
+    // the result into the plan's arrays (their addresses are the captured ones)
+    pkd_tree* Z = nullptr;
+    pkd_params p;
+    pkd_default_params(&p, T->prm.D);
+    p.lambda = T->prm.lambda;
+    p.leaf_size = T->prm.phi;
+    p.oversample = T->prm.sigma;
+    p.alpha_num = T->prm.alpha_num;
+    p.alpha_den = T->prm.alpha_den;
+    p.seed = T->prm.seed;
+    pkd_tuning tu;
+    pkd_default_tuning(&tu);
+    tu.tile_points = T->prm.tile;
+    tu.cand_shift_bias = T->prm.cand_bias;
+    std::vector<int64_t> offs(static_cast<size_t>(T->n_trees) + 1, 0);
+    {
+      // offsets from the roots (empty trees hold no task)
+      std::vector<int64_t> sizes(T->n_trees, 0);
+      for (const Task& r : plan->roots) sizes[r.slot] = r.m;
+      for (int32_t t = 0; t < T->n_trees; ++t) offs[t + 1] = offs[t] + sizes[t];
+    }
+    PKD_TRY(pkd_build_batch(&p, &tu, stream, T->n_trees, plan->in_c, plan->in_id, offs.data(), &Z));
+    int rc = PKD_OK;
+    if (Z->node_count > T->node_cap) rc = PKD_ERR_CAPACITY;
+    const int D = T->prm.D;
+    if (rc == PKD_OK && Z->node_count > 0)
+      rc = hipMemcpyAsync(T->nodes, Z->nodes, sizeof(Node) * Z->node_count, hipMemcpyDeviceToDevice, st) == hipSuccess
+               ? PKD_OK : PKD_ERR_HIP;
+    for (int d = 0; d <= D && rc == PKD_OK && plan->n > 0; ++d)
+      rc = hipMemcpyAsync(T->buf[T->cur] + static_cast<int64_t>(d) * T->cap, Z->buf[Z->cur] + static_cast<int64_t>(d) * Z->cap,
+                          sizeof(int64_t) * plan->n, hipMemcpyDeviceToDevice, st) == hipSuccess ? PKD_OK : PKD_ERR_HIP;
+    if (rc == PKD_OK && plan->n > 0)
+      rc = hipMemcpyAsync(T->c32, Z->c32, sizeof(int32_t) * D * plan->n, hipMemcpyDeviceToDevice, st) == hipSuccess
+               ? PKD_OK : PKD_ERR_HIP;
+    if (rc == PKD_OK) {
+      T->node_count = Z->node_count;
+      T->height = Z->height;
+    }
+    if (rc == PKD_OK) rc = hipStreamSynchronize(st) == hipSuccess ? PKD_OK : PKD_ERR_HIP;
+    pkd_free(Z);
+    if (rc != PKD_OK) return rc;
+    if (redone) *redone = 1;
+  } else {
+    T->node_count = h[3];
+    T->height = h[6];
+  }
+  T->compact_mark = T->node_count;
+  return PKD_OK;
+}
+
+int pkd_build_plan_tree(pkd_build_plan* plan, pkd_tree** tree) {
+  if (!plan || !tree) return PKD_ERR_INVALID_ARG;
+  *tree = plan->T;
+  return PKD_OK;
+}
+
+void pkd_build_plan_free(pkd_build_plan* plan) {
+  if (!plan) return;
+  plan_release(plan);
+  delete plan;
+}
+
 int pkd_num_trees(const pkd_tree* tree, int32_t* n_trees) {
   if (!tree || !n_trees) return PKD_ERR_INVALID_ARG;
   *n_trees = tree->n_trees;
@@ -600,7 +809,7 @@ int pkd_num_trees(const pkd_tree* tree, int32_t* n_trees) {
 int pkd_batch_insert_tree(pkd_tree* tree, int32_t t, void* stream, const int64_t* coords, const int64_t* ids,
                           int64_t m) {
   TraceRange tr("pkd_batch_insert");
-  if (!tree || m < 0 || t < 0 || t >= tree->n_trees) return PKD_ERR_INVALID_ARG;
+  if (!tree || m < 0 || t < 0 || t >= tree->n_trees || tree->plan_owned) return PKD_ERR_INVALID_ARG;
   if (m == 0) return PKD_OK;
   if (!coords || !ids) return PKD_ERR_INVALID_ARG;
   if (tree->n + m >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
@@ -615,7 +824,7 @@ int pkd_batch_delete_tree(pkd_tree* tree, int32_t t, void* stream, const int64_t
                           int64_t m, int64_t* n_deleted) {
   TraceRange tr("pkd_batch_delete");
   if (n_deleted) *n_deleted = 0;
-  if (!tree || m < 0 || t < 0 || t >= tree->n_trees) return PKD_ERR_INVALID_ARG;
+  if (!tree || m < 0 || t < 0 || t >= tree->n_trees || tree->plan_owned) return PKD_ERR_INVALID_ARG;
   if (m == 0) return PKD_OK;
   if (!coords || !ids) return PKD_ERR_INVALID_ARG;
   if (m >= INT32_MAX) return PKD_ERR_UNSUPPORTED;
@@ -756,7 +965,7 @@ int pkd_profile_get(int32_t kernel, int64_t* launches, double* total_ms, double*
 }
 
 void pkd_free(pkd_tree* tree) {
-  if (!tree) return;
+  if (!tree || tree->plan_owned) return;   // a plan's tree goes with its plan
   (void)hipDeviceSynchronize();
   release(tree, nullptr);
   (void)hipDeviceSynchronize();
@@ -765,6 +974,7 @@ void pkd_free(pkd_tree* tree) {
 
 int pkd_free_async(pkd_tree* tree, void* stream) {
   if (!tree) return PKD_OK;
+  if (tree->plan_owned) return PKD_ERR_INVALID_ARG;
   // every block goes back with an event on `stream`: its next user waits for
   // the work enqueued on `stream` before this call
   release(tree, static_cast<hipStream_t>(stream));
@@ -781,7 +991,7 @@ int pkd_set_allocator(const pkd_allocator* a) {
 }
 
 int pkd_set_bbox(pkd_tree* tree, void* stream, int32_t on) {
-  if (!tree) return PKD_ERR_INVALID_ARG;
+  if (!tree || tree->plan_owned) return PKD_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!on) {
     tree->bbox_on = false;

@@ -156,10 +156,50 @@ struct pkd_tree {
   int32_t* bbox = nullptr;
   int64_t bbox_cap = 0;
   bool bbox_on = false;
+  // the tree of a graph build plan: its arrays are the ones the captured
+  // launches write, so it is never updated, reallocated or freed on its own
+  bool plan_owned = false;
+};
+
+// A batch build whose launches need no host read: every round's work is
+// sized for the most it can hold, counts stay in device memory, so the whole
+// build can be captured into a graph and replayed on new points of the same
+// trees.  Rare cases the sized launches do not cover (a sampler retry, a
+// sample of identical points, more rounds than planned, more node records
+// than reserved) are flagged and the build is redone the usual way at finish.
+struct pkd_build_plan {
+  pkd_tree* T = nullptr;
+  std::vector<pkd::Task> roots;    // root tasks (points of tree t at its offset)
+  int64_t n = 0;                   // points of all trees
+  int rounds = 0;                  // sieve rounds enqueued
+  int64_t ns_max = 0, front_max = 0, fin_max = 0, ntiles_max = 0, nchunks_max = 0, cand_len = 0;
+  const int64_t* in_c = nullptr;   // the inputs of the last enqueue
+  const int64_t* in_id = nullptr;
+  // device workspace
+  pkd::Task *roots_d = nullptr, *front = nullptr, *next = nullptr, *sieve = nullptr, *fin = nullptr;
+  int* ctr = nullptr;              // counters, see the driver
+  int64_t *rx = nullptr, *tile_off = nullptr, *chunk_off = nullptr, *tot = nullptr;
+  uint8_t* rdim = nullptr;
+  int8_t *ext = nullptr, *mode = nullptr, *shift = nullptr, *shift_fix = nullptr;
+  int* rootext = nullptr;
+  uint64_t* cand_key = nullptr;
+  uint32_t *cand_pos = nullptr, *cand_cnt = nullptr, *A = nullptr, *S = nullptr;
+  int32_t *B = nullptr, *bsize = nullptr, *bstart = nullptr, *R = nullptr, *res_off = nullptr, *bsum = nullptr;
+  int* lists = nullptr;
+  std::vector<void*> blocks;       // every block of the workspace
 };
 
 // ---- host helpers shared by the sources (defined in pkd_api.hip) -----------
 namespace pkd {
+// The bounds query launches take from a tree.  Launches captured into a graph
+// keep their arguments, so on a build plan's tree (rebuilt by every replay)
+// they take the plan's limits: every node record it can hold, and the
+// deepest traversal stack.
+inline int32_t query_nodes(const pkd_tree* T) {
+  return T->plan_owned ? static_cast<int32_t>(T->node_cap) : T->node_count;
+}
+inline int32_t query_height(const pkd_tree* T) { return T->plan_owned ? kMaxStack - 3 : T->height; }
+
 int hip_status(hipError_t e, const char* what);
 #define PKD_HIP(call)                                   \
   do {                                                  \
@@ -289,6 +329,9 @@ int ensure_nodes(pkd_tree* tree, hipStream_t st, int64_t need);
 // built from caller input (headroom: room for a sixteenth more points);
 // exchange the storage of two trees.
 int alloc_points(pkd_tree* T, hipStream_t st, int64_t cap);
+// Graph build plans (build.hip): workspace sizes and the enqueue of one build.
+int plan_size(pkd_build_plan* G);
+int plan_enqueue(pkd_build_plan* G, hipStream_t st);
 void release(pkd_tree* T, hipStream_t st);
 int build_new(const Params& prm, hipStream_t st, const int64_t* coords, const int64_t* ids, int64_t n,
               bool headroom, pkd_tree** out);

@@ -1008,15 +1008,15 @@ int knn_launch(const pkd_tree* T, hipStream_t st, const int64_t* q, const int32_
   // stored boxes prune the one-lane kernel (k <= 32); the one-wave kernel
   // keeps the cells derived from the splitters (same results)
   const int32_t* bb = T->bbox_on ? T->bbox : nullptr;
-  if (T->height + 2 <= 32)
+  if (query_height(T) + 2 <= 32)
     launch_knn<D, 32>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
-                      T->node_count, T->n, perm, bb);
-  else if (T->height + 2 <= 64)
+                      query_nodes(T), T->n, perm, bb);
+  else if (query_height(T) + 2 <= 64)
     launch_knn<D, 64>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
-                      T->node_count, T->n, perm, bb);
-  else if (T->height + 2 <= kMaxStack)
+                      query_nodes(T), T->n, perm, bb);
+  else if (query_height(T) + 2 <= kMaxStack)
     launch_knn<D, kMaxStack>(km, g, st, T->nodes, X, T->cap, ids, q, nq, k, oi, od, flags, tree_of, T->n_trees,
-                             T->node_count, T->n, perm, bb);
+                             query_nodes(T), T->n, perm, bb);
   else
     return PKD_ERR_CAPACITY;
   hipError_t e = hipGetLastError();
@@ -1048,13 +1048,13 @@ int range_d(const pkd_tree* T, hipStream_t st, const int64_t* lo, const int64_t*
 #define PKD_RANGE(SD)                                                                                             \
   if (per_wave)                                                                                                   \
     hipLaunchKernelGGL((k_range_wave<D, SD>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags, \
-                       tree_of, T->n_trees, T->prm.phi, T->node_count, T->n, perm, bb);                            \
+                       tree_of, T->n_trees, T->prm.phi, query_nodes(T), T->n, perm, bb);                            \
   else                                                                                                            \
     hipLaunchKernelGGL((k_range<D, SD>), g, dim3(kQBlock), 0, st, T->nodes, X, T->cap, lo, hi, nb, out, flags,      \
-                       tree_of, T->n_trees, T->prm.phi, T->node_count, T->n, perm, bb);
-  if (T->height + 3 <= 48) {
+                       tree_of, T->n_trees, T->prm.phi, query_nodes(T), T->n, perm, bb);
+  if (query_height(T) + 3 <= 48) {
     PKD_RANGE(48)
-  } else if (T->height + 3 <= kMaxStack) {
+  } else if (query_height(T) + 3 <= kMaxStack) {
     PKD_RANGE(kMaxStack)
   } else {
     return PKD_ERR_CAPACITY;

@@ -239,14 +239,22 @@ def test_updates_on_a_tree_above_2_27_points(pk):
     keep[did] = False
     allc = torch.cat([c[:, keep], nc], dim=1)
     alli = torch.cat([ids[keep], nid])
-    q = torch.from_numpy(synth.uniform_queries(6, D, seed=5)).cuda()
+    # no point lost or duplicated by the relayout: every id is reported once
+    # in the box of the whole domain (range report, a different kernel)
+    full_lo = torch.zeros((D, 1), dtype=torch.int64, device="cuda")
+    full_hi = torch.full((D, 1), (1 << 30) - 1, dtype=torch.int64, device="cuda")
+    off, rid = t.range_report(full_lo, full_hi)
+    assert int(off[-1]) == n0
+    assert torch.equal(torch.sort(rid).values, torch.sort(alli).values)
+    del rid
+    q = torch.from_numpy(synth.uniform_queries(32, D, seed=5)).cuda()
     gi, gd = t.knn(q, 10)
     for j in range(q.shape[1]):
         d2 = ((allc - q[:, j:j + 1]) ** 2).sum(0)
         top = torch.topk(-d2, 64).indices
         cand = sorted(zip(d2[top].tolist(), alli[top].tolist()))[:10]
         assert gd[j].tolist() == [x for x, _ in cand] and gi[j].tolist() == [y for _, y in cand], j
-    lo, hi = (torch.from_numpy(x).cuda() for x in synth.log_uniform_boxes(6, D, seed=6))
+    lo, hi = (torch.from_numpy(x).cuda() for x in synth.log_uniform_boxes(32, D, seed=6))
     rc = t.range_count(lo, hi)
     for j in range(lo.shape[1]):
         inside = ((allc >= lo[:, j:j + 1]) & (allc <= hi[:, j:j + 1])).all(0).sum().item()
