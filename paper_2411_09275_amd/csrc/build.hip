@@ -42,6 +42,32 @@ __device__ inline int wave_append(bool take, int* counter) {
   return take ? base + static_cast<int>(__popcll(mask & ((1ULL << lane_id()) - 1))) : -1;
 }
 
+// wave_append for a whole workgroup: one counter update per workgroup (one
+// per wave serializes on the counter when tens of thousands of waves append).
+// Every thread of the workgroup calls it.
+__device__ inline int block_append(bool take, int* counter) {
+  __shared__ int wc[16];
+  __shared__ int base;
+  const int wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  const unsigned long long m = __ballot(take);
+  const int rank = static_cast<int>(__popcll(m & ((1ULL << (threadIdx.x & 63)) - 1)));
+  if ((threadIdx.x & 63) == 0) wc[wave] = static_cast<int>(__popcll(m));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < nw; ++w) {
+      const int x = wc[w];
+      wc[w] = run;
+      run += x;
+    }
+    base = run ? atomicAdd(counter, run) : 0;
+  }
+  __syncthreads();
+  const int at = take ? base + wc[wave] + rank : -1;
+  __syncthreads();   // the next call reuses wc and base
+  return at;
+}
+
 template <int D>
 __device__ inline int64_t pick(const int64_t (&c)[D], int d) {
   int64_t v = c[0];
@@ -102,8 +128,8 @@ __global__ void k_classify(const Task* front, int n_front, int s, Task* sieve, i
   const bool ok = i < n_front;
   Task t{};
   if (ok) t = front[i];
-  const int a = wave_append(ok && t.m >= s, n_sieve);
-  const int b = wave_append(ok && t.m < s, n_fin);
+  const int a = block_append(ok && t.m >= s, n_sieve);
+  const int b = block_append(ok && t.m < s, n_fin);
   if (a >= 0) sieve[a] = t;
   if (b >= 0) fin[b] = t;
 }
@@ -1371,7 +1397,15 @@ template <int D, int NPL>
 __global__ void __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(NPL <= 8 ? 8 : 1))) k_finish(const Task* tasks, const int* list, int P, Bufs bufs, int final_buf,
                                                      int phi, Node* nodes, int* overflow_ctr, int64_t node_cap,
                                                      int* height, int* flags, const int32_t* res_off,
-                                                     int32_t res_base) {
+                                                     int32_t res_base, const int* count = nullptr,
+                                                     const int* res_base_d = nullptr) {
+  // with `count` set (launches sized for the most tasks the class can hold)
+  // the blocks past the class's count leave, and the reservation base is the
+  // one in device memory
+  if (count) {
+    if (static_cast<int>(blockIdx.x) >= *count) return;
+    res_base = *res_base_d;
+  }
   finish_task<D, NPL>(list[blockIdx.x], tasks, P, bufs, final_buf, phi, nodes, overflow_ctr, node_cap, height, flags,
                       res_off, res_base);
 }
@@ -1387,7 +1421,11 @@ __global__ void __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(NPL
   const int n = *count;
   const int32_t base = *res_base;
   for (int b = blockIdx.x; b < n; b += gridDim.x) {
-    finish_task<D, NPL>(list[b], tasks, P, bufs, final_buf, phi, nodes, overflow_ctr, node_cap, height, flags,
+    // the layout and everything derived from (P, phi) are recomputed per
+    // task: hoisted out of the loop they stayed live and spilled
+    int P_t = P, phi_t = phi;
+    asm volatile("" : "+s"(P_t), "+s"(phi_t));
+    finish_task<D, NPL>(list[b], tasks, P_t, bufs, final_buf, phi_t, nodes, overflow_ctr, node_cap, height, flags,
                         res_off, base);
     __syncthreads();   // the next task reuses the LDS
   }
@@ -1456,10 +1494,31 @@ __global__ void k_bin_finish(const Task* fin, int n_fin, int* lists, int stride,
       while ((64 << cls) < t.m) ++cls;
     }
   }
+  // one counter update per class and workgroup (one per wave serialized
+  // tens of thousands of atomics on each of the 8 counters)
+  __shared__ int wcnt[8][16];
+  __shared__ int wbase[8];
+  const int wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  const unsigned long long below = (1ULL << (threadIdx.x & 63)) - 1;
+  int rank = 0;
   for (int c = 0; c < 8; ++c) {
-    const int at = wave_append(cls == c, counts + c);
-    if (at >= 0) lists[c * stride + at] = i;
+    const unsigned long long m = __ballot(cls == c);
+    if (cls == c) rank = static_cast<int>(__popcll(m & below));
+    if ((threadIdx.x & 63) == 0) wcnt[c][wave] = static_cast<int>(__popcll(m));
   }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int c = threadIdx.x;
+    int run = 0;
+    for (int w = 0; w < nw; ++w) {
+      const int x = wcnt[c][w];
+      wcnt[c][w] = run;
+      run += x;
+    }
+    wbase[c] = run ? atomicAdd(counts + c, run) : 0;
+  }
+  __syncthreads();
+  if (cls >= 0) lists[cls * stride + wbase[cls] + wcnt[cls][wave] + rank] = i;
 }
 
 // ------------------------------------------- segmented exact split
@@ -1915,7 +1974,7 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
     PKD_TRY(lists.need(static_cast<size_t>(8) * n_fin + 8));
     int* d_counts = ctr.p + 8;
     PKD_HIP(hipMemsetAsync(d_counts, 0, sizeof(int) * 8, st));
-    hipLaunchKernelGGL(k_bin_finish, dim3((n_fin + 255) / 256), dim3(256), 0, st, fin.p, n_fin, lists.p, n_fin,
+    hipLaunchKernelGGL(k_bin_finish, dim3((n_fin + 1023) / 1024), dim3(1024), 0, st, fin.p, n_fin, lists.p, n_fin,
                        d_counts);
     PKD_TRY(kernel_status("k_bin_finish"));
     int counts[8];
@@ -2492,25 +2551,30 @@ int plan_enqueue_d(pkd_build_plan* G, hipStream_t st) {
   int src = 2, dst = 1 - F;
   const size_t sel_lds = select_lds_bytes<D>(s);
   const int p2 = std::max(64, next_pow2(s));
+  // bounds of round r: at most n/s sieve subproblems, and at most
+  // 2^lambda times as many tasks as the round before (the roots in round 0)
+  int64_t front_r = n_roots;
   for (int r = 0; r < G->rounds; ++r) {
     TraceRange tr("planned sieve round");
+    const int64_t ns_r = std::min<int64_t>(G->ns_max, front_r);
+    const int64_t ntiles_r = std::min<int64_t>(G->ntiles_max, G->n / tile + ns_r + 1);
+    const int64_t nchunks_r = std::min<int64_t>(G->nchunks_max, ntiles_r / kChunkTiles + ns_r + 1);
     hipLaunchKernelGGL(k_plan_round, dim3(1), dim3(64), 0, st, ctr);
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(G->front_max, 256)), dim3(256), 0, st, front,
-                       static_cast<int>(G->front_max), s, G->sieve, ctr + kGSieve, G->fin, ctr + kGFin,
-                       ctr + kGFront);
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(front_r, 256)), dim3(256), 0, st, front,
+                       static_cast<int>(front_r), s, G->sieve, ctr + kGSieve, G->fin, ctr + kGFin, ctr + kGFront);
     PKD_TRY(kernel_status("k_classify"));
     const int* dns = ctr + kGSieve;
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, G->sieve, 0, tile, G->tile_off, G->chunk_off,
                        G->shift, s, small_max, static_cast<const int8_t*>(nullptr), G->tot, P.cand_bias, dns);
     PKD_TRY(kernel_status("k_tile_scan"));
-    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(G->ns_max, 256)), dim3(256), 0, st,
-                       reinterpret_cast<uint8_t*>(G->shift_fix), G->ns_max, static_cast<uint8_t>(0xFF));
-    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(G->ns_max, 256)), dim3(256), 0, st,
-                       reinterpret_cast<uint8_t*>(G->mode), G->ns_max, static_cast<uint8_t>(0));
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(G->ns_max * kCntStride, 256)), dim3(256), 0, st, G->cand_cnt,
-                       G->ns_max * kCntStride, 0u);
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(ns_r, 256)), dim3(256), 0, st,
+                       reinterpret_cast<uint8_t*>(G->shift_fix), ns_r, static_cast<uint8_t>(0xFF));
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(ns_r, 256)), dim3(256), 0, st, reinterpret_cast<uint8_t*>(G->mode),
+                       ns_r, static_cast<uint8_t>(0));
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(ns_r * kCntStride, 256)), dim3(256), 0, st, G->cand_cnt,
+                       ns_r * kCntStride, 0u);
     PKD_TRY(kernel_status("k_fill"));
-    const unsigned gt = static_cast<unsigned>(G->ntiles_max);
+    const unsigned gt = static_cast<unsigned>(ntiles_r);
     if (tile == 1024)
       hipLaunchKernelGGL((k_candidates<4>), dim3(gt), dim3(kBlock), 0, st, G->sieve, 0, G->tile_off, bufs, src, P.seed,
                          G->shift, small_max, G->cand_key, G->cand_pos, G->cand_cnt, cap, dns);
@@ -2522,7 +2586,7 @@ int plan_enqueue_d(pkd_build_plan* G, hipStream_t st) {
                          P.seed, G->shift, small_max, G->cand_key, G->cand_pos, G->cand_cnt, cap, dns);
     PKD_TRY(kernel_status("k_candidates"));
     SelectOut so{G->rx, G->rdim, G->ext, G->rootext, ctr + kGRootExt, G->shift_fix, d_flags};
-    const unsigned gs = static_cast<unsigned>(G->ns_max);
+    const unsigned gs = static_cast<unsigned>(ns_r);
 #define PKD_PSEL(NPL)                                                                                             \
   {                                                                                                               \
     PKD_TRY(allow_lds(k_select_skeleton<D, NPL>, sel_lds));                                                       \
@@ -2542,7 +2606,7 @@ int plan_enqueue_d(pkd_build_plan* G, hipStream_t st) {
     hipLaunchKernelGGL(k_count<D>, dim3(gt), dim3(kBlock), 0, st, G->sieve, 0, G->tile_off, tile, bufs, src, G->rx,
                        G->rdim, G->mode, P.lambda, G->A, r == 0 ? 1 : 0, d_flags, dns);
     PKD_TRY(kernel_status("k_count"));
-    const unsigned gc = static_cast<unsigned>(G->nchunks_max);
+    const unsigned gc = static_cast<unsigned>(nchunks_r);
     hipLaunchKernelGGL(k_chunk_sum, dim3(gc), dim3(kBlock), 0, st, G->chunk_off, G->tile_off, 0, P.lambda, G->A,
                        G->S, dns);
     PKD_TRY(kernel_status("k_chunk_sum"));
@@ -2572,6 +2636,7 @@ int plan_enqueue_d(pkd_build_plan* G, hipStream_t st) {
                        d_flags, dns);
     PKD_TRY(kernel_status("k_emit"));
     hipLaunchKernelGGL(k_plan_round_end, dim3(1), dim3(64), 0, st, ctr);
+    front_r = std::min<int64_t>(G->front_max, ns_r << P.lambda);
     std::swap(front, next);
     src = dst;
     dst = (dst == F) ? 1 - F : F;
@@ -2579,16 +2644,16 @@ int plan_enqueue_d(pkd_build_plan* G, hipStream_t st) {
   // the front left after the last round goes to the finisher; nothing may
   // still need a sieve round
   hipLaunchKernelGGL(k_plan_round, dim3(1), dim3(64), 0, st, ctr);
-  hipLaunchKernelGGL(k_classify, dim3(grid_for(G->front_max, 256)), dim3(256), 0, st, front,
-                     static_cast<int>(G->front_max), s, G->sieve, ctr + kGSieve, G->fin, ctr + kGFin, ctr + kGFront);
+  hipLaunchKernelGGL(k_classify, dim3(grid_for(front_r, 256)), dim3(256), 0, st, front, static_cast<int>(front_r), s,
+                     G->sieve, ctr + kGSieve, G->fin, ctr + kGFin, ctr + kGFront);
   hipLaunchKernelGGL(k_plan_rounds_done, dim3(1), dim3(64), 0, st, ctr);
   PKD_TRY(kernel_status("k_plan_rounds_done"));
 
   // finisher over every small subproblem, by size class, in persistent grids
   TraceRange tr("planned finisher");
   const int fin_max = static_cast<int>(G->fin_max);
-  hipLaunchKernelGGL(k_bin_finish, dim3(grid_for(fin_max, 256)), dim3(256), 0, st, G->fin, fin_max, G->lists, fin_max,
-                     ctr + kGClass, ctr + kGFin);
+  hipLaunchKernelGGL(k_bin_finish, dim3(grid_for(fin_max, 1024)), dim3(1024), 0, st, G->fin, fin_max, G->lists,
+                     fin_max, ctr + kGClass, ctr + kGFin);
   PKD_TRY(kernel_status("k_bin_finish"));
   hipLaunchKernelGGL(k_fin_reserve, dim3(grid_for(fin_max, 256)), dim3(256), 0, st, G->fin, fin_max, P.phi, G->R,
                      ctr + kGFin);
@@ -2600,13 +2665,25 @@ int plan_enqueue_d(pkd_build_plan* G, hipStream_t st) {
     const int Pc = 64 << cls;
     if (Pc / 2 >= s) break;   // classes above the sample size hold no task
     const size_t lds = finish_lds_bytes<D>(Pc, P.phi);
+    // a task of class cls >= 1 holds more than Pc/2 points, so the class has
+    // at most n/(Pc/2+1) tasks: one workgroup each, as in the eager build
+    // (blocks past the count leave at once).  Class 0 (up to 64 points, with
+    // no such bound) runs in a persistent grid that walks its list.
     const unsigned gf = static_cast<unsigned>(std::min<int64_t>(G->fin_max, 8192));
+    const unsigned gb = static_cast<unsigned>(std::min<int64_t>(G->fin_max, G->n / (Pc / 2 + 1) + 1));
 #define PKD_PFIN(NPL)                                                                                             \
   {                                                                                                               \
-    PKD_TRY(allow_lds(k_finish_persist<D, NPL>, lds));                                                            \
-    hipLaunchKernelGGL((k_finish_persist<D, NPL>), dim3(gf), dim3(64 * D), lds, st, G->fin, G->lists + cls * fin_max, \
-                       ctr + kGClass + cls, Pc, bufs, F, P.phi, T->nodes, ctr + kGNodes, T->node_cap,             \
-                       ctr + kGHeight, d_flags, G->res_off, ctr + kGBase);                                        \
+    if (cls == 0) {                                                                                               \
+      PKD_TRY(allow_lds(k_finish_persist<D, NPL>, lds));                                                          \
+      hipLaunchKernelGGL((k_finish_persist<D, NPL>), dim3(gf), dim3(64 * D), lds, st, G->fin,                     \
+                         G->lists + cls * fin_max, ctr + kGClass + cls, Pc, bufs, F, P.phi, T->nodes,             \
+                         ctr + kGNodes, T->node_cap, ctr + kGHeight, d_flags, G->res_off, ctr + kGBase);          \
+    } else {                                                                                                      \
+      PKD_TRY(allow_lds(k_finish<D, NPL>, lds));                                                                  \
+      hipLaunchKernelGGL((k_finish<D, NPL>), dim3(gb), dim3(64 * D), lds, st, G->fin, G->lists + cls * fin_max,  \
+                         Pc, bufs, F, P.phi, T->nodes, ctr + kGNodes, T->node_cap, ctr + kGHeight, d_flags,       \
+                         G->res_off, 0, ctr + kGClass + cls, ctr + kGBase);                                       \
+    }                                                                                                             \
   }
     switch (cls) {
       case 0: PKD_PFIN(1) break;
