@@ -318,44 +318,77 @@ __device__ void wave_partition(bool active, uint16_t* Od, int m, const uint16_t*
                                const uint16_t* segA, const uint16_t* segNL, const uint8_t* flag, uint16_t* segF) {
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = (1ULL << lane) - 1;
+  // Positions are taken in chunks of CH rows.  Every load is unconditional,
+  // on an index kept inside its array (positions below 64*NPL, the row
+  // length; segment 0 standing in where there is none), so the loads of a
+  // chunk issue back to back with no branches; values of positions >= m are
+  // dropped afterwards.
+  constexpr int CH = NPL < 2 ? NPL : 2;
   // per position: point | rank << 16, and segment | side << 16 (kNone: stays)
   uint32_t pe[NPL], ks[NPL];
   if (active) {
     int run = 0;
 #pragma unroll
-    for (int r = 0; r < NPL; ++r) {
-      pe[r] = 0;
-      ks[r] = kNone;
-      if (r * 64 < m) {
-        const int p = r * 64 + lane;
-        const bool valid = p < m;
-        const uint16_t e = valid ? Od[p] : 0;
-        const uint16_t k = valid ? seg_of_pt[e] : kNone;
-        const bool spl = k != kNone && splits[k];
-        const bool f = spl && flag[e];
+    for (int r0 = 0; r0 < NPL; r0 += CH) {
+      uint32_t e[CH], k[CH], sp[CH], fg[CH], sa[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int p = (r0 + c) * 64 + lane;
+        const uint32_t v = Od[p];
+        e[c] = p < m ? v : 0u;
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int p = (r0 + c) * 64 + lane;
+        const uint32_t v = seg_of_pt[e[c]];
+        k[c] = p < m ? v : static_cast<uint32_t>(kNone);
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const uint32_t kc = k[c] == kNone ? 0u : k[c];
+        sp[c] = splits[kc];
+        fg[c] = flag[e[c]];
+        sa[c] = segA[kc];
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int r = r0 + c, p = r * 64 + lane;
+        const bool spl = (k[c] != kNone) & (sp[c] != 0);
+        const bool f = spl & (fg[c] != 0);
         const unsigned long long mask = __ballot(f);
         const int F = run + __popcll(mask & lt);
         run += __popcll(mask);
-        if (spl && p == segA[k]) segF[k] = static_cast<uint16_t>(F);
-        pe[r] = static_cast<uint32_t>(e) | (static_cast<uint32_t>(F) << 16);
-        ks[r] = spl ? (static_cast<uint32_t>(k) | (f ? 0x10000u : 0u)) : kNone;
+        if (spl & (p == static_cast<int>(sa[c]))) segF[k[c]] = static_cast<uint16_t>(F);
+        pe[r] = e[c] | (static_cast<uint32_t>(F) << 16);
+        ks[r] = spl ? (k[c] | (f ? 0x10000u : 0u)) : static_cast<uint32_t>(kNone);
       }
     }
   }
   __syncthreads();
   if (active) {
 #pragma unroll
-    for (int r = 0; r < NPL; ++r) {
-      const int p = r * 64 + lane;
-      if (p < m) {
-        int np = p;
-        const uint32_t k = ks[r] & 0xFFFF;
-        if (k != kNone) {
-          const int a = segA[k];
-          const int lrank = static_cast<int>(pe[r] >> 16) - segF[k];
-          np = (ks[r] >> 16) ? a + lrank : a + segNL[k] + (p - a - lrank);
+    for (int r0 = 0; r0 < NPL; r0 += CH) {
+      uint32_t a[CH], fb[CH], nl[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const uint32_t k = ks[r0 + c] & 0xFFFFu;
+        const uint32_t kc = k == kNone ? 0u : k;
+        a[c] = segA[kc];
+        fb[c] = segF[kc];
+        nl[c] = segNL[kc];
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int r = r0 + c, p = r * 64 + lane;
+        if (p < m) {
+          int np = p;
+          if ((ks[r] & 0xFFFFu) != kNone) {
+            const int lrank = static_cast<int>(pe[r] >> 16) - static_cast<int>(fb[c]);
+            np = (ks[r] >> 16) ? static_cast<int>(a[c]) + lrank
+                               : static_cast<int>(a[c]) + static_cast<int>(nl[c]) + (p - static_cast<int>(a[c]) - lrank);
+          }
+          Od[np] = static_cast<uint16_t>(pe[r] & 0xFFFFu);
         }
-        Od[np] = static_cast<uint16_t>(pe[r] & 0xFFFF);
       }
     }
   }
@@ -1175,9 +1208,13 @@ __device__ __forceinline__ void finish_task(int ti, const Task* tasks, int P, Bu
   uint16_t* O = reinterpret_cast<uint16_t*>(smem + lay.O);
   uint16_t* seg = reinterpret_cast<uint16_t*>(smem + lay.seg);
   uint8_t* flag = smem + lay.flag;
-  uint16_t* lA[2] = {reinterpret_cast<uint16_t*>(smem + lay.lA0), reinterpret_cast<uint16_t*>(smem + lay.lA1)};
-  uint16_t* lL[2] = {reinterpret_cast<uint16_t*>(smem + lay.lL0), reinterpret_cast<uint16_t*>(smem + lay.lL1)};
-  int32_t* lN[2] = {reinterpret_cast<int32_t*>(smem + lay.lN0), reinterpret_cast<int32_t*>(smem + lay.lN1)};
+  // the two levels' segment lists lie back to back (list 1 = list 0 + MS);
+  // they are addressed by offset from smem, not through a table of
+  // pointers, which the compiler turned into flat (non-LDS) accesses
+  uint16_t* const lA0 = reinterpret_cast<uint16_t*>(smem + lay.lA0);
+  uint16_t* const lL0 = reinterpret_cast<uint16_t*>(smem + lay.lL0);
+  int32_t* const lN0 = reinterpret_cast<int32_t*>(smem + lay.lN0);
+  const int MS = lay.MS;
   uint32_t* sxs = reinterpret_cast<uint32_t*>(smem + lay.sxs);
   uint16_t* snl = reinterpret_cast<uint16_t*>(smem + lay.snl);
   uint16_t* srank = reinterpret_cast<uint16_t*>(smem + lay.srank);
@@ -1206,9 +1243,9 @@ __device__ __forceinline__ void finish_task(int ti, const Task* tasks, int P, Bu
     sh_over = 0;
     sh_maxdepth = 0;
     sh_next = res_base + res_off[ti];
-    lA[0][0] = 0;
-    lL[0][0] = static_cast<uint16_t>(m);
-    lN[0][0] = q.slot;
+    lA0[0] = 0;
+    lL0[0] = static_cast<uint16_t>(m);
+    lN0[0] = q.slot;
   }
   __syncthreads();
   if (m > phi) {
@@ -1238,7 +1275,7 @@ __device__ __forceinline__ void finish_task(int ti, const Task* tasks, int P, Bu
     __syncthreads();
     // decide every segment of this level
     for (int k = tid; k < nl; k += NT) {
-      const int a = lA[cur][k], L = lL[cur][k];
+      const int a = (lA0 + cur * MS)[k], L = (lL0 + cur * MS)[k];
       int d = 0, nleft = 0;
       uint32_t x = 0;
       bool split = L > phi && lds_split_rule<D>(C, O, P, a, L, &d, &x, &nleft);
@@ -1263,7 +1300,7 @@ __device__ __forceinline__ void finish_task(int ti, const Task* tasks, int P, Bu
         nd.dim = -1;
         nd.depth = static_cast<int16_t>(depth);
         nd.pad = 0;
-        const int32_t at = lN[cur][k];
+        const int32_t at = (lN0 + cur * MS)[k];
         if (at < node_cap) nodes[at] = nd;
         atomicMax(&sh_maxdepth, depth);
       }
@@ -1302,9 +1339,9 @@ __device__ __forceinline__ void finish_task(int ti, const Task* tasks, int P, Bu
     const int nxt = cur ^ 1;
     for (int k = tid; k < nl; k += NT) {
       if (!ssplit[k]) continue;
-      const int a = lA[cur][k], L = lL[cur][k], r = srank[k];
+      const int a = (lA0 + cur * MS)[k], L = (lL0 + cur * MS)[k], r = srank[k];
       const int cl = nbase + 2 * r, cr = cl + 1;
-      if (!over && lN[cur][k] < node_cap) {
+      if (!over && (lN0 + cur * MS)[k] < node_cap) {
         Node nd;
         nd.x = sxs[k];
         nd.size = L;
@@ -1314,14 +1351,14 @@ __device__ __forceinline__ void finish_task(int ti, const Task* tasks, int P, Bu
         nd.dim = sdm[k];
         nd.depth = static_cast<int16_t>(depth);
         nd.pad = 0;
-        nodes[lN[cur][k]] = nd;
+        nodes[(lN0 + cur * MS)[k]] = nd;
       }
-      lA[nxt][2 * r] = static_cast<uint16_t>(a);
-      lL[nxt][2 * r] = snl[k];
-      lN[nxt][2 * r] = cl;
-      lA[nxt][2 * r + 1] = static_cast<uint16_t>(a + snl[k]);
-      lL[nxt][2 * r + 1] = static_cast<uint16_t>(L - snl[k]);
-      lN[nxt][2 * r + 1] = cr;
+      (lA0 + nxt * MS)[2 * r] = static_cast<uint16_t>(a);
+      (lL0 + nxt * MS)[2 * r] = snl[k];
+      (lN0 + nxt * MS)[2 * r] = cl;
+      (lA0 + nxt * MS)[2 * r + 1] = static_cast<uint16_t>(a + snl[k]);
+      (lL0 + nxt * MS)[2 * r + 1] = static_cast<uint16_t>(L - snl[k]);
+      (lN0 + nxt * MS)[2 * r + 1] = cr;
     }
     if (nsplit == 0) break;
     // side flags of the points of splitting segments
@@ -1333,7 +1370,7 @@ __device__ __forceinline__ void finish_task(int ti, const Task* tasks, int P, Bu
     // wave d partitions order d; on the last splitting level only the order
     // that is written out (dimension 0) matters
     const bool active = wave < (sh_more ? D : 1);
-    wave_partition<NPL>(active, O + wave * P, m, seg, ssplit, lA[cur], snl, flag, segF + wave * lay.MS);
+    wave_partition<NPL>(active, O + wave * P, m, seg, ssplit, (lA0 + cur * MS), snl, flag, segF + wave * MS);
     __syncthreads();
     for (int e = tid; e < m; e += NT) {
       const int k = seg[e];
