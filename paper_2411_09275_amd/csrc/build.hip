@@ -121,8 +121,9 @@ __host__ __device__ inline int cand_shift(int64_t m, int s) {
 __device__ inline int dev_count(const int* d, int h) { return d ? *d : h; }
 
 // ---------------------------------------------------------------- classify
+// With sieve_pts set, the points of the sieve tasks are added up there.
 __global__ void k_classify(const Task* front, int n_front, int s, Task* sieve, int* n_sieve, Task* fin,
-                           int* n_fin, const int* dn = nullptr) {
+                           int* n_fin, const int* dn = nullptr, unsigned long long* sieve_pts = nullptr) {
   n_front = dev_count(dn, n_front);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = i < n_front;
@@ -132,6 +133,7 @@ __global__ void k_classify(const Task* front, int n_front, int s, Task* sieve, i
   const int b = block_append(ok && t.m < s, n_fin);
   if (a >= 0) sieve[a] = t;
   if (b >= 0) fin[b] = t;
+  if (sieve_pts && a >= 0) atomicAdd(sieve_pts, static_cast<unsigned long long>(t.m));
 }
 
 // ------------------------------------------------------------ tile layout
@@ -1877,6 +1879,13 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
   int* d_flags = ctr.p + 4;
   int* d_nrootext = ctr.p + 5;
   int* d_height = ctr.p + 6;
+  // slots 8-9 (during the rounds): the points of the round's sieve tasks
+  unsigned long long* d_spts = reinterpret_cast<unsigned long long*>(ctr.p + 8);
+  auto read_pts = [&]() {
+    unsigned long long v = 0;
+    std::memcpy(&v, hc + 8, sizeof(v));
+    return static_cast<int64_t>(v);
+  };
 
   int n_front = n_roots;
   PKD_TRY(front.need(n_front));
@@ -1892,20 +1901,26 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
   int rounds = 0;
   static const char* const kRoundNames[] = {"sieve round 1", "sieve round 2", "sieve round 3", "sieve round 4",
                                              "sieve round 5", "sieve round 6", "sieve round 7", "sieve round 8+"};
+  bool classified = false;   // the front was classified with the last round's emit
   while (n_front > 0) {
     if (++rounds > 200) return PKD_ERR_INTERNAL;   // every round shrinks every subproblem
     TraceRange tr(kRoundNames[std::min(rounds, 8) - 1]);
-    PKD_TRY(fin.need(static_cast<size_t>(n_fin) + n_front + 1, true));
-    PKD_TRY(sieve.need(n_front));
-    PKD_HIP(hipMemsetAsync(d_nsieve, 0, sizeof(int), st));
-    hipLaunchKernelGGL(k_classify, dim3((n_front + 255) / 256), dim3(256), 0, st, front.p, n_front, s, sieve.p,
-                       d_nsieve, fin.p, d_nfin);
-    PKD_TRY(kernel_status("k_classify"));
-    PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
-    PKD_HIP(hipStreamSynchronize(st));
-    if (hc[4] & kErrRange) return PKD_ERR_RANGE;
-    if (hc[4] & kErrInternal) return PKD_ERR_INTERNAL;
+    if (!classified) {
+      PKD_TRY(fin.need(static_cast<size_t>(n_fin) + n_front + 1, true));
+      PKD_TRY(sieve.need(n_front));
+      PKD_HIP(hipMemsetAsync(d_nsieve, 0, sizeof(int), st));
+      PKD_HIP(hipMemsetAsync(d_spts, 0, sizeof(unsigned long long), st));
+      hipLaunchKernelGGL(k_classify, dim3((n_front + 255) / 256), dim3(256), 0, st, front.p, n_front, s, sieve.p,
+                         d_nsieve, fin.p, d_nfin, static_cast<const int*>(nullptr), d_spts);
+      PKD_TRY(kernel_status("k_classify"));
+      PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 10, hipMemcpyDeviceToHost, st));
+      PKD_HIP(hipStreamSynchronize(st));
+      if (hc[4] & kErrRange) return PKD_ERR_RANGE;
+      if (hc[4] & kErrInternal) return PKD_ERR_INTERNAL;
+    }
+    classified = false;
     const int ns = hc[0];
+    const int64_t sieve_pts = read_pts();   // points of this round's sieve tasks
     n_fin = hc[1];
     node_count = hc[3];
     T->node_count = node_count;   // nodes that a growth of the node array must keep
@@ -1918,6 +1933,9 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
     PKD_HIP(hipMemsetAsync(mode.p, 0, ns, st));
     const int8_t* override_p = nullptr;
     int64_t ntiles = 0, nchunks = 0, round_pts = 0;
+    // the tile layout is not read back: its launches take bounds from the
+    // round's points and read the task count on the device
+    bool bounded = false;
     PKD_TRY(rx.need(static_cast<size_t>(ns) * NB));
     PKD_TRY(rdim.need(static_cast<size_t>(ns) * NB));
     PKD_TRY(ext.need(static_cast<size_t>(ns) * nheap));
@@ -1925,13 +1943,15 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
     PKD_TRY(cand_cnt.need(static_cast<size_t>(ns) * kCntStride));
     for (int attempt = 0; P.sigma > 0; ++attempt) {
       PKD_TRY(sieve_layout(st, sieve.p, ns, tile, W, s, small_max, override_p, &ntiles, &nchunks, &round_pts,
-                           P.cand_bias));
+                           P.cand_bias, sieve_pts));
+      bounded = true;
       PKD_TRY(cand_key.need(static_cast<size_t>(ns) * cap));
       PKD_TRY(cand_pos.need(static_cast<size_t>(ns) * cap));
       PKD_HIP(hipMemsetAsync(cand_cnt.p, 0, sizeof(uint32_t) * kCntStride * ns, st));
 #define PKD_CAND(ITER)                                                                                            \
   hipLaunchKernelGGL((k_candidates<ITER>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, sieve.p, ns, \
-                     W.tile_off.p, bufs, src, P.seed, W.shift.p, small_max, cand_key.p, cand_pos.p, cand_cnt.p, cap)
+                     W.tile_off.p, bufs, src, P.seed, W.shift.p, small_max, cand_key.p, cand_pos.p, cand_cnt.p, cap, \
+                     d_nsieve)
       if (tile == 1024) PKD_CAND(4);
       else if (tile == 2048) PKD_CAND(8);
       else PKD_CAND(16);
@@ -1973,6 +1993,7 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
                                  mode.p, EW));
       PKD_TRY(sieve_layout(st, sieve.p, ns, tile, W, s, small_max, nullptr, &ntiles, &nchunks, &round_pts,
                            P.cand_bias));
+      bounded = false;
     } else if (hc[5] > 0) {
       // subproblems whose sample was entirely identical (rare): the split
       // rule on all their points
@@ -1981,16 +2002,27 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
     }
     // sieve: count, column-major scan, stable scatter
     PKD_TRY(sieve_pass(st, D, P.lambda, tile, sieve.p, ns, bufs, src, dst, rx.p, rdim.p, mode.p, W, ntiles, nchunks,
-                       round_pts, first && src == 2 ? 1 : 0, d_flags));
+                       round_pts, first && src == 2 ? 1 : 0, d_flags, bounded ? d_nsieve : nullptr));
     // nodes and next round's tasks
     PKD_TRY(ensure_nodes(T, st, static_cast<int64_t>(node_count) + static_cast<int64_t>(ns) * nheap));
-    PKD_TRY(next.need(static_cast<size_t>(ns) * NB));
-    PKD_TRY(fin.need(static_cast<size_t>(n_fin) + ns + 1, true));
+    // the emit adds at most one heavy leaf per subproblem to the finisher's
+    // list and at most 2^lambda tasks per subproblem to the next front; the
+    // next front is classified right after, reading its count on the device,
+    // so one host read ends the round
+    const int64_t next_max = static_cast<int64_t>(ns) * NB;
+    PKD_TRY(next.need(static_cast<size_t>(next_max)));
+    PKD_TRY(fin.need(static_cast<size_t>(n_fin) + ns + next_max + 1, true));
     PKD_HIP(hipMemsetAsync(d_nnext, 0, sizeof(int), st));
     hipLaunchKernelGGL(k_emit, dim3(ns), dim3(64), 0, st, sieve.p, ns, P.lambda, rx.p, rdim.p, ext.p, mode.p,
                        W.bsize.p, W.bstart.p, dst, T->nodes, d_nodes, next.p, d_nnext, fin.p, d_nfin, d_flags);
     PKD_TRY(kernel_status("k_emit"));
-    PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+    PKD_TRY(sieve.need(static_cast<size_t>(next_max)));
+    PKD_HIP(hipMemsetAsync(d_nsieve, 0, sizeof(int), st));
+    PKD_HIP(hipMemsetAsync(d_spts, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_classify, dim3(static_cast<unsigned>((next_max + 255) / 256)), dim3(256), 0, st, next.p,
+                       static_cast<int>(next_max), s, sieve.p, d_nsieve, fin.p, d_nfin, d_nnext, d_spts);
+    PKD_TRY(kernel_status("k_classify"));
+    PKD_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(int) * 10, hipMemcpyDeviceToHost, st));
     PKD_HIP(hipStreamSynchronize(st));
     if (hc[4] & kErrRange) return PKD_ERR_RANGE;
     if (hc[4] & kErrInternal) return PKD_ERR_INTERNAL;
@@ -1998,6 +2030,7 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
     n_fin = hc[1];
     node_count = hc[3];
     T->node_count = node_count;
+    classified = true;
     std::swap(front.p, next.p);
     std::swap(front.cap, next.cap);
     src = dst;
@@ -2085,7 +2118,7 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
 template <int D>
 int sieve_pass_d(hipStream_t st, int lambda, int tile, const Task* tasks, int ns, const Bufs& bufs, int src, int dst,
                  const int64_t* rx, const uint8_t* rdim, const int8_t* mode, SieveWork& W, int64_t ntiles,
-                 int64_t nchunks, int64_t pts, int check, int* d_flags) {
+                 int64_t nchunks, int64_t pts, int check, int* d_flags, const int* dns) {
   const int NB = 1 << lambda;
   PKD_TRY(W.A.need(static_cast<size_t>(ntiles) * NB));
   PKD_TRY(W.B.need(static_cast<size_t>(ntiles) * NB));
@@ -2094,24 +2127,20 @@ int sieve_pass_d(hipStream_t st, int lambda, int tile, const Task* tasks, int ns
   PKD_TRY(W.bstart.need(static_cast<size_t>(ns) * NB));
   Prof::begin(kProfCount, st);
   hipLaunchKernelGGL(k_count<D>, dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), 0, st, tasks, ns, W.tile_off.p,
-                     tile, bufs, src, rx, rdim, mode, lambda, W.A.p, check, d_flags);
+                     tile, bufs, src, rx, rdim, mode, lambda, W.A.p, check, d_flags, dns);
   Prof::end(kProfCount, st, 8.0 * D * static_cast<double>(pts));
   PKD_TRY(kernel_status("k_count"));
-  if (check) {
-    // caller input: stop before anything moves if a coordinate is out of range
-    int h = 0;
-    PKD_HIP(hipMemcpyAsync(&h, d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
-    PKD_HIP(hipStreamSynchronize(st));
-    if (h & kErrRange) return PKD_ERR_RANGE;
-  }
+  // an out-of-range coordinate of caller input is flagged by k_count and
+  // reported at the round's end, before the tree is used: routing compares
+  // coordinates with splitters, so every later step stays in bounds
   hipLaunchKernelGGL(k_chunk_sum, dim3(static_cast<unsigned>(nchunks)), dim3(kBlock), 0, st, W.chunk_off.p,
-                     W.tile_off.p, ns, lambda, W.A.p, W.S.p);
+                     W.tile_off.p, ns, lambda, W.A.p, W.S.p, dns);
   PKD_TRY(kernel_status("k_chunk_sum"));
   hipLaunchKernelGGL(k_sp_scan, dim3(ns), dim3(kBlock), 0, st, tasks, W.chunk_off.p, lambda, W.S.p, W.bsize.p,
-                     W.bstart.p);
+                     W.bstart.p, dns);
   PKD_TRY(kernel_status("k_sp_scan"));
   hipLaunchKernelGGL(k_apply, dim3(static_cast<unsigned>(nchunks)), dim3(kBlock), 0, st, W.chunk_off.p, W.tile_off.p,
-                     ns, lambda, W.A.p, W.S.p, W.bstart.p, W.B.p);
+                     ns, lambda, W.A.p, W.S.p, W.bstart.p, W.B.p, dns);
   PKD_TRY(kernel_status("k_apply"));
   Prof::begin(kProfScatter, st);
 #define PKD_SCATTER(PPT)                                                                                          \
@@ -2119,7 +2148,7 @@ int sieve_pass_d(hipStream_t st, int lambda, int tile, const Task* tasks, int ns
     const size_t lds = ScatterLayout(kBlock * (PPT), lambda).end;                                               \
     PKD_TRY(allow_lds(k_scatter<D, PPT>, lds));                                                                   \
     hipLaunchKernelGGL((k_scatter<D, PPT>), dim3(static_cast<unsigned>(ntiles)), dim3(kBlock), lds, st, tasks, ns, \
-                       W.tile_off.p, bufs, src, dst, rx, rdim, mode, lambda, W.B.p);                               \
+                       W.tile_off.p, bufs, src, dst, rx, rdim, mode, lambda, W.B.p, dns);                          \
   }
   if (tile == 2048)
     PKD_SCATTER(8)
@@ -2426,7 +2455,8 @@ int radix_sort_pairs_raw(hipStream_t st, uint64_t* keys, uint32_t* vals, int64_t
 }
 
 int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,
-                 const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts, int cand_bias) {
+                 const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts, int cand_bias,
+                 int64_t known_pts) {
   PKD_TRY(W.tile_off.need(ns + 1));
   PKD_TRY(W.chunk_off.need(ns + 1));
   PKD_TRY(W.shift.need(ns));
@@ -2434,6 +2464,13 @@ int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork&
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, tasks, ns, tile, W.tile_off.p, W.chunk_off.p, W.shift.p,
                      s, small_max, shift_override, W.tot.p + 2, cand_bias);
   PKD_TRY(kernel_status("k_tile_scan"));
+  if (known_pts >= 0) {
+    // a task of m points has ceil(m/tile) tiles; a chunk holds kChunkTiles
+    *ntiles = known_pts / tile + ns + 1;
+    *nchunks = *ntiles / kChunkTiles + ns + 1;
+    *pts = known_pts;
+    return PKD_OK;
+  }
   PKD_HIP(hipMemcpyAsync(W.tot.p, W.tile_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
   PKD_HIP(hipMemcpyAsync(W.tot.p + 1, W.chunk_off.p + ns, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
   int64_t tot[3];
@@ -2447,10 +2484,10 @@ int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork&
 
 int sieve_pass(hipStream_t st, int D, int lambda, int tile, const Task* tasks, int ns, const Bufs& bufs, int src,
                int dst, const int64_t* rx, const uint8_t* rdim, const int8_t* mode, SieveWork& W, int64_t ntiles,
-               int64_t nchunks, int64_t pts, int check, int* d_flags) {
+               int64_t nchunks, int64_t pts, int check, int* d_flags, const int* dns) {
   switch (D) {
 #define PKD_SIEVE_CASE(DD) \
-  case DD: return sieve_pass_d<DD>(st, lambda, tile, tasks, ns, bufs, src, dst, rx, rdim, mode, W, ntiles, nchunks, pts, check, d_flags);
+  case DD: return sieve_pass_d<DD>(st, lambda, tile, tasks, ns, bufs, src, dst, rx, rdim, mode, W, ntiles, nchunks, pts, check, d_flags, dns);
     PKD_SIEVE_CASE(1)
     PKD_SIEVE_CASE(2)
     PKD_SIEVE_CASE(3)

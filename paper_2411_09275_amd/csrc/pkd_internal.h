@@ -304,14 +304,20 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 // Tile layout of `ns` tasks (device array): tiles of `tile` points, scan
 // chunks; returns the numbers of tiles and chunks and the points covered.
+// With known_pts >= 0 (the tasks' points, known to the caller) nothing is
+// read back: the numbers returned are upper bounds (pts/tile + ns + 1 tiles),
+// and the launches that use them must read the task count on the device.
 int sieve_layout(hipStream_t st, const Task* tasks, int ns, int tile, SieveWork& W, int s, int small_max,
-                 const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts, int cand_bias = 0);
+                 const int8_t* shift_override, int64_t* ntiles, int64_t* nchunks, int64_t* pts, int cand_bias = 0,
+                 int64_t known_pts = -1);
 // Count, column-major scan and stable scatter of the tasks' points from
 // buffer src to dst through per-task routing skeletons rx/rdim ([ns][2^lambda]).
 // Bucket sizes and starts land in W.bsize / W.bstart ([ns][2^lambda]).
+// With dns set (the task count in device memory) ntiles and nchunks may be
+// upper bounds: the workgroups past the real counts leave.
 int sieve_pass(hipStream_t st, int D, int lambda, int tile, const Task* tasks, int ns, const Bufs& bufs, int src,
                int dst, const int64_t* rx, const uint8_t* rdim, const int8_t* mode, SieveWork& W, int64_t ntiles,
-               int64_t nchunks, int64_t pts, int check, int* d_flags);
+               int64_t nchunks, int64_t pts, int check, int* d_flags, const int* dns = nullptr);
 
 // Build the subtrees of the given root tasks into `tree` (whose point buffers
 // and node array are set up by the caller).  Points of the tasks live in the
