@@ -2047,9 +2047,6 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
     hipLaunchKernelGGL(k_bin_finish, dim3((n_fin + 1023) / 1024), dim3(1024), 0, st, fin.p, n_fin, lists.p, n_fin,
                        d_counts);
     PKD_TRY(kernel_status("k_bin_finish"));
-    int counts[8];
-    PKD_HIP(hipMemcpyAsync(counts, d_counts, sizeof(counts), hipMemcpyDeviceToHost, st));
-    PKD_HIP(hipStreamSynchronize(st));
     // node slots: a reserved range per task from a prefix sum of size bounds
     DArr<int32_t> R(st), res_off(st), bsum(st);
     PKD_TRY(R.need(n_fin + 1));
@@ -2057,9 +2054,15 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
     hipLaunchKernelGGL(k_fin_reserve, dim3((n_fin + 255) / 256), dim3(256), 0, st, fin.p, n_fin, P.phi, R.p);
     PKD_TRY(kernel_status("k_fin_reserve"));
     PKD_TRY(exscan_i32(st, R.p, res_off.p, n_fin, bsum));
-    int32_t reserved = 0;
-    PKD_HIP(hipMemcpyAsync(&reserved, res_off.p + n_fin, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    // one host read for the total reservation (into spare slot 7) and the
+    // class counts (slots 8-15)
+    PKD_HIP(hipMemcpyAsync(ctr.p + 7, res_off.p + n_fin, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    int hf[9];
+    PKD_HIP(hipMemcpyAsync(hf, ctr.p + 7, sizeof(hf), hipMemcpyDeviceToHost, st));
     PKD_HIP(hipStreamSynchronize(st));
+    const int32_t reserved = hf[0];
+    int counts[8];
+    for (int c = 0; c < 8; ++c) counts[c] = hf[1 + c];
     const int base_nodes = node_count;
     T->node_count = base_nodes;   // the finisher's nodes are rewritten on a retry
     int64_t want = static_cast<int64_t>(base_nodes) + reserved + 1024;
