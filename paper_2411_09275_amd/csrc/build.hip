@@ -1089,69 +1089,119 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const Task* sp, int ns, cons
 // Skeleton nodes of each subproblem become tree nodes; its buckets become
 // tasks of the next round.  One workgroup of 64 threads per subproblem; the
 // heap is processed level by level.
-__global__ void __launch_bounds__(64) k_emit(const Task* sp, int ns, int lambda, const int64_t* rx,
-                                             const uint8_t* rdim, const int8_t* ext, const int8_t* mode,
-                                             const int32_t* bsize, const int32_t* bstart, int dst, Node* nodes,
-                                             int* node_count, Task* front, int* n_front, Task* fin, int* n_fin,
-                                             int* flags, const int* dns = nullptr) {
-  if (dns && static_cast<int>(blockIdx.x) >= *dns) return;
+// Four subproblems per workgroup, one per wave: the waves reserve their node
+// slots and their next-front entries with one counter update per workgroup
+// each (one update per subproblem serialized on the two counters when
+// thousands of subproblems emit at once).
+constexpr int kEmitWaves = 4;
+
+// Per wave: `count` items to reserve on `counter`; returns the wave's first
+// slot.  Every thread of the workgroup calls it.
+__device__ inline int block_reserve(int wave, int count, int* counter) {
+  __shared__ int wcnt[kEmitWaves], wbase[kEmitWaves];
+  if ((threadIdx.x & 63) == 0) wcnt[wave] = count;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < kEmitWaves; ++w) {
+      wbase[w] = t;
+      t += wcnt[w];
+    }
+    const int b = t > 0 ? atomicAdd(counter, t) : 0;
+    for (int w = 0; w < kEmitWaves; ++w) wbase[w] += b;
+  }
+  __syncthreads();
+  return wbase[wave];
+}
+
+__global__ void __launch_bounds__(64 * kEmitWaves) k_emit(const Task* sp, int ns, int lambda, const int64_t* rx,
+                                                          const uint8_t* rdim, const int8_t* ext, const int8_t* mode,
+                                                          const int32_t* bsize, const int32_t* bstart, int dst,
+                                                          Node* nodes, int* node_count, Task* front, int* n_front,
+                                                          Task* fin, int* n_fin, int* flags,
+                                                          const int* dns = nullptr) {
+  ns = dev_count(dns, ns);
+  if (static_cast<int>(blockIdx.x) * kEmitWaves >= ns) return;   // the whole workgroup has nothing
   const int NB = 1 << lambda;
   const int nheap = 2 << lambda;
-  __shared__ int32_t size[2 << kMaxLambda], off[2 << kMaxLambda], idx[2 << kMaxLambda];
-  __shared__ uint8_t reach[2 << kMaxLambda], exs[2 << kMaxLambda];
-  __shared__ int32_t part[64];
-  __shared__ int sh_base;
-  const int sig = blockIdx.x;
-  const int tid = threadIdx.x;
-  const Task q = sp[sig];
-  if (mode[sig] == 1) {
-    // identical points: one heavy leaf, data stays where it is
-    if (tid == 0) {
-      Task h = q;
-      h.mode = 1;
-      fin[atomicAdd(n_fin, 1)] = h;
+  constexpr int H = 2 << kMaxLambda;
+  __shared__ int32_t size_[kEmitWaves][H], off_[kEmitWaves][H], idx_[kEmitWaves][H];
+  __shared__ uint8_t reach_[kEmitWaves][H], exs_[kEmitWaves][H];
+  const int wave = threadIdx.x >> 6, tid = threadIdx.x & 63;
+  int32_t* size = size_[wave];
+  int32_t* off = off_[wave];
+  int32_t* idx = idx_[wave];
+  uint8_t* reach = reach_[wave];
+  uint8_t* exs = exs_[wave];
+  const int sig = blockIdx.x * kEmitWaves + wave;
+  // a wave emits unless it has no subproblem or a heavy leaf of identical
+  // points (one finisher task, data staying where it is)
+  bool active = sig < ns;
+  Task q{};
+  if (active) {
+    q = sp[sig];
+    if (mode[sig] == 1) {
+      if (tid == 0) {
+        Task h = q;
+        h.mode = 1;
+        fin[atomicAdd(n_fin, 1)] = h;
+      }
+      active = false;
     }
-    return;
   }
-  const int8_t* ex = ext + static_cast<int64_t>(sig) * nheap;
-  for (int v = tid; v < nheap; v += 64) exs[v] = ex[v];
-  for (int j = tid; j < NB; j += 64) {
-    size[NB + j] = bsize[static_cast<int64_t>(sig) * NB + j];
-    off[NB + j] = bstart[static_cast<int64_t>(sig) * NB + j];
-  }
-  __syncthreads();
-  for (int l = lambda - 1; l >= 0; --l) {
-    for (int v = (1 << l) + tid; v < (2 << l); v += 64) {
-      size[v] = size[2 * v] + size[2 * v + 1];
-      off[v] = off[2 * v];
+  if (active) {
+    const int8_t* ex = ext + static_cast<int64_t>(sig) * nheap;
+    for (int v = tid; v < nheap; v += 64) exs[v] = ex[v];
+    for (int j = tid; j < NB; j += 64) {
+      size[NB + j] = bsize[static_cast<int64_t>(sig) * NB + j];
+      off[NB + j] = bstart[static_cast<int64_t>(sig) * NB + j];
     }
-    __syncthreads();
-  }
-  if (tid == 0) reach[1] = 1;
-  __syncthreads();
-  for (int l = 1; l <= lambda; ++l) {
-    for (int v = (1 << l) + tid; v < (2 << l); v += 64) reach[v] = reach[v >> 1] && !exs[v >> 1];
-    __syncthreads();
+    wave_sync();
+    for (int l = lambda - 1; l >= 0; --l) {
+      for (int v = (1 << l) + tid; v < (2 << l); v += 64) {
+        size[v] = size[2 * v] + size[2 * v + 1];
+        off[v] = off[2 * v];
+      }
+      wave_sync();
+    }
+    if (tid == 0) reach[1] = 1;
+    wave_sync();
+    for (int l = 1; l <= lambda; ++l) {
+      for (int v = (1 << l) + tid; v < (2 << l); v += 64) reach[v] = reach[v >> 1] && !exs[v >> 1];
+      wave_sync();
+    }
   }
   // rank the reachable heap nodes other than the root in heap order
   const int per = (nheap + 63) / 64;
   const int b = tid * per, e = min(nheap, b + per);
   int cnt = 0;
-  for (int v = max(b, 2); v < e; ++v) cnt += reach[v];
+  if (active)
+    for (int v = max(b, 2); v < e; ++v) cnt += reach[v];
   int incl = cnt;
   for (int o = 1; o < 64; o <<= 1) {
     const int y = __shfl_up(incl, o);
     if (tid >= o) incl += y;
   }
-  if (tid == 63) sh_base = atomicAdd(node_count, incl);
-  __syncthreads();
-  int r = sh_base + incl - cnt;
+  const int nbase = block_reserve(wave, __shfl(incl, 63), node_count);
+  // external (next-round) nodes of this subproblem, counted per wave
+  int n_ext = 0;
+  if (active) {
+    for (int base = 0; base < nheap; base += 64) {
+      const int v = base + tid;
+      n_ext += __popcll(__ballot(v >= 1 && v < nheap && reach[v] && exs[v]));
+    }
+  }
+  const int fbase = block_reserve(wave, n_ext, n_front);
+  if (!active) return;
+  int r = nbase + incl - cnt;
   for (int v = max(b, 2); v < e; ++v)
     if (reach[v]) idx[v] = r++;
   if (tid == 0) idx[1] = q.slot;
-  __syncthreads();
+  wave_sync();
   const int64_t* sxv = rx + static_cast<int64_t>(sig) * NB;
   const uint8_t* sdv = rdim + static_cast<int64_t>(sig) * NB;
+  const unsigned long long lt = (1ULL << tid) - 1;
+  int fpos = fbase;
   for (int base = 0; base < nheap; base += 64) {
     const int v = base + tid;
     const bool live = v >= 1 && v < nheap && reach[v];
@@ -1170,7 +1220,7 @@ __global__ void __launch_bounds__(64) k_emit(const Task* sp, int ns, int lambda,
       nd.pad = 0;
       nodes[idx[v]] = nd;
     }
-    const int at = wave_append(external, n_front);
+    const unsigned long long em = __ballot(external);
     if (external) {
       const int level = 31 - __clz(v);
       if (size[v] <= 0) atomicOr(flags, kErrInternal);
@@ -1181,8 +1231,9 @@ __global__ void __launch_bounds__(64) k_emit(const Task* sp, int ns, int lambda,
       c.depth = static_cast<int16_t>(q.depth + level);
       c.buf = static_cast<int8_t>(dst);
       c.mode = 0;
-      front[at] = c;
+      front[fpos + __popcll(em & lt)] = c;
     }
+    fpos += __popcll(em);
   }
 }
 
@@ -2013,7 +2064,8 @@ int build_tasks_d(pkd_tree* T, hipStream_t st, const Task* roots, int n_roots, b
     PKD_TRY(next.need(static_cast<size_t>(next_max)));
     PKD_TRY(fin.need(static_cast<size_t>(n_fin) + ns + next_max + 1, true));
     PKD_HIP(hipMemsetAsync(d_nnext, 0, sizeof(int), st));
-    hipLaunchKernelGGL(k_emit, dim3(ns), dim3(64), 0, st, sieve.p, ns, P.lambda, rx.p, rdim.p, ext.p, mode.p,
+    hipLaunchKernelGGL(k_emit, dim3((ns + kEmitWaves - 1) / kEmitWaves), dim3(64 * kEmitWaves), 0, st, sieve.p, ns,
+                       P.lambda, rx.p, rdim.p, ext.p, mode.p,
                        W.bsize.p, W.bstart.p, dst, T->nodes, d_nodes, next.p, d_nnext, fin.p, d_nfin, d_flags);
     PKD_TRY(kernel_status("k_emit"));
     PKD_TRY(sieve.need(static_cast<size_t>(next_max)));
@@ -2708,7 +2760,8 @@ int plan_enqueue_d(pkd_build_plan* G, hipStream_t st) {
       PKD_PSCATTER(16)
 #undef PKD_PSCATTER
     PKD_TRY(kernel_status("k_scatter"));
-    hipLaunchKernelGGL(k_emit, dim3(gs), dim3(64), 0, st, G->sieve, 0, P.lambda, G->rx, G->rdim, G->ext, G->mode,
+    hipLaunchKernelGGL(k_emit, dim3((gs + kEmitWaves - 1) / kEmitWaves), dim3(64 * kEmitWaves), 0, st, G->sieve, 0,
+                       P.lambda, G->rx, G->rdim, G->ext, G->mode,
                        G->bsize, G->bstart, dst, T->nodes, ctr + kGNodes, next, ctr + kGNext, G->fin, ctr + kGFin,
                        d_flags, dns);
     PKD_TRY(kernel_status("k_emit"));
