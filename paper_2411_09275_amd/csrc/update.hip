@@ -6,15 +6,17 @@
 //             lambda levels, with the build's count/scan/scatter kernels, until
 //             every batch point sits in the slice of the leaf it belongs to;
 //             the batch ends up in the tree's in-order.
-//   match     (delete) each entry claims the stored point of its leaf with the
-//             same id and coordinates; absent entries drop out.
+//   match     (delete) each entry finds the stored point of its leaf with the
+//             same id and coordinates; absent entries drop out, and of the
+//             entries naming one point the first claims it.
 //   decide    the rounds are replayed top-down with exact counts (inserted
 //             points, or points actually removed): a touched node that stays
 //             alpha-balanced keeps its splitter and takes its new size; the
 //             topmost one that does not becomes a rebuild region and nothing
 //             below it is visited; an inserted-into leaf is rebuilt.
-//   relayout  the tree keeps its points packed in in-order: one prefix sum of
-//             the size changes gives every surviving point and node its new
+//   relayout  the tree keeps its points packed in in-order: the regions sorted
+//             by old end (with the batch points each adds) and the sorted
+//             removed positions give every surviving point and node its new
 //             offset; old points, batch points and survivors move in one pass.
 //   rebuild   all regions are rebuilt by one segmented Build (Algorithm 1),
 //             each at the depth of the node it replaces.
@@ -300,11 +302,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(const Res* res, int nres
   }
 }
 
-// Delete: each batch entry claims the stored point of its leaf with the same
-// id and coordinates (at most one entry wins a point).
+// Delete: each batch entry looks in its leaf for the stored point with the
+// same id and coordinates and notes its position (n when there is none).
 template <int D>
 __global__ void k_match(const int64_t* batch, int64_t m, const int32_t* leaf_of, const Node* nodes, const int64_t* X,
-                        int64_t cap, int32_t* delflag, int32_t* matched) {
+                        int64_t cap, int64_t n, uint64_t* pos, uint32_t* entry) {
   const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (p >= m) return;
   int64_t c[D];
@@ -312,16 +314,37 @@ __global__ void k_match(const int64_t* batch, int64_t m, const int32_t* leaf_of,
   const int64_t id = batch[D * m + p];
   const Node nd = nodes[leaf_of[p]];
   const int64_t* ids = X + static_cast<int64_t>(D) * cap;
-  int32_t got = 0;
+  int64_t at = n;
   for (int64_t i = nd.off; i < static_cast<int64_t>(nd.off) + nd.size; ++i) {
     if (ids[i] != id) continue;
     bool same = true;
     for (int d = 0; d < D; ++d) same &= X[d * cap + i] == c[d];
     if (!same) continue;
-    got = atomicCAS(delflag + i, 0, 1) == 0 ? 1 : 0;
+    at = i;
     break;
   }
-  matched[p] = got;
+  pos[p] = static_cast<uint64_t>(at);
+  entry[p] = static_cast<uint32_t>(p);
+}
+
+// After the positions are sorted: the first entry of each matched position
+// claims it (repeated entries of one point drop out), weight 1 for the claim.
+__global__ void k_claim(const uint64_t* pos, const uint32_t* entry, int64_t m, int64_t n, int32_t* claim,
+                        int32_t* weight) {
+  for (int64_t j = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; j < m;
+       j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int32_t c = pos[j] < static_cast<uint64_t>(n) && (j == 0 || pos[j] != pos[j - 1]) ? 1 : 0;
+    claim[j] = c;
+    weight[entry[j]] = c;
+  }
+}
+
+// The claimed positions, ascending and without repeats.
+__global__ void k_removed_list(const uint64_t* pos, const int32_t* claim, const int32_t* at, int64_t m,
+                               uint64_t* removed) {
+  for (int64_t j = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; j < m;
+       j += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    if (claim[j]) removed[at[j]] = pos[j];
 }
 
 __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
@@ -457,33 +480,113 @@ __global__ void k_add_regions(int* n_regions, const int32_t* roff, int* n_sizes,
   *n_sizes += soff[ns];
 }
 
-// Region bookkeeping on the old positions: regid marks the points inside each
-// region; for inserts the size change of a region is noted at its end.  Grid
-// (regions, y): the y blocks of a region share its range.
-__global__ void k_region_mark(const Region* regions, int32_t* regid, int32_t* delta, int insert) {
-  const Region r = regions[blockIdx.x];
-  const int64_t stride = static_cast<int64_t>(gridDim.y) * blockDim.x;
-  for (int64_t o = r.a + static_cast<int64_t>(blockIdx.y) * blockDim.x + threadIdx.x; o < r.b; o += stride)
-    regid[o] = blockIdx.x;
-  if (insert && blockIdx.y == 0 && threadIdx.x == 0) atomicAdd(delta + r.b, r.e - r.s);
+// ---- where the old points go.  Two sorted event lists replace per-point
+// arrays (which cost O(n) fills and a prefix sum over the whole tree at every
+// batch, however small): the rebuild regions ordered by their old end b (an
+// insert adds a region's batch points there; a region's own points are left
+// to the rebuild), and for a delete the ascending positions of the removed
+// points.  A table per chunk of kEvChunk old positions holds how many events
+// lie below the chunk, so a lookup searches only the chunk's own events.
+constexpr int64_t kEvChunk = 4096;
+
+struct EvView {
+  const uint64_t* rkey;   // [R] 2 b + (region empty), ascending: at equal ends a non-empty region comes first
+  const uint32_t* rk;     // [R] the region of sorted entry j
+  const int32_t* gx;      // [R + 1] insert: batch points of the sorted entries below j
+  const int32_t* rc;      // [nch + 1] entries whose end lies below c kEvChunk
+  const uint64_t* dp;     // [nd] delete: removed positions, ascending
+  const int32_t* dc;      // [nch + 1] removed positions below c kEvChunk
+  int32_t R, nd;
+};
+
+// Index of the first a[lo .. hi) that is >= x (hi if none); a ascending.
+__device__ inline int32_t first_not_below(const uint64_t* a, int32_t lo, int32_t hi, uint64_t x) {
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
 }
 
-// New places of the old points outside every region: insert: o + S[o+1]
-// (batch points noted at region ends before o); delete: o - S[o] (removed
-// points before o).  The packed 32-bit coordinates go to the new layout's own
+// Regions whose old end lies below x, for 0 <= x <= n.
+__device__ inline int32_t ends_below(const EvView& ev, int64_t x) {
+  const int64_t c = x / kEvChunk;
+  return first_not_below(ev.rkey, ev.rc[c], ev.rc[c + 1], static_cast<uint64_t>(x) << 1);
+}
+
+// Removed positions below x, for 0 <= x <= n.
+__device__ inline int32_t removed_below(const EvView& ev, int64_t x) {
+  const int64_t c = x / kEvChunk;
+  return first_not_below(ev.dp, ev.dc[c], ev.dc[c + 1], static_cast<uint64_t>(x));
+}
+
+// Batch points an insert places before the old position x: those of the
+// regions ending at or before x (x < n), or before x (x = n: a node at the
+// end is placed before the regions that end there).
+__device__ inline int32_t inserted_before(const EvView& ev, int64_t x, int64_t n) {
+  return ev.gx[ends_below(ev, x < n ? x + 1 : x)];
+}
+
+// The region holding old position o (0 <= o < n), or -1.  The first entry
+// ending after o is the only candidate: regions are disjoint, and an empty
+// region (an empty tree of a batch handle) sits at a boundary between trees,
+// never strictly inside another region.
+__device__ inline int32_t region_at(const EvView& ev, const Region* regions, int64_t o) {
+  const int32_t u = ends_below(ev, o + 1);
+  if (u >= ev.R) return -1;
+  const int32_t k = static_cast<int32_t>(ev.rk[u]);
+  return regions[k].a <= o ? k : -1;
+}
+
+__device__ inline bool removed_at(const EvView& ev, int64_t o, int32_t* below) {
+  const int32_t j = removed_below(ev, o);
+  *below = j;
+  return j < ev.nd && ev.dp[j] == static_cast<uint64_t>(o);
+}
+
+// Sort keys of the regions by old end.
+__global__ void k_region_keys(const Region* regions, int n_regions, uint64_t* key, uint32_t* val) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_regions; k += gridDim.x * blockDim.x) {
+    const Region r = regions[k];
+    key[k] = (static_cast<uint64_t>(r.b) << 1) | (r.a == r.b ? 1u : 0u);
+    val[k] = static_cast<uint32_t>(k);
+  }
+}
+
+// Batch points of the sorted regions (the insert's growth at each end).
+__global__ void k_region_growth(const Region* regions, const uint32_t* rk, int n_regions, int32_t* g) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n_regions; j += gridDim.x * blockDim.x) {
+    const Region r = regions[rk[j]];
+    g[j] = r.e - r.s;
+  }
+}
+
+// Chunk table of an ascending key list: out[c] = keys below c kEvChunk << shift.
+__global__ void k_chunk_table(const uint64_t* keys, int32_t cnt, int shift, int64_t nch, int32_t* out) {
+  for (int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; c <= nch;
+       c += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    out[c] = first_not_below(keys, 0, cnt, static_cast<uint64_t>(c * kEvChunk) << shift);
+}
+
+// New places of the old points outside every region: insert: o plus the batch
+// points of the regions ending at or before o; delete: o minus the removed
+// points before o.  The packed 32-bit coordinates go to the new layout's own
 // array.  Points of regions are left to the rebuild.
 template <int D>
-__global__ void k_relayout(const int64_t* X, int64_t xcap, int64_t n, const int32_t* S, const int32_t* delflag,
-                           const int32_t* regid, int insert, int64_t* Y, int64_t ycap, int32_t* C32) {
+__global__ void k_relayout(const int64_t* X, int64_t xcap, int64_t n, EvView ev, const Region* regions, int insert,
+                           int64_t* Y, int64_t ycap, int32_t* C32) {
   for (int64_t o = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; o < n;
        o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    if (regid[o] >= 0) continue;
+    const int32_t u = ends_below(ev, o + 1);
+    if (u < ev.R && regions[ev.rk[u]].a <= o) continue;
     int64_t dst;
     if (insert) {
-      dst = o + S[o + 1];
+      dst = o + ev.gx[u];
     } else {
-      if (delflag[o]) continue;
-      dst = o - S[o];
+      int32_t j;
+      if (removed_at(ev, o, &j)) continue;
+      dst = o - j;
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -498,14 +601,14 @@ __global__ void k_relayout(const int64_t* X, int64_t xcap, int64_t n, const int3
 // New offsets of the surviving nodes.  Live node ranges nest like the tree,
 // so a node whose first point lies inside a region and that is deeper than
 // the region's node is below it: it dies (the rebuilt subtree replaces it).
-__global__ void k_node_update(Node* nodes, int32_t n_nodes, const int32_t* regid, const Region* regions,
-                              const int32_t* S, int insert, int64_t n_old) {
+__global__ void k_node_update(Node* nodes, int32_t n_nodes, EvView ev, const Region* regions, int insert,
+                              int64_t n_old) {
   for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_nodes; t += gridDim.x * blockDim.x) {
     const Node nd = nodes[t];
     if (nd.pad != 0) continue;   // dead since an earlier update
     if (nd.off < 0 || nd.off > n_old) continue;
     if (nd.off < n_old && nd.size > 0) {
-      const int32_t k = regid[nd.off];
+      const int32_t k = region_at(ev, regions, nd.off);
       if (k >= 0) {
         const Region r = regions[k];
         if (r.node == t) continue;   // overwritten by its rebuilt subtree
@@ -515,23 +618,24 @@ __global__ void k_node_update(Node* nodes, int32_t n_nodes, const int32_t* regid
         }
       }
     }
-    if (insert) nodes[t].off = nd.off + (nd.off < n_old ? S[nd.off + 1] : S[n_old]);
-    else nodes[t].off = nd.off - S[nd.off];
+    if (insert) nodes[t].off = nd.off + inserted_before(ev, nd.off, n_old);
+    else nodes[t].off = nd.off - removed_below(ev, nd.off);
   }
 }
 
-__global__ void k_region_final(Region* regions, int n_regions, const int32_t* S, int insert, int32_t* new_size) {
+__global__ void k_region_final(Region* regions, int n_regions, EvView ev, int insert, int32_t* new_size) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_regions; k += gridDim.x * blockDim.x) {
     Region& r = regions[k];
     if (insert) {
-      // batch points are noted at region ends; for a region with old points
+      // batch points are placed at region ends; for a region with old points
       // the end lies after its start, for an empty one (an empty tree of a
       // batch handle) on it, and its own batch points are not before it
-      r.new_start = r.a + (r.a < r.b ? S[r.a + 1] : S[r.a]);
+      r.new_start = r.a + ev.gx[ends_below(ev, r.a < r.b ? r.a + 1 : r.a)];
       r.new_size = (r.b - r.a) + (r.e - r.s);
     } else {
-      r.new_start = r.a - S[r.a];
-      r.new_size = (r.b - r.a) - (S[r.b] - S[r.a]);
+      const int32_t before = removed_below(ev, r.a);
+      r.new_start = r.a - before;
+      r.new_size = (r.b - r.a) - (removed_below(ev, r.b) - before);
     }
     new_size[k] = r.new_size;
   }
@@ -560,8 +664,7 @@ __global__ void k_region_roots(const Region* regions, int n_regions, const int32
 // region that survive, then (insert) its batch points.  Grid (regions, y).
 template <int D>
 __global__ void k_gather_regions(const Region* regions, const int64_t* comp, const int64_t* X, int64_t xcap,
-                                 const int32_t* S, const int32_t* delflag, const int64_t* batch, int64_t m,
-                                 int insert, int64_t* cin, int64_t ccap) {
+                                 EvView ev, const int64_t* batch, int64_t m, int insert, int64_t* cin, int64_t ccap) {
   const Region r = regions[blockIdx.x];
   const int64_t c0 = comp[blockIdx.x];
   const int64_t stride = static_cast<int64_t>(gridDim.y) * blockDim.x;
@@ -571,8 +674,9 @@ __global__ void k_gather_regions(const Region* regions, const int64_t* comp, con
     if (insert) {
       at = c0 + (o - r.a);
     } else {
-      if (delflag[o]) continue;
-      at = c0 + (o - S[o]) - r.new_start;
+      int32_t j;
+      if (removed_at(ev, o, &j)) continue;
+      at = c0 + (o - j) - r.new_start;
     }
 #pragma unroll
     for (int d = 0; d <= D; ++d) cin[d * ccap + at] = X[d * xcap + o];
@@ -869,18 +973,40 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
 
   // ---- weights: 1 per inserted point, 1 per point actually removed
   const int64_t* X = T->buf[T->cur];
-  DArr<int32_t> delflag(st), S(st), regid(st);
   PKD_TRY(Mw.need(m + 1));
   PKD_TRY(M.need(m + 1));
+  // the chunk tables of the event lists cover old positions 0 .. n
+  const int64_t nch = n / kEvChunk + 1;
+  const unsigned gch = static_cast<unsigned>(std::min<int64_t>(4096, (nch + 256) / 256));
+  DArr<uint64_t> dpos(st);
+  DArr<int32_t> dtab(st);
   int64_t n_removed = 0;
   if (insert) {
     PKD_TRY(fill(st, Mw.p, m, 1));
   } else {
-    PKD_TRY(delflag.need(n + 1));
-    PKD_TRY(fill(st, delflag.p, n + 1, 0));
+    // removed positions: matched, sorted, repeats dropped
+    DArr<uint64_t> pos(st);
+    DArr<uint32_t> ent(st);
+    DArr<int32_t> claim(st), at(st);
+    SortWork SW(st);
+    PKD_TRY(pos.need(m));
+    PKD_TRY(ent.need(m));
+    PKD_TRY(claim.need(m));
+    PKD_TRY(at.need(m + 1));
+    PKD_TRY(dpos.need(m));
+    PKD_TRY(dtab.need(static_cast<size_t>(nch) + 1));
     hipLaunchKernelGGL(k_match<D>, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256), 0, st, wf.p, m,
-                       leaf_of.p, T->nodes, X, T->cap, delflag.p, Mw.p);
+                       leaf_of.p, T->nodes, X, T->cap, n, pos.p, ent.p);
     PKD_TRY(kernel_status("k_match"));
+    uint64_t* ks = nullptr;
+    uint32_t* vs = nullptr;
+    PKD_TRY(radix_sort_pairs(st, pos.p, ent.p, m, bits_for(n), SW, &ks, &vs));
+    const unsigned gm = static_cast<unsigned>(std::min<int64_t>(4096, (m + 255) / 256));
+    hipLaunchKernelGGL(k_claim, dim3(gm), dim3(256), 0, st, ks, vs, m, n, claim.p, Mw.p);
+    PKD_TRY(kernel_status("k_claim"));
+    PKD_TRY(exscan_i32(st, claim.p, at.p, m, bsum));
+    hipLaunchKernelGGL(k_removed_list, dim3(gm), dim3(256), 0, st, ks, claim.p, at.p, m, dpos.p);
+    PKD_TRY(kernel_status("k_removed_list"));
   }
   PKD_TRY(exscan_i32(st, Mw.p, M.p, m, bsum));
   if (!insert) {
@@ -893,6 +1019,8 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
       T->last_regions = T->last_rebuilt = 0;
       return PKD_OK;
     }
+    hipLaunchKernelGGL(k_chunk_table, dim3(gch), dim3(256), 0, st, dpos.p, tot, 0, nch, dtab.p);
+    PKD_TRY(kernel_status("k_chunk_table"));
   }
 
   // ---- decide, round by round, top-down.  Nothing is written to the tree
@@ -985,28 +1113,49 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     PKD_TRY(dev_alloc(&own.p[2], sizeof(int32_t) * static_cast<size_t>(D) * static_cast<size_t>(new_cap), st));
     c32_new = static_cast<int32_t*>(own.p[2]);
   }
-  PKD_TRY(S.need(n + 2));
-  PKD_TRY(regid.need(n + 1));
-  PKD_TRY(fill(st, regid.p, n + 1, -1));
+  // the regions ordered by old end, their chunk table and (insert) the batch
+  // points placed before each end
+  DArr<uint64_t> rkey(st);
+  DArr<uint32_t> rval(st);
+  DArr<int32_t> rtab(st), growth(st), gx(st);
+  SortWork RW(st);
+  PKD_TRY(rtab.need(static_cast<size_t>(nch) + 1));
+  PKD_TRY(gx.need(static_cast<size_t>(n_regions) + 1));
+  EvView ev{};
+  ev.R = n_regions;
+  ev.rc = rtab.p;
+  ev.gx = gx.p;
+  ev.nd = static_cast<int32_t>(n_removed);
+  ev.dp = dpos.p;
+  ev.dc = dtab.p;
+  if (n_regions > 0) {
+    PKD_TRY(rkey.need(n_regions));
+    PKD_TRY(rval.need(n_regions));
+    const unsigned gr = static_cast<unsigned>(std::min<int64_t>(4096, (n_regions + 255) / 256));
+    hipLaunchKernelGGL(k_region_keys, dim3(gr), dim3(256), 0, st, regions.p, n_regions, rkey.p, rval.p);
+    PKD_TRY(kernel_status("k_region_keys"));
+    uint64_t* ks = nullptr;
+    uint32_t* vs = nullptr;
+    PKD_TRY(radix_sort_pairs(st, rkey.p, rval.p, n_regions, bits_for(2 * n + 1), RW, &ks, &vs));
+    ev.rkey = ks;
+    ev.rk = vs;
+    if (insert) {
+      PKD_TRY(growth.need(n_regions));
+      hipLaunchKernelGGL(k_region_growth, dim3(gr), dim3(256), 0, st, regions.p, vs, n_regions, growth.p);
+      PKD_TRY(kernel_status("k_region_growth"));
+      PKD_TRY(exscan_i32(st, growth.p, gx.p, n_regions, bsum));
+    }
+  } else {
+    PKD_TRY(fill(st, gx.p, 1, 0));
+  }
+  hipLaunchKernelGGL(k_chunk_table, dim3(gch), dim3(256), 0, st, ev.rkey, n_regions, 1, nch, rtab.p);
+  PKD_TRY(kernel_status("k_chunk_table"));
   // region ranges share out over y blocks in proportion to the points per region
   const unsigned ry = static_cast<unsigned>(
       std::min<int64_t>(1024, std::max<int64_t>(1, (n + m) / (std::max(n_regions, 1) * int64_t{8192}))));
-  if (insert) {
-    PKD_TRY(delflag.need(n + 2));
-    PKD_TRY(fill(st, delflag.p, n + 2, 0));
-    if (n_regions > 0)
-      hipLaunchKernelGGL(k_region_mark, dim3(n_regions, ry), dim3(256), 0, st, regions.p, regid.p, delflag.p, 1);
-    PKD_TRY(kernel_status("k_region_mark"));
-    PKD_TRY(exscan_i32(st, delflag.p, S.p, n + 1, bsum));   // S[o] = batch points noted at ends < o
-  } else {
-    if (n_regions > 0)
-      hipLaunchKernelGGL(k_region_mark, dim3(n_regions, ry), dim3(256), 0, st, regions.p, regid.p, delflag.p, 0);
-    PKD_TRY(kernel_status("k_region_mark"));
-    PKD_TRY(exscan_i32(st, delflag.p, S.p, n, bsum));       // S[o] = removed points before o
-  }
   if (n > 0) {
     const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (n + 255) / 256));
-    hipLaunchKernelGGL(k_relayout<D>, dim3(g), dim3(256), 0, st, Xold, old_cap, n, S.p, delflag.p, regid.p,
+    hipLaunchKernelGGL(k_relayout<D>, dim3(g), dim3(256), 0, st, Xold, old_cap, n, ev, regions.p,
                        insert ? 1 : 0, Ynew, new_cap, c32_new);
     PKD_TRY(kernel_status("k_relayout"));
   }
@@ -1022,7 +1171,7 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     PKD_TRY(dcomp.need(static_cast<size_t>(n_regions) + 1));
     PKD_TRY(roots.need(static_cast<size_t>(n_regions)));
     const unsigned gr = static_cast<unsigned>(std::min<int64_t>(65536, (n_regions + 256) / 256));
-    hipLaunchKernelGGL(k_region_final, dim3(gr), dim3(256), 0, st, regions.p, n_regions, S.p, insert ? 1 : 0,
+    hipLaunchKernelGGL(k_region_final, dim3(gr), dim3(256), 0, st, regions.p, n_regions, ev, insert ? 1 : 0,
                        rsize.p);
     PKD_TRY(kernel_status("k_region_final"));
     PKD_TRY(exscan_i32(st, rsize.p, comp32.p, n_regions, bsum));
@@ -1059,7 +1208,7 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     PKD_TRY(cin.need(static_cast<size_t>(D + 1) * std::max<int64_t>(R_pts, 1)));
     const int64_t ccap = std::max<int64_t>(R_pts, 1);
     hipLaunchKernelGGL(k_gather_regions<D>, dim3(n_regions, ry), dim3(256), 0, st, regions.p, dcomp.p, Xold, old_cap,
-                       S.p, delflag.p, wf.p, m, insert ? 1 : 0, cin.p, ccap);
+                       ev, wf.p, m, insert ? 1 : 0, cin.p, ccap);
     PKD_TRY(kernel_status("k_gather_regions"));
     tmp.t->node_count = n_regions;
     tmp.t->height = 0;
@@ -1077,7 +1226,7 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
   PKD_TRY(kernel_status("k_apply_sizes"));
   if (T->node_count > 0) {
     const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (T->node_count + 255) / 256));
-    hipLaunchKernelGGL(k_node_update, dim3(g), dim3(256), 0, st, T->nodes, T->node_count, regid.p, regions.p, S.p,
+    hipLaunchKernelGGL(k_node_update, dim3(g), dim3(256), 0, st, T->nodes, T->node_count, ev, regions.p,
                        insert ? 1 : 0, n);
     PKD_TRY(kernel_status("k_node_update"));
   }
