@@ -572,20 +572,73 @@ __global__ void k_chunk_table(const uint64_t* keys, int32_t cnt, int shift, int6
 // New places of the old points outside every region: insert: o plus the batch
 // points of the regions ending at or before o; delete: o minus the removed
 // points before o.  The packed 32-bit coordinates go to the new layout's own
-// array.  Points of regions are left to the rebuild.
+// array.  Points of regions are left to the rebuild.  One workgroup per chunk
+// of kEvChunk positions; the chunk's events (the region entries ending in it
+// and the first one after it, the removed positions in it) are staged in LDS
+// when they fit, so a point's lookup is a short search there.
+constexpr int kEvStage = 512;
+
 template <int D>
-__global__ void k_relayout(const int64_t* X, int64_t xcap, int64_t n, EvView ev, const Region* regions, int insert,
-                           int64_t* Y, int64_t ycap, int32_t* C32) {
-  for (int64_t o = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; o < n;
-       o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int32_t u = ends_below(ev, o + 1);
-    if (u < ev.R && regions[ev.rk[u]].a <= o) continue;
+__global__ void __launch_bounds__(256) k_relayout(const int64_t* X, int64_t xcap, int64_t n, EvView ev,
+                                                  const Region* regions, int insert, int64_t* Y, int64_t ycap,
+                                                  int32_t* C32) {
+  __shared__ uint64_t s_key[kEvStage];
+  __shared__ int32_t s_a[kEvStage];
+  __shared__ int32_t s_g[kEvStage];
+  __shared__ uint64_t s_dp[kEvStage];
+  const int64_t c = blockIdx.x;
+  const int64_t o0 = c * kEvChunk;
+  const int64_t o1 = o0 + kEvChunk < n ? o0 + kEvChunk : n;
+  if (o0 >= o1) return;
+  // o in the chunk: the first entry ending after o lies in [r0, r1], the
+  // removed positions below o number d0 + (those of [d0, d1) below o)
+  const int32_t r0 = ev.rc[c], r1 = ev.rc[c + 1];
+  const int32_t d0 = insert ? 0 : ev.dc[c], d1 = insert ? 0 : ev.dc[c + 1];
+  const int32_t nr = r1 - r0, nd = d1 - d0;
+  const bool staged = nr < kEvStage && nd <= kEvStage;
+  if (staged) {
+    const int32_t na = (r1 < ev.R ? nr + 1 : nr);
+    for (int i = threadIdx.x; i <= nr; i += blockDim.x) {
+      if (i < nr) s_key[i] = ev.rkey[r0 + i];
+      if (i < na) s_a[i] = regions[ev.rk[r0 + i]].a;
+      if (insert) s_g[i] = ev.gx[r0 + i];
+    }
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) s_dp[i] = ev.dp[d0 + i];
+  }
+  __syncthreads();
+  for (int64_t o = o0 + threadIdx.x; o < o1; o += blockDim.x) {
+    int32_t u = 0, j = 0;   // u: first entry ending after o; j: removed positions below o
+    bool removed = false;
+    if (staged) {
+      int32_t lo = 0, hi = nr;
+      const uint64_t x = static_cast<uint64_t>(o + 1) << 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (s_key[mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      if (r0 + lo < ev.R && s_a[lo] <= o) continue;
+      u = lo;
+      if (!insert) {
+        int32_t l2 = 0, h2 = nd;
+        while (l2 < h2) {
+          const int32_t mid = (l2 + h2) >> 1;
+          if (s_dp[mid] < static_cast<uint64_t>(o)) l2 = mid + 1;
+          else h2 = mid;
+        }
+        removed = l2 < nd && s_dp[l2] == static_cast<uint64_t>(o);
+        j = d0 + l2;
+      }
+    } else {
+      u = ends_below(ev, o + 1);
+      if (u < ev.R && regions[ev.rk[u]].a <= o) continue;
+      if (!insert) removed = removed_at(ev, o, &j);
+    }
     int64_t dst;
     if (insert) {
-      dst = o + ev.gx[u];
+      dst = o + (staged ? s_g[u] : ev.gx[u]);
     } else {
-      int32_t j;
-      if (removed_at(ev, o, &j)) continue;
+      if (removed) continue;
       dst = o - j;
     }
 #pragma unroll
@@ -661,14 +714,20 @@ __global__ void k_region_roots(const Region* regions, int n_regions, const int32
 
 // The points of every region after the update, packed region after region
 // (region r from comp[r]) as the input of the rebuild: the old points of the
-// region that survive, then (insert) its batch points.  Grid (regions, y).
+// region that survive, then (insert) its batch points.  One wave per region
+// (four per workgroup; most regions are a leaf and its few new points), the
+// ry blocks of grid dimension y sharing a large region's range.
 template <int D>
-__global__ void k_gather_regions(const Region* regions, const int64_t* comp, const int64_t* X, int64_t xcap,
-                                 EvView ev, const int64_t* batch, int64_t m, int insert, int64_t* cin, int64_t ccap) {
-  const Region r = regions[blockIdx.x];
-  const int64_t c0 = comp[blockIdx.x];
-  const int64_t stride = static_cast<int64_t>(gridDim.y) * blockDim.x;
-  const int64_t first = static_cast<int64_t>(blockIdx.y) * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_gather_regions(const Region* regions, int n_regions, const int64_t* comp,
+                                                        const int64_t* X, int64_t xcap, EvView ev,
+                                                        const int64_t* batch, int64_t m, int insert, int64_t* cin,
+                                                        int64_t ccap) {
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= n_regions) return;
+  const Region r = regions[k];
+  const int64_t c0 = comp[k];
+  const int64_t stride = static_cast<int64_t>(gridDim.y) * 64;
+  const int64_t first = static_cast<int64_t>(blockIdx.y) * 64 + (threadIdx.x & 63);
   for (int64_t o = r.a + first; o < r.b; o += stride) {
     int64_t at;
     if (insert) {
@@ -706,14 +765,19 @@ __device__ inline int region_of(const int64_t* comp, int nreg, int64_t p) {
   return lo;
 }
 
-// Rebuilt points back from the packed rebuild to their regions' ranges.
+// Rebuilt points back from the packed rebuild to their regions' ranges: one
+// wave per region as in the gather.
 template <int D>
-__global__ void k_scatter_back(const Region* regions, const int64_t* comp, int nreg, const int64_t* Z, int64_t zcap,
-                               int64_t total, int64_t* Y, int64_t ycap, int32_t* C32) {
-  for (int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; p < total;
-       p += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int r = region_of(comp, nreg, p);
-    const int64_t dst = regions[r].new_start + (p - comp[r]);
+__global__ void __launch_bounds__(256) k_scatter_back(const Region* regions, const int64_t* comp, int nreg,
+                                                      const int64_t* Z, int64_t zcap, int64_t* Y, int64_t ycap,
+                                                      int32_t* C32) {
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= nreg) return;
+  const int64_t p0 = comp[k], p1 = comp[k + 1];
+  const int64_t shift = regions[k].new_start - p0;
+  const int64_t stride = static_cast<int64_t>(gridDim.y) * 64;
+  for (int64_t p = p0 + static_cast<int64_t>(blockIdx.y) * 64 + (threadIdx.x & 63); p < p1; p += stride) {
+    const int64_t dst = p + shift;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int64_t v = Z[d * zcap + p];
@@ -1150,13 +1214,9 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
   }
   hipLaunchKernelGGL(k_chunk_table, dim3(gch), dim3(256), 0, st, ev.rkey, n_regions, 1, nch, rtab.p);
   PKD_TRY(kernel_status("k_chunk_table"));
-  // region ranges share out over y blocks in proportion to the points per region
-  const unsigned ry = static_cast<unsigned>(
-      std::min<int64_t>(1024, std::max<int64_t>(1, (n + m) / (std::max(n_regions, 1) * int64_t{8192}))));
   if (n > 0) {
-    const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (n + 255) / 256));
-    hipLaunchKernelGGL(k_relayout<D>, dim3(g), dim3(256), 0, st, Xold, old_cap, n, ev, regions.p,
-                       insert ? 1 : 0, Ynew, new_cap, c32_new);
+    hipLaunchKernelGGL(k_relayout<D>, dim3(static_cast<unsigned>(nch)), dim3(256), 0, st, Xold, old_cap, n, ev,
+                       regions.p, insert ? 1 : 0, Ynew, new_cap, c32_new);
     PKD_TRY(kernel_status("k_relayout"));
   }
   // region sizes and places after the update, their packed offsets in the
@@ -1198,6 +1258,12 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     }
   } tmp{nullptr, st};
   const int64_t R_pts = R_pts32;
+  // one wave per region in the gather and the scatter back; the blocks of
+  // grid dimension y share the range of a region in proportion to the points
+  // per region (old points before a delete)
+  const unsigned ry = static_cast<unsigned>(std::min<int64_t>(
+      4096, std::max<int64_t>(1, (R_pts + n_removed) / (std::max(n_regions, 1) * int64_t{2048}))));
+  const unsigned gx4 = static_cast<unsigned>((std::max(n_regions, 1) + 3) / 4);
   int32_t appended = 0;
   if (n_regions > 0) {
     tmp.t = new pkd_tree;
@@ -1207,8 +1273,8 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     PKD_TRY(ensure_nodes(tmp.t, st, std::max<int64_t>(1024, n_regions + R_pts / 8)));
     PKD_TRY(cin.need(static_cast<size_t>(D + 1) * std::max<int64_t>(R_pts, 1)));
     const int64_t ccap = std::max<int64_t>(R_pts, 1);
-    hipLaunchKernelGGL(k_gather_regions<D>, dim3(n_regions, ry), dim3(256), 0, st, regions.p, dcomp.p, Xold, old_cap,
-                       ev, wf.p, m, insert ? 1 : 0, cin.p, ccap);
+    hipLaunchKernelGGL(k_gather_regions<D>, dim3(gx4, ry), dim3(256), 0, st, regions.p, n_regions, dcomp.p, Xold,
+                       old_cap, ev, wf.p, m, insert ? 1 : 0, cin.p, ccap);
     PKD_TRY(kernel_status("k_gather_regions"));
     tmp.t->node_count = n_regions;
     tmp.t->height = 0;
@@ -1233,9 +1299,8 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
   if (n_regions > 0) {
     pkd_tree* Z = tmp.t;
     if (R_pts > 0) {
-      const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (R_pts + 255) / 256));
-      hipLaunchKernelGGL(k_scatter_back<D>, dim3(g), dim3(256), 0, st, regions.p, dcomp.p, n_regions,
-                         Z->buf[Z->cur], Z->cap, R_pts, Ynew, new_cap, c32_new);
+      hipLaunchKernelGGL(k_scatter_back<D>, dim3(gx4, ry), dim3(256), 0, st, regions.p, dcomp.p, n_regions,
+                         Z->buf[Z->cur], Z->cap, Ynew, new_cap, c32_new);
       PKD_TRY(kernel_status("k_scatter_back"));
     }
     const int32_t base = T->node_count;
