@@ -88,7 +88,11 @@ typedef struct {
                                every sieving subproblem's sample-candidate threshold, so the
                                sampler's overflow (bias < 0) or underflow (bias > 0) retry
                                runs; the tree never changes */
-  int32_t reserved[6];
+  int32_t update_events;    /* test knob, default 0: how a batch update places the old
+                               points: 0 by the batch's density, 1 always from the sorted
+                               update events, 2 always from per-point arrays; the tree
+                               never changes */
+  int32_t reserved[5];
 } pkd_tuning;
 
 /*

@@ -54,7 +54,8 @@ class _Allocator(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("tile_points", C.c_int32), ("cand_shift_bias", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("tile_points", C.c_int32), ("cand_shift_bias", C.c_int32), ("update_events", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 _lib = None
@@ -230,11 +231,12 @@ class Params:
         return p
 
 
-def _tuning(tile, cand_bias=0):
+def _tuning(tile, cand_bias=0, update_events=0):
     t = _Tuning()
     lib().pkd_default_tuning(C.byref(t))
     t.tile_points = tile
     t.cand_shift_bias = cand_bias
+    t.update_events = update_events
     return t
 
 
@@ -243,7 +245,8 @@ class Tree:
     builds one tree; Tree.batch(params, coords, ids, offsets) builds many trees
     in one pass (tree t owns points offsets[t]:offsets[t+1])."""
 
-    def __init__(self, params: Params, coords, ids, tile: int = 2048, stream=None, _handle=None, cand_bias: int = 0):
+    def __init__(self, params: Params, coords, ids, tile: int = 2048, stream=None, _handle=None, cand_bias: int = 0,
+                 update_events: int = 0):
         self.p = params
         if _handle is not None:
             self.h = _handle
@@ -253,18 +256,20 @@ class Tree:
         n = i.shape[0]
         assert tuple(c.shape) == (params.dim, n)
         h = C.c_void_p()
-        _check(lib().pkd_build(C.byref(params._c()), C.byref(_tuning(tile, cand_bias)), _stream(stream), _ptr(c), _ptr(i), n,
-                               C.byref(h)), "pkd_build")
+        _check(lib().pkd_build(C.byref(params._c()), C.byref(_tuning(tile, cand_bias, update_events)), _stream(stream),
+                               _ptr(c), _ptr(i), n, C.byref(h)), "pkd_build")
         self.h = h
 
     @classmethod
-    def batch(cls, params: Params, coords, ids, offsets, tile: int = 2048, stream=None, cand_bias: int = 0):
+    def batch(cls, params: Params, coords, ids, offsets, tile: int = 2048, stream=None, cand_bias: int = 0,
+              update_events: int = 0):
         c = _dev(coords)
         i = _dev(ids)
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         assert tuple(c.shape) == (params.dim, i.shape[0]) and off[-1] == i.shape[0]
         h = C.c_void_p()
-        _check(lib().pkd_build_batch(C.byref(params._c()), C.byref(_tuning(tile, cand_bias)), _stream(stream),
+        _check(lib().pkd_build_batch(C.byref(params._c()), C.byref(_tuning(tile, cand_bias, update_events)),
+                                     _stream(stream),
                                      off.shape[0] - 1, _ptr(c), _ptr(i), off.ctypes.data_as(C.c_void_p),
                                      C.byref(h)), "pkd_build_batch")
         return cls(params, None, None, _handle=h)

@@ -258,6 +258,8 @@ int check_params(const pkd_params* p, const pkd_tuning* t, Params* out) {
   if (tile != 1024 && tile != 2048 && tile != 4096) return PKD_ERR_INVALID_ARG;
   const int bias = t ? t->cand_shift_bias : 0;
   if (bias < -4 || bias > 4) return PKD_ERR_INVALID_ARG;
+  const int events = t ? t->update_events : 0;
+  if (events < 0 || events > 2) return PKD_ERR_INVALID_ARG;
   out->D = p->dim;
   out->lambda = p->lambda;
   out->phi = p->leaf_size;
@@ -268,6 +270,7 @@ int check_params(const pkd_params* p, const pkd_tuning* t, Params* out) {
   out->seed = p->seed;
   out->tile = tile;
   out->cand_bias = bias;
+  out->update_events = events;
   return PKD_OK;
 }
 
@@ -752,6 +755,7 @@ int pkd_build_plan_finish(pkd_build_plan* plan, void* stream, int32_t* redone) {
     pkd_default_tuning(&tu);
     tu.tile_points = T->prm.tile;
     tu.cand_shift_bias = T->prm.cand_bias;
+    tu.update_events = T->prm.update_events;
     std::vector<int64_t> offs(static_cast<size_t>(T->n_trees) + 1, 0);
     {
       // offsets from the roots (empty trees hold no task)

@@ -100,6 +100,7 @@ struct Params {
   uint64_t seed;
   int tile;
   int cand_bias;   // test knob: shifts every candidate threshold (results unchanged)
+  int update_events;   // test knob: 0 auto, 1 sorted event lists, 2 per-point arrays (results unchanged)
 };
 
 // Workgroups are handed to the 8 XCDs round robin (workgroup b runs on XCD

@@ -480,14 +480,19 @@ __global__ void k_add_regions(int* n_regions, const int32_t* roff, int* n_sizes,
   *n_sizes += soff[ns];
 }
 
-// ---- where the old points go.  Two sorted event lists replace per-point
-// arrays (which cost O(n) fills and a prefix sum over the whole tree at every
-// batch, however small): the rebuild regions ordered by their old end b (an
-// insert adds a region's batch points there; a region's own points are left
-// to the rebuild), and for a delete the ascending positions of the removed
-// points.  A table per chunk of kEvChunk old positions holds how many events
-// lie below the chunk, so a lookup searches only the chunk's own events.
+// ---- where the old points go.  A batch that is small against the tree is
+// described by two sorted event lists instead of per-point arrays (which cost
+// O(n) fills and a prefix sum over the whole tree at every batch, however
+// small): the rebuild regions ordered by their old end b (an insert adds a
+// region's batch points there; a region's own points are left to the
+// rebuild), and for a delete the ascending positions of the removed points.
+// A table per chunk of kEvChunk old positions holds how many events lie below
+// the chunk, so a lookup searches only the chunk's own events.  A batch whose
+// events are dense in the tree (more than one per kDenseRatio positions)
+// takes per-point arrays instead: region marks, and the prefix sum of the
+// batch points noted at region ends or of the removal flags.
 constexpr int64_t kEvChunk = 4096;
+constexpr int64_t kDenseRatio = 32;
 
 struct EvView {
   const uint64_t* rkey;   // [R] 2 b + (region empty), ascending: at equal ends a non-empty region comes first
@@ -497,6 +502,10 @@ struct EvView {
   const uint64_t* dp;     // [nd] delete: removed positions, ascending
   const int32_t* dc;      // [nch + 1] removed positions below c kEvChunk
   int32_t R, nd;
+  int dense;              // per-point arrays instead of the lists:
+  const int32_t* S;       //   [n + 2] insert: batch points at region ends below o; delete: removed below o
+  const int32_t* regid;   //   [n] the region holding o, or -1
+  const int32_t* delflag; //   [n] delete: o is removed
 };
 
 // Index of the first a[lo .. hi) that is >= x (hi if none); a ascending.
@@ -509,14 +518,20 @@ __device__ inline int32_t first_not_below(const uint64_t* a, int32_t lo, int32_t
   return lo;
 }
 
-// Regions whose old end lies below x, for 0 <= x <= n.
+// Regions whose old end lies below x, for 0 <= x <= n (event lists only).
 __device__ inline int32_t ends_below(const EvView& ev, int64_t x) {
   const int64_t c = x / kEvChunk;
   return first_not_below(ev.rkey, ev.rc[c], ev.rc[c + 1], static_cast<uint64_t>(x) << 1);
 }
 
+// Batch points of the regions whose old end lies below x, for 0 <= x <= n.
+__device__ inline int32_t growth_below(const EvView& ev, int64_t x) {
+  return ev.dense ? ev.S[x] : ev.gx[ends_below(ev, x)];
+}
+
 // Removed positions below x, for 0 <= x <= n.
 __device__ inline int32_t removed_below(const EvView& ev, int64_t x) {
+  if (ev.dense) return ev.S[x];
   const int64_t c = x / kEvChunk;
   return first_not_below(ev.dp, ev.dc[c], ev.dc[c + 1], static_cast<uint64_t>(x));
 }
@@ -525,24 +540,46 @@ __device__ inline int32_t removed_below(const EvView& ev, int64_t x) {
 // regions ending at or before x (x < n), or before x (x = n: a node at the
 // end is placed before the regions that end there).
 __device__ inline int32_t inserted_before(const EvView& ev, int64_t x, int64_t n) {
-  return ev.gx[ends_below(ev, x < n ? x + 1 : x)];
+  return growth_below(ev, x < n ? x + 1 : x);
 }
 
-// The region holding old position o (0 <= o < n), or -1.  The first entry
-// ending after o is the only candidate: regions are disjoint, and an empty
-// region (an empty tree of a batch handle) sits at a boundary between trees,
-// never strictly inside another region.
+// The region holding old position o (0 <= o < n), or -1.  In the lists the
+// first entry ending after o is the only candidate: regions are disjoint, and
+// an empty region (an empty tree of a batch handle) sits at a boundary
+// between trees, never strictly inside another region.
 __device__ inline int32_t region_at(const EvView& ev, const Region* regions, int64_t o) {
+  if (ev.dense) return ev.regid[o];
   const int32_t u = ends_below(ev, o + 1);
   if (u >= ev.R) return -1;
   const int32_t k = static_cast<int32_t>(ev.rk[u]);
   return regions[k].a <= o ? k : -1;
 }
 
+// Whether old position o (0 <= o < n) is removed; *below = removed below o.
 __device__ inline bool removed_at(const EvView& ev, int64_t o, int32_t* below) {
+  if (ev.dense) {
+    *below = ev.S[o];
+    return ev.delflag[o] != 0;
+  }
   const int32_t j = removed_below(ev, o);
   *below = j;
   return j < ev.nd && ev.dp[j] == static_cast<uint64_t>(o);
+}
+
+// Per-point arrays of a dense batch: the region of every old position, and
+// (insert) each region's batch points noted at its end.  Grid (regions, y):
+// the y blocks of a region share its range.
+__global__ void k_region_mark(const Region* regions, int32_t* regid, int32_t* at_end) {
+  const Region r = regions[blockIdx.x];
+  const int64_t stride = static_cast<int64_t>(gridDim.y) * blockDim.x;
+  for (int64_t o = r.a + static_cast<int64_t>(blockIdx.y) * blockDim.x + threadIdx.x; o < r.b; o += stride)
+    regid[o] = blockIdx.x;
+  if (at_end && blockIdx.y == 0 && threadIdx.x == 0) atomicAdd(at_end + r.b, r.e - r.s);
+}
+
+// Removal flags of a dense delete from the sorted removed positions.
+__global__ void k_mark_removed(const uint64_t* dp, int32_t nd, int32_t* flag) {
+  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nd; j += gridDim.x * blockDim.x) flag[dp[j]] = 1;
 }
 
 // Sort keys of the regions by old end.
@@ -575,7 +612,8 @@ __global__ void k_chunk_table(const uint64_t* keys, int32_t cnt, int shift, int6
 // array.  Points of regions are left to the rebuild.  One workgroup per chunk
 // of kEvChunk positions; the chunk's events (the region entries ending in it
 // and the first one after it, the removed positions in it) are staged in LDS
-// when they fit, so a point's lookup is a short search there.
+// when they fit, so a point's lookup is a short search there (a dense batch
+// reads its per-point arrays).
 constexpr int kEvStage = 512;
 
 template <int D>
@@ -592,10 +630,11 @@ __global__ void __launch_bounds__(256) k_relayout(const int64_t* X, int64_t xcap
   if (o0 >= o1) return;
   // o in the chunk: the first entry ending after o lies in [r0, r1], the
   // removed positions below o number d0 + (those of [d0, d1) below o)
-  const int32_t r0 = ev.rc[c], r1 = ev.rc[c + 1];
-  const int32_t d0 = insert ? 0 : ev.dc[c], d1 = insert ? 0 : ev.dc[c + 1];
+  const bool lists = !ev.dense;
+  const int32_t r0 = lists ? ev.rc[c] : 0, r1 = lists ? ev.rc[c + 1] : 0;
+  const int32_t d0 = lists && !insert ? ev.dc[c] : 0, d1 = lists && !insert ? ev.dc[c + 1] : 0;
   const int32_t nr = r1 - r0, nd = d1 - d0;
-  const bool staged = nr < kEvStage && nd <= kEvStage;
+  const bool staged = lists && nr < kEvStage && nd <= kEvStage;
   if (staged) {
     const int32_t na = (r1 < ev.R ? nr + 1 : nr);
     for (int i = threadIdx.x; i <= nr; i += blockDim.x) {
@@ -629,14 +668,17 @@ __global__ void __launch_bounds__(256) k_relayout(const int64_t* X, int64_t xcap
         removed = l2 < nd && s_dp[l2] == static_cast<uint64_t>(o);
         j = d0 + l2;
       }
-    } else {
+    } else if (lists) {
       u = ends_below(ev, o + 1);
       if (u < ev.R && regions[ev.rk[u]].a <= o) continue;
+      if (!insert) removed = removed_at(ev, o, &j);
+    } else {
+      if (ev.regid[o] >= 0) continue;
       if (!insert) removed = removed_at(ev, o, &j);
     }
     int64_t dst;
     if (insert) {
-      dst = o + (staged ? s_g[u] : ev.gx[u]);
+      dst = o + (staged ? s_g[u] : (lists ? ev.gx[u] : ev.S[o + 1]));
     } else {
       if (removed) continue;
       dst = o - j;
@@ -676,14 +718,15 @@ __global__ void k_node_update(Node* nodes, int32_t n_nodes, EvView ev, const Reg
   }
 }
 
-__global__ void k_region_final(Region* regions, int n_regions, EvView ev, int insert, int32_t* new_size) {
+__global__ void k_region_final(Region* regions, int n_regions, EvView ev, int insert, int32_t* new_size,
+                               int32_t* old_size) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_regions; k += gridDim.x * blockDim.x) {
     Region& r = regions[k];
     if (insert) {
       // batch points are placed at region ends; for a region with old points
       // the end lies after its start, for an empty one (an empty tree of a
       // batch handle) on it, and its own batch points are not before it
-      r.new_start = r.a + ev.gx[ends_below(ev, r.a < r.b ? r.a + 1 : r.a)];
+      r.new_start = r.a + growth_below(ev, r.a < r.b ? r.a + 1 : r.a);
       r.new_size = (r.b - r.a) + (r.e - r.s);
     } else {
       const int32_t before = removed_below(ev, r.a);
@@ -691,6 +734,7 @@ __global__ void k_region_final(Region* regions, int n_regions, EvView ev, int in
       r.new_size = (r.b - r.a) - (removed_below(ev, r.b) - before);
     }
     new_size[k] = r.new_size;
+    old_size[k] = r.b - r.a;
   }
 }
 
@@ -712,39 +756,71 @@ __global__ void k_region_roots(const Region* regions, int n_regions, const int32
   }
 }
 
+// Work over the regions' points is spread by points, not by regions (their
+// sizes are skewed: many leaves and a few large subtrees): each workgroup
+// takes kFlatChunk consecutive entries q of a per-region prefix sum P (region
+// k owns P[k] .. P[k+1]-1), finds the regions of its first and last entry by
+// binary search, and each thread then searches only that range.
+constexpr int kFlatChunk = 2048;
+
+// The last index in [lo, hi) whose P is <= q (P[lo] <= q).  An empty region
+// shares its P with the next one and is never chosen over it.
+__device__ inline int last_at_or_below(const int32_t* P, int lo, int hi, int64_t q) {
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (P[mid] <= q) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ inline void chunk_regions(const int32_t* P, int nreg, int64_t q0, int64_t q1, int* k0, int* k1) {
+  __shared__ int s_k[2];
+  if (threadIdx.x == 0) s_k[0] = last_at_or_below(P, 0, nreg, q0);
+  if (threadIdx.x == 1) s_k[1] = last_at_or_below(P, 0, nreg, q1 - 1);
+  __syncthreads();
+  *k0 = s_k[0];
+  *k1 = s_k[1];
+}
+
 // The points of every region after the update, packed region after region
-// (region r from comp[r]) as the input of the rebuild: the old points of the
-// region that survive, then (insert) its batch points.  One wave per region
-// (four per workgroup; most regions are a leaf and its few new points), the
-// ry blocks of grid dimension y sharing a large region's range.
+// (region k from comp[k]) as the input of the rebuild: the old points of the
+// region that survive, then (insert) its batch points.  Insert: P = comp and
+// entry q is output position q; delete: P is the prefix of the regions' old
+// sizes and entry q an old point, placed among the survivors.
 template <int D>
-__global__ void __launch_bounds__(256) k_gather_regions(const Region* regions, int n_regions, const int64_t* comp,
-                                                        const int64_t* X, int64_t xcap, EvView ev,
-                                                        const int64_t* batch, int64_t m, int insert, int64_t* cin,
-                                                        int64_t ccap) {
-  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (k >= n_regions) return;
-  const Region r = regions[k];
-  const int64_t c0 = comp[k];
-  const int64_t stride = static_cast<int64_t>(gridDim.y) * 64;
-  const int64_t first = static_cast<int64_t>(blockIdx.y) * 64 + (threadIdx.x & 63);
-  for (int64_t o = r.a + first; o < r.b; o += stride) {
-    int64_t at;
+__global__ void __launch_bounds__(256) k_gather_regions(const Region* regions, int n_regions, const int32_t* P,
+                                                        int64_t total, const int32_t* comp, const int64_t* X,
+                                                        int64_t xcap, EvView ev, const int64_t* batch, int64_t m,
+                                                        int insert, int64_t* cin, int64_t ccap) {
+  const int64_t q0 = static_cast<int64_t>(blockIdx.x) * kFlatChunk;
+  if (q0 >= total) return;
+  const int64_t q1 = q0 + kFlatChunk < total ? q0 + kFlatChunk : total;
+  int k0, k1;
+  chunk_regions(P, n_regions, q0, q1, &k0, &k1);
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+    const int k = last_at_or_below(P, k0, k1 + 1, q);
+    const Region r = regions[k];
+    const int64_t local = q - P[k];
     if (insert) {
-      at = c0 + (o - r.a);
+      const int64_t nold = r.b - r.a;
+      if (local < nold) {
+        const int64_t o = r.a + local;
+#pragma unroll
+        for (int d = 0; d <= D; ++d) cin[d * ccap + q] = X[d * xcap + o];
+      } else {
+        const int64_t i = r.s + (local - nold);
+#pragma unroll
+        for (int d = 0; d <= D; ++d) cin[d * ccap + q] = batch[d * m + i];
+      }
     } else {
+      const int64_t o = r.a + local;
       int32_t j;
       if (removed_at(ev, o, &j)) continue;
-      at = c0 + (o - j) - r.new_start;
+      const int64_t at = comp[k] + (o - j) - r.new_start;
+#pragma unroll
+      for (int d = 0; d <= D; ++d) cin[d * ccap + at] = X[d * xcap + o];
     }
-#pragma unroll
-    for (int d = 0; d <= D; ++d) cin[d * ccap + at] = X[d * xcap + o];
-  }
-  if (insert) {
-    const int64_t base = c0 + (r.b - r.a) - r.s;
-    for (int64_t i = r.s + first; i < r.e; i += stride)
-#pragma unroll
-      for (int d = 0; d <= D; ++d) cin[d * ccap + base + i] = batch[d * m + i];
   }
 }
 
@@ -765,19 +841,20 @@ __device__ inline int region_of(const int64_t* comp, int nreg, int64_t p) {
   return lo;
 }
 
-// Rebuilt points back from the packed rebuild to their regions' ranges: one
-// wave per region as in the gather.
+// Rebuilt points back from the packed rebuild (region k from comp[k]) to
+// their regions' ranges, spread by points as in the gather.
 template <int D>
-__global__ void __launch_bounds__(256) k_scatter_back(const Region* regions, const int64_t* comp, int nreg,
-                                                      const int64_t* Z, int64_t zcap, int64_t* Y, int64_t ycap,
-                                                      int32_t* C32) {
-  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (k >= nreg) return;
-  const int64_t p0 = comp[k], p1 = comp[k + 1];
-  const int64_t shift = regions[k].new_start - p0;
-  const int64_t stride = static_cast<int64_t>(gridDim.y) * 64;
-  for (int64_t p = p0 + static_cast<int64_t>(blockIdx.y) * 64 + (threadIdx.x & 63); p < p1; p += stride) {
-    const int64_t dst = p + shift;
+__global__ void __launch_bounds__(256) k_scatter_back(const Region* regions, const int32_t* comp, int nreg,
+                                                      int64_t total, const int64_t* Z, int64_t zcap, int64_t* Y,
+                                                      int64_t ycap, int32_t* C32) {
+  const int64_t q0 = static_cast<int64_t>(blockIdx.x) * kFlatChunk;
+  if (q0 >= total) return;
+  const int64_t q1 = q0 + kFlatChunk < total ? q0 + kFlatChunk : total;
+  int k0, k1;
+  chunk_regions(comp, nreg, q0, q1, &k0, &k1);
+  for (int64_t p = q0 + threadIdx.x; p < q1; p += blockDim.x) {
+    const int k = last_at_or_below(comp, k0, k1 + 1, p);
+    const int64_t dst = regions[k].new_start + (p - comp[k]);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int64_t v = Z[d * zcap + p];
@@ -1058,7 +1135,6 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     PKD_TRY(claim.need(m));
     PKD_TRY(at.need(m + 1));
     PKD_TRY(dpos.need(m));
-    PKD_TRY(dtab.need(static_cast<size_t>(nch) + 1));
     hipLaunchKernelGGL(k_match<D>, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256), 0, st, wf.p, m,
                        leaf_of.p, T->nodes, X, T->cap, n, pos.p, ent.p);
     PKD_TRY(kernel_status("k_match"));
@@ -1083,8 +1159,6 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
       T->last_regions = T->last_rebuilt = 0;
       return PKD_OK;
     }
-    hipLaunchKernelGGL(k_chunk_table, dim3(gch), dim3(256), 0, st, dpos.p, tot, 0, nch, dtab.p);
-    PKD_TRY(kernel_status("k_chunk_table"));
   }
 
   // ---- decide, round by round, top-down.  Nothing is written to the tree
@@ -1177,43 +1251,81 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     PKD_TRY(dev_alloc(&own.p[2], sizeof(int32_t) * static_cast<size_t>(D) * static_cast<size_t>(new_cap), st));
     c32_new = static_cast<int32_t*>(own.p[2]);
   }
-  // the regions ordered by old end, their chunk table and (insert) the batch
-  // points placed before each end
+  // the update's events: sorted lists with chunk tables for a batch that is
+  // small against the tree, per-point arrays for a dense one
+  const bool dense = P.update_events == 0 ? (static_cast<int64_t>(n_regions) + n_removed) * kDenseRatio > n
+                                          : P.update_events == 2;
   DArr<uint64_t> rkey(st);
   DArr<uint32_t> rval(st);
-  DArr<int32_t> rtab(st), growth(st), gx(st);
+  DArr<int32_t> rtab(st), growth(st), gx(st), S(st), regid(st), flag(st);
   SortWork RW(st);
-  PKD_TRY(rtab.need(static_cast<size_t>(nch) + 1));
-  PKD_TRY(gx.need(static_cast<size_t>(n_regions) + 1));
   EvView ev{};
   ev.R = n_regions;
-  ev.rc = rtab.p;
-  ev.gx = gx.p;
   ev.nd = static_cast<int32_t>(n_removed);
   ev.dp = dpos.p;
-  ev.dc = dtab.p;
-  if (n_regions > 0) {
-    PKD_TRY(rkey.need(n_regions));
-    PKD_TRY(rval.need(n_regions));
-    const unsigned gr = static_cast<unsigned>(std::min<int64_t>(4096, (n_regions + 255) / 256));
-    hipLaunchKernelGGL(k_region_keys, dim3(gr), dim3(256), 0, st, regions.p, n_regions, rkey.p, rval.p);
-    PKD_TRY(kernel_status("k_region_keys"));
-    uint64_t* ks = nullptr;
-    uint32_t* vs = nullptr;
-    PKD_TRY(radix_sort_pairs(st, rkey.p, rval.p, n_regions, bits_for(2 * n + 1), RW, &ks, &vs));
-    ev.rkey = ks;
-    ev.rk = vs;
+  ev.dense = dense ? 1 : 0;
+  if (dense) {
+    PKD_TRY(S.need(n + 2));
+    PKD_TRY(regid.need(n + 1));
+    PKD_TRY(flag.need(n + 2));
+    PKD_TRY(fill(st, regid.p, n + 1, -1));
+    PKD_TRY(fill(st, flag.p, n + 2, 0));
+    // region ranges share out over y blocks in proportion to the points per region
+    const unsigned rym = static_cast<unsigned>(
+        std::min<int64_t>(1024, std::max<int64_t>(1, (n + m) / (std::max(n_regions, 1) * int64_t{8192}))));
+    if (n_regions > 0)
+      hipLaunchKernelGGL(k_region_mark, dim3(n_regions, rym), dim3(256), 0, st, regions.p, regid.p,
+                         insert ? flag.p : nullptr);
+    PKD_TRY(kernel_status("k_region_mark"));
     if (insert) {
-      PKD_TRY(growth.need(n_regions));
-      hipLaunchKernelGGL(k_region_growth, dim3(gr), dim3(256), 0, st, regions.p, vs, n_regions, growth.p);
-      PKD_TRY(kernel_status("k_region_growth"));
-      PKD_TRY(exscan_i32(st, growth.p, gx.p, n_regions, bsum));
+      PKD_TRY(exscan_i32(st, flag.p, S.p, n + 1, bsum));   // S[o] = batch points noted at ends below o
+    } else {
+      if (n_removed > 0)
+        hipLaunchKernelGGL(k_mark_removed, dim3(static_cast<unsigned>(std::min<int64_t>(4096, (n_removed + 255) / 256))),
+                           dim3(256), 0, st, dpos.p, static_cast<int32_t>(n_removed), flag.p);
+      PKD_TRY(kernel_status("k_mark_removed"));
+      PKD_TRY(exscan_i32(st, flag.p, S.p, n, bsum));       // S[o] = removed points below o
     }
+    ev.S = S.p;
+    ev.regid = regid.p;
+    ev.delflag = flag.p;
   } else {
-    PKD_TRY(fill(st, gx.p, 1, 0));
+    // the regions ordered by old end, their chunk table and (insert) the
+    // batch points placed before each end; the removed positions' table
+    PKD_TRY(rtab.need(static_cast<size_t>(nch) + 1));
+    PKD_TRY(gx.need(static_cast<size_t>(n_regions) + 1));
+    ev.rc = rtab.p;
+    ev.gx = gx.p;
+    if (n_regions > 0) {
+      PKD_TRY(rkey.need(n_regions));
+      PKD_TRY(rval.need(n_regions));
+      const unsigned gr = static_cast<unsigned>(std::min<int64_t>(4096, (n_regions + 255) / 256));
+      hipLaunchKernelGGL(k_region_keys, dim3(gr), dim3(256), 0, st, regions.p, n_regions, rkey.p, rval.p);
+      PKD_TRY(kernel_status("k_region_keys"));
+      uint64_t* ks = nullptr;
+      uint32_t* vs = nullptr;
+      PKD_TRY(radix_sort_pairs(st, rkey.p, rval.p, n_regions, bits_for(2 * n + 1), RW, &ks, &vs));
+      ev.rkey = ks;
+      ev.rk = vs;
+      if (insert) {
+        PKD_TRY(growth.need(n_regions));
+        hipLaunchKernelGGL(k_region_growth, dim3(gr), dim3(256), 0, st, regions.p, vs, n_regions, growth.p);
+        PKD_TRY(kernel_status("k_region_growth"));
+        PKD_TRY(exscan_i32(st, growth.p, gx.p, n_regions, bsum));
+      }
+    } else {
+      PKD_TRY(fill(st, gx.p, 1, 0));
+    }
+    hipLaunchKernelGGL(k_chunk_table, dim3(gch), dim3(256), 0, st, ev.rkey, n_regions, 1, nch, rtab.p);
+    PKD_TRY(kernel_status("k_chunk_table"));
+    if (!insert) {
+      PKD_TRY(dtab.need(static_cast<size_t>(nch) + 1));
+      hipLaunchKernelGGL(k_chunk_table, dim3(gch), dim3(256), 0, st, dpos.p, static_cast<int32_t>(n_removed), 0, nch,
+                         dtab.p);
+      PKD_TRY(kernel_status("k_chunk_table"));
+      ev.dc = dtab.p;
+    }
   }
-  hipLaunchKernelGGL(k_chunk_table, dim3(gch), dim3(256), 0, st, ev.rkey, n_regions, 1, nch, rtab.p);
-  PKD_TRY(kernel_status("k_chunk_table"));
   if (n > 0) {
     hipLaunchKernelGGL(k_relayout<D>, dim3(static_cast<unsigned>(nch)), dim3(256), 0, st, Xold, old_cap, n, ev,
                        regions.p, insert ? 1 : 0, Ynew, new_cap, c32_new);
@@ -1221,20 +1333,26 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
   }
   // region sizes and places after the update, their packed offsets in the
   // rebuild's input (comp) and the rebuild's root tasks, all on the device
-  DArr<int32_t> rsize(st), comp32(st);
+  DArr<int32_t> rsize(st), comp32(st), osize(st), ocomp32(st);
   DArr<int64_t> dcomp(st), cin(st);
   DArr<Task> roots(st);
-  int32_t R_pts32 = 0;
+  int32_t R_pts32 = 0, R_old32 = 0;
   if (n_regions > 0) {
     PKD_TRY(rsize.need(static_cast<size_t>(n_regions) + 1));
+    PKD_TRY(osize.need(static_cast<size_t>(n_regions) + 1));
+    PKD_TRY(ocomp32.need(static_cast<size_t>(n_regions) + 1));
     PKD_TRY(comp32.need(static_cast<size_t>(n_regions) + 1));
     PKD_TRY(dcomp.need(static_cast<size_t>(n_regions) + 1));
     PKD_TRY(roots.need(static_cast<size_t>(n_regions)));
     const unsigned gr = static_cast<unsigned>(std::min<int64_t>(65536, (n_regions + 256) / 256));
     hipLaunchKernelGGL(k_region_final, dim3(gr), dim3(256), 0, st, regions.p, n_regions, ev, insert ? 1 : 0,
-                       rsize.p);
+                       rsize.p, osize.p);
     PKD_TRY(kernel_status("k_region_final"));
     PKD_TRY(exscan_i32(st, rsize.p, comp32.p, n_regions, bsum));
+    if (!insert) {
+      PKD_TRY(exscan_i32(st, osize.p, ocomp32.p, n_regions, bsum));
+      PKD_HIP(hipMemcpyAsync(&R_old32, ocomp32.p + n_regions, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    }
     hipLaunchKernelGGL(k_region_roots, dim3(gr), dim3(256), 0, st, regions.p, n_regions, comp32.p, dcomp.p,
                        roots.p);
     PKD_TRY(kernel_status("k_region_roots"));
@@ -1258,12 +1376,6 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     }
   } tmp{nullptr, st};
   const int64_t R_pts = R_pts32;
-  // one wave per region in the gather and the scatter back; the blocks of
-  // grid dimension y share the range of a region in proportion to the points
-  // per region (old points before a delete)
-  const unsigned ry = static_cast<unsigned>(std::min<int64_t>(
-      4096, std::max<int64_t>(1, (R_pts + n_removed) / (std::max(n_regions, 1) * int64_t{2048}))));
-  const unsigned gx4 = static_cast<unsigned>((std::max(n_regions, 1) + 3) / 4);
   int32_t appended = 0;
   if (n_regions > 0) {
     tmp.t = new pkd_tree;
@@ -1273,8 +1385,13 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     PKD_TRY(ensure_nodes(tmp.t, st, std::max<int64_t>(1024, n_regions + R_pts / 8)));
     PKD_TRY(cin.need(static_cast<size_t>(D + 1) * std::max<int64_t>(R_pts, 1)));
     const int64_t ccap = std::max<int64_t>(R_pts, 1);
-    hipLaunchKernelGGL(k_gather_regions<D>, dim3(gx4, ry), dim3(256), 0, st, regions.p, n_regions, dcomp.p, Xold,
-                       old_cap, ev, wf.p, m, insert ? 1 : 0, cin.p, ccap);
+    // entries of the gather: the output positions (insert) or the regions'
+    // old points (delete)
+    const int64_t gtot = insert ? R_pts : static_cast<int64_t>(R_old32);
+    if (R_pts > 0 && gtot > 0)
+      hipLaunchKernelGGL(k_gather_regions<D>, dim3(static_cast<unsigned>((gtot + kFlatChunk - 1) / kFlatChunk)),
+                         dim3(256), 0, st, regions.p, n_regions, insert ? comp32.p : ocomp32.p, gtot, comp32.p, Xold,
+                         old_cap, ev, wf.p, m, insert ? 1 : 0, cin.p, ccap);
     PKD_TRY(kernel_status("k_gather_regions"));
     tmp.t->node_count = n_regions;
     tmp.t->height = 0;
@@ -1299,8 +1416,9 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
   if (n_regions > 0) {
     pkd_tree* Z = tmp.t;
     if (R_pts > 0) {
-      hipLaunchKernelGGL(k_scatter_back<D>, dim3(gx4, ry), dim3(256), 0, st, regions.p, dcomp.p, n_regions,
-                         Z->buf[Z->cur], Z->cap, Ynew, new_cap, c32_new);
+      hipLaunchKernelGGL(k_scatter_back<D>, dim3(static_cast<unsigned>((R_pts + kFlatChunk - 1) / kFlatChunk)),
+                         dim3(256), 0, st, regions.p, comp32.p, n_regions, R_pts, Z->buf[Z->cur], Z->cap, Ynew,
+                         new_cap, c32_new);
       PKD_TRY(kernel_status("k_scatter_back"));
     }
     const int32_t base = T->node_count;

@@ -75,6 +75,11 @@ def test_parameter_validation_before_any_device_work(L):
     for bias in (-5, 5, 100):
         t.cand_shift_bias = bias
         assert L.pkd_build(C.byref(p), C.byref(t), None, None, None, 0, C.byref(out)) == -1
+    L.pkd_default_tuning(C.byref(t))
+    assert t.update_events == 0
+    for events in (-1, 3):
+        t.update_events = events
+        assert L.pkd_build(C.byref(p), C.byref(t), None, None, None, 0, C.byref(out)) == -1
     assert L.pkd_knn(None, None, None, 1, 1, None, None) == -1
     assert L.pkd_range_count(None, None, None, None, 1, None) == -1
     assert L.pkd_size(None, None) == -1

@@ -24,13 +24,15 @@ def _check_all(bt, trees, pts, label, orc, D):
         assert np.array_equal(gi[mine], bi) and np.array_equal(gd[mine], bd), (label, t)
 
 
-@pytest.mark.parametrize("bbox", [False, True])
-def test_updates_tree_by_tree(pk, orc, bbox):
+# events: how an update places the old points (0: by the batch's density,
+# 1: sorted event lists, 2: per-point arrays); the trees are the same
+@pytest.mark.parametrize("bbox,events", [(False, 0), (True, 0), (False, 1), (False, 2)])
+def test_updates_tree_by_tree(pk, orc, bbox, events):
     D = 3
     sizes = [0, 5000, 30000, 200, 80000]
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     c, i = synth.uniform_points(int(off[-1]), D, seed=800)
-    bt = pk.Tree.batch(pk.Params(D), c, i, off)
+    bt = pk.Tree.batch(pk.Params(D), c, i, off, update_events=events)
     if bbox:
         bt.set_bbox(True)
     op = orc.Params(D)

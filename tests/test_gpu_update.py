@@ -36,11 +36,11 @@ def _same(gt, ot, label):
 class Pair:
     """The same tree on the GPU and in the oracle, plus the current point set."""
 
-    def __init__(self, orc, pk, c, i, **kw):
+    def __init__(self, orc, pk, c, i, events=0, **kw):
         D = c.shape[0]
         self.orc, self.pk = orc, pk
         self.op = orc.Params(D, **kw)
-        self.g = pk.Tree(pk.Params(D, **kw), c, i)
+        self.g = pk.Tree(pk.Params(D, **kw), c, i, update_events=events)
         self.o = orc.Tree(self.op, c, i)
         self.c, self.i = c, i
 
@@ -87,10 +87,13 @@ class Pair:
             assert np.array_equal(got, self.orc.brute_range_count(self.c, *boxes)), label
 
 
-@pytest.mark.parametrize("D,kw", [(3, {}), (2, dict(lam=3, phi=4, sigma=4)), (2, dict(alpha=(1, 10)))])
-def test_insert_delete_sequence(orc, pk, D, kw):
+# events: how an update places the old points (0: by the batch's density,
+# 1: sorted event lists, 2: per-point arrays); the trees are the same
+@pytest.mark.parametrize("D,kw,events", [(3, {}, 0), (2, dict(lam=3, phi=4, sigma=4), 0), (2, dict(alpha=(1, 10)), 0),
+                                         (3, {}, 1), (2, dict(lam=3, phi=4, sigma=4), 2)])
+def test_insert_delete_sequence(orc, pk, D, kw, events):
     c, i, state = synth.clustered_points(120000, D, seed=60, n_clusters=60)
-    P = Pair(orc, pk, c, i, **kw)
+    P = Pair(orc, pk, c, i, events=events, **kw)
     q = synth.uniform_queries(300, D, seed=61)
     boxes = synth.log_uniform_boxes(300, D, seed=62)
     P.check("build", q, boxes)
@@ -105,9 +108,10 @@ def test_insert_delete_sequence(orc, pk, D, kw):
         P.check("delete %d" % step, q, boxes)
 
 
-def test_uniform_small_batches(orc, pk):
+@pytest.mark.parametrize("events", [0, 2])
+def test_uniform_small_batches(orc, pk, events):
     c, i = synth.uniform_points(200000, 3, seed=80)
-    P = Pair(orc, pk, c, i)
+    P = Pair(orc, pk, c, i, events=events)
     nid = 10 ** 7
     for step, m in enumerate([1, 7, 100, 1000]):
         nc, ni = synth.uniform_points(m, 3, seed=81 + step, id_base=nid)
@@ -119,9 +123,10 @@ def test_uniform_small_batches(orc, pk):
         P.check("delete m=%d" % m)
 
 
-def test_large_batches(orc, pk):
+@pytest.mark.parametrize("events", [0, 1])
+def test_large_batches(orc, pk, events):
     c, i = synth.uniform_points(100000, 2, seed=100)
-    P = Pair(orc, pk, c, i)
+    P = Pair(orc, pk, c, i, events=events)
     nc, ni = synth.uniform_points(150000, 2, seed=101, id_base=10 ** 7)
     P.insert(nc, ni)
     P.check("insert 150%")
@@ -159,9 +164,10 @@ def test_empty_tree_and_delete_everything(orc, pk):
     E.check("delete all small")
 
 
-def test_delete_absent_mismatched_and_repeated(orc, pk):
+@pytest.mark.parametrize("events", [0, 2])
+def test_delete_absent_mismatched_and_repeated(orc, pk, events):
     c, i = synth.uniform_points(30000, 2, seed=120)
-    P = Pair(orc, pk, c, i)
+    P = Pair(orc, pk, c, i, events=events)
     ac, ai = synth.uniform_points(500, 2, seed=121, id_base=10 ** 8)
     assert P.delete(ac, ai) == 0
     wrong = c[:, :300].copy()
@@ -218,11 +224,14 @@ def test_scattered_batches_route_by_sort(orc, pk):
 
 
 def test_updates_on_a_tree_above_2_27_points(pk):
-    # the prefix sums over all points of an update then take their recursive
-    # form; answers are checked against brute force over the current set on
+    # small batches on a 1.5e8-point tree (new places from the sorted update
+    # events and their chunk tables), then a batch of 1.4e8 points, whose
+    # per-entry prefix sums take the recursive form of the scan (inputs above
+    # 2^27); answers are checked against brute force over the current set on
     # the device (exact int64 arithmetic)
     import torch
-    D, n0, m = 2, 150_000_000, 100_000
+    D, n0, m, m2 = 2, 150_000_000, 100_000, 140_000_000
+    assert m2 > (1 << 27)
     ids = torch.arange(n0, device="cuda", dtype=torch.int64)
     c = synth.hashed_points_torch(ids, D, 21)
     print("large tree build", flush=True)
@@ -235,16 +244,22 @@ def test_updates_on_a_tree_above_2_27_points(pk):
     did = torch.arange(0, 3 * m, 3, device="cuda", dtype=torch.int64)
     assert t.delete(c[:, did].contiguous(), did) == m
     assert t.size() == n0
+    print("large batch insert", flush=True)
+    bid = torch.arange(n0 + m, n0 + m + m2, device="cuda", dtype=torch.int64)
+    bc = synth.hashed_points_torch(bid, D, 123)
+    t.insert(bc, bid)
+    assert t.size() == n0 + m2
     keep = torch.ones(n0, dtype=torch.bool, device="cuda")
     keep[did] = False
-    allc = torch.cat([c[:, keep], nc], dim=1)
-    alli = torch.cat([ids[keep], nid])
+    allc = torch.cat([c[:, keep], nc, bc], dim=1)
+    alli = torch.cat([ids[keep], nid, bid])
+    del c, bc, keep
     # no point lost or duplicated by the relayout: every id is reported once
     # in the box of the whole domain (range report, a different kernel)
     full_lo = torch.zeros((D, 1), dtype=torch.int64, device="cuda")
     full_hi = torch.full((D, 1), (1 << 30) - 1, dtype=torch.int64, device="cuda")
     off, rid = t.range_report(full_lo, full_hi)
-    assert int(off[-1]) == n0
+    assert int(off[-1]) == n0 + m2
     assert torch.equal(torch.sort(rid).values, torch.sort(alli).values)
     del rid
     q = torch.from_numpy(synth.uniform_queries(32, D, seed=5)).cuda()
