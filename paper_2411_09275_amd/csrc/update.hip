@@ -364,7 +364,7 @@ __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
 // shared by all waves serialized tens of millions of atomics when a batch
 // touched millions of nodes.)
 __host__ __device__ inline size_t decide_lds_per_wave(int lambda) {
-  return (static_cast<size_t>(2 << lambda) * (3 * sizeof(int32_t) + 1) + 15) & ~size_t{15};
+  return (static_cast<size_t>(2 << lambda) * (7 * sizeof(int32_t) + 1) + 15) & ~size_t{15};
 }
 
 __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int ns, int lambda, const int32_t* hn_all,
@@ -376,8 +376,9 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
                                                         const int32_t* roff, int2* sizes, const int* n_sizes,
                                                         int32_t* scount, const int32_t* soff) {
   const int NB = 1 << lambda, nheap = 2 << lambda;
-  // per wave: cnt, s0, sz [nheap] int32, alive [nheap] bytes (dynamic LDS,
-  // sized for this lambda)
+  // per wave: cnt, s0, sz, and the touched nodes' size, offset, depth and
+  // left child's size [nheap] int32, alive [nheap] bytes (dynamic LDS, sized
+  // for this lambda)
   extern __shared__ __align__(16) unsigned char smem[];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int sig = blockIdx.x * kWaves + w;
@@ -391,7 +392,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
   int32_t* cnt = reinterpret_cast<int32_t*>(mine);
   int32_t* s0 = cnt + nheap;
   int32_t* sz = s0 + nheap;
-  uint8_t* alive = reinterpret_cast<uint8_t*>(sz + nheap);
+  int32_t* t_size = sz + nheap;
+  int32_t* t_off = t_size + nheap;
+  int32_t* t_depth = t_off + nheap;
+  int32_t* t_lsize = t_depth + nheap;   // left child's size; -1: a leaf
+  uint8_t* alive = reinterpret_cast<uint8_t*>(t_lsize + nheap);
   const int32_t* hn = hn_all + static_cast<int64_t>(sig) * nheap;
   for (int j = lane; j < NB; j += 64) {
     const int32_t st = bstart[static_cast<int64_t>(sig) * NB + j];
@@ -410,6 +415,20 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
     }
     wave_sync();
   }
+  // the records of every node the batch reaches, loaded together (the walk
+  // below would otherwise wait on two dependent loads per level)
+  for (int v = 1 + lane; v < nheap; v += 64) {
+    const int32_t u = hn[v];
+    if (u >= 0 && cnt[v] != 0) {
+      const Node nd = nodes[u];
+      t_size[v] = nd.size;
+      t_off[v] = nd.off;
+      t_depth[v] = nd.depth;
+      const int lev = 31 - __clz(v);
+      t_lsize[v] = nd.left < 0 ? -1 : (lev < lambda ? nodes[nd.left].size : 0);
+    }
+  }
+  wave_sync();
   int added = 0;   // regions this wave has added so far (uniform)
   int sized = 0;   // sizes this wave has recorded so far (uniform)
   const int32_t base = apply ? *n_regions + roff[sig] : 0;
@@ -431,21 +450,21 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
         int32_t newsz = 0;
         Region reg{};
         if (in && alive[v] && u >= 0 && cnt[v] != 0) {
-          const Node nd = nodes[u];
+          const int32_t nsize = t_size[v], noff = t_off[v], ndepth = t_depth[v], lsize = t_lsize[v];
           const int sign = insert ? 1 : -1;
-          if (nd.left < 0) {
+          if (lsize < 0) {
             if (insert) {
               add = true;
-              reg = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
+              reg = Region{u, ndepth, noff, noff + nsize, s0[v], s0[v] + sz[v], 0, 0};
             } else {
               setsz = true;
-              newsz = nd.size - cnt[v];
+              newsz = nsize - cnt[v];
             }
           } else if (l == lambda) {
             if (apply) killed_next[child_idx[static_cast<int64_t>(sig) * nheap + v]] = 0;
           } else {
-            const int64_t n2 = static_cast<int64_t>(nd.size) + sign * cnt[v];
-            const int64_t l2 = static_cast<int64_t>(nodes[nd.left].size) + sign * cnt[2 * v];
+            const int64_t n2 = static_cast<int64_t>(nsize) + sign * cnt[v];
+            const int64_t l2 = static_cast<int64_t>(lsize) + sign * cnt[2 * v];
             const bool bal = n2 > 0 && (ad - 2 * an) * n2 <= 2 * ad * l2 && 2 * ad * l2 <= (ad + 2 * an) * n2;
             if (bal) {
               setsz = true;
@@ -453,7 +472,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_decide(const Task* tasks, int n
               alive[2 * v] = alive[2 * v + 1] = 1;
             } else {
               add = true;
-              reg = Region{u, nd.depth, nd.off, nd.off + nd.size, s0[v], s0[v] + sz[v], 0, 0};
+              reg = Region{u, ndepth, noff, noff + nsize, s0[v], s0[v] + sz[v], 0, 0};
             }
           }
         }
