@@ -555,13 +555,6 @@ __device__ inline int32_t removed_below(const EvView& ev, int64_t x) {
   return first_not_below(ev.dp, ev.dc[c], ev.dc[c + 1], static_cast<uint64_t>(x));
 }
 
-// Batch points an insert places before the old position x: those of the
-// regions ending at or before x (x < n), or before x (x = n: a node at the
-// end is placed before the regions that end there).
-__device__ inline int32_t inserted_before(const EvView& ev, int64_t x, int64_t n) {
-  return growth_below(ev, x < n ? x + 1 : x);
-}
-
 // The region holding old position o (0 <= o < n), or -1.  In the lists the
 // first entry ending after o is the only candidate: regions are disjoint, and
 // an empty region (an empty tree of a batch handle) sits at a boundary
@@ -721,8 +714,19 @@ __global__ void k_node_update(Node* nodes, int32_t n_nodes, EvView ev, const Reg
     const Node nd = nodes[t];
     if (nd.pad != 0) continue;   // dead since an earlier update
     if (nd.off < 0 || nd.off > n_old) continue;
-    if (nd.off < n_old && nd.size > 0) {
-      const int32_t k = region_at(ev, regions, nd.off);
+    const bool inside = nd.off < n_old;
+    // in the lists one lookup serves both the region test and an insert's
+    // shift: the first entry ending after the node's first point
+    int32_t u = 0;
+    if (!ev.dense && (insert || inside)) u = ends_below(ev, inside ? nd.off + 1 : nd.off);
+    if (inside && nd.size > 0) {
+      int32_t k = -1;
+      if (ev.dense) {
+        k = ev.regid[nd.off];
+      } else if (u < ev.R) {
+        const int32_t c = static_cast<int32_t>(ev.rk[u]);
+        if (regions[c].a <= nd.off) k = c;
+      }
       if (k >= 0) {
         const Region r = regions[k];
         if (r.node == t) continue;   // overwritten by its rebuilt subtree
@@ -732,7 +736,7 @@ __global__ void k_node_update(Node* nodes, int32_t n_nodes, EvView ev, const Reg
         }
       }
     }
-    if (insert) nodes[t].off = nd.off + inserted_before(ev, nd.off, n_old);
+    if (insert) nodes[t].off = nd.off + (ev.dense ? ev.S[inside ? nd.off + 1 : nd.off] : ev.gx[u]);
     else nodes[t].off = nd.off - removed_below(ev, nd.off);
   }
 }
@@ -986,6 +990,7 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
   const Params& P = T->prm;
   const int lambda = P.lambda, NB = 1 << lambda, nheap = 2 << lambda;
   const int64_t n = T->n;
+  Node root{};
   DArr<int> flags(st);
   PKD_TRY(flags.need(8));
   PKD_HIP(hipMemsetAsync(flags.p, 0, sizeof(int) * 8, st));
@@ -995,6 +1000,10 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
     PKD_TRY(kernel_status("k_validate"));
     int h = 0;
     PKD_HIP(hipMemcpyAsync(&h, flags.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    // the tree's root (node `tree`: the trees of a handle have their roots
+    // first) comes back with the same wait
+    if (!(insert && n == 0 && T->n_trees == 1))   // (that insert is a fresh build)
+      PKD_HIP(hipMemcpyAsync(&root, T->nodes + tree, sizeof(Node), hipMemcpyDeviceToHost, st));
     PKD_HIP(hipStreamSynchronize(st));
     if (h & kErrRange) return PKD_ERR_RANGE;
   }
@@ -1038,10 +1047,6 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
   int* d_regions = ctr.p + 2;
   PKD_TRY(res.need(static_cast<size_t>(m) + 1));
 
-  Node root;
-  // the tree's root: node `tree` (the trees of a handle have their roots first)
-  PKD_HIP(hipMemcpyAsync(&root, T->nodes + tree, sizeof(Node), hipMemcpyDeviceToHost, st));
-  PKD_HIP(hipStreamSynchronize(st));
   std::vector<RoundSave*> rounds;
   struct Cleanup {
     std::vector<RoundSave*>& r;
