@@ -2222,7 +2222,8 @@ int sieve_pass_d(hipStream_t st, int lambda, int tile, const Task* tasks, int ns
 // ------------------------------------------------ int32 exclusive prefix sum
 constexpr int kScanThreads = 256;
 // Exclusive prefix sums over int32 arrays: block sums, one-workgroup scan of
-// the block sums, then the per-block pass.  out[i] = sum in[0..i), out[n] = total.
+// the block sums, then the per-block pass (the last alone for inputs of one
+// block).  out[i] = sum in[0..i), out[n] = total.
 constexpr int kScanBlock = 2048;
 
 __global__ void k_scan_blocks(const int32_t* in, int64_t n, int32_t* bsum) {
@@ -2294,7 +2295,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int32_t* in, 
   }
   if (lane == 63) wtot[w] = incl;
   __syncthreads();
-  int32_t before = bsum[blockIdx.x];
+  int32_t before = bsum ? bsum[blockIdx.x] : 0;   // no block sums: a single block
   for (int j = 0; j < w; ++j) before += wtot[j];
   int32_t run = before + incl - s;
   for (int k = 0; k < per; ++k) {
@@ -2314,6 +2315,11 @@ int64_t exscan_bsum_need(int64_t n) { return std::max<int64_t>(1, (n + kScanBloc
 int exscan_i32_raw(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, int32_t* bsum) {
   const int64_t nb = std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock);
   if (nb > kScanSumsMax) return PKD_ERR_INTERNAL;   // callers with larger inputs use exscan_i32
+  if (nb == 1) {   // one block scans it all (most scans of an update are this small)
+    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, st, in, n, static_cast<const int32_t*>(nullptr),
+                       out);
+    return kernel_status("k_scan_apply");
+  }
   hipLaunchKernelGGL(k_scan_blocks, dim3(static_cast<unsigned>(nb)), dim3(kScanThreads), 0, st, in, n, bsum);
   PKD_TRY(kernel_status("k_scan_blocks"));
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum, nb);
