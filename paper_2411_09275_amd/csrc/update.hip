@@ -530,7 +530,7 @@ struct EvView {
 // Index of the first a[lo .. hi) that is >= x (hi if none); a ascending.
 __device__ inline int32_t first_not_below(const uint64_t* a, int32_t lo, int32_t hi, uint64_t x) {
   while (lo < hi) {
-    const int32_t mid = (lo + hi) >> 1;
+    const int32_t mid = lo + ((hi - lo) >> 1);
     if (a[mid] < x) lo = mid + 1;
     else hi = mid;
   }
@@ -790,7 +790,7 @@ constexpr int kFlatChunk = 2048;
 // shares its P with the next one and is never chosen over it.
 __device__ inline int last_at_or_below(const int32_t* P, int lo, int hi, int64_t q) {
   while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
+    const int mid = lo + ((hi - lo) >> 1);
     if (P[mid] <= q) lo = mid;
     else hi = mid;
   }
@@ -858,7 +858,7 @@ __global__ void k_apply_sizes(Node* nodes, const int2* sizes, const int* n_sizes
 __device__ inline int region_of(const int64_t* comp, int nreg, int64_t p) {
   int lo = 0, hi = nreg;   // last region whose packed range starts at or before p
   while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
+    const int mid = lo + ((hi - lo) >> 1);
     if (comp[mid] <= p) lo = mid; else hi = mid;
   }
   return lo;
