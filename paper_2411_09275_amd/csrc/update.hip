@@ -708,36 +708,61 @@ __global__ void __launch_bounds__(256) k_relayout(const int64_t* X, int64_t xcap
 // New offsets of the surviving nodes.  Live node ranges nest like the tree,
 // so a node whose first point lies inside a region and that is deeper than
 // the region's node is below it: it dies (the rebuilt subtree replaces it).
-__global__ void k_node_update(Node* nodes, int32_t n_nodes, EvView ev, const Region* regions, int insert,
-                              int64_t n_old) {
-  for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_nodes; t += gridDim.x * blockDim.x) {
-    const Node nd = nodes[t];
-    if (nd.pad != 0) continue;   // dead since an earlier update
-    if (nd.off < 0 || nd.off > n_old) continue;
-    const bool inside = nd.off < n_old;
-    // in the lists one lookup serves both the region test and an insert's
-    // shift: the first entry ending after the node's first point
-    int32_t u = 0;
-    if (!ev.dense && (insert || inside)) u = ends_below(ev, inside ? nd.off + 1 : nd.off);
-    if (inside && nd.size > 0) {
-      int32_t k = -1;
-      if (ev.dense) {
-        k = ev.regid[nd.off];
-      } else if (u < ev.R) {
-        const int32_t c = static_cast<int32_t>(ev.rk[u]);
-        if (regions[c].a <= nd.off) k = c;
-      }
-      if (k >= 0) {
-        const Region r = regions[k];
-        if (r.node == t) continue;   // overwritten by its rebuilt subtree
-        if (nd.depth > r.depth) {
-          nodes[t].pad = 1;
-          continue;
-        }
-      }
+// Returns the node's new offset, -1 to leave it, -2 to mark it dead.
+__device__ inline int64_t node_new_off(const Node& nd, int32_t t, const EvView& ev, const Region* regions,
+                                       int insert, int64_t n_old) {
+  if (nd.pad != 0) return -1;   // dead since an earlier update
+  if (nd.off < 0 || nd.off > n_old) return -1;
+  const bool inside = nd.off < n_old;
+  // in the lists one lookup serves both the region test and an insert's
+  // shift: the first entry ending after the node's first point
+  int32_t u = 0;
+  if (!ev.dense && (insert || inside)) u = ends_below(ev, inside ? nd.off + 1 : nd.off);
+  if (inside && nd.size > 0) {
+    int32_t k = -1;
+    if (ev.dense) {
+      k = ev.regid[nd.off];
+    } else if (u < ev.R) {
+      const int32_t c = static_cast<int32_t>(ev.rk[u]);
+      if (regions[c].a <= nd.off) k = c;
     }
-    if (insert) nodes[t].off = nd.off + (ev.dense ? ev.S[inside ? nd.off + 1 : nd.off] : ev.gx[u]);
-    else nodes[t].off = nd.off - removed_below(ev, nd.off);
+    if (k >= 0) {
+      const Region r = regions[k];
+      if (r.node == t) return -1;        // overwritten by its rebuilt subtree
+      if (nd.depth > r.depth) return -2;
+    }
+  }
+  if (insert) return nd.off + (ev.dense ? ev.S[inside ? nd.off + 1 : nd.off] : ev.gx[u]);
+  return nd.off - removed_below(ev, nd.off);
+}
+
+// Four nodes per thread, their records loaded together (coalesced across the
+// wave) and their lookups done before any store, so a thread has four chains
+// of dependent loads in flight rather than one.
+constexpr int kNodesPerThread = 4;
+
+__global__ void __launch_bounds__(256) k_node_update(Node* nodes, int32_t n_nodes, EvView ev, const Region* regions,
+                                                     int insert, int64_t n_old) {
+  const int64_t S = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t0 < n_nodes;
+       t0 += S * kNodesPerThread) {
+    Node nd[kNodesPerThread];
+#pragma unroll
+    for (int i = 0; i < kNodesPerThread; ++i) {
+      const int64_t t = t0 + i * S;
+      if (t < n_nodes) nd[i] = nodes[t];
+      else nd[i].pad = 1;
+    }
+    int64_t no[kNodesPerThread];
+#pragma unroll
+    for (int i = 0; i < kNodesPerThread; ++i)
+      no[i] = node_new_off(nd[i], static_cast<int32_t>(t0 + i * S), ev, regions, insert, n_old);
+#pragma unroll
+    for (int i = 0; i < kNodesPerThread; ++i) {
+      const int64_t t = t0 + i * S;
+      if (no[i] == -2) nodes[t].pad = 1;
+      else if (no[i] >= 0) nodes[t].off = static_cast<int32_t>(no[i]);
+    }
   }
 }
 
@@ -1432,7 +1457,8 @@ int update_d(pkd_tree* T, int32_t tree, hipStream_t st, const int64_t* coords, c
                        sizes.p, d_sizes);
   PKD_TRY(kernel_status("k_apply_sizes"));
   if (T->node_count > 0) {
-    const unsigned g = static_cast<unsigned>(std::min<int64_t>(65536, (T->node_count + 255) / 256));
+    const unsigned g = static_cast<unsigned>(
+        std::min<int64_t>(65536, (T->node_count + 256 * kNodesPerThread - 1) / (256 * kNodesPerThread)));
     hipLaunchKernelGGL(k_node_update, dim3(g), dim3(256), 0, st, T->nodes, T->node_count, ev, regions.p,
                        insert ? 1 : 0, n);
     PKD_TRY(kernel_status("k_node_update"));
