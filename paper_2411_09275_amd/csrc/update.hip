@@ -17,7 +17,9 @@
 //   relayout  the tree keeps its points packed in in-order: the regions sorted
 //             by old end (with the batch points each adds) and the sorted
 //             removed positions give every surviving point and node its new
-//             offset; old points, batch points and survivors move in one pass.
+//             offset (a batch dense in the tree uses per-point arrays
+//             instead); old points, batch points and survivors move in one
+//             pass.
 //   rebuild   all regions are rebuilt by one segmented Build (Algorithm 1),
 //             each at the depth of the node it replaces.
 #include <algorithm>
